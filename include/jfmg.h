@@ -1,0 +1,199 @@
+/*
+ * jfmg: Jacobian-free Newton-GMRES with an FV-subgrid multigrid preconditioner
+ * for the well-balanced DG discretization of 2D compressible Euler / viscous
+ * flow with gravity on Cartesian quadrilaterals, on AMD MI355X (gfx950).
+ *
+ * Method: P. Birken, A. Dedner, R. Kloefkorn, "A Jacobian-free Multigrid
+ * Preconditioner for Discontinuous Galerkin Methods applied to Numerical
+ * Weather Prediction", arXiv 2505.24504.
+ *
+ * Conventions for every entry point
+ *  - Vectors are DEVICE pointers owned by the caller.  The library never
+ *    allocates device memory after jfmg_create_problem: everything lives in
+ *    the caller's workspace (size from jfmg_workspace_bytes).
+ *  - DG vector layout: the perturbation U' of the well-balanced form (Sec.
+ *    "euler-model", eq. perturbed-euler) as FP64 SoA [4][nz][nx][(k+1)^2],
+ *    components (rho, rho u, rho w, rho theta); element e = ez*nx + ex; node
+ *    b*(k+1) + a with a along x and nodes at the Gauss-Legendre points in
+ *    ascending order.  N = 4 nx nz (k+1)^2 entries (jfmg_num_dofs).
+ *  - FV vector layout (finest level = (k+1)nx x (k+1)nz subcells, each coarser
+ *    level halves both counts): SoA [4][nzl][nxl], cell (I,J) at J*nxl + I, in
+ *    the problem's multigrid precision (double for mg_precision 64, float for 32).
+ *  - All work is stream ordered on the stream given at creation.  Entry points
+ *    that return scalars or make convergence decisions synchronize that stream.
+ *  - Every call returns a jfmg_status; jfmg_last_error gives a message.  No
+ *    exception crosses the ABI.  A problem is used by one host thread at a time.
+ */
+#ifndef JFMG_H
+#define JFMG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    JFMG_OK = 0,
+    JFMG_EINVAL = 1,      /* bad configuration or argument                     */
+    JFMG_ENOMEM = 2,      /* workspace too small                               */
+    JFMG_ENOCONV = 3,     /* Newton or GMRES hit its iteration cap             */
+    JFMG_ENONFINITE = 4,  /* NaN/Inf in a norm                                 */
+    JFMG_ESTATE = 5,      /* call needs a prior jfmg_linearize                 */
+    JFMG_EDEVICE = 6      /* HIP runtime error                                 */
+} jfmg_status;
+
+typedef struct {
+    int nx, nz, k;            /* quads in x and z; DG degree k in {1,2,3}                 */
+    int physics;              /* 0 Euler, 1 viscous flux F_v (eq. compressible-euler)    */
+    int background;           /* 0 neutral (theta = theta0), 1 constant N                */
+    int bc;                   /* 0 slip walls, 1 periodic in x + slip walls in z        */
+    int scheme;               /* 0 implicit Euler, 1 SDIRK2 of Ellsiepen (eq. ellsiep)   */
+    int newton_maxit;         /* Newton cap (ENOCONV beyond)                            */
+    int gmres_m;              /* FGMRES restart length, <= 64                           */
+    int gmres_max_restarts;   /* restarts before ENOCONV                                */
+    int fd_eps_mode;          /* DG FD step: 0 sqrt(eps)/||y||, 1 sqrt(eps)||U+Ubar||/||y|| */
+    int mg_levels;            /* FV levels including the finest, 1..8                   */
+    int rk_stages;            /* stages of the RK pseudo-time smoother, 1..4            */
+    int mass_fix;             /* 1: mass-fixed transfers (eq. transfer-mass-fix)        */
+    int mg_precision;         /* 64 or 32: precision of the whole multigrid             */
+    int precond;              /* 1 multigrid Q^-1 = T^-1 q^-1 T, 0 identity             */
+    char mg_key[16];          /* "mg a b c d e f G", e.g. "mg002222V"; a = b = 0        */
+    double x0, x1, z0, z1;    /* domain                                                 */
+    double g, gamma, R, p0;   /* gravity, adiabatic index, gas constant, reference p    */
+    double theta0, N, u_mean; /* background theta (surface), Brunt-Vaisala N, mean wind */
+    double mu, c_ip;          /* kinematic viscosity [m^2/s]; interior-penalty constant */
+    double dt, newton_rtol;   /* time step; Newton stops at ||G|| < rtol ||G^0||        */
+    double ew_gamma, ew_alpha, ew_eta0, ew_eta_max; /* Eisenstat-Walker choice 2        */
+    double rk_alpha[4];       /* smoother coefficients; 0 entries: 1/(s-j+1)            */
+    double pseudo_cfl;        /* c* in the pseudo time step                             */
+} jfmg_config;
+
+typedef struct {
+    int shape;                /* 0 cosine bubble (density current), 1 inertia-gravity  */
+    int pad;
+    double amp, xc, zc, xr, zr, a, Z;
+} jfmg_perturbation;
+
+typedef struct {
+    int newton_its, gmres_its, lh_evals, jvps;
+    int fv_matvecs[8];        /* FV operator evaluations per level (finest first)      */
+    int host_syncs, status;
+    double g0_norm, g_norm;   /* ||G(U^0)||, ||G|| at exit of the last stage          */
+    double seconds;           /* host wall time of the call                           */
+} jfmg_stats;
+
+typedef struct jfmg_problem jfmg_problem;
+
+/* Fill a configuration with the defaults (16x16, k=1, Euler, neutral 300 K,
+   slip walls, SDIRK2, dt 1 s, rtol 1e-8, FGMRES(30), 3 levels, mg002222V,
+   3 RK stages, mass fix, FP64 multigrid). */
+jfmg_status jfmg_config_default(jfmg_config* cfg);
+
+/* Device workspace bytes a problem with this configuration needs.
+   EINVAL for an invalid configuration (k outside 1..3, an FV dimension that
+   becomes odd before the last level, a or b of the key nonzero, m > 64, ...). */
+jfmg_status jfmg_workspace_bytes(const jfmg_config* cfg, size_t* bytes);
+
+/* Create a problem in the caller's device workspace (>= jfmg_workspace_bytes,
+   256-byte aligned) on the HIP stream `hip_stream` (NULL = default stream).
+   Builds the reference-element, background and index tables on the host and
+   uploads them.  The workspace stays owned by the caller and must outlive the
+   problem. */
+jfmg_status jfmg_create_problem(const jfmg_config* cfg, void* workspace, size_t ws_bytes,
+                                void* hip_stream, jfmg_problem** out);
+
+/* Release the host-side handle; frees nothing the caller gave. */
+jfmg_status jfmg_destroy_problem(jfmg_problem* p);
+
+/* N = 4 nx nz (k+1)^2, and 4 nxl nzl of FV level `level` (0 = finest). */
+size_t jfmg_num_dofs(const jfmg_problem* p);
+size_t jfmg_fv_size(const jfmg_problem* p, int level);
+
+/* Initial perturbation U' at the GL nodes: theta' inserted at constant
+   pressure (eq. add-perturbation), rho theta' = 0, v = background wind. */
+jfmg_status jfmg_initial_state(jfmg_problem* p, const jfmg_perturbation* pert, double* U);
+
+/* out = <psi, L_h(U')> (eqs. convDiscr, elementint, surfaceint on the
+   perturbation system), or f = M^-1 L_h (Sec. "Temporal discretization") when
+   apply_minv = 1.  U and out are DG vectors; no host synchronization. */
+jfmg_status jfmg_residual(jfmg_problem* p, const double* U, double* out, int apply_minv);
+
+/* G = U - alpha_dt f(U) - Ubar (eq. newton) and, if norm != NULL, ||G||_2
+   (host pointer; synchronizes). */
+jfmg_status jfmg_stage_residual(jfmg_problem* p, const double* U, const double* Ubar,
+                                double alpha_dt, double* G, double* norm);
+
+/* Set the Newton iterate U (copied) and alpha*dt for jfmg_jvp / jfmg_mg_apply:
+   ||U + Ubar||, the FV linearization states u_L = T^mf U, u_{l-1} = R u_l,
+   f_low(u_l) and the pseudo time steps of every level. */
+jfmg_status jfmg_linearize(jfmg_problem* p, const double* U, double alpha_dt);
+
+/* out = G'(U) y by finite differences (Sec. "Solver"):
+   y - (alpha dt/eps) M^-1 (L_h(U + eps y) - L_h(U)), eps per fd_eps_mode.
+   ESTATE without jfmg_linearize.  y = 0 gives 0. */
+jfmg_status jfmg_jvp(jfmg_problem* p, const double* y, double* out);
+
+/* z = Q^-1 r = T^-1 MG(0, T r; u_L) (eq. preconditioner); identity when
+   precond = 0.  ESTATE without jfmg_linearize. */
+jfmg_status jfmg_mg_apply(jfmg_problem* p, const double* r, double* z);
+
+/* One implicit step U^n -> U^{n+1} in place (implicit Euler or SDIRK2), each
+   stage by inexact Newton with Eisenstat-Walker forcing and right-preconditioned
+   FGMRES (Sec. "Solver").  On any error U is left unchanged.  stats may be NULL. */
+jfmg_status jfmg_implicit_step(jfmg_problem* p, double* U, jfmg_stats* stats);
+
+/* ---- finer-grained calls on the preconditioner's pieces (FV vectors in the
+        problem's multigrid precision) ---- */
+
+/* u = T^mf U (DG -> finest FV level) or U = T^-1,mf u (FV -> DG), dir 0 / 1
+   (Sec. "Transfer functions", eq. transfer-mass-fix, appendix weights). */
+jfmg_status jfmg_transfer(jfmg_problem* p, int dir, const void* in, void* out);
+/* coarse = R fine (agglomeration average, fine_level -> fine_level+1) */
+jfmg_status jfmg_restrict(jfmg_problem* p, int fine_level, const void* fine, void* coarse);
+/* fine = P coarse (injection, coarse_level -> coarse_level-1) */
+jfmg_status jfmg_prolong(jfmg_problem* p, int coarse_level, const void* coarse, void* fine);
+/* Copy of the linearization state u_l of `level`; ESTATE without linearize. */
+jfmg_status jfmg_fv_level_state(jfmg_problem* p, int level, void* u);
+/* Pseudo time step of `level` (host double; synchronizes). */
+jfmg_status jfmg_fv_dtau(jfmg_problem* p, int level, double* dtau);
+/* out = g'_l(u_l) x = x - (alpha dt/eps)(f_low(u_l + eps x) - f_low(u_l)),
+   eps = sqrt(eps_p) ||u_l + Ubar|| / ||x||. */
+jfmg_status jfmg_fv_matvec(jfmg_problem* p, int level, const void* x, void* out);
+/* x = MG_L(0, b; u_L): one multigrid cycle on the FV levels from x = 0. */
+jfmg_status jfmg_mg_fv(jfmg_problem* p, const void* b, void* x);
+/* fv_to_dg[J*nxf + I] = e*(k+1)^2 + node of the DG node whose subcell is (I,J). */
+jfmg_status jfmg_subgrid_map(jfmg_problem* p, int* fv_to_dg);
+
+/* ---- kernel-class timing (benchmark instrumentation) ----
+   When a class's bit is set in class_mask, every launch of that class is
+   bracketed by two HIP events on the problem's stream; jfmg_profile_read
+   returns per class the summed event time [ms], the launch count and the
+   summed algorithmic HBM bytes (what the launch must read and write at
+   minimum, e.g. 5 FV vectors for a smoother stage with a matvec).  Enabling
+   resets the counters and synchronizes the stream. */
+typedef enum {
+    JFMG_K_DG_RESIDUAL = 0,   /* stage residual G and ||G||                         */
+    JFMG_K_DG_JVP = 1,        /* fused FD Jacobian-vector product                   */
+    JFMG_K_FV_STAGE = 2,      /* RK smoother stage with an FV matvec                */
+    JFMG_K_FV_STAGE_ZERO = 3, /* first stage from x = 0 (no matvec)                 */
+    JFMG_K_FV_DEFECT = 4,     /* defect + agglomeration restriction                 */
+    JFMG_K_FV_PROLONG = 5,    /* injection prolongation + correction               */
+    JFMG_K_FV_LINEARIZE = 6,  /* f_low(u_l), ||u_l + Ubar||, pseudo time step       */
+    JFMG_K_TRANSFER_T = 7,    /* DG -> FV                                           */
+    JFMG_K_TRANSFER_TINV = 8, /* FV -> DG                                           */
+    JFMG_K_MULTIDOT = 9,      /* Arnoldi <w, v_i>                                   */
+    JFMG_K_UPDATE = 10,       /* Arnoldi w -= V h                                   */
+    JFMG_K_NCLASS = 11
+} jfmg_kernel_class;
+jfmg_status jfmg_profile_enable(jfmg_problem* p, unsigned class_mask);
+/* ms, launches and bytes are host arrays of JFMG_K_NCLASS entries. */
+jfmg_status jfmg_profile_read(jfmg_problem* p, double* ms, long long* launches, double* bytes);
+
+/* Message of the last failed call on p (or of the last failed creation if p is NULL). */
+const char* jfmg_last_error(const jfmg_problem* p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* JFMG_H */

@@ -1,0 +1,446 @@
+// DG space operator of the well-balanced perturbation system (paper eqs.
+// convDiscr, elementint, surfaceint and perturbed-euler) on gfx950.
+//
+// One work-group holds EPB whole elements, one thread per GL node (k = 3: 8
+// elements x 16 nodes = 128 threads).  Element values are staged in LDS; each
+// thread then
+//   B  evaluates the volume flux at its node (total state U' + Ubar minus the
+//      background flux, minus the viscous flux) into LDS,
+//   C1 loads the neighbour element's trace and normal derivative at one face
+//      point from global memory into LDS (faces are recomputed from both sides;
+//      this costs flops, not HBM bytes),
+//   C2 evaluates HLLC minus the background HLLC, the interior-penalty terms
+//      and the symmetric term at that face point,
+//   D  contracts the volume fluxes with the GL derivative matrix, lifts the
+//      face terms to its node and writes the requested output.
+// The same kernel in JVP mode carries two states, U' and U' + eps y, and
+// differences the fluxes point by point before contracting.
+#include "jfmg_internal.h"
+
+namespace jfmg {
+
+template <int N1> struct DgShape {
+    static constexpr int NP = N1 * N1;
+    static constexpr int NTH = (N1 == 2) ? 64 : 128;
+    static constexpr int EPB = NTH / NP;
+};
+
+__device__ __forceinline__ int face_nb(int f, int ex, int ez, int nx, int nz, int bc)
+{
+    // returns neighbour element index, or -1 for a slip wall
+    if (f == 0) { if (ex > 0) return ez * nx + ex - 1; return bc == 1 ? ez * nx + nx - 1 : -1; }
+    if (f == 1) { if (ex < nx - 1) return ez * nx + ex + 1; return bc == 1 ? ez * nx : -1; }
+    if (f == 2) return ez > 0 ? (ez - 1) * nx + ex : -1;
+    return ez < nz - 1 ? (ez + 1) * nx + ex : -1;
+}
+
+template <int N1, bool NS, int MODE>
+__global__ void __launch_bounds__(DgShape<N1>::NTH)
+dg_kernel(DgArgs A, const double* __restrict__ U, const double* __restrict__ Y, const double* __restrict__ Ubar,
+          double* __restrict__ out, const double* __restrict__ yn2p, const double* __restrict__ ut2p, int eps_mode,
+          double adt, Red red)
+{
+    constexpr int NP = DgShape<N1>::NP, NTH = DgShape<N1>::NTH, EPB = DgShape<N1>::EPB;
+    constexpr int NSt = (MODE == 3) ? 2 : 1;
+    __shared__ double sS[NSt][EPB][4][NP];
+    __shared__ double sFx[EPB][4][NP], sFz[EPB][4][NP];
+    __shared__ double sTx[NSt][EPB][4][N1][4];
+    __shared__ double sNx[NS ? NSt : 1][NS ? EPB : 1][4][N1][4];
+    __shared__ double sFc[EPB][4][N1][4];
+    __shared__ double sSy[NS ? EPB : 1][4][N1][4];
+
+    const int t = threadIdx.x;
+    const int le = t / NP, nd = t - le * NP;
+    const bool act = le < EPB;
+    const long e = (long)blockIdx.x * EPB + le;
+    const bool valid = act && e < A.ne;
+    const int ez = valid ? (int)(e / A.nx) : 0;
+    const int ex = valid ? (int)(e - (long)ez * A.nx) : 0;
+    const long N = A.ne * NP;
+    const RefTab& R = A.R;
+
+    double eps = 0.0;
+    if constexpr (MODE == 3) {
+        const double yn2 = yn2p[0];
+        if (!(yn2 > 0.0)) {   // y = 0: the product is 0 (uniform over the grid)
+            if (valid)
+                for (int c = 0; c < 4; ++c) out[c * N + e * NP + nd] = 0.0;
+            return;
+        }
+        eps = eps_mode == 0 ? FdEps<double>::sqrt_eps / sqrt(yn2)
+                            : FdEps<double>::sqrt_eps * sqrt(ut2p[0]) / sqrt(yn2);
+    }
+
+    // ---- A: stage element values ----
+    double yv[4] = {0, 0, 0, 0};
+    if (act) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const double u = valid ? U[c * N + e * NP + nd] : 0.0;
+            sS[0][le][c][nd] = u;
+            if constexpr (MODE == 3) {
+                yv[c] = valid ? Y[c * N + e * NP + nd] : 0.0;
+                sS[1][le][c][nd] = u + eps * yv[c];
+            }
+        }
+    }
+    __syncthreads();
+
+    const int a = nd % N1, b = nd / N1;
+    // ---- B: volume fluxes ----
+    if (act) {
+        double Ub[4], dUb[4];
+        const int zi = ez * N1 + b;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) { Ub[c] = A.bg_node[zi * 4 + c]; dUb[c] = A.dbg_node[zi * 4 + c]; }
+        double fx[4], fz[4];
+#pragma unroll
+        for (int s = 0; s < NSt; ++s) {
+            double Ut[4], Fx[4], Fz[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) Ut[c] = sS[s][le][c][nd] + Ub[c];
+            conv_flux(A.gas, Ut, 1.0, 0.0, Fx);
+            conv_flux(A.gas, Ut, 0.0, 1.0, Fz);
+            if constexpr (MODE != 3) {
+                double Bx[4], Bz[4];
+                conv_flux(A.gas, Ub, 1.0, 0.0, Bx);
+                conv_flux(A.gas, Ub, 0.0, 1.0, Bz);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) { Fx[c] -= Bx[c]; Fz[c] -= Bz[c]; }
+            }
+            if constexpr (NS) {
+                double Gx[4], Gz[4], Vx[4], Vz[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    double sx = 0.0, sz = 0.0;
+#pragma unroll
+                    for (int j = 0; j < N1; ++j) {
+                        sx += R.D[a][j] * sS[s][le][c][b * N1 + j];
+                        sz += R.D[b][j] * sS[s][le][c][j * N1 + a];
+                    }
+                    Gx[c] = (2.0 / A.dx) * sx;
+                    Gz[c] = (2.0 / A.dz) * sz + dUb[c];
+                }
+                visc_flux(A.mu, Ut, Gx, Gz, 1.0, 0.0, Vx);
+                visc_flux(A.mu, Ut, Gx, Gz, 0.0, 1.0, Vz);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) { Fx[c] -= Vx[c]; Fz[c] -= Vz[c]; }
+            }
+            if (s == 0) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) { fx[c] = Fx[c]; fz[c] = Fz[c]; }
+            } else {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) { fx[c] = Fx[c] - fx[c]; fz[c] = Fz[c] - fz[c]; }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) { sFx[le][c][nd] = fx[c]; sFz[le][c][nd] = fz[c]; }
+    }
+
+    // ---- C1: neighbour traces (and normal derivatives) at the face points ----
+    if (act) {
+        for (int fp = nd; fp < 4 * N1; fp += NP) {
+            const int f = fp / N1, r = fp - f * N1;
+            const bool xf = f < 2;
+            const int side = (f == 0 || f == 2) ? -1 : 1;
+            const double* eo = side > 0 ? R.em : R.ep;
+            const double* dso = side > 0 ? R.dm : R.dp;
+            const int nb = valid ? face_nb(f, ex, ez, A.nx, A.nz, A.bc) : -1;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                double tr[NSt], dn[NSt];
+#pragma unroll
+                for (int s = 0; s < NSt; ++s) { tr[s] = 0.0; dn[s] = 0.0; }
+                if (nb >= 0) {
+#pragma unroll
+                    for (int j = 0; j < N1; ++j) {
+                        const int idx = xf ? r * N1 + j : j * N1 + r;
+                        const double v = U[c * N + (long)nb * NP + idx];
+                        tr[0] += eo[j] * v;
+                        if constexpr (NS) dn[0] += dso[j] * v;
+                        if constexpr (MODE == 3) {
+                            const double v1 = v + eps * Y[c * N + (long)nb * NP + idx];
+                            tr[1] += eo[j] * v1;
+                            if constexpr (NS) dn[1] += dso[j] * v1;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int s = 0; s < NSt; ++s) {
+                    sTx[s][le][f][r][c] = tr[s];
+                    if constexpr (NS) sNx[s][le][f][r][c] = dn[s];
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- C2: face fluxes ----
+    if (act) {
+        for (int fp = nd; fp < 4 * N1; fp += NP) {
+            const int f = fp / N1, r = fp - f * N1;
+            const bool xf = f < 2;
+            const int side = (f == 0 || f == 2) ? -1 : 1;
+            const double nxn = xf ? (double)side : 0.0, nzn = xf ? 0.0 : (double)side;
+            const double* es = side > 0 ? R.ep : R.em;
+            const double* ds = side > 0 ? R.dp : R.dm;
+            const double hperp = xf ? A.dx : A.dz, htan = xf ? A.dz : A.dx;
+            const double flen = xf ? A.dz : A.dx;
+            const bool wall = !valid || face_nb(f, ex, ez, A.nx, A.nz, A.bc) < 0;
+            double Ub[4], dUb[4];
+            const int zrow = xf ? (ez * N1 + r) : (ez + (side > 0 ? 1 : 0));
+            const double* bgp = xf ? A.bg_node : A.bg_face;
+            const double* dbgp = xf ? A.dbg_node : A.dbg_face;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) { Ub[c] = bgp[zrow * 4 + c]; dUb[c] = dbgp[zrow * 4 + c]; }
+            double flux[4] = {0, 0, 0, 0}, sym[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < NSt; ++s) {
+                double tro[4], Uo[4], Ux[4], H[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int j = 0; j < N1; ++j) v += es[j] * sS[s][le][c][xf ? r * N1 + j : j * N1 + r];
+                    tro[c] = v;
+                    Uo[c] = v + Ub[c];
+                }
+                if (wall) {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) Ux[c] = Uo[c];
+                    if (xf) Ux[1] = -Uo[1]; else Ux[2] = -Uo[2];
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) Ux[c] = sTx[s][le][f][r][c] + Ub[c];
+                }
+                hllc(A.gas, Uo, Ux, nxn, nzn, H);
+                double fl[4], sy[4] = {0, 0, 0, 0};
+                if constexpr (MODE != 3) {
+                    double Um[4], Hb[4];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) Um[c] = Ub[c];
+                    if (wall) { if (xf) Um[1] = -Ub[1]; else Um[2] = -Ub[2]; }
+                    hllc(A.gas, Ub, Um, nxn, nzn, Hb);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) H[c] -= Hb[c];
+                }
+#pragma unroll
+                for (int c = 0; c < 4; ++c) fl[c] = -H[c];
+                if constexpr (NS) {
+                    if (!wall) {
+                        double Gxo[4], Gzo[4], Gxx[4], Gzx[4], Fo[4], Fxx[4];
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            double sn = 0.0, st_o = 0.0, st_x = 0.0;
+#pragma unroll
+                            for (int j = 0; j < N1; ++j) sn += ds[j] * sS[s][le][c][xf ? r * N1 + j : j * N1 + r];
+#pragma unroll
+                            for (int q = 0; q < N1; ++q) {
+                                double trq = 0.0;
+#pragma unroll
+                                for (int j = 0; j < N1; ++j) trq += es[j] * sS[s][le][c][xf ? q * N1 + j : j * N1 + q];
+                                st_o += R.D[r][q] * trq;
+                                st_x += R.D[r][q] * sTx[s][le][f][q][c];
+                            }
+                            const double gn_o = (2.0 / hperp) * sn, gn_x = (2.0 / hperp) * sNx[s][le][f][r][c];
+                            const double gt_o = (2.0 / htan) * st_o, gt_x = (2.0 / htan) * st_x;
+                            if (xf) {
+                                Gxo[c] = gn_o; Gxx[c] = gn_x;
+                                Gzo[c] = gt_o + dUb[c]; Gzx[c] = gt_x + dUb[c];
+                            } else {
+                                Gzo[c] = gn_o + dUb[c]; Gzx[c] = gn_x + dUb[c];
+                                Gxo[c] = gt_o; Gxx[c] = gt_x;
+                            }
+                        }
+                        visc_flux(A.mu, Uo, Gxo, Gzo, nxn, nzn, Fo);
+                        visc_flux(A.mu, Ux, Gxx, Gzx, nxn, nzn, Fxx);
+                        const double eta = A.c_ip * (double)(N1 * N1) / hperp;
+                        double Dl[4], Um[4];
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            Dl[c] = tro[c] - sTx[s][le][f][r][c];
+                            Um[c] = 0.5 * (Uo[c] + Ux[c]);
+                        }
+#pragma unroll
+                        for (int c = 1; c < 4; ++c) {
+                            const double pen = eta * A.mu * (Dl[c] - (Um[c] / Um[0]) * Dl[0]);
+                            fl[c] += 0.5 * (Fo[c] + Fxx[c]) - pen;
+                            sy[c] = 0.5 * A.mu * (Dl[c] - (Uo[c] / Uo[0]) * Dl[0]);
+                        }
+                    }
+                }
+                if (s == 0) {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) { flux[c] = fl[c]; sym[c] = sy[c]; }
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) { flux[c] = fl[c] - flux[c]; sym[c] = sy[c] - sym[c]; }
+                }
+            }
+            const double W = R.w[r] * flen * 0.5;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                sFc[le][f][r][c] = W * flux[c];
+                if constexpr (NS) sSy[le][f][r][c] = W * sym[c];
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- D: contraction, lifting and output ----
+    double nrm = 0.0;
+    if (valid) {
+        const double m = R.w[a] * R.w[b] * A.J;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            double sx = 0.0, sz = 0.0;
+#pragma unroll
+            for (int q = 0; q < N1; ++q) sx += R.w[q] * R.D[q][a] * sFx[le][c][b * N1 + q];
+#pragma unroll
+            for (int q = 0; q < N1; ++q) sz += R.w[q] * R.D[q][b] * sFz[le][c][q * N1 + a];
+            double L = A.J * ((2.0 / A.dx) * R.w[b] * sx + (2.0 / A.dz) * R.w[a] * sz);
+            L += sFc[le][0][b][c] * R.em[a] + sFc[le][1][b][c] * R.ep[a];
+            L += sFc[le][2][a][c] * R.em[b] + sFc[le][3][a][c] * R.ep[b];
+            if constexpr (NS) {
+                L += sSy[le][0][b][c] * (-(2.0 / A.dx) * R.dm[a]) + sSy[le][1][b][c] * ((2.0 / A.dx) * R.dp[a]);
+                L += sSy[le][2][a][c] * (-(2.0 / A.dz) * R.dm[b]) + sSy[le][3][a][c] * ((2.0 / A.dz) * R.dp[b]);
+            }
+            if (c == 2) {
+                if constexpr (MODE == 3) L += m * (-A.g * (sS[1][le][0][nd] - sS[0][le][0][nd]));
+                else L += m * (-A.g * sS[0][le][0][nd]);
+            }
+            const long o = c * N + e * NP + nd;
+            if constexpr (MODE == 0) out[o] = L;
+            else if constexpr (MODE == 1) out[o] = L / m;
+            else if constexpr (MODE == 2) {
+                const double G = sS[0][le][c][nd] - adt * (L / m) - Ubar[o];
+                out[o] = G;
+                nrm += G * G;
+            } else {
+                out[o] = yv[c] - (adt / eps) * (L / m);
+            }
+        }
+    }
+    if constexpr (MODE == 2) put_partial<NTH>(red, nrm);
+}
+
+int dg_grid(int k, long ne)
+{
+    const int epb = k == 1 ? DgShape<2>::EPB : k == 2 ? DgShape<3>::EPB : DgShape<4>::EPB;
+    return (int)((ne + epb - 1) / epb);
+}
+
+template <int N1, bool NS>
+static void launch_dg_n(int mode, const DgArgs& A, const double* U, const double* Y, const double* Ubar,
+                        double* out, const double* yn2, const double* ut2, int eps_mode, double adt, Red red,
+                        hipStream_t st)
+{
+    const dim3 grid(dg_grid(N1 - 1, A.ne)), block(DgShape<N1>::NTH);
+    if (mode == 2 && red.out) {
+        dg_kernel<N1, NS, 2><<<grid, block, 0, st>>>(A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red);
+        launch_finalize(red.partials, (int)grid.x, 1, red.out, st);
+        return;
+    }
+    switch (mode) {
+    case 0: dg_kernel<N1, NS, 0><<<grid, block, 0, st>>>(A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red); break;
+    case 1: dg_kernel<N1, NS, 1><<<grid, block, 0, st>>>(A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red); break;
+    case 2: dg_kernel<N1, NS, 2><<<grid, block, 0, st>>>(A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red); break;
+    default: dg_kernel<N1, NS, 3><<<grid, block, 0, st>>>(A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red); break;
+    }
+}
+
+void launch_dg(int k, bool ns, int mode, const DgArgs& A, const double* U, const double* Y, const double* Ubar,
+               double* out, const double* yn2, const double* ut2, int eps_mode, double adt, Red red, hipStream_t st)
+{
+    if (k == 1) { if (ns) launch_dg_n<2, true>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st);
+                  else launch_dg_n<2, false>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st); }
+    else if (k == 2) { if (ns) launch_dg_n<3, true>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st);
+                       else launch_dg_n<3, false>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st); }
+    else { if (ns) launch_dg_n<4, true>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st);
+           else launch_dg_n<4, false>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st); }
+}
+
+// ---------------------------------------------------------------------------
+// Initial data (eq. add-perturbation): theta' inserted at constant pressure.
+// ---------------------------------------------------------------------------
+template <int N1>
+__global__ void __launch_bounds__(256)
+init_kernel(DgArgs A, int shape, double amp, double xc, double zc, double xr, double zr, double aa, double Z,
+            double x0, double z0, double u_mean, double* __restrict__ U)
+{
+    constexpr int NP = N1 * N1;
+    const long n = A.ne * NP;
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const long e = i / NP;
+    const int nd = (int)(i - e * NP);
+    const int a = nd % N1, b = nd / N1;
+    const int ez = (int)(e / A.nx), ex = (int)(e - (long)ez * A.nx);
+    const double x = x0 + (ex + 0.5 * (1.0 + A.R.xi[a])) * A.dx;
+    const double z = z0 + (ez + 0.5 * (1.0 + A.R.xi[b])) * A.dz;
+    double th1 = 0.0;
+    if (shape == 0) {
+        const double rx = (x - xc) / xr, rz = (z - zc) / zr;
+        const double r = sqrt(rx * rx + rz * rz);
+        if (r < 1.0) th1 = 0.5 * amp * (1.0 + cos(M_PI * r));
+    } else {
+        const double s = (x - xc) / aa;
+        th1 = amp / (1.0 + s * s) * sin(M_PI * z / Z);
+    }
+    const int zi = ez * N1 + b;
+    const double rt = A.bg_node[zi * 4 + 3], rhob = A.bg_node[zi * 4 + 0], mb = A.bg_node[zi * 4 + 1];
+    const double rho = rt / (A.th_node[zi] + th1);
+    U[i] = rho - rhob;
+    U[n + i] = rho * u_mean - mb;
+    U[2 * n + i] = 0.0;
+    U[3 * n + i] = 0.0;
+}
+
+void launch_initial_state(int k, const DgArgs& A, int shape, double amp, double xc, double zc, double xr, double zr,
+                          double a, double Z, double x0, double z0, double u_mean, double* U, hipStream_t st)
+{
+    const long n = A.ne * (k + 1) * (k + 1);
+    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    if (k == 1) init_kernel<2><<<grid, block, 0, st>>>(A, shape, amp, xc, zc, xr, zr, a, Z, x0, z0, u_mean, U);
+    else if (k == 2) init_kernel<3><<<grid, block, 0, st>>>(A, shape, amp, xc, zc, xr, zr, a, Z, x0, z0, u_mean, U);
+    else init_kernel<4><<<grid, block, 0, st>>>(A, shape, amp, xc, zc, xr, zr, a, Z, x0, z0, u_mean, U);
+}
+
+// sum over all nodes and components of (U' + Ubar)^2
+template <int N1>
+__global__ void __launch_bounds__(256) norm_total_kernel(DgArgs A, const double* __restrict__ U, Red red)
+{
+    constexpr int NP = N1 * N1;
+    const long n = A.ne * NP;
+    double s = 0.0;
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+        const long e = i / NP;
+        const int b = (int)(i - e * NP) / N1;
+        const int zi = (int)(e / A.nx) * N1 + b;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const double v = U[c * n + i] + A.bg_node[zi * 4 + c];
+            s += v * v;
+        }
+    }
+    put_partial<256>(red, s);
+}
+
+int norm_total_grid(long n)
+{
+    long b = (n + 255) / 256;
+    return (int)(b < 1024 ? b : 1024);
+}
+
+void launch_norm2_total(int k, const DgArgs& A, const double* U, Red red, hipStream_t st)
+{
+    const long n = A.ne * (k + 1) * (k + 1);
+    const dim3 grid(norm_total_grid(n)), block(256);
+    if (k == 1) norm_total_kernel<2><<<grid, block, 0, st>>>(A, U, red);
+    else if (k == 2) norm_total_kernel<3><<<grid, block, 0, st>>>(A, U, red);
+    else norm_total_kernel<4><<<grid, block, 0, st>>>(A, U, red);
+    launch_finalize(red.partials, (int)grid.x, 1, red.out, st);
+}
+
+}  // namespace jfmg

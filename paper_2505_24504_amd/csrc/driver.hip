@@ -1,0 +1,1182 @@
+// Host side of the library: configuration checks, reference-element and
+// background tables, workspace carving, the stage solver (inexact Newton with
+// Eisenstat-Walker forcing, right-preconditioned FGMRES, the FV multigrid
+// V/W-cycle) and the C-ABI of include/jfmg.h.  All vector work runs in the
+// kernels of dg.hip, transfer.hip, fv.hip and la.hip on the problem's stream;
+// the host keeps only the small Hessenberg least-squares problem.
+#include "jfmg.h"
+#include "jfmg_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace jfmg;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+// ---------------------------------------------------------------------------
+// Reference element: Gauss-Legendre nodes (Newton on P_{k+1}), barycentric
+// Lagrange evaluation, the GL differentiation matrix, the subcell-centre
+// interpolation matrix and its inverse, the modified Newton-Cotes weights.
+// ---------------------------------------------------------------------------
+void legendre_pd(int n, double x, double& p, double& d)
+{
+    double pm = 1.0, pc = x;
+    for (int m = 1; m < n; ++m) {
+        const double pn = ((2 * m + 1) * x * pc - m * pm) / (m + 1);
+        pm = pc;
+        pc = pn;
+    }
+    p = (n == 0) ? 1.0 : pc;
+    d = (n == 0) ? 0.0 : n * (pm - x * pc) / (1.0 - x * x);
+}
+
+void gl_rule(int n, double* x, double* w)
+{
+    for (int i = 0; i < n; ++i) {
+        double r = std::cos(M_PI * (4.0 * (n - 1 - i) + 3.0) / (4.0 * n + 2.0));
+        for (int it = 0; it < 60; ++it) {
+            double p, d;
+            legendre_pd(n, r, p, d);
+            const double step = p / d;
+            r -= step;
+            if (std::fabs(step) <= 1e-17) break;
+        }
+        double p, d;
+        legendre_pd(n, r, p, d);
+        x[i] = r;
+        w[i] = 2.0 / ((1.0 - r * r) * d * d);
+    }
+}
+
+struct Bary {
+    int n;
+    double x[MAXN1], bw[MAXN1];
+    void init(int n_, const double* xs)
+    {
+        n = n_;
+        for (int j = 0; j < n; ++j) {
+            x[j] = xs[j];
+            double p = 1.0;
+            for (int m = 0; m < n; ++m)
+                if (m != j) p *= (xs[j] - xs[m]);
+            bw[j] = 1.0 / p;
+        }
+    }
+    void eval(double t, double* l) const   // all basis values at t
+    {
+        for (int j = 0; j < n; ++j)
+            if (t == x[j]) {
+                for (int m = 0; m < n; ++m) l[m] = (m == j) ? 1.0 : 0.0;
+                return;
+            }
+        double den = 0.0;
+        for (int j = 0; j < n; ++j) den += bw[j] / (t - x[j]);
+        for (int j = 0; j < n; ++j) l[j] = (bw[j] / (t - x[j])) / den;
+    }
+    void deriv(double t, double* d) const   // all basis derivatives at a non-node t
+    {
+        double l[MAXN1];
+        eval(t, l);
+        for (int j = 0; j < n; ++j) {
+            double s = 0.0;
+            for (int m = 0; m < n; ++m)
+                if (m != j) s += 1.0 / (t - x[m]);
+            d[j] = l[j] * s;
+        }
+    }
+};
+
+bool invert(int n, const double A[MAXN1][MAXN1], double Ai[MAXN1][MAXN1])
+{
+    double M[MAXN1][2 * MAXN1];
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < 2 * n; ++j) M[i][j] = j < n ? A[i][j] : (j - n == i ? 1.0 : 0.0);
+    for (int c = 0; c < n; ++c) {
+        int p = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(M[r][c]) > std::fabs(M[p][c])) p = r;
+        if (M[p][c] == 0.0) return false;
+        if (p != c)
+            for (int j = 0; j < 2 * n; ++j) std::swap(M[p][j], M[c][j]);
+        const double inv = 1.0 / M[c][c];
+        for (int j = 0; j < 2 * n; ++j) M[c][j] *= inv;
+        for (int r = 0; r < n; ++r) {
+            if (r == c || M[r][c] == 0.0) continue;
+            const double f = M[r][c];
+            for (int j = 0; j < 2 * n; ++j) M[r][j] -= f * M[c][j];
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) Ai[i][j] = M[i][n + j];
+    return true;
+}
+
+bool build_reftab(int k, RefTab& R)
+{
+    const int n = k + 1;
+    std::memset(&R, 0, sizeof(R));
+    gl_rule(n, R.xi, R.w);
+    Bary B;
+    B.init(n, R.xi);
+    // differentiation matrix D_ij = l_j'(xi_i) (barycentric form)
+    for (int i = 0; i < n; ++i) {
+        double diag = 0.0;
+        for (int j = 0; j < n; ++j) {
+            if (i == j) continue;
+            R.D[i][j] = (B.bw[j] / B.bw[i]) / (R.xi[i] - R.xi[j]);
+            diag -= R.D[i][j];
+        }
+        R.D[i][i] = diag;
+    }
+    B.eval(-1.0, R.em);
+    B.eval(1.0, R.ep);
+    B.deriv(-1.0, R.dm);
+    B.deriv(1.0, R.dp);
+    for (int i = 0; i < n; ++i) B.eval(-1.0 + (2.0 * i + 1.0) / n, R.V[i]);
+    if (!invert(n, R.V, R.Vinv)) return false;
+    // interpolatory rule on the subcell centres of [0,1]: w_i = int_0^1 of the
+    // Lagrange polynomial through G_m = (2m+1)/(2(k+1)), integrated term by term
+    double G[MAXN1];
+    for (int m = 0; m < n; ++m) G[m] = (2.0 * m + 1.0) / (2.0 * n);
+    for (int i = 0; i < n; ++i) {
+        double coef[MAXN1 + 1] = {1.0};   // polynomial coefficients, lowest degree first
+        int deg = 0;
+        for (int m = 0; m < n; ++m) {
+            if (m == i) continue;
+            const double s = 1.0 / (G[i] - G[m]);
+            for (int d = deg + 1; d >= 0; --d) {
+                const double lower = d > 0 ? coef[d - 1] : 0.0;
+                coef[d] = (lower - G[m] * coef[d]) * s;
+            }
+            ++deg;
+        }
+        double integ = 0.0;
+        for (int d = deg; d >= 0; --d) integ += coef[d] / (d + 1);
+        R.wnc[i] = integ;
+    }
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// Background atmospheres (paper test cases): neutral theta = theta0 with
+// T = theta0 - g z / cp, p = p0 (T/theta0)^(cp/R); or constant N with
+// theta = T0 e^{z/H}, T = T0 (a - (a-1) e^{z/H}), p = p0 exp(cp/R (ln(T/T0) - z/H)),
+// H = g/N^2, a = g H/(cp T0), T0 = theta0.  rho theta = p0^{R/cp} p^{1/gamma}/R.
+// ---------------------------------------------------------------------------
+struct BgPoint {
+    double U[4], dU[4], theta;
+};
+
+BgPoint background_at(const jfmg_config& c, double z)
+{
+    const double cp = c.gamma * c.R / (c.gamma - 1.0);
+    double th, dth, p, dp;
+    if (c.background == 0) {
+        th = c.theta0;
+        dth = 0.0;
+        const double T = c.theta0 - c.g * z / cp;
+        p = c.p0 * std::pow(T / c.theta0, cp / c.R);
+        dp = -(c.g * c.p0 / (c.R * c.theta0)) * std::pow(T / c.theta0, cp / c.R - 1.0);
+    } else {
+        const double H = c.g / (c.N * c.N);
+        const double a = c.g * H / (cp * c.theta0);
+        const double ez = std::exp(z / H);
+        th = c.theta0 * ez;
+        dth = th / H;
+        const double T = c.theta0 * (a - (a - 1.0) * ez);
+        const double dT = -c.theta0 * (a - 1.0) * ez / H;
+        p = c.p0 * std::exp((cp / c.R) * (std::log(T / c.theta0) - z / H));
+        dp = p * (cp / c.R) * (dT / T - 1.0 / H);
+    }
+    const double C = std::pow(c.p0, c.R / cp) / c.R;
+    const double rt = C * std::pow(p, 1.0 / c.gamma);
+    const double drt = C * (1.0 / c.gamma) * std::pow(p, 1.0 / c.gamma - 1.0) * dp;
+    const double rho = rt / th;
+    const double drho = (drt - rho * dth) / th;
+    BgPoint b;
+    b.U[0] = rho; b.U[1] = rho * c.u_mean; b.U[2] = 0.0; b.U[3] = rt;
+    b.dU[0] = drho; b.dU[1] = drho * c.u_mean; b.dU[2] = 0.0; b.dU[3] = drt;
+    b.theta = th;
+    return b;
+}
+
+struct Key {
+    int a, b, c, d, e, f, cycle;
+};
+
+bool parse_key(const char* s, Key& k)
+{
+    if (std::strlen(s) != 9 || s[0] != 'm' || s[1] != 'g') return false;
+    int v[6];
+    for (int i = 0; i < 6; ++i) {
+        if (s[2 + i] < '0' || s[2 + i] > '9') return false;
+        v[i] = s[2 + i] - '0';
+    }
+    if (s[8] != 'V' && s[8] != 'W') return false;
+    k = {v[0], v[1], v[2], v[3], v[4], v[5], s[8] == 'V' ? 1 : 2};
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace layout
+// ---------------------------------------------------------------------------
+constexpr int NSCAL = 1024;
+// scalar slots
+enum {
+    S_G = 0,        // ||G||^2
+    S_UTOT = 1,     // ||U + Ubar||^2 (DG)
+    S_Y = 2,        // ||y||^2 for jvp
+    S_Z = 3,        // ||z_j||^2
+    S_W = 4,        // ||w||^2 after orthogonalization
+    S_R = 5,        // restart residual norm^2
+    S_TMP = 6,
+    S_LEV = 16,     // + 4*level: LV_* slots
+    S_H1 = 128,     // 65 entries
+    S_H2 = 256,     // 65 entries
+    S_Yc = 384      // 65 entries: FGMRES coefficients
+};
+
+struct Carve {
+    size_t off = 0;
+    char* base = nullptr;
+    void* take(size_t bytes)
+    {
+        off = (off + 255) & ~size_t(255);
+        void* p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    }
+};
+
+struct Level {
+    int nx, nz;
+    long nc;
+    double hx, hz;
+    void* u;
+    void* F0;
+    void* buf[3];
+    void* b;
+    void* bgc;
+    void* bgf;
+    void* dbgf;
+};
+
+}  // namespace
+
+struct jfmg_problem {
+    jfmg_config cfg;
+    Key key;
+    int n1, np;
+    long ne, N;
+    double dx, dz;
+    int nlev;
+    Level lev[MAXLEV];
+    int prec;          // 64 or 32
+    hipStream_t st;
+    RefTab R;
+    DgArgs A;
+    // device memory (in the caller's workspace)
+    double* scal;
+    double* partials;   // block partials of reductions that are finalized right away
+    size_t npartials;
+    double* fvpart;     // block partials of ||x||^2 of each FV buffer, [level][buffer][FVP]
+    size_t fvp;
+    int xcnt[MAXLEV][3];
+    double* bg_node; double* dbg_node; double* th_node; double* bg_face; double* dbg_face;
+    double *Un, *Ubar, *Uk, *G, *delta, *tmp1, *tmp2, *Ulin;
+    double *V, *Z;
+    int m;
+    // kernel-class timing (HIP events on st), used by the benchmark
+    struct Pend { int cls; hipEvent_t a, b; double bytes; };
+    struct Prof {
+        unsigned mask = 0;
+        std::vector<hipEvent_t> pool;
+        std::vector<Pend> pend;
+        double ms[JFMG_K_NCLASS] = {};
+        long long cnt[JFMG_K_NCLASS] = {};
+        double bytes[JFMG_K_NCLASS] = {};
+    } prof;
+    // host side
+    int have_lin;
+    double adt;
+    std::string err;
+    jfmg_stats* stats;
+    int mv_count[MAXLEV];
+    int lh_count, jvp_count, syncs;
+    std::vector<double> hbuf;
+};
+
+namespace {
+
+jfmg_status fail(jfmg_problem* p, jfmg_status s, const std::string& msg)
+{
+    if (p) p->err = msg;
+    else g_create_error = msg;
+    return s;
+}
+
+#define HIPCHK(p, call)                                                                  \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess) return fail((p), JFMG_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+hipEvent_t ev_get(jfmg_problem* p)
+{
+    hipEvent_t e = nullptr;
+    if (!p->prof.pool.empty()) {
+        e = p->prof.pool.back();
+        p->prof.pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        e = nullptr;
+    }
+    return e;
+}
+
+// Records a HIP event pair around one launch of kernel class `cls` when that
+// class is being profiled; `bytes` is the launch's algorithmic HBM traffic.
+struct ProfScope {
+    jfmg_problem* p;
+    int cls;
+    double bytes;
+    hipEvent_t a = nullptr;
+    ProfScope(jfmg_problem* p_, int c, double b) : p(p_), cls(c), bytes(b)
+    {
+        if (p->prof.mask & (1u << cls)) {
+            a = ev_get(p);
+            if (a) (void)hipEventRecord(a, p->st);
+        }
+    }
+    ~ProfScope()
+    {
+        if (!a) return;
+        hipEvent_t b = ev_get(p);
+        if (!b) return;
+        (void)hipEventRecord(b, p->st);
+        p->prof.pend.push_back({cls, a, b, bytes});
+    }
+};
+
+void prof_flush(jfmg_problem* p)
+{
+    for (auto& q : p->prof.pend) {
+        float ms = 0.f;
+        if (hipEventSynchronize(q.b) == hipSuccess && hipEventElapsedTime(&ms, q.a, q.b) == hipSuccess) {
+            p->prof.ms[q.cls] += ms;
+            p->prof.cnt[q.cls] += 1;
+            p->prof.bytes[q.cls] += q.bytes;
+        }
+        p->prof.pool.push_back(q.a);
+        p->prof.pool.push_back(q.b);
+    }
+    p->prof.pend.clear();
+}
+
+jfmg_status check_launch(jfmg_problem* p)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(p, JFMG_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    return JFMG_OK;
+}
+
+jfmg_status validate(const jfmg_config& c, Key& key, std::string& msg)
+{
+    if (c.k < 1 || c.k > 3) { msg = "k must be 1, 2 or 3"; return JFMG_EINVAL; }
+    if (c.nx < 1 || c.nz < 1) { msg = "nx, nz must be positive"; return JFMG_EINVAL; }
+    if (!(c.x1 > c.x0) || !(c.z1 > c.z0)) { msg = "empty domain"; return JFMG_EINVAL; }
+    if (c.physics < 0 || c.physics > 1 || c.background < 0 || c.background > 1 || c.bc < 0 || c.bc > 1 ||
+        c.scheme < 0 || c.scheme > 1) { msg = "physics/background/bc/scheme out of range"; return JFMG_EINVAL; }
+    if (c.background == 1 && !(c.N > 0)) { msg = "constant-N background needs N > 0"; return JFMG_EINVAL; }
+    if (c.gmres_m < 1 || c.gmres_m > 64) { msg = "gmres_m must be in 1..64"; return JFMG_EINVAL; }
+    if (c.rk_stages < 1 || c.rk_stages > 4) { msg = "rk_stages must be in 1..4"; return JFMG_EINVAL; }
+    if (c.mg_levels < 1 || c.mg_levels > MAXLEV) { msg = "mg_levels must be in 1..8"; return JFMG_EINVAL; }
+    if (c.mg_precision != 32 && c.mg_precision != 64) { msg = "mg_precision must be 32 or 64"; return JFMG_EINVAL; }
+    if (c.newton_maxit < 1 || c.gmres_max_restarts < 0) { msg = "bad iteration caps"; return JFMG_EINVAL; }
+    if (!(c.dt > 0) || !(c.gamma > 1) || !(c.R > 0) || !(c.p0 > 0) || !(c.theta0 > 0) || c.mu < 0) {
+        msg = "bad physical constants"; return JFMG_EINVAL;
+    }
+    char ks[16];
+    std::memcpy(ks, c.mg_key, 16);
+    ks[15] = 0;
+    if (!parse_key(ks, key)) { msg = "bad multigrid key (expected mgabcdefV or mgabcdefW)"; return JFMG_EINVAL; }
+    if (key.a || key.b) { msg = "DG-level smoothing counts a, b must be 0"; return JFMG_EINVAL; }
+    int nxl = (c.k + 1) * c.nx, nzl = (c.k + 1) * c.nz;
+    for (int l = 1; l < c.mg_levels; ++l) {
+        if ((nxl & 1) || (nzl & 1)) { msg = "an FV level dimension is odd before the coarsest level"; return JFMG_EINVAL; }
+        nxl /= 2;
+        nzl /= 2;
+    }
+    return JFMG_OK;
+}
+
+// Layout of the workspace; with base == nullptr it only measures.
+template <typename F>
+size_t layout(const jfmg_config& c, char* base, F&& bind)
+{
+    Carve cv;
+    cv.base = base;
+    const int n1 = c.k + 1, np = n1 * n1;
+    const long ne = (long)c.nx * c.nz, N = 4 * ne * np;
+    const size_t ts = c.mg_precision == 32 ? 4 : 8;
+    const int m = c.gmres_m;
+    const long la = (N + 1023) / 1024;
+    long nfv = (long)n1 * c.nx * n1 * c.nz;
+    long fvblk = ((n1 * c.nx + 15) / 16) * ((n1 * c.nz + 3) / 4);   // the smallest FV tile is 16 x 4
+    const long dgblk = ne;   // at most one block per element
+    size_t npart = (size_t)std::max<long>({la * (m + 2), 2 * fvblk, dgblk, 2048, 4096});
+    bind("scal", cv.take(NSCAL * 8), 0);
+    bind("partials", cv.take(npart * 8), npart);
+    const size_t fvp = (size_t)std::max<long>(fvblk, 1024);
+    bind("fvpart", cv.take(fvp * 3 * c.mg_levels * 8), fvp);
+    bind("bg_node", cv.take((size_t)c.nz * n1 * 4 * 8), 0);
+    bind("dbg_node", cv.take((size_t)c.nz * n1 * 4 * 8), 0);
+    bind("th_node", cv.take((size_t)c.nz * n1 * 8), 0);
+    bind("bg_face", cv.take((size_t)(c.nz + 1) * 4 * 8), 0);
+    bind("dbg_face", cv.take((size_t)(c.nz + 1) * 4 * 8), 0);
+    const char* dgn[] = {"Un", "Ubar", "Uk", "G", "delta", "tmp1", "tmp2", "Ulin"};
+    for (const char* s : dgn) bind(s, cv.take((size_t)N * 8), 0);
+    bind("V", cv.take((size_t)N * 8 * (m + 1)), 0);
+    bind("Z", cv.take((size_t)N * 8 * m), 0);
+    int nxl = n1 * c.nx, nzl = n1 * c.nz;
+    for (int l = 0; l < c.mg_levels; ++l) {
+        const long nc = (long)nxl * nzl;
+        const char* fvn[] = {"u", "F0", "x0", "x1", "x2", "b"};
+        for (const char* s : fvn) bind(s, cv.take((size_t)4 * nc * ts), l);
+        bind("bgc", cv.take((size_t)nzl * 4 * ts), l);
+        bind("bgf", cv.take((size_t)(nzl + 1) * 4 * ts), l);
+        bind("dbgf", cv.take((size_t)(nzl + 1) * 4 * ts), l);
+        nxl /= 2;
+        nzl /= 2;
+    }
+    (void)nfv;
+    return cv.off + 256;
+}
+
+Red red_at(jfmg_problem* p, int slot) { return Red{p->partials, p->scal + slot}; }
+Red no_red() { return Red{nullptr, nullptr}; }
+double* fvpart(jfmg_problem* p, int l, int bi) { return p->fvpart + (3 * l + bi) * p->fvp; }
+
+// read `count` device scalars starting at `slot` (synchronizes the stream)
+jfmg_status read_scalars(jfmg_problem* p, int slot, int count, double* out)
+{
+    HIPCHK(p, hipMemcpyAsync(out, p->scal + slot, sizeof(double) * count, hipMemcpyDeviceToHost, p->st));
+    HIPCHK(p, hipStreamSynchronize(p->st));
+    p->syncs++;
+    prof_flush(p);
+    return JFMG_OK;
+}
+
+template <typename T> FvArgs<T> fv_args(const jfmg_problem* p, int l)
+{
+    FvArgs<T> A;
+    const Level& L = p->lev[l];
+    A.nxl = L.nx; A.nzl = L.nz; A.bc = p->cfg.bc; A.physics = p->cfg.physics; A.nc = L.nc;
+    A.hx = (T)L.hx; A.hz = (T)L.hz; A.area = (T)(L.hx * L.hz); A.g = (T)p->cfg.g; A.mu = (T)p->cfg.mu;
+    A.gas = Gas<T>{(T)p->cfg.gamma, (T)p->cfg.R, (T)p->cfg.p0};
+    A.bgc = (const T*)L.bgc; A.bgf = (const T*)L.bgf; A.dbgf = (const T*)L.dbgf;
+    return A;
+}
+
+// ---------------------------------------------------------------------------
+// Linearization: ||U + Ubar||, u_0 = T^mf U, u_{l+1} = R u_l, f~(u_l), dtau_l
+// ---------------------------------------------------------------------------
+template <typename T> jfmg_status linearize_t(jfmg_problem* p, const double* U, double adt)
+{
+    hipStream_t st = p->st;
+    if (U != p->Ulin) HIPCHK(p, hipMemcpyAsync(p->Ulin, U, sizeof(double) * p->N, hipMemcpyDeviceToDevice, st));
+    p->adt = adt;
+    launch_norm2_total(p->cfg.k, p->A, p->Ulin, red_at(p, S_UTOT), st);
+    launch_transfer_T<T>(p->cfg.k, p->A, p->cfg.mass_fix, p->Ulin, (T*)p->lev[0].u, p->lev[0].nx, st);
+    for (int l = 0; l + 1 < p->nlev; ++l) FvLaunch<T>::restrict_(fv_args<T>(p, l), (const T*)p->lev[l].u, (T*)p->lev[l + 1].u, st);
+    for (int l = 0; l < p->nlev; ++l) {
+        ProfScope ps(p, JFMG_K_FV_LINEARIZE, 2.0 * 4.0 * p->lev[l].nc * sizeof(T));
+        FvLaunch<T>::lin_level(fv_args<T>(p, l), (const T*)p->lev[l].u, (T*)p->lev[l].F0, Red{p->partials, nullptr},
+                               p->scal + S_LEV + 4 * l, adt, p->cfg.pseudo_cfl, st);
+    }
+    p->have_lin = 1;
+    return check_launch(p);
+}
+
+jfmg_status linearize(jfmg_problem* p, const double* U, double adt)
+{
+    return p->prec == 32 ? linearize_t<float>(p, U, adt) : linearize_t<double>(p, U, adt);
+}
+
+// ---------------------------------------------------------------------------
+// Multigrid MG_l(x, b; u): smoother = s-stage low-storage explicit RK in
+// pseudo time with one uniform dtau per level; a zero flag replaces the
+// matvec with the zero vector.  Level 0 is the finest.
+// ---------------------------------------------------------------------------
+struct MgState {
+    int xi[MAXLEV];      // buffer holding x on each level
+    bool xzero[MAXLEV];  // x is the zero vector (buffer content not valid)
+};
+
+template <typename T> struct Mg {
+    jfmg_problem* p;
+    MgState s;
+    double alpha[4];
+
+    void smooth(int l, int nu)
+    {
+        const FvArgs<T> A = fv_args<T>(p, l);
+        Level& L = p->lev[l];
+        const int S = p->cfg.rk_stages;
+        for (int sw = 0; sw < nu; ++sw) {
+            const int i0 = s.xi[l];
+            const int oth[2] = {(i0 + 1) % 3, (i0 + 2) % 3};
+            int prev = i0;
+            for (int j = 0; j < S; ++j) {
+                const int out = oth[j & 1];
+                const int zero = (j == 0 && s.xzero[l]) ? 1 : 0;
+                const T* x0 = s.xzero[l] ? nullptr : (const T*)L.buf[i0];   // null: x^(0) = 0
+                const double vb = 4.0 * L.nc * sizeof(T);
+                ProfScope ps(p, zero ? JFMG_K_FV_STAGE_ZERO : JFMG_K_FV_STAGE, zero ? 2 * vb : (x0 ? 5 : 4) * vb);
+                p->xcnt[l][out] = FvLaunch<T>::stage(
+                    A, (const T*)L.u, (const T*)L.F0, (const T*)L.buf[prev], x0, (const T*)L.b, (T*)L.buf[out],
+                    fvpart(p, l, prev), p->xcnt[l][prev], p->scal + S_LEV + 4 * l, alpha[j], p->adt, zero,
+                    Red{fvpart(p, l, out), nullptr}, p->st);
+                if (!zero) p->mv_count[l]++;
+                prev = out;
+            }
+            s.xi[l] = prev;
+            s.xzero[l] = false;
+        }
+    }
+
+    void cycle(int l)
+    {
+        const Key& k = p->key;
+        const bool fine = (l == 0);
+        smooth(l, fine ? k.c : k.e);
+        if (l + 1 < p->nlev) {
+            const FvArgs<T> A = fv_args<T>(p, l);
+            Level& L = p->lev[l];
+            Level& C = p->lev[l + 1];
+            ProfScope ps(p, JFMG_K_FV_DEFECT, (s.xzero[l] ? 1.25 : 3.25) * 4.0 * L.nc * sizeof(T));
+            FvLaunch<T>::defect_restrict(A, (const T*)L.u, (const T*)L.F0, (const T*)L.buf[s.xi[l]], (const T*)L.b,
+                                         (T*)C.b, fvpart(p, l, s.xi[l]), p->xcnt[l][s.xi[l]],
+                                         p->scal + S_LEV + 4 * l, p->adt, s.xzero[l] ? 1 : 0, p->st);
+            if (!s.xzero[l]) p->mv_count[l]++;
+            s.xzero[l + 1] = true;
+            s.xi[l + 1] = 0;
+            for (int cyc = 0; cyc < k.cycle; ++cyc) cycle(l + 1);
+            if (!s.xzero[l + 1]) {
+                if (s.xzero[l]) {
+                    // x = 0 - P v: materialize the zero vector first
+                    hipMemsetAsync(L.buf[s.xi[l]], 0, sizeof(T) * 4 * L.nc, p->st);
+                }
+                ProfScope ps2(p, JFMG_K_FV_PROLONG, 2.25 * 4.0 * L.nc * sizeof(T));
+                p->xcnt[l][s.xi[l]] = FvLaunch<T>::prolong_correct(A, (T*)L.buf[s.xi[l]], (const T*)C.buf[s.xi[l + 1]],
+                                                                   Red{fvpart(p, l, s.xi[l]), nullptr}, p->st);
+                s.xzero[l] = false;
+            }
+        }
+        smooth(l, fine ? k.d : k.f);
+    }
+
+    // x = MG(0, b) on the finest level; b must be in lev[0].b; result pointer returned
+    T* run()
+    {
+        const int S = p->cfg.rk_stages;
+        for (int j = 0; j < 4; ++j) alpha[j] = p->cfg.rk_alpha[j] > 0 ? p->cfg.rk_alpha[j] : 1.0 / (S - j);
+        s.xi[0] = 0;
+        s.xzero[0] = true;
+        cycle(0);
+        Level& L = p->lev[0];
+        if (s.xzero[0]) hipMemsetAsync(L.buf[s.xi[0]], 0, sizeof(T) * 4 * L.nc, p->st);
+        return (T*)L.buf[s.xi[0]];
+    }
+};
+
+// z = Q^-1 r; ||z||^2 into slot zslot
+template <typename T> jfmg_status mg_apply_t(jfmg_problem* p, const double* r, double* z, int zslot)
+{
+    Level& L = p->lev[0];
+    {
+        ProfScope ps(p, JFMG_K_TRANSFER_T, (double)p->N * (8 + sizeof(T)));
+        launch_transfer_T<T>(p->cfg.k, p->A, p->cfg.mass_fix, r, (T*)L.b, L.nx, p->st);
+    }
+    Mg<T> mg{p};
+    T* x = mg.run();
+    ProfScope ps(p, JFMG_K_TRANSFER_TINV, (double)p->N * (8 + sizeof(T)));
+    launch_transfer_Tinv<T>(p->cfg.k, p->A, p->cfg.mass_fix, x, z, L.nx, red_at(p, zslot), p->st);
+    return check_launch(p);
+}
+
+jfmg_status precond(jfmg_problem* p, const double* r, double* z, int zslot)
+{
+    if (!p->cfg.precond) {
+        HIPCHK(p, hipMemcpyAsync(z, r, sizeof(double) * p->N, hipMemcpyDeviceToDevice, p->st));
+        launch_norm2(z, p->N, red_at(p, zslot), p->st);
+        return check_launch(p);
+    }
+    return p->prec == 32 ? mg_apply_t<float>(p, r, z, zslot) : mg_apply_t<double>(p, r, z, zslot);
+}
+
+// out = G'(U_lin) y with ||y||^2 already in slot yslot
+void jvp_slot(jfmg_problem* p, const double* y, double* out, int yslot)
+{
+    ProfScope ps(p, JFMG_K_DG_JVP, 3.0 * p->N * 8);
+    launch_dg(p->cfg.k, p->cfg.physics == 1, 3, p->A, p->Ulin, y, nullptr, out, p->scal + yslot, p->scal + S_UTOT,
+              p->cfg.fd_eps_mode, p->adt, no_red(), p->st);
+    p->jvp_count++;
+}
+
+// G = U - adt f(U) - Ubar and its norm (host)
+jfmg_status stage_residual(jfmg_problem* p, const double* U, const double* Ubar, double adt, double* G, double* nrm)
+{
+    {
+        ProfScope ps(p, JFMG_K_DG_RESIDUAL, 3.0 * p->N * 8);
+        launch_dg(p->cfg.k, p->cfg.physics == 1, 2, p->A, U, nullptr, Ubar, G, nullptr, nullptr, 0, adt, red_at(p, S_G),
+                  p->st);
+    }
+    p->lh_count++;
+    jfmg_status s = check_launch(p);
+    if (s) return s;
+    if (nrm) {
+        double v;
+        s = read_scalars(p, S_G, 1, &v);
+        if (s) return s;
+        *nrm = std::sqrt(v);
+    }
+    return JFMG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Right-preconditioned FGMRES(m) for G'(U) delta = -G, CGS2 Arnoldi on device,
+// Givens rotations on the host; U += delta on success.
+// ---------------------------------------------------------------------------
+jfmg_status fgmres(jfmg_problem* p, const double* G, double gnorm, double tol_abs, double* U, int* its_out)
+{
+    const long N = p->N;
+    const int m = p->m;
+    hipStream_t st = p->st;
+    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), y(m);
+    double beta = gnorm;
+    int its = 0;
+    // V_0 = -G / beta
+    launch_axpby(p->V, -1.0 / beta, G, 0.0, G, N, st);
+    HIPCHK(p, hipMemsetAsync(p->delta, 0, sizeof(double) * N, st));
+    jfmg_status status = JFMG_ENOCONV;
+    std::vector<double> hb(2 * 65 + 1);
+    for (int cyc = 0; cyc <= p->cfg.gmres_max_restarts; ++cyc) {
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int jend = 0;
+        bool conv = false;
+        for (int j = 0; j < m; ++j) {
+            double* vj = p->V + (long)j * N;
+            double* zj = p->Z + (long)j * N;
+            double* w = p->V + (long)(j + 1) * N;
+            jfmg_status s = precond(p, vj, zj, S_Z);
+            if (s) return s;
+            jvp_slot(p, zj, w, S_Z);
+            // classical Gram-Schmidt, twice
+            const double md = (j + 2.0) * N * 8, up = (j + 3.0) * N * 8;
+            { ProfScope ps(p, JFMG_K_MULTIDOT, md); launch_multidot(w, p->V, N, j + 1, N, red_at(p, S_H1), st); }
+            { ProfScope ps(p, JFMG_K_UPDATE, up); launch_update(w, p->V, N, j + 1, N, p->scal + S_H1, no_red(), st); }
+            { ProfScope ps(p, JFMG_K_MULTIDOT, md); launch_multidot(w, p->V, N, j + 1, N, red_at(p, S_H2), st); }
+            { ProfScope ps(p, JFMG_K_UPDATE, up); launch_update(w, p->V, N, j + 1, N, p->scal + S_H2, red_at(p, S_W), st); }
+            s = check_launch(p);
+            if (s) return s;
+            // one readback: h1, h2, ||w||^2
+            HIPCHK(p, hipMemcpyAsync(hb.data(), p->scal + S_H1, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, st));
+            HIPCHK(p, hipMemcpyAsync(hb.data() + 65, p->scal + S_H2, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, st));
+            HIPCHK(p, hipMemcpyAsync(hb.data() + 130, p->scal + S_W, sizeof(double), hipMemcpyDeviceToHost, st));
+            HIPCHK(p, hipStreamSynchronize(st));
+            p->syncs++;
+            for (int i = 0; i <= j; ++i) H[i * m + j] = hb[i] + hb[65 + i];
+            const double hn = std::sqrt(hb[130]);
+            H[(j + 1) * m + j] = hn;
+            if (hn > 0.0) launch_scale(w, w, N, p->scal + S_W, st);
+            for (int i = 0; i < j; ++i) {
+                const double a = H[i * m + j], b = H[(i + 1) * m + j];
+                H[i * m + j] = cs[i] * a + sn[i] * b;
+                H[(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+            }
+            const double a = H[j * m + j], b = H[(j + 1) * m + j];
+            const double rr = std::sqrt(a * a + b * b);
+            cs[j] = a / rr;
+            sn[j] = b / rr;
+            H[j * m + j] = rr;
+            H[(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++its;
+            jend = j + 1;
+            if (!std::isfinite(g[j + 1]) || !std::isfinite(hn)) {
+                *its_out = its;
+                return fail(p, JFMG_ENONFINITE, "non-finite value in the Arnoldi process");
+            }
+            if (std::fabs(g[j + 1]) <= tol_abs || hn == 0.0) { conv = true; break; }
+        }
+        for (int i = jend - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int t = i + 1; t < jend; ++t) s -= H[i * m + t] * y[t];
+            y[i] = s / H[i * m + i];
+        }
+        HIPCHK(p, hipMemcpyAsync(p->scal + S_Yc, y.data(), sizeof(double) * jend, hipMemcpyHostToDevice, st));
+        launch_lincomb(p->delta, p->delta, p->Z, N, jend, N, p->scal + S_Yc, st);
+        if (conv) { status = JFMG_OK; break; }
+        if (cyc == p->cfg.gmres_max_restarts) break;
+        // restart from the true residual r = -G - G' delta
+        launch_norm2(p->delta, N, red_at(p, S_Y), st);
+        jvp_slot(p, p->delta, p->tmp2, S_Y);
+        launch_axpby(p->tmp2, -1.0, G, -1.0, p->tmp2, N, st);
+        launch_norm2(p->tmp2, N, red_at(p, S_R), st);
+        double r2;
+        jfmg_status s = read_scalars(p, S_R, 1, &r2);
+        if (s) return s;
+        beta = std::sqrt(r2);
+        if (!std::isfinite(beta)) return fail(p, JFMG_ENONFINITE, "non-finite restart residual");
+        if (beta <= tol_abs) { status = JFMG_OK; break; }
+        launch_axpby(p->V, 1.0 / beta, p->tmp2, 0.0, p->tmp2, N, st);
+    }
+    *its_out = its;
+    if (status != JFMG_OK) return fail(p, JFMG_ENOCONV, "FGMRES did not reach its tolerance");
+    launch_axpby(U, 1.0, U, 1.0, p->delta, N, st);
+    return check_launch(p);
+}
+
+// Inexact Newton for G(U) = U - adt f(U) - Ubar = 0 from U^0 = Ubar; result in p->Uk
+jfmg_status newton_stage(jfmg_problem* p, const double* Ubar, double adt, jfmg_stats* st)
+{
+    const jfmg_config& c = p->cfg;
+    HIPCHK(p, hipMemcpyAsync(p->Uk, Ubar, sizeof(double) * p->N, hipMemcpyDeviceToDevice, p->st));
+    double g0;
+    jfmg_status s = stage_residual(p, p->Uk, Ubar, adt, p->G, &g0);
+    if (s) return s;
+    if (st) st->g0_norm = g0;
+    if (!std::isfinite(g0)) return fail(p, JFMG_ENONFINITE, "non-finite initial stage residual");
+    if (g0 == 0.0) { if (st) st->g_norm = 0.0; return JFMG_OK; }
+    double gk = g0, gprev = g0, eta = c.ew_eta0;
+    for (int it = 0; it < c.newton_maxit; ++it) {
+        if (it > 0) {
+            double en = c.ew_gamma * std::pow(gk / gprev, c.ew_alpha);
+            const double safe = c.ew_gamma * std::pow(eta, c.ew_alpha);
+            if (safe > 0.1 && safe > en) en = safe;
+            eta = std::min(en, c.ew_eta_max);
+        }
+        s = linearize(p, p->Uk, adt);
+        if (s) return s;
+        int its = 0;
+        s = fgmres(p, p->G, gk, eta * gk, p->Uk, &its);
+        if (st) { st->gmres_its += its; st->newton_its++; }
+        if (s) return s;
+        gprev = gk;
+        s = stage_residual(p, p->Uk, Ubar, adt, p->G, &gk);
+        if (s) return s;
+        if (st) st->g_norm = gk;
+        if (!std::isfinite(gk)) return fail(p, JFMG_ENONFINITE, "non-finite stage residual");
+        if (gk < c.newton_rtol * g0) return JFMG_OK;
+    }
+    return fail(p, JFMG_ENOCONV, "Newton did not converge within newton_maxit");
+}
+
+}  // namespace
+
+// ===========================================================================
+// C-ABI
+// ===========================================================================
+extern "C" {
+
+jfmg_status jfmg_config_default(jfmg_config* c)
+{
+    if (!c) return JFMG_EINVAL;
+    std::memset(c, 0, sizeof(*c));
+    c->nx = 16; c->nz = 16; c->k = 1;
+    c->physics = 0; c->background = 0; c->bc = 0; c->scheme = 1;
+    c->newton_maxit = 20; c->gmres_m = 30; c->gmres_max_restarts = 10; c->fd_eps_mode = 1;
+    c->mg_levels = 3; c->rk_stages = 3; c->mass_fix = 1; c->mg_precision = 64; c->precond = 1;
+    std::strcpy(c->mg_key, "mg002222V");
+    c->x0 = 0; c->x1 = 1000; c->z0 = 0; c->z1 = 1000;
+    c->g = 9.81; c->gamma = 1.4; c->R = 287.0; c->p0 = 1e5;
+    c->theta0 = 300.0; c->N = 0.0; c->u_mean = 0.0; c->mu = 0.0; c->c_ip = 2.0;
+    c->dt = 1.0; c->newton_rtol = 1e-8;
+    c->ew_gamma = 0.1; c->ew_alpha = 1.0; c->ew_eta0 = 0.1; c->ew_eta_max = 0.9;
+    c->pseudo_cfl = 1.0;
+    return JFMG_OK;
+}
+
+jfmg_status jfmg_workspace_bytes(const jfmg_config* cfg, size_t* bytes)
+{
+    if (!cfg || !bytes) return fail(nullptr, JFMG_EINVAL, "null argument");
+    Key key;
+    std::string msg;
+    jfmg_status s = validate(*cfg, key, msg);
+    if (s) return fail(nullptr, s, msg);
+    *bytes = layout(*cfg, nullptr, [](const char*, void*, size_t) {});
+    return JFMG_OK;
+}
+
+jfmg_status jfmg_create_problem(const jfmg_config* cfg, void* workspace, size_t ws_bytes, void* hip_stream,
+                                jfmg_problem** out)
+{
+    if (!cfg || !out) return fail(nullptr, JFMG_EINVAL, "null argument");
+    *out = nullptr;
+    Key key;
+    std::string msg;
+    jfmg_status s = validate(*cfg, key, msg);
+    if (s) return fail(nullptr, s, msg);
+    const size_t need = layout(*cfg, nullptr, [](const char*, void*, size_t) {});
+    if (!workspace || ws_bytes < need) return fail(nullptr, JFMG_ENOMEM, "workspace too small");
+    if (((uintptr_t)workspace & 255) != 0) return fail(nullptr, JFMG_EINVAL, "workspace must be 256-byte aligned");
+
+    jfmg_problem* p = new jfmg_problem();
+    p->cfg = *cfg;
+    p->key = key;
+    p->n1 = cfg->k + 1;
+    p->np = p->n1 * p->n1;
+    p->ne = (long)cfg->nx * cfg->nz;
+    p->N = 4 * p->ne * p->np;
+    p->dx = (cfg->x1 - cfg->x0) / cfg->nx;
+    p->dz = (cfg->z1 - cfg->z0) / cfg->nz;
+    p->nlev = cfg->mg_levels;
+    p->prec = cfg->mg_precision;
+    p->m = cfg->gmres_m;
+    p->st = (hipStream_t)hip_stream;
+    if (!build_reftab(cfg->k, p->R)) { delete p; return fail(nullptr, JFMG_EINVAL, "singular subcell interpolation"); }
+    layout(*cfg, (char*)workspace, [&](const char* name, void* ptr, size_t n) {
+        const std::string nm(name);
+        if (nm == "scal") p->scal = (double*)ptr;
+        else if (nm == "fvpart") { p->fvpart = (double*)ptr; p->fvp = n; }
+        else if (nm == "partials") { p->partials = (double*)ptr; p->npartials = n; }
+        else if (nm == "bg_node") p->bg_node = (double*)ptr;
+        else if (nm == "dbg_node") p->dbg_node = (double*)ptr;
+        else if (nm == "th_node") p->th_node = (double*)ptr;
+        else if (nm == "bg_face") p->bg_face = (double*)ptr;
+        else if (nm == "dbg_face") p->dbg_face = (double*)ptr;
+        else if (nm == "Un") p->Un = (double*)ptr;
+        else if (nm == "Ubar") p->Ubar = (double*)ptr;
+        else if (nm == "Uk") p->Uk = (double*)ptr;
+        else if (nm == "G") p->G = (double*)ptr;
+        else if (nm == "delta") p->delta = (double*)ptr;
+        else if (nm == "tmp1") p->tmp1 = (double*)ptr;
+        else if (nm == "tmp2") p->tmp2 = (double*)ptr;
+        else if (nm == "Ulin") p->Ulin = (double*)ptr;
+        else if (nm == "V") p->V = (double*)ptr;
+        else if (nm == "Z") p->Z = (double*)ptr;
+        else {
+            Level& L = p->lev[n];
+            if (nm == "u") L.u = ptr;
+            else if (nm == "F0") L.F0 = ptr;
+            else if (nm == "x0") L.buf[0] = ptr;
+            else if (nm == "x1") L.buf[1] = ptr;
+            else if (nm == "x2") L.buf[2] = ptr;
+            else if (nm == "b") L.b = ptr;
+            else if (nm == "bgc") L.bgc = ptr;
+            else if (nm == "bgf") L.bgf = ptr;
+            else if (nm == "dbgf") L.dbgf = ptr;
+        }
+    });
+    // level geometry
+    int nxl = p->n1 * cfg->nx, nzl = p->n1 * cfg->nz;
+    for (int l = 0; l < p->nlev; ++l) {
+        Level& L = p->lev[l];
+        L.nx = nxl; L.nz = nzl; L.nc = (long)nxl * nzl;
+        L.hx = (cfg->x1 - cfg->x0) / nxl;
+        L.hz = (cfg->z1 - cfg->z0) / nzl;
+        nxl /= 2;
+        nzl /= 2;
+    }
+    // host tables
+    const int n1 = p->n1;
+    std::vector<double> bgn((size_t)cfg->nz * n1 * 4), dbgn(bgn.size()), thn((size_t)cfg->nz * n1);
+    std::vector<double> bgf((size_t)(cfg->nz + 1) * 4), dbgf(bgf.size());
+    for (int ez = 0; ez < cfg->nz; ++ez)
+        for (int b = 0; b < n1; ++b) {
+            const double z = cfg->z0 + (ez + 0.5 * (1.0 + p->R.xi[b])) * p->dz;
+            const BgPoint bp = background_at(*cfg, z);
+            const int zi = ez * n1 + b;
+            for (int c = 0; c < 4; ++c) { bgn[zi * 4 + c] = bp.U[c]; dbgn[zi * 4 + c] = bp.dU[c]; }
+            thn[zi] = bp.theta;
+        }
+    for (int f = 0; f <= cfg->nz; ++f) {
+        const BgPoint bp = background_at(*cfg, cfg->z0 + f * p->dz);
+        for (int c = 0; c < 4; ++c) { bgf[f * 4 + c] = bp.U[c]; dbgf[f * 4 + c] = bp.dU[c]; }
+    }
+    hipStream_t st = p->st;
+    auto up = [&](void* dst, const void* src, size_t bytes) { return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st); };
+    std::vector<std::vector<double>> keep_d;
+    std::vector<std::vector<float>> keep_f;
+    hipError_t e = hipSuccess;
+    e = e ? e : up(p->bg_node, bgn.data(), bgn.size() * 8);
+    e = e ? e : up(p->dbg_node, dbgn.data(), dbgn.size() * 8);
+    e = e ? e : up(p->th_node, thn.data(), thn.size() * 8);
+    e = e ? e : up(p->bg_face, bgf.data(), bgf.size() * 8);
+    e = e ? e : up(p->dbg_face, dbgf.data(), dbgf.size() * 8);
+    for (int l = 0; l < p->nlev && !e; ++l) {
+        Level& L = p->lev[l];
+        std::vector<double> c4((size_t)L.nz * 4), f4((size_t)(L.nz + 1) * 4), df4(f4.size());
+        for (int J = 0; J < L.nz; ++J) {
+            const BgPoint bp = background_at(*cfg, cfg->z0 + (J + 0.5) * L.hz);
+            for (int c = 0; c < 4; ++c) c4[J * 4 + c] = bp.U[c];
+        }
+        for (int J = 0; J <= L.nz; ++J) {
+            const BgPoint bp = background_at(*cfg, cfg->z0 + J * L.hz);
+            for (int c = 0; c < 4; ++c) { f4[J * 4 + c] = bp.U[c]; df4[J * 4 + c] = bp.dU[c]; }
+        }
+        if (p->prec == 64) {
+            keep_d.push_back(c4); keep_d.push_back(f4); keep_d.push_back(df4);
+            const size_t k0 = keep_d.size() - 3;
+            e = e ? e : up(L.bgc, keep_d[k0].data(), c4.size() * 8);
+            e = e ? e : up(L.bgf, keep_d[k0 + 1].data(), f4.size() * 8);
+            e = e ? e : up(L.dbgf, keep_d[k0 + 2].data(), df4.size() * 8);
+        } else {
+            keep_f.emplace_back(c4.begin(), c4.end());
+            keep_f.emplace_back(f4.begin(), f4.end());
+            keep_f.emplace_back(df4.begin(), df4.end());
+            const size_t k0 = keep_f.size() - 3;
+            e = e ? e : up(L.bgc, keep_f[k0].data(), c4.size() * 4);
+            e = e ? e : up(L.bgf, keep_f[k0 + 1].data(), f4.size() * 4);
+            e = e ? e : up(L.dbgf, keep_f[k0 + 2].data(), df4.size() * 4);
+        }
+    }
+    e = e ? e : hipMemsetAsync(p->scal, 0, NSCAL * 8, st);
+    e = e ? e : hipStreamSynchronize(st);
+    if (e) {
+        const std::string m2 = std::string("table upload: ") + hipGetErrorString(e);
+        delete p;
+        return fail(nullptr, JFMG_EDEVICE, m2);
+    }
+    // DG kernel arguments
+    DgArgs& A = p->A;
+    A.ne = p->ne; A.nx = cfg->nx; A.nz = cfg->nz; A.bc = cfg->bc; A.physics = cfg->physics;
+    A.dx = p->dx; A.dz = p->dz; A.J = p->dx * p->dz / 4.0; A.g = cfg->g; A.mu = cfg->mu; A.c_ip = cfg->c_ip;
+    A.gas = Gas<double>{cfg->gamma, cfg->R, cfg->p0};
+    A.bg_node = p->bg_node; A.dbg_node = p->dbg_node; A.th_node = p->th_node;
+    A.bg_face = p->bg_face; A.dbg_face = p->dbg_face;
+    A.R = p->R;
+    *out = p;
+    return JFMG_OK;
+}
+
+jfmg_status jfmg_destroy_problem(jfmg_problem* p)
+{
+    if (p) {
+        prof_flush(p);
+        for (hipEvent_t e : p->prof.pool) (void)hipEventDestroy(e);
+    }
+    delete p;
+    return JFMG_OK;
+}
+
+size_t jfmg_num_dofs(const jfmg_problem* p) { return p ? (size_t)p->N : 0; }
+
+size_t jfmg_fv_size(const jfmg_problem* p, int level)
+{
+    if (!p || level < 0 || level >= p->nlev) return 0;
+    return (size_t)(4 * p->lev[level].nc);
+}
+
+jfmg_status jfmg_initial_state(jfmg_problem* p, const jfmg_perturbation* q, double* U)
+{
+    if (!p || !q || !U) return fail(p, JFMG_EINVAL, "null argument");
+    if (q->shape < 0 || q->shape > 1) return fail(p, JFMG_EINVAL, "unknown perturbation shape");
+    launch_initial_state(p->cfg.k, p->A, q->shape, q->amp, q->xc, q->zc, q->xr, q->zr, q->a, q->Z, p->cfg.x0,
+                         p->cfg.z0, p->cfg.u_mean, U, p->st);
+    return check_launch(p);
+}
+
+jfmg_status jfmg_residual(jfmg_problem* p, const double* U, double* out, int apply_minv)
+{
+    if (!p || !U || !out) return fail(p, JFMG_EINVAL, "null argument");
+    launch_dg(p->cfg.k, p->cfg.physics == 1, apply_minv ? 1 : 0, p->A, U, nullptr, nullptr, out, nullptr, nullptr, 0,
+              0.0, no_red(), p->st);
+    return check_launch(p);
+}
+
+jfmg_status jfmg_stage_residual(jfmg_problem* p, const double* U, const double* Ubar, double alpha_dt, double* G,
+                                double* norm)
+{
+    if (!p || !U || !Ubar || !G) return fail(p, JFMG_EINVAL, "null argument");
+    return stage_residual(p, U, Ubar, alpha_dt, G, norm);
+}
+
+jfmg_status jfmg_linearize(jfmg_problem* p, const double* U, double alpha_dt)
+{
+    if (!p || !U) return fail(p, JFMG_EINVAL, "null argument");
+    return linearize(p, U, alpha_dt);
+}
+
+jfmg_status jfmg_jvp(jfmg_problem* p, const double* y, double* out)
+{
+    if (!p || !y || !out) return fail(p, JFMG_EINVAL, "null argument");
+    if (!p->have_lin) return fail(p, JFMG_ESTATE, "jfmg_jvp needs jfmg_linearize first");
+    launch_norm2(y, p->N, red_at(p, S_Y), p->st);
+    jvp_slot(p, y, out, S_Y);
+    return check_launch(p);
+}
+
+jfmg_status jfmg_mg_apply(jfmg_problem* p, const double* r, double* z)
+{
+    if (!p || !r || !z) return fail(p, JFMG_EINVAL, "null argument");
+    if (!p->have_lin) return fail(p, JFMG_ESTATE, "jfmg_mg_apply needs jfmg_linearize first");
+    return precond(p, r, z, S_TMP);
+}
+
+jfmg_status jfmg_implicit_step(jfmg_problem* p, double* U, jfmg_stats* stats)
+{
+    if (!p || !U) return fail(p, JFMG_EINVAL, "null argument");
+    const auto t0 = std::chrono::steady_clock::now();
+    jfmg_stats st;
+    std::memset(&st, 0, sizeof(st));
+    std::memset(p->mv_count, 0, sizeof(p->mv_count));
+    p->lh_count = 0;
+    p->jvp_count = 0;
+    p->syncs = 0;
+    const jfmg_config& c = p->cfg;
+    jfmg_status s;
+    hipError_t e = hipMemcpyAsync(p->Un, U, sizeof(double) * p->N, hipMemcpyDeviceToDevice, p->st);
+    if (e) return fail(p, JFMG_EDEVICE, hipGetErrorString(e));
+    if (c.scheme == 0) {
+        s = newton_stage(p, p->Un, c.dt, &st);
+    } else {
+        const double a = 1.0 - std::sqrt(2.0) / 2.0;
+        s = newton_stage(p, p->Un, a * c.dt, &st);
+        if (s == JFMG_OK) {
+            // Ubar_2 = U^n + (1 - a) dt f(U_1)
+            launch_dg(c.k, c.physics == 1, 1, p->A, p->Uk, nullptr, nullptr, p->tmp1, nullptr, nullptr, 0, 0.0, no_red(),
+                      p->st);
+            p->lh_count++;
+            launch_axpby(p->Ubar, 1.0, p->Un, (1.0 - a) * c.dt, p->tmp1, p->N, p->st);
+            s = check_launch(p);
+            if (s == JFMG_OK) s = newton_stage(p, p->Ubar, a * c.dt, &st);
+        }
+    }
+    if (s == JFMG_OK) {
+        e = hipMemcpyAsync(U, p->Uk, sizeof(double) * p->N, hipMemcpyDeviceToDevice, p->st);
+        if (!e) e = hipStreamSynchronize(p->st);
+        if (e) s = fail(p, JFMG_EDEVICE, hipGetErrorString(e));
+    } else {
+        (void)hipStreamSynchronize(p->st);
+    }
+    prof_flush(p);
+    st.status = s;
+    st.lh_evals = p->lh_count;
+    st.jvps = p->jvp_count;
+    st.host_syncs = p->syncs;
+    for (int l = 0; l < MAXLEV && l < 8; ++l) st.fv_matvecs[l] = p->mv_count[l];
+    st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) *stats = st;
+    return s;
+}
+
+jfmg_status jfmg_transfer(jfmg_problem* p, int dir, const void* in, void* out)
+{
+    if (!p || !in || !out || (dir != 0 && dir != 1)) return fail(p, JFMG_EINVAL, "bad argument");
+    const int nxf = p->lev[0].nx;
+    if (dir == 0) {
+        if (p->prec == 32) launch_transfer_T<float>(p->cfg.k, p->A, p->cfg.mass_fix, (const double*)in, (float*)out, nxf, p->st);
+        else launch_transfer_T<double>(p->cfg.k, p->A, p->cfg.mass_fix, (const double*)in, (double*)out, nxf, p->st);
+    } else {
+        if (p->prec == 32) launch_transfer_Tinv<float>(p->cfg.k, p->A, p->cfg.mass_fix, (const float*)in, (double*)out, nxf, no_red(), p->st);
+        else launch_transfer_Tinv<double>(p->cfg.k, p->A, p->cfg.mass_fix, (const double*)in, (double*)out, nxf, no_red(), p->st);
+    }
+    return check_launch(p);
+}
+
+jfmg_status jfmg_restrict(jfmg_problem* p, int fine_level, const void* fine, void* coarse)
+{
+    if (!p || !fine || !coarse || fine_level < 0 || fine_level + 1 >= p->nlev) return fail(p, JFMG_EINVAL, "bad argument");
+    if (p->prec == 32) FvLaunch<float>::restrict_(fv_args<float>(p, fine_level), (const float*)fine, (float*)coarse, p->st);
+    else FvLaunch<double>::restrict_(fv_args<double>(p, fine_level), (const double*)fine, (double*)coarse, p->st);
+    return check_launch(p);
+}
+
+jfmg_status jfmg_prolong(jfmg_problem* p, int coarse_level, const void* coarse, void* fine)
+{
+    if (!p || !fine || !coarse || coarse_level < 1 || coarse_level >= p->nlev) return fail(p, JFMG_EINVAL, "bad argument");
+    if (p->prec == 32) FvLaunch<float>::prolong(fv_args<float>(p, coarse_level - 1), (const float*)coarse, (float*)fine, p->st);
+    else FvLaunch<double>::prolong(fv_args<double>(p, coarse_level - 1), (const double*)coarse, (double*)fine, p->st);
+    return check_launch(p);
+}
+
+jfmg_status jfmg_fv_level_state(jfmg_problem* p, int level, void* u)
+{
+    if (!p || !u || level < 0 || level >= p->nlev) return fail(p, JFMG_EINVAL, "bad argument");
+    if (!p->have_lin) return fail(p, JFMG_ESTATE, "needs jfmg_linearize first");
+    const size_t ts = p->prec == 32 ? 4 : 8;
+    HIPCHK(p, hipMemcpyAsync(u, p->lev[level].u, ts * 4 * p->lev[level].nc, hipMemcpyDeviceToDevice, p->st));
+    return JFMG_OK;
+}
+
+jfmg_status jfmg_fv_dtau(jfmg_problem* p, int level, double* dtau)
+{
+    if (!p || !dtau || level < 0 || level >= p->nlev) return fail(p, JFMG_EINVAL, "bad argument");
+    if (!p->have_lin) return fail(p, JFMG_ESTATE, "needs jfmg_linearize first");
+    return read_scalars(p, S_LEV + 4 * level + LV_DTAU, 1, dtau);
+}
+
+jfmg_status jfmg_fv_matvec(jfmg_problem* p, int level, const void* x, void* out)
+{
+    if (!p || !x || !out || level < 0 || level >= p->nlev) return fail(p, JFMG_EINVAL, "bad argument");
+    if (!p->have_lin) return fail(p, JFMG_ESTATE, "needs jfmg_linearize first");
+    const Level& L = p->lev[level];
+    if (p->prec == 32) {
+        FvLaunch<float>::norm2((const float*)x, 4 * L.nc, red_at(p, S_TMP), p->st);
+        FvLaunch<float>::matvec(fv_args<float>(p, level), (const float*)L.u, (const float*)L.F0, (const float*)x,
+                                (float*)out, p->scal + S_TMP, 1, p->scal + S_LEV + 4 * level, p->adt, p->st);
+    } else {
+        FvLaunch<double>::norm2((const double*)x, 4 * L.nc, red_at(p, S_TMP), p->st);
+        FvLaunch<double>::matvec(fv_args<double>(p, level), (const double*)L.u, (const double*)L.F0, (const double*)x,
+                                 (double*)out, p->scal + S_TMP, 1, p->scal + S_LEV + 4 * level, p->adt, p->st);
+    }
+    return check_launch(p);
+}
+
+jfmg_status jfmg_mg_fv(jfmg_problem* p, const void* b, void* x)
+{
+    if (!p || !b || !x) return fail(p, JFMG_EINVAL, "bad argument");
+    if (!p->have_lin) return fail(p, JFMG_ESTATE, "needs jfmg_linearize first");
+    const Level& L = p->lev[0];
+    const size_t bytes = (p->prec == 32 ? 4 : 8) * 4 * L.nc;
+    HIPCHK(p, hipMemcpyAsync(L.b, b, bytes, hipMemcpyDeviceToDevice, p->st));
+    void* r;
+    if (p->prec == 32) { Mg<float> mg{p}; r = mg.run(); }
+    else { Mg<double> mg{p}; r = mg.run(); }
+    HIPCHK(p, hipMemcpyAsync(x, r, bytes, hipMemcpyDeviceToDevice, p->st));
+    return check_launch(p);
+}
+
+jfmg_status jfmg_subgrid_map(jfmg_problem* p, int* fv_to_dg)
+{
+    if (!p || !fv_to_dg) return fail(p, JFMG_EINVAL, "null argument");
+    launch_subgrid_map(p->cfg.k, p->A, p->lev[0].nx, fv_to_dg, p->st);
+    return check_launch(p);
+}
+
+jfmg_status jfmg_profile_enable(jfmg_problem* p, unsigned class_mask)
+{
+    if (!p) return fail(p, JFMG_EINVAL, "null argument");
+    HIPCHK(p, hipStreamSynchronize(p->st));
+    prof_flush(p);
+    p->prof.mask = class_mask;
+    for (int i = 0; i < JFMG_K_NCLASS; ++i) { p->prof.ms[i] = 0; p->prof.cnt[i] = 0; p->prof.bytes[i] = 0; }
+    return JFMG_OK;
+}
+
+jfmg_status jfmg_profile_read(jfmg_problem* p, double* ms, long long* launches, double* bytes)
+{
+    if (!p || !ms || !launches || !bytes) return fail(p, JFMG_EINVAL, "null argument");
+    HIPCHK(p, hipStreamSynchronize(p->st));
+    prof_flush(p);
+    for (int i = 0; i < JFMG_K_NCLASS; ++i) { ms[i] = p->prof.ms[i]; launches[i] = p->prof.cnt[i]; bytes[i] = p->prof.bytes[i]; }
+    return JFMG_OK;
+}
+
+const char* jfmg_last_error(const jfmg_problem* p)
+{
+    return p ? p->err.c_str() : g_create_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,460 @@
+// FV-subgrid multigrid kernels (paper Sec. "Multigrid preconditioner for
+// finite volume approximations" and "Smoother / Pseudo time iteration").
+//
+// f_low on level l is the DG scheme with k = 0 on the subgrid: HLLC on the face
+// total states (cell value + Ubar at the face), the k = 0 interior-penalty
+// diffusion flux with penalty 1/h, and the gravity source.  The kernels carry
+// the flux sum without the constant background-flux term; every use is a
+// difference f(u + eps x) - f(u), in which that constant cancels.
+//
+// Layout: SoA [4][nzl][nxl].  A work-group is a 64 x 4 tile of cells (one
+// wave per row of 64 cells along x, so loads of a component are 256-byte
+// coalesced); neighbours come through the caches.  Every kernel that produces
+// a vector the next FD product needs also produces its squared norm through a
+// deterministic two-level reduction.
+#include "jfmg_internal.h"
+
+namespace jfmg {
+
+constexpr int FV_TX = 64, FV_TZ = 4, FV_NTH = FV_TX * FV_TZ;
+
+enum { FVM_LIN = 0, FVM_STAGE = 1, FVM_MATVEC = 2, FVM_DEFECT = 3 };
+
+// FV operator on one tile of TX x TZ cells, face-centric: the perturbed states
+// w = u + eps x of the tile and a one-cell halo are staged in LDS, every face
+// of the tile gets its net flux Phi (HLLC minus the interior-penalty diffusion
+// flux, along +x or +z) exactly once, and each cell then sums its four faces:
+//   |q| f~ = -hz (Phi_{I+1/2} - Phi_{I-1/2}) - hx (Phi_{J+1/2} - Phi_{J-1/2}) - |q| g w_rho.
+// The flux through a face seen from the other cell is the same number with
+// the opposite sign (HLLC(L,R;n) = -HLLC(R,L;-n)).  Modes:
+//   LIN     out = F0 = f~(u); ||u + Ubar||^2 and max(|v| + c) -> level slots, dtau
+//   STAGE   out = x0 + alpha_j dtau (b - g'x), g'x = x - adt/eps (f~(u + eps x) - F0)
+//   MATVEC  out = g'x
+//   DEFECT  out(coarse) = R(g'x - b), 2x2 agglomeration inside the tile
+template <typename T, int TX, int TZ, int MODE>
+__global__ void __launch_bounds__(TX * TZ)
+fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, const T* __restrict__ xp,
+               const T* __restrict__ x0, const T* __restrict__ b, T* __restrict__ out,
+               const double* __restrict__ xpart, int xcount, double* __restrict__ slots, double alpha_j,
+               double adt, double cfl, Red red)
+{
+    constexpr int NTH = TX * TZ, HX = TX + 2, HZ = TZ + 2;
+    constexpr int NFX = TZ * (TX + 1), NFZ = (TZ + 1) * TX;
+    __shared__ T sw[4][HZ][HX];
+    __shared__ T sFx[TZ][TX + 1][4];
+    __shared__ T sFz[TZ + 1][TX][4];
+    const int tid = threadIdx.x;
+    const int I0 = blockIdx.x * TX, J0 = blockIdx.y * TZ;
+    const long nc = A.nc;
+    const int nxl = A.nxl, nzl = A.nzl;
+
+    T eps = T(0);
+    bool xzero = false;   // uniform: g'x = 0 for x = 0
+    if constexpr (MODE != FVM_LIN) {
+        const double xn2 = sum_partials<NTH>(xpart, xcount);   // ||x||^2, same order in every block
+        if (!(xn2 > 0.0)) xzero = true;
+        else eps = (T)(FdEps<T>::sqrt_eps * slots[LV_UTOT] / sqrt(xn2));
+    }
+
+    if (!xzero) {
+        // ---- states of the tile and its halo ----
+        for (int h = tid; h < HX * HZ; h += NTH) {
+            const int ii = h % HX, jj = h / HX;
+            int I = I0 - 1 + ii;
+            const int J = J0 - 1 + jj;
+            bool ok = (J >= 0 && J < nzl);
+            if (I < 0 || I >= nxl) {
+                if (A.bc == 1) I = (I + nxl) % nxl;
+                else ok = false;
+            }
+            const long q = (long)J * nxl + I;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                T v = T(0);
+                if (ok) {
+                    v = u[c * nc + q];
+                    if constexpr (MODE != FVM_LIN) v = v + eps * xp[c * nc + q];
+                }
+                sw[c][jj][ii] = v;
+            }
+        }
+        __syncthreads();
+        // ---- one net flux per face ----
+        for (int f = tid; f < NFX + NFZ; f += NTH) {
+            T Phi[4] = {T(0), T(0), T(0), T(0)};
+            const bool xface = f < NFX;
+            int r0, r1, sL, sR;   // LDS rows/cols of the two sides
+            bool skip = false, wallL = false, wallR = false;
+            const T* bg;
+            const T* dbg = nullptr;
+            T elen, hn;
+            if (xface) {
+                const int jj = f / (TX + 1), fi = f - jj * (TX + 1);
+                const int J = J0 + jj, Ir = I0 + fi, Il = Ir - 1;
+                skip = (J >= nzl) || (Il >= nxl);
+                wallL = (Ir == 0) && A.bc != 1;
+                wallR = (Il == nxl - 1) && A.bc != 1;
+                r0 = jj + 1; r1 = jj + 1; sL = fi; sR = fi + 1;
+                bg = A.bgc + 4 * (skip ? 0 : J);
+                elen = A.hz; hn = A.hx;
+            } else {
+                const int g = f - NFX;
+                const int fj = g / TX, ii = g - fj * TX;
+                const int I = I0 + ii, Ja = J0 + fj, Jb = Ja - 1;
+                skip = (I >= nxl) || (Jb >= nzl);
+                wallL = (Jb < 0);
+                wallR = (Ja == nzl);
+                r0 = fj; r1 = fj + 1; sL = ii + 1; sR = ii + 1;
+                bg = A.bgf + 4 * (skip ? 0 : Ja);
+                dbg = A.dbgf + 4 * (skip ? 0 : Ja);
+                elen = A.hx; hn = A.hz;
+            }
+            if (!skip) {
+                const T nx = xface ? T(1) : T(0), nz = xface ? T(0) : T(1);
+                T UL[4], UR[4], wL[4], wR[4], H[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    wL[c] = sw[c][r0][sL];
+                    wR[c] = sw[c][r1][sR];
+                    UL[c] = wL[c] + bg[c];
+                    UR[c] = wR[c] + bg[c];
+                }
+                if (wallL) {            // only the cell on the + side is inside
+                    T M[4] = {UR[0], UR[1], UR[2], UR[3]};
+                    if (xface) M[1] = -M[1]; else M[2] = -M[2];
+                    hllc(A.gas, UR, M, -nx, -nz, H);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) Phi[c] = -H[c];
+                } else if (wallR) {     // only the cell on the - side is inside
+                    T M[4] = {UL[0], UL[1], UL[2], UL[3]};
+                    if (xface) M[1] = -M[1]; else M[2] = -M[2];
+                    hllc(A.gas, UL, M, nx, nz, H);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) Phi[c] = H[c];
+                } else {
+                    hllc(A.gas, UL, UR, nx, nz, H);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) Phi[c] = H[c];
+                    if (A.physics == 1) {
+                        T FL[4] = {T(0), T(0), T(0), T(0)}, FR[4] = {T(0), T(0), T(0), T(0)};
+                        if (!xface) {
+                            const T Z4[4] = {T(0), T(0), T(0), T(0)};
+                            visc_flux(A.mu, UL, Z4, dbg, nx, nz, FL);
+                            visc_flux(A.mu, UR, Z4, dbg, nx, nz, FR);
+                        }
+#pragma unroll
+                        for (int c = 1; c < 4; ++c) {
+                            const T Dl0 = wL[0] - wR[0], Dlc = wL[c] - wR[c];
+                            const T r = T(0.5) * (UL[c] + UR[c]) / (T(0.5) * (UL[0] + UR[0]));
+                            const T pen = (T(1) / hn) * A.mu * (Dlc - r * Dl0);
+                            Phi[c] -= T(0.5) * (FL[c] + FR[c]) - pen;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < 4; ++c) Phi[c] *= elen;
+            }
+            if (xface) {
+                const int jj = f / (TX + 1), fi = f - jj * (TX + 1);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) sFx[jj][fi][c] = Phi[c];
+            } else {
+                const int g = f - NFX;
+                const int fj = g / TX, ii = g - fj * TX;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) sFz[fj][ii][c] = Phi[c];
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- per cell ----
+    const int ti = tid % TX, tj = tid / TX;
+    const int I = I0 + ti, J = J0 + tj;
+    const bool valid = (I < nxl) && (J < nzl);
+    const long q = (long)J * nxl + I;
+    T f[4] = {T(0), T(0), T(0), T(0)};
+    if (valid && !xzero) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            T L = -(sFx[tj][ti + 1][c] - sFx[tj][ti][c]) - (sFz[tj + 1][ti][c] - sFz[tj][ti][c]);
+            if (c == 2) L += A.area * (-A.g * sw[0][tj + 1][ti + 1]);
+            f[c] = L / A.area;
+        }
+    }
+    if constexpr (MODE == FVM_LIN) {
+        double ss = 0.0, lam = 0.0;
+        if (valid) {
+            T Ut[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                out[c * nc + q] = f[c];   // F0
+                Ut[c] = u[c * nc + q] + A.bgc[4 * J + c];
+                ss += (double)Ut[c] * (double)Ut[c];
+            }
+            const double rho = Ut[0], uu = Ut[1] / rho, ww = Ut[2] / rho;
+            const double p = (double)A.gas.p0 * pow((double)A.gas.R * (double)Ut[3] / (double)A.gas.p0,
+                                                    (double)A.gas.gamma);
+            lam = sqrt(uu * uu + ww * ww) + sqrt((double)A.gas.gamma * p / rho);
+        }
+        __shared__ double sh[(NTH + 63) / 64];
+        const double bs = block_sum<NTH>(ss, sh);
+        const double bm = block_max<NTH>(lam, sh);
+        if (tid == 0) {
+            const unsigned nb = gridDim.x * gridDim.y;
+            red.partials[block_linear()] = bs;
+            red.partials[nb + block_linear()] = bm;
+        }
+        return;
+    } else {
+        T Ax[4] = {T(0), T(0), T(0), T(0)};
+        if (valid && !xzero) {
+            const T sc = (T)adt / eps;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) Ax[c] = xp[c * nc + q] - sc * (f[c] - F0[c * nc + q]);
+        }
+        if constexpr (MODE == FVM_MATVEC) {
+            if (valid)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) out[c * nc + q] = Ax[c];
+        } else if constexpr (MODE == FVM_STAGE) {
+            double nrm = 0.0;
+            if (valid) {
+                const T s = (T)(alpha_j * slots[LV_DTAU]);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const T v = (x0 ? x0[c * nc + q] : T(0)) + s * (b[c * nc + q] - Ax[c]);
+                    out[c * nc + q] = v;
+                    nrm += (double)v * (double)v;
+                }
+            }
+            put_partial<NTH>(red, nrm);
+        } else {   // DEFECT: reuse the state tile for d = g'x - b, then agglomerate 2x2
+            __syncthreads();
+            if (valid)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) sw[c][tj][ti] = Ax[c] - b[c * nc + q];
+            __syncthreads();
+            if (valid && !(ti & 1) && !(tj & 1)) {
+                const int nxc = nxl / 2;
+                const long ncc = (long)nxc * (nzl / 2), qc = (long)(J / 2) * nxc + I / 2;
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    out[c * ncc + qc] = ((sw[c][tj][ti] + sw[c][tj][ti + 1]) + (sw[c][tj + 1][ti] + sw[c][tj + 1][ti + 1])) * T(0.25);
+            }
+        }
+    }
+}
+
+// first stage of a sweep from x = 0: out = alpha_1 dtau b, with ||out||^2
+template <typename T>
+__global__ void __launch_bounds__(256)
+fv_stage_zero_kernel(const T* __restrict__ b, T* __restrict__ out, long n, const double* __restrict__ slots,
+                     double alpha_j, Red red)
+{
+    const T s = (T)(alpha_j * slots[LV_DTAU]);
+    double nrm = 0.0;
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+        const T v = s * b[i];
+        out[i] = v;
+        nrm += (double)v * (double)v;
+    }
+    put_partial<256>(red, nrm);
+}
+
+// coarse = R(-b): the defect of x = 0
+template <typename T>
+__global__ void __launch_bounds__(256) fv_restrict_neg_kernel(FvArgs<T> A, const T* __restrict__ f, T* __restrict__ c)
+{
+    const int nxc = A.nxl / 2, nzc = A.nzl / 2;
+    const int Ic = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int Jc = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (Ic >= nxc || Jc >= nzc) return;
+    const long ncc = (long)nxc * nzc, qc = (long)Jc * nxc + Ic;
+    const long q00 = (long)(2 * Jc) * A.nxl + 2 * Ic, q01 = q00 + A.nxl;
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) {
+        const T* g = f + cc * A.nc;
+        c[cc * ncc + qc] = ((-g[q00] + -g[q00 + 1]) + (-g[q01] + -g[q01 + 1])) * T(0.25);
+    }
+}
+
+// x -= P v (injection) on the fine level, with ||x||^2
+template <typename T>
+__global__ void __launch_bounds__(FV_NTH)
+fv_prolong_correct_kernel(FvArgs<T> A, T* __restrict__ x, const T* __restrict__ v, Red red)
+{
+    const int I = blockIdx.x * FV_TX + (threadIdx.x & (FV_TX - 1));
+    const int J = blockIdx.y * FV_TZ + (threadIdx.x / FV_TX);
+    double nrm = 0.0;
+    if (I < A.nxl && J < A.nzl) {
+        const long q = (long)J * A.nxl + I;
+        const long ncc = (long)(A.nxl / 2) * (A.nzl / 2), qc = (long)(J / 2) * (A.nxl / 2) + I / 2;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const T val = x[c * A.nc + q] - v[c * ncc + qc];
+            x[c * A.nc + q] = val;
+            nrm += (double)val * (double)val;
+        }
+    }
+    put_partial<FV_NTH>(red, nrm);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(FV_NTH) fv_restrict_kernel(FvArgs<T> A, const T* __restrict__ f, T* __restrict__ c)
+{
+    const int nxc = A.nxl / 2, nzc = A.nzl / 2;
+    const int Ic = blockIdx.x * FV_TX + (threadIdx.x & (FV_TX - 1));
+    const int Jc = blockIdx.y * FV_TZ + (threadIdx.x / FV_TX);
+    if (Ic >= nxc || Jc >= nzc) return;
+    const long ncc = (long)nxc * nzc, qc = (long)Jc * nxc + Ic;
+    const long q00 = (long)(2 * Jc) * A.nxl + 2 * Ic, q01 = q00 + A.nxl;
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) {
+        const T* g = f + cc * A.nc;
+        c[cc * ncc + qc] = ((g[q00] + g[q00 + 1]) + (g[q01] + g[q01 + 1])) * T(0.25);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(FV_NTH) fv_prolong_kernel(FvArgs<T> A, const T* __restrict__ c, T* __restrict__ f)
+{
+    const int I = blockIdx.x * FV_TX + (threadIdx.x & (FV_TX - 1));
+    const int J = blockIdx.y * FV_TZ + (threadIdx.x / FV_TX);
+    if (I >= A.nxl || J >= A.nzl) return;
+    const long q = (long)J * A.nxl + I;
+    const long ncc = (long)(A.nxl / 2) * (A.nzl / 2), qc = (long)(J / 2) * (A.nxl / 2) + I / 2;
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) f[cc * A.nc + q] = c[cc * ncc + qc];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) fv_norm2_kernel(const T* __restrict__ x, long n, Red red)
+{
+    double s = 0.0;
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+        const double v = x[i];
+        s += v * v;
+    }
+    put_partial<256>(red, s);
+}
+
+// level slots from the LIN partials: ||u + Ubar||, max(|v| + c), pseudo time step
+__global__ void __launch_bounds__(256)
+fv_lin_finalize_kernel(const double* __restrict__ p, int nb, double* __restrict__ slots, double hx, double hz,
+                       double mu, double adt, double cfl)
+{
+    __shared__ double sh[4];
+    double a = 0.0, m = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 256) { a += p[i]; m = fmax(m, p[nb + i]); }
+    a = block_sum<256>(a, sh);
+    m = block_max<256>(m, sh);
+    if (threadIdx.x == 0) {
+        slots[LV_UTOT] = sqrt(a);
+        slots[LV_LAM] = m;
+        slots[LV_DTAU] = cfl / (1.0 + adt * (m * (1.0 / hx + 1.0 / hz) + 2.0 * mu * (1.0 / (hx * hx) + 1.0 / (hz * hz))));
+    }
+}
+
+static inline dim3 tile_grid(int nx, int nz)
+{
+    return dim3((unsigned)((nx + FV_TX - 1) / FV_TX), (unsigned)((nz + FV_TZ - 1) / FV_TZ));
+}
+
+template <typename T, int MODE>
+static int tile_launch(const FvArgs<T>& A, const T* u, const T* F0, const T* xp, const T* x0, const T* b, T* out,
+                       const double* xpart, int xcount, double* slots, double alpha_j, double adt, double cfl,
+                       Red red, hipStream_t st)
+{
+    if (A.nxl >= 1024) {
+        const dim3 g((unsigned)((A.nxl + 63) / 64), (unsigned)((A.nzl + 3) / 4));
+        fv_tile_kernel<T, 64, 4, MODE><<<g, dim3(256), 0, st>>>(A, u, F0, xp, x0, b, out, xpart, xcount, slots,
+                                                                alpha_j, adt, cfl, red);
+        return (int)(g.x * g.y);
+    }
+    const dim3 g((unsigned)((A.nxl + 15) / 16), (unsigned)((A.nzl + 3) / 4));
+    fv_tile_kernel<T, 16, 4, MODE><<<g, dim3(64), 0, st>>>(A, u, F0, xp, x0, b, out, xpart, xcount, slots, alpha_j,
+                                                           adt, cfl, red);
+    return (int)(g.x * g.y);
+}
+
+template <typename T>
+void FvLaunch<T>::lin_level(const FvArgs<T>& A, const T* u, T* F0, Red red, double* slots, double adt, double cfl,
+                            hipStream_t st)
+{
+    const int nb = tile_launch<T, FVM_LIN>(A, u, nullptr, nullptr, nullptr, nullptr, F0, nullptr, 0, slots, 0.0, adt,
+                                           cfl, red, st);
+    fv_lin_finalize_kernel<<<dim3(1), dim3(256), 0, st>>>(red.partials, nb, slots, (double)A.hx, (double)A.hz,
+                                                          (double)A.mu, adt, cfl);
+}
+template <typename T>
+int FvLaunch<T>::stage(const FvArgs<T>& A, const T* u, const T* F0, const T* xp, const T* x0, const T* b, T* xo,
+                       const double* xpart, int xcount, const double* slots, double alpha_j, double adt, int zero,
+                       Red red, hipStream_t st)
+{
+    if (zero) {
+        const long n = 4 * A.nc;
+        const int nb = norm_blocks(n);
+        fv_stage_zero_kernel<T><<<dim3(nb), dim3(256), 0, st>>>(b, xo, n, slots, alpha_j, red);
+        return nb;
+    }
+    return tile_launch<T, FVM_STAGE>(A, u, F0, xp, x0, b, xo, xpart, xcount, const_cast<double*>(slots), alpha_j,
+                                     adt, 0.0, red, st);
+}
+template <typename T>
+void FvLaunch<T>::matvec(const FvArgs<T>& A, const T* u, const T* F0, const T* x, T* out, const double* xpart,
+                         int xcount, const double* slots, double adt, hipStream_t st)
+{
+    tile_launch<T, FVM_MATVEC>(A, u, F0, x, nullptr, nullptr, out, xpart, xcount, const_cast<double*>(slots), 0.0,
+                               adt, 0.0, Red{nullptr, nullptr}, st);
+}
+template <typename T>
+void FvLaunch<T>::defect_restrict(const FvArgs<T>& A, const T* u, const T* F0, const T* x, const T* b, T* rc,
+                                  const double* xpart, int xcount, const double* slots, double adt, int zero,
+                                  hipStream_t st)
+{
+    if (zero) {
+        const dim3 g((unsigned)((A.nxl / 2 + 63) / 64), (unsigned)((A.nzl / 2 + 3) / 4));
+        fv_restrict_neg_kernel<T><<<g, dim3(256), 0, st>>>(A, b, rc);
+        return;
+    }
+    tile_launch<T, FVM_DEFECT>(A, u, F0, x, nullptr, b, rc, xpart, xcount, const_cast<double*>(slots), 0.0, adt, 0.0,
+                               Red{nullptr, nullptr}, st);
+}
+template <typename T>
+int FvLaunch<T>::prolong_correct(const FvArgs<T>& Af, T* x, const T* v, Red red, hipStream_t st)
+{
+    const dim3 g = tile_grid(Af.nxl, Af.nzl);
+    fv_prolong_correct_kernel<T><<<g, dim3(FV_NTH), 0, st>>>(Af, x, v, red);
+    return (int)(g.x * g.y);
+}
+template <typename T>
+void FvLaunch<T>::restrict_(const FvArgs<T>& Af, const T* f, T* c, hipStream_t st)
+{
+    fv_restrict_kernel<T><<<tile_grid(Af.nxl / 2, Af.nzl / 2), dim3(FV_NTH), 0, st>>>(Af, f, c);
+}
+template <typename T>
+void FvLaunch<T>::prolong(const FvArgs<T>& Af, const T* c, T* f, hipStream_t st)
+{
+    fv_prolong_kernel<T><<<tile_grid(Af.nxl, Af.nzl), dim3(FV_NTH), 0, st>>>(Af, c, f);
+}
+template <typename T>
+void FvLaunch<T>::norm2(const T* x, long n, Red red, hipStream_t st)
+{
+    fv_norm2_kernel<T><<<dim3(norm_blocks(n)), dim3(256), 0, st>>>(x, n, red);
+    if (red.out) launch_finalize(red.partials, norm_blocks(n), 1, red.out, st);
+}
+template <typename T> int FvLaunch<T>::grid_blocks(const FvArgs<T>& A)
+{
+    return ((A.nxl + 15) / 16) * ((A.nzl + 3) / 4);
+}
+template <typename T> int FvLaunch<T>::norm_blocks(long n)
+{
+    long b = (n + 255) / 256;
+    return (int)(b < 1024 ? b : 1024);
+}
+
+template struct FvLaunch<double>;
+template struct FvLaunch<float>;
+
+}  // namespace jfmg

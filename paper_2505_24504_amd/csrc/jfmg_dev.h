@@ -1,0 +1,183 @@
+// Device helpers shared by the gfx950 kernels: gas physics, the HLLC flux,
+// the viscous flux and wave64 / block / multi-block reductions (fixed
+// summation order everywhere, no float atomics).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+namespace jfmg {
+
+// sqrt of the unit roundoff used in finite-difference steps: 2^-26 (FP64), 2^-11.5 (FP32)
+template <typename T> struct FdEps;
+template <> struct FdEps<double> { static constexpr double sqrt_eps = 1.4901161193847656e-08; };
+template <> struct FdEps<float> { static constexpr double sqrt_eps = 3.4526698300124393e-04; };
+
+template <typename T> struct Gas {
+    T gamma, R, p0;
+};
+
+template <typename T> __device__ __forceinline__ T dpow(T a, T b)
+{
+    if constexpr (std::is_same_v<T, float>) return powf(a, b);
+    else return pow(a, b);
+}
+template <typename T> __device__ __forceinline__ T dsqrt(T a)
+{
+    if constexpr (std::is_same_v<T, float>) return sqrtf(a);
+    else return sqrt(a);
+}
+
+// Equation of state of the potential-temperature form: p = p0 (R rho theta / p0)^gamma
+template <typename T> __device__ __forceinline__ T pressure(const Gas<T>& G, T rt)
+{
+    return G.p0 * dpow<T>(G.R * rt / G.p0, G.gamma);
+}
+
+// Convective flux F_c(U) . n for an axis-aligned unit normal (nx, nz).
+template <typename T>
+__device__ __forceinline__ void conv_flux(const Gas<T>& G, const T* U, T nx, T nz, T* F)
+{
+    T u = U[1] / U[0], w = U[2] / U[0];
+    T p = pressure(G, U[3]);
+    T q = u * nx + w * nz;
+    F[0] = U[1] * nx + U[2] * nz;
+    F[1] = U[1] * q + p * nx;
+    F[2] = U[2] * q + p * nz;
+    F[3] = U[3] * q;
+}
+
+// HLLC flux (Toro) with Davis wave speeds S_L = min(q_L - c_L, q_R - c_R),
+// S_R = max(q_L + c_L, q_R + c_R); star flux in the S*-factored form
+// (S*(S_K U_K - F_K) + S_K p*_K D*) / (S_K - S*), p*_K = p_K + rho_K (S_K - q_K)(S* - q_K).
+template <typename T>
+__device__ __forceinline__ void hllc(const Gas<T>& G, const T* UL, const T* UR, T nx, T nz, T* F)
+{
+    const T rL = UL[0], rR = UR[0];
+    const T uL = UL[1] / rL, wL = UL[2] / rL, uR = UR[1] / rR, wR = UR[2] / rR;
+    const T pL = pressure(G, UL[3]), pR = pressure(G, UR[3]);
+    const T qL = uL * nx + wL * nz, qR = uR * nx + wR * nz;
+    const T cL = dsqrt<T>(G.gamma * pL / rL), cR = dsqrt<T>(G.gamma * pR / rR);
+    const T SL = fmin(qL - cL, qR - cR);
+    const T SR = fmax(qL + cL, qR + cR);
+    if (SL >= T(0)) {
+        F[0] = UL[1] * nx + UL[2] * nz;
+        F[1] = UL[1] * qL + pL * nx;
+        F[2] = UL[2] * qL + pL * nz;
+        F[3] = UL[3] * qL;
+        return;
+    }
+    const T Ss = (pR - pL + rL * qL * (SL - qL) - rR * qR * (SR - qR)) / (rL * (SL - qL) - rR * (SR - qR));
+    const T* UK;
+    T SK, rK, qK, pK;
+    if (Ss >= T(0)) { UK = UL; SK = SL; rK = rL; qK = qL; pK = pL; }
+    else if (SR > T(0)) { UK = UR; SK = SR; rK = rR; qK = qR; pK = pR; }
+    else {
+        F[0] = UR[1] * nx + UR[2] * nz;
+        F[1] = UR[1] * qR + pR * nx;
+        F[2] = UR[2] * qR + pR * nz;
+        F[3] = UR[3] * qR;
+        return;
+    }
+    const T FK0 = UK[1] * nx + UK[2] * nz;
+    const T FK1 = UK[1] * qK + pK * nx;
+    const T FK2 = UK[2] * qK + pK * nz;
+    const T FK3 = UK[3] * qK;
+    const T pst = pK + rK * (SK - qK) * (Ss - qK);
+    const T den = SK - Ss;
+    F[0] = (Ss * (SK * UK[0] - FK0)) / den;
+    F[1] = (Ss * (SK * UK[1] - FK1) + SK * pst * nx) / den;
+    F[2] = (Ss * (SK * UK[2] - FK2) + SK * pst * nz) / den;
+    F[3] = (Ss * (SK * UK[3] - FK3)) / den;
+}
+
+// Viscous flux F_v(U, G) . n = mu rho grad(U_c / rho) . n written with the
+// conserved-variable gradient G = (Gx, Gz): mu (G_c - (U_c/rho) G_rho), c = 1..3.
+template <typename T>
+__device__ __forceinline__ void visc_flux(T mu, const T* U, const T* Gx, const T* Gz, T nx, T nz, T* F)
+{
+    F[0] = T(0);
+#pragma unroll
+    for (int c = 1; c < 4; ++c) {
+        T r = U[c] / U[0];
+        F[c] = mu * ((Gx[c] - r * Gx[0]) * nx + (Gz[c] - r * Gz[0]) * nz);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Reductions.  Wave64 butterfly, then waves combined by thread 0 in wave order.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Block sum over NTH threads (a multiple of 64); result valid in thread 0.
+template <int NTH> __device__ __forceinline__ double block_sum(double v, double* sh)
+{
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < NTH / 64; ++i) s += sh[i];
+    __syncthreads();
+    return s;
+}
+template <int NTH> __device__ __forceinline__ double block_max(double v, double* sh)
+{
+    v = wave_max(v);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < NTH / 64; ++i) s = fmax(s, sh[i]);
+    __syncthreads();
+    return s;
+}
+
+// Multi-block reductions without tickets or fences: every block writes its
+// partial with a plain store; the partials are summed in a fixed order either
+// by a one-block finalize kernel launched right after the producer (scalars the
+// host or a later kernel reads) or by each block of the consuming kernel
+// itself (sum_partials).  Kernel boundaries make the partials visible; no
+// agent-scope fence is executed per block.
+struct Red {
+    double* partials;   // [nq][number of blocks]
+    double* out;        // if non-null the launcher finalizes into out[0..nq)
+};
+
+__device__ __forceinline__ unsigned block_linear() { return blockIdx.y * gridDim.x + blockIdx.x; }
+
+template <int NTH> __device__ __forceinline__ void put_partial(const Red& r, double v)
+{
+    __shared__ double sh[NTH / 64];
+    const double s = block_sum<NTH>(v, sh);
+    if (threadIdx.x == 0) r.partials[block_linear()] = s;
+}
+
+// deterministic sum of n partials, returned to every thread of the block
+template <int NTH> __device__ __forceinline__ double sum_partials(const double* p, int n)
+{
+    __shared__ double sh[NTH / 64];
+    __shared__ double res;
+    double a = 0.0;
+    for (int i = threadIdx.x; i < n; i += NTH) a += p[i];
+    a = block_sum<NTH>(a, sh);
+    if (threadIdx.x == 0) res = a;
+    __syncthreads();
+    return res;
+}
+
+}  // namespace jfmg

@@ -1,0 +1,111 @@
+// Internal interface between the host driver and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+#include "jfmg_dev.h"
+
+namespace jfmg {
+
+constexpr int MAXN1 = 4;      // k + 1 <= 4
+constexpr int MAXLEV = 8;
+
+// Reference-element tables (host-built, passed by value).
+struct RefTab {
+    double xi[MAXN1], w[MAXN1], D[MAXN1][MAXN1], em[MAXN1], ep[MAXN1], dm[MAXN1], dp[MAXN1];
+    double V[MAXN1][MAXN1], Vinv[MAXN1][MAXN1], wnc[MAXN1];
+};
+
+// Everything a DG kernel needs about the grid, the gas and the background.
+struct DgArgs {
+    long ne;
+    int nx, nz, bc, physics;
+    double dx, dz, J, g, mu, c_ip;
+    Gas<double> gas;
+    const double* bg_node;   // [nz*(k+1)][4] background at the z of each node row
+    const double* dbg_node;  // [nz*(k+1)][4] d/dz of it
+    const double* th_node;   // [nz*(k+1)]    background theta
+    const double* bg_face;   // [nz+1][4]     background at element z-faces
+    const double* dbg_face;  // [nz+1][4]
+    RefTab R;
+};
+
+// One FV level in precision T.
+template <typename T> struct FvArgs {
+    int nxl, nzl, bc, physics;
+    long nc;
+    T hx, hz, area, g, mu;
+    Gas<T> gas;
+    const T* bgc;    // [nzl][4]   background at cell-centre z
+    const T* bgf;    // [nzl+1][4] background at z-faces
+    const T* dbgf;   // [nzl+1][4] d/dz background at z-faces
+};
+
+// device scalar slots of one FV level (doubles)
+enum { LV_UTOT = 0, LV_LAM = 1, LV_DTAU = 2, LV_NSLOT = 4 };
+
+// ---- DG kernels (dg.hip) ----
+// mode 0: <psi,L>  1: M^-1 L  2: G = U - adt M^-1 L - Ubar (+ ||G||^2 into red.out)
+// mode 3: JVP out = Y - adt/eps M^-1 (L(U+eps Y) - L(U)), eps from the device scalars
+//         yn2 = ||Y||^2 and ut2 = ||U + Ubar||^2 (eps_mode 1)
+void launch_dg(int k, bool ns, int mode, const DgArgs& A, const double* U, const double* Y,
+               const double* Ubar, double* out, const double* yn2, const double* ut2, int eps_mode,
+               double adt, Red red, hipStream_t st);
+int transfer_grid(int k, long ne);
+int dg_grid(int k, long ne);
+void launch_initial_state(int k, const DgArgs& A, int shape, double amp, double xc, double zc,
+                          double xr, double zr, double a, double Z, double x0, double z0,
+                          double u_mean, double* U, hipStream_t st);
+// sum over nodes of (U + Ubar)^2
+void launch_norm2_total(int k, const DgArgs& A, const double* U, Red red, hipStream_t st);
+int norm_total_grid(long n);
+
+// ---- transfers (transfer.hip) ----
+template <typename T>
+void launch_transfer_T(int k, const DgArgs& A, int mass_fix, const double* U, T* u, int nxf, hipStream_t st);
+template <typename T>
+void launch_transfer_Tinv(int k, const DgArgs& A, int mass_fix, const T* u, double* U, int nxf, Red red,
+                          hipStream_t st);
+void launch_subgrid_map(int k, const DgArgs& A, int nxf, int* out, hipStream_t st);
+
+// ---- FV kernels (fv.hip) ----
+template <typename T> struct FvLaunch {
+    // F0 = f~(u), then the level slots (||u + Ubar||, max |v| + c, dtau) via red.partials
+    static void lin_level(const FvArgs<T>& A, const T* u, T* F0, Red red, double* slots, double adt, double cfl,
+                          hipStream_t st);
+    // one RK stage; ||x_p||^2 is the sum of xcount partials at xpart; writes the
+    // ||xo||^2 partials to red.partials and returns their count
+    static int stage(const FvArgs<T>& A, const T* u, const T* F0, const T* xp, const T* x0, const T* b, T* xo,
+                     const double* xpart, int xcount, const double* slots, double alpha_j, double adt, int zero,
+                     Red red, hipStream_t st);
+    static void matvec(const FvArgs<T>& A, const T* u, const T* F0, const T* x, T* out, const double* xpart,
+                       int xcount, const double* slots, double adt, hipStream_t st);
+    static void defect_restrict(const FvArgs<T>& A, const T* u, const T* F0, const T* x, const T* b, T* rc,
+                                const double* xpart, int xcount, const double* slots, double adt, int zero,
+                                hipStream_t st);
+    static int prolong_correct(const FvArgs<T>& Af, T* x, const T* v, Red red, hipStream_t st);
+    static void restrict_(const FvArgs<T>& Af, const T* f, T* c, hipStream_t st);
+    static void prolong(const FvArgs<T>& Af, const T* c, T* f, hipStream_t st);
+    static void norm2(const T* x, long n, Red red, hipStream_t st);
+    static int grid_blocks(const FvArgs<T>& A);
+    static int norm_blocks(long n);
+};
+
+// ---- linear algebra (la.hip) ----
+int la_blocks(long n);
+// out[q] = sum over nb block partials [q][nb], fixed order (one block)
+void launch_finalize(const double* partials, int nb, int nq, double* out, hipStream_t st);
+void launch_norm2(const double* x, long n, Red red, hipStream_t st);
+void launch_multidot(const double* w, const double* V, long ld, int nv, long n, Red red, hipStream_t st);
+// w -= sum_i h[i] V_i; optional ||w||^2 into red.out when red.out != nullptr
+void launch_update(double* w, const double* V, long ld, int nv, long n, const double* h, Red red, hipStream_t st);
+void launch_scale(double* out, const double* in, long n, const double* nrm2, hipStream_t st);
+// out = base + sum_i y[i] Z_i   (base may alias out)
+void launch_lincomb(double* out, const double* base, const double* Z, long ld, int nv, long n, const double* y,
+                    hipStream_t st);
+// out = a*x + b*y
+void launch_axpby(double* out, double a, const double* x, double b, const double* y, long n, hipStream_t st);
+
+}  // namespace jfmg

@@ -1,0 +1,197 @@
+// FP64 vector kernels of the FGMRES Arnoldi process (classical Gram-Schmidt
+// with one re-orthogonalization): multi-dot products <w, v_i> of one vector
+// against the whole basis in a single pass, the basis update w -= V h, scaling,
+// and the final combination delta = Z y.  Streaming, HBM bound; every
+// reduction is two-level with a fixed summation order (run-to-run identical).
+#include "jfmg_internal.h"
+
+namespace jfmg {
+
+constexpr int LA_NTH = 256, LA_EL = 4;   // threads per block, elements per thread
+
+int la_blocks(long n)
+{
+    return (int)((n + (long)LA_NTH * LA_EL - 1) / ((long)LA_NTH * LA_EL));
+}
+
+// out[q] = sum_b p[q * nb + b], one block, fixed order
+__global__ void __launch_bounds__(256) finalize_kernel(const double* __restrict__ p, int nb, int nq, double* __restrict__ out)
+{
+    __shared__ double sh[4];
+    for (int q = 0; q < nq; ++q) {
+        double a = 0.0;
+        for (int i = threadIdx.x; i < nb; i += 256) a += p[(long)q * nb + i];
+        a = block_sum<256>(a, sh);
+        if (threadIdx.x == 0) out[q] = a;
+    }
+}
+
+void launch_finalize(const double* partials, int nb, int nq, double* out, hipStream_t st)
+{
+    finalize_kernel<<<dim3(1), dim3(256), 0, st>>>(partials, nb, nq, out);
+}
+
+__global__ void __launch_bounds__(256) norm2_kernel(const double* __restrict__ x, long n, Red red)
+{
+    double s = 0.0;
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) s += x[i] * x[i];
+    put_partial<256>(red, s);
+}
+
+void launch_norm2(const double* x, long n, Red red, hipStream_t st)
+{
+    long b = (n + 255) / 256;
+    const int nb = (int)(b < 1024 ? b : 1024);
+    norm2_kernel<<<dim3(nb), dim3(256), 0, st>>>(x, n, red);
+    if (red.out) launch_finalize(red.partials, nb, 1, red.out, st);
+}
+
+// <w, v_i> for i < nv in one pass: every thread keeps one accumulator per basis
+// vector in registers, each wave reduces all of them with butterflies, and one
+// LDS exchange combines the waves (a single barrier per block); the block
+// partials [v][block] are summed by the finalize kernel.
+template <int MAXV>
+__global__ void __launch_bounds__(LA_NTH)
+multidot_kernel(const double* __restrict__ w, const double* __restrict__ V, long ld, int nv, long n, Red red)
+{
+    constexpr int NW = LA_NTH / 64;
+    __shared__ double sh[NW][MAXV];
+    const long base = (long)blockIdx.x * LA_NTH * LA_EL + threadIdx.x;
+    double acc[MAXV];
+#pragma unroll
+    for (int v = 0; v < MAXV; ++v) acc[v] = 0.0;
+#pragma unroll
+    for (int k = 0; k < LA_EL; ++k) {
+        const long i = base + (long)k * LA_NTH;
+        if (i < n) {
+            const double wi = w[i];
+#pragma unroll
+            for (int v = 0; v < MAXV; ++v)
+                if (v < nv) acc[v] += wi * V[(long)v * ld + i];
+        }
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int v = 0; v < MAXV; ++v) {
+        if (v < nv) {
+            const double s = wave_sum(acc[v]);
+            if (lane == 0) sh[wid][v] = s;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nv) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) s += sh[q][threadIdx.x];
+        red.partials[(long)threadIdx.x * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+void launch_multidot(const double* w, const double* V, long ld, int nv, long n, Red red, hipStream_t st)
+{
+    const dim3 g(la_blocks(n)), b(LA_NTH);
+    if (nv <= 8) multidot_kernel<8><<<g, b, 0, st>>>(w, V, ld, nv, n, red);
+    else if (nv <= 16) multidot_kernel<16><<<g, b, 0, st>>>(w, V, ld, nv, n, red);
+    else if (nv <= 32) multidot_kernel<32><<<g, b, 0, st>>>(w, V, ld, nv, n, red);
+    else multidot_kernel<65><<<g, b, 0, st>>>(w, V, ld, nv, n, red);
+    launch_finalize(red.partials, (int)g.x, nv, red.out, st);
+}
+
+__global__ void __launch_bounds__(LA_NTH)
+update_kernel(double* __restrict__ w, const double* __restrict__ V, long ld, int nv, long n,
+              const double* __restrict__ h, Red red)
+{
+    const long base = (long)blockIdx.x * LA_NTH * LA_EL + threadIdx.x;
+    double acc[LA_EL];
+#pragma unroll
+    for (int k = 0; k < LA_EL; ++k) {
+        const long i = base + (long)k * LA_NTH;
+        acc[k] = i < n ? w[i] : 0.0;
+    }
+    for (int v = 0; v < nv; ++v) {
+        const double hv = h[v];
+        const double* Vi = V + (long)v * ld;
+#pragma unroll
+        for (int k = 0; k < LA_EL; ++k) {
+            const long i = base + (long)k * LA_NTH;
+            if (i < n) acc[k] -= hv * Vi[i];
+        }
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < LA_EL; ++k) {
+        const long i = base + (long)k * LA_NTH;
+        if (i < n) {
+            w[i] = acc[k];
+            s += acc[k] * acc[k];
+        }
+    }
+    if (red.partials) put_partial<LA_NTH>(red, s);
+}
+
+void launch_update(double* w, const double* V, long ld, int nv, long n, const double* h, Red red, hipStream_t st)
+{
+    update_kernel<<<dim3(la_blocks(n)), dim3(LA_NTH), 0, st>>>(w, V, ld, nv, n, h, red);
+    if (red.out) launch_finalize(red.partials, la_blocks(n), 1, red.out, st);
+}
+
+__global__ void __launch_bounds__(256)
+scale_kernel(double* __restrict__ out, const double* __restrict__ in, long n, const double* __restrict__ nrm2)
+{
+    const double s = 1.0 / sqrt(nrm2[0]);
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) out[i] = in[i] * s;
+}
+
+void launch_scale(double* out, const double* in, long n, const double* nrm2, hipStream_t st)
+{
+    long b = (n + 255) / 256;
+    scale_kernel<<<dim3((unsigned)(b < 4096 ? b : 4096)), dim3(256), 0, st>>>(out, in, n, nrm2);
+}
+
+__global__ void __launch_bounds__(LA_NTH)
+lincomb_kernel(double* out, const double* base_, const double* __restrict__ Z, long ld, int nv, long n,
+               const double* __restrict__ y)
+{
+    const long base = (long)blockIdx.x * LA_NTH * LA_EL + threadIdx.x;
+    double acc[LA_EL];
+#pragma unroll
+    for (int k = 0; k < LA_EL; ++k) {
+        const long i = base + (long)k * LA_NTH;
+        acc[k] = (i < n && base_) ? base_[i] : 0.0;
+    }
+    for (int v = 0; v < nv; ++v) {
+        const double yv = y[v];
+        const double* Zi = Z + (long)v * ld;
+#pragma unroll
+        for (int k = 0; k < LA_EL; ++k) {
+            const long i = base + (long)k * LA_NTH;
+            if (i < n) acc[k] += yv * Zi[i];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < LA_EL; ++k) {
+        const long i = base + (long)k * LA_NTH;
+        if (i < n) out[i] = acc[k];
+    }
+}
+
+void launch_lincomb(double* out, const double* base, const double* Z, long ld, int nv, long n, const double* y,
+                    hipStream_t st)
+{
+    lincomb_kernel<<<dim3(la_blocks(n)), dim3(LA_NTH), 0, st>>>(out, base, Z, ld, nv, n, y);
+}
+
+__global__ void __launch_bounds__(256)
+axpby_kernel(double* out, double a, const double* x, double b, const double* y,
+             long n)
+{
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) out[i] = a * x[i] + b * y[i];
+}
+
+void launch_axpby(double* out, double a, const double* x, double b, const double* y, long n, hipStream_t st)
+{
+    long blk = (n + 255) / 256;
+    axpby_kernel<<<dim3((unsigned)(blk < 4096 ? blk : 4096)), dim3(256), 0, st>>>(out, a, x, b, y, n);
+}
+
+}  // namespace jfmg

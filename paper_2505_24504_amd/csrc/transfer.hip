@@ -1,0 +1,193 @@
+// Transfers between the DG space and its FV subgrid (paper Sec. "Transfer
+// functions", eq. transfer-mass-fix and the appendix quadrature).
+//
+//   T^mf:  t_ij = sum_ab V_ia V_jb u_ab  (DG polynomial at the subcell centres),
+//          t -= mean(t) - sum_ij w_i w_j t_ij  (mass of the DG function from the
+//          centre values with the modified Newton-Cotes weights w)
+//   T^-1,mf: u_ab = sum_ij Vinv_ai Vinv_bj t_ij - (sum_ij w_i w_j t_ij - mean(t))
+//
+// One thread per node/subcell, EPB elements per work-group; the (k+1)^2 x
+// (k+1)^2 operator is applied as two 1D contractions through LDS.  The kernels
+// are bound by HBM (<= 2 x 16 FMAs per output value), so no matrix cores.
+// Subcell (i, j) of element (ex, ez) is FV cell (ex (k+1) + i, ez (k+1) + j).
+#include "jfmg_internal.h"
+
+namespace jfmg {
+
+template <int N1> struct TrShape {
+    static constexpr int NP = N1 * N1;
+    static constexpr int NTH = (N1 == 2) ? 64 : 128;
+    static constexpr int EPB = NTH / NP;
+};
+
+__device__ __forceinline__ long subcell_index(int ex, int ez, int i, int j, int n1, int nxf)
+{
+    return (long)(ez * n1 + j) * nxf + (long)ex * n1 + i;
+}
+
+template <int N1, typename T>
+__global__ void __launch_bounds__(TrShape<N1>::NTH)
+transfer_T_kernel(DgArgs A, int mass_fix, const double* __restrict__ U, T* __restrict__ u, int nxf)
+{
+    constexpr int NP = TrShape<N1>::NP, EPB = TrShape<N1>::EPB;
+    __shared__ double sU[EPB][4][NP];
+    __shared__ double sH[EPB][4][NP];
+    const int t = threadIdx.x, le = t / NP, nd = t - le * NP;
+    const bool act = le < EPB;
+    const long e = (long)blockIdx.x * EPB + le;
+    const bool valid = act && e < A.ne;
+    const long N = A.ne * NP;
+    const long nc = N;   // number of finest FV cells
+    if (act)
+        for (int c = 0; c < 4; ++c) sU[le][c][nd] = valid ? U[c * N + e * NP + nd] : 0.0;
+    __syncthreads();
+    const int i = nd % N1, j = nd / N1;   // this thread: x-index i, z-index j
+    // first contraction along x: h_{b,i} = sum_a V_ia u_ab (stored at node slot b*N1+i)
+    if (act)
+        for (int c = 0; c < 4; ++c) {
+            double s = 0.0;
+#pragma unroll
+            for (int a = 0; a < N1; ++a) s += A.R.V[i][a] * sU[le][c][j * N1 + a];
+            sH[le][c][j * N1 + i] = s;
+        }
+    __syncthreads();
+    double tv[4];
+    if (act)
+        for (int c = 0; c < 4; ++c) {
+            double s = 0.0;
+#pragma unroll
+            for (int bb = 0; bb < N1; ++bb) s += A.R.V[j][bb] * sH[le][c][bb * N1 + i];
+            tv[c] = s;
+        }
+    __syncthreads();
+    if (act)
+        for (int c = 0; c < 4; ++c) sU[le][c][nd] = tv[c];
+    __syncthreads();
+    if (valid) {
+        const int ez = (int)(e / A.nx), ex = (int)(e - (long)ez * A.nx);
+        const long o = subcell_index(ex, ez, i, j, N1, nxf);
+        for (int c = 0; c < 4; ++c) {
+            double shift = 0.0;
+            if (mass_fix) {
+                double mean = 0.0, quad = 0.0;
+#pragma unroll
+                for (int jj = 0; jj < N1; ++jj)
+#pragma unroll
+                    for (int ii = 0; ii < N1; ++ii) {
+                        const double v = sU[le][c][jj * N1 + ii];
+                        mean += v;
+                        quad += A.R.wnc[ii] * A.R.wnc[jj] * v;
+                    }
+                shift = mean / NP - quad;
+            }
+            u[c * nc + o] = (T)(tv[c] - shift);
+        }
+    }
+}
+
+template <int N1, typename T>
+__global__ void __launch_bounds__(TrShape<N1>::NTH)
+transfer_Tinv_kernel(DgArgs A, int mass_fix, const T* __restrict__ u, double* __restrict__ U, int nxf, Red red)
+{
+    constexpr int NP = TrShape<N1>::NP, NTH = TrShape<N1>::NTH, EPB = TrShape<N1>::EPB;
+    __shared__ double sT[EPB][4][NP];
+    __shared__ double sH[EPB][4][NP];
+    const int t = threadIdx.x, le = t / NP, nd = t - le * NP;
+    const bool act = le < EPB;
+    const long e = (long)blockIdx.x * EPB + le;
+    const bool valid = act && e < A.ne;
+    const long N = A.ne * NP;
+    const int ez = valid ? (int)(e / A.nx) : 0, ex = valid ? (int)(e - (long)ez * A.nx) : 0;
+    const int i = nd % N1, j = nd / N1;
+    if (act)
+        for (int c = 0; c < 4; ++c)
+            sT[le][c][nd] = valid ? (double)u[c * N + subcell_index(ex, ez, i, j, N1, nxf)] : 0.0;
+    __syncthreads();
+    // thread slot nd = b*N1 + a computes DG node (a, b)
+    const int a = i, b = j;
+    if (act)
+        for (int c = 0; c < 4; ++c) {
+            double s = 0.0;   // h_{jj,a} = sum_i Vinv_ai t_{i,jj}, stored at slot jj*N1+a
+#pragma unroll
+            for (int ii = 0; ii < N1; ++ii) s += A.R.Vinv[a][ii] * sT[le][c][b * N1 + ii];
+            sH[le][c][b * N1 + a] = s;
+        }
+    __syncthreads();
+    double nrm = 0.0;
+    if (valid)
+        for (int c = 0; c < 4; ++c) {
+            double s = 0.0;
+#pragma unroll
+            for (int jj = 0; jj < N1; ++jj) s += A.R.Vinv[b][jj] * sH[le][c][jj * N1 + a];
+            double shift = 0.0;
+            if (mass_fix) {
+                double mean = 0.0, quad = 0.0;
+#pragma unroll
+                for (int jj = 0; jj < N1; ++jj)
+#pragma unroll
+                    for (int ii = 0; ii < N1; ++ii) {
+                        const double v = sT[le][c][jj * N1 + ii];
+                        mean += v;
+                        quad += A.R.wnc[ii] * A.R.wnc[jj] * v;
+                    }
+                shift = quad - mean / NP;
+            }
+            const double v = s - shift;
+            U[c * N + e * NP + nd] = v;
+            nrm += v * v;
+        }
+    if (red.partials) put_partial<NTH>(red, nrm);
+}
+
+template <int N1>
+__global__ void __launch_bounds__(256) subgrid_map_kernel(DgArgs A, int nxf, int* __restrict__ out)
+{
+    constexpr int NP = N1 * N1;
+    const long n = A.ne * NP;
+    const long g = (long)blockIdx.x * 256 + threadIdx.x;
+    if (g >= n) return;
+    const long e = g / NP;
+    const int nd = (int)(g - e * NP);
+    const int ez = (int)(e / A.nx), ex = (int)(e - (long)ez * A.nx);
+    out[subcell_index(ex, ez, nd % N1, nd / N1, N1, nxf)] = (int)g;
+}
+
+int transfer_grid(int k, long ne)
+{
+    const int epb = k == 1 ? TrShape<2>::EPB : k == 2 ? TrShape<3>::EPB : TrShape<4>::EPB;
+    return (int)((ne + epb - 1) / epb);
+}
+
+template <typename T>
+void launch_transfer_T(int k, const DgArgs& A, int mass_fix, const double* U, T* u, int nxf, hipStream_t st)
+{
+    if (k == 1) transfer_T_kernel<2, T><<<dim3((unsigned)((A.ne + TrShape<2>::EPB - 1) / TrShape<2>::EPB)), dim3(TrShape<2>::NTH), 0, st>>>(A, mass_fix, U, u, nxf);
+    else if (k == 2) transfer_T_kernel<3, T><<<dim3((unsigned)((A.ne + TrShape<3>::EPB - 1) / TrShape<3>::EPB)), dim3(TrShape<3>::NTH), 0, st>>>(A, mass_fix, U, u, nxf);
+    else transfer_T_kernel<4, T><<<dim3((unsigned)((A.ne + TrShape<4>::EPB - 1) / TrShape<4>::EPB)), dim3(TrShape<4>::NTH), 0, st>>>(A, mass_fix, U, u, nxf);
+}
+
+template <typename T>
+void launch_transfer_Tinv(int k, const DgArgs& A, int mass_fix, const T* u, double* U, int nxf, Red red, hipStream_t st)
+{
+    const dim3 g(transfer_grid(k, A.ne));
+    if (k == 1) transfer_Tinv_kernel<2, T><<<g, dim3(TrShape<2>::NTH), 0, st>>>(A, mass_fix, u, U, nxf, red);
+    else if (k == 2) transfer_Tinv_kernel<3, T><<<g, dim3(TrShape<3>::NTH), 0, st>>>(A, mass_fix, u, U, nxf, red);
+    else transfer_Tinv_kernel<4, T><<<g, dim3(TrShape<4>::NTH), 0, st>>>(A, mass_fix, u, U, nxf, red);
+    if (red.out) launch_finalize(red.partials, (int)g.x, 1, red.out, st);
+}
+
+template void launch_transfer_T<double>(int, const DgArgs&, int, const double*, double*, int, hipStream_t);
+template void launch_transfer_T<float>(int, const DgArgs&, int, const double*, float*, int, hipStream_t);
+template void launch_transfer_Tinv<double>(int, const DgArgs&, int, const double*, double*, int, Red, hipStream_t);
+template void launch_transfer_Tinv<float>(int, const DgArgs&, int, const float*, double*, int, Red, hipStream_t);
+
+void launch_subgrid_map(int k, const DgArgs& A, int nxf, int* out, hipStream_t st)
+{
+    const long n = A.ne * (k + 1) * (k + 1);
+    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    if (k == 1) subgrid_map_kernel<2><<<grid, block, 0, st>>>(A, nxf, out);
+    else if (k == 2) subgrid_map_kernel<3><<<grid, block, 0, st>>>(A, nxf, out);
+    else subgrid_map_kernel<4><<<grid, block, 0, st>>>(A, nxf, out);
+}
+
+}  // namespace jfmg

@@ -1,0 +1,299 @@
+"""Thin ctypes binding of the jfmg C-ABI (include/jfmg.h).
+
+Argument marshalling only: every numerical step runs in the HIP kernels of
+libjfmg.so.  PyTorch provides device memory (the workspace and the vectors)
+and the HIP stream.  There is no CPU fallback: the library must be built
+(``python -m paper_2505_24504_amd.build``) and a GPU must be present.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libjfmg.so")
+
+OK, EINVAL, ENOMEM, ENOCONV, ENONFINITE, ESTATE, EDEVICE = range(7)
+STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "ENOCONV", 4: "ENONFINITE", 5: "ESTATE", 6: "EDEVICE"}
+
+
+class JfmgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"jfmg {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Config(C.Structure):
+    _fields_ = [(n, C.c_int) for n in (
+        "nx", "nz", "k", "physics", "background", "bc", "scheme", "newton_maxit", "gmres_m",
+        "gmres_max_restarts", "fd_eps_mode", "mg_levels", "rk_stages", "mass_fix", "mg_precision",
+        "precond")] + [("mg_key", C.c_char * 16)] + [(n, C.c_double) for n in (
+        "x0", "x1", "z0", "z1", "g", "gamma", "R", "p0", "theta0", "N", "u_mean", "mu", "c_ip", "dt",
+        "newton_rtol", "ew_gamma", "ew_alpha", "ew_eta0", "ew_eta_max")] + [
+        ("rk_alpha", C.c_double * 4), ("pseudo_cfl", C.c_double)]
+
+
+class Perturbation(C.Structure):
+    _fields_ = [("shape", C.c_int), ("pad", C.c_int)] + [
+        (n, C.c_double) for n in ("amp", "xc", "zc", "xr", "zr", "a", "Z")]
+
+
+class Stats(C.Structure):
+    _fields_ = [("newton_its", C.c_int), ("gmres_its", C.c_int), ("lh_evals", C.c_int), ("jvps", C.c_int),
+                ("fv_matvecs", C.c_int * 8), ("host_syncs", C.c_int), ("status", C.c_int),
+                ("g0_norm", C.c_double), ("g_norm", C.c_double), ("seconds", C.c_double)]
+
+    def as_dict(self):
+        return {"newton_its": self.newton_its, "gmres_its": self.gmres_its, "lh_evals": self.lh_evals,
+                "jvps": self.jvps, "fv_matvecs": list(self.fv_matvecs), "host_syncs": self.host_syncs,
+                "status": self.status, "g0_norm": self.g0_norm, "g_norm": self.g_norm,
+                "seconds": self.seconds}
+
+
+_lib = None
+
+EXPORTS = [
+    "jfmg_config_default", "jfmg_workspace_bytes", "jfmg_create_problem", "jfmg_destroy_problem",
+    "jfmg_num_dofs", "jfmg_fv_size", "jfmg_initial_state", "jfmg_residual", "jfmg_stage_residual",
+    "jfmg_linearize", "jfmg_jvp", "jfmg_mg_apply", "jfmg_implicit_step", "jfmg_transfer",
+    "jfmg_restrict", "jfmg_prolong", "jfmg_fv_level_state", "jfmg_fv_dtau", "jfmg_fv_matvec",
+    "jfmg_mg_fv", "jfmg_subgrid_map", "jfmg_profile_enable", "jfmg_profile_read", "jfmg_last_error",
+]
+
+KERNEL_CLASSES = ["dg_residual", "dg_jvp", "fv_stage", "fv_stage_zero", "fv_defect_restrict",
+                  "fv_prolong_correct", "fv_linearize", "transfer_T", "transfer_Tinv", "multidot",
+                  "update"]
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libjfmg.so and declare the C signatures.  Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libjfmg.so is not built ({path}); run __graft_entry__.build()")
+    L = C.CDLL(path)
+    vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)
+    sig = {
+        "jfmg_config_default": (C.c_int, [C.POINTER(Config)]),
+        "jfmg_workspace_bytes": (C.c_int, [C.POINTER(Config), C.POINTER(C.c_size_t)]),
+        "jfmg_create_problem": (C.c_int, [C.POINTER(Config), vp, C.c_size_t, vp, C.POINTER(vp)]),
+        "jfmg_destroy_problem": (C.c_int, [vp]),
+        "jfmg_num_dofs": (C.c_size_t, [vp]),
+        "jfmg_fv_size": (C.c_size_t, [vp, C.c_int]),
+        "jfmg_initial_state": (C.c_int, [vp, C.POINTER(Perturbation), vp]),
+        "jfmg_residual": (C.c_int, [vp, vp, vp, C.c_int]),
+        "jfmg_stage_residual": (C.c_int, [vp, vp, vp, C.c_double, vp, dp]),
+        "jfmg_linearize": (C.c_int, [vp, vp, C.c_double]),
+        "jfmg_jvp": (C.c_int, [vp, vp, vp]),
+        "jfmg_mg_apply": (C.c_int, [vp, vp, vp]),
+        "jfmg_implicit_step": (C.c_int, [vp, vp, C.POINTER(Stats)]),
+        "jfmg_transfer": (C.c_int, [vp, C.c_int, vp, vp]),
+        "jfmg_restrict": (C.c_int, [vp, C.c_int, vp, vp]),
+        "jfmg_prolong": (C.c_int, [vp, C.c_int, vp, vp]),
+        "jfmg_fv_level_state": (C.c_int, [vp, C.c_int, vp]),
+        "jfmg_fv_dtau": (C.c_int, [vp, C.c_int, dp]),
+        "jfmg_fv_matvec": (C.c_int, [vp, C.c_int, vp, vp]),
+        "jfmg_mg_fv": (C.c_int, [vp, vp, vp]),
+        "jfmg_subgrid_map": (C.c_int, [vp, vp]),
+        "jfmg_profile_enable": (C.c_int, [vp, C.c_uint]),
+        "jfmg_profile_read": (C.c_int, [vp, dp, C.POINTER(C.c_longlong), dp]),
+        "jfmg_last_error": (C.c_char_p, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def make_config(d: dict) -> Config:
+    """Map a problem description dict (paper_2505_24504_amd.workloads) onto jfmg_config."""
+    L = load_library()
+    c = Config()
+    L.jfmg_config_default(C.byref(c))
+    ints = ("nx", "nz", "k", "physics", "background", "bc", "scheme", "newton_maxit", "gmres_m",
+            "gmres_max_restarts", "fd_eps_mode", "mg_levels", "rk_stages", "mass_fix", "mg_precision",
+            "precond")
+    dbls = ("x0", "x1", "z0", "z1", "g", "gamma", "R", "p0", "theta0", "N", "u_mean", "mu", "c_ip", "dt",
+            "newton_rtol", "ew_gamma", "ew_alpha", "ew_eta0", "ew_eta_max", "pseudo_cfl")
+    for n in ints:
+        if n in d:
+            setattr(c, n, int(d[n]))
+    for n in dbls:
+        if n in d:
+            setattr(c, n, float(d[n]))
+    c.mg_key = d.get("mg_key", "mg002222V").encode()
+    alpha = d.get("rk_alpha") or []
+    for j in range(4):
+        c.rk_alpha[j] = float(alpha[j]) if j < len(alpha) else 0.0
+    return c
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def workspace_bytes(d: dict) -> int:
+    L = load_library()
+    cfg = make_config(d)
+    n = C.c_size_t()
+    rc = L.jfmg_workspace_bytes(C.byref(cfg), C.byref(n))
+    if rc:
+        raise JfmgError(rc, L.jfmg_last_error(None).decode())
+    return n.value
+
+
+class Problem:
+    """One problem in a device workspace owned by this object (a torch tensor)."""
+
+    def __init__(self, d: dict, device="cuda", stream=None, workspace=None):
+        self.L = load_library()
+        self.d = dict(d)
+        self.cfg = make_config(d)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nbytes = workspace_bytes(d)
+        self.ws_bytes = nbytes
+        if workspace is None:
+            workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        self.ws = workspace
+        base = workspace.data_ptr()
+        off = (-base) % 256
+        h = C.c_void_p()
+        rc = self.L.jfmg_create_problem(C.byref(self.cfg), C.c_void_p(base + off), nbytes,
+                                        C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if rc:
+            raise JfmgError(rc, self.L.jfmg_last_error(None).decode())
+        self.h = h
+        self.ndof = self.L.jfmg_num_dofs(h)
+        self.fv_dtype = torch.float32 if self.cfg.mg_precision == 32 else torch.float64
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            self.L.jfmg_destroy_problem(h)
+            self.h = None
+
+    def _check(self, rc):
+        if rc:
+            raise JfmgError(rc, self.L.jfmg_last_error(self.h).decode())
+
+    # ---- vectors ----
+    def dg_zeros(self):
+        return torch.zeros(self.ndof, dtype=torch.float64, device=self.device)
+
+    def fv_size(self, level=0):
+        return self.L.jfmg_fv_size(self.h, level)
+
+    def fv_zeros(self, level=0):
+        return torch.zeros(self.fv_size(level), dtype=self.fv_dtype, device=self.device)
+
+    # ---- entry points ----
+    def initial_state(self, pert: dict):
+        P = Perturbation()
+        P.shape = int(pert.get("shape", 0))
+        for n in ("amp", "xc", "zc", "xr", "zr", "a", "Z"):
+            setattr(P, n, float(pert.get(n, 1.0)))
+        U = self.dg_zeros()
+        self._check(self.L.jfmg_initial_state(self.h, C.byref(P), _ptr(U)))
+        return U
+
+    def residual(self, U, apply_minv=False):
+        out = self.dg_zeros()
+        self._check(self.L.jfmg_residual(self.h, _ptr(U), _ptr(out), int(apply_minv)))
+        return out
+
+    def stage_residual(self, U, Ubar, alpha_dt):
+        G = self.dg_zeros()
+        nrm = C.c_double()
+        self._check(self.L.jfmg_stage_residual(self.h, _ptr(U), _ptr(Ubar), float(alpha_dt), _ptr(G),
+                                               C.byref(nrm)))
+        return G, nrm.value
+
+    def linearize(self, U, alpha_dt):
+        self._check(self.L.jfmg_linearize(self.h, _ptr(U), float(alpha_dt)))
+
+    def jvp(self, y):
+        out = self.dg_zeros()
+        self._check(self.L.jfmg_jvp(self.h, _ptr(y), _ptr(out)))
+        return out
+
+    def mg_apply(self, r):
+        z = self.dg_zeros()
+        self._check(self.L.jfmg_mg_apply(self.h, _ptr(r), _ptr(z)))
+        return z
+
+    def implicit_step(self, U, raise_on_error=True):
+        """Advance U (device tensor) in place by one implicit step; returns the stats dict."""
+        st = Stats()
+        rc = self.L.jfmg_implicit_step(self.h, _ptr(U), C.byref(st))
+        d = st.as_dict()
+        d["status"] = rc
+        if rc and raise_on_error:
+            self._check(rc)
+        return d
+
+    def transfer(self, direction, x):
+        if direction == 0:
+            out = self.fv_zeros(0)
+        else:
+            out = self.dg_zeros()
+        self._check(self.L.jfmg_transfer(self.h, int(direction), _ptr(x), _ptr(out)))
+        return out
+
+    def restrict(self, fine_level, x):
+        out = self.fv_zeros(fine_level + 1)
+        self._check(self.L.jfmg_restrict(self.h, fine_level, _ptr(x), _ptr(out)))
+        return out
+
+    def prolong(self, coarse_level, x):
+        out = self.fv_zeros(coarse_level - 1)
+        self._check(self.L.jfmg_prolong(self.h, coarse_level, _ptr(x), _ptr(out)))
+        return out
+
+    def fv_level_state(self, level):
+        out = self.fv_zeros(level)
+        self._check(self.L.jfmg_fv_level_state(self.h, level, _ptr(out)))
+        return out
+
+    def fv_dtau(self, level):
+        v = C.c_double()
+        self._check(self.L.jfmg_fv_dtau(self.h, level, C.byref(v)))
+        return v.value
+
+    def fv_matvec(self, level, x):
+        out = self.fv_zeros(level)
+        self._check(self.L.jfmg_fv_matvec(self.h, level, _ptr(x), _ptr(out)))
+        return out
+
+    def mg_fv(self, b):
+        x = self.fv_zeros(0)
+        self._check(self.L.jfmg_mg_fv(self.h, _ptr(b), _ptr(x)))
+        return x
+
+    def profile_enable(self, classes=()):
+        mask = 0
+        for c in classes:
+            mask |= 1 << KERNEL_CLASSES.index(c)
+        self._check(self.L.jfmg_profile_enable(self.h, mask))
+
+    def profile_read(self):
+        n = len(KERNEL_CLASSES)
+        ms = (C.c_double * n)()
+        cnt = (C.c_longlong * n)()
+        by = (C.c_double * n)()
+        self._check(self.L.jfmg_profile_read(self.h, ms, cnt, by))
+        return {KERNEL_CLASSES[i]: {"ms": ms[i], "launches": cnt[i], "bytes": by[i]} for i in range(n)}
+
+    def subgrid_map(self):
+        out = torch.zeros(self.fv_size(0) // 4, dtype=torch.int32, device=self.device)
+        self._check(self.L.jfmg_subgrid_map(self.h, _ptr(out)))
+        return out

@@ -1,0 +1,89 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol that
+include/jfmg.h declares, its struct layouts match the binding, and it rejects
+bad configurations (no GPU call is made)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2505_24504_amd import jfmg, workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "jfmg.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(jfmg.LIB_PATH):
+        from paper_2505_24504_amd import build
+        build.build()
+    return jfmg.load_library()
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(jfmg_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lib):
+    syms = declared_symbols()
+    assert len(syms) >= 20
+    out = subprocess.run(["nm", "-D", "--defined-only", jfmg.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (jfmg_\w+)", out))
+    missing = [s for s in syms if s not in exported]
+    assert not missing, missing
+    for s in syms:
+        getattr(lib, s)
+    assert set(jfmg.EXPORTS) == set(syms)
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "lay.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "jfmg.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(jfmg_config), offsetof(jfmg_config, mg_key),
+         offsetof(jfmg_config, x0), offsetof(jfmg_config, rk_alpha), sizeof(jfmg_perturbation),
+         sizeof(jfmg_stats));
+  return 0; }
+''')
+    exe = tmp_path / "lay"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    vals = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    assert vals == [C.sizeof(jfmg.Config), jfmg.Config.mg_key.offset, jfmg.Config.x0.offset,
+                    jfmg.Config.rk_alpha.offset, C.sizeof(jfmg.Perturbation), C.sizeof(jfmg.Stats)]
+
+
+def test_workspace_sizes(lib):
+    for d, _, _ in (W.bubble_small(), W.density_current(), W.inertia_gravity()):
+        n = jfmg.workspace_bytes(d)
+        N = 4 * d["nx"] * d["nz"] * (d["k"] + 1) ** 2
+        assert n > 8 * N * (2 * d["gmres_m"] + 1)
+
+
+@pytest.mark.parametrize("bad,what", [
+    ({"k": 0}, "k must"), ({"k": 4}, "k must"), ({"gmres_m": 65}, "gmres_m"),
+    ({"mg_levels": 9}, "mg_levels"), ({"mg_key": "mg102222V"}, "a, b"), ({"mg_key": "mgxx"}, "key"),
+    ({"nx": 3, "mg_levels": 3}, "odd"), ({"mg_precision": 16}, "precision"), ({"rk_stages": 5}, "rk_stages"),
+    ({"background": 1, "N": 0.0}, "N > 0"), ({"dt": 0.0}, "constants"),
+])
+def test_invalid_configs_rejected(lib, bad, what):
+    d, _, _ = W.bubble_small()
+    d = dict(d, **bad)
+    with pytest.raises(jfmg.JfmgError) as ei:
+        jfmg.workspace_bytes(d)
+    assert ei.value.status == jfmg.EINVAL
+    assert what in str(ei.value)
+
+
+def test_create_rejects_small_workspace(lib):
+    d, _, _ = W.bubble_small()
+    cfg = jfmg.make_config(d)
+    h = C.c_void_p()
+    rc = lib.jfmg_create_problem(C.byref(cfg), C.c_void_p(256), 16, None, C.byref(h))
+    assert rc == jfmg.ENOMEM
+    assert b"workspace" in lib.jfmg_last_error(None)
