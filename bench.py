@@ -103,9 +103,12 @@ def main():
     if prof_cls == "auto":
         _, _, _, _, prof_all = run_form(d, pert, 1, 0, jfmg.KERNEL_CLASSES)
         prof_cls = max(prof_all, key=lambda k: prof_all[k]["ms"])
-    # timed pass, FP64 multigrid (headline), events only around the profiled class
-    p, el, lat, its, prof = run_form(d, pert, a.steps, a.warmup, [prof_cls])
+    # timed pass, FP64 multigrid (headline): captured HIP graphs, no instrumentation
+    p, el, lat, its, _ = run_form(d, pert, a.steps, a.warmup, [])
     value = a.steps * N / el
+    # second timed pass of the same workload: the dominant kernel class timed by the
+    # start/stop events of its own dispatches (eager launches; see include/jfmg.h)
+    _, el_prof, _, _, prof = run_form(d, pert, a.steps, a.warmup, [prof_cls])
     pc = prof[prof_cls]
     avg_ms = pc["ms"] / max(pc["launches"], 1)
     bytes_per_launch = pc["bytes"] / max(pc["launches"], 1)
@@ -146,7 +149,9 @@ def main():
         "roofline": {"bound": "hbm", "kernel": prof_cls, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
                      "avg_launch_us": 1e3 * avg_ms, "launches": pc["launches"],
-                     "algorithmic_bytes_per_launch": bytes_per_launch},
+                     "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "timing": "HIP start/stop events of each dispatch of the kernel class, second timed pass "
+                               f"of the same {a.steps} steps without graph replay ({1e3 * el_prof / a.steps:.1f} ms/step)"},
     }
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()

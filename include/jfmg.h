@@ -166,12 +166,14 @@ jfmg_status jfmg_mg_fv(jfmg_problem* p, const void* b, void* x);
 jfmg_status jfmg_subgrid_map(jfmg_problem* p, int* fv_to_dg);
 
 /* ---- kernel-class timing (benchmark instrumentation) ----
-   When a class's bit is set in class_mask, every launch of that class is
-   bracketed by two HIP events on the problem's stream; jfmg_profile_read
-   returns per class the summed event time [ms], the launch count and the
-   summed algorithmic HBM bytes (what the launch must read and write at
-   minimum, e.g. 5 FV vectors for a smoother stage with a matvec).  Enabling
-   resets the counters and synchronizes the stream. */
+   When a class's bit is set in class_mask, every launch of that class records
+   the start and stop events of its own dispatch (hipExtLaunchKernel) on the
+   stream it runs on; jfmg_profile_read returns per class the summed event time
+   [ms], the launch count and the summed algorithmic HBM bytes (what the launch
+   must read and write at minimum, e.g. 5 FV vectors for a smoother stage with a
+   matvec).  While a mask is set, implicit steps launch eagerly instead of
+   replaying their captured HIP graphs (event timing inside graphs is not
+   available).  Enabling resets the counters and synchronizes the stream. */
 typedef enum {
     JFMG_K_DG_RESIDUAL = 0,   /* stage residual G and ||G||                         */
     JFMG_K_DG_JVP = 1,        /* fused FD Jacobian-vector product                   */

@@ -93,18 +93,20 @@ dg_kernel(DgArgs A, const double* __restrict__ U, const double* __restrict__ Y, 
         const int zi = ez * N1 + b;
 #pragma unroll
         for (int c = 0; c < 4; ++c) { Ub[c] = A.bg_node[zi * 4 + c]; dUb[c] = A.dbg_node[zi * 4 + c]; }
+        const double pbz = A.pb_node[zi], irz = A.irt_node[zi];
         double fx[4], fz[4];
 #pragma unroll
         for (int s = 0; s < NSt; ++s) {
             double Ut[4], Fx[4], Fz[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) Ut[c] = sS[s][le][c][nd] + Ub[c];
-            conv_flux(A.gas, Ut, 1.0, 0.0, Fx);
-            conv_flux(A.gas, Ut, 0.0, 1.0, Fz);
+            const double pt = pert_pressure(A.gas, sS[s][le][3][nd], irz, pbz);
+            conv_flux(Ut, pt, 1.0, 0.0, Fx);
+            conv_flux(Ut, pt, 0.0, 1.0, Fz);
             if constexpr (MODE != 3) {
                 double Bx[4], Bz[4];
-                conv_flux(A.gas, Ub, 1.0, 0.0, Bx);
-                conv_flux(A.gas, Ub, 0.0, 1.0, Bz);
+                conv_flux(Ub, pbz, 1.0, 0.0, Bx);
+                conv_flux(Ub, pbz, 0.0, 1.0, Bz);
 #pragma unroll
                 for (int c = 0; c < 4; ++c) { Fx[c] -= Bx[c]; Fz[c] -= Bz[c]; }
             }
@@ -194,6 +196,8 @@ dg_kernel(DgArgs A, const double* __restrict__ U, const double* __restrict__ Y, 
             const double* dbgp = xf ? A.dbg_node : A.dbg_face;
 #pragma unroll
             for (int c = 0; c < 4; ++c) { Ub[c] = bgp[zrow * 4 + c]; dUb[c] = dbgp[zrow * 4 + c]; }
+            const double pbz = xf ? A.pb_node[zrow] : A.pb_face[zrow];
+            const double irz = xf ? A.irt_node[zrow] : A.irt_face[zrow];
             double flux[4] = {0, 0, 0, 0}, sym[4] = {0, 0, 0, 0};
 #pragma unroll
             for (int s = 0; s < NSt; ++s) {
@@ -206,6 +210,8 @@ dg_kernel(DgArgs A, const double* __restrict__ U, const double* __restrict__ Y, 
                     tro[c] = v;
                     Uo[c] = v + Ub[c];
                 }
+                const double po = pert_pressure(A.gas, tro[3], irz, pbz);
+                double px = po;
                 if (wall) {
 #pragma unroll
                     for (int c = 0; c < 4; ++c) Ux[c] = Uo[c];
@@ -213,15 +219,16 @@ dg_kernel(DgArgs A, const double* __restrict__ U, const double* __restrict__ Y, 
                 } else {
 #pragma unroll
                     for (int c = 0; c < 4; ++c) Ux[c] = sTx[s][le][f][r][c] + Ub[c];
+                    px = pert_pressure(A.gas, sTx[s][le][f][r][3], irz, pbz);
                 }
-                hllc(A.gas, Uo, Ux, nxn, nzn, H);
+                hllc(A.gas, Uo, Ux, po, px, nxn, nzn, H);
                 double fl[4], sy[4] = {0, 0, 0, 0};
                 if constexpr (MODE != 3) {
                     double Um[4], Hb[4];
 #pragma unroll
                     for (int c = 0; c < 4; ++c) Um[c] = Ub[c];
                     if (wall) { if (xf) Um[1] = -Ub[1]; else Um[2] = -Ub[2]; }
-                    hllc(A.gas, Ub, Um, nxn, nzn, Hb);
+                    hllc(A.gas, Ub, Um, pbz, pbz, nxn, nzn, Hb);
 #pragma unroll
                     for (int c = 0; c < 4; ++c) H[c] -= Hb[c];
                 }
@@ -338,15 +345,15 @@ static void launch_dg_n(int mode, const DgArgs& A, const double* U, const double
 {
     const dim3 grid(dg_grid(N1 - 1, A.ne)), block(DgShape<N1>::NTH);
     if (mode == 2 && red.out) {
-        dg_kernel<N1, NS, 2><<<grid, block, 0, st>>>(A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red);
+        timed_launch(dg_kernel<N1, NS, 2>, grid, block, st, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red);
         launch_finalize(red.partials, (int)grid.x, 1, red.out, st);
         return;
     }
     switch (mode) {
-    case 0: dg_kernel<N1, NS, 0><<<grid, block, 0, st>>>(A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red); break;
-    case 1: dg_kernel<N1, NS, 1><<<grid, block, 0, st>>>(A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red); break;
-    case 2: dg_kernel<N1, NS, 2><<<grid, block, 0, st>>>(A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red); break;
-    default: dg_kernel<N1, NS, 3><<<grid, block, 0, st>>>(A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red); break;
+    case 0: timed_launch(dg_kernel<N1, NS, 0>, grid, block, st, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red); break;
+    case 1: timed_launch(dg_kernel<N1, NS, 1>, grid, block, st, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red); break;
+    case 2: timed_launch(dg_kernel<N1, NS, 2>, grid, block, st, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red); break;
+    default: timed_launch(dg_kernel<N1, NS, 3>, grid, block, st, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red); break;
     }
 }
 

@@ -11,11 +11,16 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
 
 using namespace jfmg;
+
+namespace jfmg {
+thread_local LaunchTimer g_launch_timer;
+}
 
 namespace {
 
@@ -235,12 +240,13 @@ enum {
     S_UTOT = 1,     // ||U + Ubar||^2 (DG)
     S_Y = 2,        // ||y||^2 for jvp
     S_Z = 3,        // ||z_j||^2
-    S_W = 4,        // ||w||^2 after orthogonalization
+    S_W = 258,      // ||w||^2 after orthogonalization (right after h2: one readback)
     S_R = 5,        // restart residual norm^2
     S_TMP = 6,
     S_LEV = 16,     // + 4*level: LV_* slots
     S_H1 = 128,     // 65 entries
-    S_H2 = 256,     // 65 entries
+    S_H2 = 193,     // 65 entries
+    S_HB = 131,     // doubles from S_H1 through S_W
     S_Yc = 384      // 65 entries: FGMRES coefficients
 };
 
@@ -267,6 +273,8 @@ struct Level {
     void* bgc;
     void* bgf;
     void* dbgf;
+    void* pc;
+    void* pf;
 };
 
 }  // namespace
@@ -280,7 +288,9 @@ struct jfmg_problem {
     int nlev;
     Level lev[MAXLEV];
     int prec;          // 64 or 32
-    hipStream_t st;
+    hipStream_t st;        // stream the internal functions issue to (user_st or cs)
+    hipStream_t user_st;   // the caller's stream
+    hipStream_t cs;        // private stream of jfmg_implicit_step (graph capture and replay)
     RefTab R;
     DgArgs A;
     // device memory (in the caller's workspace)
@@ -291,6 +301,7 @@ struct jfmg_problem {
     size_t fvp;
     int xcnt[MAXLEV][3];
     double* bg_node; double* dbg_node; double* th_node; double* bg_face; double* dbg_face;
+    double* pb_node; double* pb_face;   // [.][2]: background pressure, 1/(rho theta)
     double *Un, *Ubar, *Uk, *G, *delta, *tmp1, *tmp2, *Ulin;
     double *V, *Z;
     int m;
@@ -304,6 +315,18 @@ struct jfmg_problem {
         long long cnt[JFMG_K_NCLASS] = {};
         double bytes[JFMG_K_NCLASS] = {};
     } prof;
+    // one captured HIP graph per FGMRES iteration index j
+    struct IterGraph {
+        hipGraphExec_t exec = nullptr;
+        int mv[MAXLEV] = {};
+        int jvps = 0;
+    };
+    std::vector<IterGraph> graphs;
+    double graph_adt = 0.0;
+    bool use_graphs = true;
+    IterGraph* capturing = nullptr;
+    double* hpin = nullptr;            // pinned host copies of the Arnoldi scalars, per iteration
+    std::vector<hipEvent_t> hev;       // completion of each copy
     // host side
     int have_lin;
     double adt;
@@ -341,27 +364,28 @@ hipEvent_t ev_get(jfmg_problem* p)
     return e;
 }
 
-// Records a HIP event pair around one launch of kernel class `cls` when that
-// class is being profiled; `bytes` is the launch's algorithmic HBM traffic.
+// Times the next launch of kernel class `cls` (when that class is being
+// profiled) with the start/stop events of its own dispatch; `bytes` is the
+// launch's algorithmic HBM traffic.  Not used while a graph is captured.
 struct ProfScope {
     jfmg_problem* p;
     int cls;
     double bytes;
-    hipEvent_t a = nullptr;
-    ProfScope(jfmg_problem* p_, int c, double b) : p(p_), cls(c), bytes(b)
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(jfmg_problem* p_, int c, double by) : p(p_), cls(c), bytes(by)
     {
-        if (p->prof.mask & (1u << cls)) {
-            a = ev_get(p);
-            if (a) (void)hipEventRecord(a, p->st);
-        }
+        if (!(p->prof.mask & (1u << cls)) || p->capturing) return;
+        a = ev_get(p);
+        b = ev_get(p);
+        if (!a || !b) return;
+        g_launch_timer = LaunchTimer{a, b, false};
     }
     ~ProfScope()
     {
-        if (!a) return;
-        hipEvent_t b = ev_get(p);
-        if (!b) return;
-        (void)hipEventRecord(b, p->st);
-        p->prof.pend.push_back({cls, a, b, bytes});
+        if (!a || !b) return;
+        if (g_launch_timer.used) p->prof.pend.push_back({cls, a, b, bytes});
+        else { p->prof.pool.push_back(a); p->prof.pool.push_back(b); }
+        g_launch_timer = LaunchTimer{};
     }
 };
 
@@ -441,6 +465,8 @@ size_t layout(const jfmg_config& c, char* base, F&& bind)
     bind("th_node", cv.take((size_t)c.nz * n1 * 8), 0);
     bind("bg_face", cv.take((size_t)(c.nz + 1) * 4 * 8), 0);
     bind("dbg_face", cv.take((size_t)(c.nz + 1) * 4 * 8), 0);
+    bind("pb_node", cv.take((size_t)c.nz * n1 * 2 * 8), 0);
+    bind("pb_face", cv.take((size_t)(c.nz + 1) * 2 * 8), 0);
     const char* dgn[] = {"Un", "Ubar", "Uk", "G", "delta", "tmp1", "tmp2", "Ulin"};
     for (const char* s : dgn) bind(s, cv.take((size_t)N * 8), 0);
     bind("V", cv.take((size_t)N * 8 * (m + 1)), 0);
@@ -453,6 +479,8 @@ size_t layout(const jfmg_config& c, char* base, F&& bind)
         bind("bgc", cv.take((size_t)nzl * 4 * ts), l);
         bind("bgf", cv.take((size_t)(nzl + 1) * 4 * ts), l);
         bind("dbgf", cv.take((size_t)(nzl + 1) * 4 * ts), l);
+        bind("pc", cv.take((size_t)nzl * 2 * ts), l);
+        bind("pf", cv.take((size_t)(nzl + 1) * 2 * ts), l);
         nxl /= 2;
         nzl /= 2;
     }
@@ -474,14 +502,33 @@ jfmg_status read_scalars(jfmg_problem* p, int slot, int count, double* out)
     return JFMG_OK;
 }
 
+// gas constants and the binomial coefficients C(gamma, k) of (1 + s)^gamma
+template <typename T> Gas<T> make_gas(const jfmg_config& c)
+{
+    Gas<T> g;
+    g.gamma = (T)c.gamma;
+    g.R = (T)c.R;
+    g.p0 = (T)c.p0;
+    double ck = 1.0;
+    for (int k = 0; k < GAS_NCOEF; ++k) {
+        g.cg[k] = (T)ck;
+        ck *= (c.gamma - k) / (k + 1.0);
+    }
+    return g;
+}
+
+// background pressure p0 (R rho_theta / p0)^gamma of the potential-temperature equation of state
+double bg_pressure(const jfmg_config& c, double rt) { return c.p0 * std::pow(c.R * rt / c.p0, c.gamma); }
+
 template <typename T> FvArgs<T> fv_args(const jfmg_problem* p, int l)
 {
     FvArgs<T> A;
     const Level& L = p->lev[l];
     A.nxl = L.nx; A.nzl = L.nz; A.bc = p->cfg.bc; A.physics = p->cfg.physics; A.nc = L.nc;
     A.hx = (T)L.hx; A.hz = (T)L.hz; A.area = (T)(L.hx * L.hz); A.g = (T)p->cfg.g; A.mu = (T)p->cfg.mu;
-    A.gas = Gas<T>{(T)p->cfg.gamma, (T)p->cfg.R, (T)p->cfg.p0};
+    A.gas = make_gas<T>(p->cfg);
     A.bgc = (const T*)L.bgc; A.bgf = (const T*)L.bgf; A.dbgf = (const T*)L.dbgf;
+    A.pc = (const T*)L.pc; A.pf = (const T*)L.pf;
     return A;
 }
 
@@ -572,7 +619,7 @@ template <typename T> struct Mg {
             if (!s.xzero[l + 1]) {
                 if (s.xzero[l]) {
                     // x = 0 - P v: materialize the zero vector first
-                    hipMemsetAsync(L.buf[s.xi[l]], 0, sizeof(T) * 4 * L.nc, p->st);
+                    launch_zero(L.buf[s.xi[l]], sizeof(T) * 4 * L.nc, p->st);
                 }
                 ProfScope ps2(p, JFMG_K_FV_PROLONG, 2.25 * 4.0 * L.nc * sizeof(T));
                 p->xcnt[l][s.xi[l]] = FvLaunch<T>::prolong_correct(A, (T*)L.buf[s.xi[l]], (const T*)C.buf[s.xi[l + 1]],
@@ -592,7 +639,7 @@ template <typename T> struct Mg {
         s.xzero[0] = true;
         cycle(0);
         Level& L = p->lev[0];
-        if (s.xzero[0]) hipMemsetAsync(L.buf[s.xi[0]], 0, sizeof(T) * 4 * L.nc, p->st);
+        if (s.xzero[0]) launch_zero(L.buf[s.xi[0]], sizeof(T) * 4 * L.nc, p->st);
         return (T*)L.buf[s.xi[0]];
     }
 };
@@ -655,6 +702,91 @@ jfmg_status stage_residual(jfmg_problem* p, const double* U, const double* Ubar,
 // Right-preconditioned FGMRES(m) for G'(U) delta = -G, CGS2 Arnoldi on device,
 // Givens rotations on the host; U += delta on success.
 // ---------------------------------------------------------------------------
+// One FGMRES iteration on the device: v_j = w_{j-1}/||w_{j-1}|| (j > 0),
+// z_j = Q^-1 v_j, w = G'(U) z_j, classical Gram-Schmidt twice against v_0..v_j;
+// leaves h1, h2 and ||w||^2 in the scalar slots.  No host synchronization.
+jfmg_status iter_ops(jfmg_problem* p, int j)
+{
+    const long N = p->N;
+    hipStream_t st = p->st;
+    double* vj = p->V + (long)j * N;
+    double* zj = p->Z + (long)j * N;
+    double* w = p->V + (long)(j + 1) * N;
+    if (j > 0) launch_scale(vj, vj, N, p->scal + S_W, st);
+    jfmg_status s = precond(p, vj, zj, S_Z);
+    if (s) return s;
+    jvp_slot(p, zj, w, S_Z);
+    const double md = (j + 2.0) * N * 8, up = (j + 3.0) * N * 8;
+    { ProfScope ps(p, JFMG_K_MULTIDOT, md); launch_multidot(w, p->V, N, j + 1, N, red_at(p, S_H1), st); }
+    { ProfScope ps(p, JFMG_K_UPDATE, up); launch_update(w, p->V, N, j + 1, N, p->scal + S_H1, no_red(), st); }
+    { ProfScope ps(p, JFMG_K_MULTIDOT, md); launch_multidot(w, p->V, N, j + 1, N, red_at(p, S_H2), st); }
+    { ProfScope ps(p, JFMG_K_UPDATE, up); launch_update(w, p->V, N, j + 1, N, p->scal + S_H2, red_at(p, S_W), st); }
+    return check_launch(p);
+}
+
+void invalidate_graphs(jfmg_problem* p)
+{
+    for (auto& g : p->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        g.exec = nullptr;
+    }
+}
+
+// Run iteration j, from its captured graph when graphs are on (captured on
+// first use; the multigrid schedule and all pointers are fixed per problem,
+// every varying scalar lives in device memory).
+jfmg_status run_iter(jfmg_problem* p, int j)
+{
+    if (!p->use_graphs || p->prof.mask) return iter_ops(p, j);   // profiling times eager launches
+    if ((int)p->graphs.size() < p->m) p->graphs.resize(p->m);
+    if (p->graph_adt != p->adt) {
+        invalidate_graphs(p);
+        p->graph_adt = p->adt;
+    }
+    auto& G = p->graphs[j];
+    if (!G.exec) {
+        int mv0[MAXLEV];
+        std::memcpy(mv0, p->mv_count, sizeof(mv0));
+        const int j0 = p->jvp_count;
+        HIPCHK(p, hipStreamBeginCapture(p->st, hipStreamCaptureModeThreadLocal));
+        p->capturing = &G;
+        jfmg_status s = iter_ops(p, j);
+        p->capturing = nullptr;
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(p->st, &graph);
+        if (s) {
+            if (!e && graph) (void)hipGraphDestroy(graph);
+            return s;
+        }
+        if (!e) {
+            e = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+        }
+        if (e) {   // graphs unavailable here: run this problem eagerly from now on
+            G.exec = nullptr;
+            (void)hipGetLastError();
+            std::memcpy(p->mv_count, mv0, sizeof(mv0));
+            p->jvp_count = j0;
+            p->use_graphs = false;
+            return iter_ops(p, j);
+        }
+        for (int l = 0; l < MAXLEV; ++l) {
+            G.mv[l] = p->mv_count[l] - mv0[l];
+            p->mv_count[l] = mv0[l];
+        }
+        G.jvps = p->jvp_count - j0;
+        p->jvp_count = j0;
+    }
+    HIPCHK(p, hipGraphLaunch(G.exec, p->st));
+    for (int l = 0; l < MAXLEV; ++l) p->mv_count[l] += G.mv[l];
+    p->jvp_count += G.jvps;
+    return JFMG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Right-preconditioned FGMRES(m) for G'(U) delta = -G, CGS2 Arnoldi on device,
+// Givens rotations on the host; U += delta on success.
+// ---------------------------------------------------------------------------
 jfmg_status fgmres(jfmg_problem* p, const double* G, double gnorm, double tol_abs, double* U, int* its_out)
 {
     const long N = p->N;
@@ -665,39 +797,37 @@ jfmg_status fgmres(jfmg_problem* p, const double* G, double gnorm, double tol_ab
     int its = 0;
     // V_0 = -G / beta
     launch_axpby(p->V, -1.0 / beta, G, 0.0, G, N, st);
-    HIPCHK(p, hipMemsetAsync(p->delta, 0, sizeof(double) * N, st));
+    launch_zero(p->delta, sizeof(double) * N, st);
     jfmg_status status = JFMG_ENOCONV;
-    std::vector<double> hb(2 * 65 + 1);
     for (int cyc = 0; cyc <= p->cfg.gmres_max_restarts; ++cyc) {
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
         int jend = 0;
         bool conv = false;
+        // Iteration j+1 is issued before the host looks at iteration j's
+        // Hessenberg column, so the readback round trip overlaps GPU work; when
+        // iteration j converges the speculative iteration's output is unused.
+        auto issue = [&](int j) -> jfmg_status {
+            jfmg_status s = run_iter(p, j);
+            if (s) return s;
+            HIPCHK(p, hipMemcpyAsync(p->hpin + (size_t)j * S_HB, p->scal + S_H1, sizeof(double) * S_HB,
+                                     hipMemcpyDeviceToHost, st));
+            HIPCHK(p, hipEventRecord(p->hev[j], st));
+            return JFMG_OK;
+        };
+        jfmg_status s0 = issue(0);
+        if (s0) return s0;
         for (int j = 0; j < m; ++j) {
-            double* vj = p->V + (long)j * N;
-            double* zj = p->Z + (long)j * N;
-            double* w = p->V + (long)(j + 1) * N;
-            jfmg_status s = precond(p, vj, zj, S_Z);
-            if (s) return s;
-            jvp_slot(p, zj, w, S_Z);
-            // classical Gram-Schmidt, twice
-            const double md = (j + 2.0) * N * 8, up = (j + 3.0) * N * 8;
-            { ProfScope ps(p, JFMG_K_MULTIDOT, md); launch_multidot(w, p->V, N, j + 1, N, red_at(p, S_H1), st); }
-            { ProfScope ps(p, JFMG_K_UPDATE, up); launch_update(w, p->V, N, j + 1, N, p->scal + S_H1, no_red(), st); }
-            { ProfScope ps(p, JFMG_K_MULTIDOT, md); launch_multidot(w, p->V, N, j + 1, N, red_at(p, S_H2), st); }
-            { ProfScope ps(p, JFMG_K_UPDATE, up); launch_update(w, p->V, N, j + 1, N, p->scal + S_H2, red_at(p, S_W), st); }
-            s = check_launch(p);
-            if (s) return s;
-            // one readback: h1, h2, ||w||^2
-            HIPCHK(p, hipMemcpyAsync(hb.data(), p->scal + S_H1, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, st));
-            HIPCHK(p, hipMemcpyAsync(hb.data() + 65, p->scal + S_H2, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, st));
-            HIPCHK(p, hipMemcpyAsync(hb.data() + 130, p->scal + S_W, sizeof(double), hipMemcpyDeviceToHost, st));
-            HIPCHK(p, hipStreamSynchronize(st));
+            if (j + 1 < m) {
+                jfmg_status s = issue(j + 1);
+                if (s) return s;
+            }
+            HIPCHK(p, hipEventSynchronize(p->hev[j]));
             p->syncs++;
-            for (int i = 0; i <= j; ++i) H[i * m + j] = hb[i] + hb[65 + i];
-            const double hn = std::sqrt(hb[130]);
+            const double* hb = p->hpin + (size_t)j * S_HB;
+            for (int i = 0; i <= j; ++i) H[i * m + j] = hb[i] + hb[(S_H2 - S_H1) + i];
+            const double hn = std::sqrt(hb[S_W - S_H1]);
             H[(j + 1) * m + j] = hn;
-            if (hn > 0.0) launch_scale(w, w, N, p->scal + S_W, st);
             for (int i = 0; i < j; ++i) {
                 const double a = H[i * m + j], b = H[(i + 1) * m + j];
                 H[i * m + j] = cs[i] * a + sn[i] * b;
@@ -726,6 +856,7 @@ jfmg_status fgmres(jfmg_problem* p, const double* G, double gnorm, double tol_ab
         }
         HIPCHK(p, hipMemcpyAsync(p->scal + S_Yc, y.data(), sizeof(double) * jend, hipMemcpyHostToDevice, st));
         launch_lincomb(p->delta, p->delta, p->Z, N, jend, N, p->scal + S_Yc, st);
+        prof_flush(p);
         if (conv) { status = JFMG_OK; break; }
         if (cyc == p->cfg.gmres_max_restarts) break;
         // restart from the true residual r = -G - G' delta
@@ -844,6 +975,12 @@ jfmg_status jfmg_create_problem(const jfmg_config* cfg, void* workspace, size_t 
     p->prec = cfg->mg_precision;
     p->m = cfg->gmres_m;
     p->st = (hipStream_t)hip_stream;
+    p->user_st = p->st;
+    p->cs = nullptr;
+    {
+        const char* ng = std::getenv("JFMG_NO_GRAPH");
+        p->use_graphs = !(ng && ng[0] == '1');
+    }
     if (!build_reftab(cfg->k, p->R)) { delete p; return fail(nullptr, JFMG_EINVAL, "singular subcell interpolation"); }
     layout(*cfg, (char*)workspace, [&](const char* name, void* ptr, size_t n) {
         const std::string nm(name);
@@ -855,6 +992,8 @@ jfmg_status jfmg_create_problem(const jfmg_config* cfg, void* workspace, size_t 
         else if (nm == "th_node") p->th_node = (double*)ptr;
         else if (nm == "bg_face") p->bg_face = (double*)ptr;
         else if (nm == "dbg_face") p->dbg_face = (double*)ptr;
+        else if (nm == "pb_node") p->pb_node = (double*)ptr;
+        else if (nm == "pb_face") p->pb_face = (double*)ptr;
         else if (nm == "Un") p->Un = (double*)ptr;
         else if (nm == "Ubar") p->Ubar = (double*)ptr;
         else if (nm == "Uk") p->Uk = (double*)ptr;
@@ -876,6 +1015,8 @@ jfmg_status jfmg_create_problem(const jfmg_config* cfg, void* workspace, size_t 
             else if (nm == "bgc") L.bgc = ptr;
             else if (nm == "bgf") L.bgf = ptr;
             else if (nm == "dbgf") L.dbgf = ptr;
+            else if (nm == "pc") L.pc = ptr;
+            else if (nm == "pf") L.pf = ptr;
         }
     });
     // level geometry
@@ -892,6 +1033,7 @@ jfmg_status jfmg_create_problem(const jfmg_config* cfg, void* workspace, size_t 
     const int n1 = p->n1;
     std::vector<double> bgn((size_t)cfg->nz * n1 * 4), dbgn(bgn.size()), thn((size_t)cfg->nz * n1);
     std::vector<double> bgf((size_t)(cfg->nz + 1) * 4), dbgf(bgf.size());
+    std::vector<double> pbn((size_t)cfg->nz * n1 * 2), pbfc((size_t)(cfg->nz + 1) * 2);   // [pb | 1/rt]
     for (int ez = 0; ez < cfg->nz; ++ez)
         for (int b = 0; b < n1; ++b) {
             const double z = cfg->z0 + (ez + 0.5 * (1.0 + p->R.xi[b])) * p->dz;
@@ -899,10 +1041,14 @@ jfmg_status jfmg_create_problem(const jfmg_config* cfg, void* workspace, size_t 
             const int zi = ez * n1 + b;
             for (int c = 0; c < 4; ++c) { bgn[zi * 4 + c] = bp.U[c]; dbgn[zi * 4 + c] = bp.dU[c]; }
             thn[zi] = bp.theta;
+            pbn[zi] = bg_pressure(*cfg, bp.U[3]);
+            pbn[(size_t)cfg->nz * n1 + zi] = 1.0 / bp.U[3];
         }
     for (int f = 0; f <= cfg->nz; ++f) {
         const BgPoint bp = background_at(*cfg, cfg->z0 + f * p->dz);
         for (int c = 0; c < 4; ++c) { bgf[f * 4 + c] = bp.U[c]; dbgf[f * 4 + c] = bp.dU[c]; }
+        pbfc[f] = bg_pressure(*cfg, bp.U[3]);
+        pbfc[cfg->nz + 1 + f] = 1.0 / bp.U[3];
     }
     hipStream_t st = p->st;
     auto up = [&](void* dst, const void* src, size_t bytes) { return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st); };
@@ -914,35 +1060,45 @@ jfmg_status jfmg_create_problem(const jfmg_config* cfg, void* workspace, size_t 
     e = e ? e : up(p->th_node, thn.data(), thn.size() * 8);
     e = e ? e : up(p->bg_face, bgf.data(), bgf.size() * 8);
     e = e ? e : up(p->dbg_face, dbgf.data(), dbgf.size() * 8);
+    e = e ? e : up(p->pb_node, pbn.data(), pbn.size() * 8);
+    e = e ? e : up(p->pb_face, pbfc.data(), pbfc.size() * 8);
     for (int l = 0; l < p->nlev && !e; ++l) {
         Level& L = p->lev[l];
         std::vector<double> c4((size_t)L.nz * 4), f4((size_t)(L.nz + 1) * 4), df4(f4.size());
+        std::vector<double> pc2((size_t)L.nz * 2), pf2((size_t)(L.nz + 1) * 2);
         for (int J = 0; J < L.nz; ++J) {
             const BgPoint bp = background_at(*cfg, cfg->z0 + (J + 0.5) * L.hz);
             for (int c = 0; c < 4; ++c) c4[J * 4 + c] = bp.U[c];
+            pc2[2 * J] = bg_pressure(*cfg, bp.U[3]);
+            pc2[2 * J + 1] = 1.0 / bp.U[3];
         }
         for (int J = 0; J <= L.nz; ++J) {
             const BgPoint bp = background_at(*cfg, cfg->z0 + J * L.hz);
             for (int c = 0; c < 4; ++c) { f4[J * 4 + c] = bp.U[c]; df4[J * 4 + c] = bp.dU[c]; }
+            pf2[2 * J] = bg_pressure(*cfg, bp.U[3]);
+            pf2[2 * J + 1] = 1.0 / bp.U[3];
         }
-        if (p->prec == 64) {
-            keep_d.push_back(c4); keep_d.push_back(f4); keep_d.push_back(df4);
-            const size_t k0 = keep_d.size() - 3;
-            e = e ? e : up(L.bgc, keep_d[k0].data(), c4.size() * 8);
-            e = e ? e : up(L.bgf, keep_d[k0 + 1].data(), f4.size() * 8);
-            e = e ? e : up(L.dbgf, keep_d[k0 + 2].data(), df4.size() * 8);
-        } else {
-            keep_f.emplace_back(c4.begin(), c4.end());
-            keep_f.emplace_back(f4.begin(), f4.end());
-            keep_f.emplace_back(df4.begin(), df4.end());
-            const size_t k0 = keep_f.size() - 3;
-            e = e ? e : up(L.bgc, keep_f[k0].data(), c4.size() * 4);
-            e = e ? e : up(L.bgf, keep_f[k0 + 1].data(), f4.size() * 4);
-            e = e ? e : up(L.dbgf, keep_f[k0 + 2].data(), df4.size() * 4);
+        const std::vector<double>* src[5] = {&c4, &f4, &df4, &pc2, &pf2};
+        void* dst[5] = {L.bgc, L.bgf, L.dbgf, L.pc, L.pf};
+        for (int t = 0; t < 5 && !e; ++t) {
+            if (p->prec == 64) {
+                keep_d.push_back(*src[t]);
+                e = up(dst[t], keep_d.back().data(), keep_d.back().size() * 8);
+            } else {
+                keep_f.emplace_back(src[t]->begin(), src[t]->end());
+                e = up(dst[t], keep_f.back().data(), keep_f.back().size() * 4);
+            }
         }
     }
     e = e ? e : hipMemsetAsync(p->scal, 0, NSCAL * 8, st);
     e = e ? e : hipStreamSynchronize(st);
+    e = e ? e : hipStreamCreateWithFlags(&p->cs, hipStreamNonBlocking);
+    e = e ? e : hipHostMalloc((void**)&p->hpin, sizeof(double) * S_HB * cfg->gmres_m, hipHostMallocDefault);
+    for (int j = 0; j < cfg->gmres_m && !e; ++j) {
+        hipEvent_t ev = nullptr;
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (!e) p->hev.push_back(ev);
+    }
     if (e) {
         const std::string m2 = std::string("table upload: ") + hipGetErrorString(e);
         delete p;
@@ -952,9 +1108,11 @@ jfmg_status jfmg_create_problem(const jfmg_config* cfg, void* workspace, size_t 
     DgArgs& A = p->A;
     A.ne = p->ne; A.nx = cfg->nx; A.nz = cfg->nz; A.bc = cfg->bc; A.physics = cfg->physics;
     A.dx = p->dx; A.dz = p->dz; A.J = p->dx * p->dz / 4.0; A.g = cfg->g; A.mu = cfg->mu; A.c_ip = cfg->c_ip;
-    A.gas = Gas<double>{cfg->gamma, cfg->R, cfg->p0};
+    A.gas = make_gas<double>(*cfg);
     A.bg_node = p->bg_node; A.dbg_node = p->dbg_node; A.th_node = p->th_node;
     A.bg_face = p->bg_face; A.dbg_face = p->dbg_face;
+    A.pb_node = p->pb_node; A.irt_node = p->pb_node + (size_t)cfg->nz * p->n1;
+    A.pb_face = p->pb_face; A.irt_face = p->pb_face + (cfg->nz + 1);
     A.R = p->R;
     *out = p;
     return JFMG_OK;
@@ -963,8 +1121,13 @@ jfmg_status jfmg_create_problem(const jfmg_config* cfg, void* workspace, size_t 
 jfmg_status jfmg_destroy_problem(jfmg_problem* p)
 {
     if (p) {
+        if (p->cs) (void)hipStreamSynchronize(p->cs);
         prof_flush(p);
+        invalidate_graphs(p);
         for (hipEvent_t e : p->prof.pool) (void)hipEventDestroy(e);
+        if (p->cs) (void)hipStreamDestroy(p->cs);
+        for (hipEvent_t e : p->hev) (void)hipEventDestroy(e);
+        if (p->hpin) (void)hipHostFree(p->hpin);
     }
     delete p;
     return JFMG_OK;
@@ -1024,9 +1187,8 @@ jfmg_status jfmg_mg_apply(jfmg_problem* p, const double* r, double* z)
     return precond(p, r, z, S_TMP);
 }
 
-jfmg_status jfmg_implicit_step(jfmg_problem* p, double* U, jfmg_stats* stats)
+static jfmg_status implicit_step_body(jfmg_problem* p, double* U, jfmg_stats* stats)
 {
-    if (!p || !U) return fail(p, JFMG_EINVAL, "null argument");
     const auto t0 = std::chrono::steady_clock::now();
     jfmg_stats st;
     std::memset(&st, 0, sizeof(st));
@@ -1068,6 +1230,20 @@ jfmg_status jfmg_implicit_step(jfmg_problem* p, double* U, jfmg_stats* stats)
     for (int l = 0; l < MAXLEV && l < 8; ++l) st.fv_matvecs[l] = p->mv_count[l];
     st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (stats) *stats = st;
+    return s;
+}
+
+jfmg_status jfmg_implicit_step(jfmg_problem* p, double* U, jfmg_stats* stats)
+{
+    if (!p || !U) return fail(p, JFMG_EINVAL, "null argument");
+    // host-synchronous: order after the caller's stream, then work on the private
+    // stream (HIP graphs cannot be captured on the legacy default stream)
+    hipError_t e = hipStreamSynchronize(p->user_st);
+    if (e) return fail(p, JFMG_EDEVICE, hipGetErrorString(e));
+    p->st = p->cs;
+    jfmg_status s = implicit_step_body(p, U, stats);
+    (void)hipStreamSynchronize(p->cs);
+    p->st = p->user_st;
     return s;
 }
 

@@ -31,15 +31,18 @@ enum { FVM_LIN = 0, FVM_STAGE = 1, FVM_MATVEC = 2, FVM_DEFECT = 3 };
 //   STAGE   out = x0 + alpha_j dtau (b - g'x), g'x = x - adt/eps (f~(u + eps x) - F0)
 //   MATVEC  out = g'x
 //   DEFECT  out(coarse) = R(g'x - b), 2x2 agglomeration inside the tile
-template <typename T, int TX, int TZ, int MODE>
-__global__ void __launch_bounds__(TX * TZ)
+template <typename T, int TX, int TZ, int NTH, int MODE>
+__global__ void __launch_bounds__(NTH)
 fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, const T* __restrict__ xp,
                const T* __restrict__ x0, const T* __restrict__ b, T* __restrict__ out,
                const double* __restrict__ xpart, int xcount, double* __restrict__ slots, double alpha_j,
                double adt, double cfl, Red red)
 {
-    constexpr int NTH = TX * TZ, HX = TX + 2, HZ = TZ + 2;
+    constexpr int NCELL = TX * TZ, HX = TX + 2, HZ = TZ + 2;
+    constexpr int NH = HX * HZ, HITEMS = (NH + NTH - 1) / NTH;
     constexpr int NFX = TZ * (TX + 1), NFZ = (TZ + 1) * TX;
+    constexpr bool PERT = (MODE != FVM_LIN);
+    static_assert(NTH >= NCELL && NTH % 64 == 0, "tile shape");
     __shared__ T sw[4][HZ][HX];
     __shared__ T sFx[TZ][TX + 1][4];
     __shared__ T sFz[TZ + 1][TX][4];
@@ -47,36 +50,60 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
     const int I0 = blockIdx.x * TX, J0 = blockIdx.y * TZ;
     const long nc = A.nc;
     const int nxl = A.nxl, nzl = A.nzl;
+    // own cell (threads tid < NCELL)
+    const int ti = tid % TX, tj = tid / TX;
+    const int I = I0 + ti, J = J0 + tj;
+    const bool valid = tid < NCELL && I < nxl && J < nzl;
+    const long q = (long)J * nxl + I;
 
+    // ---- every global load first: own-cell operands, then the halo states ----
+    T own_x[4] = {T(0), T(0), T(0), T(0)}, own_f0[4] = {T(0), T(0), T(0), T(0)};
+    T own_b[4] = {T(0), T(0), T(0), T(0)}, own_x0[4] = {T(0), T(0), T(0), T(0)};
+    if (valid) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if constexpr (PERT) { own_x[c] = xp[c * nc + q]; own_f0[c] = F0[c * nc + q]; }
+            if constexpr (MODE == FVM_STAGE || MODE == FVM_DEFECT) own_b[c] = b[c * nc + q];
+            if constexpr (MODE == FVM_STAGE) own_x0[c] = x0 ? x0[c * nc + q] : T(0);
+        }
+    }
+    T hu[HITEMS][4], hx[HITEMS][4];
+#pragma unroll
+    for (int it = 0; it < HITEMS; ++it) {
+        const int h = tid + it * NTH;
+        int Ih = I0 - 1 + h % HX;
+        const int Jh = J0 - 1 + h / HX;
+        bool ok = h < NH && Jh >= 0 && Jh < nzl;
+        if (Ih < 0 || Ih >= nxl) {
+            if (A.bc == 1) Ih = (Ih + nxl) % nxl;
+            else ok = false;
+        }
+        const long qh = (long)Jh * nxl + Ih;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            hu[it][c] = ok ? u[c * nc + qh] : T(0);
+            if constexpr (PERT) hx[it][c] = ok ? xp[c * nc + qh] : T(0);
+        }
+    }
     T eps = T(0);
     bool xzero = false;   // uniform: g'x = 0 for x = 0
-    if constexpr (MODE != FVM_LIN) {
+    if constexpr (PERT) {
         const double xn2 = sum_partials<NTH>(xpart, xcount);   // ||x||^2, same order in every block
         if (!(xn2 > 0.0)) xzero = true;
         else eps = (T)(FdEps<T>::sqrt_eps * slots[LV_UTOT] / sqrt(xn2));
     }
 
     if (!xzero) {
-        // ---- states of the tile and its halo ----
-        for (int h = tid; h < HX * HZ; h += NTH) {
-            const int ii = h % HX, jj = h / HX;
-            int I = I0 - 1 + ii;
-            const int J = J0 - 1 + jj;
-            bool ok = (J >= 0 && J < nzl);
-            if (I < 0 || I >= nxl) {
-                if (A.bc == 1) I = (I + nxl) % nxl;
-                else ok = false;
-            }
-            const long q = (long)J * nxl + I;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                T v = T(0);
-                if (ok) {
-                    v = u[c * nc + q];
-                    if constexpr (MODE != FVM_LIN) v = v + eps * xp[c * nc + q];
+        for (int it = 0; it < HITEMS; ++it) {
+            const int h = tid + it * NTH;
+            if (h < NH)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    T v = hu[it][c];
+                    if constexpr (PERT) v = v + eps * hx[it][c];
+                    sw[c][h / HX][h % HX] = v;
                 }
-                sw[c][jj][ii] = v;
-            }
         }
         __syncthreads();
         // ---- one net flux per face ----
@@ -86,26 +113,29 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
             int r0, r1, sL, sR;   // LDS rows/cols of the two sides
             bool skip = false, wallL = false, wallR = false;
             const T* bg;
+            const T* pr;   // background pressure and 1/(rho theta) at the face
             const T* dbg = nullptr;
             T elen, hn;
             if (xface) {
                 const int jj = f / (TX + 1), fi = f - jj * (TX + 1);
-                const int J = J0 + jj, Ir = I0 + fi, Il = Ir - 1;
-                skip = (J >= nzl) || (Il >= nxl);
+                const int Jf = J0 + jj, Ir = I0 + fi, Il = Ir - 1;
+                skip = (Jf >= nzl) || (Il >= nxl);
                 wallL = (Ir == 0) && A.bc != 1;
                 wallR = (Il == nxl - 1) && A.bc != 1;
                 r0 = jj + 1; r1 = jj + 1; sL = fi; sR = fi + 1;
-                bg = A.bgc + 4 * (skip ? 0 : J);
+                bg = A.bgc + 4 * (skip ? 0 : Jf);
+                pr = A.pc + 2 * (skip ? 0 : Jf);
                 elen = A.hz; hn = A.hx;
             } else {
                 const int g = f - NFX;
                 const int fj = g / TX, ii = g - fj * TX;
-                const int I = I0 + ii, Ja = J0 + fj, Jb = Ja - 1;
-                skip = (I >= nxl) || (Jb >= nzl);
+                const int If = I0 + ii, Ja = J0 + fj, Jb = Ja - 1;
+                skip = (If >= nxl) || (Jb >= nzl);
                 wallL = (Jb < 0);
                 wallR = (Ja == nzl);
                 r0 = fj; r1 = fj + 1; sL = ii + 1; sR = ii + 1;
                 bg = A.bgf + 4 * (skip ? 0 : Ja);
+                pr = A.pf + 2 * (skip ? 0 : Ja);
                 dbg = A.dbgf + 4 * (skip ? 0 : Ja);
                 elen = A.hx; hn = A.hz;
             }
@@ -119,20 +149,24 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
                     UL[c] = wL[c] + bg[c];
                     UR[c] = wR[c] + bg[c];
                 }
+                const T pb = pr[0], irb = pr[1];
                 if (wallL) {            // only the cell on the + side is inside
                     T M[4] = {UR[0], UR[1], UR[2], UR[3]};
                     if (xface) M[1] = -M[1]; else M[2] = -M[2];
-                    hllc(A.gas, UR, M, -nx, -nz, H);
+                    const T pR = pert_pressure(A.gas, wR[3], irb, pb);
+                    hllc(A.gas, UR, M, pR, pR, -nx, -nz, H);
 #pragma unroll
                     for (int c = 0; c < 4; ++c) Phi[c] = -H[c];
                 } else if (wallR) {     // only the cell on the - side is inside
                     T M[4] = {UL[0], UL[1], UL[2], UL[3]};
                     if (xface) M[1] = -M[1]; else M[2] = -M[2];
-                    hllc(A.gas, UL, M, nx, nz, H);
+                    const T pL = pert_pressure(A.gas, wL[3], irb, pb);
+                    hllc(A.gas, UL, M, pL, pL, nx, nz, H);
 #pragma unroll
                     for (int c = 0; c < 4; ++c) Phi[c] = H[c];
                 } else {
-                    hllc(A.gas, UL, UR, nx, nz, H);
+                    const T pL = pert_pressure(A.gas, wL[3], irb, pb), pR = pert_pressure(A.gas, wR[3], irb, pb);
+                    hllc(A.gas, UL, UR, pL, pR, nx, nz, H);
 #pragma unroll
                     for (int c = 0; c < 4; ++c) Phi[c] = H[c];
                     if (A.physics == 1) {
@@ -142,11 +176,13 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
                             visc_flux(A.mu, UL, Z4, dbg, nx, nz, FL);
                             visc_flux(A.mu, UR, Z4, dbg, nx, nz, FR);
                         }
+                        const T irs = T(1) / (UL[0] + UR[0]);
+                        const T muh = A.mu / hn;
 #pragma unroll
                         for (int c = 1; c < 4; ++c) {
                             const T Dl0 = wL[0] - wR[0], Dlc = wL[c] - wR[c];
-                            const T r = T(0.5) * (UL[c] + UR[c]) / (T(0.5) * (UL[0] + UR[0]));
-                            const T pen = (T(1) / hn) * A.mu * (Dlc - r * Dl0);
+                            const T r = (UL[c] + UR[c]) * irs;
+                            const T pen = muh * (Dlc - r * Dl0);
                             Phi[c] -= T(0.5) * (FL[c] + FR[c]) - pen;
                         }
                     }
@@ -169,17 +205,14 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
     }
 
     // ---- per cell ----
-    const int ti = tid % TX, tj = tid / TX;
-    const int I = I0 + ti, J = J0 + tj;
-    const bool valid = (I < nxl) && (J < nzl);
-    const long q = (long)J * nxl + I;
     T f[4] = {T(0), T(0), T(0), T(0)};
     if (valid && !xzero) {
+        const T iarea = T(1) / A.area;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             T L = -(sFx[tj][ti + 1][c] - sFx[tj][ti][c]) - (sFz[tj + 1][ti][c] - sFz[tj][ti][c]);
             if (c == 2) L += A.area * (-A.g * sw[0][tj + 1][ti + 1]);
-            f[c] = L / A.area;
+            f[c] = L * iarea;
         }
     }
     if constexpr (MODE == FVM_LIN) {
@@ -197,7 +230,7 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
                                                     (double)A.gas.gamma);
             lam = sqrt(uu * uu + ww * ww) + sqrt((double)A.gas.gamma * p / rho);
         }
-        __shared__ double sh[(NTH + 63) / 64];
+        __shared__ double sh[NTH / 64];
         const double bs = block_sum<NTH>(ss, sh);
         const double bm = block_max<NTH>(lam, sh);
         if (tid == 0) {
@@ -211,7 +244,7 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
         if (valid && !xzero) {
             const T sc = (T)adt / eps;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) Ax[c] = xp[c * nc + q] - sc * (f[c] - F0[c * nc + q]);
+            for (int c = 0; c < 4; ++c) Ax[c] = own_x[c] - sc * (f[c] - own_f0[c]);
         }
         if constexpr (MODE == FVM_MATVEC) {
             if (valid)
@@ -223,7 +256,7 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
                 const T s = (T)(alpha_j * slots[LV_DTAU]);
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    const T v = (x0 ? x0[c * nc + q] : T(0)) + s * (b[c * nc + q] - Ax[c]);
+                    const T v = own_x0[c] + s * (own_b[c] - Ax[c]);
                     out[c * nc + q] = v;
                     nrm += (double)v * (double)v;
                 }
@@ -233,7 +266,7 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
             __syncthreads();
             if (valid)
 #pragma unroll
-                for (int c = 0; c < 4; ++c) sw[c][tj][ti] = Ax[c] - b[c * nc + q];
+                for (int c = 0; c < 4; ++c) sw[c][tj][ti] = Ax[c] - own_b[c];
             __syncthreads();
             if (valid && !(ti & 1) && !(tj & 1)) {
                 const int nxc = nxl / 2;
@@ -368,13 +401,13 @@ static int tile_launch(const FvArgs<T>& A, const T* u, const T* F0, const T* xp,
 {
     if (A.nxl >= 1024) {
         const dim3 g((unsigned)((A.nxl + 63) / 64), (unsigned)((A.nzl + 3) / 4));
-        fv_tile_kernel<T, 64, 4, MODE><<<g, dim3(256), 0, st>>>(A, u, F0, xp, x0, b, out, xpart, xcount, slots,
-                                                                alpha_j, adt, cfl, red);
+        timed_launch(fv_tile_kernel<T, 64, 4, 256, MODE>, g, dim3(256), st, A, u, F0, xp, x0, b, out, xpart, xcount, slots,
+                     alpha_j, adt, cfl, red);
         return (int)(g.x * g.y);
     }
     const dim3 g((unsigned)((A.nxl + 15) / 16), (unsigned)((A.nzl + 3) / 4));
-    fv_tile_kernel<T, 16, 4, MODE><<<g, dim3(64), 0, st>>>(A, u, F0, xp, x0, b, out, xpart, xcount, slots, alpha_j,
-                                                           adt, cfl, red);
+    timed_launch(fv_tile_kernel<T, 16, 4, 128, MODE>, g, dim3(128), st, A, u, F0, xp, x0, b, out, xpart, xcount, slots,
+                 alpha_j, adt, cfl, red);
     return (int)(g.x * g.y);
 }
 
@@ -395,7 +428,7 @@ int FvLaunch<T>::stage(const FvArgs<T>& A, const T* u, const T* F0, const T* xp,
     if (zero) {
         const long n = 4 * A.nc;
         const int nb = norm_blocks(n);
-        fv_stage_zero_kernel<T><<<dim3(nb), dim3(256), 0, st>>>(b, xo, n, slots, alpha_j, red);
+        timed_launch(fv_stage_zero_kernel<T>, dim3(nb), dim3(256), st, b, xo, n, slots, alpha_j, red);
         return nb;
     }
     return tile_launch<T, FVM_STAGE>(A, u, F0, xp, x0, b, xo, xpart, xcount, const_cast<double*>(slots), alpha_j,
@@ -415,7 +448,7 @@ void FvLaunch<T>::defect_restrict(const FvArgs<T>& A, const T* u, const T* F0, c
 {
     if (zero) {
         const dim3 g((unsigned)((A.nxl / 2 + 63) / 64), (unsigned)((A.nzl / 2 + 3) / 4));
-        fv_restrict_neg_kernel<T><<<g, dim3(256), 0, st>>>(A, b, rc);
+        timed_launch(fv_restrict_neg_kernel<T>, g, dim3(256), st, A, b, rc);
         return;
     }
     tile_launch<T, FVM_DEFECT>(A, u, F0, x, nullptr, b, rc, xpart, xcount, const_cast<double*>(slots), 0.0, adt, 0.0,
@@ -425,7 +458,7 @@ template <typename T>
 int FvLaunch<T>::prolong_correct(const FvArgs<T>& Af, T* x, const T* v, Red red, hipStream_t st)
 {
     const dim3 g = tile_grid(Af.nxl, Af.nzl);
-    fv_prolong_correct_kernel<T><<<g, dim3(FV_NTH), 0, st>>>(Af, x, v, red);
+    timed_launch(fv_prolong_correct_kernel<T>, g, dim3(FV_NTH), st, Af, x, v, red);
     return (int)(g.x * g.y);
 }
 template <typename T>

@@ -15,8 +15,12 @@ template <typename T> struct FdEps;
 template <> struct FdEps<double> { static constexpr double sqrt_eps = 1.4901161193847656e-08; };
 template <> struct FdEps<float> { static constexpr double sqrt_eps = 3.4526698300124393e-04; };
 
+// Gas constants plus the binomial coefficients C(gamma, k) used to evaluate
+// the equation of state around the background pressure (see pert_pressure).
+constexpr int GAS_NCOEF = 14;
 template <typename T> struct Gas {
     T gamma, R, p0;
+    T cg[GAS_NCOEF];   // C(gamma, k), k = 0 .. GAS_NCOEF-1
 };
 
 template <typename T> __device__ __forceinline__ T dpow(T a, T b)
@@ -29,20 +33,39 @@ template <typename T> __device__ __forceinline__ T dsqrt(T a)
     if constexpr (std::is_same_v<T, float>) return sqrtf(a);
     else return sqrt(a);
 }
-
-// Equation of state of the potential-temperature form: p = p0 (R rho theta / p0)^gamma
-template <typename T> __device__ __forceinline__ T pressure(const Gas<T>& G, T rt)
+template <typename T> __device__ __forceinline__ T dabs(T a)
 {
-    return G.p0 * dpow<T>(G.R * rt / G.p0, G.gamma);
+    if constexpr (std::is_same_v<T, float>) return fabsf(a);
+    else return fabs(a);
 }
 
-// Convective flux F_c(U) . n for an axis-aligned unit normal (nx, nz).
-template <typename T>
-__device__ __forceinline__ void conv_flux(const Gas<T>& G, const T* U, T nx, T nz, T* F)
+// Equation of state of the potential-temperature form, p = p0 (R rho theta / p0)^gamma,
+// evaluated at the total state rho theta = rtb (1 + s), s = (rho theta)' / rtb, as
+// p = pb (1 + s)^gamma with the background pressure pb = p0 (R rtb / p0)^gamma.
+// (1 + s)^gamma is the binomial series in Horner form for |s| <= 1/20 (truncation
+// below the unit roundoff: 14 terms in FP64, 7 in FP32) and pow otherwise; s = 0
+// returns pb exactly, so background and perturbed evaluations agree bitwise.
+template <typename T> __device__ __forceinline__ T pert_pressure(const Gas<T>& G, T rt1, T irtb, T pb)
 {
-    T u = U[1] / U[0], w = U[2] / U[0];
-    T p = pressure(G, U[3]);
-    T q = u * nx + w * nz;
+    const T s = rt1 * irtb;
+    T f;
+    if (dabs<T>(s) <= T(0.05)) {
+        constexpr int n = std::is_same_v<T, float> ? 7 : GAS_NCOEF;
+        f = G.cg[n - 1];
+#pragma unroll
+        for (int k = n - 2; k >= 0; --k) f = f * s + G.cg[k];
+    } else {
+        f = dpow<T>(T(1) + s, G.gamma);
+    }
+    return pb * f;
+}
+
+// Convective flux F_c(U) . n for an axis-aligned unit normal (nx, nz), pressure p given.
+template <typename T>
+__device__ __forceinline__ void conv_flux(const T* U, T p, T nx, T nz, T* F)
+{
+    const T ir = T(1) / U[0];
+    const T q = (U[1] * nx + U[2] * nz) * ir;
     F[0] = U[1] * nx + U[2] * nz;
     F[1] = U[1] * q + p * nx;
     F[2] = U[2] * q + p * nz;
@@ -52,14 +75,14 @@ __device__ __forceinline__ void conv_flux(const Gas<T>& G, const T* U, T nx, T n
 // HLLC flux (Toro) with Davis wave speeds S_L = min(q_L - c_L, q_R - c_R),
 // S_R = max(q_L + c_L, q_R + c_R); star flux in the S*-factored form
 // (S*(S_K U_K - F_K) + S_K p*_K D*) / (S_K - S*), p*_K = p_K + rho_K (S_K - q_K)(S* - q_K).
+// Pressures of both states are given.
 template <typename T>
-__device__ __forceinline__ void hllc(const Gas<T>& G, const T* UL, const T* UR, T nx, T nz, T* F)
+__device__ __forceinline__ void hllc(const Gas<T>& G, const T* UL, const T* UR, T pL, T pR, T nx, T nz, T* F)
 {
     const T rL = UL[0], rR = UR[0];
-    const T uL = UL[1] / rL, wL = UL[2] / rL, uR = UR[1] / rR, wR = UR[2] / rR;
-    const T pL = pressure(G, UL[3]), pR = pressure(G, UR[3]);
-    const T qL = uL * nx + wL * nz, qR = uR * nx + wR * nz;
-    const T cL = dsqrt<T>(G.gamma * pL / rL), cR = dsqrt<T>(G.gamma * pR / rR);
+    const T irL = T(1) / rL, irR = T(1) / rR;
+    const T qL = (UL[1] * nx + UL[2] * nz) * irL, qR = (UR[1] * nx + UR[2] * nz) * irR;
+    const T cL = dsqrt<T>(G.gamma * pL * irL), cR = dsqrt<T>(G.gamma * pR * irR);
     const T SL = fmin(qL - cL, qR - cR);
     const T SR = fmax(qL + cL, qR + cR);
     if (SL >= T(0)) {
@@ -86,11 +109,11 @@ __device__ __forceinline__ void hllc(const Gas<T>& G, const T* UL, const T* UR, 
     const T FK2 = UK[2] * qK + pK * nz;
     const T FK3 = UK[3] * qK;
     const T pst = pK + rK * (SK - qK) * (Ss - qK);
-    const T den = SK - Ss;
-    F[0] = (Ss * (SK * UK[0] - FK0)) / den;
-    F[1] = (Ss * (SK * UK[1] - FK1) + SK * pst * nx) / den;
-    F[2] = (Ss * (SK * UK[2] - FK2) + SK * pst * nz) / den;
-    F[3] = (Ss * (SK * UK[3] - FK3)) / den;
+    const T iden = T(1) / (SK - Ss);
+    F[0] = (Ss * (SK * UK[0] - FK0)) * iden;
+    F[1] = (Ss * (SK * UK[1] - FK1) + SK * pst * nx) * iden;
+    F[2] = (Ss * (SK * UK[2] - FK2) + SK * pst * nz) * iden;
+    F[3] = (Ss * (SK * UK[3] - FK3)) * iden;
 }
 
 // Viscous flux F_v(U, G) . n = mu rho grad(U_c / rho) . n written with the
@@ -99,9 +122,10 @@ template <typename T>
 __device__ __forceinline__ void visc_flux(T mu, const T* U, const T* Gx, const T* Gz, T nx, T nz, T* F)
 {
     F[0] = T(0);
+    const T ir = T(1) / U[0];
 #pragma unroll
     for (int c = 1; c < 4; ++c) {
-        T r = U[c] / U[0];
+        T r = U[c] * ir;
         F[c] = mu * ((Gx[c] - r * Gx[0]) * nx + (Gz[c] - r * Gz[0]) * nz);
     }
 }

@@ -1,6 +1,7 @@
 // Internal interface between the host driver and the kernel launchers.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -8,6 +9,27 @@
 #include "jfmg_dev.h"
 
 namespace jfmg {
+
+// Kernel timing by the dispatch packet itself (start/stop events of
+// hipExtLaunchKernel): when `start` is set, the next launch that goes through
+// timed_launch() records into these events and marks them used.  Event pairs
+// around a launch would include host gaps when the GPU waits for the host.
+struct LaunchTimer {
+    hipEvent_t start = nullptr, stop = nullptr;
+    bool used = false;
+};
+extern thread_local LaunchTimer g_launch_timer;
+
+template <typename K, typename... Args>
+inline void timed_launch(K kernel, dim3 grid, dim3 block, hipStream_t st, Args... args)
+{
+    if (g_launch_timer.start && !g_launch_timer.used) {
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, st, g_launch_timer.start, g_launch_timer.stop, 0, args...);
+        g_launch_timer.used = true;
+    } else {
+        kernel<<<grid, block, 0, st>>>(args...);
+    }
+}
 
 constexpr int MAXN1 = 4;      // k + 1 <= 4
 constexpr int MAXLEV = 8;
@@ -29,6 +51,10 @@ struct DgArgs {
     const double* th_node;   // [nz*(k+1)]    background theta
     const double* bg_face;   // [nz+1][4]     background at element z-faces
     const double* dbg_face;  // [nz+1][4]
+    const double* pb_node;   // [nz*(k+1)]    background pressure and 1/(rho theta) at node rows
+    const double* irt_node;
+    const double* pb_face;   // [nz+1]        the same at element z-faces
+    const double* irt_face;
     RefTab R;
 };
 
@@ -41,6 +67,8 @@ template <typename T> struct FvArgs {
     const T* bgc;    // [nzl][4]   background at cell-centre z
     const T* bgf;    // [nzl+1][4] background at z-faces
     const T* dbgf;   // [nzl+1][4] d/dz background at z-faces
+    const T* pc;     // [nzl][2]   background pressure, 1/(rho theta) at cell-centre z
+    const T* pf;     // [nzl+1][2] the same at z-faces
 };
 
 // device scalar slots of one FV level (doubles)
@@ -105,6 +133,8 @@ void launch_scale(double* out, const double* in, long n, const double* nrm2, hip
 // out = base + sum_i y[i] Z_i   (base may alias out)
 void launch_lincomb(double* out, const double* base, const double* Z, long ld, int nv, long n, const double* y,
                     hipStream_t st);
+// zero `bytes` (a multiple of 4) with a kernel (graph-capture safe, unlike a memset node)
+void launch_zero(void* ptr, size_t bytes, hipStream_t st);
 // out = a*x + b*y
 void launch_axpby(double* out, double a, const double* x, double b, const double* y, long n, hipStream_t st);
 

@@ -90,10 +90,10 @@ multidot_kernel(const double* __restrict__ w, const double* __restrict__ V, long
 void launch_multidot(const double* w, const double* V, long ld, int nv, long n, Red red, hipStream_t st)
 {
     const dim3 g(la_blocks(n)), b(LA_NTH);
-    if (nv <= 8) multidot_kernel<8><<<g, b, 0, st>>>(w, V, ld, nv, n, red);
-    else if (nv <= 16) multidot_kernel<16><<<g, b, 0, st>>>(w, V, ld, nv, n, red);
-    else if (nv <= 32) multidot_kernel<32><<<g, b, 0, st>>>(w, V, ld, nv, n, red);
-    else multidot_kernel<65><<<g, b, 0, st>>>(w, V, ld, nv, n, red);
+    if (nv <= 8) timed_launch(multidot_kernel<8>, g, b, st, w, V, ld, nv, n, red);
+    else if (nv <= 16) timed_launch(multidot_kernel<16>, g, b, st, w, V, ld, nv, n, red);
+    else if (nv <= 32) timed_launch(multidot_kernel<32>, g, b, st, w, V, ld, nv, n, red);
+    else timed_launch(multidot_kernel<65>, g, b, st, w, V, ld, nv, n, red);
     launch_finalize(red.partials, (int)g.x, nv, red.out, st);
 }
 
@@ -131,7 +131,7 @@ update_kernel(double* __restrict__ w, const double* __restrict__ V, long ld, int
 
 void launch_update(double* w, const double* V, long ld, int nv, long n, const double* h, Red red, hipStream_t st)
 {
-    update_kernel<<<dim3(la_blocks(n)), dim3(LA_NTH), 0, st>>>(w, V, ld, nv, n, h, red);
+    timed_launch(update_kernel, dim3(la_blocks(n)), dim3(LA_NTH), st, w, V, ld, nv, n, h, red);
     if (red.out) launch_finalize(red.partials, la_blocks(n), 1, red.out, st);
 }
 
@@ -192,6 +192,18 @@ void launch_axpby(double* out, double a, const double* x, double b, const double
 {
     long blk = (n + 255) / 256;
     axpby_kernel<<<dim3((unsigned)(blk < 4096 ? blk : 4096)), dim3(256), 0, st>>>(out, a, x, b, y, n);
+}
+
+__global__ void __launch_bounds__(256) zero_kernel(unsigned* __restrict__ x, long n)
+{
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) x[i] = 0u;
+}
+
+void launch_zero(void* ptr, size_t bytes, hipStream_t st)
+{
+    const long n = (long)(bytes / 4);
+    long blk = (n + 255) / 256;
+    zero_kernel<<<dim3((unsigned)(blk < 4096 ? blk : 4096)), dim3(256), 0, st>>>((unsigned*)ptr, n);
 }
 
 }  // namespace jfmg

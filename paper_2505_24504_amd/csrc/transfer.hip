@@ -161,18 +161,19 @@ int transfer_grid(int k, long ne)
 template <typename T>
 void launch_transfer_T(int k, const DgArgs& A, int mass_fix, const double* U, T* u, int nxf, hipStream_t st)
 {
-    if (k == 1) transfer_T_kernel<2, T><<<dim3((unsigned)((A.ne + TrShape<2>::EPB - 1) / TrShape<2>::EPB)), dim3(TrShape<2>::NTH), 0, st>>>(A, mass_fix, U, u, nxf);
-    else if (k == 2) transfer_T_kernel<3, T><<<dim3((unsigned)((A.ne + TrShape<3>::EPB - 1) / TrShape<3>::EPB)), dim3(TrShape<3>::NTH), 0, st>>>(A, mass_fix, U, u, nxf);
-    else transfer_T_kernel<4, T><<<dim3((unsigned)((A.ne + TrShape<4>::EPB - 1) / TrShape<4>::EPB)), dim3(TrShape<4>::NTH), 0, st>>>(A, mass_fix, U, u, nxf);
+    const dim3 g(transfer_grid(k, A.ne));
+    if (k == 1) timed_launch(transfer_T_kernel<2, T>, g, dim3(TrShape<2>::NTH), st, A, mass_fix, U, u, nxf);
+    else if (k == 2) timed_launch(transfer_T_kernel<3, T>, g, dim3(TrShape<3>::NTH), st, A, mass_fix, U, u, nxf);
+    else timed_launch(transfer_T_kernel<4, T>, g, dim3(TrShape<4>::NTH), st, A, mass_fix, U, u, nxf);
 }
 
 template <typename T>
 void launch_transfer_Tinv(int k, const DgArgs& A, int mass_fix, const T* u, double* U, int nxf, Red red, hipStream_t st)
 {
     const dim3 g(transfer_grid(k, A.ne));
-    if (k == 1) transfer_Tinv_kernel<2, T><<<g, dim3(TrShape<2>::NTH), 0, st>>>(A, mass_fix, u, U, nxf, red);
-    else if (k == 2) transfer_Tinv_kernel<3, T><<<g, dim3(TrShape<3>::NTH), 0, st>>>(A, mass_fix, u, U, nxf, red);
-    else transfer_Tinv_kernel<4, T><<<g, dim3(TrShape<4>::NTH), 0, st>>>(A, mass_fix, u, U, nxf, red);
+    if (k == 1) timed_launch(transfer_Tinv_kernel<2, T>, g, dim3(TrShape<2>::NTH), st, A, mass_fix, u, U, nxf, red);
+    else if (k == 2) timed_launch(transfer_Tinv_kernel<3, T>, g, dim3(TrShape<3>::NTH), st, A, mass_fix, u, U, nxf, red);
+    else timed_launch(transfer_Tinv_kernel<4, T>, g, dim3(TrShape<4>::NTH), st, A, mass_fix, u, U, nxf, red);
     if (red.out) launch_finalize(red.partials, (int)g.x, 1, red.out, st);
 }
 
