@@ -67,6 +67,25 @@ def run_form(d, pert, steps, warmup, profile_classes):
     return p, el, lat, its, prof
 
 
+def stream_copy(nbytes, reps=20):
+    """STREAM-style device copy of nbytes (read + write counted): GB/s."""
+    import torch
+    n = nbytes // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del x, y
+    return 2.0 * n * 8 / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline():
     """The oracle timed on the host: first SDIRK2 step of the density current on a
     48 x 12 quad grid of the same domain (k = 3, same physics and solver settings)."""
@@ -153,6 +172,11 @@ def main():
                      "timing": "HIP start/stop events of each dispatch of the kernel class, second timed pass "
                                f"of the same {a.steps} steps without graph replay ({1e3 * el_prof / a.steps:.1f} ms/step)"},
     }
+    # copy bandwidth of the device: HBM-resident (1 GiB) and cache-resident (32 MiB)
+    hbm_copy, mall_copy = stream_copy(1 << 30), stream_copy(32 << 20)
+    out["stream_copy"] = {"hbm_1GiB_GBs": hbm_copy, "mall_32MiB_GBs": mall_copy,
+                          "roofline_frac_vs_hbm_copy": achieved / hbm_copy if achieved else None,
+                          "roofline_frac_vs_mall_copy": achieved / mall_copy if achieved else None}
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -23,16 +23,19 @@ def hipcc():
     return os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 
-def build(verbose: bool = False, jobs: int = 5) -> str:
-    """Compile every HIP source to an object, then link the shared library."""
-    objdir = os.path.join(HERE, "_build")
+def build(verbose: bool = False, jobs: int = 5, out: str = LIB, defines: tuple = ()) -> str:
+    """Compile every HIP source to an object, then link the shared library.
+
+    `defines` (e.g. ("FV_COARSE_NTH=192",)) override the tile constants of the
+    kernels; `out` names the library file (objects go to a folder beside it)."""
+    objdir = os.path.join(HERE, "_build") if out == LIB else out + ".objs"
     os.makedirs(objdir, exist_ok=True)
     procs = []
     objs = []
     for src in SOURCES:
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
         objs.append(obj)
-        cmd = [hipcc(), "-c", "-x", "hip", os.path.join(CSRC, src), "-o", obj] + FLAGS
+        cmd = [hipcc(), "-c", "-x", "hip", os.path.join(CSRC, src), "-o", obj] + FLAGS + ["-D" + d for d in defines]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
@@ -40,13 +43,13 @@ def build(verbose: bool = False, jobs: int = 5) -> str:
             _wait(procs.pop(0))
     while procs:
         _wait(procs.pop(0))
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     cmd = [hipcc(), "-shared", "--offload-arch=gfx950", "-fPIC", "-o", tmp] + objs
-    out = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
-    if out.returncode:
-        raise RuntimeError("link failed:\n" + out.stdout.decode())
-    os.replace(tmp, LIB)
-    return LIB
+    res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
+    if res.returncode:
+        raise RuntimeError("link failed:\n" + res.stdout.decode())
+    os.replace(tmp, out)
+    return out
 
 
 def _wait(item):

@@ -52,7 +52,7 @@ dg_kernel(DgArgs A, const double* __restrict__ U, const double* __restrict__ Y, 
     const int t = threadIdx.x;
     const int le = t / NP, nd = t - le * NP;
     const bool act = le < EPB;
-    const long e = (long)blockIdx.x * EPB + le;
+    const long e = (long)xcd_tile(blockIdx.x, gridDim.x) * EPB + le;   // XCD-contiguous element ranges
     const bool valid = act && e < A.ne;
     const int ez = valid ? (int)(e / A.nx) : 0;
     const int ex = valid ? (int)(e - (long)ez * A.nx) : 0;

@@ -453,12 +453,12 @@ size_t layout(const jfmg_config& c, char* base, F&& bind)
     const int m = c.gmres_m;
     const long la = (N + 1023) / 1024;
     long nfv = (long)n1 * c.nx * n1 * c.nz;
-    long fvblk = ((n1 * c.nx + 15) / 16) * ((n1 * c.nz + 3) / 4);   // the smallest FV tile is 16 x 4
+    const long fvblk = fv_partial_blocks((long)n1 * c.nx, (long)n1 * c.nz);   // blocks of the finest FV level
     const long dgblk = ne;   // at most one block per element
     size_t npart = (size_t)std::max<long>({la * (m + 2), 2 * fvblk, dgblk, 2048, 4096});
     bind("scal", cv.take(NSCAL * 8), 0);
     bind("partials", cv.take(npart * 8), npart);
-    const size_t fvp = (size_t)std::max<long>(fvblk, 1024);
+    const size_t fvp = (size_t)fvblk;
     bind("fvpart", cv.take(fvp * 3 * c.mg_levels * 8), fvp);
     bind("bg_node", cv.take((size_t)c.nz * n1 * 4 * 8), 0);
     bind("dbg_node", cv.take((size_t)c.nz * n1 * 4 * 8), 0);

@@ -31,8 +31,8 @@ enum { FVM_LIN = 0, FVM_STAGE = 1, FVM_MATVEC = 2, FVM_DEFECT = 3 };
 //   STAGE   out = x0 + alpha_j dtau (b - g'x), g'x = x - adt/eps (f~(u + eps x) - F0)
 //   MATVEC  out = g'x
 //   DEFECT  out(coarse) = R(g'x - b), 2x2 agglomeration inside the tile
-template <typename T, int TX, int TZ, int NTH, int MODE>
-__global__ void __launch_bounds__(NTH)
+template <typename T, int TX, int TZ, int NTH, int WPE, int MODE>
+__global__ void __launch_bounds__(NTH, WPE)
 fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, const T* __restrict__ xp,
                const T* __restrict__ x0, const T* __restrict__ b, T* __restrict__ out,
                const double* __restrict__ xpart, int xcount, double* __restrict__ slots, double alpha_j,
@@ -47,7 +47,8 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
     __shared__ T sFx[TZ][TX + 1][4];
     __shared__ T sFz[TZ + 1][TX][4];
     const int tid = threadIdx.x;
-    const int I0 = blockIdx.x * TX, J0 = blockIdx.y * TZ;
+    const unsigned tile = xcd_tile(block_linear(), gridDim.x * gridDim.y);
+    const int I0 = (int)(tile % gridDim.x) * TX, J0 = (int)(tile / gridDim.x) * TZ;
     const long nc = A.nc;
     const int nxl = A.nxl, nzl = A.nzl;
     // own cell (threads tid < NCELL)
@@ -394,21 +395,49 @@ static inline dim3 tile_grid(int nx, int nz)
     return dim3((unsigned)((nx + FV_TX - 1) / FV_TX), (unsigned)((nz + FV_TZ - 1) / FV_TZ));
 }
 
+// Tile shapes: levels at least FV_WIDE_MIN cells wide use the wide tile (one
+// wave per row of 64 cells, at most 168 VGPRs so that three waves fit per SIMD);
+// narrower levels are latency bound and use a small tile with more threads than
+// cells, so that every face of the tile gets its own thread.  Measured on the
+// density-current levels (1024x256 ... 128x32 cells) against 8x4, 32x8 and
+// 128/192-thread variants.
+#ifndef FV_WIDE_MIN
+#define FV_WIDE_MIN 1024
+#endif
+#ifndef FV_WIDE_TX
+#define FV_WIDE_TX 64
+#define FV_WIDE_TZ 4
+#define FV_WIDE_NTH 256
+#define FV_WIDE_WPE 3
+#endif
+#ifndef FV_SMALL_TX
+#define FV_SMALL_TX 16
+#define FV_SMALL_TZ 4
+#define FV_SMALL_NTH 256
+#define FV_SMALL_WPE 1
+#endif
+
+template <typename T, int TX, int TZ, int NTH, int WPE, int MODE>
+static int tile_launch_shape(const FvArgs<T>& A, const T* u, const T* F0, const T* xp, const T* x0, const T* b,
+                             T* out, const double* xpart, int xcount, double* slots, double alpha_j, double adt,
+                             double cfl, Red red, hipStream_t st)
+{
+    const dim3 g((unsigned)((A.nxl + TX - 1) / TX), (unsigned)((A.nzl + TZ - 1) / TZ));
+    timed_launch(fv_tile_kernel<T, TX, TZ, NTH, WPE, MODE>, g, dim3(NTH), st, A, u, F0, xp, x0, b, out, xpart,
+                 xcount, slots, alpha_j, adt, cfl, red);
+    return (int)(g.x * g.y);
+}
+
 template <typename T, int MODE>
 static int tile_launch(const FvArgs<T>& A, const T* u, const T* F0, const T* xp, const T* x0, const T* b, T* out,
                        const double* xpart, int xcount, double* slots, double alpha_j, double adt, double cfl,
                        Red red, hipStream_t st)
 {
-    if (A.nxl >= 1024) {
-        const dim3 g((unsigned)((A.nxl + 63) / 64), (unsigned)((A.nzl + 3) / 4));
-        timed_launch(fv_tile_kernel<T, 64, 4, 256, MODE>, g, dim3(256), st, A, u, F0, xp, x0, b, out, xpart, xcount, slots,
-                     alpha_j, adt, cfl, red);
-        return (int)(g.x * g.y);
-    }
-    const dim3 g((unsigned)((A.nxl + 15) / 16), (unsigned)((A.nzl + 3) / 4));
-    timed_launch(fv_tile_kernel<T, 16, 4, 128, MODE>, g, dim3(128), st, A, u, F0, xp, x0, b, out, xpart, xcount, slots,
-                 alpha_j, adt, cfl, red);
-    return (int)(g.x * g.y);
+    if (A.nxl >= FV_WIDE_MIN)
+        return tile_launch_shape<T, FV_WIDE_TX, FV_WIDE_TZ, FV_WIDE_NTH, FV_WIDE_WPE, MODE>(
+            A, u, F0, xp, x0, b, out, xpart, xcount, slots, alpha_j, adt, cfl, red, st);
+    return tile_launch_shape<T, FV_SMALL_TX, FV_SMALL_TZ, FV_SMALL_NTH, FV_SMALL_WPE, MODE>(
+        A, u, F0, xp, x0, b, out, xpart, xcount, slots, alpha_j, adt, cfl, red, st);
 }
 
 template <typename T>
@@ -477,9 +506,12 @@ void FvLaunch<T>::norm2(const T* x, long n, Red red, hipStream_t st)
     fv_norm2_kernel<T><<<dim3(norm_blocks(n)), dim3(256), 0, st>>>(x, n, red);
     if (red.out) launch_finalize(red.partials, norm_blocks(n), 1, red.out, st);
 }
-template <typename T> int FvLaunch<T>::grid_blocks(const FvArgs<T>& A)
+long fv_partial_blocks(long nxl, long nzl)
 {
-    return ((A.nxl + 15) / 16) * ((A.nzl + 3) / 4);
+    const long wide = ((nxl + FV_WIDE_TX - 1) / FV_WIDE_TX) * ((nzl + FV_WIDE_TZ - 1) / FV_WIDE_TZ);
+    const long small = ((nxl + FV_SMALL_TX - 1) / FV_SMALL_TX) * ((nzl + FV_SMALL_TZ - 1) / FV_SMALL_TZ);
+    const long pro = ((nxl + FV_TX - 1) / FV_TX) * ((nzl + FV_TZ - 1) / FV_TZ);
+    return std::max(std::max(wide, small), std::max(pro, 1024L));
 }
 template <typename T> int FvLaunch<T>::norm_blocks(long n)
 {

@@ -184,6 +184,17 @@ struct Red {
 
 __device__ __forceinline__ unsigned block_linear() { return blockIdx.y * gridDim.x + blockIdx.x; }
 
+// The dispatcher hands work-groups to the 8 XCDs of the chip round-robin by
+// linear id, and each XCD has its own L2.  Stencil kernels therefore renumber
+// their tiles so that XCD x works on one contiguous range of tiles (rows of
+// neighbouring tiles share halo cache lines inside one L2).  Bijective on [0, nb).
+constexpr unsigned NUM_XCD = 8;
+__device__ __forceinline__ unsigned xcd_tile(unsigned w, unsigned nb)
+{
+    const unsigned x = w % NUM_XCD, i = w / NUM_XCD, q = nb / NUM_XCD, r = nb % NUM_XCD;
+    return x * q + (x < r ? x : r) + i;
+}
+
 template <int NTH> __device__ __forceinline__ void put_partial(const Red& r, double v)
 {
     __shared__ double sh[NTH / 64];

@@ -99,6 +99,9 @@ void launch_transfer_Tinv(int k, const DgArgs& A, int mass_fix, const T* u, doub
 void launch_subgrid_map(int k, const DgArgs& A, int nxf, int* out, hipStream_t st);
 
 // ---- FV kernels (fv.hip) ----
+// FV partial-sum blocks needed by the largest launch on a level of nxl x nzl cells
+long fv_partial_blocks(long nxl, long nzl);
+
 template <typename T> struct FvLaunch {
     // F0 = f~(u), then the level slots (||u + Ubar||, max |v| + c, dtau) via red.partials
     static void lin_level(const FvArgs<T>& A, const T* u, T* F0, Red red, double* slots, double adt, double cfl,
@@ -117,7 +120,6 @@ template <typename T> struct FvLaunch {
     static void restrict_(const FvArgs<T>& Af, const T* f, T* c, hipStream_t st);
     static void prolong(const FvArgs<T>& Af, const T* c, T* f, hipStream_t st);
     static void norm2(const T* x, long n, Red red, hipStream_t st);
-    static int grid_blocks(const FvArgs<T>& A);
     static int norm_blocks(long n);
 };
 

@@ -14,21 +14,20 @@ int la_blocks(long n)
     return (int)((n + (long)LA_NTH * LA_EL - 1) / ((long)LA_NTH * LA_EL));
 }
 
-// out[q] = sum_b p[q * nb + b], one block, fixed order
-__global__ void __launch_bounds__(256) finalize_kernel(const double* __restrict__ p, int nb, int nq, double* __restrict__ out)
+// out[q] = sum_b p[q * nb + b], one block per q, fixed order
+__global__ void __launch_bounds__(256) finalize_kernel(const double* __restrict__ p, int nb, double* __restrict__ out)
 {
     __shared__ double sh[4];
-    for (int q = 0; q < nq; ++q) {
-        double a = 0.0;
-        for (int i = threadIdx.x; i < nb; i += 256) a += p[(long)q * nb + i];
-        a = block_sum<256>(a, sh);
-        if (threadIdx.x == 0) out[q] = a;
-    }
+    const int q = blockIdx.x;
+    double a = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 256) a += p[(long)q * nb + i];
+    a = block_sum<256>(a, sh);
+    if (threadIdx.x == 0) out[q] = a;
 }
 
 void launch_finalize(const double* partials, int nb, int nq, double* out, hipStream_t st)
 {
-    finalize_kernel<<<dim3(1), dim3(256), 0, st>>>(partials, nb, nq, out);
+    finalize_kernel<<<dim3(nq), dim3(256), 0, st>>>(partials, nb, out);
 }
 
 __global__ void __launch_bounds__(256) norm2_kernel(const double* __restrict__ x, long n, Red red)
