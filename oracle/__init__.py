@@ -37,7 +37,7 @@ class OrcCfg(C.Structure):
         "x0", "x1", "z0", "z1", "g", "gamma", "R", "p0", "theta0", "N", "u_mean",
         "mu", "c_ip")] + [("rk_alpha", C.c_double * 4)] + [(n, C.c_double) for n in (
         "pseudo_cfl", "newton_rtol", "ew_gamma", "ew_alpha", "ew_eta0", "ew_eta_max",
-        "dt")]
+        "dt", "newton_stall")]
 
 
 class OrcPert(C.Structure):
@@ -48,13 +48,13 @@ class OrcPert(C.Structure):
 class OrcStats(C.Structure):
     _fields_ = [("newton_its", C.c_int), ("gmres_its", C.c_int), ("lh_evals", C.c_int),
                 ("jvps", C.c_int), ("fv_matvecs", C.c_int * 8), ("status", C.c_int),
-                ("pad", C.c_int), ("g0_norm", C.c_double), ("g_norm", C.c_double)]
+                ("stalls", C.c_int), ("g0_norm", C.c_double), ("g_norm", C.c_double)]
 
     def as_dict(self):
         return {"newton_its": self.newton_its, "gmres_its": self.gmres_its,
                 "lh_evals": self.lh_evals, "jvps": self.jvps,
                 "fv_matvecs": list(self.fv_matvecs), "status": self.status,
-                "g0_norm": self.g0_norm, "g_norm": self.g_norm}
+                "stalls": self.stalls, "g0_norm": self.g0_norm, "g_norm": self.g_norm}
 
 
 _OP = C.CFUNCTYPE(None, C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double))
@@ -154,7 +154,7 @@ def make_cfg(d: dict) -> OrcCfg:
                           ("theta0", 300.0), ("N", 0.0), ("u_mean", 0.0), ("mu", 0.0),
                           ("c_ip", 2.0), ("pseudo_cfl", 1.0), ("newton_rtol", 1e-8),
                           ("ew_gamma", 0.1), ("ew_alpha", 1.0), ("ew_eta0", 0.1),
-                          ("ew_eta_max", 0.9), ("dt", 1.0)):
+                          ("ew_eta_max", 0.9), ("dt", 1.0), ("newton_stall", 0.0)):
         setattr(c, name, float(d.get(name, default)))
     s = c.rk_stages
     alpha = d.get("rk_alpha") or [1.0 / (s - j) for j in range(s)]

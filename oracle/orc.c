@@ -1124,6 +1124,15 @@ int orc_newton_stage(orc_ctx* X, const double* Ubar, double alpha_dt, double* U,
         if (st) st->g_norm = gk;
         if (!isfinite(gk)) { status = ORC_ENONFINITE; goto done; }
         if (gk < c->newton_rtol * g0) { status = ORC_OK; goto done; }
+        /* rounding floor: the step no longer halves ||G|| although ||G|| is
+           already below newton_stall ||G^0|| (G = U - adt f(U) - Ubar cannot be
+           evaluated more accurately than its rounding; the relative tolerance
+           may lie below that floor for weak perturbations on fine grids) */
+        if (c->newton_stall > 0.0 && gk <= c->newton_stall * g0 && gk > 0.5 * gprev) {
+            if (st) st->stalls++;
+            status = ORC_OK;
+            goto done;
+        }
     }
 done:
     free(G);

@@ -40,6 +40,7 @@ typedef struct {
     double pseudo_cfl;
     double newton_rtol, ew_gamma, ew_alpha, ew_eta0, ew_eta_max;
     double dt;
+    double newton_stall; /* > 0: also stop at the rounding floor of G (see orc_newton_stage) */
 } orc_cfg;
 
 typedef struct {
@@ -52,7 +53,7 @@ typedef struct {
     int newton_its, gmres_its, lh_evals, jvps;
     int fv_matvecs[8];
     int status;
-    int pad;
+    int stalls;         /* stages stopped at the rounding floor of G */
     double g0_norm, g_norm;
 } orc_stats;
 

@@ -341,6 +341,26 @@ def test_newton_converges_superlinearly(orc):
     assert ratios[2] < ratios[0]
 
 
+def test_newton_stall_stop_at_rounding_floor(orc):
+    """G cannot be evaluated below its rounding, so a relative tolerance under
+    that floor is unreachable: with the plain test Newton runs into its cap.
+    With newton_stall the stage ends at the floor, i.e. at the first step that
+    does not halve ||G|| once ||G|| <= newton_stall ||G^0||.  Where the
+    tolerance is reachable the rule never fires and changes nothing."""
+    d, pert, _ = W.bubble_small()
+    base = dict(d, newton_rtol=1e-15, newton_maxit=12)
+    U0 = orc.Oracle(base).initial_state(pert)
+    rc, _, st = orc.Oracle(base).implicit_step(U0)
+    assert rc == 3 and st["newton_its"] == 12 and st["stalls"] == 0
+    rc2, U2, st2 = orc.Oracle(dict(base, newton_stall=1e-6)).implicit_step(U0)
+    assert rc2 == 0 and st2["stalls"] == 1 and st2["newton_its"] < 12
+    assert 1e-15 * st2["g0_norm"] < st2["g_norm"] <= 1e-6 * st2["g0_norm"]
+    rc3, U3, st3 = orc.Oracle(dict(d, newton_stall=1e-6)).implicit_step(U0)
+    rc4, U4, st4 = orc.Oracle(d).implicit_step(U0)
+    assert rc3 == rc4 == 0 and st3["stalls"] == 0
+    assert np.array_equal(U3, U4)
+
+
 def test_stage_residual_converged(orc):
     d, pert, _ = W.bubble_small()
     o = orc.Oracle(d)
