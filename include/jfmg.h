@@ -67,6 +67,9 @@ typedef struct {
     double ew_gamma, ew_alpha, ew_eta0, ew_eta_max; /* Eisenstat-Walker choice 2        */
     double rk_alpha[4];       /* smoother coefficients; 0 entries: 1/(s-j+1)            */
     double pseudo_cfl;        /* c* in the pseudo time step                             */
+    double newton_stall;      /* > 0: a stage also ends, successfully, once ||G|| <=
+                                 newton_stall ||G^0|| and a Newton step no longer halves
+                                 ||G|| (the rounding floor of G lies above rtol); 0: off */
 } jfmg_config;
 
 typedef struct {
@@ -79,6 +82,7 @@ typedef struct {
     int newton_its, gmres_its, lh_evals, jvps;
     int fv_matvecs[8];        /* FV operator evaluations per level (finest first)      */
     int host_syncs, status;
+    int stall_stops, pad;     /* stages ended at the rounding floor (newton_stall)     */
     double g0_norm, g_norm;   /* ||G(U^0)||, ||G|| at exit of the last stage          */
     double seconds;           /* host wall time of the call                           */
 } jfmg_stats;
@@ -191,6 +195,60 @@ typedef enum {
 jfmg_status jfmg_profile_enable(jfmg_problem* p, unsigned class_mask);
 /* ms, launches and bytes are host arrays of JFMG_K_NCLASS entries. */
 jfmg_status jfmg_profile_read(jfmg_problem* p, double* ms, long long* launches, double* bytes);
+
+/* ---- ensembles and served requests: many independent problems, one arena ----
+   A batch advances independent members (an ensemble of perturbed forecasts, or
+   requests of a solver service) concurrently.  Each member is an ordinary
+   problem whose workspace is a first-fit, 256-byte aligned range of the
+   caller's device arena, taken at admission and returned at retirement
+   (admission fails with ENOMEM when no range is large enough: the arena is the
+   HBM budget).  A pool of host worker threads advances the members one
+   implicit step at a time, each step on the member's private stream, so the
+   small kernels of different members overlap on the GPU.  A member's state U
+   is a caller-owned device vector updated in place after every step.  Members
+   share no device memory and every kernel reduces in a fixed order, so a
+   member's result is bitwise the same alone and in any mix.  The batch
+   functions are called from one host thread. */
+typedef struct jfmg_batch jfmg_batch;
+/* arena: device memory of arena_bytes (256-byte aligned), owned by the caller
+   and unused by it while the batch exists; max_members slots; workers host
+   threads (0: min(max_members, 8)); hip_stream: the stream member creation and
+   jfmg_initial_state on members use, and that run/start order after. */
+jfmg_status jfmg_batch_create(size_t arena_bytes, void* arena, int max_members, int workers, void* hip_stream,
+                              jfmg_batch** out);
+/* Stops the workers after their current steps and destroys every member. */
+jfmg_status jfmg_batch_destroy(jfmg_batch* b);
+/* Admit a member that will take n_steps implicit steps of U (device, caller
+   owned, N = 4 nx nz (k+1)^2 doubles).  With pert non-NULL, U is first set to
+   that initial state (as jfmg_initial_state, on the batch stream); else U must
+   hold the state.  ENOMEM: no free slot or arena range; EINVAL: invalid
+   configuration.  In background mode the member starts at once. */
+jfmg_status jfmg_batch_admit(jfmg_batch* b, const jfmg_config* cfg, const jfmg_perturbation* pert, double* U,
+                             int n_steps, int* slot);
+/* The member's problem, e.g. for jfmg_initial_state on U; only while the
+   member is not being advanced (before run/start, or once finished). */
+jfmg_problem* jfmg_batch_member(jfmg_batch* b, int slot);
+/* Advance every unfinished member by up to max_steps steps (all remaining if
+   max_steps <= 0) and return when they are done.  ESTATE in background mode. */
+jfmg_status jfmg_batch_run(jfmg_batch* b, int max_steps);
+/* Background mode: the workers keep advancing every member, including members
+   admitted later, until it has taken all its steps; jfmg_batch_stop ends it
+   (after the steps in flight). */
+jfmg_status jfmg_batch_start(jfmg_batch* b);
+jfmg_status jfmg_batch_stop(jfmg_batch* b);
+/* Wait up to timeout_s seconds (forever if < 0) for a member to finish; *slot
+   is the finished member, each reported once, or -1 on timeout or when no
+   member is active. */
+jfmg_status jfmg_batch_wait_any(jfmg_batch* b, double timeout_s, int* slot);
+/* finished = 1 once every step is done or a step failed; steps_done; stats
+   summed over the member's steps (status: the first failure).  Returns the
+   member's status. */
+jfmg_status jfmg_batch_poll(jfmg_batch* b, int slot, int* finished, int* steps_done, jfmg_stats* stats);
+/* Destroy a member that is not being advanced and return its arena range. */
+jfmg_status jfmg_batch_retire(jfmg_batch* b, int slot);
+/* Largest free arena range in bytes. */
+size_t jfmg_batch_arena_free(jfmg_batch* b);
+const char* jfmg_batch_last_error(const jfmg_batch* b);
 
 /* Message of the last failed call on p (or of the last failed creation if p is NULL). */
 const char* jfmg_last_error(const jfmg_problem* p);

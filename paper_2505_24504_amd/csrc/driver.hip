@@ -424,6 +424,7 @@ jfmg_status validate(const jfmg_config& c, Key& key, std::string& msg)
     if (c.mg_levels < 1 || c.mg_levels > MAXLEV) { msg = "mg_levels must be in 1..8"; return JFMG_EINVAL; }
     if (c.mg_precision != 32 && c.mg_precision != 64) { msg = "mg_precision must be 32 or 64"; return JFMG_EINVAL; }
     if (c.newton_maxit < 1 || c.gmres_max_restarts < 0) { msg = "bad iteration caps"; return JFMG_EINVAL; }
+    if (!(c.newton_stall >= 0.0 && c.newton_stall < 1.0)) { msg = "newton_stall must be in [0, 1)"; return JFMG_EINVAL; }
     if (!(c.dt > 0) || !(c.gamma > 1) || !(c.R > 0) || !(c.p0 > 0) || !(c.theta0 > 0) || c.mu < 0) {
         msg = "bad physical constants"; return JFMG_EINVAL;
     }
@@ -909,6 +910,11 @@ jfmg_status newton_stage(jfmg_problem* p, const double* Ubar, double adt, jfmg_s
         if (st) st->g_norm = gk;
         if (!std::isfinite(gk)) return fail(p, JFMG_ENONFINITE, "non-finite stage residual");
         if (gk < c.newton_rtol * g0) return JFMG_OK;
+        // rounding floor of G: no halving any more although already below newton_stall ||G^0||
+        if (c.newton_stall > 0.0 && gk <= c.newton_stall * g0 && gk > 0.5 * gprev) {
+            if (st) st->stall_stops++;
+            return JFMG_OK;
+        }
     }
     return fail(p, JFMG_ENOCONV, "Newton did not converge within newton_maxit");
 }

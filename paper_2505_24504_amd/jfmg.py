@@ -32,7 +32,7 @@ class Config(C.Structure):
         "precond")] + [("mg_key", C.c_char * 16)] + [(n, C.c_double) for n in (
         "x0", "x1", "z0", "z1", "g", "gamma", "R", "p0", "theta0", "N", "u_mean", "mu", "c_ip", "dt",
         "newton_rtol", "ew_gamma", "ew_alpha", "ew_eta0", "ew_eta_max")] + [
-        ("rk_alpha", C.c_double * 4), ("pseudo_cfl", C.c_double)]
+        ("rk_alpha", C.c_double * 4), ("pseudo_cfl", C.c_double), ("newton_stall", C.c_double)]
 
 
 class Perturbation(C.Structure):
@@ -43,12 +43,14 @@ class Perturbation(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("newton_its", C.c_int), ("gmres_its", C.c_int), ("lh_evals", C.c_int), ("jvps", C.c_int),
                 ("fv_matvecs", C.c_int * 8), ("host_syncs", C.c_int), ("status", C.c_int),
+                ("stall_stops", C.c_int), ("pad", C.c_int),
                 ("g0_norm", C.c_double), ("g_norm", C.c_double), ("seconds", C.c_double)]
 
     def as_dict(self):
         return {"newton_its": self.newton_its, "gmres_its": self.gmres_its, "lh_evals": self.lh_evals,
                 "jvps": self.jvps, "fv_matvecs": list(self.fv_matvecs), "host_syncs": self.host_syncs,
-                "status": self.status, "g0_norm": self.g0_norm, "g_norm": self.g_norm,
+                "status": self.status, "stall_stops": self.stall_stops, "g0_norm": self.g0_norm,
+                "g_norm": self.g_norm,
                 "seconds": self.seconds}
 
 
@@ -60,6 +62,9 @@ EXPORTS = [
     "jfmg_linearize", "jfmg_jvp", "jfmg_mg_apply", "jfmg_implicit_step", "jfmg_transfer",
     "jfmg_restrict", "jfmg_prolong", "jfmg_fv_level_state", "jfmg_fv_dtau", "jfmg_fv_matvec",
     "jfmg_mg_fv", "jfmg_subgrid_map", "jfmg_profile_enable", "jfmg_profile_read", "jfmg_last_error",
+    "jfmg_batch_create", "jfmg_batch_destroy", "jfmg_batch_admit", "jfmg_batch_member", "jfmg_batch_run",
+    "jfmg_batch_start", "jfmg_batch_stop", "jfmg_batch_wait_any", "jfmg_batch_poll", "jfmg_batch_retire",
+    "jfmg_batch_arena_free", "jfmg_batch_last_error",
 ]
 
 KERNEL_CLASSES = ["dg_residual", "dg_jvp", "fv_stage", "fv_stage_zero", "fv_defect_restrict",
@@ -101,6 +106,18 @@ def load_library(path: str = LIB_PATH):
         "jfmg_profile_enable": (C.c_int, [vp, C.c_uint]),
         "jfmg_profile_read": (C.c_int, [vp, dp, C.POINTER(C.c_longlong), dp]),
         "jfmg_last_error": (C.c_char_p, [vp]),
+        "jfmg_batch_create": (C.c_int, [C.c_size_t, vp, C.c_int, C.c_int, vp, C.POINTER(vp)]),
+        "jfmg_batch_destroy": (C.c_int, [vp]),
+        "jfmg_batch_admit": (C.c_int, [vp, C.POINTER(Config), C.POINTER(Perturbation), vp, C.c_int, ip]),
+        "jfmg_batch_member": (vp, [vp, C.c_int]),
+        "jfmg_batch_run": (C.c_int, [vp, C.c_int]),
+        "jfmg_batch_start": (C.c_int, [vp]),
+        "jfmg_batch_stop": (C.c_int, [vp]),
+        "jfmg_batch_wait_any": (C.c_int, [vp, C.c_double, ip]),
+        "jfmg_batch_poll": (C.c_int, [vp, C.c_int, ip, ip, C.POINTER(Stats)]),
+        "jfmg_batch_retire": (C.c_int, [vp, C.c_int]),
+        "jfmg_batch_arena_free": (C.c_size_t, [vp]),
+        "jfmg_batch_last_error": (C.c_char_p, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -119,7 +136,7 @@ def make_config(d: dict) -> Config:
             "gmres_max_restarts", "fd_eps_mode", "mg_levels", "rk_stages", "mass_fix", "mg_precision",
             "precond")
     dbls = ("x0", "x1", "z0", "z1", "g", "gamma", "R", "p0", "theta0", "N", "u_mean", "mu", "c_ip", "dt",
-            "newton_rtol", "ew_gamma", "ew_alpha", "ew_eta0", "ew_eta_max", "pseudo_cfl")
+            "newton_rtol", "ew_gamma", "ew_alpha", "ew_eta0", "ew_eta_max", "pseudo_cfl", "newton_stall")
     for n in ints:
         if n in d:
             setattr(c, n, int(d[n]))
@@ -198,10 +215,7 @@ class Problem:
 
     # ---- entry points ----
     def initial_state(self, pert: dict):
-        P = Perturbation()
-        P.shape = int(pert.get("shape", 0))
-        for n in ("amp", "xc", "zc", "xr", "zr", "a", "Z"):
-            setattr(P, n, float(pert.get(n, 1.0)))
+        P = _perturbation(pert)
         U = self.dg_zeros()
         self._check(self.L.jfmg_initial_state(self.h, C.byref(P), _ptr(U)))
         return U
@@ -297,3 +311,95 @@ class Problem:
         out = torch.zeros(self.fv_size(0) // 4, dtype=torch.int32, device=self.device)
         self._check(self.L.jfmg_subgrid_map(self.h, _ptr(out)))
         return out
+
+
+def num_dofs(d: dict) -> int:
+    """N = 4 nx nz (k+1)^2 of a problem description."""
+    return 4 * int(d["nx"]) * int(d["nz"]) * (int(d["k"]) + 1) ** 2
+
+
+def _perturbation(pert: dict) -> Perturbation:
+    P = Perturbation()
+    P.shape = int(pert.get("shape", 0))
+    for n in ("amp", "xc", "zc", "xr", "zr", "a", "Z"):
+        setattr(P, n, float(pert.get(n, 1.0)))
+    return P
+
+
+class Batch:
+    """Independent members advanced concurrently from one device arena
+    (jfmg_batch_*).  The arena (a torch uint8 tensor of arena_bytes) is the HBM
+    budget of the batch; each member's state is a torch FP64 tensor."""
+
+    def __init__(self, arena_bytes: int, max_members: int, workers: int = 0, device="cuda", stream=None):
+        self.L = load_library()
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.arena = torch.empty(int(arena_bytes) + 256, dtype=torch.uint8, device=self.device)
+        base = self.arena.data_ptr()
+        off = (-base) % 256
+        h = C.c_void_p()
+        rc = self.L.jfmg_batch_create(int(arena_bytes), C.c_void_p(base + off), int(max_members), int(workers),
+                                      C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if rc:
+            raise JfmgError(rc, "jfmg_batch_create failed")
+        self.h = h
+        self.U = {}
+
+    def _check(self, rc):
+        if rc:
+            raise JfmgError(rc, self.L.jfmg_batch_last_error(self.h).decode())
+
+    def admit(self, d: dict, n_steps: int, pert: dict = None, U=None):
+        """Admit a member; returns its slot, or None when the arena or the slots are full.
+        With pert, U is set to that initial state (on the batch stream)."""
+        if U is None:
+            U = torch.zeros(num_dofs(d), dtype=torch.float64, device=self.device)
+        cfg = make_config(d)
+        slot = C.c_int(-1)
+        P = C.byref(_perturbation(pert)) if pert is not None else None
+        rc = self.L.jfmg_batch_admit(self.h, C.byref(cfg), P, _ptr(U), int(n_steps), C.byref(slot))
+        if rc == ENOMEM:
+            return None
+        self._check(rc)
+        self.U[slot.value] = U
+        return slot.value
+
+    def run(self, max_steps: int = 0):
+        self._check(self.L.jfmg_batch_run(self.h, int(max_steps)))
+
+    def start(self):
+        self._check(self.L.jfmg_batch_start(self.h))
+
+    def stop(self):
+        self._check(self.L.jfmg_batch_stop(self.h))
+
+    def wait_any(self, timeout_s: float = -1.0):
+        """Slot of a member that finished (each reported once), or None."""
+        s = C.c_int(-1)
+        self._check(self.L.jfmg_batch_wait_any(self.h, float(timeout_s), C.byref(s)))
+        return s.value if s.value >= 0 else None
+
+    def poll(self, slot: int):
+        fin, steps, st = C.c_int(), C.c_int(), Stats()
+        rc = self.L.jfmg_batch_poll(self.h, int(slot), C.byref(fin), C.byref(steps), C.byref(st))
+        d = st.as_dict()
+        d["status"] = rc
+        return bool(fin.value), steps.value, d
+
+    def retire(self, slot: int):
+        """Destroy the member and return its state tensor."""
+        self._check(self.L.jfmg_batch_retire(self.h, int(slot)))
+        return self.U.pop(slot)
+
+    def arena_free(self) -> int:
+        return self.L.jfmg_batch_arena_free(self.h)
+
+    def close(self):
+        h = getattr(self, "h", None)
+        if h:
+            self.L.jfmg_batch_destroy(h)
+            self.h = None
+
+    def __del__(self):
+        self.close()

@@ -46,16 +46,17 @@ def test_struct_layout_matches_header(tmp_path):
 #include <stddef.h>
 #include "jfmg.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(jfmg_config), offsetof(jfmg_config, mg_key),
-         offsetof(jfmg_config, x0), offsetof(jfmg_config, rk_alpha), sizeof(jfmg_perturbation),
-         sizeof(jfmg_stats));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(jfmg_config), offsetof(jfmg_config, mg_key),
+         offsetof(jfmg_config, x0), offsetof(jfmg_config, rk_alpha), offsetof(jfmg_config, newton_stall),
+         sizeof(jfmg_perturbation), sizeof(jfmg_stats), offsetof(jfmg_stats, g0_norm));
   return 0; }
 ''')
     exe = tmp_path / "lay"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     vals = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     assert vals == [C.sizeof(jfmg.Config), jfmg.Config.mg_key.offset, jfmg.Config.x0.offset,
-                    jfmg.Config.rk_alpha.offset, C.sizeof(jfmg.Perturbation), C.sizeof(jfmg.Stats)]
+                    jfmg.Config.rk_alpha.offset, jfmg.Config.newton_stall.offset, C.sizeof(jfmg.Perturbation),
+                    C.sizeof(jfmg.Stats), jfmg.Stats.g0_norm.offset]
 
 
 def test_workspace_sizes(lib):

@@ -1,0 +1,113 @@
+"""Batched and served forms on the GPU.
+
+* a batch member gives bitwise the result of the same problem run alone, for
+  synchronous quanta and in the background (served) mode;
+* arena admission: ENOMEM when the budget is used up, the range comes back on
+  retirement;
+* steps with the FP32 multigrid agree with the FP64 oracle to what the Newton
+  tolerance fixes (only the preconditioner differs).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_common import DEV, node_total_norm, to_np
+from paper_2505_24504_amd import jfmg, serve, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GB = 2 ** 30
+
+
+def _alone(d, pert, steps):
+    p = jfmg.Problem(d, device=DEV)
+    U = p.initial_state(pert)
+    for _ in range(steps):
+        p.implicit_step(U)
+    torch.cuda.synchronize()
+    return U
+
+
+def test_batch_members_match_alone():
+    members = [(d, pert, 2) for d, pert, _ in W.ensemble(seed=4, members=5)]
+    members.append((dict(members[0][0], mg_precision=64), members[0][1], 2))
+    b = jfmg.Batch(2 * GB, max_members=8, workers=4, device=DEV)
+    slots = [b.admit(d, n, pert) for d, pert, n in members]
+    assert None not in slots
+    b.run()
+    for s, (d, pert, n) in zip(slots, members):
+        fin, steps, st = b.poll(s)
+        assert fin and steps == n and st["status"] == 0
+        U = b.retire(s)
+        Ua = _alone(d, pert, n)
+        print(f"member {d['nx']}x{d['nz']} fp{d['mg_precision']}: gmres {st['gmres_its']}")
+        assert torch.equal(U, Ua)
+    b.close()
+
+
+def test_batch_quantum_and_arena_budget():
+    d, pert, _ = W.ensemble(seed=4, members=1)[0]
+    need = jfmg.workspace_bytes(d)
+    b = jfmg.Batch(need + 4096, max_members=4, workers=2, device=DEV)
+    s0 = b.admit(d, 3, pert)
+    assert s0 is not None
+    assert b.admit(d, 3, pert) is None          # the arena holds one member
+    b.run(max_steps=1)
+    fin, steps, _ = b.poll(s0)
+    assert not fin and steps == 1
+    b.run()
+    fin, steps, st = b.poll(s0)
+    assert fin and steps == 3 and st["status"] == 0
+    U = b.retire(s0)
+    assert torch.equal(U, _alone(d, pert, 3))
+    s1 = b.admit(d, 1, pert)                     # the range came back
+    assert s1 is not None
+    b.close()
+
+
+def test_served_same_result_alone_and_in_mix():
+    reqs = [r for r in W.serving_requests(seed=5, n_requests=60) if r["cfg"]["nx"] <= 64][:14]
+    for r in reqs:
+        r["steps"] = min(r["steps"], 3)
+    arena = 3 * GB
+    b = jfmg.Batch(arena, max_members=8, workers=6, device=DEV)
+    recs = serve.serve(reqs, b, jfmg.workspace_bytes, arena, keep_state=True)
+    b.close()
+    assert all(r["status"] == "ok" for r in recs)
+    s = serve.summary(recs)
+    print(f"served {s['completed']} requests, p50 {s['p50_ms']:.1f} ms p99 {s['p99_ms']:.1f} ms")
+    for r, q in list(zip(recs, reqs))[::4]:
+        assert torch.equal(r["U"], _alone(q["cfg"], q["pert"], q["steps"])), r["id"]
+
+
+def _fp32_vs_oracle(d, pert, rtol_factor=20.0):
+    d32 = dict(d, mg_precision=32)
+    o = oracle.Oracle(dict(d, mg_precision=64))
+    U0 = o.initial_state(pert)
+    rc, Uo, st_o = o.implicit_step(U0)
+    assert rc == 0
+    p = jfmg.Problem(d32, device=DEV)
+    U = torch.from_numpy(U0).to(DEV)
+    st = p.implicit_step(U)
+    Ug = to_np(U)
+    ut, _ = node_total_norm(o, d, Uo)
+    diff, upd = np.linalg.norm(Ug - Uo), np.linalg.norm(Uo - U0)
+    n = Uo.size // 4
+    comp = [np.linalg.norm((Ug - Uo)[c * n:(c + 1) * n]) / max(np.linalg.norm((Uo - U0)[c * n:(c + 1) * n]), 1e-300)
+            for c in range(4)]
+    print(f"fp32 mg: gpu {st['newton_its']}/{st['gmres_its']} oracle fp64 {st_o['newton_its']}/{st_o['gmres_its']} "
+          f"rel(update) {diff / upd:.3e} per component {['%.2e' % x for x in comp]} rel(U+Ubar) {diff / ut:.3e}")
+    assert diff <= rtol_factor * d["newton_rtol"] * upd
+
+
+def test_fp32_mg_step_vs_fp64_oracle_bubble():
+    d, pert, _ = W.ensemble(seed=4, members=1)[0]
+    _fp32_vs_oracle(dict(d, nx=32, nz=16), pert)
+
+
+def test_fp32_mg_step_vs_fp64_oracle_inertia_gravity():
+    d, pert, _ = W.inertia_gravity(mg_precision=32)
+    d = dict(d, nx=60, nz=4, x1=30000.0)
+    pert = dict(pert, xc=15000.0)
+    _fp32_vs_oracle(d, pert)

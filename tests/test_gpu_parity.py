@@ -327,6 +327,20 @@ def test_sdirk2_step_parity(physics):
     _step_check(d, Uo, U0, to_np(U), rtol, st, st_o)
 
 
+def test_newton_stall_stop():
+    """Tolerance below the rounding floor of G: both sides end the stage at the floor."""
+    d, pert, _ = W.bubble_small()
+    d = dict(d, newton_rtol=1e-15, newton_stall=1e-6, newton_maxit=12)
+    p, o = pair(d)
+    U0 = o.initial_state(pert)
+    rc, Uo, st_o = o.implicit_step(U0)
+    assert rc == 0 and st_o["stalls"] == 1
+    U = to_dev(U0)
+    st = p.implicit_step(U)
+    assert st["stall_stops"] == 1
+    _step_check(d, Uo, U0, to_np(U), 1e-9, st, st_o)
+
+
 def test_step_determinism_and_mass():
     d, pert, _ = W.bubble_small()
     d = dict(d, k=2, mg_levels=3, scheme=1)
