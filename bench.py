@@ -23,6 +23,31 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the FV smoother-stage kernel class, from two
+# rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE) over
+#   bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-fp32 --no-forms --profile-class fv_stage
+# averaged over its launches on all four levels, each counter scaled by what it
+# reads for the 1 GiB device copy of that same run (FETCH_SIZE x2, WRITE_SIZE x1).
+# It describes the kernel sources hashed below and is reported as null once
+# they change.
+TRAFFIC = {"class": "fv_stage", "bytes_per_launch": 1.7944e7,
+           "sources": ["paper_2505_24504_amd/csrc/fv.hip", "paper_2505_24504_amd/csrc/jfmg_dev.h",
+                       "paper_2505_24504_amd/csrc/jfmg_internal.h"],
+           "sha256": "80d2f85a23a71b0150e4a725e3603d4da98b0169e6fb0bdc21c136ff43f2adf4",
+           "profile": "profiles/traffic_fv_stage_density_current_fp64.md"}
+
+
+def measured_traffic(cls):
+    """Counter-measured HBM bytes per launch of `cls`, if taken on the current kernel sources."""
+    import hashlib
+    if cls != TRAFFIC["class"]:
+        return None
+    h = hashlib.sha256()
+    for s in TRAFFIC["sources"]:
+        with open(os.path.join(ROOT, s), "rb") as fh:
+            h.update(fh.read())
+    return TRAFFIC["bytes_per_launch"] if h.hexdigest() == TRAFFIC["sha256"] else None
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -31,6 +56,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the ensemble, serving and inertia-gravity forms")
+    ap.add_argument("--serve-requests", type=int, default=32)
     ap.add_argument("--profile-class", default="auto",
                     help="kernel class timed with HIP events ('auto': largest total time)")
     return ap.parse_args()
@@ -84,6 +112,123 @@ def stream_copy(nbytes, reps=20):
     ms = e0.elapsed_time(e1) / reps
     del x, y
     return 2.0 * n * 8 / (ms * 1e-3) / 1e9
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def ensemble_forms():
+    """64-member ensemble (k = 2 warm bubbles on 32x16 / 64x32 / 96x48, 5 SDIRK2
+    steps each): batched FP32 multigrid (one arena, concurrent members) against
+    the members run one after another with the plain FP64 multigrid."""
+    from paper_2505_24504_amd import jfmg, workloads as W
+    mem = W.ensemble(seed=4, members=64)
+    work = sum(jfmg.num_dofs(d) * n for d, _, n in mem)
+    b = jfmg.Batch(48 << 30, max_members=len(mem), workers=8, device="cuda:0")
+    slots = [b.admit(d, n, pert) for d, pert, n in mem]
+    _sync()
+    t0 = time.perf_counter()
+    b.run()
+    el_b = time.perf_counter() - t0
+    polled = [b.poll(s) for s in slots]
+    b.close()
+    ok_b = sum(1 for f, _, st in polled if f and st["status"] == 0)
+    its_b = sum(st["gmres_its"] for _, _, st in polled)
+    stalls_b = sum(st["stall_stops"] for _, _, st in polled)
+    el_s, its_s, ok_s, stalls_s = 0.0, 0, 0, 0
+    for d, pert, n in mem:
+        p = jfmg.Problem(dict(d, mg_precision=64), device="cuda:0")
+        U = p.initial_state(pert)
+        _sync()
+        t0 = time.perf_counter()
+        good = True
+        for _ in range(n):
+            st = p.implicit_step(U, raise_on_error=False)
+            its_s += st["gmres_its"]
+            stalls_s += st["stall_stops"]
+            good = good and st["status"] == 0
+        _sync()
+        el_s += time.perf_counter() - t0
+        ok_s += good
+        del p
+    return {"ensemble_batched_fp32": {"value": work / el_b, "seconds": el_b, "members_ok": ok_b,
+                                      "gmres_its": its_b, "stall_stops": stalls_b},
+            "ensemble_serial_fp64": {"value": work / el_s, "seconds": el_s, "members_ok": ok_s,
+                                     "gmres_its": its_s, "stall_stops": stalls_s},
+            "ensemble_workload": "64 warm bubbles, k=2, grids 32x16/64x32/96x48, 5 SDIRK2 steps each, "
+                                 f"{work} DOF-Newton-steps"}
+
+
+def serving_forms(n_requests):
+    """The first n_requests of the Poisson request stream (200/s; grid, k, physics,
+    steps drawn per request) served with continuous batching from a 64 GB arena
+    (FP32 multigrid), against a one-at-a-time FIFO server running each request
+    with the plain FP64 multigrid (its latencies from the measured service times)."""
+    from paper_2505_24504_amd import jfmg, serve, workloads as W
+    reqs = W.serving_requests(seed=5, n_requests=n_requests)
+    arena = 64 << 30
+    b = jfmg.Batch(arena, max_members=64, workers=8, device="cuda:0")
+    recs = serve.serve(reqs, b, jfmg.workspace_bytes, arena)
+    b.close()
+    s = serve.summary(recs)
+    svc, ok = [], 0
+    for r in reqs:
+        _sync()
+        t0 = time.perf_counter()
+        p = jfmg.Problem(dict(r["cfg"], mg_precision=64), device="cuda:0")
+        U = p.initial_state(r["pert"])
+        good = True
+        for _ in range(r["steps"]):
+            good = good and p.implicit_step(U, raise_on_error=False)["status"] == 0
+        _sync()
+        svc.append(time.perf_counter() - t0)
+        ok += good
+        del p
+    lat = serve.serial_fifo(reqs, svc)
+    work = sum(jfmg.num_dofs(r["cfg"]) * r["steps"] for r in reqs)
+    return {"served_fp32": s,
+            "serial_fp64": {"value": work / sum(svc), "seconds": sum(svc), "completed": ok,
+                            "p50_ms": 1e3 * percentile(lat, 50), "p99_ms": 1e3 * percentile(lat, 99)},
+            "serving_workload": f"first {n_requests} requests of the seed-5 stream (Poisson 200/s), "
+                                "grids 16x8..256x128, k 1..3, Euler or viscous, 1..10 SDIRK2 steps, "
+                                f"{work} DOF-Newton-steps"}
+
+
+def inertia_gravity_forms(steps=3):
+    """Inertia-gravity wave (600x20, k=3, periodic, N = 0.01, 20 m/s wind, dt = 12 s):
+    FP32 multigrid against FP64 multigrid, and how far the two solutions are apart."""
+    import numpy as np
+    from paper_2505_24504_amd import jfmg, workloads as W
+    out, Us = {}, {}
+    for prec in (64, 32):
+        d, pert, _ = W.inertia_gravity(mg_precision=prec)
+        p = jfmg.Problem(d, device="cuda:0")
+        U = p.initial_state(pert)
+        U0 = U.clone()
+        p.implicit_step(U)          # warm-up step (graph capture), from the same start
+        U.copy_(U0)
+        _sync()
+        t0 = time.perf_counter()
+        its = [p.implicit_step(U, raise_on_error=False) for _ in range(steps)]
+        _sync()
+        el = time.perf_counter() - t0
+        n = jfmg.num_dofs(d)
+        out[f"fp{prec}_mg"] = {"value": steps * n / el, "ms_per_step": 1e3 * el / steps,
+                               "newton_its": sum(s["newton_its"] for s in its),
+                               "gmres_its": sum(s["gmres_its"] for s in its),
+                               "stall_stops": sum(s["stall_stops"] for s in its),
+                               "ok": all(s["status"] == 0 for s in its)}
+        Us[prec] = (U0.cpu().numpy(), U.cpu().numpy())
+        del p
+    (a0, a), (_, b) = Us[64], Us[32]
+    n4 = a.size // 4
+    out["fp32_vs_fp64_rel_l2_of_change"] = [
+        float(np.linalg.norm((b - a)[c * n4:(c + 1) * n4]) / max(np.linalg.norm((a - a0)[c * n4:(c + 1) * n4]), 1e-300))
+        for c in range(4)]
+    out["workload"] = f"inertia-gravity wave, 600x20 quads, k=3, {steps} SDIRK2 steps of 12 s"
+    return out
 
 
 def cpu_baseline():
@@ -166,12 +311,17 @@ def main():
                        "host_syncs": sum(s["host_syncs"] for s in its)},
         "forms": forms,
         "roofline": {"bound": "hbm", "kernel": prof_cls, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None,
+                     "traffic": measured_traffic(prof_cls), "traffic_unit": "bytes per launch",
                      "avg_launch_us": 1e3 * avg_ms, "launches": pc["launches"],
                      "algorithmic_bytes_per_launch": bytes_per_launch,
                      "timing": "HIP start/stop events of each dispatch of the kernel class, second timed pass "
                                f"of the same {a.steps} steps without graph replay ({1e3 * el_prof / a.steps:.1f} ms/step)"},
     }
+    if not a.no_forms:
+        forms.update(ensemble_forms())
+        forms.update(serving_forms(a.serve_requests))
+        forms["inertia_gravity"] = inertia_gravity_forms()
     # copy bandwidth of the device: HBM-resident (1 GiB) and cache-resident (32 MiB)
     hbm_copy, mall_copy = stream_copy(1 << 30), stream_copy(32 << 20)
     out["stream_copy"] = {"hbm_1GiB_GBs": hbm_copy, "mall_32MiB_GBs": mall_copy,

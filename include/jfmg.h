@@ -174,7 +174,7 @@ jfmg_status jfmg_subgrid_map(jfmg_problem* p, int* fv_to_dg);
    the start and stop events of its own dispatch (hipExtLaunchKernel) on the
    stream it runs on; jfmg_profile_read returns per class the summed event time
    [ms], the launch count and the summed algorithmic HBM bytes (what the launch
-   must read and write at minimum, e.g. 5 FV vectors for a smoother stage with a
+   must read and write at minimum, e.g. 6 FV vectors for a smoother stage with a
    matvec).  While a mask is set, implicit steps launch eagerly instead of
    replaying their captured HIP graphs (event timing inside graphs is not
    available).  Enabling resets the counters and synchronizes the stream. */

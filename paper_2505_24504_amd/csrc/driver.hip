@@ -587,7 +587,9 @@ template <typename T> struct Mg {
                 const int zero = (j == 0 && s.xzero[l]) ? 1 : 0;
                 const T* x0 = s.xzero[l] ? nullptr : (const T*)L.buf[i0];   // null: x^(0) = 0
                 const double vb = 4.0 * L.nc * sizeof(T);
-                ProfScope ps(p, zero ? JFMG_K_FV_STAGE_ZERO : JFMG_K_FV_STAGE, zero ? 2 * vb : (x0 ? 5 : 4) * vb);
+                // algorithmic bytes: reads u, F0, x^(j-1), x^(0), b, writes x^(j) (no x^(0) when it is 0);
+                // the zero-start stage reads b and writes x^(1)
+                ProfScope ps(p, zero ? JFMG_K_FV_STAGE_ZERO : JFMG_K_FV_STAGE, zero ? 2 * vb : (x0 ? 6 : 5) * vb);
                 p->xcnt[l][out] = FvLaunch<T>::stage(
                     A, (const T*)L.u, (const T*)L.F0, (const T*)L.buf[prev], x0, (const T*)L.b, (T*)L.buf[out],
                     fvpart(p, l, prev), p->xcnt[l][prev], p->scal + S_LEV + 4 * l, alpha[j], p->adt, zero,
@@ -609,7 +611,8 @@ template <typename T> struct Mg {
             const FvArgs<T> A = fv_args<T>(p, l);
             Level& L = p->lev[l];
             Level& C = p->lev[l + 1];
-            ProfScope ps(p, JFMG_K_FV_DEFECT, (s.xzero[l] ? 1.25 : 3.25) * 4.0 * L.nc * sizeof(T));
+            // reads u, F0, x, b and writes the quarter-size coarse defect (x = 0: reads b only)
+            ProfScope ps(p, JFMG_K_FV_DEFECT, (s.xzero[l] ? 1.25 : 4.25) * 4.0 * L.nc * sizeof(T));
             FvLaunch<T>::defect_restrict(A, (const T*)L.u, (const T*)L.F0, (const T*)L.buf[s.xi[l]], (const T*)L.b,
                                          (T*)C.b, fvpart(p, l, s.xi[l]), p->xcnt[l][s.xi[l]],
                                          p->scal + S_LEV + 4 * l, p->adt, s.xzero[l] ? 1 : 0, p->st);
