@@ -243,8 +243,9 @@ enum {
     S_W = 258,      // ||w||^2 after orthogonalization (right after h2: one readback)
     S_R = 5,        // restart residual norm^2
     S_TMP = 6,
+    S_W1 = 8,       // ||w||^2 after the first Gram-Schmidt pass
     S_LEV = 16,     // + 4*level: LV_* slots
-    S_H1 = 128,     // 65 entries
+    S_H1 = 128,     // 65 entries: h of the first pass, then ||w||^2 before it
     S_H2 = 193,     // 65 entries
     S_HB = 131,     // doubles from S_H1 through S_W
     S_Yc = 384      // 65 entries: FGMRES coefficients
@@ -325,7 +326,7 @@ struct jfmg_problem {
     double graph_adt = 0.0;
     bool use_graphs = true;
     IterGraph* capturing = nullptr;
-    double* hpin = nullptr;            // pinned host copies of the Arnoldi scalars, per iteration
+    double* hpin = nullptr;            // coherent pinned host copies of the Arnoldi scalars, per iteration
     std::vector<hipEvent_t> hev;       // completion of each copy
     // host side
     int have_lin;
@@ -589,7 +590,8 @@ template <typename T> struct Mg {
                 const double vb = 4.0 * L.nc * sizeof(T);
                 // algorithmic bytes: reads u, F0, x^(j-1), x^(0), b, writes x^(j) (no x^(0) when it is 0);
                 // the zero-start stage reads b and writes x^(1)
-                ProfScope ps(p, zero ? JFMG_K_FV_STAGE_ZERO : JFMG_K_FV_STAGE, zero ? 2 * vb : (x0 ? 6 : 5) * vb);
+                const int cls = zero ? JFMG_K_FV_STAGE_ZERO : (l == 0 ? JFMG_K_FV_STAGE : JFMG_K_FV_STAGE_COARSE);
+                ProfScope ps(p, cls, zero ? 2 * vb : (x0 ? 6 : 5) * vb);
                 p->xcnt[l][out] = FvLaunch<T>::stage(
                     A, (const T*)L.u, (const T*)L.F0, (const T*)L.buf[prev], x0, (const T*)L.b, (T*)L.buf[out],
                     fvpart(p, l, prev), p->xcnt[l][prev], p->scal + S_LEV + 4 * l, alpha[j], p->adt, zero,
@@ -707,8 +709,14 @@ jfmg_status stage_residual(jfmg_problem* p, const double* U, const double* Ubar,
 // Givens rotations on the host; U += delta on success.
 // ---------------------------------------------------------------------------
 // One FGMRES iteration on the device: v_j = w_{j-1}/||w_{j-1}|| (j > 0),
-// z_j = Q^-1 v_j, w = G'(U) z_j, classical Gram-Schmidt twice against v_0..v_j;
-// leaves h1, h2 and ||w||^2 in the scalar slots.  No host synchronization.
+// z_j = Q^-1 v_j, w = G'(U) z_j, classical Gram-Schmidt against v_0..v_j with a
+// re-orthogonalization pass where needed; leaves h1, h2 (0 without the second
+// pass) and ||w||^2 in the scalar slots and in pinned host memory.  No host
+// synchronization.
+// Re-orthogonalize when the first Gram-Schmidt pass leaves less than this
+// fraction of ||w|| (Kahan's "twice is enough" test with kappa = 10).
+constexpr double REORTH_TAU = 0.1;
+
 jfmg_status iter_ops(jfmg_problem* p, int j)
 {
     const long N = p->N;
@@ -720,11 +728,20 @@ jfmg_status iter_ops(jfmg_problem* p, int j)
     jfmg_status s = precond(p, vj, zj, S_Z);
     if (s) return s;
     jvp_slot(p, zj, w, S_Z);
+    // Classical Gram-Schmidt; the second (re-orthogonalization) pass runs only
+    // where the first one cancelled more than 1 - REORTH_TAU of ||w||, decided
+    // on the device (the gated kernels return at once otherwise).
+    const int nv = j + 1;
     const double md = (j + 2.0) * N * 8, up = (j + 3.0) * N * 8;
-    { ProfScope ps(p, JFMG_K_MULTIDOT, md); launch_multidot(w, p->V, N, j + 1, N, red_at(p, S_H1), st); }
-    { ProfScope ps(p, JFMG_K_UPDATE, up); launch_update(w, p->V, N, j + 1, N, p->scal + S_H1, no_red(), st); }
-    { ProfScope ps(p, JFMG_K_MULTIDOT, md); launch_multidot(w, p->V, N, j + 1, N, red_at(p, S_H2), st); }
-    { ProfScope ps(p, JFMG_K_UPDATE, up); launch_update(w, p->V, N, j + 1, N, p->scal + S_H2, red_at(p, S_W), st); }
+    const Gate reorth{p->scal + S_W1, p->scal + S_H1 + nv, REORTH_TAU * REORTH_TAU};
+    { ProfScope ps(p, JFMG_K_MULTIDOT, md); launch_multidot(w, p->V, N, nv, 1, N, Gate{}, red_at(p, S_H1), st); }
+    { ProfScope ps(p, JFMG_K_UPDATE, up); launch_update(w, p->V, N, nv, N, p->scal + S_H1, red_at(p, S_W1), st); }
+    launch_multidot(w, p->V, N, nv, 0, N, reorth, red_at(p, S_H2), st);
+    launch_update(w, p->V, N, nv, N, p->scal + S_H2, Red{p->partials, nullptr}, st, reorth);
+    // ||w||^2 (of whichever pass ran last), and the scalar block h1, h2, ||w||^2 of
+    // iteration j to pinned host memory
+    launch_finalize_publish(p->partials, la_blocks(N), p->scal + S_W, p->scal + S_H1, S_HB, S_W - S_H1,
+                            p->hpin + (size_t)j * S_HB, reorth, p->scal + S_W1, st);
     return check_launch(p);
 }
 
@@ -812,10 +829,8 @@ jfmg_status fgmres(jfmg_problem* p, const double* G, double gnorm, double tol_ab
         // Hessenberg column, so the readback round trip overlaps GPU work; when
         // iteration j converges the speculative iteration's output is unused.
         auto issue = [&](int j) -> jfmg_status {
-            jfmg_status s = run_iter(p, j);
+            jfmg_status s = run_iter(p, j);   // ends by publishing its scalars to hpin[j]
             if (s) return s;
-            HIPCHK(p, hipMemcpyAsync(p->hpin + (size_t)j * S_HB, p->scal + S_H1, sizeof(double) * S_HB,
-                                     hipMemcpyDeviceToHost, st));
             HIPCHK(p, hipEventRecord(p->hev[j], st));
             return JFMG_OK;
         };
@@ -1102,7 +1117,8 @@ jfmg_status jfmg_create_problem(const jfmg_config* cfg, void* workspace, size_t 
     e = e ? e : hipMemsetAsync(p->scal, 0, NSCAL * 8, st);
     e = e ? e : hipStreamSynchronize(st);
     e = e ? e : hipStreamCreateWithFlags(&p->cs, hipStreamNonBlocking);
-    e = e ? e : hipHostMalloc((void**)&p->hpin, sizeof(double) * S_HB * cfg->gmres_m, hipHostMallocDefault);
+    // coherent pinned memory: the last kernel of each FGMRES iteration stores its scalars here
+    e = e ? e : hipHostMalloc((void**)&p->hpin, sizeof(double) * S_HB * cfg->gmres_m, hipHostMallocCoherent);
     for (int j = 0; j < cfg->gmres_m && !e; ++j) {
         hipEvent_t ev = nullptr;
         e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);

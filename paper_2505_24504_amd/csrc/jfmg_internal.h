@@ -126,11 +126,25 @@ template <typename T> struct FvLaunch {
 // ---- linear algebra (la.hip) ----
 int la_blocks(long n);
 // out[q] = sum over nb block partials [q][nb], fixed order (one block)
-void launch_finalize(const double* partials, int nb, int nq, double* out, hipStream_t st);
+// Gate of the Arnoldi re-orthogonalization pass: the gated kernels work only
+// where after[0] < tau2 * before[0] (after/before: ||w||^2 after and before the
+// first Gram-Schmidt pass); after == nullptr means always open.
+struct Gate {
+    const double* after = nullptr;
+    const double* before = nullptr;
+    double tau2 = 0.0;
+};
+__device__ __forceinline__ bool gate_open(const Gate& g) { return !g.after || g.after[0] < g.tau2 * g.before[0]; }
+
+void launch_finalize(const double* partials, int nb, int nq, double* out, hipStream_t st, Gate gate = Gate{});
+void launch_finalize_publish(const double* partials, int nb, double* out, const double* src, int n, int idx,
+                             double* host, Gate gate, const double* fallback, hipStream_t st);
 void launch_norm2(const double* x, long n, Red red, hipStream_t st);
-void launch_multidot(const double* w, const double* V, long ld, int nv, long n, Red red, hipStream_t st);
+void launch_multidot(const double* w, const double* V, long ld, int nv, int self, long n, Gate gate, Red red,
+                     hipStream_t st);
 // w -= sum_i h[i] V_i; optional ||w||^2 into red.out when red.out != nullptr
-void launch_update(double* w, const double* V, long ld, int nv, long n, const double* h, Red red, hipStream_t st);
+void launch_update(double* w, const double* V, long ld, int nv, long n, const double* h, Red red, hipStream_t st,
+                   Gate gate = Gate{});
 void launch_scale(double* out, const double* in, long n, const double* nrm2, hipStream_t st);
 // out = base + sum_i y[i] Z_i   (base may alias out)
 void launch_lincomb(double* out, const double* base, const double* Z, long ld, int nv, long n, const double* y,

@@ -1,5 +1,5 @@
-// FP64 vector kernels of the FGMRES Arnoldi process (classical Gram-Schmidt
-// with one re-orthogonalization): multi-dot products <w, v_i> of one vector
+// FP64 vector kernels of the FGMRES Arnoldi process (classical Gram-Schmidt,
+// re-orthogonalized where the first pass cancels most of w): multi-dot products <w, v_i> of one vector
 // against the whole basis in a single pass, the basis update w -= V h, scaling,
 // and the final combination delta = Z y.  Streaming, HBM bound; every
 // reduction is two-level with a fixed summation order (run-to-run identical).
@@ -14,20 +14,56 @@ int la_blocks(long n)
     return (int)((n + (long)LA_NTH * LA_EL - 1) / ((long)LA_NTH * LA_EL));
 }
 
-// out[q] = sum_b p[q * nb + b], one block per q, fixed order
-__global__ void __launch_bounds__(256) finalize_kernel(const double* __restrict__ p, int nb, double* __restrict__ out)
+// out[q] = sum_b p[q * nb + b], one block per q, fixed order (0 where the gate is closed)
+__global__ void __launch_bounds__(256) finalize_kernel(const double* __restrict__ p, int nb, double* __restrict__ out,
+                                                       Gate gate)
 {
     __shared__ double sh[4];
     const int q = blockIdx.x;
+    if (!gate_open(gate)) {
+        if (threadIdx.x == 0) out[q] = 0.0;
+        return;
+    }
     double a = 0.0;
     for (int i = threadIdx.x; i < nb; i += 256) a += p[(long)q * nb + i];
     a = block_sum<256>(a, sh);
     if (threadIdx.x == 0) out[q] = a;
 }
 
-void launch_finalize(const double* partials, int nb, int nq, double* out, hipStream_t st)
+void launch_finalize(const double* partials, int nb, int nq, double* out, hipStream_t st, Gate gate)
 {
-    finalize_kernel<<<dim3(nq), dim3(256), 0, st>>>(partials, nb, out);
+    finalize_kernel<<<dim3(nq), dim3(256), 0, st>>>(partials, nb, out, gate);
+}
+
+// Last reduction of an FGMRES iteration: out[0] = sum of the partials (or
+// fallback[0] where the gate is closed, i.e. the re-orthogonalization pass that
+// would have produced the partials was skipped), and the iteration's scalar
+// block src[0..n) (entry idx replaced by out[0]) stored to host-visible pinned
+// memory, so the host reads the Hessenberg column after the iteration's
+// completion event without a separate copy.
+__global__ void __launch_bounds__(256)
+finalize_publish_kernel(const double* __restrict__ p, int nb, double* __restrict__ out, const double* __restrict__ src,
+                        int n, int idx, double* __restrict__ host, Gate gate, const double* __restrict__ fallback)
+{
+    __shared__ double sh[4];
+    __shared__ double total;
+    const bool open = gate_open(gate);
+    double a = 0.0;
+    if (open)
+        for (int i = threadIdx.x; i < nb; i += 256) a += p[i];
+    a = block_sum<256>(a, sh);
+    if (threadIdx.x == 0) {
+        total = open ? a : fallback[0];
+        out[0] = total;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += 256) host[i] = (i == idx) ? total : src[i];
+}
+
+void launch_finalize_publish(const double* partials, int nb, double* out, const double* src, int n, int idx,
+                             double* host, Gate gate, const double* fallback, hipStream_t st)
+{
+    finalize_publish_kernel<<<dim3(1), dim3(256), 0, st>>>(partials, nb, out, src, n, idx, host, gate, fallback);
 }
 
 __global__ void __launch_bounds__(256) norm2_kernel(const double* __restrict__ x, long n, Red red)
@@ -45,16 +81,20 @@ void launch_norm2(const double* x, long n, Red red, hipStream_t st)
     if (red.out) launch_finalize(red.partials, nb, 1, red.out, st);
 }
 
-// <w, v_i> for i < nv in one pass: every thread keeps one accumulator per basis
-// vector in registers, each wave reduces all of them with butterflies, and one
-// LDS exchange combines the waves (a single barrier per block); the block
-// partials [v][block] are summed by the finalize kernel.
+// <w, v_i> for i < nv in one pass (and <w, w> as entry nv when self is set):
+// every thread keeps one accumulator per basis vector in registers, each wave
+// reduces all of them with butterflies, and one LDS exchange combines the waves
+// (a single barrier per block); the block partials [v][block] are summed by the
+// finalize kernel.  Nothing is computed where the gate is closed.
 template <int MAXV>
 __global__ void __launch_bounds__(LA_NTH)
-multidot_kernel(const double* __restrict__ w, const double* __restrict__ V, long ld, int nv, long n, Red red)
+multidot_kernel(const double* __restrict__ w, const double* __restrict__ V, long ld, int nv, int self, long n, Gate gate,
+                Red red)
 {
     constexpr int NW = LA_NTH / 64;
     __shared__ double sh[NW][MAXV];
+    if (!gate_open(gate)) return;
+    const int nt = nv + self;
     const long base = (long)blockIdx.x * LA_NTH * LA_EL + threadIdx.x;
     double acc[MAXV];
 #pragma unroll
@@ -65,20 +105,22 @@ multidot_kernel(const double* __restrict__ w, const double* __restrict__ V, long
         if (i < n) {
             const double wi = w[i];
 #pragma unroll
-            for (int v = 0; v < MAXV; ++v)
+            for (int v = 0; v < MAXV; ++v) {
                 if (v < nv) acc[v] += wi * V[(long)v * ld + i];
+                else if (v == nv && self) acc[v] += wi * wi;
+            }
         }
     }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
     for (int v = 0; v < MAXV; ++v) {
-        if (v < nv) {
+        if (v < nt) {
             const double s = wave_sum(acc[v]);
             if (lane == 0) sh[wid][v] = s;
         }
     }
     __syncthreads();
-    if ((int)threadIdx.x < nv) {
+    if ((int)threadIdx.x < nt) {
         double s = 0.0;
 #pragma unroll
         for (int q = 0; q < NW; ++q) s += sh[q][threadIdx.x];
@@ -86,20 +128,23 @@ multidot_kernel(const double* __restrict__ w, const double* __restrict__ V, long
     }
 }
 
-void launch_multidot(const double* w, const double* V, long ld, int nv, long n, Red red, hipStream_t st)
+void launch_multidot(const double* w, const double* V, long ld, int nv, int self, long n, Gate gate, Red red,
+                     hipStream_t st)
 {
     const dim3 g(la_blocks(n)), b(LA_NTH);
-    if (nv <= 8) timed_launch(multidot_kernel<8>, g, b, st, w, V, ld, nv, n, red);
-    else if (nv <= 16) timed_launch(multidot_kernel<16>, g, b, st, w, V, ld, nv, n, red);
-    else if (nv <= 32) timed_launch(multidot_kernel<32>, g, b, st, w, V, ld, nv, n, red);
-    else timed_launch(multidot_kernel<65>, g, b, st, w, V, ld, nv, n, red);
-    launch_finalize(red.partials, (int)g.x, nv, red.out, st);
+    const int nt = nv + self;
+    if (nt <= 8) timed_launch(multidot_kernel<8>, g, b, st, w, V, ld, nv, self, n, gate, red);
+    else if (nt <= 16) timed_launch(multidot_kernel<16>, g, b, st, w, V, ld, nv, self, n, gate, red);
+    else if (nt <= 32) timed_launch(multidot_kernel<32>, g, b, st, w, V, ld, nv, self, n, gate, red);
+    else timed_launch(multidot_kernel<65>, g, b, st, w, V, ld, nv, self, n, gate, red);
+    launch_finalize(red.partials, (int)g.x, nt, red.out, st, gate);
 }
 
 __global__ void __launch_bounds__(LA_NTH)
 update_kernel(double* __restrict__ w, const double* __restrict__ V, long ld, int nv, long n,
-              const double* __restrict__ h, Red red)
+              const double* __restrict__ h, Gate gate, Red red)
 {
+    if (!gate_open(gate)) return;
     const long base = (long)blockIdx.x * LA_NTH * LA_EL + threadIdx.x;
     double acc[LA_EL];
 #pragma unroll
@@ -128,9 +173,10 @@ update_kernel(double* __restrict__ w, const double* __restrict__ V, long ld, int
     if (red.partials) put_partial<LA_NTH>(red, s);
 }
 
-void launch_update(double* w, const double* V, long ld, int nv, long n, const double* h, Red red, hipStream_t st)
+void launch_update(double* w, const double* V, long ld, int nv, long n, const double* h, Red red, hipStream_t st,
+                   Gate gate)
 {
-    timed_launch(update_kernel, dim3(la_blocks(n)), dim3(LA_NTH), st, w, V, ld, nv, n, h, red);
+    timed_launch(update_kernel, dim3(la_blocks(n)), dim3(LA_NTH), st, w, V, ld, nv, n, h, gate, red);
     if (red.out) launch_finalize(red.partials, la_blocks(n), 1, red.out, st);
 }
 
