@@ -181,7 +181,8 @@ jfmg_status jfmg_subgrid_map(jfmg_problem* p, int* fv_to_dg);
 typedef enum {
     JFMG_K_DG_RESIDUAL = 0,   /* stage residual G and ||G||                         */
     JFMG_K_DG_JVP = 1,        /* fused FD Jacobian-vector product                   */
-    JFMG_K_FV_STAGE = 2,      /* RK smoother stage with an FV matvec, finest level  */
+    JFMG_K_FV_STAGE = 2,      /* RK smoother stage with an FV matvec, levels >= 512
+                                 cells wide (wide-tile kernel)                      */
     JFMG_K_FV_STAGE_ZERO = 3, /* first stage from x = 0 (no matvec)                 */
     JFMG_K_FV_DEFECT = 4,     /* defect + agglomeration restriction                 */
     JFMG_K_FV_PROLONG = 5,    /* injection prolongation + correction               */
@@ -190,7 +191,7 @@ typedef enum {
     JFMG_K_TRANSFER_TINV = 8, /* FV -> DG                                           */
     JFMG_K_MULTIDOT = 9,      /* Arnoldi <w, v_i>                                   */
     JFMG_K_UPDATE = 10,       /* Arnoldi w -= V h                                   */
-    JFMG_K_FV_STAGE_COARSE = 11, /* RK smoother stage with an FV matvec, coarser levels */
+    JFMG_K_FV_STAGE_SMALL = 11, /* the same on narrower levels (small-tile kernel)    */
     JFMG_K_NCLASS = 12
 } jfmg_kernel_class;
 jfmg_status jfmg_profile_enable(jfmg_problem* p, unsigned class_mask);

@@ -590,7 +590,8 @@ template <typename T> struct Mg {
                 const double vb = 4.0 * L.nc * sizeof(T);
                 // algorithmic bytes: reads u, F0, x^(j-1), x^(0), b, writes x^(j) (no x^(0) when it is 0);
                 // the zero-start stage reads b and writes x^(1)
-                const int cls = zero ? JFMG_K_FV_STAGE_ZERO : (l == 0 ? JFMG_K_FV_STAGE : JFMG_K_FV_STAGE_COARSE);
+                const int cls = zero ? JFMG_K_FV_STAGE_ZERO
+                                     : (fv_wide_tile(L.nx) ? JFMG_K_FV_STAGE : JFMG_K_FV_STAGE_SMALL);
                 ProfScope ps(p, cls, zero ? 2 * vb : (x0 ? 6 : 5) * vb);
                 p->xcnt[l][out] = FvLaunch<T>::stage(
                     A, (const T*)L.u, (const T*)L.F0, (const T*)L.buf[prev], x0, (const T*)L.b, (T*)L.buf[out],

@@ -20,6 +20,40 @@ constexpr int FV_TX = 64, FV_TZ = 4, FV_NTH = FV_TX * FV_TZ;
 
 enum { FVM_LIN = 0, FVM_STAGE = 1, FVM_MATVEC = 2, FVM_DEFECT = 3 };
 
+// Tile shapes: levels at least FV_WIDE_MIN cells wide use the wide tile (one
+// wave per row of 64 cells; own-cell operands loaded after the face loop and at
+// most 128 VGPRs, so four waves fit per SIMD); narrower levels are latency bound
+// and use a small tile with more threads than cells, so that every face of the
+// tile gets its own thread.  ZREV hands the z-faces out from the last thread
+// down.  Chosen by measurement on the density-current levels (1024x256 ...
+// 128x32 cells) against 8x4, 32x8, 16x4 with 128/192 threads, 2/3/4 waves per
+// SIMD, early and late own-cell loads and both face orders.
+#ifndef FV_WIDE_MIN
+#define FV_WIDE_MIN 512
+#endif
+#ifndef FV_WIDE_TX
+#define FV_WIDE_TX 64
+#define FV_WIDE_TZ 4
+#define FV_WIDE_NTH 256
+#define FV_WIDE_WPE 4
+#endif
+#ifndef FV_WIDE_LATE
+#define FV_WIDE_LATE true
+#endif
+#ifndef FV_WIDE_ZREV
+#define FV_WIDE_ZREV true
+#endif
+#ifndef FV_SMALL_ZREV
+#define FV_SMALL_ZREV true
+#endif
+#ifndef FV_SMALL_TX
+#define FV_SMALL_TX 16
+#define FV_SMALL_TZ 4
+#define FV_SMALL_NTH 256
+#define FV_SMALL_WPE 1
+#endif
+
+
 // FV operator on one tile of TX x TZ cells, face-centric: the perturbed states
 // w = u + eps x of the tile and a one-cell halo are staged in LDS, every face
 // of the tile gets its net flux Phi (HLLC minus the interior-penalty diffusion
@@ -31,7 +65,7 @@ enum { FVM_LIN = 0, FVM_STAGE = 1, FVM_MATVEC = 2, FVM_DEFECT = 3 };
 //   STAGE   out = x0 + alpha_j dtau (b - g'x), g'x = x - adt/eps (f~(u + eps x) - F0)
 //   MATVEC  out = g'x
 //   DEFECT  out(coarse) = R(g'x - b), 2x2 agglomeration inside the tile
-template <typename T, int TX, int TZ, int NTH, int WPE, int MODE>
+template <typename T, int TX, int TZ, int NTH, int WPE, bool LATE, bool ZREV, int MODE>
 __global__ void __launch_bounds__(NTH, WPE)
 fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, const T* __restrict__ xp,
                const T* __restrict__ x0, const T* __restrict__ b, T* __restrict__ out,
@@ -57,17 +91,21 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
     const bool valid = tid < NCELL && I < nxl && J < nzl;
     const long q = (long)J * nxl + I;
 
-    // ---- every global load first: own-cell operands, then the halo states ----
+    // ---- every global load first (own-cell operands, then the halo states), or
+    // the own-cell operands only after the face loop (LATE: fewer live registers) ----
     T own_x[4] = {T(0), T(0), T(0), T(0)}, own_f0[4] = {T(0), T(0), T(0), T(0)};
     T own_b[4] = {T(0), T(0), T(0), T(0)}, own_x0[4] = {T(0), T(0), T(0), T(0)};
-    if (valid) {
+    auto load_own = [&]() {
+        if (valid) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            if constexpr (PERT) { own_x[c] = xp[c * nc + q]; own_f0[c] = F0[c * nc + q]; }
-            if constexpr (MODE == FVM_STAGE || MODE == FVM_DEFECT) own_b[c] = b[c * nc + q];
-            if constexpr (MODE == FVM_STAGE) own_x0[c] = x0 ? x0[c * nc + q] : T(0);
+            for (int c = 0; c < 4; ++c) {
+                if constexpr (PERT) { own_x[c] = xp[c * nc + q]; own_f0[c] = F0[c * nc + q]; }
+                if constexpr (MODE == FVM_STAGE || MODE == FVM_DEFECT) own_b[c] = b[c * nc + q];
+                if constexpr (MODE == FVM_STAGE) own_x0[c] = x0 ? x0[c * nc + q] : T(0);
+            }
         }
-    }
+    };
+    if constexpr (!LATE) load_own();
     T hu[HITEMS][4], hx[HITEMS][4];
 #pragma unroll
     for (int it = 0; it < HITEMS; ++it) {
@@ -107,102 +145,100 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
                 }
         }
         __syncthreads();
-        // ---- one net flux per face ----
-        for (int f = tid; f < NFX + NFZ; f += NTH) {
-            T Phi[4] = {T(0), T(0), T(0), T(0)};
-            const bool xface = f < NFX;
-            int r0, r1, sL, sR;   // LDS rows/cols of the two sides
-            bool skip = false, wallL = false, wallR = false;
-            const T* bg;
-            const T* pr;   // background pressure and 1/(rho theta) at the face
-            const T* dbg = nullptr;
-            T elen, hn;
-            if (xface) {
-                const int jj = f / (TX + 1), fi = f - jj * (TX + 1);
+        // ---- one net flux per face: x-faces in thread order, z-faces in reverse
+        // thread order (the threads with a second x-face are not those with a
+        // second z-face) ----
+        auto face = [&](auto xf_tag, int idx) {
+            constexpr bool XF = decltype(xf_tag)::value;
+            int r0, r1, sL, sR, Jrow;   // LDS rows/cols of the two sides; background row
+            bool skip, wallL, wallR;
+            if constexpr (XF) {
+                const int jj = idx / (TX + 1), fi = idx - jj * (TX + 1);
                 const int Jf = J0 + jj, Ir = I0 + fi, Il = Ir - 1;
                 skip = (Jf >= nzl) || (Il >= nxl);
                 wallL = (Ir == 0) && A.bc != 1;
                 wallR = (Il == nxl - 1) && A.bc != 1;
                 r0 = jj + 1; r1 = jj + 1; sL = fi; sR = fi + 1;
-                bg = A.bgc + 4 * (skip ? 0 : Jf);
-                pr = A.pc + 2 * (skip ? 0 : Jf);
-                elen = A.hz; hn = A.hx;
+                Jrow = skip ? 0 : Jf;
             } else {
-                const int g = f - NFX;
-                const int fj = g / TX, ii = g - fj * TX;
+                const int fj = idx / TX, ii = idx - fj * TX;
                 const int If = I0 + ii, Ja = J0 + fj, Jb = Ja - 1;
                 skip = (If >= nxl) || (Jb >= nzl);
                 wallL = (Jb < 0);
                 wallR = (Ja == nzl);
                 r0 = fj; r1 = fj + 1; sL = ii + 1; sR = ii + 1;
-                bg = A.bgf + 4 * (skip ? 0 : Ja);
-                pr = A.pf + 2 * (skip ? 0 : Ja);
-                dbg = A.dbgf + 4 * (skip ? 0 : Ja);
-                elen = A.hx; hn = A.hz;
+                Jrow = skip ? 0 : Ja;
             }
+            T Phi[4] = {T(0), T(0), T(0), T(0)};
             if (!skip) {
-                const T nx = xface ? T(1) : T(0), nz = xface ? T(0) : T(1);
-                T UL[4], UR[4], wL[4], wR[4], H[4];
+                constexpr int NRM = XF ? 1 : 2;   // normal momentum component
+                const T* bg = (XF ? A.bgc : A.bgf) + 4 * Jrow;
+                const T* pr = (XF ? A.pc : A.pf) + 2 * Jrow;
+                const bool wall = wallL || wallR;
+                // HLLC(a, b; s n), Phi = s H: interior a = L, b = R, s = +1; a slip wall
+                // mirrors the inside cell (a = R, s = -1 on the low side; a = L, s = +1 on the high side)
+                const T sgn = wallL ? T(-1) : T(1);
+                T Dw[4], Ua[4], Ub[4], H[4];   // Dw = w_a - w_b (perturbations), for the penalty
+                T pa, pbb;
+                {
+                    T wa[4], wb[4];
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    wL[c] = sw[c][r0][sL];
-                    wR[c] = sw[c][r1][sR];
-                    UL[c] = wL[c] + bg[c];
-                    UR[c] = wR[c] + bg[c];
+                    for (int c = 0; c < 4; ++c) {
+                        const T l = sw[c][r0][sL], r = sw[c][r1][sR];
+                        wa[c] = wallL ? r : l;
+                        wb[c] = wall ? wa[c] : r;
+                        Ua[c] = wa[c] + bg[c];
+                        Ub[c] = wb[c] + bg[c];
+                        Dw[c] = wa[c] - wb[c];
+                    }
+                    const T pb = pr[0], irb = pr[1];
+                    pa = pert_pressure(A.gas, wa[3], irb, pb);
+                    pbb = pert_pressure(A.gas, wb[3], irb, pb);
                 }
-                const T pb = pr[0], irb = pr[1];
-                if (wallL) {            // only the cell on the + side is inside
-                    T M[4] = {UR[0], UR[1], UR[2], UR[3]};
-                    if (xface) M[1] = -M[1]; else M[2] = -M[2];
-                    const T pR = pert_pressure(A.gas, wR[3], irb, pb);
-                    hllc(A.gas, UR, M, pR, pR, -nx, -nz, H);
+                if (wall) Ub[NRM] = -Ua[NRM];
+                hllc(A.gas, Ua, Ub, pa, pbb, sgn * T(XF ? 1 : 0), sgn * T(XF ? 0 : 1), H);
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) Phi[c] = -H[c];
-                } else if (wallR) {     // only the cell on the - side is inside
-                    T M[4] = {UL[0], UL[1], UL[2], UL[3]};
-                    if (xface) M[1] = -M[1]; else M[2] = -M[2];
-                    const T pL = pert_pressure(A.gas, wL[3], irb, pb);
-                    hllc(A.gas, UL, M, pL, pL, nx, nz, H);
+                for (int c = 0; c < 4; ++c) Phi[c] = sgn * H[c];
+                if (A.physics == 1 && !wall) {
+                    T FL[4] = {T(0), T(0), T(0), T(0)}, FR[4] = {T(0), T(0), T(0), T(0)};
+                    if constexpr (!XF) {
+                        const T Z4[4] = {T(0), T(0), T(0), T(0)};
+                        const T* dbg = A.dbgf + 4 * Jrow;
+                        visc_flux(A.mu, Ua, Z4, dbg, T(0), T(1), FL);
+                        visc_flux(A.mu, Ub, Z4, dbg, T(0), T(1), FR);
+                    }
+                    const T irs = T(1) / (Ua[0] + Ub[0]);
+                    const T muh = A.mu / (XF ? A.hx : A.hz);
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) Phi[c] = H[c];
-                } else {
-                    const T pL = pert_pressure(A.gas, wL[3], irb, pb), pR = pert_pressure(A.gas, wR[3], irb, pb);
-                    hllc(A.gas, UL, UR, pL, pR, nx, nz, H);
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) Phi[c] = H[c];
-                    if (A.physics == 1) {
-                        T FL[4] = {T(0), T(0), T(0), T(0)}, FR[4] = {T(0), T(0), T(0), T(0)};
-                        if (!xface) {
-                            const T Z4[4] = {T(0), T(0), T(0), T(0)};
-                            visc_flux(A.mu, UL, Z4, dbg, nx, nz, FL);
-                            visc_flux(A.mu, UR, Z4, dbg, nx, nz, FR);
-                        }
-                        const T irs = T(1) / (UL[0] + UR[0]);
-                        const T muh = A.mu / hn;
-#pragma unroll
-                        for (int c = 1; c < 4; ++c) {
-                            const T Dl0 = wL[0] - wR[0], Dlc = wL[c] - wR[c];
-                            const T r = (UL[c] + UR[c]) * irs;
-                            const T pen = muh * (Dlc - r * Dl0);
-                            Phi[c] -= T(0.5) * (FL[c] + FR[c]) - pen;
-                        }
+                    for (int c = 1; c < 4; ++c) {
+                        const T rr = (Ua[c] + Ub[c]) * irs;
+                        const T pen = muh * (Dw[c] - rr * Dw[0]);
+                        Phi[c] -= T(0.5) * (FL[c] + FR[c]) - pen;
                     }
                 }
+                const T elen = XF ? A.hz : A.hx;
 #pragma unroll
                 for (int c = 0; c < 4; ++c) Phi[c] *= elen;
             }
-            if (xface) {
-                const int jj = f / (TX + 1), fi = f - jj * (TX + 1);
+            if constexpr (XF) {
+                const int jj = idx / (TX + 1), fi = idx - jj * (TX + 1);
 #pragma unroll
                 for (int c = 0; c < 4; ++c) sFx[jj][fi][c] = Phi[c];
             } else {
-                const int g = f - NFX;
-                const int fj = g / TX, ii = g - fj * TX;
+                const int fj = idx / TX, ii = idx - fj * TX;
 #pragma unroll
                 for (int c = 0; c < 4; ++c) sFz[fj][ii][c] = Phi[c];
             }
-        }
+        };
+        for (int fx = tid; fx < NFX; fx += NTH) face(std::true_type{}, fx);
+        if constexpr (ZREV)   // z-faces from the last thread down
+            for (int fz = NTH - 1 - tid; fz < NFZ; fz += NTH) face(std::false_type{}, fz);
+        else                  // z-faces continue the numbering after the x-faces
+            for (int fz = (tid + NTH - NFX % NTH) % NTH; fz < NFZ; fz += NTH) face(std::false_type{}, fz);
+        if constexpr (LATE) load_own();
         __syncthreads();
+    } else if constexpr (LATE) {
+        load_own();
     }
 
     // ---- per cell ----
@@ -395,35 +431,13 @@ static inline dim3 tile_grid(int nx, int nz)
     return dim3((unsigned)((nx + FV_TX - 1) / FV_TX), (unsigned)((nz + FV_TZ - 1) / FV_TZ));
 }
 
-// Tile shapes: levels at least FV_WIDE_MIN cells wide use the wide tile (one
-// wave per row of 64 cells, at most 168 VGPRs so that three waves fit per SIMD);
-// narrower levels are latency bound and use a small tile with more threads than
-// cells, so that every face of the tile gets its own thread.  Measured on the
-// density-current levels (1024x256 ... 128x32 cells) against 8x4, 32x8 and
-// 128/192-thread variants.
-#ifndef FV_WIDE_MIN
-#define FV_WIDE_MIN 1024
-#endif
-#ifndef FV_WIDE_TX
-#define FV_WIDE_TX 64
-#define FV_WIDE_TZ 4
-#define FV_WIDE_NTH 256
-#define FV_WIDE_WPE 3
-#endif
-#ifndef FV_SMALL_TX
-#define FV_SMALL_TX 16
-#define FV_SMALL_TZ 4
-#define FV_SMALL_NTH 256
-#define FV_SMALL_WPE 1
-#endif
-
-template <typename T, int TX, int TZ, int NTH, int WPE, int MODE>
+template <typename T, int TX, int TZ, int NTH, int WPE, bool LATE, bool ZREV, int MODE>
 static int tile_launch_shape(const FvArgs<T>& A, const T* u, const T* F0, const T* xp, const T* x0, const T* b,
                              T* out, const double* xpart, int xcount, double* slots, double alpha_j, double adt,
                              double cfl, Red red, hipStream_t st)
 {
     const dim3 g((unsigned)((A.nxl + TX - 1) / TX), (unsigned)((A.nzl + TZ - 1) / TZ));
-    timed_launch(fv_tile_kernel<T, TX, TZ, NTH, WPE, MODE>, g, dim3(NTH), st, A, u, F0, xp, x0, b, out, xpart,
+    timed_launch(fv_tile_kernel<T, TX, TZ, NTH, WPE, LATE, ZREV, MODE>, g, dim3(NTH), st, A, u, F0, xp, x0, b, out, xpart,
                  xcount, slots, alpha_j, adt, cfl, red);
     return (int)(g.x * g.y);
 }
@@ -433,10 +447,10 @@ static int tile_launch(const FvArgs<T>& A, const T* u, const T* F0, const T* xp,
                        const double* xpart, int xcount, double* slots, double alpha_j, double adt, double cfl,
                        Red red, hipStream_t st)
 {
-    if (A.nxl >= FV_WIDE_MIN)
-        return tile_launch_shape<T, FV_WIDE_TX, FV_WIDE_TZ, FV_WIDE_NTH, FV_WIDE_WPE, MODE>(
+    if (fv_wide_tile(A.nxl))
+        return tile_launch_shape<T, FV_WIDE_TX, FV_WIDE_TZ, FV_WIDE_NTH, FV_WIDE_WPE, FV_WIDE_LATE, FV_WIDE_ZREV, MODE>(
             A, u, F0, xp, x0, b, out, xpart, xcount, slots, alpha_j, adt, cfl, red, st);
-    return tile_launch_shape<T, FV_SMALL_TX, FV_SMALL_TZ, FV_SMALL_NTH, FV_SMALL_WPE, MODE>(
+    return tile_launch_shape<T, FV_SMALL_TX, FV_SMALL_TZ, FV_SMALL_NTH, FV_SMALL_WPE, false, FV_SMALL_ZREV, MODE>(
         A, u, F0, xp, x0, b, out, xpart, xcount, slots, alpha_j, adt, cfl, red, st);
 }
 
@@ -506,6 +520,8 @@ void FvLaunch<T>::norm2(const T* x, long n, Red red, hipStream_t st)
     fv_norm2_kernel<T><<<dim3(norm_blocks(n)), dim3(256), 0, st>>>(x, n, red);
     if (red.out) launch_finalize(red.partials, norm_blocks(n), 1, red.out, st);
 }
+bool fv_wide_tile(long nxl) { return nxl >= FV_WIDE_MIN; }
+
 long fv_partial_blocks(long nxl, long nzl)
 {
     const long wide = ((nxl + FV_WIDE_TX - 1) / FV_WIDE_TX) * ((nzl + FV_WIDE_TZ - 1) / FV_WIDE_TZ);

@@ -99,6 +99,8 @@ void launch_transfer_Tinv(int k, const DgArgs& A, int mass_fix, const T* u, doub
 void launch_subgrid_map(int k, const DgArgs& A, int nxf, int* out, hipStream_t st);
 
 // ---- FV kernels (fv.hip) ----
+// the FV operator of a level nxl cells wide runs the wide-tile kernel (else the small-tile one)
+bool fv_wide_tile(long nxl);
 // FV partial-sum blocks needed by the largest launch on a level of nxl x nzl cells
 long fv_partial_blocks(long nxl, long nzl);
 

@@ -69,7 +69,7 @@ EXPORTS = [
 
 KERNEL_CLASSES = ["dg_residual", "dg_jvp", "fv_stage", "fv_stage_zero", "fv_defect_restrict",
                   "fv_prolong_correct", "fv_linearize", "transfer_T", "transfer_Tinv", "multidot",
-                  "update", "fv_stage_coarse"]
+                  "update", "fv_stage_small"]
 
 
 def load_library(path: str = LIB_PATH):
