@@ -263,6 +263,9 @@ struct Carve {
     }
 };
 
+// partial-sum regions per FV level: one per iterate buffer
+constexpr int FVP_PER_LEVEL = 3;
+
 struct Level {
     int nx, nz;
     long nc;
@@ -298,7 +301,7 @@ struct jfmg_problem {
     double* scal;
     double* partials;   // block partials of reductions that are finalized right away
     size_t npartials;
-    double* fvpart;     // block partials of ||x||^2 of each FV buffer, [level][buffer][FVP]
+    double* fvpart;     // block partials of ||x||^2 of each FV buffer, [level][FVP_PER_LEVEL][FVP]
     size_t fvp;
     int xcnt[MAXLEV][3];
     double* bg_node; double* dbg_node; double* th_node; double* bg_face; double* dbg_face;
@@ -461,7 +464,7 @@ size_t layout(const jfmg_config& c, char* base, F&& bind)
     bind("scal", cv.take(NSCAL * 8), 0);
     bind("partials", cv.take(npart * 8), npart);
     const size_t fvp = (size_t)fvblk;
-    bind("fvpart", cv.take(fvp * 3 * c.mg_levels * 8), fvp);
+    bind("fvpart", cv.take(fvp * FVP_PER_LEVEL * c.mg_levels * 8), fvp);
     bind("bg_node", cv.take((size_t)c.nz * n1 * 4 * 8), 0);
     bind("dbg_node", cv.take((size_t)c.nz * n1 * 4 * 8), 0);
     bind("th_node", cv.take((size_t)c.nz * n1 * 8), 0);
@@ -492,7 +495,7 @@ size_t layout(const jfmg_config& c, char* base, F&& bind)
 
 Red red_at(jfmg_problem* p, int slot) { return Red{p->partials, p->scal + slot}; }
 Red no_red() { return Red{nullptr, nullptr}; }
-double* fvpart(jfmg_problem* p, int l, int bi) { return p->fvpart + (3 * l + bi) * p->fvp; }
+double* fvpart(jfmg_problem* p, int l, int bi) { return p->fvpart + (FVP_PER_LEVEL * l + bi) * p->fvp; }
 
 // read `count` device scalars starting at `slot` (synchronizes the stream)
 jfmg_status read_scalars(jfmg_problem* p, int slot, int count, double* out)
@@ -651,13 +654,14 @@ template <typename T> struct Mg {
     }
 };
 
-// z = Q^-1 r; ||z||^2 into slot zslot
-template <typename T> jfmg_status mg_apply_t(jfmg_problem* p, const double* r, double* z, int zslot)
+// z = Q^-1 r, ||z||^2 into slot zslot; with rnrm2 != nullptr r is first
+// normalized in place, r /= sqrt(rnrm2[0]), by the DG -> FV transfer
+template <typename T> jfmg_status mg_apply_t(jfmg_problem* p, double* r, double* z, int zslot, const double* rnrm2)
 {
     Level& L = p->lev[0];
     {
-        ProfScope ps(p, JFMG_K_TRANSFER_T, (double)p->N * (8 + sizeof(T)));
-        launch_transfer_T<T>(p->cfg.k, p->A, p->cfg.mass_fix, r, (T*)L.b, L.nx, p->st);
+        ProfScope ps(p, JFMG_K_TRANSFER_T, (double)p->N * (8 + sizeof(T)) + (rnrm2 ? 8.0 * p->N : 0.0));
+        launch_transfer_T<T>(p->cfg.k, p->A, p->cfg.mass_fix, r, (T*)L.b, L.nx, p->st, rnrm2, rnrm2 ? r : nullptr);
     }
     Mg<T> mg{p};
     T* x = mg.run();
@@ -666,14 +670,17 @@ template <typename T> jfmg_status mg_apply_t(jfmg_problem* p, const double* r, d
     return check_launch(p);
 }
 
-jfmg_status precond(jfmg_problem* p, const double* r, double* z, int zslot)
+// z = Q^-1 r, ||z||^2 into slot zslot; with rnrm2 != nullptr r is first
+// normalized in place (r /= sqrt(rnrm2[0]), the Arnoldi v_j = w / ||w||)
+jfmg_status precond(jfmg_problem* p, double* r, double* z, int zslot, const double* rnrm2 = nullptr)
 {
     if (!p->cfg.precond) {
+        if (rnrm2) launch_scale(r, r, p->N, rnrm2, p->st);
         HIPCHK(p, hipMemcpyAsync(z, r, sizeof(double) * p->N, hipMemcpyDeviceToDevice, p->st));
         launch_norm2(z, p->N, red_at(p, zslot), p->st);
         return check_launch(p);
     }
-    return p->prec == 32 ? mg_apply_t<float>(p, r, z, zslot) : mg_apply_t<double>(p, r, z, zslot);
+    return p->prec == 32 ? mg_apply_t<float>(p, r, z, zslot, rnrm2) : mg_apply_t<double>(p, r, z, zslot, rnrm2);
 }
 
 // out = G'(U_lin) y with ||y||^2 already in slot yslot
@@ -725,8 +732,8 @@ jfmg_status iter_ops(jfmg_problem* p, int j)
     double* vj = p->V + (long)j * N;
     double* zj = p->Z + (long)j * N;
     double* w = p->V + (long)(j + 1) * N;
-    if (j > 0) launch_scale(vj, vj, N, p->scal + S_W, st);
-    jfmg_status s = precond(p, vj, zj, S_Z);
+    // v_j = w_{j-1} / ||w_{j-1}|| (j > 0) is formed by the preconditioner's first kernel
+    jfmg_status s = precond(p, vj, zj, S_Z, j > 0 ? p->scal + S_W : nullptr);
     if (s) return s;
     jvp_slot(p, zj, w, S_Z);
     // Classical Gram-Schmidt; the second (re-orthogonalization) pass runs only
@@ -1210,7 +1217,7 @@ jfmg_status jfmg_mg_apply(jfmg_problem* p, const double* r, double* z)
 {
     if (!p || !r || !z) return fail(p, JFMG_EINVAL, "null argument");
     if (!p->have_lin) return fail(p, JFMG_ESTATE, "jfmg_mg_apply needs jfmg_linearize first");
-    return precond(p, r, z, S_TMP);
+    return precond(p, const_cast<double*>(r), z, S_TMP);   // r is written only when normalizing
 }
 
 static jfmg_status implicit_step_body(jfmg_problem* p, double* U, jfmg_stats* stats)

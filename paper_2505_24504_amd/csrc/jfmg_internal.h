@@ -92,7 +92,8 @@ int norm_total_grid(long n);
 
 // ---- transfers (transfer.hip) ----
 template <typename T>
-void launch_transfer_T(int k, const DgArgs& A, int mass_fix, const double* U, T* u, int nxf, hipStream_t st);
+void launch_transfer_T(int k, const DgArgs& A, int mass_fix, const double* U, T* u, int nxf, hipStream_t st,
+                       const double* snrm2 = nullptr, double* Us = nullptr);
 template <typename T>
 void launch_transfer_Tinv(int k, const DgArgs& A, int mass_fix, const T* u, double* U, int nxf, Red red,
                           hipStream_t st);

@@ -25,9 +25,13 @@ __device__ __forceinline__ long subcell_index(int ex, int ez, int i, int j, int 
     return (long)(ez * n1 + j) * nxf + (long)ex * n1 + i;
 }
 
+// snrm2 != nullptr: the input is U / ||U|| (||U||^2 = snrm2[0]); the scaled DG
+// vector is also written back to Us (may alias U: every value is read and
+// written by the same thread).
 template <int N1, typename T>
 __global__ void __launch_bounds__(TrShape<N1>::NTH)
-transfer_T_kernel(DgArgs A, int mass_fix, const double* __restrict__ U, T* __restrict__ u, int nxf)
+transfer_T_kernel(DgArgs A, int mass_fix, const double* U, T* __restrict__ u, int nxf, const double* snrm2,
+                  double* Us)
 {
     constexpr int NP = TrShape<N1>::NP, EPB = TrShape<N1>::EPB;
     __shared__ double sU[EPB][4][NP];
@@ -38,26 +42,37 @@ transfer_T_kernel(DgArgs A, int mass_fix, const double* __restrict__ U, T* __res
     const bool valid = act && e < A.ne;
     const long N = A.ne * NP;
     const long nc = N;   // number of finest FV cells
+    const double s = snrm2 ? 1.0 / sqrt(snrm2[0]) : 1.0;
     if (act)
-        for (int c = 0; c < 4; ++c) sU[le][c][nd] = valid ? U[c * N + e * NP + nd] : 0.0;
+        for (int c = 0; c < 4; ++c) {
+            double v = 0.0;
+            if (valid) {
+                v = U[c * N + e * NP + nd];
+                if (snrm2) {
+                    v = v * s;
+                    Us[c * N + e * NP + nd] = v;
+                }
+            }
+            sU[le][c][nd] = v;
+        }
     __syncthreads();
     const int i = nd % N1, j = nd / N1;   // this thread: x-index i, z-index j
     // first contraction along x: h_{b,i} = sum_a V_ia u_ab (stored at node slot b*N1+i)
     if (act)
         for (int c = 0; c < 4; ++c) {
-            double s = 0.0;
+            double s2 = 0.0;
 #pragma unroll
-            for (int a = 0; a < N1; ++a) s += A.R.V[i][a] * sU[le][c][j * N1 + a];
-            sH[le][c][j * N1 + i] = s;
+            for (int a = 0; a < N1; ++a) s2 += A.R.V[i][a] * sU[le][c][j * N1 + a];
+            sH[le][c][j * N1 + i] = s2;
         }
     __syncthreads();
     double tv[4];
     if (act)
         for (int c = 0; c < 4; ++c) {
-            double s = 0.0;
+            double s2 = 0.0;
 #pragma unroll
-            for (int bb = 0; bb < N1; ++bb) s += A.R.V[j][bb] * sH[le][c][bb * N1 + i];
-            tv[c] = s;
+            for (int bb = 0; bb < N1; ++bb) s2 += A.R.V[j][bb] * sH[le][c][bb * N1 + i];
+            tv[c] = s2;
         }
     __syncthreads();
     if (act)
@@ -159,12 +174,13 @@ int transfer_grid(int k, long ne)
 }
 
 template <typename T>
-void launch_transfer_T(int k, const DgArgs& A, int mass_fix, const double* U, T* u, int nxf, hipStream_t st)
+void launch_transfer_T(int k, const DgArgs& A, int mass_fix, const double* U, T* u, int nxf, hipStream_t st,
+                       const double* snrm2, double* Us)
 {
     const dim3 g(transfer_grid(k, A.ne));
-    if (k == 1) timed_launch(transfer_T_kernel<2, T>, g, dim3(TrShape<2>::NTH), st, A, mass_fix, U, u, nxf);
-    else if (k == 2) timed_launch(transfer_T_kernel<3, T>, g, dim3(TrShape<3>::NTH), st, A, mass_fix, U, u, nxf);
-    else timed_launch(transfer_T_kernel<4, T>, g, dim3(TrShape<4>::NTH), st, A, mass_fix, U, u, nxf);
+    if (k == 1) timed_launch(transfer_T_kernel<2, T>, g, dim3(TrShape<2>::NTH), st, A, mass_fix, U, u, nxf, snrm2, Us);
+    else if (k == 2) timed_launch(transfer_T_kernel<3, T>, g, dim3(TrShape<3>::NTH), st, A, mass_fix, U, u, nxf, snrm2, Us);
+    else timed_launch(transfer_T_kernel<4, T>, g, dim3(TrShape<4>::NTH), st, A, mass_fix, U, u, nxf, snrm2, Us);
 }
 
 template <typename T>
@@ -177,8 +193,10 @@ void launch_transfer_Tinv(int k, const DgArgs& A, int mass_fix, const T* u, doub
     if (red.out) launch_finalize(red.partials, (int)g.x, 1, red.out, st);
 }
 
-template void launch_transfer_T<double>(int, const DgArgs&, int, const double*, double*, int, hipStream_t);
-template void launch_transfer_T<float>(int, const DgArgs&, int, const double*, float*, int, hipStream_t);
+template void launch_transfer_T<double>(int, const DgArgs&, int, const double*, double*, int, hipStream_t,
+                                        const double*, double*);
+template void launch_transfer_T<float>(int, const DgArgs&, int, const double*, float*, int, hipStream_t,
+                                       const double*, double*);
 template void launch_transfer_Tinv<double>(int, const DgArgs&, int, const double*, double*, int, Red, hipStream_t);
 template void launch_transfer_Tinv<float>(int, const DgArgs&, int, const float*, double*, int, Red, hipStream_t);
 
