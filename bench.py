@@ -121,8 +121,10 @@ def _sync():
 
 def ensemble_forms():
     """64-member ensemble (k = 2 warm bubbles on 32x16 / 64x32 / 96x48, 5 SDIRK2
-    steps each): batched FP32 multigrid (one arena, concurrent members) against
-    the members run one after another with the plain FP64 multigrid."""
+    steps each) with the FP32 multigrid, lock-step (one batched problem per grid
+    size) and as concurrent single problems from one arena, against the members
+    run one after another with the plain FP64 multigrid."""
+    import torch
     from paper_2505_24504_amd import jfmg, workloads as W
     mem = W.ensemble(seed=4, members=64)
     work = sum(jfmg.num_dofs(d) * n for d, _, n in mem)
@@ -153,7 +155,29 @@ def ensemble_forms():
         el_s += time.perf_counter() - t0
         ok_s += good
         del p
-    return {"ensemble_batched_fp32": {"value": work / el_b, "seconds": el_b, "members_ok": ok_b,
+    # lock-step: the members of each grid size form one batched problem (every kernel
+    # launch covers all of them); the three problems run concurrently
+    groups = {}
+    for d, pert, n in mem:
+        groups.setdefault((d["nx"], d["nz"]), []).append((d, pert, n))
+    b = jfmg.Batch(48 << 30, max_members=len(groups), workers=len(groups), device="cuda:0")
+    gslots = []
+    for ms in groups.values():
+        single = jfmg.Problem(ms[0][0], device="cuda:0")
+        U = torch.cat([single.initial_state(pert) for _, pert, _ in ms])
+        del single
+        gslots.append(b.admit(dict(ms[0][0], batch=len(ms)), ms[0][2], None, U))
+    _sync()
+    t0 = time.perf_counter()
+    b.run()
+    el_l = time.perf_counter() - t0
+    polled_l = [b.poll(s) for s in gslots]
+    b.close()
+    ok_l = sum(len(ms) for ms, (f_, _, st) in zip(groups.values(), polled_l) if f_ and st["status"] == 0)
+    return {"ensemble_lockstep_fp32": {"value": work / el_l, "seconds": el_l, "members_ok": ok_l,
+                                       "groups": [len(ms) for ms in groups.values()],
+                                       "lockstep_gmres_its": [st["gmres_its"] for _, _, st in polled_l]},
+            "ensemble_batched_fp32": {"value": work / el_b, "seconds": el_b, "members_ok": ok_b,
                                       "gmres_its": its_b, "stall_stops": stalls_b},
             "ensemble_serial_fp64": {"value": work / el_s, "seconds": el_s, "members_ok": ok_s,
                                      "gmres_its": its_s, "stall_stops": stalls_s},

@@ -70,6 +70,9 @@ typedef struct {
     double newton_stall;      /* > 0: a stage also ends, successfully, once ||G|| <=
                                  newton_stall ||G^0|| and a Newton step no longer halves
                                  ||G|| (the rounding floor of G lies above rtol); 0: off */
+    int batch;                /* members of a lock-step batch (0 or 1: a single problem);
+                                 see "lock-step batches" below                          */
+    int reserved;
 } jfmg_config;
 
 typedef struct {
@@ -141,6 +144,19 @@ jfmg_status jfmg_jvp(jfmg_problem* p, const double* y, double* out);
 /* z = Q^-1 r = T^-1 MG(0, T r; u_L) (eq. preconditioner); identity when
    precond = 0.  ESTATE without jfmg_linearize. */
 jfmg_status jfmg_mg_apply(jfmg_problem* p, const double* r, double* z);
+
+/* ---- lock-step batches (config.batch = B > 1) ----
+   B members of one configuration (an ensemble: same grid, physics and solver,
+   different states) share one problem: jfmg_workspace_bytes returns B times
+   the bytes of one member, every kernel covers all members in one launch
+   (launch grid z = member), and the Newton and FGMRES iterations run in lock
+   step with per-member norms, forcing terms, Hessenberg matrices and stopping
+   tests; a member that has converged takes no further part (its updates are
+   zero).  Each member's result is bitwise the one it gives as a single problem.
+   State vectors passed in are B * N doubles, members back to back.  Only
+   jfmg_implicit_step and jfmg_initial_state (the same state for every member)
+   accept batched problems; the other calls return EINVAL.  Stats count the
+   lock-step iterations. */
 
 /* One implicit step U^n -> U^{n+1} in place (implicit Euler or SDIRK2), each
    stage by inexact Newton with Eisenstat-Walker forcing and right-preconditioned

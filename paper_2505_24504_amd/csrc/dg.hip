@@ -38,8 +38,15 @@ template <int N1, bool NS, int MODE>
 __global__ void __launch_bounds__(DgShape<N1>::NTH)
 dg_kernel(DgArgs A, const double* __restrict__ U, const double* __restrict__ Y, const double* __restrict__ Ubar,
           double* __restrict__ out, const double* __restrict__ yn2p, const double* __restrict__ ut2p, int eps_mode,
-          double adt, Red red)
+          double adt, Red red, long ms)
 {
+    U = mbr(U, ms);
+    Y = mbr(Y, ms);
+    Ubar = mbr(Ubar, ms);
+    out = mbr(out, ms);
+    yn2p = mbr(yn2p, ms);
+    ut2p = mbr(ut2p, ms);
+    red = mbr(red, ms);
     constexpr int NP = DgShape<N1>::NP, NTH = DgShape<N1>::NTH, EPB = DgShape<N1>::EPB;
     constexpr int NSt = (MODE == 3) ? 2 : 1;
     __shared__ double sS[NSt][EPB][4][NP];
@@ -341,31 +348,32 @@ int dg_grid(int k, long ne)
 template <int N1, bool NS>
 static void launch_dg_n(int mode, const DgArgs& A, const double* U, const double* Y, const double* Ubar,
                         double* out, const double* yn2, const double* ut2, int eps_mode, double adt, Red red,
-                        hipStream_t st)
+                        hipStream_t st, const Mb& mb)
 {
-    const dim3 grid(dg_grid(N1 - 1, A.ne)), block(DgShape<N1>::NTH);
+    const dim3 grid(dg_grid(N1 - 1, A.ne), 1, mb.n), block(DgShape<N1>::NTH);
     if (mode == 2 && red.out) {
-        timed_launch(dg_kernel<N1, NS, 2>, grid, block, st, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red);
-        launch_finalize(red.partials, (int)grid.x, 1, red.out, st);
+        timed_launch(dg_kernel<N1, NS, 2>, grid, block, st, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, mb.ms);
+        launch_finalize(red.partials, (int)grid.x, 1, red.out, st, Gate{}, mb);
         return;
     }
     switch (mode) {
-    case 0: timed_launch(dg_kernel<N1, NS, 0>, grid, block, st, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red); break;
-    case 1: timed_launch(dg_kernel<N1, NS, 1>, grid, block, st, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red); break;
-    case 2: timed_launch(dg_kernel<N1, NS, 2>, grid, block, st, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red); break;
-    default: timed_launch(dg_kernel<N1, NS, 3>, grid, block, st, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red); break;
+    case 0: timed_launch(dg_kernel<N1, NS, 0>, grid, block, st, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, mb.ms); break;
+    case 1: timed_launch(dg_kernel<N1, NS, 1>, grid, block, st, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, mb.ms); break;
+    case 2: timed_launch(dg_kernel<N1, NS, 2>, grid, block, st, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, mb.ms); break;
+    default: timed_launch(dg_kernel<N1, NS, 3>, grid, block, st, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, mb.ms); break;
     }
 }
 
 void launch_dg(int k, bool ns, int mode, const DgArgs& A, const double* U, const double* Y, const double* Ubar,
-               double* out, const double* yn2, const double* ut2, int eps_mode, double adt, Red red, hipStream_t st)
+               double* out, const double* yn2, const double* ut2, int eps_mode, double adt, Red red, hipStream_t st,
+               const Mb& mb)
 {
-    if (k == 1) { if (ns) launch_dg_n<2, true>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st);
-                  else launch_dg_n<2, false>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st); }
-    else if (k == 2) { if (ns) launch_dg_n<3, true>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st);
-                       else launch_dg_n<3, false>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st); }
-    else { if (ns) launch_dg_n<4, true>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st);
-           else launch_dg_n<4, false>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st); }
+    if (k == 1) { if (ns) launch_dg_n<2, true>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb);
+                  else launch_dg_n<2, false>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb); }
+    else if (k == 2) { if (ns) launch_dg_n<3, true>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb);
+                       else launch_dg_n<3, false>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb); }
+    else { if (ns) launch_dg_n<4, true>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb);
+           else launch_dg_n<4, false>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb); }
 }
 
 // ---------------------------------------------------------------------------
@@ -374,8 +382,9 @@ void launch_dg(int k, bool ns, int mode, const DgArgs& A, const double* U, const
 template <int N1>
 __global__ void __launch_bounds__(256)
 init_kernel(DgArgs A, int shape, double amp, double xc, double zc, double xr, double zr, double aa, double Z,
-            double x0, double z0, double u_mean, double* __restrict__ U)
+            double x0, double z0, double u_mean, double* __restrict__ U, long ms)
 {
+    U = mbr(U, ms);
     constexpr int NP = N1 * N1;
     const long n = A.ne * NP;
     const long i = (long)blockIdx.x * 256 + threadIdx.x;
@@ -405,19 +414,22 @@ init_kernel(DgArgs A, int shape, double amp, double xc, double zc, double xr, do
 }
 
 void launch_initial_state(int k, const DgArgs& A, int shape, double amp, double xc, double zc, double xr, double zr,
-                          double a, double Z, double x0, double z0, double u_mean, double* U, hipStream_t st)
+                          double a, double Z, double x0, double z0, double u_mean, double* U, hipStream_t st,
+                          const Mb& mb)
 {
     const long n = A.ne * (k + 1) * (k + 1);
-    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
-    if (k == 1) init_kernel<2><<<grid, block, 0, st>>>(A, shape, amp, xc, zc, xr, zr, a, Z, x0, z0, u_mean, U);
-    else if (k == 2) init_kernel<3><<<grid, block, 0, st>>>(A, shape, amp, xc, zc, xr, zr, a, Z, x0, z0, u_mean, U);
-    else init_kernel<4><<<grid, block, 0, st>>>(A, shape, amp, xc, zc, xr, zr, a, Z, x0, z0, u_mean, U);
+    const dim3 grid((unsigned)((n + 255) / 256), 1, mb.n), block(256);
+    if (k == 1) init_kernel<2><<<grid, block, 0, st>>>(A, shape, amp, xc, zc, xr, zr, a, Z, x0, z0, u_mean, U, mb.ms);
+    else if (k == 2) init_kernel<3><<<grid, block, 0, st>>>(A, shape, amp, xc, zc, xr, zr, a, Z, x0, z0, u_mean, U, mb.ms);
+    else init_kernel<4><<<grid, block, 0, st>>>(A, shape, amp, xc, zc, xr, zr, a, Z, x0, z0, u_mean, U, mb.ms);
 }
 
 // sum over all nodes and components of (U' + Ubar)^2
 template <int N1>
-__global__ void __launch_bounds__(256) norm_total_kernel(DgArgs A, const double* __restrict__ U, Red red)
+__global__ void __launch_bounds__(256) norm_total_kernel(DgArgs A, const double* __restrict__ U, Red red, long ms)
 {
+    U = mbr(U, ms);
+    red = mbr(red, ms);
     constexpr int NP = N1 * N1;
     const long n = A.ne * NP;
     double s = 0.0;
@@ -440,14 +452,14 @@ int norm_total_grid(long n)
     return (int)(b < 1024 ? b : 1024);
 }
 
-void launch_norm2_total(int k, const DgArgs& A, const double* U, Red red, hipStream_t st)
+void launch_norm2_total(int k, const DgArgs& A, const double* U, Red red, hipStream_t st, const Mb& mb)
 {
     const long n = A.ne * (k + 1) * (k + 1);
-    const dim3 grid(norm_total_grid(n)), block(256);
-    if (k == 1) norm_total_kernel<2><<<grid, block, 0, st>>>(A, U, red);
-    else if (k == 2) norm_total_kernel<3><<<grid, block, 0, st>>>(A, U, red);
-    else norm_total_kernel<4><<<grid, block, 0, st>>>(A, U, red);
-    launch_finalize(red.partials, (int)grid.x, 1, red.out, st);
+    const dim3 grid(norm_total_grid(n), 1, mb.n), block(256);
+    if (k == 1) norm_total_kernel<2><<<grid, block, 0, st>>>(A, U, red, mb.ms);
+    else if (k == 2) norm_total_kernel<3><<<grid, block, 0, st>>>(A, U, red, mb.ms);
+    else norm_total_kernel<4><<<grid, block, 0, st>>>(A, U, red, mb.ms);
+    launch_finalize(red.partials, (int)grid.x, 1, red.out, st, Gate{}, mb);
 }
 
 }  // namespace jfmg

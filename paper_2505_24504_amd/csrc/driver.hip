@@ -309,6 +309,7 @@ struct jfmg_problem {
     double *Un, *Ubar, *Uk, *G, *delta, *tmp1, *tmp2, *Ulin;
     double *V, *Z;
     int m;
+    Mb mb;   // members of a lock-step batch (1 for a single problem) and their byte stride
     // kernel-class timing (HIP events on st), used by the benchmark
     struct Pend { int cls; hipEvent_t a, b; double bytes; };
     struct Prof {
@@ -415,8 +416,11 @@ jfmg_status check_launch(jfmg_problem* p)
     return JFMG_OK;
 }
 
+int members_of(const jfmg_config& c) { return c.batch > 1 ? c.batch : 1; }
+
 jfmg_status validate(const jfmg_config& c, Key& key, std::string& msg)
 {
+    if (c.batch < 0 || c.batch > 4096) { msg = "batch must be in 0..4096"; return JFMG_EINVAL; }
     if (c.k < 1 || c.k > 3) { msg = "k must be 1, 2 or 3"; return JFMG_EINVAL; }
     if (c.nx < 1 || c.nz < 1) { msg = "nx, nz must be positive"; return JFMG_EINVAL; }
     if (!(c.x1 > c.x0) || !(c.z1 > c.z0)) { msg = "empty domain"; return JFMG_EINVAL; }
@@ -490,17 +494,26 @@ size_t layout(const jfmg_config& c, char* base, F&& bind)
         nzl /= 2;
     }
     (void)nfv;
-    return cv.off + 256;
+    return (cv.off + 255) & ~size_t(255);   // bytes of one member
 }
 
 Red red_at(jfmg_problem* p, int slot) { return Red{p->partials, p->scal + slot}; }
+
+// copy `bytes` of every member from src to dst (both inside the members' workspaces)
+hipError_t copy_members(jfmg_problem* p, void* dst, const void* src, size_t bytes)
+{
+    return hipMemcpy2DAsync(dst, (size_t)p->mb.ms, src, (size_t)p->mb.ms, bytes, (size_t)p->mb.n,
+                            hipMemcpyDeviceToDevice, p->st);
+}
 Red no_red() { return Red{nullptr, nullptr}; }
 double* fvpart(jfmg_problem* p, int l, int bi) { return p->fvpart + (FVP_PER_LEVEL * l + bi) * p->fvp; }
 
-// read `count` device scalars starting at `slot` (synchronizes the stream)
+// read `count` device scalars starting at `slot` of every member into
+// out[member * count + i] (synchronizes the stream)
 jfmg_status read_scalars(jfmg_problem* p, int slot, int count, double* out)
 {
-    HIPCHK(p, hipMemcpyAsync(out, p->scal + slot, sizeof(double) * count, hipMemcpyDeviceToHost, p->st));
+    HIPCHK(p, hipMemcpy2DAsync(out, sizeof(double) * count, p->scal + slot, (size_t)p->mb.ms, sizeof(double) * count,
+                               (size_t)p->mb.n, hipMemcpyDeviceToHost, p->st));
     HIPCHK(p, hipStreamSynchronize(p->st));
     p->syncs++;
     prof_flush(p);
@@ -543,15 +556,17 @@ template <typename T> FvArgs<T> fv_args(const jfmg_problem* p, int l)
 template <typename T> jfmg_status linearize_t(jfmg_problem* p, const double* U, double adt)
 {
     hipStream_t st = p->st;
-    if (U != p->Ulin) HIPCHK(p, hipMemcpyAsync(p->Ulin, U, sizeof(double) * p->N, hipMemcpyDeviceToDevice, st));
+    if (U != p->Ulin) HIPCHK(p, copy_members(p, p->Ulin, U, sizeof(double) * p->N));
     p->adt = adt;
-    launch_norm2_total(p->cfg.k, p->A, p->Ulin, red_at(p, S_UTOT), st);
-    launch_transfer_T<T>(p->cfg.k, p->A, p->cfg.mass_fix, p->Ulin, (T*)p->lev[0].u, p->lev[0].nx, st);
-    for (int l = 0; l + 1 < p->nlev; ++l) FvLaunch<T>::restrict_(fv_args<T>(p, l), (const T*)p->lev[l].u, (T*)p->lev[l + 1].u, st);
+    launch_norm2_total(p->cfg.k, p->A, p->Ulin, red_at(p, S_UTOT), st, p->mb);
+    launch_transfer_T<T>(p->cfg.k, p->A, p->cfg.mass_fix, p->Ulin, (T*)p->lev[0].u, p->lev[0].nx, st, nullptr, nullptr,
+                         p->mb);
+    for (int l = 0; l + 1 < p->nlev; ++l)
+        FvLaunch<T>::restrict_(fv_args<T>(p, l), (const T*)p->lev[l].u, (T*)p->lev[l + 1].u, st, p->mb);
     for (int l = 0; l < p->nlev; ++l) {
         ProfScope ps(p, JFMG_K_FV_LINEARIZE, 2.0 * 4.0 * p->lev[l].nc * sizeof(T));
         FvLaunch<T>::lin_level(fv_args<T>(p, l), (const T*)p->lev[l].u, (T*)p->lev[l].F0, Red{p->partials, nullptr},
-                               p->scal + S_LEV + 4 * l, adt, p->cfg.pseudo_cfl, st);
+                               p->scal + S_LEV + 4 * l, adt, p->cfg.pseudo_cfl, st, p->mb);
     }
     p->have_lin = 1;
     return check_launch(p);
@@ -599,7 +614,7 @@ template <typename T> struct Mg {
                 p->xcnt[l][out] = FvLaunch<T>::stage(
                     A, (const T*)L.u, (const T*)L.F0, (const T*)L.buf[prev], x0, (const T*)L.b, (T*)L.buf[out],
                     fvpart(p, l, prev), p->xcnt[l][prev], p->scal + S_LEV + 4 * l, alpha[j], p->adt, zero,
-                    Red{fvpart(p, l, out), nullptr}, p->st);
+                    Red{fvpart(p, l, out), nullptr}, p->st, p->mb);
                 if (!zero) p->mv_count[l]++;
                 prev = out;
             }
@@ -621,7 +636,7 @@ template <typename T> struct Mg {
             ProfScope ps(p, JFMG_K_FV_DEFECT, (s.xzero[l] ? 1.25 : 4.25) * 4.0 * L.nc * sizeof(T));
             FvLaunch<T>::defect_restrict(A, (const T*)L.u, (const T*)L.F0, (const T*)L.buf[s.xi[l]], (const T*)L.b,
                                          (T*)C.b, fvpart(p, l, s.xi[l]), p->xcnt[l][s.xi[l]],
-                                         p->scal + S_LEV + 4 * l, p->adt, s.xzero[l] ? 1 : 0, p->st);
+                                         p->scal + S_LEV + 4 * l, p->adt, s.xzero[l] ? 1 : 0, p->st, p->mb);
             if (!s.xzero[l]) p->mv_count[l]++;
             s.xzero[l + 1] = true;
             s.xi[l + 1] = 0;
@@ -629,11 +644,11 @@ template <typename T> struct Mg {
             if (!s.xzero[l + 1]) {
                 if (s.xzero[l]) {
                     // x = 0 - P v: materialize the zero vector first
-                    launch_zero(L.buf[s.xi[l]], sizeof(T) * 4 * L.nc, p->st);
+                    launch_zero(L.buf[s.xi[l]], sizeof(T) * 4 * L.nc, p->st, p->mb);
                 }
                 ProfScope ps2(p, JFMG_K_FV_PROLONG, 2.25 * 4.0 * L.nc * sizeof(T));
                 p->xcnt[l][s.xi[l]] = FvLaunch<T>::prolong_correct(A, (T*)L.buf[s.xi[l]], (const T*)C.buf[s.xi[l + 1]],
-                                                                   Red{fvpart(p, l, s.xi[l]), nullptr}, p->st);
+                                                                   Red{fvpart(p, l, s.xi[l]), nullptr}, p->st, p->mb);
                 s.xzero[l] = false;
             }
         }
@@ -649,7 +664,7 @@ template <typename T> struct Mg {
         s.xzero[0] = true;
         cycle(0);
         Level& L = p->lev[0];
-        if (s.xzero[0]) launch_zero(L.buf[s.xi[0]], sizeof(T) * 4 * L.nc, p->st);
+        if (s.xzero[0]) launch_zero(L.buf[s.xi[0]], sizeof(T) * 4 * L.nc, p->st, p->mb);
         return (T*)L.buf[s.xi[0]];
     }
 };
@@ -661,12 +676,13 @@ template <typename T> jfmg_status mg_apply_t(jfmg_problem* p, double* r, double*
     Level& L = p->lev[0];
     {
         ProfScope ps(p, JFMG_K_TRANSFER_T, (double)p->N * (8 + sizeof(T)) + (rnrm2 ? 8.0 * p->N : 0.0));
-        launch_transfer_T<T>(p->cfg.k, p->A, p->cfg.mass_fix, r, (T*)L.b, L.nx, p->st, rnrm2, rnrm2 ? r : nullptr);
+        launch_transfer_T<T>(p->cfg.k, p->A, p->cfg.mass_fix, r, (T*)L.b, L.nx, p->st, rnrm2, rnrm2 ? r : nullptr,
+                             p->mb);
     }
     Mg<T> mg{p};
     T* x = mg.run();
     ProfScope ps(p, JFMG_K_TRANSFER_TINV, (double)p->N * (8 + sizeof(T)));
-    launch_transfer_Tinv<T>(p->cfg.k, p->A, p->cfg.mass_fix, x, z, L.nx, red_at(p, zslot), p->st);
+    launch_transfer_Tinv<T>(p->cfg.k, p->A, p->cfg.mass_fix, x, z, L.nx, red_at(p, zslot), p->st, p->mb);
     return check_launch(p);
 }
 
@@ -675,9 +691,9 @@ template <typename T> jfmg_status mg_apply_t(jfmg_problem* p, double* r, double*
 jfmg_status precond(jfmg_problem* p, double* r, double* z, int zslot, const double* rnrm2 = nullptr)
 {
     if (!p->cfg.precond) {
-        if (rnrm2) launch_scale(r, r, p->N, rnrm2, p->st);
-        HIPCHK(p, hipMemcpyAsync(z, r, sizeof(double) * p->N, hipMemcpyDeviceToDevice, p->st));
-        launch_norm2(z, p->N, red_at(p, zslot), p->st);
+        if (rnrm2) launch_scale(r, r, p->N, rnrm2, p->st, 1.0, p->mb);
+        HIPCHK(p, copy_members(p, z, r, sizeof(double) * p->N));
+        launch_norm2(z, p->N, red_at(p, zslot), p->st, p->mb);
         return check_launch(p);
     }
     return p->prec == 32 ? mg_apply_t<float>(p, r, z, zslot, rnrm2) : mg_apply_t<double>(p, r, z, zslot, rnrm2);
@@ -688,7 +704,7 @@ void jvp_slot(jfmg_problem* p, const double* y, double* out, int yslot)
 {
     ProfScope ps(p, JFMG_K_DG_JVP, 3.0 * p->N * 8);
     launch_dg(p->cfg.k, p->cfg.physics == 1, 3, p->A, p->Ulin, y, nullptr, out, p->scal + yslot, p->scal + S_UTOT,
-              p->cfg.fd_eps_mode, p->adt, no_red(), p->st);
+              p->cfg.fd_eps_mode, p->adt, no_red(), p->st, p->mb);
     p->jvp_count++;
 }
 
@@ -698,16 +714,15 @@ jfmg_status stage_residual(jfmg_problem* p, const double* U, const double* Ubar,
     {
         ProfScope ps(p, JFMG_K_DG_RESIDUAL, 3.0 * p->N * 8);
         launch_dg(p->cfg.k, p->cfg.physics == 1, 2, p->A, U, nullptr, Ubar, G, nullptr, nullptr, 0, adt, red_at(p, S_G),
-                  p->st);
+                  p->st, p->mb);
     }
     p->lh_count++;
     jfmg_status s = check_launch(p);
     if (s) return s;
-    if (nrm) {
-        double v;
-        s = read_scalars(p, S_G, 1, &v);
+    if (nrm) {   // one norm per member
+        s = read_scalars(p, S_G, 1, nrm);
         if (s) return s;
-        *nrm = std::sqrt(v);
+        for (int b = 0; b < p->mb.n; ++b) nrm[b] = std::sqrt(nrm[b]);
     }
     return JFMG_OK;
 }
@@ -742,14 +757,14 @@ jfmg_status iter_ops(jfmg_problem* p, int j)
     const int nv = j + 1;
     const double md = (j + 2.0) * N * 8, up = (j + 3.0) * N * 8;
     const Gate reorth{p->scal + S_W1, p->scal + S_H1 + nv, REORTH_TAU * REORTH_TAU};
-    { ProfScope ps(p, JFMG_K_MULTIDOT, md); launch_multidot(w, p->V, N, nv, 1, N, Gate{}, red_at(p, S_H1), st); }
-    { ProfScope ps(p, JFMG_K_UPDATE, up); launch_update(w, p->V, N, nv, N, p->scal + S_H1, red_at(p, S_W1), st); }
-    launch_multidot(w, p->V, N, nv, 0, N, reorth, red_at(p, S_H2), st);
-    launch_update(w, p->V, N, nv, N, p->scal + S_H2, Red{p->partials, nullptr}, st, reorth);
+    { ProfScope ps(p, JFMG_K_MULTIDOT, md); launch_multidot(w, p->V, N, nv, 1, N, Gate{}, red_at(p, S_H1), st, p->mb); }
+    { ProfScope ps(p, JFMG_K_UPDATE, up); launch_update(w, p->V, N, nv, N, p->scal + S_H1, red_at(p, S_W1), st, Gate{}, p->mb); }
+    launch_multidot(w, p->V, N, nv, 0, N, reorth, red_at(p, S_H2), st, p->mb);
+    launch_update(w, p->V, N, nv, N, p->scal + S_H2, Red{p->partials, nullptr}, st, reorth, p->mb);
     // ||w||^2 (of whichever pass ran last), and the scalar block h1, h2, ||w||^2 of
     // iteration j to pinned host memory
     launch_finalize_publish(p->partials, la_blocks(N), p->scal + S_W, p->scal + S_H1, S_HB, S_W - S_H1,
-                            p->hpin + (size_t)j * S_HB, reorth, p->scal + S_W1, st);
+                            p->hpin + (size_t)j * S_HB, reorth, p->scal + S_W1, st, p->mb, (long)S_HB * p->m);
     return check_launch(p);
 }
 
@@ -816,28 +831,53 @@ jfmg_status run_iter(jfmg_problem* p, int j)
 // Right-preconditioned FGMRES(m) for G'(U) delta = -G, CGS2 Arnoldi on device,
 // Givens rotations on the host; U += delta on success.
 // ---------------------------------------------------------------------------
-jfmg_status fgmres(jfmg_problem* p, const double* G, double gnorm, double tol_abs, double* U, int* its_out)
+// Members of a lock-step batch run the same iterations; each member's
+// Hessenberg column is read from its own pinned block and a member stops
+// taking part (its coefficients stay 0, so its delta is no longer changed)
+// once it has converged.  `active` marks the members that solve at all.
+jfmg_status fgmres(jfmg_problem* p, const double* G, const std::vector<double>& gnorm, const std::vector<double>& tol,
+                   const std::vector<char>& active, double* U, int* its_out)
 {
     const long N = p->N;
-    const int m = p->m;
+    const int m = p->m, B = p->mb.n;
     hipStream_t st = p->st;
-    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), y(m);
-    double beta = gnorm;
-    int its = 0;
-    // V_0 = -G / beta
-    launch_axpby(p->V, -1.0 / beta, G, 0.0, G, N, st);
-    launch_zero(p->delta, sizeof(double) * N, st);
-    jfmg_status status = JFMG_ENOCONV;
-    for (int cyc = 0; cyc <= p->cfg.gmres_max_restarts; ++cyc) {
-        std::fill(g.begin(), g.end(), 0.0);
-        g[0] = beta;
+    struct Member {
+        std::vector<double> H, cs, sn, g, y;
+        double beta = 0.0;
+        bool done = false, conv = false;
         int jend = 0;
-        bool conv = false;
+    };
+    std::vector<Member> M(B);
+    int left = 0;
+    for (int b = 0; b < B; ++b) {
+        Member& x = M[b];
+        x.H.assign((size_t)(m + 1) * m, 0.0);
+        x.cs.assign(m, 0.0);
+        x.sn.assign(m, 0.0);
+        x.g.assign(m + 1, 0.0);
+        x.y.assign(m, 0.0);
+        x.beta = gnorm[b];
+        x.done = !active[b];
+        left += !x.done;
+    }
+    int its = 0;
+    // V_0 = -G / ||G|| (||G||^2 of each member in slot S_G)
+    launch_scale(p->V, G, N, p->scal + S_G, st, -1.0, p->mb);
+    launch_zero(p->delta, sizeof(double) * N, st, p->mb);
+    std::vector<double> ybuf((size_t)B * m), r2(B);
+    jfmg_status status = left ? JFMG_ENOCONV : JFMG_OK;
+    for (int cyc = 0; left && cyc <= p->cfg.gmres_max_restarts; ++cyc) {
+        for (Member& x : M) {
+            std::fill(x.g.begin(), x.g.end(), 0.0);
+            x.g[0] = x.beta;
+            x.jend = 0;
+            x.conv = false;
+        }
         // Iteration j+1 is issued before the host looks at iteration j's
-        // Hessenberg column, so the readback round trip overlaps GPU work; when
+        // Hessenberg columns, so the readback round trip overlaps GPU work; when
         // iteration j converges the speculative iteration's output is unused.
         auto issue = [&](int j) -> jfmg_status {
-            jfmg_status s = run_iter(p, j);   // ends by publishing its scalars to hpin[j]
+            jfmg_status s = run_iter(p, j);   // ends by publishing its scalars to hpin
             if (s) return s;
             HIPCHK(p, hipEventRecord(p->hev[j], st));
             return JFMG_OK;
@@ -851,98 +891,145 @@ jfmg_status fgmres(jfmg_problem* p, const double* G, double gnorm, double tol_ab
             }
             HIPCHK(p, hipEventSynchronize(p->hev[j]));
             p->syncs++;
-            const double* hb = p->hpin + (size_t)j * S_HB;
-            for (int i = 0; i <= j; ++i) H[i * m + j] = hb[i] + hb[(S_H2 - S_H1) + i];
-            const double hn = std::sqrt(hb[S_W - S_H1]);
-            H[(j + 1) * m + j] = hn;
-            for (int i = 0; i < j; ++i) {
-                const double a = H[i * m + j], b = H[(i + 1) * m + j];
-                H[i * m + j] = cs[i] * a + sn[i] * b;
-                H[(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
-            }
-            const double a = H[j * m + j], b = H[(j + 1) * m + j];
-            const double rr = std::sqrt(a * a + b * b);
-            cs[j] = a / rr;
-            sn[j] = b / rr;
-            H[j * m + j] = rr;
-            H[(j + 1) * m + j] = 0.0;
-            g[j + 1] = -sn[j] * g[j];
-            g[j] = cs[j] * g[j];
             ++its;
-            jend = j + 1;
-            if (!std::isfinite(g[j + 1]) || !std::isfinite(hn)) {
-                *its_out = its;
-                return fail(p, JFMG_ENONFINITE, "non-finite value in the Arnoldi process");
+            bool all_conv = true;
+            for (int mb = 0; mb < B; ++mb) {
+                Member& x = M[mb];
+                if (x.done || x.conv) continue;
+                std::vector<double>& H = x.H;
+                const double* hb = p->hpin + ((size_t)mb * m + j) * S_HB;
+                for (int i = 0; i <= j; ++i) H[i * m + j] = hb[i] + hb[(S_H2 - S_H1) + i];
+                const double hn = std::sqrt(hb[S_W - S_H1]);
+                H[(j + 1) * m + j] = hn;
+                for (int i = 0; i < j; ++i) {
+                    const double a = H[i * m + j], b = H[(i + 1) * m + j];
+                    H[i * m + j] = x.cs[i] * a + x.sn[i] * b;
+                    H[(i + 1) * m + j] = -x.sn[i] * a + x.cs[i] * b;
+                }
+                const double a = H[j * m + j], b = H[(j + 1) * m + j];
+                const double rr = std::sqrt(a * a + b * b);
+                x.cs[j] = a / rr;
+                x.sn[j] = b / rr;
+                H[j * m + j] = rr;
+                H[(j + 1) * m + j] = 0.0;
+                x.g[j + 1] = -x.sn[j] * x.g[j];
+                x.g[j] = x.cs[j] * x.g[j];
+                x.jend = j + 1;
+                if (!std::isfinite(x.g[j + 1]) || !std::isfinite(hn)) {
+                    *its_out = its;
+                    return fail(p, JFMG_ENONFINITE, "non-finite value in the Arnoldi process");
+                }
+                if (std::fabs(x.g[j + 1]) <= tol[mb] || hn == 0.0) x.conv = true;
+                else all_conv = false;
             }
-            if (std::fabs(g[j + 1]) <= tol_abs || hn == 0.0) { conv = true; break; }
+            if (all_conv) break;
         }
-        for (int i = jend - 1; i >= 0; --i) {
-            double s = g[i];
-            for (int t = i + 1; t < jend; ++t) s -= H[i * m + t] * y[t];
-            y[i] = s / H[i * m + i];
+        int jmax = 0;
+        std::fill(ybuf.begin(), ybuf.end(), 0.0);
+        for (int mb = 0; mb < B; ++mb) {
+            Member& x = M[mb];
+            if (x.done) continue;
+            for (int i = x.jend - 1; i >= 0; --i) {
+                double s = x.g[i];
+                for (int t = i + 1; t < x.jend; ++t) s -= x.H[i * m + t] * x.y[t];
+                x.y[i] = s / x.H[i * m + i];
+            }
+            std::copy(x.y.begin(), x.y.begin() + x.jend, ybuf.begin() + (size_t)mb * m);
+            jmax = std::max(jmax, x.jend);
         }
-        HIPCHK(p, hipMemcpyAsync(p->scal + S_Yc, y.data(), sizeof(double) * jend, hipMemcpyHostToDevice, st));
-        launch_lincomb(p->delta, p->delta, p->Z, N, jend, N, p->scal + S_Yc, st);
+        if (jmax > 0) {
+            HIPCHK(p, hipMemcpy2DAsync(p->scal + S_Yc, (size_t)p->mb.ms, ybuf.data(), sizeof(double) * m,
+                                       sizeof(double) * jmax, (size_t)B, hipMemcpyHostToDevice, st));
+            launch_lincomb(p->delta, p->delta, p->Z, N, jmax, N, p->scal + S_Yc, st, p->mb);
+        }
         prof_flush(p);
-        if (conv) { status = JFMG_OK; break; }
+        for (Member& x : M)
+            if (!x.done && x.conv) { x.done = true; --left; }
+        if (!left) { status = JFMG_OK; break; }
         if (cyc == p->cfg.gmres_max_restarts) break;
-        // restart from the true residual r = -G - G' delta
-        launch_norm2(p->delta, N, red_at(p, S_Y), st);
+        // restart the others from the true residual r = -G - G' delta
+        launch_norm2(p->delta, N, red_at(p, S_Y), st, p->mb);
         jvp_slot(p, p->delta, p->tmp2, S_Y);
-        launch_axpby(p->tmp2, -1.0, G, -1.0, p->tmp2, N, st);
-        launch_norm2(p->tmp2, N, red_at(p, S_R), st);
-        double r2;
-        jfmg_status s = read_scalars(p, S_R, 1, &r2);
+        launch_axpby(p->tmp2, -1.0, G, -1.0, p->tmp2, N, st, p->mb);
+        launch_norm2(p->tmp2, N, red_at(p, S_R), st, p->mb);
+        jfmg_status s = read_scalars(p, S_R, 1, r2.data());
         if (s) return s;
-        beta = std::sqrt(r2);
-        if (!std::isfinite(beta)) return fail(p, JFMG_ENONFINITE, "non-finite restart residual");
-        if (beta <= tol_abs) { status = JFMG_OK; break; }
-        launch_axpby(p->V, 1.0 / beta, p->tmp2, 0.0, p->tmp2, N, st);
+        for (int mb = 0; mb < B; ++mb) {
+            Member& x = M[mb];
+            if (x.done) continue;
+            x.beta = std::sqrt(r2[mb]);
+            if (!std::isfinite(x.beta)) return fail(p, JFMG_ENONFINITE, "non-finite restart residual");
+            if (x.beta <= tol[mb]) { x.done = true; --left; }
+        }
+        if (!left) { status = JFMG_OK; break; }
+        launch_scale(p->V, p->tmp2, N, p->scal + S_R, st, 1.0, p->mb);   // V_0 = r / ||r||
     }
     *its_out = its;
     if (status != JFMG_OK) return fail(p, JFMG_ENOCONV, "FGMRES did not reach its tolerance");
-    launch_axpby(U, 1.0, U, 1.0, p->delta, N, st);
+    launch_axpby(U, 1.0, U, 1.0, p->delta, N, st, p->mb);
     return check_launch(p);
 }
 
-// Inexact Newton for G(U) = U - adt f(U) - Ubar = 0 from U^0 = Ubar; result in p->Uk
+// Inexact Newton for G(U) = U - adt f(U) - Ubar = 0 from U^0 = Ubar; result in
+// p->Uk.  The members of a batch iterate in lock step; a member whose test is
+// met takes no further part (its updates are zero).
 jfmg_status newton_stage(jfmg_problem* p, const double* Ubar, double adt, jfmg_stats* st)
 {
     const jfmg_config& c = p->cfg;
-    HIPCHK(p, hipMemcpyAsync(p->Uk, Ubar, sizeof(double) * p->N, hipMemcpyDeviceToDevice, p->st));
-    double g0;
-    jfmg_status s = stage_residual(p, p->Uk, Ubar, adt, p->G, &g0);
+    const int B = p->mb.n;
+    HIPCHK(p, copy_members(p, p->Uk, Ubar, sizeof(double) * p->N));
+    std::vector<double> g0(B), gk(B), gprev(B), eta(B, c.ew_eta0), tol(B);
+    std::vector<char> active(B, 1);
+    jfmg_status s = stage_residual(p, p->Uk, Ubar, adt, p->G, g0.data());
     if (s) return s;
-    if (st) st->g0_norm = g0;
-    if (!std::isfinite(g0)) return fail(p, JFMG_ENONFINITE, "non-finite initial stage residual");
-    if (g0 == 0.0) { if (st) st->g_norm = 0.0; return JFMG_OK; }
-    double gk = g0, gprev = g0, eta = c.ew_eta0;
-    for (int it = 0; it < c.newton_maxit; ++it) {
-        if (it > 0) {
-            double en = c.ew_gamma * std::pow(gk / gprev, c.ew_alpha);
-            const double safe = c.ew_gamma * std::pow(eta, c.ew_alpha);
-            if (safe > 0.1 && safe > en) en = safe;
-            eta = std::min(en, c.ew_eta_max);
+    int left = 0;
+    for (int b = 0; b < B; ++b) {
+        if (!std::isfinite(g0[b])) return fail(p, JFMG_ENONFINITE, "non-finite initial stage residual");
+        if (g0[b] == 0.0) active[b] = 0;
+        left += active[b];
+    }
+    if (st) {
+        st->g0_norm = *std::max_element(g0.begin(), g0.end());
+        st->g_norm = 0.0;
+    }
+    gk = g0;
+    gprev = g0;
+    for (int it = 0; left && it < c.newton_maxit; ++it) {
+        for (int b = 0; b < B; ++b) {
+            if (it > 0 && active[b]) {
+                double en = c.ew_gamma * std::pow(gk[b] / gprev[b], c.ew_alpha);
+                const double safe = c.ew_gamma * std::pow(eta[b], c.ew_alpha);
+                if (safe > 0.1 && safe > en) en = safe;
+                eta[b] = std::min(en, c.ew_eta_max);
+            }
+            tol[b] = eta[b] * gk[b];
         }
         s = linearize(p, p->Uk, adt);
         if (s) return s;
         int its = 0;
-        s = fgmres(p, p->G, gk, eta * gk, p->Uk, &its);
+        s = fgmres(p, p->G, gk, tol, active, p->Uk, &its);
         if (st) { st->gmres_its += its; st->newton_its++; }
         if (s) return s;
         gprev = gk;
-        s = stage_residual(p, p->Uk, Ubar, adt, p->G, &gk);
+        s = stage_residual(p, p->Uk, Ubar, adt, p->G, gk.data());
         if (s) return s;
-        if (st) st->g_norm = gk;
-        if (!std::isfinite(gk)) return fail(p, JFMG_ENONFINITE, "non-finite stage residual");
-        if (gk < c.newton_rtol * g0) return JFMG_OK;
-        // rounding floor of G: no halving any more although already below newton_stall ||G^0||
-        if (c.newton_stall > 0.0 && gk <= c.newton_stall * g0 && gk > 0.5 * gprev) {
-            if (st) st->stall_stops++;
-            return JFMG_OK;
+        double gmax = 0.0;
+        for (int b = 0; b < B; ++b) {
+            if (!active[b]) continue;
+            if (!std::isfinite(gk[b])) return fail(p, JFMG_ENONFINITE, "non-finite stage residual");
+            gmax = std::max(gmax, gk[b]);
+            if (gk[b] < c.newton_rtol * g0[b]) { active[b] = 0; --left; continue; }
+            // rounding floor of G: no halving any more although already below newton_stall ||G^0||
+            if (c.newton_stall > 0.0 && gk[b] <= c.newton_stall * g0[b] && gk[b] > 0.5 * gprev[b]) {
+                if (st) st->stall_stops++;
+                active[b] = 0;
+                --left;
+            }
         }
+        if (st) st->g_norm = gmax;
     }
-    return fail(p, JFMG_ENOCONV, "Newton did not converge within newton_maxit");
+    if (left) return fail(p, JFMG_ENOCONV, "Newton did not converge within newton_maxit");
+    return JFMG_OK;
 }
 
 }  // namespace
@@ -977,7 +1064,7 @@ jfmg_status jfmg_workspace_bytes(const jfmg_config* cfg, size_t* bytes)
     std::string msg;
     jfmg_status s = validate(*cfg, key, msg);
     if (s) return fail(nullptr, s, msg);
-    *bytes = layout(*cfg, nullptr, [](const char*, void*, size_t) {});
+    *bytes = layout(*cfg, nullptr, [](const char*, void*, size_t) {}) * (size_t)members_of(*cfg);
     return JFMG_OK;
 }
 
@@ -990,7 +1077,8 @@ jfmg_status jfmg_create_problem(const jfmg_config* cfg, void* workspace, size_t 
     std::string msg;
     jfmg_status s = validate(*cfg, key, msg);
     if (s) return fail(nullptr, s, msg);
-    const size_t need = layout(*cfg, nullptr, [](const char*, void*, size_t) {});
+    const size_t member_bytes = layout(*cfg, nullptr, [](const char*, void*, size_t) {});
+    const size_t need = member_bytes * (size_t)members_of(*cfg);
     if (!workspace || ws_bytes < need) return fail(nullptr, JFMG_ENOMEM, "workspace too small");
     if (((uintptr_t)workspace & 255) != 0) return fail(nullptr, JFMG_EINVAL, "workspace must be 256-byte aligned");
 
@@ -1006,6 +1094,7 @@ jfmg_status jfmg_create_problem(const jfmg_config* cfg, void* workspace, size_t 
     p->nlev = cfg->mg_levels;
     p->prec = cfg->mg_precision;
     p->m = cfg->gmres_m;
+    p->mb = Mb{members_of(*cfg), (long)member_bytes};
     p->st = (hipStream_t)hip_stream;
     p->user_st = p->st;
     p->cs = nullptr;
@@ -1122,11 +1211,11 @@ jfmg_status jfmg_create_problem(const jfmg_config* cfg, void* workspace, size_t 
             }
         }
     }
-    e = e ? e : hipMemsetAsync(p->scal, 0, NSCAL * 8, st);
+    for (int b = 0; b < p->mb.n && !e; ++b) e = hipMemsetAsync((char*)p->scal + (size_t)b * p->mb.ms, 0, NSCAL * 8, st);
     e = e ? e : hipStreamSynchronize(st);
     e = e ? e : hipStreamCreateWithFlags(&p->cs, hipStreamNonBlocking);
     // coherent pinned memory: the last kernel of each FGMRES iteration stores its scalars here
-    e = e ? e : hipHostMalloc((void**)&p->hpin, sizeof(double) * S_HB * cfg->gmres_m, hipHostMallocCoherent);
+    e = e ? e : hipHostMalloc((void**)&p->hpin, sizeof(double) * S_HB * cfg->gmres_m * p->mb.n, hipHostMallocCoherent);
     for (int j = 0; j < cfg->gmres_m && !e; ++j) {
         hipEvent_t ev = nullptr;
         e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
@@ -1178,14 +1267,16 @@ jfmg_status jfmg_initial_state(jfmg_problem* p, const jfmg_perturbation* q, doub
 {
     if (!p || !q || !U) return fail(p, JFMG_EINVAL, "null argument");
     if (q->shape < 0 || q->shape > 1) return fail(p, JFMG_EINVAL, "unknown perturbation shape");
+    // every member of a batch gets the same state ([members][N] back to back)
     launch_initial_state(p->cfg.k, p->A, q->shape, q->amp, q->xc, q->zc, q->xr, q->zr, q->a, q->Z, p->cfg.x0,
-                         p->cfg.z0, p->cfg.u_mean, U, p->st);
+                         p->cfg.z0, p->cfg.u_mean, U, p->st, Mb{p->mb.n, (long)(sizeof(double) * p->N)});
     return check_launch(p);
 }
 
 jfmg_status jfmg_residual(jfmg_problem* p, const double* U, double* out, int apply_minv)
 {
     if (!p || !U || !out) return fail(p, JFMG_EINVAL, "null argument");
+    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step and jfmg_initial_state");
     launch_dg(p->cfg.k, p->cfg.physics == 1, apply_minv ? 1 : 0, p->A, U, nullptr, nullptr, out, nullptr, nullptr, 0,
               0.0, no_red(), p->st);
     return check_launch(p);
@@ -1195,18 +1286,21 @@ jfmg_status jfmg_stage_residual(jfmg_problem* p, const double* U, const double* 
                                 double* norm)
 {
     if (!p || !U || !Ubar || !G) return fail(p, JFMG_EINVAL, "null argument");
+    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step and jfmg_initial_state");
     return stage_residual(p, U, Ubar, alpha_dt, G, norm);
 }
 
 jfmg_status jfmg_linearize(jfmg_problem* p, const double* U, double alpha_dt)
 {
     if (!p || !U) return fail(p, JFMG_EINVAL, "null argument");
+    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step and jfmg_initial_state");
     return linearize(p, U, alpha_dt);
 }
 
 jfmg_status jfmg_jvp(jfmg_problem* p, const double* y, double* out)
 {
     if (!p || !y || !out) return fail(p, JFMG_EINVAL, "null argument");
+    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step and jfmg_initial_state");
     if (!p->have_lin) return fail(p, JFMG_ESTATE, "jfmg_jvp needs jfmg_linearize first");
     launch_norm2(y, p->N, red_at(p, S_Y), p->st);
     jvp_slot(p, y, out, S_Y);
@@ -1216,6 +1310,7 @@ jfmg_status jfmg_jvp(jfmg_problem* p, const double* y, double* out)
 jfmg_status jfmg_mg_apply(jfmg_problem* p, const double* r, double* z)
 {
     if (!p || !r || !z) return fail(p, JFMG_EINVAL, "null argument");
+    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step and jfmg_initial_state");
     if (!p->have_lin) return fail(p, JFMG_ESTATE, "jfmg_mg_apply needs jfmg_linearize first");
     return precond(p, const_cast<double*>(r), z, S_TMP);   // r is written only when normalizing
 }
@@ -1231,7 +1326,9 @@ static jfmg_status implicit_step_body(jfmg_problem* p, double* U, jfmg_stats* st
     p->syncs = 0;
     const jfmg_config& c = p->cfg;
     jfmg_status s;
-    hipError_t e = hipMemcpyAsync(p->Un, U, sizeof(double) * p->N, hipMemcpyDeviceToDevice, p->st);
+    // the caller's U holds the members back to back ([members][N])
+    const size_t vb = sizeof(double) * p->N;
+    hipError_t e = hipMemcpy2DAsync(p->Un, (size_t)p->mb.ms, U, vb, vb, (size_t)p->mb.n, hipMemcpyDeviceToDevice, p->st);
     if (e) return fail(p, JFMG_EDEVICE, hipGetErrorString(e));
     if (c.scheme == 0) {
         s = newton_stage(p, p->Un, c.dt, &st);
@@ -1241,15 +1338,15 @@ static jfmg_status implicit_step_body(jfmg_problem* p, double* U, jfmg_stats* st
         if (s == JFMG_OK) {
             // Ubar_2 = U^n + (1 - a) dt f(U_1)
             launch_dg(c.k, c.physics == 1, 1, p->A, p->Uk, nullptr, nullptr, p->tmp1, nullptr, nullptr, 0, 0.0, no_red(),
-                      p->st);
+                      p->st, p->mb);
             p->lh_count++;
-            launch_axpby(p->Ubar, 1.0, p->Un, (1.0 - a) * c.dt, p->tmp1, p->N, p->st);
+            launch_axpby(p->Ubar, 1.0, p->Un, (1.0 - a) * c.dt, p->tmp1, p->N, p->st, p->mb);
             s = check_launch(p);
             if (s == JFMG_OK) s = newton_stage(p, p->Ubar, a * c.dt, &st);
         }
     }
     if (s == JFMG_OK) {
-        e = hipMemcpyAsync(U, p->Uk, sizeof(double) * p->N, hipMemcpyDeviceToDevice, p->st);
+        e = hipMemcpy2DAsync(U, vb, p->Uk, (size_t)p->mb.ms, vb, (size_t)p->mb.n, hipMemcpyDeviceToDevice, p->st);
         if (!e) e = hipStreamSynchronize(p->st);
         if (e) s = fail(p, JFMG_EDEVICE, hipGetErrorString(e));
     } else {
@@ -1283,6 +1380,7 @@ jfmg_status jfmg_implicit_step(jfmg_problem* p, double* U, jfmg_stats* stats)
 jfmg_status jfmg_transfer(jfmg_problem* p, int dir, const void* in, void* out)
 {
     if (!p || !in || !out || (dir != 0 && dir != 1)) return fail(p, JFMG_EINVAL, "bad argument");
+    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step and jfmg_initial_state");
     const int nxf = p->lev[0].nx;
     if (dir == 0) {
         if (p->prec == 32) launch_transfer_T<float>(p->cfg.k, p->A, p->cfg.mass_fix, (const double*)in, (float*)out, nxf, p->st);
@@ -1297,6 +1395,7 @@ jfmg_status jfmg_transfer(jfmg_problem* p, int dir, const void* in, void* out)
 jfmg_status jfmg_restrict(jfmg_problem* p, int fine_level, const void* fine, void* coarse)
 {
     if (!p || !fine || !coarse || fine_level < 0 || fine_level + 1 >= p->nlev) return fail(p, JFMG_EINVAL, "bad argument");
+    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step and jfmg_initial_state");
     if (p->prec == 32) FvLaunch<float>::restrict_(fv_args<float>(p, fine_level), (const float*)fine, (float*)coarse, p->st);
     else FvLaunch<double>::restrict_(fv_args<double>(p, fine_level), (const double*)fine, (double*)coarse, p->st);
     return check_launch(p);
@@ -1305,6 +1404,7 @@ jfmg_status jfmg_restrict(jfmg_problem* p, int fine_level, const void* fine, voi
 jfmg_status jfmg_prolong(jfmg_problem* p, int coarse_level, const void* coarse, void* fine)
 {
     if (!p || !fine || !coarse || coarse_level < 1 || coarse_level >= p->nlev) return fail(p, JFMG_EINVAL, "bad argument");
+    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step and jfmg_initial_state");
     if (p->prec == 32) FvLaunch<float>::prolong(fv_args<float>(p, coarse_level - 1), (const float*)coarse, (float*)fine, p->st);
     else FvLaunch<double>::prolong(fv_args<double>(p, coarse_level - 1), (const double*)coarse, (double*)fine, p->st);
     return check_launch(p);
@@ -1313,6 +1413,7 @@ jfmg_status jfmg_prolong(jfmg_problem* p, int coarse_level, const void* coarse, 
 jfmg_status jfmg_fv_level_state(jfmg_problem* p, int level, void* u)
 {
     if (!p || !u || level < 0 || level >= p->nlev) return fail(p, JFMG_EINVAL, "bad argument");
+    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step and jfmg_initial_state");
     if (!p->have_lin) return fail(p, JFMG_ESTATE, "needs jfmg_linearize first");
     const size_t ts = p->prec == 32 ? 4 : 8;
     HIPCHK(p, hipMemcpyAsync(u, p->lev[level].u, ts * 4 * p->lev[level].nc, hipMemcpyDeviceToDevice, p->st));
@@ -1322,6 +1423,7 @@ jfmg_status jfmg_fv_level_state(jfmg_problem* p, int level, void* u)
 jfmg_status jfmg_fv_dtau(jfmg_problem* p, int level, double* dtau)
 {
     if (!p || !dtau || level < 0 || level >= p->nlev) return fail(p, JFMG_EINVAL, "bad argument");
+    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step and jfmg_initial_state");
     if (!p->have_lin) return fail(p, JFMG_ESTATE, "needs jfmg_linearize first");
     return read_scalars(p, S_LEV + 4 * level + LV_DTAU, 1, dtau);
 }
@@ -1329,6 +1431,7 @@ jfmg_status jfmg_fv_dtau(jfmg_problem* p, int level, double* dtau)
 jfmg_status jfmg_fv_matvec(jfmg_problem* p, int level, const void* x, void* out)
 {
     if (!p || !x || !out || level < 0 || level >= p->nlev) return fail(p, JFMG_EINVAL, "bad argument");
+    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step and jfmg_initial_state");
     if (!p->have_lin) return fail(p, JFMG_ESTATE, "needs jfmg_linearize first");
     const Level& L = p->lev[level];
     if (p->prec == 32) {
@@ -1346,6 +1449,7 @@ jfmg_status jfmg_fv_matvec(jfmg_problem* p, int level, const void* x, void* out)
 jfmg_status jfmg_mg_fv(jfmg_problem* p, const void* b, void* x)
 {
     if (!p || !b || !x) return fail(p, JFMG_EINVAL, "bad argument");
+    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step and jfmg_initial_state");
     if (!p->have_lin) return fail(p, JFMG_ESTATE, "needs jfmg_linearize first");
     const Level& L = p->lev[0];
     const size_t bytes = (p->prec == 32 ? 4 : 8) * 4 * L.nc;

@@ -70,8 +70,17 @@ __global__ void __launch_bounds__(NTH, WPE)
 fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, const T* __restrict__ xp,
                const T* __restrict__ x0, const T* __restrict__ b, T* __restrict__ out,
                const double* __restrict__ xpart, int xcount, double* __restrict__ slots, double alpha_j,
-               double adt, double cfl, Red red)
+               double adt, double cfl, Red red, long ms)
 {
+    u = mbr(u, ms);
+    F0 = mbr(F0, ms);
+    xp = mbr(xp, ms);
+    x0 = mbr(x0, ms);
+    b = mbr(b, ms);
+    out = mbr(out, ms);
+    xpart = mbr(xpart, ms);
+    slots = mbr(slots, ms);
+    red = mbr(red, ms);
     constexpr int NCELL = TX * TZ, HX = TX + 2, HZ = TZ + 2;
     constexpr int NH = HX * HZ, HITEMS = (NH + NTH - 1) / NTH;
     constexpr int NFX = TZ * (TX + 1), NFZ = (TZ + 1) * TX;
@@ -320,8 +329,12 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
 template <typename T>
 __global__ void __launch_bounds__(256)
 fv_stage_zero_kernel(const T* __restrict__ b, T* __restrict__ out, long n, const double* __restrict__ slots,
-                     double alpha_j, Red red)
+                     double alpha_j, Red red, long ms)
 {
+    b = mbr(b, ms);
+    out = mbr(out, ms);
+    slots = mbr(slots, ms);
+    red = mbr(red, ms);
     const T s = (T)(alpha_j * slots[LV_DTAU]);
     double nrm = 0.0;
     for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
@@ -334,8 +347,11 @@ fv_stage_zero_kernel(const T* __restrict__ b, T* __restrict__ out, long n, const
 
 // coarse = R(-b): the defect of x = 0
 template <typename T>
-__global__ void __launch_bounds__(256) fv_restrict_neg_kernel(FvArgs<T> A, const T* __restrict__ f, T* __restrict__ c)
+__global__ void __launch_bounds__(256)
+fv_restrict_neg_kernel(FvArgs<T> A, const T* __restrict__ f, T* __restrict__ c, long ms)
 {
+    f = mbr(f, ms);
+    c = mbr(c, ms);
     const int nxc = A.nxl / 2, nzc = A.nzl / 2;
     const int Ic = blockIdx.x * 64 + (threadIdx.x & 63);
     const int Jc = blockIdx.y * 4 + (threadIdx.x >> 6);
@@ -352,8 +368,11 @@ __global__ void __launch_bounds__(256) fv_restrict_neg_kernel(FvArgs<T> A, const
 // x -= P v (injection) on the fine level, with ||x||^2
 template <typename T>
 __global__ void __launch_bounds__(FV_NTH)
-fv_prolong_correct_kernel(FvArgs<T> A, T* __restrict__ x, const T* __restrict__ v, Red red)
+fv_prolong_correct_kernel(FvArgs<T> A, T* __restrict__ x, const T* __restrict__ v, Red red, long ms)
 {
+    x = mbr(x, ms);
+    v = mbr(v, ms);
+    red = mbr(red, ms);
     const int I = blockIdx.x * FV_TX + (threadIdx.x & (FV_TX - 1));
     const int J = blockIdx.y * FV_TZ + (threadIdx.x / FV_TX);
     double nrm = 0.0;
@@ -371,8 +390,11 @@ fv_prolong_correct_kernel(FvArgs<T> A, T* __restrict__ x, const T* __restrict__ 
 }
 
 template <typename T>
-__global__ void __launch_bounds__(FV_NTH) fv_restrict_kernel(FvArgs<T> A, const T* __restrict__ f, T* __restrict__ c)
+__global__ void __launch_bounds__(FV_NTH)
+fv_restrict_kernel(FvArgs<T> A, const T* __restrict__ f, T* __restrict__ c, long ms)
 {
+    f = mbr(f, ms);
+    c = mbr(c, ms);
     const int nxc = A.nxl / 2, nzc = A.nzl / 2;
     const int Ic = blockIdx.x * FV_TX + (threadIdx.x & (FV_TX - 1));
     const int Jc = blockIdx.y * FV_TZ + (threadIdx.x / FV_TX);
@@ -387,8 +409,11 @@ __global__ void __launch_bounds__(FV_NTH) fv_restrict_kernel(FvArgs<T> A, const 
 }
 
 template <typename T>
-__global__ void __launch_bounds__(FV_NTH) fv_prolong_kernel(FvArgs<T> A, const T* __restrict__ c, T* __restrict__ f)
+__global__ void __launch_bounds__(FV_NTH)
+fv_prolong_kernel(FvArgs<T> A, const T* __restrict__ c, T* __restrict__ f, long ms)
 {
+    c = mbr(c, ms);
+    f = mbr(f, ms);
     const int I = blockIdx.x * FV_TX + (threadIdx.x & (FV_TX - 1));
     const int J = blockIdx.y * FV_TZ + (threadIdx.x / FV_TX);
     if (I >= A.nxl || J >= A.nzl) return;
@@ -399,8 +424,10 @@ __global__ void __launch_bounds__(FV_NTH) fv_prolong_kernel(FvArgs<T> A, const T
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) fv_norm2_kernel(const T* __restrict__ x, long n, Red red)
+__global__ void __launch_bounds__(256) fv_norm2_kernel(const T* __restrict__ x, long n, Red red, long ms)
 {
+    x = mbr(x, ms);
+    red = mbr(red, ms);
     double s = 0.0;
     for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
         const double v = x[i];
@@ -412,8 +439,10 @@ __global__ void __launch_bounds__(256) fv_norm2_kernel(const T* __restrict__ x, 
 // level slots from the LIN partials: ||u + Ubar||, max(|v| + c), pseudo time step
 __global__ void __launch_bounds__(256)
 fv_lin_finalize_kernel(const double* __restrict__ p, int nb, double* __restrict__ slots, double hx, double hz,
-                       double mu, double adt, double cfl)
+                       double mu, double adt, double cfl, long ms)
 {
+    p = mbr(p, ms);
+    slots = mbr(slots, ms);
     __shared__ double sh[4];
     double a = 0.0, m = 0.0;
     for (int i = threadIdx.x; i < nb; i += 256) { a += p[i]; m = fmax(m, p[nb + i]); }
@@ -426,99 +455,99 @@ fv_lin_finalize_kernel(const double* __restrict__ p, int nb, double* __restrict_
     }
 }
 
-static inline dim3 tile_grid(int nx, int nz)
+static inline dim3 tile_grid(int nx, int nz, int members = 1)
 {
-    return dim3((unsigned)((nx + FV_TX - 1) / FV_TX), (unsigned)((nz + FV_TZ - 1) / FV_TZ));
+    return dim3((unsigned)((nx + FV_TX - 1) / FV_TX), (unsigned)((nz + FV_TZ - 1) / FV_TZ), (unsigned)members);
 }
 
 template <typename T, int TX, int TZ, int NTH, int WPE, bool LATE, bool ZREV, int MODE>
 static int tile_launch_shape(const FvArgs<T>& A, const T* u, const T* F0, const T* xp, const T* x0, const T* b,
                              T* out, const double* xpart, int xcount, double* slots, double alpha_j, double adt,
-                             double cfl, Red red, hipStream_t st)
+                             double cfl, Red red, hipStream_t st, const Mb& mb)
 {
-    const dim3 g((unsigned)((A.nxl + TX - 1) / TX), (unsigned)((A.nzl + TZ - 1) / TZ));
+    const dim3 g((unsigned)((A.nxl + TX - 1) / TX), (unsigned)((A.nzl + TZ - 1) / TZ), (unsigned)mb.n);
     timed_launch(fv_tile_kernel<T, TX, TZ, NTH, WPE, LATE, ZREV, MODE>, g, dim3(NTH), st, A, u, F0, xp, x0, b, out, xpart,
-                 xcount, slots, alpha_j, adt, cfl, red);
+                 xcount, slots, alpha_j, adt, cfl, red, mb.ms);
     return (int)(g.x * g.y);
 }
 
 template <typename T, int MODE>
 static int tile_launch(const FvArgs<T>& A, const T* u, const T* F0, const T* xp, const T* x0, const T* b, T* out,
                        const double* xpart, int xcount, double* slots, double alpha_j, double adt, double cfl,
-                       Red red, hipStream_t st)
+                       Red red, hipStream_t st, const Mb& mb)
 {
     if (fv_wide_tile(A.nxl))
         return tile_launch_shape<T, FV_WIDE_TX, FV_WIDE_TZ, FV_WIDE_NTH, FV_WIDE_WPE, FV_WIDE_LATE, FV_WIDE_ZREV, MODE>(
-            A, u, F0, xp, x0, b, out, xpart, xcount, slots, alpha_j, adt, cfl, red, st);
+            A, u, F0, xp, x0, b, out, xpart, xcount, slots, alpha_j, adt, cfl, red, st, mb);
     return tile_launch_shape<T, FV_SMALL_TX, FV_SMALL_TZ, FV_SMALL_NTH, FV_SMALL_WPE, false, FV_SMALL_ZREV, MODE>(
-        A, u, F0, xp, x0, b, out, xpart, xcount, slots, alpha_j, adt, cfl, red, st);
+        A, u, F0, xp, x0, b, out, xpart, xcount, slots, alpha_j, adt, cfl, red, st, mb);
 }
 
 template <typename T>
 void FvLaunch<T>::lin_level(const FvArgs<T>& A, const T* u, T* F0, Red red, double* slots, double adt, double cfl,
-                            hipStream_t st)
+                            hipStream_t st, const Mb& mb)
 {
     const int nb = tile_launch<T, FVM_LIN>(A, u, nullptr, nullptr, nullptr, nullptr, F0, nullptr, 0, slots, 0.0, adt,
-                                           cfl, red, st);
-    fv_lin_finalize_kernel<<<dim3(1), dim3(256), 0, st>>>(red.partials, nb, slots, (double)A.hx, (double)A.hz,
-                                                          (double)A.mu, adt, cfl);
+                                           cfl, red, st, mb);
+    fv_lin_finalize_kernel<<<dim3(1, 1, mb.n), dim3(256), 0, st>>>(red.partials, nb, slots, (double)A.hx,
+                                                                   (double)A.hz, (double)A.mu, adt, cfl, mb.ms);
 }
 template <typename T>
 int FvLaunch<T>::stage(const FvArgs<T>& A, const T* u, const T* F0, const T* xp, const T* x0, const T* b, T* xo,
                        const double* xpart, int xcount, const double* slots, double alpha_j, double adt, int zero,
-                       Red red, hipStream_t st)
+                       Red red, hipStream_t st, const Mb& mb)
 {
     if (zero) {
         const long n = 4 * A.nc;
         const int nb = norm_blocks(n);
-        timed_launch(fv_stage_zero_kernel<T>, dim3(nb), dim3(256), st, b, xo, n, slots, alpha_j, red);
+        timed_launch(fv_stage_zero_kernel<T>, dim3(nb, 1, mb.n), dim3(256), st, b, xo, n, slots, alpha_j, red, mb.ms);
         return nb;
     }
     return tile_launch<T, FVM_STAGE>(A, u, F0, xp, x0, b, xo, xpart, xcount, const_cast<double*>(slots), alpha_j,
-                                     adt, 0.0, red, st);
+                                     adt, 0.0, red, st, mb);
 }
 template <typename T>
 void FvLaunch<T>::matvec(const FvArgs<T>& A, const T* u, const T* F0, const T* x, T* out, const double* xpart,
-                         int xcount, const double* slots, double adt, hipStream_t st)
+                         int xcount, const double* slots, double adt, hipStream_t st, const Mb& mb)
 {
     tile_launch<T, FVM_MATVEC>(A, u, F0, x, nullptr, nullptr, out, xpart, xcount, const_cast<double*>(slots), 0.0,
-                               adt, 0.0, Red{nullptr, nullptr}, st);
+                               adt, 0.0, Red{nullptr, nullptr}, st, mb);
 }
 template <typename T>
 void FvLaunch<T>::defect_restrict(const FvArgs<T>& A, const T* u, const T* F0, const T* x, const T* b, T* rc,
                                   const double* xpart, int xcount, const double* slots, double adt, int zero,
-                                  hipStream_t st)
+                                  hipStream_t st, const Mb& mb)
 {
     if (zero) {
-        const dim3 g((unsigned)((A.nxl / 2 + 63) / 64), (unsigned)((A.nzl / 2 + 3) / 4));
-        timed_launch(fv_restrict_neg_kernel<T>, g, dim3(256), st, A, b, rc);
+        const dim3 g((unsigned)((A.nxl / 2 + 63) / 64), (unsigned)((A.nzl / 2 + 3) / 4), (unsigned)mb.n);
+        timed_launch(fv_restrict_neg_kernel<T>, g, dim3(256), st, A, b, rc, mb.ms);
         return;
     }
     tile_launch<T, FVM_DEFECT>(A, u, F0, x, nullptr, b, rc, xpart, xcount, const_cast<double*>(slots), 0.0, adt, 0.0,
-                               Red{nullptr, nullptr}, st);
+                               Red{nullptr, nullptr}, st, mb);
 }
 template <typename T>
-int FvLaunch<T>::prolong_correct(const FvArgs<T>& Af, T* x, const T* v, Red red, hipStream_t st)
+int FvLaunch<T>::prolong_correct(const FvArgs<T>& Af, T* x, const T* v, Red red, hipStream_t st, const Mb& mb)
 {
-    const dim3 g = tile_grid(Af.nxl, Af.nzl);
-    timed_launch(fv_prolong_correct_kernel<T>, g, dim3(FV_NTH), st, Af, x, v, red);
+    const dim3 g = tile_grid(Af.nxl, Af.nzl, mb.n);
+    timed_launch(fv_prolong_correct_kernel<T>, g, dim3(FV_NTH), st, Af, x, v, red, mb.ms);
     return (int)(g.x * g.y);
 }
 template <typename T>
-void FvLaunch<T>::restrict_(const FvArgs<T>& Af, const T* f, T* c, hipStream_t st)
+void FvLaunch<T>::restrict_(const FvArgs<T>& Af, const T* f, T* c, hipStream_t st, const Mb& mb)
 {
-    fv_restrict_kernel<T><<<tile_grid(Af.nxl / 2, Af.nzl / 2), dim3(FV_NTH), 0, st>>>(Af, f, c);
+    fv_restrict_kernel<T><<<tile_grid(Af.nxl / 2, Af.nzl / 2, mb.n), dim3(FV_NTH), 0, st>>>(Af, f, c, mb.ms);
 }
 template <typename T>
-void FvLaunch<T>::prolong(const FvArgs<T>& Af, const T* c, T* f, hipStream_t st)
+void FvLaunch<T>::prolong(const FvArgs<T>& Af, const T* c, T* f, hipStream_t st, const Mb& mb)
 {
-    fv_prolong_kernel<T><<<tile_grid(Af.nxl, Af.nzl), dim3(FV_NTH), 0, st>>>(Af, c, f);
+    fv_prolong_kernel<T><<<tile_grid(Af.nxl, Af.nzl, mb.n), dim3(FV_NTH), 0, st>>>(Af, c, f, mb.ms);
 }
 template <typename T>
-void FvLaunch<T>::norm2(const T* x, long n, Red red, hipStream_t st)
+void FvLaunch<T>::norm2(const T* x, long n, Red red, hipStream_t st, const Mb& mb)
 {
-    fv_norm2_kernel<T><<<dim3(norm_blocks(n)), dim3(256), 0, st>>>(x, n, red);
-    if (red.out) launch_finalize(red.partials, norm_blocks(n), 1, red.out, st);
+    fv_norm2_kernel<T><<<dim3(norm_blocks(n), 1, mb.n), dim3(256), 0, st>>>(x, n, red, mb.ms);
+    if (red.out) launch_finalize(red.partials, norm_blocks(n), 1, red.out, st, Gate{}, mb);
 }
 bool fv_wide_tile(long nxl) { return nxl >= FV_WIDE_MIN; }
 

@@ -202,6 +202,15 @@ template <int NTH> __device__ __forceinline__ void put_partial(const Red& r, dou
     if (threadIdx.x == 0) r.partials[block_linear()] = s;
 }
 
+// Lock-step batches: member m of a batched problem lives m * ms bytes after
+// member 0 (identical layouts); kernels run with gridDim.z = members and shift
+// every per-member pointer by blockIdx.z * ms (ms = 0 for a single problem).
+template <typename P> __device__ __forceinline__ P* mbr(P* p, long ms)
+{
+    return p ? (P*)((char*)p + (long)blockIdx.z * ms) : p;
+}
+__device__ __forceinline__ Red mbr(Red r, long ms) { return Red{mbr(r.partials, ms), mbr(r.out, ms)}; }
+
 // deterministic sum of n partials, returned to every thread of the block
 template <int NTH> __device__ __forceinline__ double sum_partials(const double* p, int n)
 {

@@ -74,29 +74,36 @@ template <typename T> struct FvArgs {
 // device scalar slots of one FV level (doubles)
 enum { LV_UTOT = 0, LV_LAM = 1, LV_DTAU = 2, LV_NSLOT = 4 };
 
+// Members of a lock-step batch: n members, member m at byte offset m * ms from
+// member 0 in every per-member buffer (device workspace regions of equal layout).
+struct Mb {
+    int n = 1;
+    long ms = 0;
+};
+
 // ---- DG kernels (dg.hip) ----
 // mode 0: <psi,L>  1: M^-1 L  2: G = U - adt M^-1 L - Ubar (+ ||G||^2 into red.out)
 // mode 3: JVP out = Y - adt/eps M^-1 (L(U+eps Y) - L(U)), eps from the device scalars
 //         yn2 = ||Y||^2 and ut2 = ||U + Ubar||^2 (eps_mode 1)
 void launch_dg(int k, bool ns, int mode, const DgArgs& A, const double* U, const double* Y,
                const double* Ubar, double* out, const double* yn2, const double* ut2, int eps_mode,
-               double adt, Red red, hipStream_t st);
+               double adt, Red red, hipStream_t st, const Mb& mb = Mb{});
 int transfer_grid(int k, long ne);
 int dg_grid(int k, long ne);
 void launch_initial_state(int k, const DgArgs& A, int shape, double amp, double xc, double zc,
                           double xr, double zr, double a, double Z, double x0, double z0,
-                          double u_mean, double* U, hipStream_t st);
+                          double u_mean, double* U, hipStream_t st, const Mb& mb = Mb{});
 // sum over nodes of (U + Ubar)^2
-void launch_norm2_total(int k, const DgArgs& A, const double* U, Red red, hipStream_t st);
+void launch_norm2_total(int k, const DgArgs& A, const double* U, Red red, hipStream_t st, const Mb& mb = Mb{});
 int norm_total_grid(long n);
 
 // ---- transfers (transfer.hip) ----
 template <typename T>
 void launch_transfer_T(int k, const DgArgs& A, int mass_fix, const double* U, T* u, int nxf, hipStream_t st,
-                       const double* snrm2 = nullptr, double* Us = nullptr);
+                       const double* snrm2 = nullptr, double* Us = nullptr, const Mb& mb = Mb{});
 template <typename T>
 void launch_transfer_Tinv(int k, const DgArgs& A, int mass_fix, const T* u, double* U, int nxf, Red red,
-                          hipStream_t st);
+                          hipStream_t st, const Mb& mb = Mb{});
 void launch_subgrid_map(int k, const DgArgs& A, int nxf, int* out, hipStream_t st);
 
 // ---- FV kernels (fv.hip) ----
@@ -108,21 +115,21 @@ long fv_partial_blocks(long nxl, long nzl);
 template <typename T> struct FvLaunch {
     // F0 = f~(u), then the level slots (||u + Ubar||, max |v| + c, dtau) via red.partials
     static void lin_level(const FvArgs<T>& A, const T* u, T* F0, Red red, double* slots, double adt, double cfl,
-                          hipStream_t st);
+                          hipStream_t st, const Mb& mb = Mb{});
     // one RK stage; ||x_p||^2 is the sum of xcount partials at xpart; writes the
     // ||xo||^2 partials to red.partials and returns their count
     static int stage(const FvArgs<T>& A, const T* u, const T* F0, const T* xp, const T* x0, const T* b, T* xo,
                      const double* xpart, int xcount, const double* slots, double alpha_j, double adt, int zero,
-                     Red red, hipStream_t st);
+                     Red red, hipStream_t st, const Mb& mb = Mb{});
     static void matvec(const FvArgs<T>& A, const T* u, const T* F0, const T* x, T* out, const double* xpart,
-                       int xcount, const double* slots, double adt, hipStream_t st);
+                       int xcount, const double* slots, double adt, hipStream_t st, const Mb& mb = Mb{});
     static void defect_restrict(const FvArgs<T>& A, const T* u, const T* F0, const T* x, const T* b, T* rc,
                                 const double* xpart, int xcount, const double* slots, double adt, int zero,
-                                hipStream_t st);
-    static int prolong_correct(const FvArgs<T>& Af, T* x, const T* v, Red red, hipStream_t st);
-    static void restrict_(const FvArgs<T>& Af, const T* f, T* c, hipStream_t st);
-    static void prolong(const FvArgs<T>& Af, const T* c, T* f, hipStream_t st);
-    static void norm2(const T* x, long n, Red red, hipStream_t st);
+                                hipStream_t st, const Mb& mb = Mb{});
+    static int prolong_correct(const FvArgs<T>& Af, T* x, const T* v, Red red, hipStream_t st, const Mb& mb = Mb{});
+    static void restrict_(const FvArgs<T>& Af, const T* f, T* c, hipStream_t st, const Mb& mb = Mb{});
+    static void prolong(const FvArgs<T>& Af, const T* c, T* f, hipStream_t st, const Mb& mb = Mb{});
+    static void norm2(const T* x, long n, Red red, hipStream_t st, const Mb& mb = Mb{});
     static int norm_blocks(long n);
 };
 
@@ -139,22 +146,26 @@ struct Gate {
 };
 __device__ __forceinline__ bool gate_open(const Gate& g) { return !g.after || g.after[0] < g.tau2 * g.before[0]; }
 
-void launch_finalize(const double* partials, int nb, int nq, double* out, hipStream_t st, Gate gate = Gate{});
+void launch_finalize(const double* partials, int nb, int nq, double* out, hipStream_t st, Gate gate = Gate{},
+                     const Mb& mb = Mb{});
 void launch_finalize_publish(const double* partials, int nb, double* out, const double* src, int n, int idx,
-                             double* host, Gate gate, const double* fallback, hipStream_t st);
-void launch_norm2(const double* x, long n, Red red, hipStream_t st);
+                             double* host, Gate gate, const double* fallback, hipStream_t st, const Mb& mb,
+                             long host_stride);
+void launch_norm2(const double* x, long n, Red red, hipStream_t st, const Mb& mb = Mb{});
 void launch_multidot(const double* w, const double* V, long ld, int nv, int self, long n, Gate gate, Red red,
-                     hipStream_t st);
+                     hipStream_t st, const Mb& mb = Mb{});
 // w -= sum_i h[i] V_i; optional ||w||^2 into red.out when red.out != nullptr
 void launch_update(double* w, const double* V, long ld, int nv, long n, const double* h, Red red, hipStream_t st,
-                   Gate gate = Gate{});
-void launch_scale(double* out, const double* in, long n, const double* nrm2, hipStream_t st);
+                   Gate gate = Gate{}, const Mb& mb = Mb{});
+void launch_scale(double* out, const double* in, long n, const double* nrm2, hipStream_t st, double sgn = 1.0,
+                  const Mb& mb = Mb{});
 // out = base + sum_i y[i] Z_i   (base may alias out)
 void launch_lincomb(double* out, const double* base, const double* Z, long ld, int nv, long n, const double* y,
-                    hipStream_t st);
+                    hipStream_t st, const Mb& mb = Mb{});
 // zero `bytes` (a multiple of 4) with a kernel (graph-capture safe, unlike a memset node)
-void launch_zero(void* ptr, size_t bytes, hipStream_t st);
+void launch_zero(void* ptr, size_t bytes, hipStream_t st, const Mb& mb = Mb{});
 // out = a*x + b*y
-void launch_axpby(double* out, double a, const double* x, double b, const double* y, long n, hipStream_t st);
+void launch_axpby(double* out, double a, const double* x, double b, const double* y, long n, hipStream_t st,
+                  const Mb& mb = Mb{});
 
 }  // namespace jfmg

@@ -16,8 +16,12 @@ int la_blocks(long n)
 
 // out[q] = sum_b p[q * nb + b], one block per q, fixed order (0 where the gate is closed)
 __global__ void __launch_bounds__(256) finalize_kernel(const double* __restrict__ p, int nb, double* __restrict__ out,
-                                                       Gate gate)
+                                                       Gate gate, long ms)
 {
+    p = mbr(p, ms);
+    out = mbr(out, ms);
+    gate.after = mbr(gate.after, ms);
+    gate.before = mbr(gate.before, ms);
     __shared__ double sh[4];
     const int q = blockIdx.x;
     if (!gate_open(gate)) {
@@ -30,9 +34,9 @@ __global__ void __launch_bounds__(256) finalize_kernel(const double* __restrict_
     if (threadIdx.x == 0) out[q] = a;
 }
 
-void launch_finalize(const double* partials, int nb, int nq, double* out, hipStream_t st, Gate gate)
+void launch_finalize(const double* partials, int nb, int nq, double* out, hipStream_t st, Gate gate, const Mb& mb)
 {
-    finalize_kernel<<<dim3(nq), dim3(256), 0, st>>>(partials, nb, out, gate);
+    finalize_kernel<<<dim3(nq, 1, mb.n), dim3(256), 0, st>>>(partials, nb, out, gate, mb.ms);
 }
 
 // Last reduction of an FGMRES iteration: out[0] = sum of the partials (or
@@ -43,8 +47,16 @@ void launch_finalize(const double* partials, int nb, int nq, double* out, hipStr
 // completion event without a separate copy.
 __global__ void __launch_bounds__(256)
 finalize_publish_kernel(const double* __restrict__ p, int nb, double* __restrict__ out, const double* __restrict__ src,
-                        int n, int idx, double* __restrict__ host, Gate gate, const double* __restrict__ fallback)
+                        int n, int idx, double* __restrict__ host, Gate gate, const double* __restrict__ fallback,
+                        long ms, long host_stride)
 {
+    p = mbr(p, ms);
+    out = mbr(out, ms);
+    src = mbr(src, ms);
+    fallback = mbr(fallback, ms);
+    gate.after = mbr(gate.after, ms);
+    gate.before = mbr(gate.before, ms);
+    host += (long)blockIdx.z * host_stride;
     __shared__ double sh[4];
     __shared__ double total;
     const bool open = gate_open(gate);
@@ -61,24 +73,28 @@ finalize_publish_kernel(const double* __restrict__ p, int nb, double* __restrict
 }
 
 void launch_finalize_publish(const double* partials, int nb, double* out, const double* src, int n, int idx,
-                             double* host, Gate gate, const double* fallback, hipStream_t st)
+                             double* host, Gate gate, const double* fallback, hipStream_t st, const Mb& mb,
+                             long host_stride)
 {
-    finalize_publish_kernel<<<dim3(1), dim3(256), 0, st>>>(partials, nb, out, src, n, idx, host, gate, fallback);
+    finalize_publish_kernel<<<dim3(1, 1, mb.n), dim3(256), 0, st>>>(partials, nb, out, src, n, idx, host, gate,
+                                                                    fallback, mb.ms, host_stride);
 }
 
-__global__ void __launch_bounds__(256) norm2_kernel(const double* __restrict__ x, long n, Red red)
+__global__ void __launch_bounds__(256) norm2_kernel(const double* __restrict__ x, long n, Red red, long ms)
 {
+    x = mbr(x, ms);
+    red = mbr(red, ms);
     double s = 0.0;
     for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) s += x[i] * x[i];
     put_partial<256>(red, s);
 }
 
-void launch_norm2(const double* x, long n, Red red, hipStream_t st)
+void launch_norm2(const double* x, long n, Red red, hipStream_t st, const Mb& mb)
 {
     long b = (n + 255) / 256;
     const int nb = (int)(b < 1024 ? b : 1024);
-    norm2_kernel<<<dim3(nb), dim3(256), 0, st>>>(x, n, red);
-    if (red.out) launch_finalize(red.partials, nb, 1, red.out, st);
+    norm2_kernel<<<dim3(nb, 1, mb.n), dim3(256), 0, st>>>(x, n, red, mb.ms);
+    if (red.out) launch_finalize(red.partials, nb, 1, red.out, st, Gate{}, mb);
 }
 
 // <w, v_i> for i < nv in one pass (and <w, w> as entry nv when self is set):
@@ -89,10 +105,15 @@ void launch_norm2(const double* x, long n, Red red, hipStream_t st)
 template <int MAXV>
 __global__ void __launch_bounds__(LA_NTH)
 multidot_kernel(const double* __restrict__ w, const double* __restrict__ V, long ld, int nv, int self, long n, Gate gate,
-                Red red)
+                Red red, long ms)
 {
     constexpr int NW = LA_NTH / 64;
     __shared__ double sh[NW][MAXV];
+    w = mbr(w, ms);
+    V = mbr(V, ms);
+    gate.after = mbr(gate.after, ms);
+    gate.before = mbr(gate.before, ms);
+    red = mbr(red, ms);
     if (!gate_open(gate)) return;
     const int nt = nv + self;
     const long base = (long)blockIdx.x * LA_NTH * LA_EL + threadIdx.x;
@@ -129,22 +150,28 @@ multidot_kernel(const double* __restrict__ w, const double* __restrict__ V, long
 }
 
 void launch_multidot(const double* w, const double* V, long ld, int nv, int self, long n, Gate gate, Red red,
-                     hipStream_t st)
+                     hipStream_t st, const Mb& mb)
 {
-    const dim3 g(la_blocks(n)), b(LA_NTH);
+    const dim3 g(la_blocks(n), 1, mb.n), b(LA_NTH);
     const int nt = nv + self;
-    if (nt <= 8) timed_launch(multidot_kernel<8>, g, b, st, w, V, ld, nv, self, n, gate, red);
-    else if (nt <= 16) timed_launch(multidot_kernel<16>, g, b, st, w, V, ld, nv, self, n, gate, red);
-    else if (nt <= 32) timed_launch(multidot_kernel<32>, g, b, st, w, V, ld, nv, self, n, gate, red);
-    else timed_launch(multidot_kernel<65>, g, b, st, w, V, ld, nv, self, n, gate, red);
-    launch_finalize(red.partials, (int)g.x, nt, red.out, st, gate);
+    if (nt <= 8) timed_launch(multidot_kernel<8>, g, b, st, w, V, ld, nv, self, n, gate, red, mb.ms);
+    else if (nt <= 16) timed_launch(multidot_kernel<16>, g, b, st, w, V, ld, nv, self, n, gate, red, mb.ms);
+    else if (nt <= 32) timed_launch(multidot_kernel<32>, g, b, st, w, V, ld, nv, self, n, gate, red, mb.ms);
+    else timed_launch(multidot_kernel<65>, g, b, st, w, V, ld, nv, self, n, gate, red, mb.ms);
+    launch_finalize(red.partials, (int)g.x, nt, red.out, st, gate, mb);
 }
 
 __global__ void __launch_bounds__(LA_NTH)
 update_kernel(double* __restrict__ w, const double* __restrict__ V, long ld, int nv, long n,
-              const double* __restrict__ h, Gate gate, Red red)
+              const double* __restrict__ h, Gate gate, Red red, long ms)
 {
+    gate.after = mbr(gate.after, ms);
+    gate.before = mbr(gate.before, ms);
     if (!gate_open(gate)) return;
+    w = mbr(w, ms);
+    V = mbr(V, ms);
+    h = mbr(h, ms);
+    red = mbr(red, ms);
     const long base = (long)blockIdx.x * LA_NTH * LA_EL + threadIdx.x;
     double acc[LA_EL];
 #pragma unroll
@@ -174,29 +201,39 @@ update_kernel(double* __restrict__ w, const double* __restrict__ V, long ld, int
 }
 
 void launch_update(double* w, const double* V, long ld, int nv, long n, const double* h, Red red, hipStream_t st,
-                   Gate gate)
+                   Gate gate, const Mb& mb)
 {
-    timed_launch(update_kernel, dim3(la_blocks(n)), dim3(LA_NTH), st, w, V, ld, nv, n, h, gate, red);
-    if (red.out) launch_finalize(red.partials, la_blocks(n), 1, red.out, st);
+    timed_launch(update_kernel, dim3(la_blocks(n), 1, mb.n), dim3(LA_NTH), st, w, V, ld, nv, n, h, gate, red, mb.ms);
+    if (red.out) launch_finalize(red.partials, la_blocks(n), 1, red.out, st, Gate{}, mb);
 }
 
 __global__ void __launch_bounds__(256)
-scale_kernel(double* __restrict__ out, const double* __restrict__ in, long n, const double* __restrict__ nrm2)
+scale_kernel(double* __restrict__ out, const double* __restrict__ in, long n, const double* __restrict__ nrm2,
+             double sgn, long ms)
 {
-    const double s = 1.0 / sqrt(nrm2[0]);
+    out = mbr(out, ms);
+    in = mbr(in, ms);
+    nrm2 = mbr(nrm2, ms);
+    const double s = sgn / sqrt(nrm2[0]);
     for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) out[i] = in[i] * s;
 }
 
-void launch_scale(double* out, const double* in, long n, const double* nrm2, hipStream_t st)
+// out = sgn * in / sqrt(nrm2[0]) (per member)
+void launch_scale(double* out, const double* in, long n, const double* nrm2, hipStream_t st, double sgn,
+                  const Mb& mb)
 {
     long b = (n + 255) / 256;
-    scale_kernel<<<dim3((unsigned)(b < 4096 ? b : 4096)), dim3(256), 0, st>>>(out, in, n, nrm2);
+    scale_kernel<<<dim3((unsigned)(b < 4096 ? b : 4096), 1, mb.n), dim3(256), 0, st>>>(out, in, n, nrm2, sgn, mb.ms);
 }
 
 __global__ void __launch_bounds__(LA_NTH)
 lincomb_kernel(double* out, const double* base_, const double* __restrict__ Z, long ld, int nv, long n,
-               const double* __restrict__ y)
+               const double* __restrict__ y, long ms)
 {
+    out = mbr(out, ms);
+    base_ = mbr(base_, ms);
+    Z = mbr(Z, ms);
+    y = mbr(y, ms);
     const long base = (long)blockIdx.x * LA_NTH * LA_EL + threadIdx.x;
     double acc[LA_EL];
 #pragma unroll
@@ -206,6 +243,7 @@ lincomb_kernel(double* out, const double* base_, const double* __restrict__ Z, l
     }
     for (int v = 0; v < nv; ++v) {
         const double yv = y[v];
+        if (yv == 0.0) continue;   // a zero coefficient adds nothing (its column may be unset)
         const double* Zi = Z + (long)v * ld;
 #pragma unroll
         for (int k = 0; k < LA_EL; ++k) {
@@ -221,34 +259,39 @@ lincomb_kernel(double* out, const double* base_, const double* __restrict__ Z, l
 }
 
 void launch_lincomb(double* out, const double* base, const double* Z, long ld, int nv, long n, const double* y,
-                    hipStream_t st)
+                    hipStream_t st, const Mb& mb)
 {
-    lincomb_kernel<<<dim3(la_blocks(n)), dim3(LA_NTH), 0, st>>>(out, base, Z, ld, nv, n, y);
+    lincomb_kernel<<<dim3(la_blocks(n), 1, mb.n), dim3(LA_NTH), 0, st>>>(out, base, Z, ld, nv, n, y, mb.ms);
 }
 
 __global__ void __launch_bounds__(256)
 axpby_kernel(double* out, double a, const double* x, double b, const double* y,
-             long n)
+             long n, long ms)
 {
+    out = mbr(out, ms);
+    x = mbr(x, ms);
+    y = mbr(y, ms);
     for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) out[i] = a * x[i] + b * y[i];
 }
 
-void launch_axpby(double* out, double a, const double* x, double b, const double* y, long n, hipStream_t st)
+void launch_axpby(double* out, double a, const double* x, double b, const double* y, long n, hipStream_t st,
+                  const Mb& mb)
 {
     long blk = (n + 255) / 256;
-    axpby_kernel<<<dim3((unsigned)(blk < 4096 ? blk : 4096)), dim3(256), 0, st>>>(out, a, x, b, y, n);
+    axpby_kernel<<<dim3((unsigned)(blk < 4096 ? blk : 4096), 1, mb.n), dim3(256), 0, st>>>(out, a, x, b, y, n, mb.ms);
 }
 
-__global__ void __launch_bounds__(256) zero_kernel(unsigned* __restrict__ x, long n)
+__global__ void __launch_bounds__(256) zero_kernel(unsigned* __restrict__ x, long n, long ms)
 {
+    x = mbr(x, ms);
     for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) x[i] = 0u;
 }
 
-void launch_zero(void* ptr, size_t bytes, hipStream_t st)
+void launch_zero(void* ptr, size_t bytes, hipStream_t st, const Mb& mb)
 {
     const long n = (long)(bytes / 4);
     long blk = (n + 255) / 256;
-    zero_kernel<<<dim3((unsigned)(blk < 4096 ? blk : 4096)), dim3(256), 0, st>>>((unsigned*)ptr, n);
+    zero_kernel<<<dim3((unsigned)(blk < 4096 ? blk : 4096), 1, mb.n), dim3(256), 0, st>>>((unsigned*)ptr, n, mb.ms);
 }
 
 }  // namespace jfmg

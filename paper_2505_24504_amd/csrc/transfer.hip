@@ -31,8 +31,12 @@ __device__ __forceinline__ long subcell_index(int ex, int ez, int i, int j, int 
 template <int N1, typename T>
 __global__ void __launch_bounds__(TrShape<N1>::NTH)
 transfer_T_kernel(DgArgs A, int mass_fix, const double* U, T* __restrict__ u, int nxf, const double* snrm2,
-                  double* Us)
+                  double* Us, long ms)
 {
+    U = mbr(U, ms);
+    u = mbr(u, ms);
+    snrm2 = mbr(snrm2, ms);
+    Us = mbr(Us, ms);
     constexpr int NP = TrShape<N1>::NP, EPB = TrShape<N1>::EPB;
     __shared__ double sU[EPB][4][NP];
     __shared__ double sH[EPB][4][NP];
@@ -102,8 +106,12 @@ transfer_T_kernel(DgArgs A, int mass_fix, const double* U, T* __restrict__ u, in
 
 template <int N1, typename T>
 __global__ void __launch_bounds__(TrShape<N1>::NTH)
-transfer_Tinv_kernel(DgArgs A, int mass_fix, const T* __restrict__ u, double* __restrict__ U, int nxf, Red red)
+transfer_Tinv_kernel(DgArgs A, int mass_fix, const T* __restrict__ u, double* __restrict__ U, int nxf, Red red,
+                     long ms)
 {
+    u = mbr(u, ms);
+    U = mbr(U, ms);
+    red = mbr(red, ms);
     constexpr int NP = TrShape<N1>::NP, NTH = TrShape<N1>::NTH, EPB = TrShape<N1>::EPB;
     __shared__ double sT[EPB][4][NP];
     __shared__ double sH[EPB][4][NP];
@@ -175,30 +183,33 @@ int transfer_grid(int k, long ne)
 
 template <typename T>
 void launch_transfer_T(int k, const DgArgs& A, int mass_fix, const double* U, T* u, int nxf, hipStream_t st,
-                       const double* snrm2, double* Us)
+                       const double* snrm2, double* Us, const Mb& mb)
 {
-    const dim3 g(transfer_grid(k, A.ne));
-    if (k == 1) timed_launch(transfer_T_kernel<2, T>, g, dim3(TrShape<2>::NTH), st, A, mass_fix, U, u, nxf, snrm2, Us);
-    else if (k == 2) timed_launch(transfer_T_kernel<3, T>, g, dim3(TrShape<3>::NTH), st, A, mass_fix, U, u, nxf, snrm2, Us);
-    else timed_launch(transfer_T_kernel<4, T>, g, dim3(TrShape<4>::NTH), st, A, mass_fix, U, u, nxf, snrm2, Us);
+    const dim3 g(transfer_grid(k, A.ne), 1, mb.n);
+    if (k == 1) timed_launch(transfer_T_kernel<2, T>, g, dim3(TrShape<2>::NTH), st, A, mass_fix, U, u, nxf, snrm2, Us, mb.ms);
+    else if (k == 2) timed_launch(transfer_T_kernel<3, T>, g, dim3(TrShape<3>::NTH), st, A, mass_fix, U, u, nxf, snrm2, Us, mb.ms);
+    else timed_launch(transfer_T_kernel<4, T>, g, dim3(TrShape<4>::NTH), st, A, mass_fix, U, u, nxf, snrm2, Us, mb.ms);
 }
 
 template <typename T>
-void launch_transfer_Tinv(int k, const DgArgs& A, int mass_fix, const T* u, double* U, int nxf, Red red, hipStream_t st)
+void launch_transfer_Tinv(int k, const DgArgs& A, int mass_fix, const T* u, double* U, int nxf, Red red, hipStream_t st,
+                          const Mb& mb)
 {
-    const dim3 g(transfer_grid(k, A.ne));
-    if (k == 1) timed_launch(transfer_Tinv_kernel<2, T>, g, dim3(TrShape<2>::NTH), st, A, mass_fix, u, U, nxf, red);
-    else if (k == 2) timed_launch(transfer_Tinv_kernel<3, T>, g, dim3(TrShape<3>::NTH), st, A, mass_fix, u, U, nxf, red);
-    else timed_launch(transfer_Tinv_kernel<4, T>, g, dim3(TrShape<4>::NTH), st, A, mass_fix, u, U, nxf, red);
-    if (red.out) launch_finalize(red.partials, (int)g.x, 1, red.out, st);
+    const dim3 g(transfer_grid(k, A.ne), 1, mb.n);
+    if (k == 1) timed_launch(transfer_Tinv_kernel<2, T>, g, dim3(TrShape<2>::NTH), st, A, mass_fix, u, U, nxf, red, mb.ms);
+    else if (k == 2) timed_launch(transfer_Tinv_kernel<3, T>, g, dim3(TrShape<3>::NTH), st, A, mass_fix, u, U, nxf, red, mb.ms);
+    else timed_launch(transfer_Tinv_kernel<4, T>, g, dim3(TrShape<4>::NTH), st, A, mass_fix, u, U, nxf, red, mb.ms);
+    if (red.out) launch_finalize(red.partials, (int)g.x, 1, red.out, st, Gate{}, mb);
 }
 
 template void launch_transfer_T<double>(int, const DgArgs&, int, const double*, double*, int, hipStream_t,
-                                        const double*, double*);
+                                        const double*, double*, const Mb&);
 template void launch_transfer_T<float>(int, const DgArgs&, int, const double*, float*, int, hipStream_t,
-                                       const double*, double*);
-template void launch_transfer_Tinv<double>(int, const DgArgs&, int, const double*, double*, int, Red, hipStream_t);
-template void launch_transfer_Tinv<float>(int, const DgArgs&, int, const float*, double*, int, Red, hipStream_t);
+                                       const double*, double*, const Mb&);
+template void launch_transfer_Tinv<double>(int, const DgArgs&, int, const double*, double*, int, Red, hipStream_t,
+                                           const Mb&);
+template void launch_transfer_Tinv<float>(int, const DgArgs&, int, const float*, double*, int, Red, hipStream_t,
+                                          const Mb&);
 
 void launch_subgrid_map(int k, const DgArgs& A, int nxf, int* out, hipStream_t st)
 {

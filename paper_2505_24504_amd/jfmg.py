@@ -32,7 +32,8 @@ class Config(C.Structure):
         "precond")] + [("mg_key", C.c_char * 16)] + [(n, C.c_double) for n in (
         "x0", "x1", "z0", "z1", "g", "gamma", "R", "p0", "theta0", "N", "u_mean", "mu", "c_ip", "dt",
         "newton_rtol", "ew_gamma", "ew_alpha", "ew_eta0", "ew_eta_max")] + [
-        ("rk_alpha", C.c_double * 4), ("pseudo_cfl", C.c_double), ("newton_stall", C.c_double)]
+        ("rk_alpha", C.c_double * 4), ("pseudo_cfl", C.c_double), ("newton_stall", C.c_double),
+        ("batch", C.c_int), ("reserved", C.c_int)]
 
 
 class Perturbation(C.Structure):
@@ -134,7 +135,7 @@ def make_config(d: dict) -> Config:
     L.jfmg_config_default(C.byref(c))
     ints = ("nx", "nz", "k", "physics", "background", "bc", "scheme", "newton_maxit", "gmres_m",
             "gmres_max_restarts", "fd_eps_mode", "mg_levels", "rk_stages", "mass_fix", "mg_precision",
-            "precond")
+            "precond", "batch")
     dbls = ("x0", "x1", "z0", "z1", "g", "gamma", "R", "p0", "theta0", "N", "u_mean", "mu", "c_ip", "dt",
             "newton_rtol", "ew_gamma", "ew_alpha", "ew_eta0", "ew_eta_max", "pseudo_cfl", "newton_stall")
     for n in ints:
@@ -190,7 +191,8 @@ class Problem:
         if rc:
             raise JfmgError(rc, self.L.jfmg_last_error(None).decode())
         self.h = h
-        self.ndof = self.L.jfmg_num_dofs(h)
+        self.ndof = self.L.jfmg_num_dofs(h)            # per member
+        self.members = max(1, int(self.cfg.batch))    # lock-step batch size
         self.fv_dtype = torch.float32 if self.cfg.mg_precision == 32 else torch.float64
 
     def __del__(self):
@@ -207,6 +209,10 @@ class Problem:
     def dg_zeros(self):
         return torch.zeros(self.ndof, dtype=torch.float64, device=self.device)
 
+    def state_zeros(self):
+        """A state of every member, members back to back (B * N)."""
+        return torch.zeros(self.members * self.ndof, dtype=torch.float64, device=self.device)
+
     def fv_size(self, level=0):
         return self.L.jfmg_fv_size(self.h, level)
 
@@ -216,7 +222,7 @@ class Problem:
     # ---- entry points ----
     def initial_state(self, pert: dict):
         P = _perturbation(pert)
-        U = self.dg_zeros()
+        U = self.state_zeros()
         self._check(self.L.jfmg_initial_state(self.h, C.byref(P), _ptr(U)))
         return U
 

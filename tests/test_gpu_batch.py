@@ -111,3 +111,29 @@ def test_fp32_mg_step_vs_fp64_oracle_inertia_gravity():
     d = dict(d, nx=60, nz=4, x1=30000.0)
     pert = dict(pert, xc=15000.0)
     _fp32_vs_oracle(d, pert)
+
+
+@pytest.mark.parametrize("prec", [32, 64])
+def test_lockstep_members_equal_alone(prec):
+    """A lock-step batch (one problem, all members in every launch) gives each
+    member bitwise the result of the same member as a single problem."""
+    ens = [m for m in W.ensemble(seed=4, members=64) if m[0]["nx"] == 32][:3]
+    assert len(ens) == 3
+    d = dict(ens[0][0], mg_precision=prec)
+    alone = [_alone(d, pert, 2) for _, pert, _ in ens]
+    pb = jfmg.Problem(dict(d, batch=len(ens)), device=DEV)
+    single = jfmg.Problem(d, device=DEV)
+    U = torch.cat([single.initial_state(pert) for _, pert, _ in ens])
+    for _ in range(2):
+        st = pb.implicit_step(U)
+        assert st["status"] == 0
+    n = pb.ndof
+    for i in range(len(ens)):
+        assert torch.equal(U[i * n:(i + 1) * n], alone[i]), i
+
+
+def test_lockstep_rejects_single_problem_calls():
+    d, _, _ = W.ensemble(seed=4, members=1)[0]
+    pb = jfmg.Problem(dict(d, batch=2), device=DEV)
+    with pytest.raises(jfmg.JfmgError):
+        pb.residual(pb.dg_zeros())
