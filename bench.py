@@ -23,17 +23,18 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per launch of the finest-level FV smoother-stage kernel, from two
+# HBM bytes per launch of the FV smoother-stage kernel class fv_stage (the
+# wide-tile kernel: levels of 1024x256 and 512x128 cells), from two
 # rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE) over
 #   bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-fp32 --no-forms --profile-class fv_stage
-# each counter scaled by what it reads for the 1 GiB device copy of that same
-# run (FETCH_SIZE x2, WRITE_SIZE x1).
+# averaged over its launches, each counter scaled by what it reads for the 1 GiB
+# device copy of that same run (FETCH_SIZE x2, WRITE_SIZE x1).
 # It describes the kernel sources hashed below and is reported as null once
 # they change.
-TRAFFIC = {"class": "fv_stage", "bytes_per_launch": 5.494e7,
+TRAFFIC = {"class": "fv_stage", "bytes_per_launch": 3.9988e7,
            "sources": ["paper_2505_24504_amd/csrc/fv.hip", "paper_2505_24504_amd/csrc/jfmg_dev.h",
                        "paper_2505_24504_amd/csrc/jfmg_internal.h"],
-           "sha256": "80d2f85a23a71b0150e4a725e3603d4da98b0169e6fb0bdc21c136ff43f2adf4",
+           "sha256": "16a273b0884fa412e11f9058268602f24d175301888ebbc8e395cd6cabbad83e",
            "profile": "profiles/traffic_fv_stage_density_current_fp64.md"}
 
 

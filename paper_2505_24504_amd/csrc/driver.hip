@@ -248,7 +248,8 @@ enum {
     S_H1 = 128,     // 65 entries: h of the first pass, then ||w||^2 before it
     S_H2 = 193,     // 65 entries
     S_HB = 131,     // doubles from S_H1 through S_W
-    S_Yc = 384      // 65 entries: FGMRES coefficients
+    S_Yc = 384,     // 65 entries: FGMRES coefficients
+    HSCAL = 8       // scalars per member the host reads at once
 };
 
 struct Carve {
@@ -331,6 +332,8 @@ struct jfmg_problem {
     bool use_graphs = true;
     IterGraph* capturing = nullptr;
     double* hpin = nullptr;            // coherent pinned host copies of the Arnoldi scalars, per iteration
+    double* hscal = nullptr;           // coherent pinned: scalars read by the host, [member][HSCAL]
+    double* ycoef = nullptr;           // coherent pinned: FGMRES coefficients, [member][m]
     std::vector<hipEvent_t> hev;       // completion of each copy
     // host side
     int have_lin;
@@ -502,6 +505,7 @@ Red red_at(jfmg_problem* p, int slot) { return Red{p->partials, p->scal + slot};
 // copy `bytes` of every member from src to dst (both inside the members' workspaces)
 hipError_t copy_members(jfmg_problem* p, void* dst, const void* src, size_t bytes)
 {
+    if (p->mb.n == 1) return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, p->st);
     return hipMemcpy2DAsync(dst, (size_t)p->mb.ms, src, (size_t)p->mb.ms, bytes, (size_t)p->mb.n,
                             hipMemcpyDeviceToDevice, p->st);
 }
@@ -512,9 +516,10 @@ double* fvpart(jfmg_problem* p, int l, int bi) { return p->fvpart + (FVP_PER_LEV
 // out[member * count + i] (synchronizes the stream)
 jfmg_status read_scalars(jfmg_problem* p, int slot, int count, double* out)
 {
-    HIPCHK(p, hipMemcpy2DAsync(out, sizeof(double) * count, p->scal + slot, (size_t)p->mb.ms, sizeof(double) * count,
-                               (size_t)p->mb.n, hipMemcpyDeviceToHost, p->st));
+    if (count > HSCAL) return fail(p, JFMG_EINVAL, "too many scalars");
+    launch_gather(p->scal + slot, count, p->hscal, p->st, p->mb);
     HIPCHK(p, hipStreamSynchronize(p->st));
+    std::memcpy(out, p->hscal, sizeof(double) * count * p->mb.n);
     p->syncs++;
     prof_flush(p);
     return JFMG_OK;
@@ -938,8 +943,10 @@ jfmg_status fgmres(jfmg_problem* p, const double* G, const std::vector<double>& 
             jmax = std::max(jmax, x.jend);
         }
         if (jmax > 0) {
-            HIPCHK(p, hipMemcpy2DAsync(p->scal + S_Yc, (size_t)p->mb.ms, ybuf.data(), sizeof(double) * m,
-                                       sizeof(double) * jmax, (size_t)B, hipMemcpyHostToDevice, st));
+            // the previous cycle's scatter has finished reading ycoef (its lincomb was
+            // followed by a synchronizing read or this cycle's event waits)
+            std::copy(ybuf.begin(), ybuf.end(), p->ycoef);
+            launch_scatter(p->scal + S_Yc, jmax, p->ycoef, m, st, p->mb);
             launch_lincomb(p->delta, p->delta, p->Z, N, jmax, N, p->scal + S_Yc, st, p->mb);
         }
         prof_flush(p);
@@ -1216,6 +1223,8 @@ jfmg_status jfmg_create_problem(const jfmg_config* cfg, void* workspace, size_t 
     e = e ? e : hipStreamCreateWithFlags(&p->cs, hipStreamNonBlocking);
     // coherent pinned memory: the last kernel of each FGMRES iteration stores its scalars here
     e = e ? e : hipHostMalloc((void**)&p->hpin, sizeof(double) * S_HB * cfg->gmres_m * p->mb.n, hipHostMallocCoherent);
+    e = e ? e : hipHostMalloc((void**)&p->hscal, sizeof(double) * HSCAL * p->mb.n, hipHostMallocCoherent);
+    e = e ? e : hipHostMalloc((void**)&p->ycoef, sizeof(double) * cfg->gmres_m * p->mb.n, hipHostMallocCoherent);
     for (int j = 0; j < cfg->gmres_m && !e; ++j) {
         hipEvent_t ev = nullptr;
         e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
@@ -1250,6 +1259,8 @@ jfmg_status jfmg_destroy_problem(jfmg_problem* p)
         if (p->cs) (void)hipStreamDestroy(p->cs);
         for (hipEvent_t e : p->hev) (void)hipEventDestroy(e);
         if (p->hpin) (void)hipHostFree(p->hpin);
+        if (p->hscal) (void)hipHostFree(p->hscal);
+        if (p->ycoef) (void)hipHostFree(p->ycoef);
     }
     delete p;
     return JFMG_OK;
@@ -1328,7 +1339,10 @@ static jfmg_status implicit_step_body(jfmg_problem* p, double* U, jfmg_stats* st
     jfmg_status s;
     // the caller's U holds the members back to back ([members][N])
     const size_t vb = sizeof(double) * p->N;
-    hipError_t e = hipMemcpy2DAsync(p->Un, (size_t)p->mb.ms, U, vb, vb, (size_t)p->mb.n, hipMemcpyDeviceToDevice, p->st);
+    hipError_t e = p->mb.n == 1
+                       ? hipMemcpyAsync(p->Un, U, vb, hipMemcpyDeviceToDevice, p->st)
+                       : hipMemcpy2DAsync(p->Un, (size_t)p->mb.ms, U, vb, vb, (size_t)p->mb.n, hipMemcpyDeviceToDevice,
+                                          p->st);
     if (e) return fail(p, JFMG_EDEVICE, hipGetErrorString(e));
     if (c.scheme == 0) {
         s = newton_stage(p, p->Un, c.dt, &st);
@@ -1346,7 +1360,9 @@ static jfmg_status implicit_step_body(jfmg_problem* p, double* U, jfmg_stats* st
         }
     }
     if (s == JFMG_OK) {
-        e = hipMemcpy2DAsync(U, vb, p->Uk, (size_t)p->mb.ms, vb, (size_t)p->mb.n, hipMemcpyDeviceToDevice, p->st);
+        e = p->mb.n == 1 ? hipMemcpyAsync(U, p->Uk, vb, hipMemcpyDeviceToDevice, p->st)
+                         : hipMemcpy2DAsync(U, vb, p->Uk, (size_t)p->mb.ms, vb, (size_t)p->mb.n,
+                                            hipMemcpyDeviceToDevice, p->st);
         if (!e) e = hipStreamSynchronize(p->st);
         if (e) s = fail(p, JFMG_EDEVICE, hipGetErrorString(e));
     } else {

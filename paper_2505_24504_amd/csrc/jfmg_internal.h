@@ -152,6 +152,9 @@ void launch_finalize_publish(const double* partials, int nb, double* out, const 
                              double* host, Gate gate, const double* fallback, hipStream_t st, const Mb& mb,
                              long host_stride);
 void launch_norm2(const double* x, long n, Red red, hipStream_t st, const Mb& mb = Mb{});
+// device scalar slots <-> coherent pinned host memory (count values per member)
+void launch_gather(const double* src, int count, double* host, hipStream_t st, const Mb& mb);
+void launch_scatter(double* dst, int count, const double* host, long hstride, hipStream_t st, const Mb& mb);
 void launch_multidot(const double* w, const double* V, long ld, int nv, int self, long n, Gate gate, Red red,
                      hipStream_t st, const Mb& mb = Mb{});
 // w -= sum_i h[i] V_i; optional ||w||^2 into red.out when red.out != nullptr

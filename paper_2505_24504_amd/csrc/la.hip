@@ -80,6 +80,35 @@ void launch_finalize_publish(const double* partials, int nb, double* out, const 
                                                                     fallback, mb.ms, host_stride);
 }
 
+// Scalars between the device slots of every member and coherent pinned host
+// memory, by kernels (no copy engine): gather host[m * count + i] = slot_m[i],
+// scatter slot_m[i] = host[m * hstride + i].
+__global__ void __launch_bounds__(64) gather_kernel(const double* __restrict__ src, int count, double* __restrict__ host,
+                                                    long ms)
+{
+    src = mbr(src, ms);
+    host += (long)blockIdx.z * count;
+    for (int i = threadIdx.x; i < count; i += 64) host[i] = src[i];
+}
+
+__global__ void __launch_bounds__(64) scatter_kernel(double* __restrict__ dst, int count, const double* __restrict__ host,
+                                                     long hstride, long ms)
+{
+    dst = mbr(dst, ms);
+    host += (long)blockIdx.z * hstride;
+    for (int i = threadIdx.x; i < count; i += 64) dst[i] = host[i];
+}
+
+void launch_gather(const double* src, int count, double* host, hipStream_t st, const Mb& mb)
+{
+    gather_kernel<<<dim3(1, 1, mb.n), dim3(64), 0, st>>>(src, count, host, mb.ms);
+}
+
+void launch_scatter(double* dst, int count, const double* host, long hstride, hipStream_t st, const Mb& mb)
+{
+    scatter_kernel<<<dim3(1, 1, mb.n), dim3(64), 0, st>>>(dst, count, host, hstride, mb.ms);
+}
+
 __global__ void __launch_bounds__(256) norm2_kernel(const double* __restrict__ x, long n, Red red, long ms)
 {
     x = mbr(x, ms);
