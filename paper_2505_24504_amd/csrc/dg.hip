@@ -40,13 +40,15 @@ dg_kernel(DgArgs A, const double* __restrict__ U, const double* __restrict__ Y, 
           double* __restrict__ out, const double* __restrict__ yn2p, const double* __restrict__ ut2p, int eps_mode,
           double adt, Red red, long ms)
 {
-    U = mbr(U, ms);
-    Y = mbr(Y, ms);
-    Ubar = mbr(Ubar, ms);
-    out = mbr(out, ms);
-    yn2p = mbr(yn2p, ms);
-    ut2p = mbr(ut2p, ms);
-    red = mbr(red, ms);
+    if (gridDim.z > 1) {   // member of a lock-step batch
+        U = mbr(U, ms);
+        Y = mbr(Y, ms);
+        Ubar = mbr(Ubar, ms);
+        out = mbr(out, ms);
+        yn2p = mbr(yn2p, ms);
+        ut2p = mbr(ut2p, ms);
+        red = mbr(red, ms);
+    }
     constexpr int NP = DgShape<N1>::NP, NTH = DgShape<N1>::NTH, EPB = DgShape<N1>::EPB;
     constexpr int NSt = (MODE == 3) ? 2 : 1;
     __shared__ double sS[NSt][EPB][4][NP];

@@ -65,22 +65,24 @@ enum { FVM_LIN = 0, FVM_STAGE = 1, FVM_MATVEC = 2, FVM_DEFECT = 3 };
 //   STAGE   out = x0 + alpha_j dtau (b - g'x), g'x = x - adt/eps (f~(u + eps x) - F0)
 //   MATVEC  out = g'x
 //   DEFECT  out(coarse) = R(g'x - b), 2x2 agglomeration inside the tile
-template <typename T, int TX, int TZ, int NTH, int WPE, bool LATE, bool ZREV, int MODE>
+template <typename T, int TX, int TZ, int NTH, int WPE, bool LATE, bool ZREV, bool MB, int MODE>
 __global__ void __launch_bounds__(NTH, WPE)
 fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, const T* __restrict__ xp,
                const T* __restrict__ x0, const T* __restrict__ b, T* __restrict__ out,
                const double* __restrict__ xpart, int xcount, double* __restrict__ slots, double alpha_j,
                double adt, double cfl, Red red, long ms)
 {
-    u = mbr(u, ms);
-    F0 = mbr(F0, ms);
-    xp = mbr(xp, ms);
-    x0 = mbr(x0, ms);
-    b = mbr(b, ms);
-    out = mbr(out, ms);
-    xpart = mbr(xpart, ms);
-    slots = mbr(slots, ms);
-    red = mbr(red, ms);
+    if constexpr (MB) {   // member blockIdx.z of a lock-step batch
+        u = mbr(u, ms);
+        F0 = mbr(F0, ms);
+        xp = mbr(xp, ms);
+        x0 = mbr(x0, ms);
+        b = mbr(b, ms);
+        out = mbr(out, ms);
+        xpart = mbr(xpart, ms);
+        slots = mbr(slots, ms);
+        red = mbr(red, ms);
+    }
     constexpr int NCELL = TX * TZ, HX = TX + 2, HZ = TZ + 2;
     constexpr int NH = HX * HZ, HITEMS = (NH + NTH - 1) / NTH;
     constexpr int NFX = TZ * (TX + 1), NFZ = (TZ + 1) * TX;
@@ -466,8 +468,12 @@ static int tile_launch_shape(const FvArgs<T>& A, const T* u, const T* F0, const 
                              double cfl, Red red, hipStream_t st, const Mb& mb)
 {
     const dim3 g((unsigned)((A.nxl + TX - 1) / TX), (unsigned)((A.nzl + TZ - 1) / TZ), (unsigned)mb.n);
-    timed_launch(fv_tile_kernel<T, TX, TZ, NTH, WPE, LATE, ZREV, MODE>, g, dim3(NTH), st, A, u, F0, xp, x0, b, out, xpart,
-                 xcount, slots, alpha_j, adt, cfl, red, mb.ms);
+    if (mb.n > 1)
+        timed_launch(fv_tile_kernel<T, TX, TZ, NTH, WPE, LATE, ZREV, true, MODE>, g, dim3(NTH), st, A, u, F0, xp, x0, b,
+                     out, xpart, xcount, slots, alpha_j, adt, cfl, red, mb.ms);
+    else
+        timed_launch(fv_tile_kernel<T, TX, TZ, NTH, WPE, LATE, ZREV, false, MODE>, g, dim3(NTH), st, A, u, F0, xp, x0,
+                     b, out, xpart, xcount, slots, alpha_j, adt, cfl, red, 0L);
     return (int)(g.x * g.y);
 }
 
