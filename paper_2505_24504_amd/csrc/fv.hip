@@ -218,7 +218,7 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
                         visc_flux(A.mu, Ua, Z4, dbg, T(0), T(1), FL);
                         visc_flux(A.mu, Ub, Z4, dbg, T(0), T(1), FR);
                     }
-                    const T irs = T(1) / (Ua[0] + Ub[0]);
+                    const T irs = frcp<T>(Ua[0] + Ub[0]);
                     const T muh = A.mu / (XF ? A.hx : A.hz);
 #pragma unroll
                     for (int c = 1; c < 4; ++c) {
