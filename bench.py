@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the ensemble, serving and inertia-gravity forms")
     ap.add_argument("--serve-requests", type=int, default=32)
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the HBM-resident (above cache size) kernel measurements")
     ap.add_argument("--profile-class", default="auto",
                     help="kernel class timed with HIP events ('auto': largest total time)")
     return ap.parse_args()
@@ -256,6 +258,54 @@ def inertia_gravity_forms(steps=3):
     return out
 
 
+def large_roofline(reps=20):
+    """The FV operator and the DG JVP on vectors far above the 256 MB cache:
+    a 1024x1024-quad, k = 3 problem (FV level 4096x4096 cells, DG vector 537 MB,
+    density-current physics).  GB/s of algorithmic bytes of the whole call: an FV
+    matvec call reads x for ||x|| (eps), then u, F0 and x (with halo) and writes
+    g'x (5 vectors); a JVP call reads y for ||y||, then U and y, and writes the
+    product (4 vectors).  Events on the launch stream bracket `reps` back-to-back
+    calls."""
+    import ctypes
+    import torch
+    from paper_2505_24504_amd import jfmg, workloads as W
+    out = {}
+    d0, pert, _ = W.density_current()
+    for prec in (64, 32):
+        d = dict(d0, nx=1024, nz=1024, z1=102400.0, gmres_m=2, mg_precision=prec)
+        p = jfmg.Problem(d, device="cuda:0")
+        U = p.initial_state(pert)
+        p.linearize(U, 0.5)
+        nfv = p.fv_size(0)
+        g = torch.Generator(device="cuda:0").manual_seed(7)
+        x = torch.randn(nfv, generator=g, device="cuda:0", dtype=p.fv_dtype)
+        y = torch.randn(p.ndof, generator=g, device="cuda:0", dtype=torch.float64)
+        xo = torch.empty_like(x)
+        yo = torch.empty_like(y)
+        ptr = lambda t: ctypes.c_void_p(t.data_ptr())
+        res = {}
+        for name, call, nbytes in (
+                ("fv_matvec_4096x4096", lambda: p.L.jfmg_fv_matvec(p.h, 0, ptr(x), ptr(xo)), 5 * nfv * x.element_size()),
+                ("dg_jvp_1024x1024_k3", lambda: p.L.jfmg_jvp(p.h, ptr(y), ptr(yo)), 4 * p.ndof * 8)):
+            if prec == 32 and name.startswith("dg"):
+                continue
+            assert call() == 0
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                call()
+            e1.record()
+            torch.cuda.synchronize()
+            us = 1e3 * e0.elapsed_time(e1) / reps
+            gbs = nbytes / (us * 1e-6) / 1e9
+            res[name] = {"us": us, "algorithmic_MB": nbytes / 1e6, "GBs": gbs, "frac_of_8TBs": gbs / HBM_PEAK_GBS}
+        out[f"fp{prec}"] = res
+        del p, U, x, y, xo, yo
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline():
     """The oracle timed on the host: first SDIRK2 step of the density current on a
     48 x 12 quad grid of the same domain (k = 3, same physics and solver settings)."""
@@ -347,6 +397,8 @@ def main():
         forms.update(ensemble_forms())
         forms.update(serving_forms(a.serve_requests))
         forms["inertia_gravity"] = inertia_gravity_forms()
+    if not a.no_large:
+        out["roofline_hbm_resident"] = large_roofline()
     # copy bandwidth of the device: HBM-resident (1 GiB) and cache-resident (32 MiB)
     hbm_copy, mall_copy = stream_copy(1 << 30), stream_copy(32 << 20)
     out["stream_copy"] = {"hbm_1GiB_GBs": hbm_copy, "mall_32MiB_GBs": mall_copy,
