@@ -161,7 +161,8 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
         // second z-face) ----
         auto face = [&](auto xf_tag, int idx) {
             constexpr bool XF = decltype(xf_tag)::value;
-            int r0, r1, sL, sR, Jrow;   // LDS rows/cols of the two sides; background row
+            constexpr int D = XF ? 1 : 2;   // normal momentum component
+            int rl, cl, rr, cr, Jrow;       // LDS row/col of the low (L) and high (R) cell; background row
             bool skip, wallL, wallR;
             if constexpr (XF) {
                 const int jj = idx / (TX + 1), fi = idx - jj * (TX + 1);
@@ -169,7 +170,7 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
                 skip = (Jf >= nzl) || (Il >= nxl);
                 wallL = (Ir == 0) && A.bc != 1;
                 wallR = (Il == nxl - 1) && A.bc != 1;
-                r0 = jj + 1; r1 = jj + 1; sL = fi; sR = fi + 1;
+                rl = jj + 1; rr = jj + 1; cl = fi; cr = fi + 1;
                 Jrow = skip ? 0 : Jf;
             } else {
                 const int fj = idx / TX, ii = idx - fj * TX;
@@ -177,54 +178,48 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
                 skip = (If >= nxl) || (Jb >= nzl);
                 wallL = (Jb < 0);
                 wallR = (Ja == nzl);
-                r0 = fj; r1 = fj + 1; sL = ii + 1; sR = ii + 1;
+                rl = fj; rr = fj + 1; cl = ii + 1; cr = ii + 1;
                 Jrow = skip ? 0 : Ja;
             }
             T Phi[4] = {T(0), T(0), T(0), T(0)};
             if (!skip) {
-                constexpr int NRM = XF ? 1 : 2;   // normal momentum component
                 const T* bg = (XF ? A.bgc : A.bgf) + 4 * Jrow;
                 const T* pr = (XF ? A.pc : A.pf) + 2 * Jrow;
                 const bool wall = wallL || wallR;
-                // HLLC(a, b; s n), Phi = s H: interior a = L, b = R, s = +1; a slip wall
-                // mirrors the inside cell (a = R, s = -1 on the low side; a = L, s = +1 on the high side)
-                const T sgn = wallL ? T(-1) : T(1);
-                T Dw[4], Ua[4], Ub[4], H[4];   // Dw = w_a - w_b (perturbations), for the penalty
-                T pa, pbb;
-                {
-                    T wa[4], wb[4];
+                // a slip wall: the missing side is the inside cell mirrored (normal momentum negated)
+                const int rlx = wallL ? rr : rl, clx = wallL ? cr : cl;
+                const int rrx = wallR ? rl : rr, crx = wallR ? cl : cr;
+                T wL[4], wR[4], UL[4], UR[4];
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        const T l = sw[c][r0][sL], r = sw[c][r1][sR];
-                        wa[c] = wallL ? r : l;
-                        wb[c] = wall ? wa[c] : r;
-                        Ua[c] = wa[c] + bg[c];
-                        Ub[c] = wb[c] + bg[c];
-                        Dw[c] = wa[c] - wb[c];
-                    }
-                    const T pb = pr[0], irb = pr[1];
-                    pa = pert_pressure(A.gas, wa[3], irb, pb);
-                    pbb = pert_pressure(A.gas, wb[3], irb, pb);
+                for (int c = 0; c < 4; ++c) {
+                    wL[c] = sw[c][rlx][clx];
+                    wR[c] = sw[c][rrx][crx];
+                    UL[c] = wL[c] + bg[c];
+                    UR[c] = wR[c] + bg[c];
                 }
-                if (wall) Ub[NRM] = -Ua[NRM];
-                hllc(A.gas, Ua, Ub, pa, pbb, sgn * T(XF ? 1 : 0), sgn * T(XF ? 0 : 1), H);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) Phi[c] = sgn * H[c];
+                if (wallL) UL[D] = -UL[D];
+                if (wallR) UR[D] = -UR[D];
+                const T pb = pr[0], irb = pr[1];
+                const T pL = pert_pressure(A.gas, wL[3], irb, pb), pR = pert_pressure(A.gas, wR[3], irb, pb);
+                const T irL = frcp<T>(UL[0]), irR = frcp<T>(UR[0]);
+                hllc_ax<T, D>(A.gas, UL, UR, pL, pR, irL, irR, Phi);
                 if (A.physics == 1 && !wall) {
-                    T FL[4] = {T(0), T(0), T(0), T(0)}, FR[4] = {T(0), T(0), T(0), T(0)};
-                    if constexpr (!XF) {
-                        const T Z4[4] = {T(0), T(0), T(0), T(0)};
-                        const T* dbg = A.dbgf + 4 * Jrow;
-                        visc_flux(A.mu, Ua, Z4, dbg, T(0), T(1), FL);
-                        visc_flux(A.mu, Ub, Z4, dbg, T(0), T(1), FR);
-                    }
-                    const T irs = frcp<T>(Ua[0] + Ub[0]);
+                    // k = 0 diffusion: mean of mu (G_c - (U_c/rho) G_rho) over both sides, where the
+                    // only gradient is the background's (z-faces), minus the interior penalty
+                    // (mu/h) (dw_c - (U_c/rho)_avg dw_rho), dw = w_L - w_R, on the averaged state
+                    const T irs = frcp<T>(UL[0] + UR[0]);
                     const T muh = A.mu / (XF ? A.hx : A.hz);
+                    const T* dbg = A.dbgf + 4 * Jrow;
+                    const T dw0 = wL[0] - wR[0];
 #pragma unroll
                     for (int c = 1; c < 4; ++c) {
-                        const T rr = (Ua[c] + Ub[c]) * irs;
-                        const T pen = muh * (Dw[c] - rr * Dw[0]);
-                        Phi[c] -= T(0.5) * (FL[c] + FR[c]) - pen;
+                        if constexpr (!XF) {
+                            const T fl = A.mu * (dbg[c] - UL[c] * irL * dbg[0]);
+                            const T fr = A.mu * (dbg[c] - UR[c] * irR * dbg[0]);
+                            Phi[c] -= T(0.5) * (fl + fr);
+                        }
+                        const T rr = (UL[c] + UR[c]) * irs;
+                        Phi[c] += muh * ((wL[c] - wR[c]) - rr * dw0);
                     }
                 }
                 const T elen = XF ? A.hz : A.hx;

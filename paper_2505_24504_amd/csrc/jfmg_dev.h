@@ -33,6 +33,26 @@ template <typename T> __device__ __forceinline__ T dsqrt(T a)
     if constexpr (std::is_same_v<T, float>) return sqrtf(a);
     else return sqrt(a);
 }
+// Square root of a positive normal number (sound speeds): hardware 1/sqrt
+// estimate, one coupled Goldschmidt step for g ~ sqrt(a), h ~ 1/(2 sqrt(a)),
+// then two Newton corrections g += h (a - g^2).  Without the rescaling of
+// denormal, zero and infinite arguments that the library square root carries.
+template <typename T> __device__ __forceinline__ T psqrt(T a)
+{
+    if constexpr (std::is_same_v<T, float>) {
+        return sqrtf(a);
+    } else {
+        const double y = __builtin_amdgcn_rsq(a);
+        double g = a * y, h = 0.5 * y;
+        const double r = fma(-h, g, 0.5);
+        g = fma(g, r, g);
+        h = fma(h, r, h);
+        double d = fma(-g, g, a);
+        g = fma(d, h, g);
+        d = fma(-g, g, a);
+        return fma(d, h, g);
+    }
+}
 template <typename T> __device__ __forceinline__ T dabs(T a)
 {
     if constexpr (std::is_same_v<T, float>) return fabsf(a);
@@ -133,6 +153,45 @@ __device__ __forceinline__ void hllc(const Gas<T>& G, const T* UL, const T* UR, 
     F[1] = (Ss * (SK * UK[1] - FK1) + SK * pst * nx) * iden;
     F[2] = (Ss * (SK * UK[2] - FK2) + SK * pst * nz) * iden;
     F[3] = (Ss * (SK * UK[3] - FK3)) * iden;
+}
+
+// The same HLLC flux for the normal +e_D of a Cartesian face (D = 1: x, D = 2: z),
+// with 1/rho of both states given (the callers reuse them).  A face with normal
+// -e_D is the mirror case, H(a, b; -e) = -H(b, a; +e), so every Cartesian face
+// (slip walls included, via a mirrored ghost state) needs only this form.
+template <typename T, int D>
+__device__ __forceinline__ void hllc_ax(const Gas<T>& G, const T* UL, const T* UR, T pL, T pR, T irL, T irR, T* F)
+{
+    constexpr int E = 3 - D;   // tangential momentum
+    const T rL = UL[0], rR = UR[0];
+    const T qL = UL[D] * irL, qR = UR[D] * irR;
+    const T cL = psqrt<T>(G.gamma * pL * irL), cR = psqrt<T>(G.gamma * pR * irR);
+    const T SL = fmin(qL - cL, qR - cR);
+    const T SR = fmax(qL + cL, qR + cR);
+    if (SL >= T(0)) {
+        F[0] = UL[D];
+        F[D] = UL[D] * qL + pL;
+        F[E] = UL[E] * qL;
+        F[3] = UL[3] * qL;
+        return;
+    }
+    if (SR <= T(0)) {
+        F[0] = UR[D];
+        F[D] = UR[D] * qR + pR;
+        F[E] = UR[E] * qR;
+        F[3] = UR[3] * qR;
+        return;
+    }
+    const T Ss = (pR - pL + rL * qL * (SL - qL) - rR * qR * (SR - qR)) * frcp<T>(rL * (SL - qL) - rR * (SR - qR));
+    const bool lk = Ss >= T(0);
+    const T SK = lk ? SL : SR, rK = lk ? rL : rR, qK = lk ? qL : qR, pK = lk ? pL : pR;
+    const T uD = lk ? UL[D] : UR[D], uE = lk ? UL[E] : UR[E], u3 = lk ? UL[3] : UR[3];
+    const T pst = pK + rK * (SK - qK) * (Ss - qK);
+    const T iden = frcp<T>(SK - Ss);
+    F[0] = (Ss * (SK * rK - uD)) * iden;
+    F[D] = (Ss * (SK * uD - (uD * qK + pK)) + SK * pst) * iden;
+    F[E] = (Ss * (SK * uE - uE * qK)) * iden;
+    F[3] = (Ss * (SK * u3 - u3 * qK)) * iden;
 }
 
 // Viscous flux F_v(U, G) . n = mu rho grad(U_c / rho) . n written with the
