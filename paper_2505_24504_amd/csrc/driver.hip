@@ -548,7 +548,7 @@ template <typename T> FvArgs<T> fv_args(const jfmg_problem* p, int l)
     FvArgs<T> A;
     const Level& L = p->lev[l];
     A.nxl = L.nx; A.nzl = L.nz; A.bc = p->cfg.bc; A.physics = p->cfg.physics; A.nc = L.nc;
-    A.hx = (T)L.hx; A.hz = (T)L.hz; A.area = (T)(L.hx * L.hz); A.g = (T)p->cfg.g; A.mu = (T)p->cfg.mu;
+    A.hx = (T)L.hx; A.hz = (T)L.hz; A.area = (T)(L.hx * L.hz); A.iarea = (T)(1.0 / (L.hx * L.hz)); A.g = (T)p->cfg.g; A.mu = (T)p->cfg.mu;
     A.gas = make_gas<T>(p->cfg);
     A.bgc = (const T*)L.bgc; A.bgf = (const T*)L.bgf; A.dbgf = (const T*)L.dbgf;
     A.pc = (const T*)L.pc; A.pf = (const T*)L.pf;

@@ -135,12 +135,18 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
             if constexpr (PERT) hx[it][c] = ok ? xp[c * nc + qh] : T(0);
         }
     }
-    T eps = T(0);
+    // eps = sqrt(eps_p) ||u + Ubar|| / ||x|| and adt / eps, from ||x|| and the stored 1/||u + Ubar||
+    T eps = T(0), sc = T(0);
     bool xzero = false;   // uniform: g'x = 0 for x = 0
     if constexpr (PERT) {
         const double xn2 = sum_partials<NTH>(xpart, xcount);   // ||x||^2, same order in every block
-        if (!(xn2 > 0.0)) xzero = true;
-        else eps = (T)(FdEps<T>::sqrt_eps * slots[LV_UTOT] / sqrt(xn2));
+        if (!(xn2 > 0.0)) {
+            xzero = true;
+        } else {
+            const double xn = psqrt(xn2);
+            eps = (T)(FdEps<T>::sqrt_eps * slots[LV_UTOT] * frcp(xn));
+            sc = (T)(adt * xn * (FdEps<T>::inv_sqrt_eps * slots[LV_IUTOT]));
+        }
     }
 
     if (!xzero) {
@@ -250,7 +256,7 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
     // ---- per cell ----
     T f[4] = {T(0), T(0), T(0), T(0)};
     if (valid && !xzero) {
-        const T iarea = T(1) / A.area;
+        const T iarea = A.iarea;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             T L = -(sFx[tj][ti + 1][c] - sFx[tj][ti][c]) - (sFz[tj + 1][ti][c] - sFz[tj][ti][c]);
@@ -285,7 +291,6 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
     } else {
         T Ax[4] = {T(0), T(0), T(0), T(0)};
         if (valid && !xzero) {
-            const T sc = (T)adt / eps;
 #pragma unroll
             for (int c = 0; c < 4; ++c) Ax[c] = own_x[c] - sc * (f[c] - own_f0[c]);
         }
@@ -447,6 +452,7 @@ fv_lin_finalize_kernel(const double* __restrict__ p, int nb, double* __restrict_
     m = block_max<256>(m, sh);
     if (threadIdx.x == 0) {
         slots[LV_UTOT] = sqrt(a);
+        slots[LV_IUTOT] = a > 0.0 ? 1.0 / sqrt(a) : 0.0;
         slots[LV_LAM] = m;
         slots[LV_DTAU] = cfl / (1.0 + adt * (m * (1.0 / hx + 1.0 / hz) + 2.0 * mu * (1.0 / (hx * hx) + 1.0 / (hz * hz))));
     }

@@ -12,12 +12,18 @@ namespace jfmg {
 
 // sqrt of the unit roundoff used in finite-difference steps: 2^-26 (FP64), 2^-11.5 (FP32)
 template <typename T> struct FdEps;
-template <> struct FdEps<double> { static constexpr double sqrt_eps = 1.4901161193847656e-08; };
-template <> struct FdEps<float> { static constexpr double sqrt_eps = 3.4526698300124393e-04; };
+template <> struct FdEps<double> {
+    static constexpr double sqrt_eps = 1.4901161193847656e-08;
+    static constexpr double inv_sqrt_eps = 1.0 / sqrt_eps;
+};
+template <> struct FdEps<float> {
+    static constexpr double sqrt_eps = 3.4526698300124393e-04;
+    static constexpr double inv_sqrt_eps = 1.0 / sqrt_eps;
+};
 
 // Gas constants plus the binomial coefficients C(gamma, k) used to evaluate
 // the equation of state around the background pressure (see pert_pressure).
-constexpr int GAS_NCOEF = 14;
+constexpr int GAS_NCOEF = 12;
 template <typename T> struct Gas {
     T gamma, R, p0;
     T cg[GAS_NCOEF];   // C(gamma, k), k = 0 .. GAS_NCOEF-1
@@ -82,8 +88,9 @@ template <typename T> __device__ __forceinline__ T frcp(T a)
 // evaluated at the total state rho theta = rtb (1 + s), s = (rho theta)' / rtb, as
 // p = pb (1 + s)^gamma with the background pressure pb = p0 (R rtb / p0)^gamma.
 // (1 + s)^gamma is the binomial series in Horner form for |s| <= 1/20 (truncation
-// below the unit roundoff: 14 terms in FP64, 7 in FP32) and pow otherwise; s = 0
-// returns pb exactly, so background and perturbed evaluations agree bitwise.
+// below the unit roundoff: 12 terms in FP64, <= 3e-19 for 1 < gamma <= 5/3; 7 in
+// FP32) and pow otherwise; s = 0 returns pb exactly, so background and perturbed
+// evaluations agree bitwise.
 template <typename T> __device__ __forceinline__ T pert_pressure(const Gas<T>& G, T rt1, T irtb, T pb)
 {
     const T s = rt1 * irtb;

@@ -62,7 +62,7 @@ struct DgArgs {
 template <typename T> struct FvArgs {
     int nxl, nzl, bc, physics;
     long nc;
-    T hx, hz, area, g, mu;
+    T hx, hz, area, iarea, g, mu;
     Gas<T> gas;
     const T* bgc;    // [nzl][4]   background at cell-centre z
     const T* bgf;    // [nzl+1][4] background at z-faces
@@ -72,7 +72,7 @@ template <typename T> struct FvArgs {
 };
 
 // device scalar slots of one FV level (doubles)
-enum { LV_UTOT = 0, LV_LAM = 1, LV_DTAU = 2, LV_NSLOT = 4 };
+enum { LV_UTOT = 0, LV_LAM = 1, LV_DTAU = 2, LV_IUTOT = 3, LV_NSLOT = 4 };   // LV_IUTOT = 1/||u + Ubar||
 
 // Members of a lock-step batch: n members, member m at byte offset m * ms from
 // member 0 in every per-member buffer (device workspace regions of equal layout).
