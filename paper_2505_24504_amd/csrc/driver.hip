@@ -470,7 +470,7 @@ size_t layout(const jfmg_config& c, char* base, F&& bind)
     size_t npart = (size_t)std::max<long>({la * (m + 2), 2 * fvblk, dgblk, 2048, 4096});
     bind("scal", cv.take(NSCAL * 8), 0);
     bind("partials", cv.take(npart * 8), npart);
-    const size_t fvp = (size_t)fvblk;
+    const size_t fvp = (size_t)std::max<long>(fvblk, transfer_grid(c.k, ne));   // FV stages, fused transfer
     bind("fvpart", cv.take(fvp * FVP_PER_LEVEL * c.mg_levels * 8), fvp);
     bind("bg_node", cv.take((size_t)c.nz * n1 * 4 * 8), 0);
     bind("dbg_node", cv.take((size_t)c.nz * n1 * 4 * 8), 0);
@@ -590,12 +590,33 @@ jfmg_status linearize(jfmg_problem* p, const double* U, double adt)
 struct MgState {
     int xi[MAXLEV];      // buffer holding x on each level
     bool xzero[MAXLEV];  // x is the zero vector (buffer content not valid)
+    int pre[MAXLEV];     // > 0: the first stage from x = 0 is already in buffer 1 (made by the
+                         // kernel that wrote b), with this many ||x||^2 partials
 };
 
 template <typename T> struct Mg {
     jfmg_problem* p;
     MgState s;
     double alpha[4];
+
+    void init()
+    {
+        const int S = p->cfg.rk_stages;
+        for (int j = 0; j < 4; ++j) alpha[j] = p->cfg.rk_alpha[j] > 0 ? p->cfg.rk_alpha[j] : 1.0 / (S - j);
+        for (int l = 0; l < MAXLEV; ++l) s.pre[l] = 0;
+    }
+    // the first stage of level l from x = 0 can be fused into the kernel that writes b
+    ZeroStage<T> zero_stage(int l, int nu_pre)
+    {
+        ZeroStage<T> z;
+        if (nu_pre > 0 && p->cfg.rk_stages >= 1) {
+            z.x1 = (T*)p->lev[l].buf[1];
+            z.slots = p->scal + S_LEV + 4 * l;
+            z.alpha = alpha[0];
+            z.red = Red{fvpart(p, l, 1), nullptr};
+        }
+        return z;
+    }
 
     void smooth(int l, int nu)
     {
@@ -609,6 +630,12 @@ template <typename T> struct Mg {
             for (int j = 0; j < S; ++j) {
                 const int out = oth[j & 1];
                 const int zero = (j == 0 && s.xzero[l]) ? 1 : 0;
+                if (zero && s.pre[l] > 0 && out == 1) {   // made by the producer of b
+                    p->xcnt[l][out] = s.pre[l];
+                    s.pre[l] = 0;
+                    prev = out;
+                    continue;
+                }
                 const T* x0 = s.xzero[l] ? nullptr : (const T*)L.buf[i0];   // null: x^(0) = 0
                 const double vb = 4.0 * L.nc * sizeof(T);
                 // algorithmic bytes: reads u, F0, x^(j-1), x^(0), b, writes x^(j) (no x^(0) when it is 0);
@@ -637,14 +664,18 @@ template <typename T> struct Mg {
             const FvArgs<T> A = fv_args<T>(p, l);
             Level& L = p->lev[l];
             Level& C = p->lev[l + 1];
-            // reads u, F0, x, b and writes the quarter-size coarse defect (x = 0: reads b only)
-            ProfScope ps(p, JFMG_K_FV_DEFECT, (s.xzero[l] ? 1.25 : 4.25) * 4.0 * L.nc * sizeof(T));
-            FvLaunch<T>::defect_restrict(A, (const T*)L.u, (const T*)L.F0, (const T*)L.buf[s.xi[l]], (const T*)L.b,
-                                         (T*)C.b, fvpart(p, l, s.xi[l]), p->xcnt[l][s.xi[l]],
-                                         p->scal + S_LEV + 4 * l, p->adt, s.xzero[l] ? 1 : 0, p->st, p->mb);
+            // reads u, F0, x, b and writes the quarter-size coarse defect (x = 0: reads b only),
+            // and with x != 0 the coarse level's first stage from zero as well
+            const ZeroStage<T> z0 = s.xzero[l] ? ZeroStage<T>{} : zero_stage(l + 1, k.e);
+            ProfScope ps(p, JFMG_K_FV_DEFECT, (s.xzero[l] ? 1.25 : (z0.x1 ? 4.5 : 4.25)) * 4.0 * L.nc * sizeof(T));
+            const int nb = FvLaunch<T>::defect_restrict(A, (const T*)L.u, (const T*)L.F0, (const T*)L.buf[s.xi[l]],
+                                                        (const T*)L.b, (T*)C.b, fvpart(p, l, s.xi[l]),
+                                                        p->xcnt[l][s.xi[l]], p->scal + S_LEV + 4 * l, p->adt,
+                                                        s.xzero[l] ? 1 : 0, p->st, p->mb, z0);
             if (!s.xzero[l]) p->mv_count[l]++;
             s.xzero[l + 1] = true;
             s.xi[l + 1] = 0;
+            s.pre[l + 1] = nb;
             for (int cyc = 0; cyc < k.cycle; ++cyc) cycle(l + 1);
             if (!s.xzero[l + 1]) {
                 if (s.xzero[l]) {
@@ -663,8 +694,6 @@ template <typename T> struct Mg {
     // x = MG(0, b) on the finest level; b must be in lev[0].b; result pointer returned
     T* run()
     {
-        const int S = p->cfg.rk_stages;
-        for (int j = 0; j < 4; ++j) alpha[j] = p->cfg.rk_alpha[j] > 0 ? p->cfg.rk_alpha[j] : 1.0 / (S - j);
         s.xi[0] = 0;
         s.xzero[0] = true;
         cycle(0);
@@ -679,12 +708,17 @@ template <typename T> struct Mg {
 template <typename T> jfmg_status mg_apply_t(jfmg_problem* p, double* r, double* z, int zslot, const double* rnrm2)
 {
     Level& L = p->lev[0];
-    {
-        ProfScope ps(p, JFMG_K_TRANSFER_T, (double)p->N * (8 + sizeof(T)) + (rnrm2 ? 8.0 * p->N : 0.0));
-        launch_transfer_T<T>(p->cfg.k, p->A, p->cfg.mass_fix, r, (T*)L.b, L.nx, p->st, rnrm2, rnrm2 ? r : nullptr,
-                             p->mb);
-    }
     Mg<T> mg{p};
+    mg.init();
+    {
+        // b = T r, and the finest level's first stage from zero in the same kernel
+        const ZeroStage<T> z0 = mg.zero_stage(0, p->key.c);
+        ProfScope ps(p, JFMG_K_TRANSFER_T,
+                     (double)p->N * (8 + (z0.x1 ? 2 : 1) * sizeof(T)) + (rnrm2 ? 8.0 * p->N : 0.0));
+        const int nb = launch_transfer_T<T>(p->cfg.k, p->A, p->cfg.mass_fix, r, (T*)L.b, L.nx, p->st, rnrm2,
+                                            rnrm2 ? r : nullptr, p->mb, z0);
+        if (z0.x1) mg.s.pre[0] = nb;
+    }
     T* x = mg.run();
     ProfScope ps(p, JFMG_K_TRANSFER_TINV, (double)p->N * (8 + sizeof(T)));
     launch_transfer_Tinv<T>(p->cfg.k, p->A, p->cfg.mass_fix, x, z, L.nx, red_at(p, zslot), p->st, p->mb);
@@ -1471,8 +1505,8 @@ jfmg_status jfmg_mg_fv(jfmg_problem* p, const void* b, void* x)
     const size_t bytes = (p->prec == 32 ? 4 : 8) * 4 * L.nc;
     HIPCHK(p, hipMemcpyAsync(L.b, b, bytes, hipMemcpyDeviceToDevice, p->st));
     void* r;
-    if (p->prec == 32) { Mg<float> mg{p}; r = mg.run(); }
-    else { Mg<double> mg{p}; r = mg.run(); }
+    if (p->prec == 32) { Mg<float> mg{p}; mg.init(); r = mg.run(); }
+    else { Mg<double> mg{p}; mg.init(); r = mg.run(); }
     HIPCHK(p, hipMemcpyAsync(x, r, bytes, hipMemcpyDeviceToDevice, p->st));
     return check_launch(p);
 }

@@ -64,13 +64,15 @@ enum { FVM_LIN = 0, FVM_STAGE = 1, FVM_MATVEC = 2, FVM_DEFECT = 3 };
 //   LIN     out = F0 = f~(u); ||u + Ubar||^2 and max(|v| + c) -> level slots, dtau
 //   STAGE   out = x0 + alpha_j dtau (b - g'x), g'x = x - adt/eps (f~(u + eps x) - F0)
 //   MATVEC  out = g'x
-//   DEFECT  out(coarse) = R(g'x - b), 2x2 agglomeration inside the tile
+//   DEFECT  out(coarse) = R(g'x - b), 2x2 agglomeration inside the tile; with out2 also
+//           the coarse level's first RK stage from zero, out2 = alpha_j dtau_c out (dtau_c in
+//           slots2), and its ||.||^2 block partials into red
 template <typename T, int TX, int TZ, int NTH, int WPE, bool LATE, bool ZREV, bool MB, int MODE>
 __global__ void __launch_bounds__(NTH, WPE)
 fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, const T* __restrict__ xp,
-               const T* __restrict__ x0, const T* __restrict__ b, T* __restrict__ out,
-               const double* __restrict__ xpart, int xcount, double* __restrict__ slots, double alpha_j,
-               double adt, double cfl, Red red, long ms)
+               const T* __restrict__ x0, const T* __restrict__ b, T* __restrict__ out, T* __restrict__ out2,
+               const double* __restrict__ xpart, int xcount, double* __restrict__ slots,
+               const double* __restrict__ slots2, double alpha_j, double adt, double cfl, Red red, long ms)
 {
     if constexpr (MB) {   // member blockIdx.z of a lock-step batch
         u = mbr(u, ms);
@@ -79,6 +81,8 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
         x0 = mbr(x0, ms);
         b = mbr(b, ms);
         out = mbr(out, ms);
+        out2 = mbr(out2, ms);
+        slots2 = mbr(slots2, ms);
         xpart = mbr(xpart, ms);
         slots = mbr(slots, ms);
         red = mbr(red, ms);
@@ -316,13 +320,23 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
 #pragma unroll
                 for (int c = 0; c < 4; ++c) sw[c][tj][ti] = Ax[c] - own_b[c];
             __syncthreads();
+            double nrm = 0.0;
             if (valid && !(ti & 1) && !(tj & 1)) {
                 const int nxc = nxl / 2;
                 const long ncc = (long)nxc * (nzl / 2), qc = (long)(J / 2) * nxc + I / 2;
+                const T s1 = out2 ? (T)(alpha_j * slots2[LV_DTAU]) : T(0);
 #pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    out[c * ncc + qc] = ((sw[c][tj][ti] + sw[c][tj][ti + 1]) + (sw[c][tj + 1][ti] + sw[c][tj + 1][ti + 1])) * T(0.25);
+                for (int c = 0; c < 4; ++c) {
+                    const T r = ((sw[c][tj][ti] + sw[c][tj][ti + 1]) + (sw[c][tj + 1][ti] + sw[c][tj + 1][ti + 1])) * T(0.25);
+                    out[c * ncc + qc] = r;
+                    if (out2) {
+                        const T v = s1 * r;
+                        out2[c * ncc + qc] = v;
+                        nrm += (double)v * (double)v;
+                    }
+                }
             }
+            if (out2) put_partial<NTH>(red, nrm);
         }
     }
 }
@@ -465,29 +479,29 @@ static inline dim3 tile_grid(int nx, int nz, int members = 1)
 
 template <typename T, int TX, int TZ, int NTH, int WPE, bool LATE, bool ZREV, int MODE>
 static int tile_launch_shape(const FvArgs<T>& A, const T* u, const T* F0, const T* xp, const T* x0, const T* b,
-                             T* out, const double* xpart, int xcount, double* slots, double alpha_j, double adt,
-                             double cfl, Red red, hipStream_t st, const Mb& mb)
+                             T* out, T* out2, const double* xpart, int xcount, double* slots, const double* slots2,
+                             double alpha_j, double adt, double cfl, Red red, hipStream_t st, const Mb& mb)
 {
     const dim3 g((unsigned)((A.nxl + TX - 1) / TX), (unsigned)((A.nzl + TZ - 1) / TZ), (unsigned)mb.n);
     if (mb.n > 1)
         timed_launch(fv_tile_kernel<T, TX, TZ, NTH, WPE, LATE, ZREV, true, MODE>, g, dim3(NTH), st, A, u, F0, xp, x0, b,
-                     out, xpart, xcount, slots, alpha_j, adt, cfl, red, mb.ms);
+                     out, out2, xpart, xcount, slots, slots2, alpha_j, adt, cfl, red, mb.ms);
     else
         timed_launch(fv_tile_kernel<T, TX, TZ, NTH, WPE, LATE, ZREV, false, MODE>, g, dim3(NTH), st, A, u, F0, xp, x0,
-                     b, out, xpart, xcount, slots, alpha_j, adt, cfl, red, 0L);
+                     b, out, out2, xpart, xcount, slots, slots2, alpha_j, adt, cfl, red, 0L);
     return (int)(g.x * g.y);
 }
 
 template <typename T, int MODE>
 static int tile_launch(const FvArgs<T>& A, const T* u, const T* F0, const T* xp, const T* x0, const T* b, T* out,
                        const double* xpart, int xcount, double* slots, double alpha_j, double adt, double cfl,
-                       Red red, hipStream_t st, const Mb& mb)
+                       Red red, hipStream_t st, const Mb& mb, T* out2 = nullptr, const double* slots2 = nullptr)
 {
     if (fv_wide_tile(A.nxl))
         return tile_launch_shape<T, FV_WIDE_TX, FV_WIDE_TZ, FV_WIDE_NTH, FV_WIDE_WPE, FV_WIDE_LATE, FV_WIDE_ZREV, MODE>(
-            A, u, F0, xp, x0, b, out, xpart, xcount, slots, alpha_j, adt, cfl, red, st, mb);
+            A, u, F0, xp, x0, b, out, out2, xpart, xcount, slots, slots2, alpha_j, adt, cfl, red, st, mb);
     return tile_launch_shape<T, FV_SMALL_TX, FV_SMALL_TZ, FV_SMALL_NTH, FV_SMALL_WPE, false, FV_SMALL_ZREV, MODE>(
-        A, u, F0, xp, x0, b, out, xpart, xcount, slots, alpha_j, adt, cfl, red, st, mb);
+        A, u, F0, xp, x0, b, out, out2, xpart, xcount, slots, slots2, alpha_j, adt, cfl, red, st, mb);
 }
 
 template <typename T>
@@ -521,17 +535,18 @@ void FvLaunch<T>::matvec(const FvArgs<T>& A, const T* u, const T* F0, const T* x
                                adt, 0.0, Red{nullptr, nullptr}, st, mb);
 }
 template <typename T>
-void FvLaunch<T>::defect_restrict(const FvArgs<T>& A, const T* u, const T* F0, const T* x, const T* b, T* rc,
-                                  const double* xpart, int xcount, const double* slots, double adt, int zero,
-                                  hipStream_t st, const Mb& mb)
+int FvLaunch<T>::defect_restrict(const FvArgs<T>& A, const T* u, const T* F0, const T* x, const T* b, T* rc,
+                                 const double* xpart, int xcount, const double* slots, double adt, int zero,
+                                 hipStream_t st, const Mb& mb, const ZeroStage<T>& z0)
 {
     if (zero) {
         const dim3 g((unsigned)((A.nxl / 2 + 63) / 64), (unsigned)((A.nzl / 2 + 3) / 4), (unsigned)mb.n);
         timed_launch(fv_restrict_neg_kernel<T>, g, dim3(256), st, A, b, rc, mb.ms);
-        return;
+        return 0;
     }
-    tile_launch<T, FVM_DEFECT>(A, u, F0, x, nullptr, b, rc, xpart, xcount, const_cast<double*>(slots), 0.0, adt, 0.0,
-                               Red{nullptr, nullptr}, st, mb);
+    const int nb = tile_launch<T, FVM_DEFECT>(A, u, F0, x, nullptr, b, rc, xpart, xcount, const_cast<double*>(slots),
+                                              z0.alpha, adt, 0.0, z0.red, st, mb, z0.x1, z0.slots);
+    return z0.x1 ? nb : 0;
 }
 template <typename T>
 int FvLaunch<T>::prolong_correct(const FvArgs<T>& Af, T* x, const T* v, Red red, hipStream_t st, const Mb& mb)

@@ -98,9 +98,19 @@ void launch_norm2_total(int k, const DgArgs& A, const double* U, Red red, hipStr
 int norm_total_grid(long n);
 
 // ---- transfers (transfer.hip) ----
+// The first RK stage of the finest level from x = 0, x1 = alpha dtau u (dtau in
+// slots[LV_DTAU]) with ||x1||^2 block partials into red.partials, can be produced
+// by the same kernel (x1 != nullptr); the return value is the number of blocks.
+template <typename T> struct ZeroStage {
+    T* x1 = nullptr;
+    const double* slots = nullptr;
+    double alpha = 0.0;
+    Red red{nullptr, nullptr};
+};
 template <typename T>
-void launch_transfer_T(int k, const DgArgs& A, int mass_fix, const double* U, T* u, int nxf, hipStream_t st,
-                       const double* snrm2 = nullptr, double* Us = nullptr, const Mb& mb = Mb{});
+int launch_transfer_T(int k, const DgArgs& A, int mass_fix, const double* U, T* u, int nxf, hipStream_t st,
+                      const double* snrm2 = nullptr, double* Us = nullptr, const Mb& mb = Mb{},
+                      const ZeroStage<T>& z0 = ZeroStage<T>{});
 template <typename T>
 void launch_transfer_Tinv(int k, const DgArgs& A, int mass_fix, const T* u, double* U, int nxf, Red red,
                           hipStream_t st, const Mb& mb = Mb{});
@@ -123,9 +133,12 @@ template <typename T> struct FvLaunch {
                      Red red, hipStream_t st, const Mb& mb = Mb{});
     static void matvec(const FvArgs<T>& A, const T* u, const T* F0, const T* x, T* out, const double* xpart,
                        int xcount, const double* slots, double adt, hipStream_t st, const Mb& mb = Mb{});
-    static void defect_restrict(const FvArgs<T>& A, const T* u, const T* F0, const T* x, const T* b, T* rc,
-                                const double* xpart, int xcount, const double* slots, double adt, int zero,
-                                hipStream_t st, const Mb& mb = Mb{});
+    // coarse defect rc = R(g'x - b) (x = 0: R(-b)); with z0.x1 the first RK stage of the
+    // coarse level from x = 0 as well (z0.slots = the coarse level's slots); returns the
+    // number of ||x1||^2 partials (0 when z0.x1 is null or x = 0)
+    static int defect_restrict(const FvArgs<T>& A, const T* u, const T* F0, const T* x, const T* b, T* rc,
+                               const double* xpart, int xcount, const double* slots, double adt, int zero,
+                               hipStream_t st, const Mb& mb = Mb{}, const ZeroStage<T>& z0 = ZeroStage<T>{});
     static int prolong_correct(const FvArgs<T>& Af, T* x, const T* v, Red red, hipStream_t st, const Mb& mb = Mb{});
     static void restrict_(const FvArgs<T>& Af, const T* f, T* c, hipStream_t st, const Mb& mb = Mb{});
     static void prolong(const FvArgs<T>& Af, const T* c, T* f, hipStream_t st, const Mb& mb = Mb{});

@@ -28,15 +28,20 @@ __device__ __forceinline__ long subcell_index(int ex, int ez, int i, int j, int 
 // snrm2 != nullptr: the input is U / ||U|| (||U||^2 = snrm2[0]); the scaled DG
 // vector is also written back to Us (may alias U: every value is read and
 // written by the same thread).
+// With x1 != nullptr the kernel also takes the first RK stage of the finest FV
+// level from x = 0: x1 = (alpha dtau) u and the block partials of ||x1||^2.
 template <int N1, typename T>
 __global__ void __launch_bounds__(TrShape<N1>::NTH)
 transfer_T_kernel(DgArgs A, int mass_fix, const double* U, T* __restrict__ u, int nxf, const double* snrm2,
-                  double* Us, long ms)
+                  double* Us, T* __restrict__ x1, const double* __restrict__ slots, double alpha, Red red, long ms)
 {
     U = mbr(U, ms);
     u = mbr(u, ms);
     snrm2 = mbr(snrm2, ms);
     Us = mbr(Us, ms);
+    x1 = mbr(x1, ms);
+    slots = mbr(slots, ms);
+    red = mbr(red, ms);
     constexpr int NP = TrShape<N1>::NP, EPB = TrShape<N1>::EPB;
     __shared__ double sU[EPB][4][NP];
     __shared__ double sH[EPB][4][NP];
@@ -82,9 +87,11 @@ transfer_T_kernel(DgArgs A, int mass_fix, const double* U, T* __restrict__ u, in
     if (act)
         for (int c = 0; c < 4; ++c) sU[le][c][nd] = tv[c];
     __syncthreads();
+    double nrm = 0.0;
     if (valid) {
         const int ez = (int)(e / A.nx), ex = (int)(e - (long)ez * A.nx);
         const long o = subcell_index(ex, ez, i, j, N1, nxf);
+        const T s1 = x1 ? (T)(alpha * slots[LV_DTAU]) : T(0);
         for (int c = 0; c < 4; ++c) {
             double shift = 0.0;
             if (mass_fix) {
@@ -99,9 +106,16 @@ transfer_T_kernel(DgArgs A, int mass_fix, const double* U, T* __restrict__ u, in
                     }
                 shift = mean / NP - quad;
             }
-            u[c * nc + o] = (T)(tv[c] - shift);
+            const T b = (T)(tv[c] - shift);
+            u[c * nc + o] = b;
+            if (x1) {
+                const T v = s1 * b;
+                x1[c * nc + o] = v;
+                nrm += (double)v * (double)v;
+            }
         }
     }
+    if (x1) put_partial<TrShape<N1>::NTH>(red, nrm);
 }
 
 template <int N1, typename T>
@@ -182,13 +196,20 @@ int transfer_grid(int k, long ne)
 }
 
 template <typename T>
-void launch_transfer_T(int k, const DgArgs& A, int mass_fix, const double* U, T* u, int nxf, hipStream_t st,
-                       const double* snrm2, double* Us, const Mb& mb)
+int launch_transfer_T(int k, const DgArgs& A, int mass_fix, const double* U, T* u, int nxf, hipStream_t st,
+                      const double* snrm2, double* Us, const Mb& mb, const ZeroStage<T>& z0)
 {
     const dim3 g(transfer_grid(k, A.ne), 1, mb.n);
-    if (k == 1) timed_launch(transfer_T_kernel<2, T>, g, dim3(TrShape<2>::NTH), st, A, mass_fix, U, u, nxf, snrm2, Us, mb.ms);
-    else if (k == 2) timed_launch(transfer_T_kernel<3, T>, g, dim3(TrShape<3>::NTH), st, A, mass_fix, U, u, nxf, snrm2, Us, mb.ms);
-    else timed_launch(transfer_T_kernel<4, T>, g, dim3(TrShape<4>::NTH), st, A, mass_fix, U, u, nxf, snrm2, Us, mb.ms);
+    if (k == 1)
+        timed_launch(transfer_T_kernel<2, T>, g, dim3(TrShape<2>::NTH), st, A, mass_fix, U, u, nxf, snrm2, Us, z0.x1,
+                     z0.slots, z0.alpha, z0.red, mb.ms);
+    else if (k == 2)
+        timed_launch(transfer_T_kernel<3, T>, g, dim3(TrShape<3>::NTH), st, A, mass_fix, U, u, nxf, snrm2, Us, z0.x1,
+                     z0.slots, z0.alpha, z0.red, mb.ms);
+    else
+        timed_launch(transfer_T_kernel<4, T>, g, dim3(TrShape<4>::NTH), st, A, mass_fix, U, u, nxf, snrm2, Us, z0.x1,
+                     z0.slots, z0.alpha, z0.red, mb.ms);
+    return (int)g.x;
 }
 
 template <typename T>
@@ -202,10 +223,10 @@ void launch_transfer_Tinv(int k, const DgArgs& A, int mass_fix, const T* u, doub
     if (red.out) launch_finalize(red.partials, (int)g.x, 1, red.out, st, Gate{}, mb);
 }
 
-template void launch_transfer_T<double>(int, const DgArgs&, int, const double*, double*, int, hipStream_t,
-                                        const double*, double*, const Mb&);
-template void launch_transfer_T<float>(int, const DgArgs&, int, const double*, float*, int, hipStream_t,
-                                       const double*, double*, const Mb&);
+template int launch_transfer_T<double>(int, const DgArgs&, int, const double*, double*, int, hipStream_t,
+                                       const double*, double*, const Mb&, const ZeroStage<double>&);
+template int launch_transfer_T<float>(int, const DgArgs&, int, const double*, float*, int, hipStream_t,
+                                      const double*, double*, const Mb&, const ZeroStage<float>&);
 template void launch_transfer_Tinv<double>(int, const DgArgs&, int, const double*, double*, int, Red, hipStream_t,
                                            const Mb&);
 template void launch_transfer_Tinv<float>(int, const DgArgs&, int, const float*, double*, int, Red, hipStream_t,
