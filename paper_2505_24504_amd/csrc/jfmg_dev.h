@@ -87,16 +87,24 @@ template <typename T> __device__ __forceinline__ T frcp(T a)
 // Equation of state of the potential-temperature form, p = p0 (R rho theta / p0)^gamma,
 // evaluated at the total state rho theta = rtb (1 + s), s = (rho theta)' / rtb, as
 // p = pb (1 + s)^gamma with the background pressure pb = p0 (R rtb / p0)^gamma.
-// (1 + s)^gamma is the binomial series in Horner form for |s| <= 1/20 (truncation
-// below the unit roundoff: 12 terms in FP64, <= 3e-19 for 1 < gamma <= 5/3; 7 in
-// FP32) and pow otherwise; s = 0 returns pb exactly, so background and perturbed
-// evaluations agree bitwise.
+// (1 + s)^gamma is the binomial series in Horner form, truncated below the unit
+// roundoff for 1 < gamma <= 5/3: 6 terms for |s| <= 2^-10 (atmospheric pressure
+// perturbations; truncation <= 6e-21) and 12 for |s| <= 1/20 (<= 3e-19) in FP64,
+// 4 and 7 terms in FP32; pow beyond.  s = 0 returns pb exactly, so background and
+// perturbed evaluations agree bitwise.
 template <typename T> __device__ __forceinline__ T pert_pressure(const Gas<T>& G, T rt1, T irtb, T pb)
 {
+    constexpr bool F32 = std::is_same_v<T, float>;
     const T s = rt1 * irtb;
+    const T as = dabs<T>(s);
     T f;
-    if (dabs<T>(s) <= T(0.05)) {
-        constexpr int n = std::is_same_v<T, float> ? 7 : GAS_NCOEF;
+    if (as <= T(1.0 / 1024.0)) {
+        constexpr int n = F32 ? 4 : 6;
+        f = G.cg[n - 1];
+#pragma unroll
+        for (int k = n - 2; k >= 0; --k) f = f * s + G.cg[k];
+    } else if (as <= T(0.05)) {
+        constexpr int n = F32 ? 7 : GAS_NCOEF;
         f = G.cg[n - 1];
 #pragma unroll
         for (int k = n - 2; k >= 0; --k) f = f * s + G.cg[k];
