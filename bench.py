@@ -170,6 +170,10 @@ def ensemble_forms():
         U = torch.cat([single.initial_state(pert) for _, pert, _ in ms])
         del single
         gslots.append(b.admit(dict(ms[0][0], batch=len(ms)), ms[0][2], None, U))
+    # FV tile shapes of each lock-step problem by the autotuner (setup, not timed)
+    t0 = time.perf_counter()
+    tiles = [b.autotune(s) for s in gslots]
+    el_tune = time.perf_counter() - t0
     _sync()
     t0 = time.perf_counter()
     b.run()
@@ -179,6 +183,7 @@ def ensemble_forms():
     ok_l = sum(len(ms) for ms, (f_, _, st) in zip(groups.values(), polled_l) if f_ and st["status"] == 0)
     return {"ensemble_lockstep_fp32": {"value": work / el_l, "seconds": el_l, "members_ok": ok_l,
                                        "groups": [len(ms) for ms in groups.values()],
+                                       "tiles": tiles, "autotune_seconds": el_tune,
                                        "lockstep_gmres_its": [st["gmres_its"] for _, _, st in polled_l]},
             "ensemble_batched_fp32": {"value": work / el_b, "seconds": el_b, "members_ok": ok_b,
                                       "gmres_its": its_b, "stall_stops": stalls_b},

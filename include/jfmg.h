@@ -154,9 +154,10 @@ jfmg_status jfmg_mg_apply(jfmg_problem* p, const double* r, double* z);
    tests; a member that has converged takes no further part (its updates are
    zero).  Each member's result is bitwise the one it gives as a single problem.
    State vectors passed in are B * N doubles, members back to back.  Only
-   jfmg_implicit_step and jfmg_initial_state (the same state for every member)
-   accept batched problems; the other calls return EINVAL.  Stats count the
-   lock-step iterations. */
+   jfmg_implicit_step, jfmg_initial_state (the same state for every member),
+   jfmg_linearize (every member at its own state), the tile-shape calls and
+   jfmg_autotune accept batched problems; the other calls return EINVAL.  Stats
+   count the lock-step iterations. */
 
 /* One implicit step U^n -> U^{n+1} in place (implicit Euler or SDIRK2), each
    stage by inexact Newton with Eisenstat-Walker forcing and right-preconditioned
@@ -184,6 +185,38 @@ jfmg_status jfmg_fv_matvec(jfmg_problem* p, int level, const void* x, void* out)
 jfmg_status jfmg_mg_fv(jfmg_problem* p, const void* b, void* x);
 /* fv_to_dg[J*nxf + I] = e*(k+1)^2 + node of the DG node whose subcell is (I,J). */
 jfmg_status jfmg_subgrid_map(jfmg_problem* p, int* fv_to_dg);
+
+/* ---- tile shapes of the FV operator kernels, per multigrid level ----
+   The smoother stage, matvec, defect and linearization kernels of a level (the
+   FV operator of Sec. "Multigrid preconditioner for finite volume
+   approximations") run with one of these work-group tiles of cells:
+     JFMG_TILE_64x4  256 threads, one wave per 64-cell row
+     JFMG_TILE_64x8  512 threads, one wave per 64-cell row
+     JFMG_TILE_16x4  256 threads, every face of the tile on its own thread
+     JFMG_TILE_8x4   128 threads, every face of the tile on its own thread
+   A new problem uses 64x4 on levels at least 512 cells wide and 16x4 below.
+   Shapes change the order of the partial sums of the FD step norms only, so
+   results agree to rounding; the same shapes give bitwise the same results. */
+typedef enum {
+    JFMG_TILE_64x4 = 0,
+    JFMG_TILE_64x8 = 1,
+    JFMG_TILE_16x4 = 2,
+    JFMG_TILE_8x4 = 3,
+    JFMG_TILE_NSHAPE = 4
+} jfmg_tile;
+/* shapes: host array of mg_levels entries (finest level first). */
+jfmg_status jfmg_get_tiles(const jfmg_problem* p, int* shapes);
+/* EINVAL for an unknown shape (nothing changed).  Drops captured HIP graphs. */
+jfmg_status jfmg_set_tiles(jfmg_problem* p, const int* shapes);
+/* Autotuner: on every level, time every shape with `reps` back-to-back launches
+   (after one warm-up launch) of the smoother stage kernel at the current
+   linearization state, with a fixed nonzero test vector, and keep the fastest.
+   A lock-step batch times all its members in each launch.  shapes (mg_levels
+   entries) receives the choice and times_us (mg_levels * JFMG_TILE_NSHAPE
+   entries, level-major) the mean launch time in microseconds; either may be
+   NULL.  ESTATE without jfmg_linearize; EINVAL for reps outside 1..1000.
+   Synchronizes the stream and overwrites the multigrid work vectors. */
+jfmg_status jfmg_autotune(jfmg_problem* p, int reps, int* shapes, double* times_us);
 
 /* ---- kernel-class timing (benchmark instrumentation) ----
    When a class's bit is set in class_mask, every launch of that class records

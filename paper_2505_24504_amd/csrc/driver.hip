@@ -270,6 +270,7 @@ constexpr int FVP_PER_LEVEL = 3;
 struct Level {
     int nx, nz;
     long nc;
+    int tile;   // jfmg_tile of the FV operator kernels
     double hx, hz;
     void* u;
     void* F0;
@@ -552,6 +553,7 @@ template <typename T> FvArgs<T> fv_args(const jfmg_problem* p, int l)
     A.gas = make_gas<T>(p->cfg);
     A.bgc = (const T*)L.bgc; A.bgf = (const T*)L.bgf; A.dbgf = (const T*)L.dbgf;
     A.pc = (const T*)L.pc; A.pf = (const T*)L.pf;
+    A.tile = L.tile;
     return A;
 }
 
@@ -641,7 +643,7 @@ template <typename T> struct Mg {
                 // algorithmic bytes: reads u, F0, x^(j-1), x^(0), b, writes x^(j) (no x^(0) when it is 0);
                 // the zero-start stage reads b and writes x^(1)
                 const int cls = zero ? JFMG_K_FV_STAGE_ZERO
-                                     : (fv_wide_tile(L.nx) ? JFMG_K_FV_STAGE : JFMG_K_FV_STAGE_SMALL);
+                                     : (fv_wide_tile(L.tile) ? JFMG_K_FV_STAGE : JFMG_K_FV_STAGE_SMALL);
                 ProfScope ps(p, cls, zero ? 2 * vb : (x0 ? 6 : 5) * vb);
                 p->xcnt[l][out] = FvLaunch<T>::stage(
                     A, (const T*)L.u, (const T*)L.F0, (const T*)L.buf[prev], x0, (const T*)L.b, (T*)L.buf[out],
@@ -1078,6 +1080,60 @@ jfmg_status newton_stage(jfmg_problem* p, const double* Ubar, double adt, jfmg_s
 // ===========================================================================
 // C-ABI
 // ===========================================================================
+namespace {
+// Time the smoother stage kernel of every level in every tile shape (see jfmg_autotune).
+template <typename T> jfmg_status autotune_t(jfmg_problem* p, int reps, int* shapes, double* times_us)
+{
+    hipStream_t st = p->st;
+    hipEvent_t e0, e1;
+    HIPCHK(p, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(p, JFMG_EDEVICE, "hipEventCreate failed");
+    }
+    jfmg_status res = JFMG_OK;
+    for (int l = 0; l < p->nlev && res == JFMG_OK; ++l) {
+        Level& L = p->lev[l];
+        const long n = 4 * L.nc;
+        // test vector in buffer 0 (fixed pattern of O(1) values) and its norm partials
+        launch_fill_pattern((T*)L.buf[0], n, st, p->mb);
+        FvLaunch<T>::norm2((const T*)L.buf[0], n, Red{fvpart(p, l, 0), nullptr}, st, p->mb);
+        const int xc = FvLaunch<T>::norm_blocks(n);
+        int best = L.tile;
+        float best_ms = 0.0f;
+        for (int sh = 0; sh < JFMG_TILE_NSHAPE; ++sh) {
+            FvArgs<T> A = fv_args<T>(p, l);
+            A.tile = sh;
+            auto launch = [&]() {
+                FvLaunch<T>::stage(A, (const T*)L.u, (const T*)L.F0, (const T*)L.buf[0], (const T*)L.buf[0],
+                                   (const T*)L.buf[0], (T*)L.buf[1], fvpart(p, l, 0), xc, p->scal + S_LEV + 4 * l,
+                                   1.0, p->adt, 0, Red{fvpart(p, l, 1), nullptr}, st, p->mb);
+            };
+            launch();
+            if (hipEventRecord(e0, st) != hipSuccess) { res = fail(p, JFMG_EDEVICE, "hipEventRecord failed"); break; }
+            for (int r = 0; r < reps; ++r) launch();
+            float ms = 0.0f;
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                res = fail(p, JFMG_EDEVICE, "event timing failed");
+                break;
+            }
+            if (times_us) times_us[l * JFMG_TILE_NSHAPE + sh] = 1e3 * ms / reps;
+            if (sh == 0 || ms < best_ms) { best = sh; best_ms = ms; }
+        }
+        if (res == JFMG_OK) {
+            L.tile = best;
+            if (shapes) shapes[l] = best;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    invalidate_graphs(p);
+    if (res) return res;
+    return check_launch(p);
+}
+}  // namespace
+
 extern "C" {
 
 jfmg_status jfmg_config_default(jfmg_config* c)
@@ -1186,6 +1242,7 @@ jfmg_status jfmg_create_problem(const jfmg_config* cfg, void* workspace, size_t 
     for (int l = 0; l < p->nlev; ++l) {
         Level& L = p->lev[l];
         L.nx = nxl; L.nz = nzl; L.nc = (long)nxl * nzl;
+        L.tile = fv_default_tile(nxl);
         L.hx = (cfg->x1 - cfg->x0) / nxl;
         L.hz = (cfg->z1 - cfg->z0) / nzl;
         nxl /= 2;
@@ -1321,7 +1378,7 @@ jfmg_status jfmg_initial_state(jfmg_problem* p, const jfmg_perturbation* q, doub
 jfmg_status jfmg_residual(jfmg_problem* p, const double* U, double* out, int apply_minv)
 {
     if (!p || !U || !out) return fail(p, JFMG_EINVAL, "null argument");
-    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step and jfmg_initial_state");
+    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step, jfmg_initial_state, jfmg_linearize and the tile calls");
     launch_dg(p->cfg.k, p->cfg.physics == 1, apply_minv ? 1 : 0, p->A, U, nullptr, nullptr, out, nullptr, nullptr, 0,
               0.0, no_red(), p->st);
     return check_launch(p);
@@ -1331,21 +1388,26 @@ jfmg_status jfmg_stage_residual(jfmg_problem* p, const double* U, const double* 
                                 double* norm)
 {
     if (!p || !U || !Ubar || !G) return fail(p, JFMG_EINVAL, "null argument");
-    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step and jfmg_initial_state");
+    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step, jfmg_initial_state, jfmg_linearize and the tile calls");
     return stage_residual(p, U, Ubar, alpha_dt, G, norm);
 }
 
 jfmg_status jfmg_linearize(jfmg_problem* p, const double* U, double alpha_dt)
 {
     if (!p || !U) return fail(p, JFMG_EINVAL, "null argument");
-    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step and jfmg_initial_state");
+    if (p->mb.n > 1) {   // caller's members back to back -> member-strided workspace
+        const size_t vb = sizeof(double) * p->N;
+        HIPCHK(p, hipMemcpy2DAsync(p->Ulin, (size_t)p->mb.ms, U, vb, vb, (size_t)p->mb.n, hipMemcpyDeviceToDevice,
+                                   p->st));
+        return linearize(p, p->Ulin, alpha_dt);
+    }
     return linearize(p, U, alpha_dt);
 }
 
 jfmg_status jfmg_jvp(jfmg_problem* p, const double* y, double* out)
 {
     if (!p || !y || !out) return fail(p, JFMG_EINVAL, "null argument");
-    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step and jfmg_initial_state");
+    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step, jfmg_initial_state, jfmg_linearize and the tile calls");
     if (!p->have_lin) return fail(p, JFMG_ESTATE, "jfmg_jvp needs jfmg_linearize first");
     launch_norm2(y, p->N, red_at(p, S_Y), p->st);
     jvp_slot(p, y, out, S_Y);
@@ -1355,7 +1417,7 @@ jfmg_status jfmg_jvp(jfmg_problem* p, const double* y, double* out)
 jfmg_status jfmg_mg_apply(jfmg_problem* p, const double* r, double* z)
 {
     if (!p || !r || !z) return fail(p, JFMG_EINVAL, "null argument");
-    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step and jfmg_initial_state");
+    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step, jfmg_initial_state, jfmg_linearize and the tile calls");
     if (!p->have_lin) return fail(p, JFMG_ESTATE, "jfmg_mg_apply needs jfmg_linearize first");
     return precond(p, const_cast<double*>(r), z, S_TMP);   // r is written only when normalizing
 }
@@ -1430,7 +1492,7 @@ jfmg_status jfmg_implicit_step(jfmg_problem* p, double* U, jfmg_stats* stats)
 jfmg_status jfmg_transfer(jfmg_problem* p, int dir, const void* in, void* out)
 {
     if (!p || !in || !out || (dir != 0 && dir != 1)) return fail(p, JFMG_EINVAL, "bad argument");
-    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step and jfmg_initial_state");
+    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step, jfmg_initial_state, jfmg_linearize and the tile calls");
     const int nxf = p->lev[0].nx;
     if (dir == 0) {
         if (p->prec == 32) launch_transfer_T<float>(p->cfg.k, p->A, p->cfg.mass_fix, (const double*)in, (float*)out, nxf, p->st);
@@ -1445,7 +1507,7 @@ jfmg_status jfmg_transfer(jfmg_problem* p, int dir, const void* in, void* out)
 jfmg_status jfmg_restrict(jfmg_problem* p, int fine_level, const void* fine, void* coarse)
 {
     if (!p || !fine || !coarse || fine_level < 0 || fine_level + 1 >= p->nlev) return fail(p, JFMG_EINVAL, "bad argument");
-    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step and jfmg_initial_state");
+    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step, jfmg_initial_state, jfmg_linearize and the tile calls");
     if (p->prec == 32) FvLaunch<float>::restrict_(fv_args<float>(p, fine_level), (const float*)fine, (float*)coarse, p->st);
     else FvLaunch<double>::restrict_(fv_args<double>(p, fine_level), (const double*)fine, (double*)coarse, p->st);
     return check_launch(p);
@@ -1454,7 +1516,7 @@ jfmg_status jfmg_restrict(jfmg_problem* p, int fine_level, const void* fine, voi
 jfmg_status jfmg_prolong(jfmg_problem* p, int coarse_level, const void* coarse, void* fine)
 {
     if (!p || !fine || !coarse || coarse_level < 1 || coarse_level >= p->nlev) return fail(p, JFMG_EINVAL, "bad argument");
-    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step and jfmg_initial_state");
+    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step, jfmg_initial_state, jfmg_linearize and the tile calls");
     if (p->prec == 32) FvLaunch<float>::prolong(fv_args<float>(p, coarse_level - 1), (const float*)coarse, (float*)fine, p->st);
     else FvLaunch<double>::prolong(fv_args<double>(p, coarse_level - 1), (const double*)coarse, (double*)fine, p->st);
     return check_launch(p);
@@ -1463,7 +1525,7 @@ jfmg_status jfmg_prolong(jfmg_problem* p, int coarse_level, const void* coarse, 
 jfmg_status jfmg_fv_level_state(jfmg_problem* p, int level, void* u)
 {
     if (!p || !u || level < 0 || level >= p->nlev) return fail(p, JFMG_EINVAL, "bad argument");
-    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step and jfmg_initial_state");
+    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step, jfmg_initial_state, jfmg_linearize and the tile calls");
     if (!p->have_lin) return fail(p, JFMG_ESTATE, "needs jfmg_linearize first");
     const size_t ts = p->prec == 32 ? 4 : 8;
     HIPCHK(p, hipMemcpyAsync(u, p->lev[level].u, ts * 4 * p->lev[level].nc, hipMemcpyDeviceToDevice, p->st));
@@ -1473,7 +1535,7 @@ jfmg_status jfmg_fv_level_state(jfmg_problem* p, int level, void* u)
 jfmg_status jfmg_fv_dtau(jfmg_problem* p, int level, double* dtau)
 {
     if (!p || !dtau || level < 0 || level >= p->nlev) return fail(p, JFMG_EINVAL, "bad argument");
-    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step and jfmg_initial_state");
+    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step, jfmg_initial_state, jfmg_linearize and the tile calls");
     if (!p->have_lin) return fail(p, JFMG_ESTATE, "needs jfmg_linearize first");
     return read_scalars(p, S_LEV + 4 * level + LV_DTAU, 1, dtau);
 }
@@ -1481,7 +1543,7 @@ jfmg_status jfmg_fv_dtau(jfmg_problem* p, int level, double* dtau)
 jfmg_status jfmg_fv_matvec(jfmg_problem* p, int level, const void* x, void* out)
 {
     if (!p || !x || !out || level < 0 || level >= p->nlev) return fail(p, JFMG_EINVAL, "bad argument");
-    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step and jfmg_initial_state");
+    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step, jfmg_initial_state, jfmg_linearize and the tile calls");
     if (!p->have_lin) return fail(p, JFMG_ESTATE, "needs jfmg_linearize first");
     const Level& L = p->lev[level];
     if (p->prec == 32) {
@@ -1499,7 +1561,7 @@ jfmg_status jfmg_fv_matvec(jfmg_problem* p, int level, const void* x, void* out)
 jfmg_status jfmg_mg_fv(jfmg_problem* p, const void* b, void* x)
 {
     if (!p || !b || !x) return fail(p, JFMG_EINVAL, "bad argument");
-    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step and jfmg_initial_state");
+    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step, jfmg_initial_state, jfmg_linearize and the tile calls");
     if (!p->have_lin) return fail(p, JFMG_ESTATE, "needs jfmg_linearize first");
     const Level& L = p->lev[0];
     const size_t bytes = (p->prec == 32 ? 4 : 8) * 4 * L.nc;
@@ -1516,6 +1578,31 @@ jfmg_status jfmg_subgrid_map(jfmg_problem* p, int* fv_to_dg)
     if (!p || !fv_to_dg) return fail(p, JFMG_EINVAL, "null argument");
     launch_subgrid_map(p->cfg.k, p->A, p->lev[0].nx, fv_to_dg, p->st);
     return check_launch(p);
+}
+
+jfmg_status jfmg_get_tiles(const jfmg_problem* p, int* shapes)
+{
+    if (!p || !shapes) return JFMG_EINVAL;
+    for (int l = 0; l < p->nlev; ++l) shapes[l] = p->lev[l].tile;
+    return JFMG_OK;
+}
+
+jfmg_status jfmg_set_tiles(jfmg_problem* p, const int* shapes)
+{
+    if (!p || !shapes) return fail(p, JFMG_EINVAL, "bad argument");
+    for (int l = 0; l < p->nlev; ++l)
+        if (shapes[l] < 0 || shapes[l] >= JFMG_TILE_NSHAPE) return fail(p, JFMG_EINVAL, "unknown tile shape");
+    for (int l = 0; l < p->nlev; ++l) p->lev[l].tile = shapes[l];
+    invalidate_graphs(p);
+    return JFMG_OK;
+}
+
+
+jfmg_status jfmg_autotune(jfmg_problem* p, int reps, int* shapes, double* times_us)
+{
+    if (!p || reps < 1 || reps > 1000) return fail(p, JFMG_EINVAL, "bad argument");
+    if (!p->have_lin) return fail(p, JFMG_ESTATE, "needs jfmg_linearize first");
+    return p->prec == 32 ? autotune_t<float>(p, reps, shapes, times_us) : autotune_t<double>(p, reps, shapes, times_us);
 }
 
 jfmg_status jfmg_profile_enable(jfmg_problem* p, unsigned class_mask)

@@ -20,39 +20,21 @@ constexpr int FV_TX = 64, FV_TZ = 4, FV_NTH = FV_TX * FV_TZ;
 
 enum { FVM_LIN = 0, FVM_STAGE = 1, FVM_MATVEC = 2, FVM_DEFECT = 3 };
 
-// Tile shapes: levels at least FV_WIDE_MIN cells wide use the wide tile (one
-// wave per row of 64 cells; own-cell operands loaded after the face loop and at
-// most 128 VGPRs, so four waves fit per SIMD); narrower levels are latency bound
-// and use a small tile with more threads than cells, so that every face of the
-// tile gets its own thread.  ZREV hands the z-faces out from the last thread
-// down.  Chosen by measurement on the density-current levels (1024x256 ...
-// 128x32 cells) against 8x4, 32x8, 16x4 with 128/192 threads, 2/3/4 waves per
-// SIMD, early and late own-cell loads and both face orders.
-#ifndef FV_WIDE_MIN
-#define FV_WIDE_MIN 512
-#endif
-#ifndef FV_WIDE_TX
-#define FV_WIDE_TX 64
-#define FV_WIDE_TZ 4
-#define FV_WIDE_NTH 256
-#define FV_WIDE_WPE 4
-#endif
-#ifndef FV_WIDE_LATE
-#define FV_WIDE_LATE true
-#endif
-#ifndef FV_WIDE_ZREV
-#define FV_WIDE_ZREV true
-#endif
-#ifndef FV_SMALL_ZREV
-#define FV_SMALL_ZREV true
-#endif
-#ifndef FV_SMALL_TX
-#define FV_SMALL_TX 16
-#define FV_SMALL_TZ 4
-#define FV_SMALL_NTH 256
-#define FV_SMALL_WPE 1
-#endif
-
+// Tile shapes of the FV operator kernels (jfmg_tile; chosen per level, by
+// jfmg_autotune or by default):
+//   64x4 / 256 threads: one wave per row of 64 cells (loads of a component are
+//         512-byte rows); own-cell operands loaded after the face loop and at most
+//         128 VGPRs, so four waves fit per SIMD
+//   64x8 / 512 threads: the same with fewer halo faces per cell (2.14 vs 2.27)
+//   16x4 / 256 threads: more threads than cells, so every face of the tile gets
+//         its own thread (latency-bound narrow levels)
+//   8x4 / 128 threads: the same with a quarter of the work per work-group
+// z-faces are handed out from the last thread down, so that the threads with a
+// second x-face are not those with a second z-face.  Default: 64x4 on levels at
+// least 512 cells wide, 16x4 below (measured on the density-current levels
+// 1024x256 ... 128x32 against 8x4, 32x8, 16x4 with 128/192 threads, 2/3/4 waves
+// per SIMD, early and late own-cell loads and both face orders).
+constexpr int FV_WIDE_MIN = 512;
 
 // FV operator on one tile of TX x TZ cells, face-centric: the perturbed states
 // w = u + eps x of the tile and a one-cell halo are staged in LDS, every face
@@ -497,11 +479,20 @@ static int tile_launch(const FvArgs<T>& A, const T* u, const T* F0, const T* xp,
                        const double* xpart, int xcount, double* slots, double alpha_j, double adt, double cfl,
                        Red red, hipStream_t st, const Mb& mb, T* out2 = nullptr, const double* slots2 = nullptr)
 {
-    if (fv_wide_tile(A.nxl))
-        return tile_launch_shape<T, FV_WIDE_TX, FV_WIDE_TZ, FV_WIDE_NTH, FV_WIDE_WPE, FV_WIDE_LATE, FV_WIDE_ZREV, MODE>(
-            A, u, F0, xp, x0, b, out, out2, xpart, xcount, slots, slots2, alpha_j, adt, cfl, red, st, mb);
-    return tile_launch_shape<T, FV_SMALL_TX, FV_SMALL_TZ, FV_SMALL_NTH, FV_SMALL_WPE, false, FV_SMALL_ZREV, MODE>(
-        A, u, F0, xp, x0, b, out, out2, xpart, xcount, slots, slots2, alpha_j, adt, cfl, red, st, mb);
+    switch (A.tile) {
+    case JFMG_TILE_64x8:
+        return tile_launch_shape<T, 64, 8, 512, 4, true, true, MODE>(A, u, F0, xp, x0, b, out, out2, xpart, xcount,
+                                                                       slots, slots2, alpha_j, adt, cfl, red, st, mb);
+    case JFMG_TILE_16x4:
+        return tile_launch_shape<T, 16, 4, 256, 1, false, true, MODE>(A, u, F0, xp, x0, b, out, out2, xpart, xcount,
+                                                                        slots, slots2, alpha_j, adt, cfl, red, st, mb);
+    case JFMG_TILE_8x4:
+        return tile_launch_shape<T, 8, 4, 128, 1, false, true, MODE>(A, u, F0, xp, x0, b, out, out2, xpart, xcount,
+                                                                       slots, slots2, alpha_j, adt, cfl, red, st, mb);
+    default:
+        return tile_launch_shape<T, 64, 4, 256, 4, true, true, MODE>(A, u, F0, xp, x0, b, out, out2, xpart, xcount,
+                                                                       slots, slots2, alpha_j, adt, cfl, red, st, mb);
+    }
 }
 
 template <typename T>
@@ -571,14 +562,15 @@ void FvLaunch<T>::norm2(const T* x, long n, Red red, hipStream_t st, const Mb& m
     fv_norm2_kernel<T><<<dim3(norm_blocks(n), 1, mb.n), dim3(256), 0, st>>>(x, n, red, mb.ms);
     if (red.out) launch_finalize(red.partials, norm_blocks(n), 1, red.out, st, Gate{}, mb);
 }
-bool fv_wide_tile(long nxl) { return nxl >= FV_WIDE_MIN; }
+int fv_default_tile(long nxl) { return nxl >= FV_WIDE_MIN ? JFMG_TILE_64x4 : JFMG_TILE_16x4; }
+bool fv_wide_tile(int tile) { return tile == JFMG_TILE_64x4 || tile == JFMG_TILE_64x8; }
 
 long fv_partial_blocks(long nxl, long nzl)
 {
-    const long wide = ((nxl + FV_WIDE_TX - 1) / FV_WIDE_TX) * ((nzl + FV_WIDE_TZ - 1) / FV_WIDE_TZ);
-    const long small = ((nxl + FV_SMALL_TX - 1) / FV_SMALL_TX) * ((nzl + FV_SMALL_TZ - 1) / FV_SMALL_TZ);
+    // the most work-groups of any tile shape (8x4) or of the 64x4 streaming kernels, at least 1024
+    const long smallest = ((nxl + 7) / 8) * ((nzl + 3) / 4);
     const long pro = ((nxl + FV_TX - 1) / FV_TX) * ((nzl + FV_TZ - 1) / FV_TZ);
-    return std::max(std::max(wide, small), std::max(pro, 1024L));
+    return std::max(std::max(smallest, pro), 1024L);
 }
 template <typename T> int FvLaunch<T>::norm_blocks(long n)
 {

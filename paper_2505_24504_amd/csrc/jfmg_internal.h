@@ -6,6 +6,7 @@
 
 #include <cstddef>
 
+#include "jfmg.h"
 #include "jfmg_dev.h"
 
 namespace jfmg {
@@ -63,6 +64,7 @@ template <typename T> struct FvArgs {
     int nxl, nzl, bc, physics;
     long nc;
     T hx, hz, area, iarea, g, mu;
+    int tile;        // jfmg_tile shape of the operator kernels on this level (host side)
     Gas<T> gas;
     const T* bgc;    // [nzl][4]   background at cell-centre z
     const T* bgf;    // [nzl+1][4] background at z-faces
@@ -117,8 +119,10 @@ void launch_transfer_Tinv(int k, const DgArgs& A, int mass_fix, const T* u, doub
 void launch_subgrid_map(int k, const DgArgs& A, int nxf, int* out, hipStream_t st);
 
 // ---- FV kernels (fv.hip) ----
-// the FV operator of a level nxl cells wide runs the wide-tile kernel (else the small-tile one)
-bool fv_wide_tile(long nxl);
+// default tile shape of the FV operator kernels on a level nxl cells wide, and
+// whether a shape is one of the wide ones (one wave per 64-cell row)
+int fv_default_tile(long nxl);
+bool fv_wide_tile(int tile);
 // FV partial-sum blocks needed by the largest launch on a level of nxl x nzl cells
 long fv_partial_blocks(long nxl, long nzl);
 
@@ -180,6 +184,7 @@ void launch_lincomb(double* out, const double* base, const double* Z, long ld, i
                     hipStream_t st, const Mb& mb = Mb{});
 // zero `bytes` (a multiple of 4) with a kernel (graph-capture safe, unlike a memset node)
 void launch_zero(void* ptr, size_t bytes, hipStream_t st, const Mb& mb = Mb{});
+template <typename T> void launch_fill_pattern(T* x, long n, hipStream_t st, const Mb& mb = Mb{});
 // out = a*x + b*y
 void launch_axpby(double* out, double a, const double* x, double b, const double* y, long n, hipStream_t st,
                   const Mb& mb = Mb{});

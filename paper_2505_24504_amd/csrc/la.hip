@@ -316,6 +316,22 @@ __global__ void __launch_bounds__(256) zero_kernel(unsigned* __restrict__ x, lon
     for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) x[i] = 0u;
 }
 
+// x[i] = a fixed pattern of values in [-1/2, 1/2) (test vectors of the autotuner)
+template <typename T> __global__ void __launch_bounds__(256) fill_pattern_kernel(T* __restrict__ x, long n, long ms)
+{
+    x = mbr(x, ms);
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256)
+        x[i] = (T)((double)(((unsigned long)i * 2654435761UL) & 0xffffUL) * (1.0 / 65536.0) - 0.5);
+}
+
+template <typename T> void launch_fill_pattern(T* x, long n, hipStream_t st, const Mb& mb)
+{
+    const long nb = (n + 255) / 256 < 2048 ? (n + 255) / 256 : 2048;
+    fill_pattern_kernel<T><<<dim3((unsigned)nb, 1, mb.n), dim3(256), 0, st>>>(x, n, mb.ms);
+}
+template void launch_fill_pattern<double>(double*, long, hipStream_t, const Mb&);
+template void launch_fill_pattern<float>(float*, long, hipStream_t, const Mb&);
+
 void launch_zero(void* ptr, size_t bytes, hipStream_t st, const Mb& mb)
 {
     const long n = (long)(bytes / 4);

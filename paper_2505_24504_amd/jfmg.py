@@ -65,8 +65,11 @@ EXPORTS = [
     "jfmg_mg_fv", "jfmg_subgrid_map", "jfmg_profile_enable", "jfmg_profile_read", "jfmg_last_error",
     "jfmg_batch_create", "jfmg_batch_destroy", "jfmg_batch_admit", "jfmg_batch_member", "jfmg_batch_run",
     "jfmg_batch_start", "jfmg_batch_stop", "jfmg_batch_wait_any", "jfmg_batch_poll", "jfmg_batch_retire",
-    "jfmg_batch_arena_free", "jfmg_batch_last_error",
+    "jfmg_batch_arena_free", "jfmg_batch_last_error", "jfmg_get_tiles", "jfmg_set_tiles", "jfmg_autotune",
 ]
+
+# FV operator tile shapes (jfmg_tile), by index
+TILES = ["64x4", "64x8", "16x4", "8x4"]
 
 KERNEL_CLASSES = ["dg_residual", "dg_jvp", "fv_stage", "fv_stage_zero", "fv_defect_restrict",
                   "fv_prolong_correct", "fv_linearize", "transfer_T", "transfer_Tinv", "multidot",
@@ -119,6 +122,9 @@ def load_library(path: str = LIB_PATH):
         "jfmg_batch_retire": (C.c_int, [vp, C.c_int]),
         "jfmg_batch_arena_free": (C.c_size_t, [vp]),
         "jfmg_batch_last_error": (C.c_char_p, [vp]),
+        "jfmg_get_tiles": (C.c_int, [vp, ip]),
+        "jfmg_set_tiles": (C.c_int, [vp, ip]),
+        "jfmg_autotune": (C.c_int, [vp, C.c_int, ip, dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -318,6 +324,30 @@ class Problem:
         self._check(self.L.jfmg_subgrid_map(self.h, _ptr(out)))
         return out
 
+    def get_tiles(self):
+        """Tile shape names of the FV operator kernels, finest level first."""
+        n = int(self.cfg.mg_levels)
+        a = (C.c_int * n)()
+        self._check(self.L.jfmg_get_tiles(self.h, a))
+        return [TILES[a[i]] for i in range(n)]
+
+    def set_tiles(self, shapes):
+        n = int(self.cfg.mg_levels)
+        if len(shapes) != n:
+            raise ValueError(f"{n} shapes expected")
+        a = (C.c_int * n)(*[TILES.index(s) if isinstance(s, str) else int(s) for s in shapes])
+        self._check(self.L.jfmg_set_tiles(self.h, a))
+
+    def autotune(self, reps: int = 10):
+        """Time every tile shape on every level (needs linearize) and keep the
+        fastest; returns (shapes, {level: {shape: mean us per launch}})."""
+        n = int(self.cfg.mg_levels)
+        a = (C.c_int * n)()
+        t = (C.c_double * (n * len(TILES)))()
+        self._check(self.L.jfmg_autotune(self.h, int(reps), a, t))
+        times = {l: {TILES[s]: t[l * len(TILES) + s] for s in range(len(TILES))} for l in range(n)}
+        return [TILES[a[i]] for i in range(n)], times
+
 
 def num_dofs(d: dict) -> int:
     """N = 4 nx nz (k+1)^2 of a problem description."""
@@ -351,6 +381,7 @@ class Batch:
             raise JfmgError(rc, "jfmg_batch_create failed")
         self.h = h
         self.U = {}
+        self.cfgs = {}
 
     def _check(self, rc):
         if rc:
@@ -369,7 +400,28 @@ class Batch:
             return None
         self._check(rc)
         self.U[slot.value] = U
+        self.cfgs[slot.value] = cfg
         return slot.value
+
+    def autotune(self, slot: int, reps: int = 5):
+        """Tune the FV tile shapes of a member that has not started (jfmg_autotune on
+        the member's problem, linearized at its current state with its stage alpha dt);
+        returns the shapes, finest level first."""
+        h = self.L.jfmg_batch_member(self.h, int(slot))
+        if not h:
+            raise JfmgError(EINVAL, f"no member in slot {slot}")
+        torch.cuda.synchronize(self.device)   # the member state may come from another stream
+        cfg = self.cfgs[slot]
+        alpha = 1.0 if cfg.scheme == 0 else 1.0 - 2.0 ** -0.5
+        rc = self.L.jfmg_linearize(C.c_void_p(h), _ptr(self.U[slot]), alpha * cfg.dt)
+        if rc:
+            raise JfmgError(rc, self.L.jfmg_last_error(C.c_void_p(h)).decode())
+        n = int(cfg.mg_levels)
+        a = (C.c_int * n)()
+        rc = self.L.jfmg_autotune(C.c_void_p(h), int(reps), a, None)
+        if rc:
+            raise JfmgError(rc, self.L.jfmg_last_error(C.c_void_p(h)).decode())
+        return [TILES[a[i]] for i in range(n)]
 
     def run(self, max_steps: int = 0):
         self._check(self.L.jfmg_batch_run(self.h, int(max_steps)))

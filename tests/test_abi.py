@@ -39,6 +39,13 @@ def test_exports_every_declared_symbol(lib):
     assert set(jfmg.EXPORTS) == set(syms)
 
 
+def test_tile_enum_matches_binding():
+    text = open(HEADER).read()
+    vals = dict((n, int(v)) for n, v in re.findall(r"JFMG_TILE_(\w+)\s*=\s*(\d+)", text))
+    assert vals.pop("NSHAPE") == len(jfmg.TILES)
+    assert sorted(vals, key=vals.get) == jfmg.TILES
+
+
 def test_struct_layout_matches_header(tmp_path):
     src = tmp_path / "lay.c"
     src.write_text(r'''

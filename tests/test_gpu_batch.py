@@ -132,6 +132,29 @@ def test_lockstep_members_equal_alone(prec):
         assert torch.equal(U[i * n:(i + 1) * n], alone[i]), i
 
 
+def test_lockstep_autotuned_members_equal_alone():
+    """A lock-step batch tuned by the autotuner and single problems given the same
+    tile shapes give bitwise the same members."""
+    ens = [m for m in W.ensemble(seed=4, members=64) if m[0]["nx"] == 32][:3]
+    d = dict(ens[0][0], mg_precision=32)
+    pb = jfmg.Problem(dict(d, batch=len(ens)), device=DEV)
+    single = jfmg.Problem(d, device=DEV)
+    U = torch.cat([single.initial_state(pert) for _, pert, _ in ens])
+    pb.linearize(U, 0.5)
+    shapes, _ = pb.autotune(reps=2)
+    print("lock-step autotuned", shapes)
+    st = pb.implicit_step(U)
+    assert st["status"] == 0
+    n = pb.ndof
+    for i, (_, pert, _) in enumerate(ens):
+        q = jfmg.Problem(d, device=DEV)
+        q.set_tiles(shapes)
+        Ua = q.initial_state(pert)
+        q.implicit_step(Ua)
+        torch.cuda.synchronize()
+        assert torch.equal(U[i * n:(i + 1) * n], Ua), i
+
+
 def test_lockstep_rejects_single_problem_calls():
     d, _, _ = W.ensemble(seed=4, members=1)[0]
     pb = jfmg.Problem(dict(d, batch=2), device=DEV)

@@ -249,6 +249,67 @@ def test_fv_matvec_parity(case):
         assert err <= tol
 
 
+@pytest.mark.parametrize("tile", jfmg.TILES)
+@pytest.mark.parametrize("case", [(3, 1, 0, 0), (2, 0, 1, 1)])
+def test_fv_tile_shapes_parity(case, tile):
+    """Every tile shape of the FV operator kernels gives the oracle's FV matvec on
+    every level and its multigrid cycle.  Levels 80x32, 40x16, 20x8 cells (k = 3;
+    60x24, 30x12, 15x6 for k = 2): several tiles per level, ragged in x for every
+    shape and in z for 64x8."""
+    k, ph, bg, bc = case
+    d = _cfg(k, nx=20, nz=8, physics=ph, mu=75.0 if ph else 0.0, background=bg, N=0.01 if bg else 0.0,
+             bc=bc, u_mean=10.0 if bc else 0.0, mg_levels=3, z1=3000.0, x1=10000.0)
+    p, o = pair(d)
+    p.set_tiles([tile] * 3)
+    assert p.get_tiles() == [tile] * 3
+    U = rand_state(o, 71)
+    adt = 1.1
+    p.linearize(to_dev(U), adt)
+    o.linearize(U, adt)
+    for lev in range(3):
+        x = W.random_state(o.fv_size(lev), 72 + lev, [1e-3, 1.0, 1.0, 0.3])
+        ag = to_np(p.fv_matvec(lev, to_dev(x)))
+        ao = o.fv_matvec(lev, x)
+        u = o.fv_level_state(lev)
+        nx, nz = o.fv_dims(lev)
+        h = min((d["x1"] - d["x0"]) / nx, (d["z1"] - d["z0"]) / nz)
+        eps = np.sqrt(EPS) * fv_total_norm(o, d, lev, u) / np.linalg.norm(x)
+        tol = 2 * 64 * (adt / eps) * EPS * (4 * 1.1e5 / h) * np.sqrt(x.size)
+        assert np.linalg.norm(ag - ao) <= tol, (lev, tile)
+    b = W.random_state(o.fv_size(0), 75, [1e-3, 1.0, 1.0, 0.3])
+    xg = to_np(p.mg_fv(to_dev(b)))
+    xo = o.mg_fv(b)
+    err = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
+    print(f"tile {tile} case {case}: mg_fv rel err {err:.3e}")
+    assert err <= 1e-6
+
+
+def test_autotune_choice_and_step_parity():
+    """The autotuner keeps the fastest timed shape of every level, and an implicit
+    step with the tuned shapes still matches the oracle."""
+    d, pert, _ = W.bubble_small()
+    rtol = 1e-9
+    d = dict(d, newton_rtol=rtol)
+    p, o = pair(d)
+    U0 = o.initial_state(pert)
+    p.linearize(to_dev(U0), 0.5)
+    shapes, times = p.autotune(reps=3)
+    n = d["mg_levels"]
+    assert len(shapes) == n and p.get_tiles() == shapes
+    for lev in range(n):
+        assert all(t > 0 for t in times[lev].values())
+        assert times[lev][shapes[lev]] == min(times[lev].values())
+    print("autotuned", shapes, {l: {s: round(t, 2) for s, t in v.items()} for l, v in times.items()})
+    rc, Uo, st_o = o.implicit_step(U0)
+    assert rc == 0
+    U = to_dev(U0)
+    st = p.implicit_step(U)
+    _step_check(d, Uo, U0, to_np(U), rtol, st, st_o)
+    with pytest.raises(jfmg.JfmgError):
+        p.set_tiles([7] * n)
+    assert p.get_tiles() == shapes
+
+
 @pytest.mark.parametrize("case", FV_CASES)
 @pytest.mark.parametrize("key", ["mg002222V", "mg001111W", "mg000200V"])
 def test_mg_fv_parity(case, key):
