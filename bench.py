@@ -76,11 +76,14 @@ def percentile(xs, q):
 
 
 def run_form(d, pert, steps, warmup, profile_classes):
+    """Warm-up and timed implicit steps with the library's default FV tile shapes
+    (the same in every pass and under the profilers)."""
     import torch
 
     from paper_2505_24504_amd import jfmg
     p = jfmg.Problem(d, device="cuda:0")
     U = p.initial_state(pert)
+    p.tiles = p.get_tiles()
     for _ in range(warmup):
         p.implicit_step(U)
     p.profile_enable(profile_classes)
@@ -96,6 +99,23 @@ def run_form(d, pert, steps, warmup, profile_classes):
     el = time.perf_counter() - t0
     prof = p.profile_read()
     return p, el, lat, its, prof
+
+
+def autotune_report(d, pert):
+    """What the autotuner chooses for the workload at its initial state (FP64 and
+    FP32 multigrid): the mean stage-kernel time of every tile shape per level."""
+    from paper_2505_24504_amd import jfmg
+    out = {}
+    for prec in (64, 32):
+        p = jfmg.Problem(dict(d, mg_precision=prec), device="cuda:0")
+        U = p.initial_state(pert)
+        p.linearize(U, (1.0 - 2.0 ** -0.5) * d["dt"])
+        default = p.get_tiles()
+        choice, times = p.autotune(reps=20)
+        out[f"fp{prec}"] = {"default": default, "choice": choice,
+                            "stage_us": {str(l): {s: round(t, 2) for s, t in v.items()} for l, v in times.items()}}
+        del p
+    return out
 
 
 def stream_copy(nbytes, reps=20):
@@ -358,11 +378,13 @@ def main():
     bytes_per_launch = pc["bytes"] / max(pc["launches"], 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if pc["launches"] else None
     forms = {"fp64_mg": {"value": value, "ms_per_step": 1e3 * el / a.steps,
-                         "p50_ms": 1e3 * percentile(lat, 50), "p99_ms": 1e3 * percentile(lat, 99)}}
+                         "p50_ms": 1e3 * percentile(lat, 50), "p99_ms": 1e3 * percentile(lat, 99),
+                         "tiles": p.tiles}}
+    forms["autotune"] = autotune_report(d, pert)
     if not a.no_fp32:
         d32 = dict(d, mg_precision=32)
-        _, el32, lat32, its32, _ = run_form(d32, pert, a.steps, a.warmup, [])
-        forms["fp32_mg"] = {"value": a.steps * N / el32, "ms_per_step": 1e3 * el32 / a.steps,
+        p32, el32, lat32, its32, _ = run_form(d32, pert, a.steps, a.warmup, [])
+        forms["fp32_mg"] = {"value": a.steps * N / el32, "ms_per_step": 1e3 * el32 / a.steps, "tiles": p32.tiles,
                             "p50_ms": 1e3 * percentile(lat32, 50), "p99_ms": 1e3 * percentile(lat32, 99),
                             "newton_its": sum(s["newton_its"] for s in its32),
                             "gmres_its": sum(s["gmres_its"] for s in its32)}

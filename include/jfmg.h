@@ -194,7 +194,8 @@ jfmg_status jfmg_subgrid_map(jfmg_problem* p, int* fv_to_dg);
      JFMG_TILE_64x8  512 threads, one wave per 64-cell row
      JFMG_TILE_16x4  256 threads, every face of the tile on its own thread
      JFMG_TILE_8x4   128 threads, every face of the tile on its own thread
-   A new problem uses 64x4 on levels at least 512 cells wide and 16x4 below.
+   A new problem uses, by level width in cells, 64x8 from 1024, 64x4 from 512,
+   16x4 from 256 and 8x4 below.
    Shapes change the order of the partial sums of the FD step norms only, so
    results agree to rounding; the same shapes give bitwise the same results. */
 typedef enum {

@@ -30,11 +30,11 @@ enum { FVM_LIN = 0, FVM_STAGE = 1, FVM_MATVEC = 2, FVM_DEFECT = 3 };
 //         its own thread (latency-bound narrow levels)
 //   8x4 / 128 threads: the same with a quarter of the work per work-group
 // z-faces are handed out from the last thread down, so that the threads with a
-// second x-face are not those with a second z-face.  Default: 64x4 on levels at
-// least 512 cells wide, 16x4 below (measured on the density-current levels
-// 1024x256 ... 128x32 against 8x4, 32x8, 16x4 with 128/192 threads, 2/3/4 waves
-// per SIMD, early and late own-cell loads and both face orders).
-constexpr int FV_WIDE_MIN = 512;
+// second x-face are not those with a second z-face.  Default by level width: 64x8
+// from 1024 cells, 64x4 from 512, 16x4 from 256, 8x4 below (the autotuner's choice
+// on the density-current levels 1024x256 ... 128x32 in FP64; earlier measurements
+// also ruled out 32x8, 16x4 with 128/192 threads, 64x4 with 2/3 waves per SIMD and
+// early own-cell loads).
 
 // FV operator on one tile of TX x TZ cells, face-centric: the perturbed states
 // w = u + eps x of the tile and a one-cell halo are staged in LDS, every face
@@ -562,7 +562,10 @@ void FvLaunch<T>::norm2(const T* x, long n, Red red, hipStream_t st, const Mb& m
     fv_norm2_kernel<T><<<dim3(norm_blocks(n), 1, mb.n), dim3(256), 0, st>>>(x, n, red, mb.ms);
     if (red.out) launch_finalize(red.partials, norm_blocks(n), 1, red.out, st, Gate{}, mb);
 }
-int fv_default_tile(long nxl) { return nxl >= FV_WIDE_MIN ? JFMG_TILE_64x4 : JFMG_TILE_16x4; }
+int fv_default_tile(long nxl)
+{
+    return nxl >= 1024 ? JFMG_TILE_64x8 : nxl >= 512 ? JFMG_TILE_64x4 : nxl >= 256 ? JFMG_TILE_16x4 : JFMG_TILE_8x4;
+}
 bool fv_wide_tile(int tile) { return tile == JFMG_TILE_64x4 || tile == JFMG_TILE_64x8; }
 
 long fv_partial_blocks(long nxl, long nzl)
