@@ -31,10 +31,10 @@ HBM_PEAK_GBS = 8000.0
 # device copy of that same run (FETCH_SIZE x2, WRITE_SIZE x1).
 # It describes the kernel sources hashed below and is reported as null once
 # they change.
-TRAFFIC = {"class": "fv_stage", "bytes_per_launch": 3.9988e7,
+TRAFFIC = {"class": "fv_stage", "bytes_per_launch": 3.0489e7,
            "sources": ["paper_2505_24504_amd/csrc/fv.hip", "paper_2505_24504_amd/csrc/jfmg_dev.h",
                        "paper_2505_24504_amd/csrc/jfmg_internal.h"],
-           "sha256": "16a273b0884fa412e11f9058268602f24d175301888ebbc8e395cd6cabbad83e",
+           "sha256": "19f900d9de188c471607a695a401f520d02338297b1ab62fb3b499307fd58d85",
            "profile": "profiles/traffic_fv_stage_density_current_fp64.md"}
 
 
