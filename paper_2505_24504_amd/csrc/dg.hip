@@ -110,17 +110,16 @@ dg_kernel(DgArgs A, const double* __restrict__ U, const double* __restrict__ Y, 
 #pragma unroll
             for (int c = 0; c < 4; ++c) Ut[c] = sS[s][le][c][nd] + Ub[c];
             const double pt = pert_pressure(A.gas, sS[s][le][3][nd], irz, pbz);
-            conv_flux(Ut, pt, 1.0, 0.0, Fx);
-            conv_flux(Ut, pt, 0.0, 1.0, Fz);
+            conv_flux_xz(Ut, pt, Fx, Fz);
             if constexpr (MODE != 3) {
                 double Bx[4], Bz[4];
-                conv_flux(Ub, pbz, 1.0, 0.0, Bx);
-                conv_flux(Ub, pbz, 0.0, 1.0, Bz);
+                conv_flux_xz(Ub, pbz, Bx, Bz);
 #pragma unroll
                 for (int c = 0; c < 4; ++c) { Fx[c] -= Bx[c]; Fz[c] -= Bz[c]; }
             }
             if constexpr (NS) {
-                double Gx[4], Gz[4], Vx[4], Vz[4];
+                // F_v^x and F_v^z: mu (G_c - (U_c/rho) G_rho) with the x- and z-derivatives
+                double Gx[4], Gz[4];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     double sx = 0.0, sz = 0.0;
@@ -132,10 +131,13 @@ dg_kernel(DgArgs A, const double* __restrict__ U, const double* __restrict__ Y, 
                     Gx[c] = (2.0 / A.dx) * sx;
                     Gz[c] = (2.0 / A.dz) * sz + dUb[c];
                 }
-                visc_flux(A.mu, Ut, Gx, Gz, 1.0, 0.0, Vx);
-                visc_flux(A.mu, Ut, Gx, Gz, 0.0, 1.0, Vz);
+                const double ir = frcp(Ut[0]);
 #pragma unroll
-                for (int c = 0; c < 4; ++c) { Fx[c] -= Vx[c]; Fz[c] -= Vz[c]; }
+                for (int c = 1; c < 4; ++c) {
+                    const double rc = Ut[c] * ir;
+                    Fx[c] -= A.mu * (Gx[c] - rc * Gx[0]);
+                    Fz[c] -= A.mu * (Gz[c] - rc * Gz[0]);
+                }
             }
             if (s == 0) {
 #pragma unroll
@@ -196,7 +198,7 @@ dg_kernel(DgArgs A, const double* __restrict__ U, const double* __restrict__ Y, 
             const double nxn = xf ? (double)side : 0.0, nzn = xf ? 0.0 : (double)side;
             const double* es = side > 0 ? R.ep : R.em;
             const double* ds = side > 0 ? R.dp : R.dm;
-            const double hperp = xf ? A.dx : A.dz, htan = xf ? A.dz : A.dx;
+            const double hperp = xf ? A.dx : A.dz;
             const double flen = xf ? A.dz : A.dx;
             const bool wall = !valid || face_nb(f, ex, ez, A.nx, A.nz, A.bc) < 0;
             double Ub[4], dUb[4];
@@ -245,44 +247,34 @@ dg_kernel(DgArgs A, const double* __restrict__ U, const double* __restrict__ Y, 
                 for (int c = 0; c < 4; ++c) fl[c] = -H[c];
                 if constexpr (NS) {
                     if (!wall) {
-                        double Gxo[4], Gzo[4], Gxx[4], Gzx[4], Fo[4], Fxx[4];
+                        // F_v(U, G) . n of a Cartesian face involves only the normal derivative
+                        // G_n (the tangential part enters multiplied by 0): own side from the
+                        // element's values, other side from the neighbour's trace derivative,
+                        // plus the background's z-derivative on z-faces
+                        const double gs = 2.0 / hperp, sg = (double)side;
+                        const double iro = frcp(Uo[0]), irx = frcp(Ux[0]);
+                        double Gno[4], Gnx[4];
 #pragma unroll
                         for (int c = 0; c < 4; ++c) {
-                            double sn = 0.0, st_o = 0.0, st_x = 0.0;
+                            double sn = 0.0;
 #pragma unroll
                             for (int j = 0; j < N1; ++j) sn += ds[j] * sS[s][le][c][xf ? r * N1 + j : j * N1 + r];
-#pragma unroll
-                            for (int q = 0; q < N1; ++q) {
-                                double trq = 0.0;
-#pragma unroll
-                                for (int j = 0; j < N1; ++j) trq += es[j] * sS[s][le][c][xf ? q * N1 + j : j * N1 + q];
-                                st_o += R.D[r][q] * trq;
-                                st_x += R.D[r][q] * sTx[s][le][f][q][c];
-                            }
-                            const double gn_o = (2.0 / hperp) * sn, gn_x = (2.0 / hperp) * sNx[s][le][f][r][c];
-                            const double gt_o = (2.0 / htan) * st_o, gt_x = (2.0 / htan) * st_x;
-                            if (xf) {
-                                Gxo[c] = gn_o; Gxx[c] = gn_x;
-                                Gzo[c] = gt_o + dUb[c]; Gzx[c] = gt_x + dUb[c];
-                            } else {
-                                Gzo[c] = gn_o + dUb[c]; Gzx[c] = gn_x + dUb[c];
-                                Gxo[c] = gt_o; Gxx[c] = gt_x;
-                            }
+                            const double db = xf ? 0.0 : dUb[c];
+                            Gno[c] = gs * sn + db;
+                            Gnx[c] = gs * sNx[s][le][f][r][c] + db;
                         }
-                        visc_flux(A.mu, Uo, Gxo, Gzo, nxn, nzn, Fo);
-                        visc_flux(A.mu, Ux, Gxx, Gzx, nxn, nzn, Fxx);
                         const double eta = A.c_ip * (double)(N1 * N1) / hperp;
-                        double Dl[4], Um[4];
-#pragma unroll
-                        for (int c = 0; c < 4; ++c) {
-                            Dl[c] = tro[c] - sTx[s][le][f][r][c];
-                            Um[c] = 0.5 * (Uo[c] + Ux[c]);
-                        }
+                        const double Dl0 = tro[0] - sTx[s][le][f][r][0];
+                        const double irm = frcp(0.5 * (Uo[0] + Ux[0]));
 #pragma unroll
                         for (int c = 1; c < 4; ++c) {
-                            const double pen = eta * A.mu * (Dl[c] - (Um[c] / Um[0]) * Dl[0]);
-                            fl[c] += 0.5 * (Fo[c] + Fxx[c]) - pen;
-                            sy[c] = 0.5 * A.mu * (Dl[c] - (Uo[c] / Uo[0]) * Dl[0]);
+                            const double ro = Uo[c] * iro;
+                            const double Fo = sg * A.mu * (Gno[c] - ro * Gno[0]);
+                            const double Fxx = sg * A.mu * (Gnx[c] - Ux[c] * irx * Gnx[0]);
+                            const double Dlc = tro[c] - sTx[s][le][f][r][c];
+                            const double pen = eta * A.mu * (Dlc - (0.5 * (Uo[c] + Ux[c]) * irm) * Dl0);
+                            fl[c] += 0.5 * (Fo + Fxx) - pen;
+                            sy[c] = 0.5 * A.mu * (Dlc - ro * Dl0);
                         }
                     }
                 }
@@ -307,7 +299,8 @@ dg_kernel(DgArgs A, const double* __restrict__ U, const double* __restrict__ Y, 
     // ---- D: contraction, lifting and output ----
     double nrm = 0.0;
     if (valid) {
-        const double m = R.w[a] * R.w[b] * A.J;
+        const double m = R.w[a] * R.w[b] * A.J, im = frcp(m);
+        const double sc = MODE == 3 ? adt / eps : 0.0;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             double sx = 0.0, sz = 0.0;
@@ -328,13 +321,13 @@ dg_kernel(DgArgs A, const double* __restrict__ U, const double* __restrict__ Y, 
             }
             const long o = c * N + e * NP + nd;
             if constexpr (MODE == 0) out[o] = L;
-            else if constexpr (MODE == 1) out[o] = L / m;
+            else if constexpr (MODE == 1) out[o] = L * im;
             else if constexpr (MODE == 2) {
-                const double G = sS[0][le][c][nd] - adt * (L / m) - Ubar[o];
+                const double G = sS[0][le][c][nd] - adt * (L * im) - Ubar[o];
                 out[o] = G;
                 nrm += G * G;
             } else {
-                out[o] = yv[c] - (adt / eps) * (L / m);
+                out[o] = yv[c] - sc * (L * im);
             }
         }
     }

@@ -126,6 +126,23 @@ __device__ __forceinline__ void conv_flux(const T* U, T p, T nx, T nz, T* F)
     F[3] = U[3] * q;
 }
 
+// Both Cartesian convective fluxes F_c^x(U) and F_c^z(U) (pressure given) with one
+// reciprocal of rho; the same numbers as conv_flux with (1, 0) and (0, 1).
+template <typename T>
+__device__ __forceinline__ void conv_flux_xz(const T* U, T p, T* Fx, T* Fz)
+{
+    const T ir = frcp<T>(U[0]);
+    const T u = U[1] * ir, w = U[2] * ir;
+    Fx[0] = U[1];
+    Fx[1] = U[1] * u + p;
+    Fx[2] = U[2] * u;
+    Fx[3] = U[3] * u;
+    Fz[0] = U[2];
+    Fz[1] = U[1] * w;
+    Fz[2] = U[2] * w + p;
+    Fz[3] = U[3] * w;
+}
+
 // HLLC flux (Toro) with Davis wave speeds S_L = min(q_L - c_L, q_R - c_R),
 // S_R = max(q_L + c_L, q_R + c_R); star flux in the S*-factored form
 // (S*(S_K U_K - F_K) + S_K p*_K D*) / (S_K - S*), p*_K = p_K + rho_K (S_K - q_K)(S* - q_K).
