@@ -29,6 +29,8 @@ enum { FVM_LIN = 0, FVM_STAGE = 1, FVM_MATVEC = 2, FVM_DEFECT = 3 };
 //   16x4 / 256 threads: more threads than cells, so every face of the tile gets
 //         its own thread (latency-bound narrow levels)
 //   8x4 / 128 threads: the same with a quarter of the work per work-group
+//   32x4 / 256 threads: two threads per cell (x-faces on the first threads,
+//         z-faces from the last down), two waves per SIMD
 // z-faces are handed out from the last thread down, so that the threads with a
 // second x-face are not those with a second z-face.  Default by level width: 64x8
 // from 1024 cells, 64x4 from 512, 16x4 from 256, 8x4 below (the autotuner's choice
@@ -489,6 +491,9 @@ static int tile_launch(const FvArgs<T>& A, const T* u, const T* F0, const T* xp,
     case JFMG_TILE_8x4:
         return tile_launch_shape<T, 8, 4, 128, 1, false, true, MODE>(A, u, F0, xp, x0, b, out, out2, xpart, xcount,
                                                                        slots, slots2, alpha_j, adt, cfl, red, st, mb);
+    case JFMG_TILE_32x4:
+        return tile_launch_shape<T, 32, 4, 256, 2, false, true, MODE>(A, u, F0, xp, x0, b, out, out2, xpart, xcount,
+                                                                        slots, slots2, alpha_j, adt, cfl, red, st, mb);
     default:
         return tile_launch_shape<T, 64, 4, 256, 4, true, true, MODE>(A, u, F0, xp, x0, b, out, out2, xpart, xcount,
                                                                        slots, slots2, alpha_j, adt, cfl, red, st, mb);
