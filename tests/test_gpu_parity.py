@@ -284,6 +284,33 @@ def test_fv_tile_shapes_parity(case, tile):
     assert err <= 1e-6
 
 
+@pytest.mark.parametrize("tile", jfmg.TILES)
+def test_fv_tile_shapes_fp32(tile):
+    """The FP32 kernels of every tile shape: the multigrid cycle agrees with the same
+    cycle in the default shapes (the shapes only change the order of the FP64 norm
+    partial sums, which the FP32 step eps rounds away: measured bitwise equal) and
+    with the FP64 oracle to the FP32 cycle's accuracy (FD step sqrt(2^-23) ||u||/||x||,
+    truncation O(3e-4) relative per product; measured 3.3e-4)."""
+    d = _cfg(3, nx=20, nz=8, physics=1, mu=75.0, mg_levels=3, z1=3000.0, x1=10000.0, mg_precision=32)
+    o = oracle.Oracle(dict(d, mg_precision=64))
+    U = rand_state(o, 81)
+    b = W.random_state(o.fv_size(0), 82, [1e-3, 1.0, 1.0, 0.3])
+    res = {}
+    for name, tiles in (("default", None), (tile, [tile] * 3)):
+        p = jfmg.Problem(d, device=DEV)
+        if tiles:
+            p.set_tiles(tiles)
+        p.linearize(to_dev(U), 0.8)
+        res[name] = to_np(p.mg_fv(to_dev(b, torch.float32)))
+    o.linearize(U, 0.8)
+    xo = o.mg_fv(b)
+    e_def = np.linalg.norm(res[tile] - res["default"]) / np.linalg.norm(res["default"])
+    e_orc = np.linalg.norm(res[tile] - xo) / np.linalg.norm(xo)
+    print(f"fp32 tile {tile}: vs default shapes {e_def:.3e}, vs FP64 oracle {e_orc:.3e}")
+    assert e_def <= 1e-6
+    assert e_orc <= 2e-3
+
+
 def test_autotune_choice_and_step_parity():
     """The autotuner keeps the fastest timed shape of every level, and an implicit
     step with the tuned shapes still matches the oracle."""
