@@ -79,6 +79,10 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
     __shared__ T sw[4][HZ][HX];
     __shared__ T sFx[TZ][TX + 1][4];
     __shared__ T sFz[TZ + 1][TX][4];
+    // background of the tile's rows: cell centres [Ubar(4), p, 1/(rho theta)], z-faces
+    // [Ubar(4), p, 1/(rho theta), dUbar/dz(4)]
+    __shared__ T sBc[TZ][6];
+    __shared__ T sBf[TZ + 1][10];
     const int tid = threadIdx.x;
     const unsigned tile = xcd_tile(block_linear(), gridDim.x * gridDim.y);
     const int I0 = (int)(tile % gridDim.x) * TX, J0 = (int)(tile / gridDim.x) * TZ;
@@ -149,6 +153,14 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
                     sw[c][h / HX][h % HX] = v;
                 }
         }
+        static_assert(NTH >= 6 * TZ + 10 * (TZ + 1), "background staging");
+        if (tid < 6 * TZ) {
+            const int r = tid / 6, k = tid - 6 * r, J = J0 + r;
+            if (J < nzl) sBc[r][k] = k < 4 ? A.bgc[4 * J + k] : A.pc[2 * J + k - 4];
+        } else if (tid < 6 * TZ + 10 * (TZ + 1)) {
+            const int t2 = tid - 6 * TZ, r = t2 / 10, k = t2 - 10 * r, J = J0 + r;
+            if (J <= nzl) sBf[r][k] = k < 4 ? A.bgf[4 * J + k] : k < 6 ? A.pf[2 * J + k - 4] : A.dbgf[4 * J + k - 6];
+        }
         __syncthreads();
         // ---- one net flux per face: x-faces in thread order, z-faces in reverse
         // thread order (the threads with a second x-face are not those with a
@@ -156,7 +168,7 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
         auto face = [&](auto xf_tag, int idx) {
             constexpr bool XF = decltype(xf_tag)::value;
             constexpr int D = XF ? 1 : 2;   // normal momentum component
-            int rl, cl, rr, cr, Jrow;       // LDS row/col of the low (L) and high (R) cell; background row
+            int rl, cl, rr, cr, brow;       // LDS row/col of the low (L) and high (R) cell; background row of the tile
             bool skip, wallL, wallR;
             if constexpr (XF) {
                 const int jj = idx / (TX + 1), fi = idx - jj * (TX + 1);
@@ -165,7 +177,7 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
                 wallL = (Ir == 0) && A.bc != 1;
                 wallR = (Il == nxl - 1) && A.bc != 1;
                 rl = jj + 1; rr = jj + 1; cl = fi; cr = fi + 1;
-                Jrow = skip ? 0 : Jf;
+                brow = jj;
             } else {
                 const int fj = idx / TX, ii = idx - fj * TX;
                 const int If = I0 + ii, Ja = J0 + fj, Jb = Ja - 1;
@@ -173,12 +185,12 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
                 wallL = (Jb < 0);
                 wallR = (Ja == nzl);
                 rl = fj; rr = fj + 1; cl = ii + 1; cr = ii + 1;
-                Jrow = skip ? 0 : Ja;
+                brow = fj;
             }
             T Phi[4] = {T(0), T(0), T(0), T(0)};
             if (!skip) {
-                const T* bg = (XF ? A.bgc : A.bgf) + 4 * Jrow;
-                const T* pr = (XF ? A.pc : A.pf) + 2 * Jrow;
+                const T* bg = XF ? &sBc[brow][0] : &sBf[brow][0];   // Ubar, then p, 1/(rho theta)
+                const T* pr = bg + 4;
                 const bool wall = wallL || wallR;
                 // a slip wall: the missing side is the inside cell mirrored (normal momentum negated)
                 const int rlx = wallL ? rr : rl, clx = wallL ? cr : cl;
@@ -203,7 +215,7 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
                     // (mu/h) (dw_c - (U_c/rho)_avg dw_rho), dw = w_L - w_R, on the averaged state
                     const T irs = frcp<T>(UL[0] + UR[0]);
                     const T muh = A.mu / (XF ? A.hx : A.hz);
-                    const T* dbg = A.dbgf + 4 * Jrow;
+                    const T* dbg = &sBf[brow][6];
                     const T dw0 = wL[0] - wR[0];
 #pragma unroll
                     for (int c = 1; c < 4; ++c) {
