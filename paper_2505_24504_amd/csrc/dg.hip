@@ -6,11 +6,10 @@
 // thread then
 //   B  evaluates the volume flux at its node (total state U' + Ubar minus the
 //      background flux, minus the viscous flux) into LDS,
-//   C1 loads the neighbour element's trace and normal derivative at one face
-//      point from global memory into LDS (faces are recomputed from both sides;
-//      this costs flops, not HBM bytes),
-//   C2 evaluates HLLC minus the background HLLC, the interior-penalty terms
-//      and the symmetric term at that face point,
+//   C  loads the neighbour element's trace and normal derivative at one face
+//      point from global memory into registers (faces are recomputed from both
+//      sides; this costs flops, not HBM bytes) and evaluates HLLC minus the
+//      background HLLC, the interior-penalty terms and the symmetric term there,
 //   D  contracts the volume fluxes with the GL derivative matrix, lifts the
 //      face terms to its node and writes the requested output.
 // The same kernel in JVP mode carries two states, U' and U' + eps y, and
@@ -34,8 +33,10 @@ __device__ __forceinline__ int face_nb(int f, int ex, int ez, int nx, int nz, in
     return ez < nz - 1 ? (ez + 1) * nx + ex : -1;
 }
 
+// At most 168 VGPRs so that three waves fit per SIMD (with 24 KB of LDS per
+// 128-thread work-group, LDS allows six work-groups per CU).
 template <int N1, bool NS, int MODE>
-__global__ void __launch_bounds__(DgShape<N1>::NTH)
+__global__ void __launch_bounds__(DgShape<N1>::NTH, 3)
 dg_kernel(DgArgs A, const double* __restrict__ U, const double* __restrict__ Y, const double* __restrict__ Ubar,
           double* __restrict__ out, const double* __restrict__ yn2p, const double* __restrict__ ut2p, int eps_mode,
           double adt, Red red, long ms)
@@ -53,8 +54,6 @@ dg_kernel(DgArgs A, const double* __restrict__ U, const double* __restrict__ Y, 
     constexpr int NSt = (MODE == 3) ? 2 : 1;
     __shared__ double sS[NSt][EPB][4][NP];
     __shared__ double sFx[EPB][4][NP], sFz[EPB][4][NP];
-    __shared__ double sTx[NSt][EPB][4][N1][4];
-    __shared__ double sNx[NS ? NSt : 1][NS ? EPB : 1][4][N1][4];
     __shared__ double sFc[EPB][4][N1][4];
     __shared__ double sSy[NS ? EPB : 1][4][N1][4];
 
@@ -151,45 +150,8 @@ dg_kernel(DgArgs A, const double* __restrict__ U, const double* __restrict__ Y, 
         for (int c = 0; c < 4; ++c) { sFx[le][c][nd] = fx[c]; sFz[le][c][nd] = fz[c]; }
     }
 
-    // ---- C1: neighbour traces (and normal derivatives) at the face points ----
-    if (act) {
-        for (int fp = nd; fp < 4 * N1; fp += NP) {
-            const int f = fp / N1, r = fp - f * N1;
-            const bool xf = f < 2;
-            const int side = (f == 0 || f == 2) ? -1 : 1;
-            const double* eo = side > 0 ? R.em : R.ep;
-            const double* dso = side > 0 ? R.dm : R.dp;
-            const int nb = valid ? face_nb(f, ex, ez, A.nx, A.nz, A.bc) : -1;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                double tr[NSt], dn[NSt];
-#pragma unroll
-                for (int s = 0; s < NSt; ++s) { tr[s] = 0.0; dn[s] = 0.0; }
-                if (nb >= 0) {
-#pragma unroll
-                    for (int j = 0; j < N1; ++j) {
-                        const int idx = xf ? r * N1 + j : j * N1 + r;
-                        const double v = U[c * N + (long)nb * NP + idx];
-                        tr[0] += eo[j] * v;
-                        if constexpr (NS) dn[0] += dso[j] * v;
-                        if constexpr (MODE == 3) {
-                            const double v1 = v + eps * Y[c * N + (long)nb * NP + idx];
-                            tr[1] += eo[j] * v1;
-                            if constexpr (NS) dn[1] += dso[j] * v1;
-                        }
-                    }
-                }
-#pragma unroll
-                for (int s = 0; s < NSt; ++s) {
-                    sTx[s][le][f][r][c] = tr[s];
-                    if constexpr (NS) sNx[s][le][f][r][c] = dn[s];
-                }
-            }
-        }
-    }
-    __syncthreads();
-
-    // ---- C2: face fluxes ----
+    // ---- C: face fluxes; the neighbour element's trace and normal derivative at
+    // the face point come straight from global memory into registers ----
     if (act) {
         for (int fp = nd; fp < 4 * N1; fp += NP) {
             const int f = fp / N1, r = fp - f * N1;
@@ -200,7 +162,32 @@ dg_kernel(DgArgs A, const double* __restrict__ U, const double* __restrict__ Y, 
             const double* ds = side > 0 ? R.dp : R.dm;
             const double hperp = xf ? A.dx : A.dz;
             const double flen = xf ? A.dz : A.dx;
-            const bool wall = !valid || face_nb(f, ex, ez, A.nx, A.nz, A.bc) < 0;
+            const int nb = valid ? face_nb(f, ex, ez, A.nx, A.nz, A.bc) : -1;
+            const bool wall = nb < 0;
+            double trx[NSt][4], dnx[NSt][4];   // other side: trace and normal derivative (d/d xi of the neighbour)
+            {
+                const double* eo = side > 0 ? R.em : R.ep;
+                const double* dso = side > 0 ? R.dm : R.dp;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+#pragma unroll
+                    for (int st = 0; st < NSt; ++st) { trx[st][c] = 0.0; dnx[st][c] = 0.0; }
+                    if (!wall) {
+#pragma unroll
+                        for (int j = 0; j < N1; ++j) {
+                            const int idx = xf ? r * N1 + j : j * N1 + r;
+                            const double v = U[c * N + (long)nb * NP + idx];
+                            trx[0][c] += eo[j] * v;
+                            if constexpr (NS) dnx[0][c] += dso[j] * v;
+                            if constexpr (MODE == 3) {
+                                const double v1 = v + eps * Y[c * N + (long)nb * NP + idx];
+                                trx[1][c] += eo[j] * v1;
+                                if constexpr (NS) dnx[1][c] += dso[j] * v1;
+                            }
+                        }
+                    }
+                }
+            }
             double Ub[4], dUb[4];
             const int zrow = xf ? (ez * N1 + r) : (ez + (side > 0 ? 1 : 0));
             const double* bgp = xf ? A.bg_node : A.bg_face;
@@ -229,8 +216,8 @@ dg_kernel(DgArgs A, const double* __restrict__ U, const double* __restrict__ Y, 
                     if (xf) Ux[1] = -Uo[1]; else Ux[2] = -Uo[2];
                 } else {
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) Ux[c] = sTx[s][le][f][r][c] + Ub[c];
-                    px = pert_pressure(A.gas, sTx[s][le][f][r][3], irz, pbz);
+                    for (int c = 0; c < 4; ++c) Ux[c] = trx[s][c] + Ub[c];
+                    px = pert_pressure(A.gas, trx[s][3], irz, pbz);
                 }
                 hllc(A.gas, Uo, Ux, po, px, nxn, nzn, H);
                 double fl[4], sy[4] = {0, 0, 0, 0};
@@ -261,17 +248,17 @@ dg_kernel(DgArgs A, const double* __restrict__ U, const double* __restrict__ Y, 
                             for (int j = 0; j < N1; ++j) sn += ds[j] * sS[s][le][c][xf ? r * N1 + j : j * N1 + r];
                             const double db = xf ? 0.0 : dUb[c];
                             Gno[c] = gs * sn + db;
-                            Gnx[c] = gs * sNx[s][le][f][r][c] + db;
+                            Gnx[c] = gs * dnx[s][c] + db;
                         }
                         const double eta = A.c_ip * (double)(N1 * N1) / hperp;
-                        const double Dl0 = tro[0] - sTx[s][le][f][r][0];
+                        const double Dl0 = tro[0] - trx[s][0];
                         const double irm = frcp(0.5 * (Uo[0] + Ux[0]));
 #pragma unroll
                         for (int c = 1; c < 4; ++c) {
                             const double ro = Uo[c] * iro;
                             const double Fo = sg * A.mu * (Gno[c] - ro * Gno[0]);
                             const double Fxx = sg * A.mu * (Gnx[c] - Ux[c] * irx * Gnx[0]);
-                            const double Dlc = tro[c] - sTx[s][le][f][r][c];
+                            const double Dlc = tro[c] - trx[s][c];
                             const double pen = eta * A.mu * (Dlc - (0.5 * (Uo[c] + Ux[c]) * irm) * Dl0);
                             fl[c] += 0.5 * (Fo + Fxx) - pen;
                             sy[c] = 0.5 * A.mu * (Dlc - ro * Dl0);
