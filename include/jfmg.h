@@ -195,8 +195,9 @@ jfmg_status jfmg_subgrid_map(jfmg_problem* p, int* fv_to_dg);
      JFMG_TILE_16x4  256 threads, every face of the tile on its own thread
      JFMG_TILE_8x4   128 threads, every face of the tile on its own thread
      JFMG_TILE_32x4  256 threads, two per cell
-   A new problem uses, by level width in cells, 64x8 from 1024, 64x4 from 512,
-   16x4 from 256 and 8x4 below.
+     JFMG_TILE_64x4_512  512 threads, two per cell
+   A new problem uses, by level width in cells, 64x8 from 1024, 64x4_512 from
+   512, 16x4 from 256 and 8x4 below.
    Shapes change the order of the partial sums of the FD step norms only, so
    results agree to rounding; the same shapes give bitwise the same results. */
 typedef enum {
@@ -205,7 +206,8 @@ typedef enum {
     JFMG_TILE_16x4 = 2,
     JFMG_TILE_8x4 = 3,
     JFMG_TILE_32x4 = 4,
-    JFMG_TILE_NSHAPE = 5
+    JFMG_TILE_64x4_512 = 5,
+    JFMG_TILE_NSHAPE = 6
 } jfmg_tile;
 /* shapes: host array of mg_levels entries (finest level first). */
 jfmg_status jfmg_get_tiles(const jfmg_problem* p, int* shapes);

@@ -31,12 +31,14 @@ enum { FVM_LIN = 0, FVM_STAGE = 1, FVM_MATVEC = 2, FVM_DEFECT = 3 };
 //   8x4 / 128 threads: the same with a quarter of the work per work-group
 //   32x4 / 256 threads: two threads per cell (x-faces on the first threads,
 //         z-faces from the last down), two waves per SIMD
+//   64x4 / 512 threads: the 64x4 tile with two threads per cell (twice the waves
+//         of the 256-thread form on a level too small to fill the chip)
 // z-faces are handed out from the last thread down, so that the threads with a
 // second x-face are not those with a second z-face.  Default by level width: 64x8
-// from 1024 cells, 64x4 from 512, 16x4 from 256, 8x4 below (the autotuner's choice
-// on the density-current levels 1024x256 ... 128x32 in FP64; earlier measurements
-// also ruled out 32x8, 16x4 with 128/192 threads, 64x4 with 2/3 waves per SIMD and
-// early own-cell loads).
+// from 1024 cells, 64x4 with 512 threads from 512, 16x4 from 256, 8x4 below (the
+// autotuner's choice on the density-current levels 1024x256 ... 128x32; earlier
+// measurements also ruled out 32x8, 16x4 with 128/192 threads, 64x4 with 2/3 waves
+// per SIMD and early own-cell loads).
 
 // FV operator on one tile of TX x TZ cells, face-centric: the perturbed states
 // w = u + eps x of the tile and a one-cell halo are staged in LDS, every face
@@ -506,6 +508,9 @@ static int tile_launch(const FvArgs<T>& A, const T* u, const T* F0, const T* xp,
     case JFMG_TILE_32x4:
         return tile_launch_shape<T, 32, 4, 256, 2, false, true, MODE>(A, u, F0, xp, x0, b, out, out2, xpart, xcount,
                                                                         slots, slots2, alpha_j, adt, cfl, red, st, mb);
+    case JFMG_TILE_64x4_512:
+        return tile_launch_shape<T, 64, 4, 512, 4, true, true, MODE>(A, u, F0, xp, x0, b, out, out2, xpart, xcount,
+                                                                       slots, slots2, alpha_j, adt, cfl, red, st, mb);
     default:
         return tile_launch_shape<T, 64, 4, 256, 4, true, true, MODE>(A, u, F0, xp, x0, b, out, out2, xpart, xcount,
                                                                        slots, slots2, alpha_j, adt, cfl, red, st, mb);
@@ -581,9 +586,11 @@ void FvLaunch<T>::norm2(const T* x, long n, Red red, hipStream_t st, const Mb& m
 }
 int fv_default_tile(long nxl)
 {
-    return nxl >= 1024 ? JFMG_TILE_64x8 : nxl >= 512 ? JFMG_TILE_64x4 : nxl >= 256 ? JFMG_TILE_16x4 : JFMG_TILE_8x4;
+    return nxl >= 1024 ? JFMG_TILE_64x8
+           : nxl >= 512 ? JFMG_TILE_64x4_512
+           : nxl >= 256 ? JFMG_TILE_16x4 : JFMG_TILE_8x4;
 }
-bool fv_wide_tile(int tile) { return tile == JFMG_TILE_64x4 || tile == JFMG_TILE_64x8; }
+bool fv_wide_tile(int tile) { return tile == JFMG_TILE_64x4 || tile == JFMG_TILE_64x8 || tile == JFMG_TILE_64x4_512; }
 
 long fv_partial_blocks(long nxl, long nzl)
 {

@@ -69,7 +69,7 @@ EXPORTS = [
 ]
 
 # FV operator tile shapes (jfmg_tile), by index
-TILES = ["64x4", "64x8", "16x4", "8x4", "32x4"]
+TILES = ["64x4", "64x8", "16x4", "8x4", "32x4", "64x4_512"]
 
 KERNEL_CLASSES = ["dg_residual", "dg_jvp", "fv_stage", "fv_stage_zero", "fv_defect_restrict",
                   "fv_prolong_correct", "fv_linearize", "transfer_T", "transfer_Tinv", "multidot",
