@@ -30,7 +30,7 @@ def build() -> str:
 
 class OrcCfg(C.Structure):
     _fields_ = [(n, C.c_int) for n in (
-        "nx", "nz", "k", "physics", "background", "bc", "mass_fix", "mg_levels",
+        "nx", "nz", "k", "physics", "background", "bc", "mass_fix", "transfer", "mg_levels",
         "nu_pre_fine", "nu_post_fine", "nu_pre", "nu_post", "cycle", "rk_stages",
         "fd_eps_mode", "gmres_m", "gmres_max_restarts", "newton_maxit", "scheme",
         "precond")] + [(n, C.c_double) for n in (
@@ -75,6 +75,7 @@ def lib():
         L.orc_num_dofs.argtypes = [C.c_void_p]
         L.orc_fv_dims.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.orc_ref_tables.argtypes = [C.c_int] + [dp] * 10
+        L.orc_proj_tables.argtypes = [C.c_int, dp, dp]
         L.orc_background.argtypes = [C.c_void_p, C.c_double, dp, dp]
         L.orc_flux.argtypes = [C.c_void_p, dp, C.c_double, C.c_double, dp]
         L.orc_hllc.argtypes = [C.c_void_p, dp, dp, C.c_double, C.c_double, dp]
@@ -128,6 +129,15 @@ def ref_tables(k: int):
     return out
 
 
+def proj_tables(k: int):
+    """L2 projection onto the k+1 subintervals: P[i][a] = mean of l_a over subinterval i, and P^-1."""
+    n = k + 1
+    P, Pinv = np.zeros((n, n)), np.zeros((n, n))
+    if lib().orc_proj_tables(k, _p(P), _p(Pinv)):
+        raise ValueError("k out of range")
+    return P, Pinv
+
+
 def make_cfg(d: dict) -> OrcCfg:
     c = OrcCfg()
     key = parse_mg_key(d.get("mg_key", "mg002222V"))
@@ -139,6 +149,7 @@ def make_cfg(d: dict) -> OrcCfg:
     c.background = int(d.get("background", 0))
     c.bc = int(d.get("bc", 0))
     c.mass_fix = int(d.get("mass_fix", 1))
+    c.transfer = int(d.get("transfer", 0))
     c.mg_levels = int(d.get("mg_levels", 3))
     c.nu_pre_fine, c.nu_post_fine, c.nu_pre, c.nu_post = key["c"], key["d"], key["e"], key["f"]
     c.cycle = key["cycle"]

@@ -29,6 +29,7 @@ struct orc_ctx {
     double dx, dz, J;           /* element sizes, |J| = dx dz / 4 */
     double xi[MAXN], w[MAXN], D[MAXN][MAXN], em[MAXN], ep[MAXN], dm[MAXN], dp[MAXN];
     double V[MAXN][MAXN], Vinv[MAXN][MAXN], wnc[MAXN];
+    double P[MAXN][MAXN], Pinv[MAXN][MAXN];   /* L2 projection onto subcells (transfer = 1) */
     int nlev, nxl[MAXLEV], nzl[MAXLEV];
     double hx[MAXLEV], hz[MAXLEV];
     /* linearization (Newton iterate) */
@@ -167,6 +168,34 @@ int orc_ref_tables(int k, double* xi, double* w, double* D, double* em, double* 
         for (int q = 0; q < n; ++q) s += 0.5 * w[q] * lagrange(n, G, i, 0.5 * (1.0 + xi[q]));
         wnc[i] = s;
     }
+    return ORC_OK;
+}
+
+/* L2 projection of the element polynomial onto the piecewise constants of the
+   (k+1)^2 subcells (the alternative to interpolation that Sec. "Transfer
+   functions" names; it conserves mass by construction): in 1D the average of l_a
+   over subinterval i = [-1 + 2i/(k+1), -1 + 2(i+1)/(k+1)],
+       P[i][a] = (1/2) sum_q w_q l_a(s_i + (1 + xi_q)/(k+1)),
+   the (k+1)-point GL rule on the subinterval (exact: l_a has degree k), and the
+   element map is the tensor product P (x) P.  Its inverse gives T^-1. */
+int orc_proj_tables(int k, double* P, double* Pinv)
+{
+    if (k < 1 || k > MAXK) return ORC_EINVAL;
+    int n = k + 1;
+    double xi[MAXN], w[MAXN], A[MAXN * MAXN];
+    gauss_legendre(n, xi, w);
+    for (int i = 0; i < n; ++i) {
+        double si = -1.0 + 2.0 * i / n;
+        for (int a = 0; a < n; ++a) {
+            double s = 0.0;
+            for (int q = 0; q < n; ++q) s += w[q] * lagrange(n, xi, a, si + (1.0 + xi[q]) / n);
+            P[i * n + a] = 0.5 * s;
+        }
+    }
+    memcpy(A, P, sizeof(double) * n * n);
+    for (int i = 0; i < n * n; ++i) Pinv[i] = 0.0;
+    for (int i = 0; i < n; ++i) Pinv[i * n + i] = 1.0;
+    if (solve_dense(n, A, Pinv, n)) return ORC_EINVAL;
     return ORC_OK;
 }
 
@@ -310,11 +339,15 @@ orc_ctx* orc_create(const orc_cfg* cfg)
     X->J = X->dx * X->dz / 4.0;
     double D[MAXN * MAXN], V[MAXN * MAXN], Vi[MAXN * MAXN];
     orc_ref_tables(cfg->k, X->xi, X->w, D, X->em, X->ep, X->dm, X->dp, V, Vi, X->wnc);
+    double Pp[MAXN * MAXN], Pi[MAXN * MAXN];
+    orc_proj_tables(cfg->k, Pp, Pi);
     for (int i = 0; i < X->n1; ++i)
         for (int j = 0; j < X->n1; ++j) {
             X->D[i][j] = D[i * X->n1 + j];
             X->V[i][j] = V[i * X->n1 + j];
             X->Vinv[i][j] = Vi[i * X->n1 + j];
+            X->P[i][j] = Pp[i * X->n1 + j];
+            X->Pinv[i][j] = Pi[i * X->n1 + j];
         }
     /* FV levels: finest = (k+1)nx x (k+1)nz subcells, each coarser level
        agglomerates 2x2 cells (Sec. "Multigrid preconditioner for finite volume") */
@@ -662,18 +695,20 @@ void orc_transfer_T(const orc_ctx* X, const double* U, double* u)
             for (int cc = 0; cc < 4; ++cc) {
                 double t[MAXN][MAXN];
                 double mean = 0.0, quad = 0.0;
+                const int proj = X->c.transfer == 1;   /* subcell averages instead of centre values */
                 for (int j = 0; j < n1; ++j)
                     for (int i = 0; i < n1; ++i) {
                         double s = 0.0;
                         for (int b = 0; b < n1; ++b)
                             for (int a = 0; a < n1; ++a)
-                                s += X->V[i][a] * X->V[j][b] * U[UIDX(X, cc, e, b * n1 + a)];
+                                s += (proj ? X->P[i][a] * X->P[j][b] : X->V[i][a] * X->V[j][b]) *
+                                     U[UIDX(X, cc, e, b * n1 + a)];
                         t[j][i] = s;
                         mean += s;
                         quad += X->wnc[i] * X->wnc[j] * s;
                     }
                 mean /= np;
-                double shift = X->c.mass_fix ? (mean - quad) : 0.0;
+                double shift = (X->c.mass_fix && !proj) ? (mean - quad) : 0.0;
                 for (int j = 0; j < n1; ++j)
                     for (int i = 0; i < n1; ++i)
                         u[cc * nc + (long)(ez * n1 + j) * nxf + ex * n1 + i] = t[j][i] - shift;
@@ -698,12 +733,14 @@ void orc_transfer_Tinv(const orc_ctx* X, const double* u, double* U)
                         quad += X->wnc[i] * X->wnc[j] * t[j][i];
                     }
                 mean /= np;
-                double shift = X->c.mass_fix ? (quad - mean) : 0.0;
+                const int proj = X->c.transfer == 1;
+                double shift = (X->c.mass_fix && !proj) ? (quad - mean) : 0.0;
                 for (int b = 0; b < n1; ++b)
                     for (int a = 0; a < n1; ++a) {
                         double s = 0.0;
                         for (int j = 0; j < n1; ++j)
-                            for (int i = 0; i < n1; ++i) s += X->Vinv[a][i] * X->Vinv[b][j] * t[j][i];
+                            for (int i = 0; i < n1; ++i)
+                                s += (proj ? X->Pinv[a][i] * X->Pinv[b][j] : X->Vinv[a][i] * X->Vinv[b][j]) * t[j][i];
                         U[UIDX(X, cc, e, b * n1 + a)] = s - shift;
                     }
             }

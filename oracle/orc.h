@@ -26,6 +26,8 @@ typedef struct {
     int background;     /* 0 neutral (theta const), 1 constant Brunt-Vaisala N */
     int bc;             /* 0 slip walls everywhere, 1 periodic x + slip z      */
     int mass_fix;       /* 1: transfer with the mass fix (eq. transfer-mass-fix) */
+    int transfer;       /* 0 interpolation at the subcell centres, 1 L2 projection
+                           onto the subcells (subcell averages; no mass fix)       */
     int mg_levels;      /* number of FV levels, finest included               */
     int nu_pre_fine, nu_post_fine, nu_pre, nu_post; /* key mg a b c d e f G: c d e f */
     int cycle;          /* 1 V-cycle, 2 W-cycle                               */
@@ -63,6 +65,9 @@ typedef struct orc_ctx orc_ctx;
 
 int  orc_ref_tables(int k, double* xi, double* w, double* D, double* em, double* ep,
                     double* dm, double* dp, double* V, double* Vinv, double* wnc);
+/* L2 projection onto the k+1 equal subintervals of [-1, 1]: P[i][a] = mean of the
+   Lagrange basis function l_a over subinterval i, and its inverse. */
+int  orc_proj_tables(int k, double* P, double* Pinv);
 orc_ctx* orc_create(const orc_cfg* cfg);
 void orc_destroy(orc_ctx* X);
 long orc_num_dofs(const orc_ctx* X);

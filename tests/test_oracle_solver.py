@@ -85,6 +85,61 @@ def test_transfer_mass_fix_conserves_and_inverts(orc, k):
         assert np.abs(_fv_mass(d, o0.transfer_T(U), dims) - _gl_mass(orc, d, U)).max() > 1e-6
 
 
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_projection_tables_give_exact_subcell_averages(orc, k):
+    """L2 projection onto the subcells: P applied to the nodal values of x^m (m <= k)
+    gives the exact averages (b^(m+1) - a^(m+1)) / ((m+1)(b-a)) over the k+1 equal
+    subintervals [a, b] of [-1, 1]; at degree k+1 the nodal values no longer represent
+    the monomial, so the averages are off (the pin is not satisfied trivially)."""
+    P, Pinv = orc.proj_tables(k)
+    xi = orc.ref_tables(k)["xi"]
+    n1 = k + 1
+    edges = -1.0 + 2.0 * np.arange(n1 + 1) / n1
+    for m in range(k + 2):
+        exact = (edges[1:] ** (m + 1) - edges[:-1] ** (m + 1)) / ((m + 1) * (edges[1:] - edges[:-1]))
+        got = P @ xi ** m
+        if m <= k:
+            np.testing.assert_allclose(got, exact, rtol=0, atol=1e-14)
+        elif k >= 2:   # (k = 1: x^2 at the two GL nodes and its half-interval averages are all 1/3)
+            assert np.abs(got - exact).max() > 1e-4
+    np.testing.assert_allclose(P @ Pinv, np.eye(n1), atol=1e-14)
+    np.testing.assert_allclose(P.sum(axis=1), 1.0, atol=1e-15)   # constants are kept
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_projection_transfer_conserves_and_inverts(orc, k):
+    """transfer = 1: T is the subcell averaging of the DG polynomial, so the FV mass
+    equals the element integral (GL quadrature is exact for the nodal Q_k function);
+    T^-1 is its exact inverse; the mass fix does not apply (it would be the identity
+    for exact arithmetic and is switched off)."""
+    d = W.small(nx=3, nz=2, k=k, transfer=1, mass_fix=1)
+    o = orc.Oracle(d)
+    U = W.random_state(o.ndof, 9, [1.0, 2.0, 3.0, 4.0])
+    u = o.transfer_T(U)
+    dims = o.fv_dims(0)
+    np.testing.assert_allclose(_fv_mass(d, u, dims), _gl_mass(orc, d, U), rtol=1e-13, atol=1e-9)
+    np.testing.assert_allclose(o.transfer_Tinv(u), U, rtol=0, atol=1e-12)
+    v = W.random_state(dims[0] * dims[1] * 4, 10, [1.0, 1.0, 1.0, 1.0])
+    np.testing.assert_allclose(_gl_mass(orc, d, o.transfer_Tinv(v)), _fv_mass(d, v, dims), rtol=1e-13, atol=1e-9)
+    # a polynomial of degree <= k: each subcell value is its exact average over the subcell
+    rng = np.random.default_rng(20 + k)
+    coef = rng.standard_normal((4, k + 1, k + 1))
+    U = _poly_dg(orc, d, coef)
+    u = o.transfer_T(U)
+    n1 = k + 1
+    nxf = 3 * n1
+    edges = -1.0 + 2.0 * np.arange(n1 + 1) / n1
+    avg = lambda p, i: (edges[i + 1] ** (p + 1) - edges[i] ** (p + 1)) / ((p + 1) * (edges[i + 1] - edges[i]))
+    for c in range(4):
+        for e in range(6):
+            ez, ex = divmod(e, 3)
+            for j in range(n1):
+                for i in range(n1):
+                    val = sum(coef[c][p][q] * avg(p, i) * avg(q, j) for p in range(n1) for q in range(n1)) + e
+                    got = u[c * (nxf * 2 * n1) + (ez * n1 + j) * nxf + ex * n1 + i]
+                    assert got == pytest.approx(val, abs=1e-12)
+
+
 def test_restriction_prolongation(orc):
     d = W.small(nx=4, nz=4, k=1, mg_levels=3)
     o = orc.Oracle(d)
@@ -413,9 +468,12 @@ def test_newton_update_conserves_mass(orc):
     assert np.all(drift[0] > 100 * drift[1]), drift
 
 
-def test_step_conserves_mass(orc):
+@pytest.mark.parametrize("transfer", [0, 1])
+def test_step_conserves_mass(orc, transfer):
+    """Mass-fixed interpolation (transfer 0) and the L2 projection (transfer 1) both keep
+    the rho and rho-theta mass of a whole SDIRK2 step."""
     d, pert, _ = W.bubble_small()
-    dd = dict(d, nx=8, nz=8, k=2, scheme=1, dt=2.0)
+    dd = dict(d, nx=8, nz=8, k=2, scheme=1, dt=2.0, transfer=transfer)
     o = orc.Oracle(dd)
     U0 = o.initial_state(pert)
     rc, U1, _ = o.implicit_step(U0)
