@@ -72,7 +72,10 @@ typedef struct {
                                  ||G|| (the rounding floor of G lies above rtol); 0: off */
     int batch;                /* members of a lock-step batch (0 or 1: a single problem);
                                  see "lock-step batches" below                          */
-    int reserved;
+    int transfer;             /* DG <-> FV transfer (Sec. "Transfer functions"): 0 the
+                                 interpolation at the subcell centres (with mass_fix),
+                                 1 the L2 projection onto the subcells (subcell averages;
+                                 conserves mass, mass_fix does not apply)              */
 } jfmg_config;
 
 typedef struct {

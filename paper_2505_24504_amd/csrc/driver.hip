@@ -124,7 +124,28 @@ bool invert(int n, const double A[MAXN1][MAXN1], double Ai[MAXN1][MAXN1])
     return true;
 }
 
-bool build_reftab(int k, RefTab& R)
+// Monomial coefficients (lowest degree first) of the Lagrange polynomial l_j
+// through the nodes x[0..n).
+void lagrange_coefs(int n, const double* x, int j, double* coef)
+{
+    for (int d = 0; d <= n; ++d) coef[d] = 0.0;
+    coef[0] = 1.0;
+    int deg = 0;
+    for (int m = 0; m < n; ++m) {
+        if (m == j) continue;
+        const double s = 1.0 / (x[j] - x[m]);
+        for (int d = deg + 1; d >= 0; --d) {
+            const double lower = d > 0 ? coef[d - 1] : 0.0;
+            coef[d] = (lower - x[m] * coef[d]) * s;
+        }
+        ++deg;
+    }
+}
+
+// transfer 0: the subcell-centre values of the nodal polynomial (V) and the inverse
+// map; transfer 1: its subcell averages (L2 projection onto the subcells), in 1D
+// P_ia = (1/h) int over [s_i, s_i + h] of l_a, h = 2/(k+1), integrated term by term.
+bool build_reftab(int k, int transfer, RefTab& R)
 {
     const int n = k + 1;
     std::memset(&R, 0, sizeof(R));
@@ -145,7 +166,25 @@ bool build_reftab(int k, RefTab& R)
     B.eval(1.0, R.ep);
     B.deriv(-1.0, R.dm);
     B.deriv(1.0, R.dp);
-    for (int i = 0; i < n; ++i) B.eval(-1.0 + (2.0 * i + 1.0) / n, R.V[i]);
+    if (transfer == 1) {
+        const double h = 2.0 / n;
+        for (int a = 0; a < n; ++a) {
+            double coef[MAXN1 + 1];
+            lagrange_coefs(n, R.xi, a, coef);
+            for (int i = 0; i < n; ++i) {
+                const double lo = -1.0 + i * h, hi = lo + h;
+                double integ = 0.0, plo = lo, phi = hi;   // lo^(d+1), hi^(d+1)
+                for (int d = 0; d < n; ++d) {
+                    integ += coef[d] * (phi - plo) / (d + 1);
+                    plo *= lo;
+                    phi *= hi;
+                }
+                R.V[i][a] = integ / h;
+            }
+        }
+    } else {
+        for (int i = 0; i < n; ++i) B.eval(-1.0 + (2.0 * i + 1.0) / n, R.V[i]);
+    }
     if (!invert(n, R.V, R.Vinv)) return false;
     // interpolatory rule on the subcell centres of [0,1]: w_i = int_0^1 of the
     // Lagrange polynomial through G_m = (2m+1)/(2(k+1)), integrated term by term
@@ -435,6 +474,7 @@ jfmg_status validate(const jfmg_config& c, Key& key, std::string& msg)
     if (c.rk_stages < 1 || c.rk_stages > 4) { msg = "rk_stages must be in 1..4"; return JFMG_EINVAL; }
     if (c.mg_levels < 1 || c.mg_levels > MAXLEV) { msg = "mg_levels must be in 1..8"; return JFMG_EINVAL; }
     if (c.mg_precision != 32 && c.mg_precision != 64) { msg = "mg_precision must be 32 or 64"; return JFMG_EINVAL; }
+    if (c.transfer != 0 && c.transfer != 1) { msg = "transfer must be 0 (interpolation) or 1 (L2 projection)"; return JFMG_EINVAL; }
     if (c.newton_maxit < 1 || c.gmres_max_restarts < 0) { msg = "bad iteration caps"; return JFMG_EINVAL; }
     if (!(c.newton_stall >= 0.0 && c.newton_stall < 1.0)) { msg = "newton_stall must be in [0, 1)"; return JFMG_EINVAL; }
     if (!(c.dt > 0) || !(c.gamma > 1) || !(c.R > 0) || !(c.p0 > 0) || !(c.theta0 > 0) || c.mu < 0) {
@@ -511,6 +551,8 @@ hipError_t copy_members(jfmg_problem* p, void* dst, const void* src, size_t byte
                             hipMemcpyDeviceToDevice, p->st);
 }
 Red no_red() { return Red{nullptr, nullptr}; }
+// the mass fix corrects the interpolation transfer only (the L2 projection conserves mass)
+int mass_fix_of(const jfmg_problem* p) { return p->cfg.transfer == 0 ? p->cfg.mass_fix : 0; }
 double* fvpart(jfmg_problem* p, int l, int bi) { return p->fvpart + (FVP_PER_LEVEL * l + bi) * p->fvp; }
 
 // read `count` device scalars starting at `slot` of every member into
@@ -566,7 +608,7 @@ template <typename T> jfmg_status linearize_t(jfmg_problem* p, const double* U, 
     if (U != p->Ulin) HIPCHK(p, copy_members(p, p->Ulin, U, sizeof(double) * p->N));
     p->adt = adt;
     launch_norm2_total(p->cfg.k, p->A, p->Ulin, red_at(p, S_UTOT), st, p->mb);
-    launch_transfer_T<T>(p->cfg.k, p->A, p->cfg.mass_fix, p->Ulin, (T*)p->lev[0].u, p->lev[0].nx, st, nullptr, nullptr,
+    launch_transfer_T<T>(p->cfg.k, p->A, mass_fix_of(p), p->Ulin, (T*)p->lev[0].u, p->lev[0].nx, st, nullptr, nullptr,
                          p->mb);
     for (int l = 0; l + 1 < p->nlev; ++l)
         FvLaunch<T>::restrict_(fv_args<T>(p, l), (const T*)p->lev[l].u, (T*)p->lev[l + 1].u, st, p->mb);
@@ -717,13 +759,13 @@ template <typename T> jfmg_status mg_apply_t(jfmg_problem* p, double* r, double*
         const ZeroStage<T> z0 = mg.zero_stage(0, p->key.c);
         ProfScope ps(p, JFMG_K_TRANSFER_T,
                      (double)p->N * (8 + (z0.x1 ? 2 : 1) * sizeof(T)) + (rnrm2 ? 8.0 * p->N : 0.0));
-        const int nb = launch_transfer_T<T>(p->cfg.k, p->A, p->cfg.mass_fix, r, (T*)L.b, L.nx, p->st, rnrm2,
+        const int nb = launch_transfer_T<T>(p->cfg.k, p->A, mass_fix_of(p), r, (T*)L.b, L.nx, p->st, rnrm2,
                                             rnrm2 ? r : nullptr, p->mb, z0);
         if (z0.x1) mg.s.pre[0] = nb;
     }
     T* x = mg.run();
     ProfScope ps(p, JFMG_K_TRANSFER_TINV, (double)p->N * (8 + sizeof(T)));
-    launch_transfer_Tinv<T>(p->cfg.k, p->A, p->cfg.mass_fix, x, z, L.nx, red_at(p, zslot), p->st, p->mb);
+    launch_transfer_Tinv<T>(p->cfg.k, p->A, mass_fix_of(p), x, z, L.nx, red_at(p, zslot), p->st, p->mb);
     return check_launch(p);
 }
 
@@ -1199,7 +1241,10 @@ jfmg_status jfmg_create_problem(const jfmg_config* cfg, void* workspace, size_t 
         const char* ng = std::getenv("JFMG_NO_GRAPH");
         p->use_graphs = !(ng && ng[0] == '1');
     }
-    if (!build_reftab(cfg->k, p->R)) { delete p; return fail(nullptr, JFMG_EINVAL, "singular subcell interpolation"); }
+    if (!build_reftab(cfg->k, cfg->transfer, p->R)) {
+        delete p;
+        return fail(nullptr, JFMG_EINVAL, "singular subcell transfer");
+    }
     layout(*cfg, (char*)workspace, [&](const char* name, void* ptr, size_t n) {
         const std::string nm(name);
         if (nm == "scal") p->scal = (double*)ptr;
@@ -1495,11 +1540,11 @@ jfmg_status jfmg_transfer(jfmg_problem* p, int dir, const void* in, void* out)
     if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step, jfmg_initial_state, jfmg_linearize and the tile calls");
     const int nxf = p->lev[0].nx;
     if (dir == 0) {
-        if (p->prec == 32) launch_transfer_T<float>(p->cfg.k, p->A, p->cfg.mass_fix, (const double*)in, (float*)out, nxf, p->st);
-        else launch_transfer_T<double>(p->cfg.k, p->A, p->cfg.mass_fix, (const double*)in, (double*)out, nxf, p->st);
+        if (p->prec == 32) launch_transfer_T<float>(p->cfg.k, p->A, mass_fix_of(p), (const double*)in, (float*)out, nxf, p->st);
+        else launch_transfer_T<double>(p->cfg.k, p->A, mass_fix_of(p), (const double*)in, (double*)out, nxf, p->st);
     } else {
-        if (p->prec == 32) launch_transfer_Tinv<float>(p->cfg.k, p->A, p->cfg.mass_fix, (const float*)in, (double*)out, nxf, no_red(), p->st);
-        else launch_transfer_Tinv<double>(p->cfg.k, p->A, p->cfg.mass_fix, (const double*)in, (double*)out, nxf, no_red(), p->st);
+        if (p->prec == 32) launch_transfer_Tinv<float>(p->cfg.k, p->A, mass_fix_of(p), (const float*)in, (double*)out, nxf, no_red(), p->st);
+        else launch_transfer_Tinv<double>(p->cfg.k, p->A, mass_fix_of(p), (const double*)in, (double*)out, nxf, no_red(), p->st);
     }
     return check_launch(p);
 }

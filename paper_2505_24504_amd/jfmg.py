@@ -33,7 +33,7 @@ class Config(C.Structure):
         "x0", "x1", "z0", "z1", "g", "gamma", "R", "p0", "theta0", "N", "u_mean", "mu", "c_ip", "dt",
         "newton_rtol", "ew_gamma", "ew_alpha", "ew_eta0", "ew_eta_max")] + [
         ("rk_alpha", C.c_double * 4), ("pseudo_cfl", C.c_double), ("newton_stall", C.c_double),
-        ("batch", C.c_int), ("reserved", C.c_int)]
+        ("batch", C.c_int), ("transfer", C.c_int)]
 
 
 class Perturbation(C.Structure):
@@ -141,7 +141,7 @@ def make_config(d: dict) -> Config:
     L.jfmg_config_default(C.byref(c))
     ints = ("nx", "nz", "k", "physics", "background", "bc", "scheme", "newton_maxit", "gmres_m",
             "gmres_max_restarts", "fd_eps_mode", "mg_levels", "rk_stages", "mass_fix", "mg_precision",
-            "precond", "batch")
+            "precond", "batch", "transfer")
     dbls = ("x0", "x1", "z0", "z1", "g", "gamma", "R", "p0", "theta0", "N", "u_mean", "mu", "c_ip", "dt",
             "newton_rtol", "ew_gamma", "ew_alpha", "ew_eta0", "ew_eta_max", "pseudo_cfl", "newton_stall")
     for n in ints:

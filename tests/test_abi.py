@@ -77,7 +77,7 @@ def test_workspace_sizes(lib):
     ({"k": 0}, "k must"), ({"k": 4}, "k must"), ({"gmres_m": 65}, "gmres_m"),
     ({"mg_levels": 9}, "mg_levels"), ({"mg_key": "mg102222V"}, "a, b"), ({"mg_key": "mgxx"}, "key"),
     ({"nx": 3, "mg_levels": 3}, "odd"), ({"mg_precision": 16}, "precision"), ({"rk_stages": 5}, "rk_stages"),
-    ({"background": 1, "N": 0.0}, "N > 0"), ({"dt": 0.0}, "constants"),
+    ({"background": 1, "N": 0.0}, "N > 0"), ({"dt": 0.0}, "constants"), ({"transfer": 2}, "transfer"),
 ])
 def test_invalid_configs_rejected(lib, bad, what):
     d, _, _ = W.bubble_small()
