@@ -100,6 +100,7 @@ def lib():
                                  C.c_int, C.c_int, dp, C.POINTER(C.c_int)]
         L.orc_newton_stage.argtypes = [C.c_void_p, dp, C.c_double, dp, C.POINTER(OrcStats)]
         L.orc_implicit_step.argtypes = [C.c_void_p, dp, C.POINTER(OrcStats)]
+        L.orc_explicit_steps.argtypes = [C.c_void_p, dp, C.c_double, C.c_int]
         _lib = L
     return _lib
 
@@ -326,6 +327,12 @@ class Oracle:
         st = OrcStats()
         rc = self.L.orc_newton_stage(self.h, _p(Ubar), float(alpha_dt), _p(U), C.byref(st))
         return rc, U, st.as_dict()
+
+    def explicit_steps(self, U, dt, nsteps):
+        """nsteps explicit SSP RK(4,3) steps of size dt; returns the new state."""
+        U = np.array(U, dtype=np.float64, copy=True)
+        self.L.orc_explicit_steps(self.h, _p(U), float(dt), int(nsteps))
+        return U
 
     def implicit_step(self, U):
         U = np.array(U, dtype=np.float64, copy=True)

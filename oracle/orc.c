@@ -1178,6 +1178,33 @@ done:
     return status;
 }
 
+/* Explicit reference time stepping (the paper's reference runs use a 4-stage,
+   third-order SSP Runge-Kutta method, cited to Ketcheson 2008): for
+   dU/dt = f(U) = M^-1 L_h(U), with SSP coefficient 2,
+       U1 = U + dt/2 f(U)
+       U2 = U1 + dt/2 f(U1)
+       U3 = 2/3 U + 1/3 U2 + dt/6 f(U2)
+       U_new = U3 + dt/2 f(U3).
+   nsteps steps of size dt, U updated in place. */
+void orc_explicit_steps(orc_ctx* X, double* U, double dt, int nsteps)
+{
+    long n = X->ndof;
+    double* U1 = (double*)malloc(sizeof(double) * n);
+    double* f = (double*)malloc(sizeof(double) * n);
+    for (int it = 0; it < nsteps; ++it) {
+        orc_residual(X, U, f, 1);
+        for (long i = 0; i < n; ++i) U1[i] = U[i] + 0.5 * dt * f[i];
+        orc_residual(X, U1, f, 1);
+        for (long i = 0; i < n; ++i) U1[i] = U1[i] + 0.5 * dt * f[i];
+        orc_residual(X, U1, f, 1);
+        for (long i = 0; i < n; ++i) U1[i] = (2.0 / 3.0) * U[i] + (1.0 / 3.0) * U1[i] + (dt / 6.0) * f[i];
+        orc_residual(X, U1, f, 1);
+        for (long i = 0; i < n; ++i) U[i] = U1[i] + 0.5 * dt * f[i];
+    }
+    free(U1);
+    free(f);
+}
+
 /* One implicit step (Sec. "Temporal discretization"): implicit Euler, or
    SDIRK2 of Ellsiepen, alpha = 1 - sqrt(2)/2, tableau [[a,0],[1-a,a]]:
    U_1 solves G with Ubar_1 = U^n; Ubar_2 = U^n + (1-a) dt f(U_1); U^{n+1} = U_2.

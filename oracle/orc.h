@@ -104,6 +104,8 @@ int  orc_fgmres(long n, orc_op A, void* actx, orc_op P, void* pctx, const double
 
 int  orc_newton_stage(orc_ctx* X, const double* Ubar, double alpha_dt, double* U, orc_stats* st);
 int  orc_implicit_step(orc_ctx* X, double* U, orc_stats* st);
+/* nsteps explicit SSP RK(4,3) steps of size dt (the paper's reference method) */
+void orc_explicit_steps(orc_ctx* X, double* U, double dt, int nsteps);
 
 #ifdef __cplusplus
 }

@@ -481,3 +481,55 @@ def test_step_conserves_mass(orc, transfer):
     m0, m1 = _gl_mass(orc, dd, U0), _gl_mass(orc, dd, U1)
     ww = np.abs(_gl_mass(orc, dd, np.abs(U1 - U0)))
     assert np.all((np.abs(m1 - m0) / ww)[[0, 3]] < 1e-9)
+
+
+# --------------------------------------------------------------------------
+# explicit SSP RK(4,3) reference time stepping
+# --------------------------------------------------------------------------
+
+def test_explicit_rest_state_stays_zero(orc):
+    """Hydrostatic rest without viscosity: f(0) = 0 bitwise (well-balanced operator), so
+    every step keeps 0."""
+    d = W.small(nx=4, nz=4, k=2)
+    o = orc.Oracle(d)
+    U = np.zeros(o.ndof)
+    assert np.array_equal(o.explicit_steps(U, 0.05, 3), U)
+
+
+def test_explicit_stability_polynomial(orc):
+    """For a small perturbation of the rest state f(U) = J U + O(|U|^2), so one step is
+    R(dt J) U with the method's stability polynomial R(z) = 1 + z + z^2/2 + z^3/6 + z^4/48
+    (the closed form of the 4-stage, order-3 SSP scheme).  J v from the oracle's FD
+    Jacobian-vector product at the rest state: G'v = v - adt J v."""
+    d = W.small(nx=4, nz=4, k=2)
+    o = orc.Oracle(d)
+    U = W.random_state(o.ndof, 11, [1e-9, 3e-8, 3e-8, 3e-7])
+    dt, adt = 0.02, 0.5
+    o.linearize(np.zeros(o.ndof), adt)
+    Jv = lambda v: (v - o.jvp(v)) / adt
+    p, term = U.copy(), U.copy()
+    for m, c in ((1, 1.0), (2, 0.5), (3, 1.0 / 6.0), (4, 1.0 / 48.0)):
+        term = Jv(term)
+        p = p + c * dt ** m * term
+    got = o.explicit_steps(U, dt, 1)
+    # the dt^4 term is ~1e-3 of the step's change here: a wrong coefficient shows
+    assert np.linalg.norm(got - p) <= 1e-6 * np.linalg.norm(got - U)
+    bad = p + (1.0 / 24.0 - 1.0 / 48.0) * dt ** 4 * Jv(Jv(Jv(Jv(U))))   # classical RK4's z^4/24
+    assert np.linalg.norm(got - bad) > 1e-4 * np.linalg.norm(got - U)
+
+
+def test_explicit_order_and_mass(orc):
+    """Third order in dt (against a 32x finer run) and rho / rho-theta mass kept."""
+    d, pert, _ = W.bubble_small()
+    d = dict(d, nx=8, nz=8, k=2, physics=1, mu=75.0)
+    o = orc.Oracle(d)
+    U0 = o.initial_state(pert)
+    T = 0.2
+    ref = o.explicit_steps(U0, T / 128, 128)
+    e = [np.linalg.norm(o.explicit_steps(U0, T / n, n) - ref) for n in (4, 8, 16)]
+    orders = [np.log2(e[0] / e[1]), np.log2(e[1] / e[2])]
+    assert all(abs(r - 3.0) < 0.3 for r in orders), (e, orders)
+    U1 = o.explicit_steps(U0, T / 8, 8)
+    m0, m1 = _gl_mass(orc, d, U0), _gl_mass(orc, d, U1)
+    ww = np.abs(_gl_mass(orc, d, np.abs(U1 - U0)))
+    assert np.all((np.abs(m1 - m0) / ww)[[0, 3]] < 1e-12)
