@@ -287,6 +287,43 @@ def inertia_gravity_forms(steps=3):
     return out
 
 
+def explicit_reference_form(d, pert, implicit_ms_per_step, reps=5):
+    """The paper's reference method beside the implicit solver on the same workload:
+    SSP RK(4,3) at dt = h / ((2k+1) 380 m/s), the largest of the tried CFL factors
+    that stays finite over 20 s of the density current (1.25x diverges), run over one
+    implicit step interval; the SDIRK2 step's relative L2 distance from it at that time
+    is the implicit step's time-discretisation error against the reference."""
+    import numpy as np
+    import torch
+    from paper_2505_24504_amd import jfmg
+    T = d["dt"]
+    h = min((d["x1"] - d["x0"]) / d["nx"], (d["z1"] - d["z0"]) / d["nz"])
+    n = int(np.ceil(T / (h / ((2 * d["k"] + 1) * 380.0))))
+    dt = T / n
+    p = jfmg.Problem(d, device="cuda:0")
+    U0 = p.initial_state(pert)
+    Ue = U0.clone()
+    p.explicit_steps(Ue, dt, n)      # warm-up run, also the reference state at time T
+    Ui = U0.clone()
+    st = p.implicit_step(Ui)
+    U = U0.clone()
+    _sync()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        p.explicit_steps(U, dt, n)
+    _sync()
+    el = (time.perf_counter() - t0) / reps
+    N = jfmg.num_dofs(d)
+    return {"dt": dt, "steps_per_interval": n, "interval_s": T,
+            "explicit_ms_per_simulated_s": 1e3 * el / T,
+            "implicit_ms_per_simulated_s": implicit_ms_per_step / T,
+            "explicit_dof_steps_per_s": n * N / el,
+            "dg_stage_us": 1e6 * el / (4 * n),
+            "implicit_vs_explicit_rel_l2": float((Ui - Ue).norm() / (Ue - U0).norm()),
+            "implicit_newton_its": st["newton_its"], "implicit_gmres_its": st["gmres_its"],
+            "finite": bool(torch.isfinite(U).all().item())}
+
+
 def large_roofline(reps=20):
     """The FV operator and the DG JVP on vectors far above the 256 MB cache:
     a 1024x1024-quad, k = 3 problem (FV level 4096x4096 cells, DG vector 537 MB,
@@ -428,6 +465,7 @@ def main():
         forms.update(ensemble_forms())
         forms.update(serving_forms(a.serve_requests))
         forms["inertia_gravity"] = inertia_gravity_forms()
+        forms["explicit_reference"] = explicit_reference_form(d, pert, 1e3 * el / a.steps)
     if not a.no_large:
         out["roofline_hbm_resident"] = large_roofline()
     # copy bandwidth of the device: HBM-resident (1 GiB) and cache-resident (32 MiB)

@@ -167,6 +167,17 @@ jfmg_status jfmg_mg_apply(jfmg_problem* p, const double* r, double* z);
    FGMRES (Sec. "Solver").  On any error U is left unchanged.  stats may be NULL. */
 jfmg_status jfmg_implicit_step(jfmg_problem* p, double* U, jfmg_stats* stats);
 
+/* nsteps explicit steps U^n -> U^{n+1} in place with the four-stage,
+   third-order strong-stability-preserving Runge-Kutta method (Ketcheson 2008)
+   that the paper's reference runs use (Sec. "Numerical Experiments", set-up):
+   U1 = U + dt/2 f(U), U2 = U1 + dt/2 f(U1), U3 = 2/3 U + 1/3 U2 + dt/6 f(U2),
+   U^{n+1} = U3 + dt/2 f(U3), with f = M^-1 L_h.  U is a device DG vector; the
+   call is queued on the problem's stream without host synchronization and uses
+   the problem's workspace (do not overlap it with other calls on the problem).
+   dt is not limited here: a step beyond the CFL limit diverges.  EINVAL for a
+   batched problem, a non-finite dt or nsteps < 0. */
+jfmg_status jfmg_explicit_steps(jfmg_problem* p, double* U, double dt, int nsteps);
+
 /* ---- finer-grained calls on the preconditioner's pieces (FV vectors in the
         problem's multigrid precision) ---- */
 

@@ -39,7 +39,7 @@ template <int N1, bool NS, int MODE>
 __global__ void __launch_bounds__(DgShape<N1>::NTH, 3)
 dg_kernel(DgArgs A, const double* __restrict__ U, const double* __restrict__ Y, const double* __restrict__ Ubar,
           double* __restrict__ out, const double* __restrict__ yn2p, const double* __restrict__ ut2p, int eps_mode,
-          double adt, Red red, long ms)
+          double adt, Red red, long ms, ExStage rk)
 {
     if (gridDim.z > 1) {   // member of a lock-step batch
         U = mbr(U, ms);
@@ -313,8 +313,11 @@ dg_kernel(DgArgs A, const double* __restrict__ U, const double* __restrict__ Y, 
                 const double G = sS[0][le][c][nd] - adt * (L * im) - Ubar[o];
                 out[o] = G;
                 nrm += G * G;
-            } else {
+            } else if constexpr (MODE == 3) {
                 out[o] = yv[c] - sc * (L * im);
+            } else {   // explicit Runge-Kutta stage
+                const double base = rk.a0 != 0.0 ? rk.a0 * Ubar[o] : 0.0;
+                out[o] = base + rk.a1 * sS[0][le][c][nd] + rk.c * (L * im);
             }
         }
     }
@@ -330,32 +333,43 @@ int dg_grid(int k, long ne)
 template <int N1, bool NS>
 static void launch_dg_n(int mode, const DgArgs& A, const double* U, const double* Y, const double* Ubar,
                         double* out, const double* yn2, const double* ut2, int eps_mode, double adt, Red red,
-                        hipStream_t st, const Mb& mb)
+                        hipStream_t st, const Mb& mb, const ExStage& ex)
 {
     const dim3 grid(dg_grid(N1 - 1, A.ne), 1, mb.n), block(DgShape<N1>::NTH);
     if (mode == 2 && red.out) {
-        timed_launch(dg_kernel<N1, NS, 2>, grid, block, st, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, mb.ms);
+        timed_launch(dg_kernel<N1, NS, 2>, grid, block, st, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, mb.ms,
+                     ex);
         launch_finalize(red.partials, (int)grid.x, 1, red.out, st, Gate{}, mb);
         return;
     }
+#define JFMG_DG_CASE(M)                                                                                             \
+    case M:                                                                                                         \
+        timed_launch(dg_kernel<N1, NS, M>, grid, block, st, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, mb.ms, \
+                     ex);                                                                                           \
+        break;
     switch (mode) {
-    case 0: timed_launch(dg_kernel<N1, NS, 0>, grid, block, st, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, mb.ms); break;
-    case 1: timed_launch(dg_kernel<N1, NS, 1>, grid, block, st, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, mb.ms); break;
-    case 2: timed_launch(dg_kernel<N1, NS, 2>, grid, block, st, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, mb.ms); break;
-    default: timed_launch(dg_kernel<N1, NS, 3>, grid, block, st, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, mb.ms); break;
+        JFMG_DG_CASE(0)
+        JFMG_DG_CASE(1)
+        JFMG_DG_CASE(2)
+        JFMG_DG_CASE(4)
+    default:
+        timed_launch(dg_kernel<N1, NS, 3>, grid, block, st, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, mb.ms,
+                     ex);
+        break;
     }
+#undef JFMG_DG_CASE
 }
 
 void launch_dg(int k, bool ns, int mode, const DgArgs& A, const double* U, const double* Y, const double* Ubar,
                double* out, const double* yn2, const double* ut2, int eps_mode, double adt, Red red, hipStream_t st,
-               const Mb& mb)
+               const Mb& mb, const ExStage& ex)
 {
-    if (k == 1) { if (ns) launch_dg_n<2, true>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb);
-                  else launch_dg_n<2, false>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb); }
-    else if (k == 2) { if (ns) launch_dg_n<3, true>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb);
-                       else launch_dg_n<3, false>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb); }
-    else { if (ns) launch_dg_n<4, true>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb);
-           else launch_dg_n<4, false>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb); }
+    if (k == 1) { if (ns) launch_dg_n<2, true>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb, ex);
+                  else launch_dg_n<2, false>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb, ex); }
+    else if (k == 2) { if (ns) launch_dg_n<3, true>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb, ex);
+                       else launch_dg_n<3, false>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb, ex); }
+    else { if (ns) launch_dg_n<4, true>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb, ex);
+           else launch_dg_n<4, false>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb, ex); }
 }
 
 // ---------------------------------------------------------------------------

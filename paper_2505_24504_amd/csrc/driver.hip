@@ -1534,6 +1534,27 @@ jfmg_status jfmg_implicit_step(jfmg_problem* p, double* U, jfmg_stats* stats)
     return s;
 }
 
+jfmg_status jfmg_explicit_steps(jfmg_problem* p, double* U, double dt, int nsteps)
+{
+    if (!p || !U) return fail(p, JFMG_EINVAL, "null argument");
+    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step, jfmg_initial_state, jfmg_linearize and the tile calls");
+    if (!(std::isfinite(dt)) || nsteps < 0) return fail(p, JFMG_EINVAL, "dt must be finite and nsteps >= 0");
+    // SSP RK(4,3): four stages of size dt/2 with the convex combination
+    // 2/3 U^n + 1/3 U^(2) before the third; every stage is one DG launch with
+    // the combination fused into its output (the input is never the output)
+    const int k = p->cfg.k;
+    const bool ns = p->cfg.physics == 1;
+    const ExStage half{0.0, 1.0, 0.5 * dt}, third{2.0 / 3.0, 1.0 / 3.0, dt / 6.0};
+    for (int it = 0; it < nsteps; ++it) {
+        launch_dg(k, ns, 4, p->A, U, nullptr, nullptr, p->Uk, nullptr, nullptr, 0, 0.0, no_red(), p->st, Mb{}, half);
+        launch_dg(k, ns, 4, p->A, p->Uk, nullptr, nullptr, p->tmp2, nullptr, nullptr, 0, 0.0, no_red(), p->st, Mb{},
+                  half);
+        launch_dg(k, ns, 4, p->A, p->tmp2, nullptr, U, p->Uk, nullptr, nullptr, 0, 0.0, no_red(), p->st, Mb{}, third);
+        launch_dg(k, ns, 4, p->A, p->Uk, nullptr, nullptr, U, nullptr, nullptr, 0, 0.0, no_red(), p->st, Mb{}, half);
+    }
+    return check_launch(p);
+}
+
 jfmg_status jfmg_transfer(jfmg_problem* p, int dir, const void* in, void* out)
 {
     if (!p || !in || !out || (dir != 0 && dir != 1)) return fail(p, JFMG_EINVAL, "bad argument");

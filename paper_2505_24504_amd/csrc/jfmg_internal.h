@@ -87,9 +87,14 @@ struct Mb {
 // mode 0: <psi,L>  1: M^-1 L  2: G = U - adt M^-1 L - Ubar (+ ||G||^2 into red.out)
 // mode 3: JVP out = Y - adt/eps M^-1 (L(U+eps Y) - L(U)), eps from the device scalars
 //         yn2 = ||Y||^2 and ut2 = ||U + Ubar||^2 (eps_mode 1)
+// mode 4: explicit Runge-Kutta stage out = ex.a0 Ubar + ex.a1 U + ex.c M^-1 L(U)
+//         (out must not alias U: neighbour traces are read from U by other blocks)
+struct ExStage {
+    double a0 = 0.0, a1 = 1.0, c = 0.0;
+};
 void launch_dg(int k, bool ns, int mode, const DgArgs& A, const double* U, const double* Y,
                const double* Ubar, double* out, const double* yn2, const double* ut2, int eps_mode,
-               double adt, Red red, hipStream_t st, const Mb& mb = Mb{});
+               double adt, Red red, hipStream_t st, const Mb& mb = Mb{}, const ExStage& ex = ExStage{});
 int transfer_grid(int k, long ne);
 int dg_grid(int k, long ne);
 void launch_initial_state(int k, const DgArgs& A, int shape, double amp, double xc, double zc,

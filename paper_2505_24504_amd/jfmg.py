@@ -60,7 +60,7 @@ _lib = None
 EXPORTS = [
     "jfmg_config_default", "jfmg_workspace_bytes", "jfmg_create_problem", "jfmg_destroy_problem",
     "jfmg_num_dofs", "jfmg_fv_size", "jfmg_initial_state", "jfmg_residual", "jfmg_stage_residual",
-    "jfmg_linearize", "jfmg_jvp", "jfmg_mg_apply", "jfmg_implicit_step", "jfmg_transfer",
+    "jfmg_linearize", "jfmg_jvp", "jfmg_mg_apply", "jfmg_implicit_step", "jfmg_explicit_steps", "jfmg_transfer",
     "jfmg_restrict", "jfmg_prolong", "jfmg_fv_level_state", "jfmg_fv_dtau", "jfmg_fv_matvec",
     "jfmg_mg_fv", "jfmg_subgrid_map", "jfmg_profile_enable", "jfmg_profile_read", "jfmg_last_error",
     "jfmg_batch_create", "jfmg_batch_destroy", "jfmg_batch_admit", "jfmg_batch_member", "jfmg_batch_run",
@@ -99,6 +99,7 @@ def load_library(path: str = LIB_PATH):
         "jfmg_jvp": (C.c_int, [vp, vp, vp]),
         "jfmg_mg_apply": (C.c_int, [vp, vp, vp]),
         "jfmg_implicit_step": (C.c_int, [vp, vp, C.POINTER(Stats)]),
+        "jfmg_explicit_steps": (C.c_int, [vp, vp, C.c_double, C.c_int]),
         "jfmg_transfer": (C.c_int, [vp, C.c_int, vp, vp]),
         "jfmg_restrict": (C.c_int, [vp, C.c_int, vp, vp]),
         "jfmg_prolong": (C.c_int, [vp, C.c_int, vp, vp]),
@@ -266,6 +267,10 @@ class Problem:
         if rc and raise_on_error:
             self._check(rc)
         return d
+
+    def explicit_steps(self, U, dt, nsteps):
+        """Advance U (device tensor) in place by nsteps explicit SSP RK(4,3) steps of size dt."""
+        self._check(self.L.jfmg_explicit_steps(self.h, _ptr(U), float(dt), int(nsteps)))
 
     def transfer(self, direction, x):
         if direction == 0:

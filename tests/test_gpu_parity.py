@@ -456,6 +456,78 @@ def test_step_determinism_and_mass():
     assert drift[(0, 0)] > 100 * max(drift[(1, 0)], drift[(0, 1)])
 
 
+# --------------------------------------------------------------------------
+# explicit SSP RK(4,3) reference stepping
+# --------------------------------------------------------------------------
+
+def _cfl_dt(d, frac=0.3, speed=380.0):
+    h = min((d["x1"] - d["x0"]) / d["nx"], (d["z1"] - d["z0"]) / d["nz"])
+    return frac * h / ((2 * d["k"] + 1) * speed)
+
+
+def _explicit_check(d, o, U0, Ug, Uo, dt, n):
+    """Each of the 4n stages adds the rounding of L_h, a few ulps of the rounding scale
+    sigma of the well-balanced form (sums of absolute values of the unsubtracted terms),
+    scaled by dt/2, and rounding of the stage combination relative to U itself:
+    tol = 1e-11 ||update|| + 1e-15 n dt ||sigma / m|| + 1e-14 ||U||."""
+    sig = o.residual(U0, 3) / dg_mass(d)[None, :].repeat(4, 0).ravel()
+    sdt = n * dt * np.linalg.norm(sig)
+    tol = 1e-11 * np.linalg.norm(Uo - U0) + 1e-15 * sdt + 1e-14 * np.linalg.norm(Uo)
+    err = np.linalg.norm(Ug - Uo)
+    print(f"  dt={dt:.4g} steps={n} err={err:.3e} tol={tol:.3e} rel={err / np.linalg.norm(Uo - U0):.3e} "
+          f"err/(n dt sigma)={err / sdt:.3e}")
+    assert np.all(np.isfinite(Ug)) and err <= tol
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_explicit_steps_parity(case):
+    """Three SSP RK(4,3) steps against the oracle's."""
+    d = _case_cfg(case)
+    print(f"case explicit {case}", flush=True)
+    p, o = pair(d)
+    U0 = rand_state(o, 21, 1e-3)
+    dt, n = _cfl_dt(d), 3
+    Ug = to_dev(U0)
+    p.explicit_steps(Ug, dt, n)
+    _explicit_check(d, o, U0, to_np(Ug), o.explicit_steps(U0, dt, n), dt, n)
+
+
+def test_explicit_steps_rest_and_bubble():
+    """The rest state stays 0 bitwise (Euler, well balanced); a bubble run keeps the rho
+    and rho-theta mass to round-off; 0 steps leave U alone; a batched problem, a negative
+    step count and a non-finite dt are rejected."""
+    d, pert, _ = W.bubble_small()
+    d = dict(d, k=2)
+    p, o = pair(d)
+    U = p.dg_zeros()
+    p.explicit_steps(U, _cfl_dt(d), 4)
+    assert torch.count_nonzero(U).item() == 0
+    U0 = p.initial_state(pert)
+    U = U0.clone()
+    p.explicit_steps(U, _cfl_dt(d), 0)
+    assert torch.equal(U, U0)
+    dt, n = _cfl_dt(d), 5
+    p.explicit_steps(U, dt, n)
+    Uo = o.explicit_steps(to_np(U0), dt, n)
+    Ug = to_np(U)
+    _explicit_check(d, o, to_np(U0), Ug, Uo, dt, n)
+    # mass: the face fluxes cancel between neighbours up to rounding of the flux sums
+    # (scale sigma, summed over the 4n stages of size dt/2) and of the updates (scale m |U|)
+    m = dg_mass(d)
+    a, b = to_np(U0).reshape(4, -1), Ug.reshape(4, -1)
+    sig = o.residual(to_np(U0), 3).reshape(4, -1)
+    for c in (0, 3):
+        scale = (m * (np.abs(a[c]) + np.abs(b[c]))).sum() + 2 * n * dt * sig[c].sum()
+        print(f"  mass drift c={c}: {abs((m * (b[c] - a[c])).sum()):.3e} of scale {scale:.3e}")
+        assert abs((m * (b[c] - a[c])).sum()) <= 1e-14 * scale
+    for bad in ((dt, -1), (float("nan"), 1), (float("inf"), 1)):
+        with pytest.raises(jfmg.JfmgError):
+            p.explicit_steps(U, *bad)
+    pb = jfmg.Problem(dict(d, batch=2), device=DEV)
+    with pytest.raises(jfmg.JfmgError):
+        pb.explicit_steps(torch.zeros(2 * o.ndof, dtype=torch.float64, device=DEV), dt, 1)
+
+
 def test_failure_leaves_state_unchanged():
     d, pert, _ = W.bubble_small()
     p, _ = pair(dict(d, newton_maxit=1, newton_rtol=1e-30))
