@@ -37,7 +37,8 @@ class OrcCfg(C.Structure):
         "x0", "x1", "z0", "z1", "g", "gamma", "R", "p0", "theta0", "N", "u_mean",
         "mu", "c_ip")] + [("rk_alpha", C.c_double * 4)] + [(n, C.c_double) for n in (
         "pseudo_cfl", "newton_rtol", "ew_gamma", "ew_alpha", "ew_eta0", "ew_eta_max",
-        "dt", "newton_stall")]
+        "dt", "newton_stall")] + [("nu_pre_dg", C.c_int), ("nu_post_dg", C.c_int),
+                                  ("pseudo_cfl_dg", C.c_double)]
 
 
 class OrcPert(C.Structure):
@@ -92,6 +93,8 @@ def lib():
         L.orc_fv_level_state.argtypes = [C.c_void_p, C.c_int, dp]
         L.orc_fv_dtau.restype = C.c_double
         L.orc_fv_dtau.argtypes = [C.c_void_p, C.c_int]
+        L.orc_dg_dtau.restype = C.c_double
+        L.orc_dg_dtau.argtypes = [C.c_void_p]
         L.orc_fv_matvec.argtypes = [C.c_void_p, C.c_int, dp, dp]
         L.orc_jvp.argtypes = [C.c_void_p, dp, dp]
         L.orc_mg_fv.argtypes = [C.c_void_p, dp, dp]
@@ -142,8 +145,6 @@ def proj_tables(k: int):
 def make_cfg(d: dict) -> OrcCfg:
     c = OrcCfg()
     key = parse_mg_key(d.get("mg_key", "mg002222V"))
-    if key["a"] or key["b"]:
-        raise ValueError("DG-level smoothing counts a, b are not supported")
     for name in ("nx", "nz", "k"):
         setattr(c, name, int(d[name]))
     c.physics = int(d.get("physics", 0))
@@ -154,6 +155,8 @@ def make_cfg(d: dict) -> OrcCfg:
     c.mg_levels = int(d.get("mg_levels", 3))
     c.nu_pre_fine, c.nu_post_fine, c.nu_pre, c.nu_post = key["c"], key["d"], key["e"], key["f"]
     c.cycle = key["cycle"]
+    c.nu_pre_dg, c.nu_post_dg = key["a"], key["b"]
+    c.pseudo_cfl_dg = float(d.get("pseudo_cfl_dg", 1.0))
     c.rk_stages = int(d.get("rk_stages", 3))
     c.fd_eps_mode = int(d.get("fd_eps_mode", 1))
     c.gmres_m = int(d.get("gmres_m", 30))
@@ -296,6 +299,10 @@ class Oracle:
 
     def fv_dtau(self, level):
         return self.L.orc_fv_dtau(self.h, level)
+
+    def dg_dtau(self):
+        """Pseudo time step of the DG-level smoother (key counts a, b)."""
+        return self.L.orc_dg_dtau(self.h)
 
     def fv_matvec(self, level, x):
         x = np.ascontiguousarray(x, dtype=np.float64)

@@ -41,6 +41,7 @@ struct orc_ctx {
     double* ulev[MAXLEV];       /* FV linearization states u_l (perturbation) */
     double* flev[MAXLEV];       /* f_low(u_l) */
     double utot[MAXLEV], lam[MAXLEV], dtau[MAXLEV];
+    double dtau_dg;             /* pseudo time step of the DG-level smoother */
     int* mv_count;              /* counts FV matvecs per level (stats) */
     int mv_local[MAXLEV];
     int lh_count, jvp_count;
@@ -901,6 +902,16 @@ int orc_linearize(orc_ctx* X, const double* U, double alpha_dt)
         orc_fv_residual(X, l, X->ulev[l], X->flev[l]);
         fv_level_stats(X, l);
     }
+    /* DG-level pseudo time step: the level formula with the element widths divided
+       by 2k+1 (the explicit DG step scale) and the wave speed of the finest FV level */
+    {
+        const orc_cfg* c = &X->c;
+        double hx = (c->x1 - c->x0) / c->nx / (2.0 * c->k + 1.0);
+        double hz = (c->z1 - c->z0) / c->nz / (2.0 * c->k + 1.0);
+        X->dtau_dg = c->pseudo_cfl_dg /
+                     (1.0 + X->adt * (X->lam[0] * (1.0 / hx + 1.0 / hz) +
+                                      2.0 * c->mu * (1.0 / (hx * hx) + 1.0 / (hz * hz))));
+    }
     X->have_lin = 1;
     if (!isfinite(X->utot_dg)) return ORC_ENONFINITE;
     return ORC_OK;
@@ -912,6 +923,8 @@ void orc_fv_level_state(const orc_ctx* X, int l, double* u)
 }
 
 double orc_fv_dtau(const orc_ctx* X, int l) { return X->dtau[l]; }
+
+double orc_dg_dtau(const orc_ctx* X) { return X->dtau_dg; }
 
 /* FV Jacobian-free matvec g'_l(u) x = x - (alpha dt / eps)(f_low(u + eps x) - f_low(u)),
    eps = sqrt(eps_mach) ||u + Ubar||_2 / ||x||_2; x = 0 gives 0. */
@@ -1023,10 +1036,9 @@ void orc_mg_fv(orc_ctx* X, const double* b, double* x)
     mg_cycle(X, 0, x, b, &xzero);
 }
 
-/* Q^-1 r = T^-1 q^-1 T r (eq. preconditioner), q^-1 = one MG cycle from x = 0 */
-void orc_mg_apply(orc_ctx* X, const double* r, double* z)
+/* T^-1 q^-1 T r (eq. preconditioner), q^-1 = one MG cycle from x = 0 */
+static void coarse_correction(orc_ctx* X, const double* r, double* z)
 {
-    if (!X->c.precond) { memcpy(z, r, sizeof(double) * X->ndof); return; }
     long n = 4L * X->nxl[0] * X->nzl[0];
     double* b = (double*)malloc(sizeof(double) * n);
     double* x = (double*)malloc(sizeof(double) * n);
@@ -1035,6 +1047,62 @@ void orc_mg_apply(orc_ctx* X, const double* r, double* z)
     orc_transfer_Tinv(X, x, z);
     free(b);
     free(x);
+}
+
+/* Pseudo-time smoothing on the DG data (Sec. "Smoother / Pseudo time iteration":
+   the FV smoother's iteration applied to G'(U) z = r before the transfer to the
+   FV grid or after the reconstruction): nu sweeps of
+   z_j = z_0 + alpha_j dtau_dg (r - G' z_{j-1}), the zero flag skipping G' 0. */
+static void smooth_dg(orc_ctx* X, double* z, const double* r, int nu, int* zzero)
+{
+    long n = X->ndof;
+    double* z0 = (double*)malloc(sizeof(double) * n);
+    double* zp = (double*)malloc(sizeof(double) * n);
+    double* Az = (double*)malloc(sizeof(double) * n);
+    for (int sweep = 0; sweep < nu; ++sweep) {
+        memcpy(z0, z, sizeof(double) * n);
+        memcpy(zp, z, sizeof(double) * n);
+        for (int j = 0; j < X->c.rk_stages; ++j) {
+            if (j == 0 && *zzero) memset(Az, 0, sizeof(double) * n);
+            else orc_jvp(X, zp, Az);
+            double s = X->c.rk_alpha[j] * X->dtau_dg;
+            for (long i = 0; i < n; ++i) zp[i] = z0[i] + s * (r[i] - Az[i]);
+        }
+        memcpy(z, zp, sizeof(double) * n);
+        *zzero = 0;
+    }
+    free(z0);
+    free(zp);
+    free(Az);
+}
+
+/* Q^-1 r: with the DG smoothing counts a = b = 0 of the key, T^-1 q^-1 T r
+   (eq. preconditioner); otherwise the DG data are the finest level of the cycle:
+   a DG sweeps from z = 0, the coarse correction z += T^-1 q^-1 T (r - G' z),
+   b DG sweeps. */
+void orc_mg_apply(orc_ctx* X, const double* r, double* z)
+{
+    if (!X->c.precond) { memcpy(z, r, sizeof(double) * X->ndof); return; }
+    int a = X->c.nu_pre_dg, b = X->c.nu_post_dg;
+    if (a == 0 && b == 0) { coarse_correction(X, r, z); return; }
+    long n = X->ndof;
+    double* d = (double*)malloc(sizeof(double) * n);
+    double* cc = (double*)malloc(sizeof(double) * n);
+    memset(z, 0, sizeof(double) * n);
+    int zzero = 1;
+    smooth_dg(X, z, r, a, &zzero);
+    if (zzero) {
+        coarse_correction(X, r, z);
+    } else {
+        orc_jvp(X, z, d);
+        for (long i = 0; i < n; ++i) d[i] = r[i] - d[i];
+        coarse_correction(X, d, cc);
+        for (long i = 0; i < n; ++i) z[i] += cc[i];
+    }
+    zzero = 0;
+    smooth_dg(X, z, r, b, &zzero);
+    free(d);
+    free(cc);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -43,6 +43,8 @@ typedef struct {
     double newton_rtol, ew_gamma, ew_alpha, ew_eta0, ew_eta_max;
     double dt;
     double newton_stall; /* > 0: also stop at the rounding floor of G (see orc_newton_stage) */
+    int nu_pre_dg, nu_post_dg; /* key mg a b c d e f G: a b, pseudo-time sweeps on the DG data */
+    double pseudo_cfl_dg;      /* c* of the DG-level pseudo time step                      */
 } orc_cfg;
 
 typedef struct {
@@ -93,6 +95,7 @@ void orc_subgrid_map(const orc_ctx* X, int* fv_to_dg);
 int  orc_linearize(orc_ctx* X, const double* U, double alpha_dt);
 void orc_fv_level_state(const orc_ctx* X, int level, double* u);
 double orc_fv_dtau(const orc_ctx* X, int level);
+double orc_dg_dtau(const orc_ctx* X);
 void orc_fv_matvec(orc_ctx* X, int level, const double* x, double* out);
 void orc_jvp(orc_ctx* X, const double* y, double* out);
 void orc_mg_fv(orc_ctx* X, const double* b, double* x);

@@ -368,6 +368,111 @@ def test_fgmres_matches_dense_solve(orc, precond):
     assert np.linalg.norm(x - ref) <= 1e-9 * np.linalg.norm(ref)
 
 
+# --------------------------------------------------------------------------
+# DG-level pseudo-time smoothing (key counts a, b)
+# --------------------------------------------------------------------------
+
+def _dg_smooth_setup(orc, key, s):
+    d = W.small(nx=4, nz=4, k=1, mg_levels=2, physics=1, mu=75.0, mg_key=key, rk_stages=s)
+    o = orc.Oracle(d)
+    o0 = orc.Oracle(dict(d, mg_key="mg00" + key[4:]))
+    U = W.random_state(o.ndof, 80, [1e-3, 0.1, 0.1, 0.3])
+    adt = 2.0
+    A = _assembled_stage_jacobian(o, U, adt)
+    o.linearize(U, adt)
+    o0.linearize(U, adt)
+    r = W.random_state(o.ndof, 81, [1e-3, 1.0, 1.0, 1.0])
+    return o, o0, A, r
+
+
+# The oracle's FD product and the central-difference Jacobian of G agree to ~1e-6..1e-5
+# relative on these states (worst on the rho and rho w components), and a sweep chains up
+# to s of them: measured 7e-7 (s = 1) and 2e-6 (s = 3) for the whole preconditioner;
+# tolerance 2e-5.  The plausible mistakes checked below move the result by more than 1e-2.
+DG_SMOOTH_TOL = 2e-5
+
+
+def _taylor_sweep(A, dt, s, res):
+    """One s-stage low-storage sweep from 0 on A w = res: dt sum_{m<s} (-dt A)^m/(m+1)! res."""
+    term, w, fact = res.copy(), np.zeros_like(res), 1.0
+    for m in range(s):
+        fact *= (m + 1)
+        w += dt * term / fact
+        term = -dt * (A @ term)
+    return w
+
+
+@pytest.mark.parametrize("s", [1, 3])
+def test_dg_pre_smoothing_then_coarse_correction(orc, s):
+    """Key a = 1: one DG sweep from z = 0 is the Taylor polynomial of the pseudo-time
+    iteration on G' (assembled from central differences of G), followed by the coarse
+    correction z += T^-1 q^-1 T (r - G' z) of the a = b = 0 preconditioner."""
+    o, o0, A, r = _dg_smooth_setup(orc, "mg102222V", s)
+    zp = _taylor_sweep(A, o.dg_dtau(), s, r)
+    exp = zp + o0.mg_apply(r - A @ zp)
+    got = o.mg_apply(r)
+    err = np.linalg.norm(got - exp) / np.linalg.norm(exp)
+    # plausible mistakes: the correction of r instead of the defect; the smoother's sign
+    no_defect = np.linalg.norm(got - (zp + o0.mg_apply(r))) / np.linalg.norm(exp)
+    zm = _taylor_sweep(-A, o.dg_dtau(), s, r)
+    sign = np.linalg.norm(got - (zm + o0.mg_apply(r - A @ zm))) / np.linalg.norm(exp)
+    print(f"s={s}: err {err:.2e}, no-defect {no_defect:.2e}, sign {sign:.2e}")
+    assert err <= DG_SMOOTH_TOL and no_defect > 1e-2 and (s == 1 or sign > 1e-2)
+
+
+@pytest.mark.parametrize("s", [1, 2])
+def test_dg_post_smoothing(orc, s):
+    """Key b = 1: z = c + (sweep from 0 on the residual r - G' c), c the a = b = 0 result;
+    b = 2 repeats the sweep from the new z."""
+    o, o0, A, r = _dg_smooth_setup(orc, "mg012222V", s)
+    dt = o.dg_dtau()
+    c = o0.mg_apply(r)
+    z1 = c + _taylor_sweep(A, dt, s, r - A @ c)
+    got = o.mg_apply(r)
+    assert np.linalg.norm(got - z1) <= DG_SMOOTH_TOL * np.linalg.norm(z1)
+    assert np.linalg.norm(got - c) > 1e-2 * np.linalg.norm(z1)      # the sweep does something
+    o2, _, _, _ = _dg_smooth_setup(orc, "mg022222V", s)
+    z2 = z1 + _taylor_sweep(A, dt, s, r - A @ z1)
+    assert np.linalg.norm(o2.mg_apply(r) - z2) <= DG_SMOOTH_TOL * np.linalg.norm(z2)
+    assert np.linalg.norm(z2 - z1) > 1e-2 * np.linalg.norm(z2)
+
+
+def test_dg_pseudo_time_step_formula(orc):
+    """dtau_dg = c*/(1 + adt (lam_0 (1/hx + 1/hz) + 2 mu (1/hx^2 + 1/hz^2))) with the element
+    widths over 2k+1 and the wave speed of the finest FV level (rest state: lam = max c)."""
+    for k in (1, 2):
+        d = W.small(nx=4, nz=4, k=k, mg_levels=2, physics=1, mu=75.0, mg_key="mg112222V",
+                    pseudo_cfl_dg=0.7)
+        o = orc.Oracle(d)
+        o.linearize(np.zeros(o.ndof), 0.3)
+        nx, nz = o.fv_dims(0)
+        hzf = 1000.0 / nz
+        lam = 0.0
+        for J in range(nz):
+            Ub, _ = o.background((J + 0.5) * hzf)
+            p = 1e5 * (287.0 * Ub[3] / 1e5) ** 1.4
+            lam = max(lam, np.sqrt(1.4 * p / Ub[0]))
+        h = 1000.0 / 4 / (2 * k + 1)
+        exp = 0.7 / (1 + 0.3 * (lam * 2 / h + 2 * 75.0 * 2 / h**2))
+        assert o.dg_dtau() == pytest.approx(exp, rel=1e-13)
+
+
+def test_dg_smoothing_step_converges_to_the_same_solution(orc):
+    """An implicit step preconditioned with DG smoothing solves the same G = 0: both
+    converged results lie within the Newton tolerance of each other."""
+    d, pert, _ = W.bubble_small()
+    res = {}
+    for key in ("mg002222V", "mg112222V"):
+        o = orc.Oracle(dict(d, mg_key=key, newton_rtol=1e-9))
+        U0 = o.initial_state(pert)
+        rc, U1, st = o.implicit_step(U0)
+        assert rc == 0
+        res[key] = (U0, U1, st["gmres_its"], st["jvps"])
+    (U0, a, ia, ja), (_, b, ib, jb) = res["mg002222V"], res["mg112222V"]
+    print(f"GMRES its / JVPs: mg002222V {ia} / {ja}, mg112222V {ib} / {jb}")
+    assert np.linalg.norm(a - b) <= 20 * 1e-9 * np.linalg.norm(a - U0) + 1e-12 * np.linalg.norm(a)
+
+
 def test_preconditioner_reduces_iterations(orc):
     """Preconditioned GMRES needs fewer iterations than unpreconditioned (numerical experiments)."""
     d, pert, _ = W.bubble_small()
