@@ -58,7 +58,7 @@ typedef struct {
     int mass_fix;             /* 1: mass-fixed transfers (eq. transfer-mass-fix)        */
     int mg_precision;         /* 64 or 32: precision of the whole multigrid             */
     int precond;              /* 1 multigrid Q^-1 = T^-1 q^-1 T, 0 identity             */
-    char mg_key[16];          /* "mg a b c d e f G", e.g. "mg002222V"; a = b = 0        */
+    char mg_key[16];          /* "mg a b c d e f G", e.g. "mg002222V" (one digit each)  */
     double x0, x1, z0, z1;    /* domain                                                 */
     double g, gamma, R, p0;   /* gravity, adiabatic index, gas constant, reference p    */
     double theta0, N, u_mean; /* background theta (surface), Brunt-Vaisala N, mean wind */
@@ -76,6 +76,10 @@ typedef struct {
                                  interpolation at the subcell centres (with mass_fix),
                                  1 the L2 projection onto the subcells (subcell averages;
                                  conserves mass, mass_fix does not apply)              */
+    double pseudo_cfl_dg;     /* c* of the DG-level smoother's pseudo time step (key a, b):
+                                 dtau_dg = c* / (1 + alpha dt (lam_0 (1/hx + 1/hz)
+                                 + 2 mu (1/hx^2 + 1/hz^2))), hx, hz = element widths over
+                                 2k+1, lam_0 = max |v| + c of the finest FV level      */
 } jfmg_config;
 
 typedef struct {
@@ -145,7 +149,13 @@ jfmg_status jfmg_linearize(jfmg_problem* p, const double* U, double alpha_dt);
 jfmg_status jfmg_jvp(jfmg_problem* p, const double* y, double* out);
 
 /* z = Q^-1 r = T^-1 MG(0, T r; u_L) (eq. preconditioner); identity when
-   precond = 0.  ESTATE without jfmg_linearize. */
+   precond = 0.  With the DG smoothing counts a, b of mg_key nonzero the DG data
+   are the finest level of the cycle (Sec. "Smoother / Pseudo time iteration":
+   pseudo-time smoothing on the DG data before the transfer and after the
+   reconstruction): a sweeps of the s-stage smoother
+   z_j = z_0 + alpha_j dtau_dg (r - G' z_{j-1}) from z = 0, the coarse
+   correction z += T^-1 MG(0, T(r - G' z)), then b sweeps.  Workspace vectors of
+   the problem hold the intermediate vectors.  ESTATE without jfmg_linearize. */
 jfmg_status jfmg_mg_apply(jfmg_problem* p, const double* r, double* z);
 
 /* ---- lock-step batches (config.batch = B > 1) ----
@@ -192,6 +202,9 @@ jfmg_status jfmg_prolong(jfmg_problem* p, int coarse_level, const void* coarse, 
 jfmg_status jfmg_fv_level_state(jfmg_problem* p, int level, void* u);
 /* Pseudo time step of `level` (host double; synchronizes). */
 jfmg_status jfmg_fv_dtau(jfmg_problem* p, int level, double* dtau);
+/* Pseudo time step of the DG-level smoother (see pseudo_cfl_dg; host double;
+   synchronizes).  ESTATE without jfmg_linearize; EINVAL when a = b = 0. */
+jfmg_status jfmg_dg_dtau(jfmg_problem* p, double* dtau);
 /* out = g'_l(u_l) x = x - (alpha dt/eps)(f_low(u_l + eps x) - f_low(u_l)),
    eps = sqrt(eps_p) ||u_l + Ubar|| / ||x||. */
 jfmg_status jfmg_fv_matvec(jfmg_problem* p, int level, const void* x, void* out);
@@ -260,7 +273,8 @@ typedef enum {
     JFMG_K_MULTIDOT = 9,      /* Arnoldi <w, v_i>                                   */
     JFMG_K_UPDATE = 10,       /* Arnoldi w -= V h                                   */
     JFMG_K_FV_STAGE_SMALL = 11, /* the same on narrower levels (small-tile kernel)    */
-    JFMG_K_NCLASS = 12
+    JFMG_K_DG_SMOOTH = 12,    /* DG-level smoother stage combination (key a, b)     */
+    JFMG_K_NCLASS = 13
 } jfmg_kernel_class;
 jfmg_status jfmg_profile_enable(jfmg_problem* p, unsigned class_mask);
 /* ms, launches and bytes are host arrays of JFMG_K_NCLASS entries. */

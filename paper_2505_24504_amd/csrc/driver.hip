@@ -283,6 +283,10 @@ enum {
     S_R = 5,        // restart residual norm^2
     S_TMP = 6,
     S_W1 = 8,       // ||w||^2 after the first Gram-Schmidt pass
+    S_DGZ = 9,      // ||z||^2 and ||z_j||^2 of the DG-level smoother (key a, b)
+    S_DGX = 10,
+    S_DGC = 11,     // ||T^-1 x||^2 of a coarse correction that is added to z
+    S_DTDG = 12,    // pseudo time step of the DG-level smoother
     S_LEV = 16,     // + 4*level: LV_* slots
     S_H1 = 128,     // 65 entries: h of the first pass, then ||w||^2 before it
     S_H2 = 193,     // 65 entries
@@ -484,7 +488,7 @@ jfmg_status validate(const jfmg_config& c, Key& key, std::string& msg)
     std::memcpy(ks, c.mg_key, 16);
     ks[15] = 0;
     if (!parse_key(ks, key)) { msg = "bad multigrid key (expected mgabcdefV or mgabcdefW)"; return JFMG_EINVAL; }
-    if (key.a || key.b) { msg = "DG-level smoothing counts a, b must be 0"; return JFMG_EINVAL; }
+    if ((key.a || key.b) && !(c.pseudo_cfl_dg > 0)) { msg = "pseudo_cfl_dg must be > 0"; return JFMG_EINVAL; }
     int nxl = (c.k + 1) * c.nx, nzl = (c.k + 1) * c.nz;
     for (int l = 1; l < c.mg_levels; ++l) {
         if ((nxl & 1) || (nzl & 1)) { msg = "an FV level dimension is odd before the coarsest level"; return JFMG_EINVAL; }
@@ -616,6 +620,13 @@ template <typename T> jfmg_status linearize_t(jfmg_problem* p, const double* U, 
         ProfScope ps(p, JFMG_K_FV_LINEARIZE, 2.0 * 4.0 * p->lev[l].nc * sizeof(T));
         FvLaunch<T>::lin_level(fv_args<T>(p, l), (const T*)p->lev[l].u, (T*)p->lev[l].F0, Red{p->partials, nullptr},
                                p->scal + S_LEV + 4 * l, adt, p->cfg.pseudo_cfl, st, p->mb);
+    }
+    if (p->key.a || p->key.b) {
+        // DG-level pseudo time step: the level formula with the element widths over
+        // 2k+1 (the explicit DG step scale) and the finest FV level's wave speed
+        const double kk = 2.0 * p->cfg.k + 1.0;
+        launch_dg_dtau(p->scal + S_LEV + LV_LAM, p->scal + S_DTDG, p->A.dx / kk, p->A.dz / kk, p->cfg.mu, adt,
+                       p->cfg.pseudo_cfl_dg, st, p->mb);
     }
     p->have_lin = 1;
     return check_launch(p);
@@ -769,6 +780,78 @@ template <typename T> jfmg_status mg_apply_t(jfmg_problem* p, double* r, double*
     return check_launch(p);
 }
 
+// out = G'(U_lin) y with ||y||^2 already in slot yslot
+void jvp_slot(jfmg_problem* p, const double* y, double* out, int yslot)
+{
+    ProfScope ps(p, JFMG_K_DG_JVP, 3.0 * p->N * 8);
+    launch_dg(p->cfg.k, p->cfg.physics == 1, 3, p->A, p->Ulin, y, nullptr, out, p->scal + yslot, p->scal + S_UTOT,
+              p->cfg.fd_eps_mode, p->adt, no_red(), p->st, p->mb);
+    p->jvp_count++;
+}
+
+// nu sweeps of the DG-level smoother on G'(U) z = r, z_j = z_0 + alpha_j dtau_dg (r - G' z_{j-1})
+// (G' 0 skipped while z is zero).  ||z||^2 is in S_DGZ on entry (z nonzero) and on exit,
+// except that the very last stage writes it into slot `last` instead.  The stages
+// alternate between z (the last stage of a sweep, in place over z_0) and tmp1; tmp2
+// holds the products.
+void dg_smooth(jfmg_problem* p, const Mg<double>& mg, double* z, const double* r, int nu, bool& zzero, int last)
+{
+    const int S = p->cfg.rk_stages;
+    double* xs = p->tmp1;
+    double* t = p->tmp2;
+    const double* dtau = p->scal + S_DTDG;
+    for (int sw = 0; sw < nu; ++sw) {
+        for (int j = 0; j < S; ++j) {
+            const bool lastst = j == S - 1;
+            double* out = lastst ? z : xs;
+            const double* prev = j == 0 ? z : xs;
+            const int slot = lastst ? (sw == nu - 1 ? last : S_DGZ) : S_DGX;
+            if (j == 0 && zzero) {   // reads r, writes z_1
+                ProfScope ps(p, JFMG_K_DG_SMOOTH, 2.0 * p->N * 8);
+                launch_dg_smooth(out, nullptr, r, nullptr, mg.alpha[j], dtau, p->N, red_at(p, slot), p->st, p->mb);
+            } else {                 // reads r, G' z_{j-1} and z_0 (when nonzero), writes z_j
+                jvp_slot(p, prev, t, j == 0 ? S_DGZ : S_DGX);
+                ProfScope ps(p, JFMG_K_DG_SMOOTH, (zzero ? 3.0 : 4.0) * p->N * 8);
+                launch_dg_smooth(out, zzero ? nullptr : z, r, t, mg.alpha[j], dtau, p->N, red_at(p, slot), p->st,
+                                 p->mb);
+            }
+        }
+        zzero = false;
+    }
+}
+
+// z = Q^-1 r with the DG data as the finest level of the cycle (key a, b > 0): a DG
+// sweeps from z = 0, z += T^-1 q^-1 T (r - G' z), b DG sweeps; ||z||^2 into zslot
+template <typename T> jfmg_status mg_apply_dg_t(jfmg_problem* p, double* r, double* z, int zslot, const double* rnrm2)
+{
+    const Key& k = p->key;
+    Mg<double> mg{p};
+    mg.init();
+    if (rnrm2) launch_scale(r, r, p->N, rnrm2, p->st, 1.0, p->mb);
+    bool zzero = true;
+    dg_smooth(p, mg, z, r, k.a, zzero, S_DGZ);
+    const int cslot = k.b ? S_DGZ : zslot;
+    jfmg_status s;
+    if (zzero) {
+        s = mg_apply_t<T>(p, r, z, cslot, nullptr);
+    } else {
+        // defect d = r - G' z in tmp2, correction into tmp1, z += it
+        jvp_slot(p, z, p->tmp2, S_DGZ);
+        {
+            ProfScope ps(p, JFMG_K_DG_SMOOTH, 3.0 * p->N * 8);
+            launch_dg_smooth(p->tmp2, nullptr, r, p->tmp2, 1.0, nullptr, p->N, Red{nullptr, nullptr}, p->st, p->mb);
+        }
+        s = mg_apply_t<T>(p, p->tmp2, p->tmp1, S_DGC, nullptr);
+        if (s) return s;
+        ProfScope ps(p, JFMG_K_DG_SMOOTH, 3.0 * p->N * 8);
+        launch_dg_smooth(z, z, p->tmp1, nullptr, 1.0, nullptr, p->N, red_at(p, cslot), p->st, p->mb);
+    }
+    if (s) return s;
+    zzero = false;
+    dg_smooth(p, mg, z, r, k.b, zzero, zslot);
+    return check_launch(p);
+}
+
 // z = Q^-1 r, ||z||^2 into slot zslot; with rnrm2 != nullptr r is first
 // normalized in place (r /= sqrt(rnrm2[0]), the Arnoldi v_j = w / ||w||)
 jfmg_status precond(jfmg_problem* p, double* r, double* z, int zslot, const double* rnrm2 = nullptr)
@@ -779,16 +862,9 @@ jfmg_status precond(jfmg_problem* p, double* r, double* z, int zslot, const doub
         launch_norm2(z, p->N, red_at(p, zslot), p->st, p->mb);
         return check_launch(p);
     }
+    if (p->key.a || p->key.b)
+        return p->prec == 32 ? mg_apply_dg_t<float>(p, r, z, zslot, rnrm2) : mg_apply_dg_t<double>(p, r, z, zslot, rnrm2);
     return p->prec == 32 ? mg_apply_t<float>(p, r, z, zslot, rnrm2) : mg_apply_t<double>(p, r, z, zslot, rnrm2);
-}
-
-// out = G'(U_lin) y with ||y||^2 already in slot yslot
-void jvp_slot(jfmg_problem* p, const double* y, double* out, int yslot)
-{
-    ProfScope ps(p, JFMG_K_DG_JVP, 3.0 * p->N * 8);
-    launch_dg(p->cfg.k, p->cfg.physics == 1, 3, p->A, p->Ulin, y, nullptr, out, p->scal + yslot, p->scal + S_UTOT,
-              p->cfg.fd_eps_mode, p->adt, no_red(), p->st, p->mb);
-    p->jvp_count++;
 }
 
 // G = U - adt f(U) - Ubar and its norm (host)
@@ -1193,6 +1269,7 @@ jfmg_status jfmg_config_default(jfmg_config* c)
     c->dt = 1.0; c->newton_rtol = 1e-8;
     c->ew_gamma = 0.1; c->ew_alpha = 1.0; c->ew_eta0 = 0.1; c->ew_eta_max = 0.9;
     c->pseudo_cfl = 1.0;
+    c->pseudo_cfl_dg = 1.0;
     return JFMG_OK;
 }
 
@@ -1604,6 +1681,15 @@ jfmg_status jfmg_fv_dtau(jfmg_problem* p, int level, double* dtau)
     if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step, jfmg_initial_state, jfmg_linearize and the tile calls");
     if (!p->have_lin) return fail(p, JFMG_ESTATE, "needs jfmg_linearize first");
     return read_scalars(p, S_LEV + 4 * level + LV_DTAU, 1, dtau);
+}
+
+jfmg_status jfmg_dg_dtau(jfmg_problem* p, double* dtau)
+{
+    if (!p || !dtau) return fail(p, JFMG_EINVAL, "bad argument");
+    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step, jfmg_initial_state, jfmg_linearize and the tile calls");
+    if (!p->key.a && !p->key.b) return fail(p, JFMG_EINVAL, "no DG-level smoothing in mg_key");
+    if (!p->have_lin) return fail(p, JFMG_ESTATE, "needs jfmg_linearize first");
+    return read_scalars(p, S_DTDG, 1, dtau);
 }
 
 jfmg_status jfmg_fv_matvec(jfmg_problem* p, int level, const void* x, void* out)

@@ -190,6 +190,14 @@ void launch_lincomb(double* out, const double* base, const double* Z, long ld, i
 // zero `bytes` (a multiple of 4) with a kernel (graph-capture safe, unlike a memset node)
 void launch_zero(void* ptr, size_t bytes, hipStream_t st, const Mb& mb = Mb{});
 template <typename T> void launch_fill_pattern(T* x, long n, hipStream_t st, const Mb& mb = Mb{});
+// DG-level smoother stage out = x0 + s (r - t), s = alpha dtau[0] (alpha when dtau is null),
+// x0 / t null meaning 0; out may alias x0 or t (elementwise); ||out||^2 into red.out
+// (when red.out is set)
+void launch_dg_smooth(double* out, const double* x0, const double* r, const double* t, double alpha,
+                      const double* dtau, long n, Red red, hipStream_t st, const Mb& mb = Mb{});
+// out[0] = cfl / (1 + adt (lam[0] (1/hx + 1/hz) + 2 mu (1/hx^2 + 1/hz^2)))
+void launch_dg_dtau(const double* lam, double* out, double hx, double hz, double mu, double adt, double cfl,
+                    hipStream_t st, const Mb& mb = Mb{});
 // out = a*x + b*y
 void launch_axpby(double* out, double a, const double* x, double b, const double* y, long n, hipStream_t st,
                   const Mb& mb = Mb{});

@@ -310,6 +310,55 @@ void launch_axpby(double* out, double a, const double* x, double b, const double
     axpby_kernel<<<dim3((unsigned)(blk < 4096 ? blk : 4096), 1, mb.n), dim3(256), 0, st>>>(out, a, x, b, y, n, mb.ms);
 }
 
+// Stage of the DG-level pseudo-time smoother; out may alias x0 or t (no restrict):
+// every element is read and written by the same thread.
+__global__ void __launch_bounds__(256)
+dg_smooth_kernel(double* out, const double* x0, const double* __restrict__ r, const double* t, double alpha,
+                 const double* __restrict__ dtau, long n, Red red, long ms)
+{
+    out = mbr(out, ms);
+    x0 = mbr(x0, ms);
+    r = mbr(r, ms);
+    t = mbr(t, ms);
+    dtau = mbr(dtau, ms);
+    red = mbr(red, ms);
+    const double s = dtau ? alpha * dtau[0] : alpha;
+    double a = 0.0;
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+        const double d = t ? r[i] - t[i] : r[i];
+        const double v = x0 ? x0[i] + s * d : s * d;
+        out[i] = v;
+        a += v * v;
+    }
+    if (red.partials) put_partial<256>(red, a);
+}
+
+void launch_dg_smooth(double* out, const double* x0, const double* r, const double* t, double alpha,
+                      const double* dtau, long n, Red red, hipStream_t st, const Mb& mb)
+{
+    long b = (n + 255) / 256;
+    const int nb = (int)(b < 1024 ? b : 1024);
+    if (!red.out) red.partials = nullptr;
+    timed_launch(dg_smooth_kernel, dim3(nb, 1, mb.n), dim3(256), st, out, x0, r, t, alpha, dtau, n, red, mb.ms);
+    if (red.out) launch_finalize(red.partials, nb, 1, red.out, st, Gate{}, mb);
+}
+
+__global__ void __launch_bounds__(64) dg_dtau_kernel(const double* __restrict__ lam, double* __restrict__ out,
+                                                     double hx, double hz, double mu, double adt, double cfl,
+                                                     long ms)
+{
+    lam = mbr(lam, ms);
+    out = mbr(out, ms);
+    if (threadIdx.x == 0)
+        out[0] = cfl / (1.0 + adt * (lam[0] * (1.0 / hx + 1.0 / hz) + 2.0 * mu * (1.0 / (hx * hx) + 1.0 / (hz * hz))));
+}
+
+void launch_dg_dtau(const double* lam, double* out, double hx, double hz, double mu, double adt, double cfl,
+                    hipStream_t st, const Mb& mb)
+{
+    dg_dtau_kernel<<<dim3(1, 1, mb.n), dim3(64), 0, st>>>(lam, out, hx, hz, mu, adt, cfl, mb.ms);
+}
+
 __global__ void __launch_bounds__(256) zero_kernel(unsigned* __restrict__ x, long n, long ms)
 {
     x = mbr(x, ms);

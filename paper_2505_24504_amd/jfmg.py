@@ -33,7 +33,7 @@ class Config(C.Structure):
         "x0", "x1", "z0", "z1", "g", "gamma", "R", "p0", "theta0", "N", "u_mean", "mu", "c_ip", "dt",
         "newton_rtol", "ew_gamma", "ew_alpha", "ew_eta0", "ew_eta_max")] + [
         ("rk_alpha", C.c_double * 4), ("pseudo_cfl", C.c_double), ("newton_stall", C.c_double),
-        ("batch", C.c_int), ("transfer", C.c_int)]
+        ("batch", C.c_int), ("transfer", C.c_int), ("pseudo_cfl_dg", C.c_double)]
 
 
 class Perturbation(C.Structure):
@@ -61,7 +61,7 @@ EXPORTS = [
     "jfmg_config_default", "jfmg_workspace_bytes", "jfmg_create_problem", "jfmg_destroy_problem",
     "jfmg_num_dofs", "jfmg_fv_size", "jfmg_initial_state", "jfmg_residual", "jfmg_stage_residual",
     "jfmg_linearize", "jfmg_jvp", "jfmg_mg_apply", "jfmg_implicit_step", "jfmg_explicit_steps", "jfmg_transfer",
-    "jfmg_restrict", "jfmg_prolong", "jfmg_fv_level_state", "jfmg_fv_dtau", "jfmg_fv_matvec",
+    "jfmg_restrict", "jfmg_prolong", "jfmg_fv_level_state", "jfmg_fv_dtau", "jfmg_dg_dtau", "jfmg_fv_matvec",
     "jfmg_mg_fv", "jfmg_subgrid_map", "jfmg_profile_enable", "jfmg_profile_read", "jfmg_last_error",
     "jfmg_batch_create", "jfmg_batch_destroy", "jfmg_batch_admit", "jfmg_batch_member", "jfmg_batch_run",
     "jfmg_batch_start", "jfmg_batch_stop", "jfmg_batch_wait_any", "jfmg_batch_poll", "jfmg_batch_retire",
@@ -73,7 +73,7 @@ TILES = ["64x4", "64x8", "16x4", "8x4", "32x4", "64x4_512"]
 
 KERNEL_CLASSES = ["dg_residual", "dg_jvp", "fv_stage", "fv_stage_zero", "fv_defect_restrict",
                   "fv_prolong_correct", "fv_linearize", "transfer_T", "transfer_Tinv", "multidot",
-                  "update", "fv_stage_small"]
+                  "update", "fv_stage_small", "dg_smooth"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -105,6 +105,7 @@ def load_library(path: str = LIB_PATH):
         "jfmg_prolong": (C.c_int, [vp, C.c_int, vp, vp]),
         "jfmg_fv_level_state": (C.c_int, [vp, C.c_int, vp]),
         "jfmg_fv_dtau": (C.c_int, [vp, C.c_int, dp]),
+        "jfmg_dg_dtau": (C.c_int, [vp, dp]),
         "jfmg_fv_matvec": (C.c_int, [vp, C.c_int, vp, vp]),
         "jfmg_mg_fv": (C.c_int, [vp, vp, vp]),
         "jfmg_subgrid_map": (C.c_int, [vp, vp]),
@@ -144,7 +145,8 @@ def make_config(d: dict) -> Config:
             "gmres_max_restarts", "fd_eps_mode", "mg_levels", "rk_stages", "mass_fix", "mg_precision",
             "precond", "batch", "transfer")
     dbls = ("x0", "x1", "z0", "z1", "g", "gamma", "R", "p0", "theta0", "N", "u_mean", "mu", "c_ip", "dt",
-            "newton_rtol", "ew_gamma", "ew_alpha", "ew_eta0", "ew_eta_max", "pseudo_cfl", "newton_stall")
+            "newton_rtol", "ew_gamma", "ew_alpha", "ew_eta0", "ew_eta_max", "pseudo_cfl", "newton_stall",
+            "pseudo_cfl_dg")
     for n in ints:
         if n in d:
             setattr(c, n, int(d[n]))
@@ -298,6 +300,11 @@ class Problem:
     def fv_dtau(self, level):
         v = C.c_double()
         self._check(self.L.jfmg_fv_dtau(self.h, level, C.byref(v)))
+        return v.value
+
+    def dg_dtau(self):
+        v = C.c_double()
+        self._check(self.L.jfmg_dg_dtau(self.h, C.byref(v)))
         return v.value
 
     def fv_matvec(self, level, x):

@@ -53,16 +53,18 @@ def test_struct_layout_matches_header(tmp_path):
 #include <stddef.h>
 #include "jfmg.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(jfmg_config), offsetof(jfmg_config, mg_key),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(jfmg_config), offsetof(jfmg_config, mg_key),
          offsetof(jfmg_config, x0), offsetof(jfmg_config, rk_alpha), offsetof(jfmg_config, newton_stall),
-         sizeof(jfmg_perturbation), sizeof(jfmg_stats), offsetof(jfmg_stats, g0_norm));
+         offsetof(jfmg_config, pseudo_cfl_dg), sizeof(jfmg_perturbation), sizeof(jfmg_stats),
+         offsetof(jfmg_stats, g0_norm));
   return 0; }
 ''')
     exe = tmp_path / "lay"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     vals = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     assert vals == [C.sizeof(jfmg.Config), jfmg.Config.mg_key.offset, jfmg.Config.x0.offset,
-                    jfmg.Config.rk_alpha.offset, jfmg.Config.newton_stall.offset, C.sizeof(jfmg.Perturbation),
+                    jfmg.Config.rk_alpha.offset, jfmg.Config.newton_stall.offset, jfmg.Config.pseudo_cfl_dg.offset,
+                    C.sizeof(jfmg.Perturbation),
                     C.sizeof(jfmg.Stats), jfmg.Stats.g0_norm.offset]
 
 
@@ -75,7 +77,7 @@ def test_workspace_sizes(lib):
 
 @pytest.mark.parametrize("bad,what", [
     ({"k": 0}, "k must"), ({"k": 4}, "k must"), ({"gmres_m": 65}, "gmres_m"),
-    ({"mg_levels": 9}, "mg_levels"), ({"mg_key": "mg102222V"}, "a, b"), ({"mg_key": "mgxx"}, "key"),
+    ({"mg_levels": 9}, "mg_levels"), ({"mg_key": "mg102222V", "pseudo_cfl_dg": 0.0}, "pseudo_cfl_dg"), ({"mg_key": "mgxx"}, "key"),
     ({"nx": 3, "mg_levels": 3}, "odd"), ({"mg_precision": 16}, "precision"), ({"rk_stages": 5}, "rk_stages"),
     ({"background": 1, "N": 0.0}, "N > 0"), ({"dt": 0.0}, "constants"), ({"transfer": 2}, "transfer"),
 ])

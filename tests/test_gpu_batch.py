@@ -113,13 +113,16 @@ def test_fp32_mg_step_vs_fp64_oracle_inertia_gravity():
     _fp32_vs_oracle(d, pert)
 
 
-@pytest.mark.parametrize("prec", [32, 64])
-def test_lockstep_members_equal_alone(prec):
+@pytest.mark.parametrize("prec,key", [(32, None), (64, None), (32, "mg112222V")])
+def test_lockstep_members_equal_alone(prec, key):
     """A lock-step batch (one problem, all members in every launch) gives each
-    member bitwise the result of the same member as a single problem."""
+    member bitwise the result of the same member as a single problem (also with
+    DG-level smoothing in the preconditioner)."""
     ens = [m for m in W.ensemble(seed=4, members=64) if m[0]["nx"] == 32][:3]
     assert len(ens) == 3
     d = dict(ens[0][0], mg_precision=prec)
+    if key:
+        d["mg_key"] = key
     alone = [_alone(d, pert, 2) for _, pert, _ in ens]
     pb = jfmg.Problem(dict(d, batch=len(ens)), device=DEV)
     single = jfmg.Problem(d, device=DEV)

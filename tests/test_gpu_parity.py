@@ -371,6 +371,37 @@ def test_mg_apply_parity(case, precond, transfer):
     assert err <= (1e-6 if precond else 0.0)
 
 
+# DG-level smoothing (key a, b): a JVP per smoother stage, so the FD products' round-off
+# enters like in the FV matvecs; same 1e-6 bound as the preconditioner above
+DG_KEYS = ["mg102222V", "mg012222V", "mg112222V", "mg211111W"]
+
+
+@pytest.mark.parametrize("case", [(1, 0, 0, 0, 0.0), (3, 1, 0, 0, 0.0), (2, 0, 1, 1, 20.0)])
+@pytest.mark.parametrize("key", DG_KEYS)
+def test_mg_apply_dg_smoothing_parity(case, key):
+    d = dict(_case_cfg(case, nx=16, nz=8), mg_levels=3, mg_key=key, pseudo_cfl_dg=0.8)
+    p, o = pair(d)
+    U = rand_state(o, 61)
+    p.linearize(to_dev(U), 0.8)
+    o.linearize(U, 0.8)
+    dg, do = p.dg_dtau(), o.dg_dtau()
+    assert abs(dg - do) <= 1e-13 * do
+    r = rand_state(o, 62, 1.0)
+    zg = to_np(p.mg_apply(to_dev(r)))
+    zo = o.mg_apply(r)
+    err = np.linalg.norm(zg - zo) / np.linalg.norm(zo)
+    print(f"case mg_apply {case} {key}: dtau_dg {dg:.6e} rel err {err:.3e}")
+    assert err <= 1e-6
+
+
+def test_dg_dtau_needs_dg_smoothing():
+    d = _case_cfg((1, 0, 0, 0, 0.0))
+    p, _ = pair(d)
+    p.linearize(p.dg_zeros(), 0.5)
+    with pytest.raises(jfmg.JfmgError):
+        p.dg_dtau()
+
+
 # --------------------------------------------------------------------------
 # whole implicit steps
 # --------------------------------------------------------------------------
@@ -394,6 +425,21 @@ def test_implicit_euler_step_parity_bubble(transfer):
     d, pert, _ = W.bubble_small()
     rtol = 1e-9          # the FP64 round-off floor of ||G||/||G^0|| is ~4e-10 here
     d = dict(d, newton_rtol=rtol, transfer=transfer)
+    p, o = pair(d)
+    U0 = o.initial_state(pert)
+    rc, Uo, st_o = o.implicit_step(U0)
+    assert rc == 0
+    U = to_dev(U0)
+    st = p.implicit_step(U)
+    _step_check(d, Uo, U0, to_np(U), rtol, st, st_o)
+
+
+@pytest.mark.parametrize("key", ["mg112222V", "mg011111V"])
+def test_implicit_step_dg_smoothing_parity(key):
+    """Steps preconditioned with DG-level smoothing against the oracle's (16x16 bubble, k = 1)."""
+    d, pert, _ = W.bubble_small()
+    rtol = 1e-9
+    d = dict(d, newton_rtol=rtol, mg_key=key)
     p, o = pair(d)
     U0 = o.initial_state(pert)
     rc, Uo, st_o = o.implicit_step(U0)
