@@ -693,11 +693,12 @@ template <typename T> struct Mg {
                 }
                 const T* x0 = s.xzero[l] ? nullptr : (const T*)L.buf[i0];   // null: x^(0) = 0
                 const double vb = 4.0 * L.nc * sizeof(T);
-                // algorithmic bytes: reads u, F0, x^(j-1), x^(0), b, writes x^(j) (no x^(0) when it is 0);
-                // the zero-start stage reads b and writes x^(1)
+                // algorithmic bytes: reads u, F0, x^(j-1), x^(0), b, writes x^(j) (x^(0) not when it is 0
+                // or when it is x^(j-1), the first stage of a sweep); the zero-start stage reads b and
+                // writes x^(1)
                 const int cls = zero ? JFMG_K_FV_STAGE_ZERO
                                      : (fv_wide_tile(L.tile) ? JFMG_K_FV_STAGE : JFMG_K_FV_STAGE_SMALL);
-                ProfScope ps(p, cls, zero ? 2 * vb : (x0 ? 6 : 5) * vb);
+                ProfScope ps(p, cls, zero ? 2 * vb : (x0 && prev != i0 ? 6 : 5) * vb);
                 p->xcnt[l][out] = FvLaunch<T>::stage(
                     A, (const T*)L.u, (const T*)L.F0, (const T*)L.buf[prev], x0, (const T*)L.b, (T*)L.buf[out],
                     fvpart(p, l, prev), p->xcnt[l][prev], p->scal + S_LEV + 4 * l, alpha[j], p->adt, zero,
@@ -722,11 +723,14 @@ template <typename T> struct Mg {
             // reads u, F0, x, b and writes the quarter-size coarse defect (x = 0: reads b only),
             // and with x != 0 the coarse level's first stage from zero as well
             const ZeroStage<T> z0 = s.xzero[l] ? ZeroStage<T>{} : zero_stage(l + 1, k.e);
-            ProfScope ps(p, JFMG_K_FV_DEFECT, (s.xzero[l] ? 1.25 : (z0.x1 ? 4.5 : 4.25)) * 4.0 * L.nc * sizeof(T));
-            const int nb = FvLaunch<T>::defect_restrict(A, (const T*)L.u, (const T*)L.F0, (const T*)L.buf[s.xi[l]],
-                                                        (const T*)L.b, (T*)C.b, fvpart(p, l, s.xi[l]),
-                                                        p->xcnt[l][s.xi[l]], p->scal + S_LEV + 4 * l, p->adt,
-                                                        s.xzero[l] ? 1 : 0, p->st, p->mb, z0);
+            int nb;
+            {   // the scope ends before the coarse cycle, whose own scopes would reset the timer
+                ProfScope ps(p, JFMG_K_FV_DEFECT, (s.xzero[l] ? 1.25 : (z0.x1 ? 4.5 : 4.25)) * 4.0 * L.nc * sizeof(T));
+                nb = FvLaunch<T>::defect_restrict(A, (const T*)L.u, (const T*)L.F0, (const T*)L.buf[s.xi[l]],
+                                                  (const T*)L.b, (T*)C.b, fvpart(p, l, s.xi[l]),
+                                                  p->xcnt[l][s.xi[l]], p->scal + S_LEV + 4 * l, p->adt,
+                                                  s.xzero[l] ? 1 : 0, p->st, p->mb, z0);
+            }
             if (!s.xzero[l]) p->mv_count[l]++;
             s.xzero[l + 1] = true;
             s.xi[l + 1] = 0;

@@ -106,7 +106,8 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
             for (int c = 0; c < 4; ++c) {
                 if constexpr (PERT) { own_x[c] = xp[c * nc + q]; own_f0[c] = F0[c * nc + q]; }
                 if constexpr (MODE == FVM_STAGE || MODE == FVM_DEFECT) own_b[c] = b[c * nc + q];
-                if constexpr (MODE == FVM_STAGE) own_x0[c] = x0 ? x0[c * nc + q] : T(0);
+                // the first stage of a sweep has x^(0) = x^(j-1): no second load
+                if constexpr (MODE == FVM_STAGE) own_x0[c] = x0 ? (x0 == xp ? own_x[c] : x0[c * nc + q]) : T(0);
             }
         }
     };

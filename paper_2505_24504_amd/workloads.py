@@ -32,12 +32,15 @@ def bubble_small():
 
 
 def density_current():
-    """256x64 quads on 25.6 km x 6.4 km, k = 3, viscous, cold bubble, 10 SDIRK2 steps."""
+    """256x64 quads on 25.6 km x 6.4 km, k = 3, viscous, cold bubble, 10 SDIRK2 steps.
+
+    The smoother is the one-stage explicit Euler pseudo-time iteration, the one the
+    paper's experiments use (Sec. "Smoother / Pseudo time iteration")."""
     d = dict(PHYS)
     d.update(nx=256, nz=64, k=3, x0=0.0, x1=25600.0, z0=0.0, z1=6400.0,
              physics=1, background=0, bc=0, theta0=300.0, N=0.0, u_mean=0.0, mu=75.0,
              scheme=1, dt=2.0, newton_rtol=1e-8, gmres_m=30, mg_levels=4,
-             mg_key="mg002222V", rk_stages=3, mass_fix=1, fd_eps_mode=1, mg_precision=64)
+             mg_key="mg002222V", rk_stages=1, mass_fix=1, fd_eps_mode=1, mg_precision=64)
     pert = dict(shape=0, amp=-15.0, xc=0.0, zc=3000.0, xr=4000.0, zr=2000.0)
     return d, pert, 10
 
