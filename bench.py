@@ -423,7 +423,7 @@ def main():
                          "tiles": p.tiles}}
     forms["autotune"] = autotune_report(d, pert)
     # other preconditioner configurations of the same workload (same rtol, same steps)
-    for name, kw in (("fp64_mg_3stage_smoother", dict(rk_stages=3)),
+    for name, kw in () if a.no_forms else (("fp64_mg_3stage_smoother", dict(rk_stages=3)),
                      ("fp64_mg111111V_dg_smoothing", dict(mg_key="mg111111V", pseudo_cfl_dg=0.3)),
                      ("fp64_mg112222V_dg_smoothing", dict(mg_key="mg112222V", pseudo_cfl_dg=0.1))):
         try:
