@@ -31,10 +31,10 @@ HBM_PEAK_GBS = 8000.0
 # device copy of that same run (FETCH_SIZE x2, WRITE_SIZE x1).
 # It describes the kernel sources hashed below and is reported as null once
 # they change.
-TRAFFIC = {"class": "fv_stage", "bytes_per_launch": 3.0645e+07,
+TRAFFIC = {"class": "fv_stage", "bytes_per_launch": 2.7055e+07,
            "sources": ["paper_2505_24504_amd/csrc/fv.hip", "paper_2505_24504_amd/csrc/jfmg_dev.h",
                        "paper_2505_24504_amd/csrc/jfmg_internal.h"],
-           "sha256": "3842c11e4abda08406b12d8cc4909614d0290df6b3b07b880e2dd69449b8263c",
+           "sha256": "b78963a5aeb8f4d206068ce0dce1b9e3d968e36c7f48204192b545411497e74b",
            "profile": "profiles/traffic_fv_stage_density_current_fp64.md"}
 
 
