@@ -314,7 +314,23 @@ def explicit_reference_form(d, pert, implicit_ms_per_step, reps=5):
     _sync()
     el = (time.perf_counter() - t0) / reps
     N = jfmg.num_dofs(d)
-    return {"dt": dt, "steps_per_interval": n, "interval_s": T,
+    # the implicit step's cost per simulated second at larger time steps (one warm-up
+    # and two timed steps each from the initial state)
+    sweep = {}
+    for dti in (5.0, 10.0, 20.0):
+        q = jfmg.Problem(dict(d, dt=dti), device="cuda:0")
+        V = q.initial_state(pert)
+        q.implicit_step(V, raise_on_error=False)
+        _sync()
+        t1 = time.perf_counter()
+        sts = [q.implicit_step(V, raise_on_error=False) for _ in range(2)]
+        _sync()
+        e1 = (time.perf_counter() - t1) / 2
+        sweep[str(dti)] = {"ms_per_simulated_s": 1e3 * e1 / dti, "ms_per_step": 1e3 * e1,
+                           "gmres_its_per_step": sum(x["gmres_its"] for x in sts) / 2,
+                           "ok": all(x["status"] == 0 for x in sts)}
+        del q, V
+    return {"implicit_dt_sweep": sweep, "dt": dt, "steps_per_interval": n, "interval_s": T,
             "explicit_ms_per_simulated_s": 1e3 * el / T,
             "implicit_ms_per_simulated_s": implicit_ms_per_step / T,
             "explicit_dof_steps_per_s": n * N / el,
