@@ -673,11 +673,15 @@ template <typename T> struct Mg {
         return z;
     }
 
-    void smooth(int l, int nu)
+    // nu sweeps on level l.  With pc >= 0 (the next finer level) the last stage of the
+    // last sweep does not store its result v but applies the coarse-grid correction
+    // x_pc -= P v itself (FvLaunch::stage_prolong); returns whether it did.
+    bool smooth(int l, int nu, int pc = -1)
     {
         const FvArgs<T> A = fv_args<T>(p, l);
         Level& L = p->lev[l];
         const int S = p->cfg.rk_stages;
+        bool fused = false;
         for (int sw = 0; sw < nu; ++sw) {
             const int i0 = s.xi[l];
             const int oth[2] = {(i0 + 1) % 3, (i0 + 2) % 3};
@@ -693,6 +697,23 @@ template <typename T> struct Mg {
                 }
                 const T* x0 = s.xzero[l] ? nullptr : (const T*)L.buf[i0];   // null: x^(0) = 0
                 const double vb = 4.0 * L.nc * sizeof(T);
+                if (pc >= 0 && sw == nu - 1 && j == S - 1 && !zero) {
+                    Level& F = p->lev[pc];
+                    const bool fz = s.xzero[pc];
+                    const int cls = fv_wide_tile(L.tile) ? JFMG_K_FV_STAGE : JFMG_K_FV_STAGE_SMALL;
+                    // the stage's reads (no write of v), x_f read unless zero and written: four
+                    // vectors of this level each
+                    ProfScope ps(p, cls, ((x0 && prev != i0 ? 5 : 4) + (fz ? 4 : 8)) * vb);
+                    p->xcnt[pc][s.xi[pc]] = FvLaunch<T>::stage_prolong(
+                        A, (const T*)L.u, (const T*)L.F0, (const T*)L.buf[prev], x0, (const T*)L.b,
+                        (T*)F.buf[s.xi[pc]], fz, fvpart(p, l, prev), p->xcnt[l][prev], p->scal + S_LEV + 4 * l,
+                        alpha[j], p->adt, Red{fvpart(p, pc, s.xi[pc]), nullptr}, p->st, p->mb);
+                    p->mv_count[l]++;
+                    s.xzero[pc] = false;
+                    fused = true;
+                    prev = out;   // v itself is not needed any more
+                    continue;
+                }
                 // algorithmic bytes: reads u, F0, x^(j-1), x^(0), b, writes x^(j) (x^(0) not when it is 0
                 // or when it is x^(j-1), the first stage of a sweep); the zero-start stage reads b and
                 // writes x^(1)
@@ -709,9 +730,12 @@ template <typename T> struct Mg {
             s.xi[l] = prev;
             s.xzero[l] = false;
         }
+        return fused;
     }
 
-    void cycle(int l)
+    // MG_l; with pc >= 0 the final smoother stage applies the correction of level pc
+    // (see smooth); returns whether it did
+    bool cycle(int l, int pc = -1)
     {
         const Key& k = p->key;
         const bool fine = (l == 0);
@@ -735,8 +759,9 @@ template <typename T> struct Mg {
             s.xzero[l + 1] = true;
             s.xi[l + 1] = 0;
             s.pre[l + 1] = nb;
-            for (int cyc = 0; cyc < k.cycle; ++cyc) cycle(l + 1);
-            if (!s.xzero[l + 1]) {
+            bool fused = false;
+            for (int cyc = 0; cyc < k.cycle; ++cyc) fused = cycle(l + 1, cyc == k.cycle - 1 ? l : -1);
+            if (!fused && !s.xzero[l + 1]) {
                 if (s.xzero[l]) {
                     // x = 0 - P v: materialize the zero vector first
                     launch_zero(L.buf[s.xi[l]], sizeof(T) * 4 * L.nc, p->st, p->mb);
@@ -747,7 +772,7 @@ template <typename T> struct Mg {
                 s.xzero[l] = false;
             }
         }
-        smooth(l, fine ? k.d : k.f);
+        return smooth(l, fine ? k.d : k.f, pc);
     }
 
     // x = MG(0, b) on the finest level; b must be in lev[0].b; result pointer returned

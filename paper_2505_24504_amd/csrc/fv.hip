@@ -18,7 +18,7 @@ namespace jfmg {
 
 constexpr int FV_TX = 64, FV_TZ = 4, FV_NTH = FV_TX * FV_TZ;
 
-enum { FVM_LIN = 0, FVM_STAGE = 1, FVM_MATVEC = 2, FVM_DEFECT = 3 };
+enum { FVM_LIN = 0, FVM_STAGE = 1, FVM_MATVEC = 2, FVM_DEFECT = 3, FVM_STAGE_PC = 4 };
 
 // Tile shapes of the FV operator kernels (jfmg_tile; chosen per level, by
 // jfmg_autotune or by default):
@@ -53,6 +53,9 @@ enum { FVM_LIN = 0, FVM_STAGE = 1, FVM_MATVEC = 2, FVM_DEFECT = 3 };
 //   DEFECT  out(coarse) = R(g'x - b), 2x2 agglomeration inside the tile; with out2 also
 //           the coarse level's first RK stage from zero, out2 = alpha_j dtau_c out (dtau_c in
 //           slots2), and its ||.||^2 block partials into red
+//   STAGE_PC the STAGE result v is not stored: it corrects the next finer level's x in
+//           out2 by injection, x_f -= P v (x_f = -P v when cfl != 0, x_f being zero), with the
+//           ||x_f||^2 block partials into red (the last smoother stage of a coarse level)
 template <typename T, int TX, int TZ, int NTH, int WPE, bool LATE, bool ZREV, bool MB, int MODE>
 __global__ void __launch_bounds__(NTH, WPE)
 fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, const T* __restrict__ xp,
@@ -105,9 +108,11 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 if constexpr (PERT) { own_x[c] = xp[c * nc + q]; own_f0[c] = F0[c * nc + q]; }
-                if constexpr (MODE == FVM_STAGE || MODE == FVM_DEFECT) own_b[c] = b[c * nc + q];
+                if constexpr (MODE == FVM_STAGE || MODE == FVM_STAGE_PC || MODE == FVM_DEFECT)
+                    own_b[c] = b[c * nc + q];
                 // the first stage of a sweep has x^(0) = x^(j-1): no second load
-                if constexpr (MODE == FVM_STAGE) own_x0[c] = x0 ? (x0 == xp ? own_x[c] : x0[c * nc + q]) : T(0);
+                if constexpr (MODE == FVM_STAGE || MODE == FVM_STAGE_PC)
+                    own_x0[c] = x0 ? (x0 == xp ? own_x[c] : x0[c * nc + q]) : T(0);
             }
         }
     };
@@ -310,6 +315,29 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
                     const T v = own_x0[c] + s * (own_b[c] - Ax[c]);
                     out[c * nc + q] = v;
                     nrm += (double)v * (double)v;
+                }
+            }
+            put_partial<NTH>(red, nrm);
+        } else if constexpr (MODE == FVM_STAGE_PC) {
+            double nrm = 0.0;
+            if (valid) {
+                const T s = (T)(alpha_j * slots[LV_DTAU]);
+                const bool fzero = cfl != 0.0;
+                const long nxf = 2L * nxl, ncf = 4 * nc;
+                const long q00 = (long)(2 * J) * nxf + 2 * I, q10 = q00 + nxf;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const T v = own_x0[c] + s * (own_b[c] - Ax[c]);
+                    T* xf = out2 + c * ncf;
+                    T f00 = -v, f01 = -v, f10 = -v, f11 = -v;
+                    if (!fzero) {
+                        f00 = xf[q00] - v; f01 = xf[q00 + 1] - v;
+                        f10 = xf[q10] - v; f11 = xf[q10 + 1] - v;
+                    }
+                    xf[q00] = f00; xf[q00 + 1] = f01;
+                    xf[q10] = f10; xf[q10 + 1] = f11;
+                    nrm += ((double)f00 * (double)f00 + (double)f01 * (double)f01) +
+                           ((double)f10 * (double)f10 + (double)f11 * (double)f11);
                 }
             }
             put_partial<NTH>(red, nrm);
@@ -540,6 +568,14 @@ int FvLaunch<T>::stage(const FvArgs<T>& A, const T* u, const T* F0, const T* xp,
     }
     return tile_launch<T, FVM_STAGE>(A, u, F0, xp, x0, b, xo, xpart, xcount, const_cast<double*>(slots), alpha_j,
                                      adt, 0.0, red, st, mb);
+}
+template <typename T>
+int FvLaunch<T>::stage_prolong(const FvArgs<T>& A, const T* u, const T* F0, const T* xp, const T* x0, const T* b,
+                               T* xf, bool fine_zero, const double* xpart, int xcount, const double* slots,
+                               double alpha_j, double adt, Red red, hipStream_t st, const Mb& mb)
+{
+    return tile_launch<T, FVM_STAGE_PC>(A, u, F0, xp, x0, b, nullptr, xpart, xcount, const_cast<double*>(slots),
+                                        alpha_j, adt, fine_zero ? 1.0 : 0.0, red, st, mb, xf);
 }
 template <typename T>
 void FvLaunch<T>::matvec(const FvArgs<T>& A, const T* u, const T* F0, const T* x, T* out, const double* xpart,

@@ -140,6 +140,12 @@ template <typename T> struct FvLaunch {
     static int stage(const FvArgs<T>& A, const T* u, const T* F0, const T* xp, const T* x0, const T* b, T* xo,
                      const double* xpart, int xcount, const double* slots, double alpha_j, double adt, int zero,
                      Red red, hipStream_t st, const Mb& mb = Mb{});
+    // the same stage without storing its result v: the next finer level's x (xf, level
+    // dimensions twice those of A) becomes xf - P v (-P v when fine_zero), with the
+    // ||xf||^2 partials into red.partials; returns their count
+    static int stage_prolong(const FvArgs<T>& A, const T* u, const T* F0, const T* xp, const T* x0, const T* b,
+                             T* xf, bool fine_zero, const double* xpart, int xcount, const double* slots,
+                             double alpha_j, double adt, Red red, hipStream_t st, const Mb& mb = Mb{});
     static void matvec(const FvArgs<T>& A, const T* u, const T* F0, const T* x, T* out, const double* xpart,
                        int xcount, const double* slots, double adt, hipStream_t st, const Mb& mb = Mb{});
     // coarse defect rc = R(g'x - b) (x = 0: R(-b)); with z0.x1 the first RK stage of the

@@ -340,9 +340,13 @@ def test_autotune_choice_and_step_parity():
 
 
 @pytest.mark.parametrize("case", FV_CASES)
-@pytest.mark.parametrize("key", ["mg002222V", "mg001111W", "mg000200V"])
-def test_mg_fv_parity(case, key):
-    d = dict(_fv_cfg(case), mg_key=key)
+@pytest.mark.parametrize("key,stages", [("mg002222V", 3), ("mg001111W", 3), ("mg000200V", 3),
+                                        ("mg002222V", 1), ("mg001111W", 1), ("mg000011V", 1)])
+def test_mg_fv_parity(case, key, stages):
+    """The FV cycle against the oracle's; the one-stage keys cover a coarse level's last
+    stage applying the correction of the finer level itself (with and without pre-smoothing
+    on the finer level: the finer x nonzero or zero), also in the W-cycle's second pass."""
+    d = dict(_fv_cfg(case), mg_key=key, rk_stages=stages)
     p, o = pair(d)
     U = rand_state(o, 51)
     p.linearize(to_dev(U), 0.8)
@@ -351,7 +355,7 @@ def test_mg_fv_parity(case, key):
     xg = to_np(p.mg_fv(to_dev(b)))
     xo = o.mg_fv(b)
     err = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
-    print(f"case mg_fv {case} {key}: rel err {err:.3e}")
+    print(f"case mg_fv {case} {key} s={stages}: rel err {err:.3e}")
     assert err <= 1e-6
 
 
