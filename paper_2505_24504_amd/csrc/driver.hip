@@ -1031,6 +1031,7 @@ jfmg_status fgmres(jfmg_problem* p, const double* G, const std::vector<double>& 
     hipStream_t st = p->st;
     struct Member {
         std::vector<double> H, cs, sn, g, y;
+        std::vector<double> res;   // residual estimate |g_j| after iteration j-1 (res[0] = beta)
         double beta = 0.0;
         bool done = false, conv = false;
         int jend = 0;
@@ -1044,6 +1045,7 @@ jfmg_status fgmres(jfmg_problem* p, const double* G, const std::vector<double>& 
         x.sn.assign(m, 0.0);
         x.g.assign(m + 1, 0.0);
         x.y.assign(m, 0.0);
+        x.res.assign(m + 1, 0.0);
         x.beta = gnorm[b];
         x.done = !active[b];
         left += !x.done;
@@ -1058,12 +1060,32 @@ jfmg_status fgmres(jfmg_problem* p, const double* G, const std::vector<double>& 
         for (Member& x : M) {
             std::fill(x.g.begin(), x.g.end(), 0.0);
             x.g[0] = x.beta;
+            x.res[0] = std::fabs(x.beta);
             x.jend = 0;
             x.conv = false;
         }
         // Iteration j+1 is issued before the host looks at iteration j's
-        // Hessenberg columns, so the readback round trip overlaps GPU work; when
-        // iteration j converges the speculative iteration's output is unused.
+        // Hessenberg columns, so the readback round trip overlaps GPU work, except
+        // where iteration j is likely to end the cycle: a speculative iteration
+        // issued in vain costs a whole iteration of the device, one issued after
+        // the readback only the host's turnaround (≈15 us).  "Likely": every active
+        // member's residual estimate, extrapolated by its fastest recent reduction
+        // factor (1/4 before the first iteration), is within SPEC_MARGIN of its
+        // tolerance.
+        constexpr double SPEC_MARGIN = 4.0;
+        auto likely_end = [&](int j) {
+            bool any = false;
+            for (int mb = 0; mb < B; ++mb) {
+                const Member& x = M[mb];
+                if (x.done || x.conv) continue;
+                any = true;
+                double rho = 0.25;
+                if (j >= 1 && x.res[j - 1] > 0.0) rho = x.res[j] / x.res[j - 1];
+                if (j >= 2 && x.res[j - 2] > 0.0) rho = std::min(rho, x.res[j - 1] / x.res[j - 2]);
+                if (!(x.res[j] * rho <= SPEC_MARGIN * tol[mb])) return false;
+            }
+            return any;
+        };
         auto issue = [&](int j) -> jfmg_status {
             jfmg_status s = run_iter(p, j);   // ends by publishing its scalars to hpin
             if (s) return s;
@@ -1072,10 +1094,12 @@ jfmg_status fgmres(jfmg_problem* p, const double* G, const std::vector<double>& 
         };
         jfmg_status s0 = issue(0);
         if (s0) return s0;
+        int next = 1;   // next iteration to issue
         for (int j = 0; j < m; ++j) {
-            if (j + 1 < m) {
+            if (next == j + 1 && j + 1 < m && !likely_end(j)) {
                 jfmg_status s = issue(j + 1);
                 if (s) return s;
+                ++next;
             }
             HIPCHK(p, hipEventSynchronize(p->hev[j]));
             p->syncs++;
@@ -1102,6 +1126,7 @@ jfmg_status fgmres(jfmg_problem* p, const double* G, const std::vector<double>& 
                 H[(j + 1) * m + j] = 0.0;
                 x.g[j + 1] = -x.sn[j] * x.g[j];
                 x.g[j] = x.cs[j] * x.g[j];
+                x.res[j + 1] = std::fabs(x.g[j + 1]);
                 x.jend = j + 1;
                 if (!std::isfinite(x.g[j + 1]) || !std::isfinite(hn)) {
                     *its_out = its;
@@ -1111,6 +1136,11 @@ jfmg_status fgmres(jfmg_problem* p, const double* G, const std::vector<double>& 
                 else all_conv = false;
             }
             if (all_conv) break;
+            if (next == j + 1 && j + 1 < m) {   // not issued speculatively
+                jfmg_status s = issue(j + 1);
+                if (s) return s;
+                ++next;
+            }
         }
         int jmax = 0;
         std::fill(ybuf.begin(), ybuf.end(), 0.0);
