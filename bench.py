@@ -263,7 +263,7 @@ def inertia_gravity_forms(steps=3):
         p = jfmg.Problem(d, device="cuda:0")
         U = p.initial_state(pert)
         U0 = U.clone()
-        p.implicit_step(U)          # warm-up step (graph capture), from the same start
+        p.implicit_step(U)          # warm-up step, from the same start
         U.copy_(U0)
         _sync()
         t0 = time.perf_counter()
@@ -424,7 +424,7 @@ def main():
     if prof_cls == "auto":
         _, _, _, _, prof_all = run_form(d, pert, 1, 0, jfmg.KERNEL_CLASSES)
         prof_cls = max(prof_all, key=lambda k: prof_all[k]["ms"])
-    # timed pass, FP64 multigrid (headline): captured HIP graphs, no instrumentation
+    # timed pass, FP64 multigrid (headline): no instrumentation
     p, el, lat, its, _ = run_form(d, pert, a.steps, a.warmup, [])
     value = a.steps * N / el
     # second timed pass of the same workload: the dominant kernel class timed by the
@@ -489,7 +489,7 @@ def main():
                      "avg_launch_us": 1e3 * avg_ms, "launches": pc["launches"],
                      "algorithmic_bytes_per_launch": bytes_per_launch,
                      "timing": "HIP start/stop events of each dispatch of the kernel class, second timed pass "
-                               f"of the same {a.steps} steps without graph replay ({1e3 * el_prof / a.steps:.1f} ms/step)"},
+                               f"of the same {a.steps} steps ({1e3 * el_prof / a.steps:.1f} ms/step with the events)"},
     }
     if not a.no_forms:
         forms.update(ensemble_forms())

@@ -174,7 +174,10 @@ jfmg_status jfmg_mg_apply(jfmg_problem* p, const double* r, double* z);
 
 /* One implicit step U^n -> U^{n+1} in place (implicit Euler or SDIRK2), each
    stage by inexact Newton with Eisenstat-Walker forcing and right-preconditioned
-   FGMRES (Sec. "Solver").  On any error U is left unchanged.  stats may be NULL. */
+   FGMRES (Sec. "Solver").  On any error U is left unchanged.  stats may be NULL.
+   FGMRES iterations are launched kernel by kernel; with the environment variable
+   JFMG_GRAPH=1 when the problem is created, each iteration index is captured
+   once as a HIP graph and replayed instead (bitwise the same results). */
 jfmg_status jfmg_implicit_step(jfmg_problem* p, double* U, jfmg_stats* stats);
 
 /* nsteps explicit steps U^n -> U^{n+1} in place with the four-stage,

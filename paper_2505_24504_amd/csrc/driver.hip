@@ -373,7 +373,7 @@ struct jfmg_problem {
     };
     std::vector<IterGraph> graphs;
     double graph_adt = 0.0;
-    bool use_graphs = true;
+    bool use_graphs = false;
     IterGraph* capturing = nullptr;
     double* hpin = nullptr;            // coherent pinned host copies of the Arnoldi scalars, per iteration
     double* hscal = nullptr;           // coherent pinned: scalars read by the host, [member][HSCAL]
@@ -1373,9 +1373,9 @@ jfmg_status jfmg_create_problem(const jfmg_config* cfg, void* workspace, size_t 
     p->st = (hipStream_t)hip_stream;
     p->user_st = p->st;
     p->cs = nullptr;
-    {
-        const char* ng = std::getenv("JFMG_NO_GRAPH");
-        p->use_graphs = !(ng && ng[0] == '1');
+    {   // FGMRES iterations run eagerly unless JFMG_GRAPH=1 asks for graph replay
+        const char* g = std::getenv("JFMG_GRAPH");
+        p->use_graphs = g && g[0] == '1';
     }
     if (!build_reftab(cfg->k, cfg->transfer, p->R)) {
         delete p;

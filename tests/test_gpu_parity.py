@@ -596,8 +596,9 @@ def test_graph_replay_matches_eager(monkeypatch):
     """FGMRES iterations replayed from captured HIP graphs give bitwise the eager result."""
     d, pert, _ = W.bubble_small()
     d = dict(d, k=2, mg_levels=3, scheme=1)
+    monkeypatch.setenv("JFMG_GRAPH", "1")
     p_graph = jfmg.Problem(d, device=DEV)
-    monkeypatch.setenv("JFMG_NO_GRAPH", "1")
+    monkeypatch.delenv("JFMG_GRAPH")
     p_eager = jfmg.Problem(d, device=DEV)
     U1 = p_graph.initial_state(pert)
     U2 = U1.clone()
