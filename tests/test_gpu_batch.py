@@ -121,8 +121,8 @@ def test_lockstep_members_equal_alone(prec, key):
     ens = [m for m in W.ensemble(seed=4, members=64) if m[0]["nx"] == 32][:3]
     assert len(ens) == 3
     d = dict(ens[0][0], mg_precision=prec)
-    if key:
-        d["mg_key"] = key
+    if key:   # DG-level smoothing with the one-stage smoother needs a small c*_DG
+        d.update(mg_key=key, pseudo_cfl_dg=0.1)
     alone = [_alone(d, pert, 2) for _, pert, _ in ens]
     pb = jfmg.Problem(dict(d, batch=len(ens)), device=DEV)
     single = jfmg.Problem(d, device=DEV)
