@@ -340,6 +340,42 @@ def explicit_reference_form(d, pert, implicit_ms_per_step, reps=5):
             "finite": bool(torch.isfinite(U).all().item())}
 
 
+def preconditioner_keys(steps=2):
+    """The paper's preconditioner configurations (key mg a b c d e f G) on the three
+    workload shapes of its experiments: time, FGMRES iterations and operator calls per
+    implicit step (one warm-up step, then `steps` timed ones, FP64 multigrid, one-stage
+    smoother; DG-level smoothing at c*_DG = 0.3)."""
+    import torch
+    from paper_2505_24504_amd import jfmg, workloads as W
+    dc, dc_pert, _ = W.density_current()
+    ig, ig_pert, _ = W.inertia_gravity(mg_precision=64)
+    rb, rb_pert, _ = W.bubble_small()
+    rb = dict(rb, nx=64, nz=64, k=2, scheme=1, mg_levels=4, rk_stages=1, newton_rtol=1e-8, gmres_m=30)
+    cases = {"density_current_256x64_k3": (dc, dc_pert), "inertia_gravity_600x20_k3": (ig, ig_pert),
+             "rising_bubble_64x64_k2": (rb, rb_pert)}
+    out = {}
+    for wname, (d0, pert) in cases.items():
+        res = {}
+        for key in ("mg002222V", "mg001111V", "mg111111V", "mg001111W", "mg111111W"):
+            d = dict(d0, mg_key=key, pseudo_cfl_dg=0.3, mg_precision=64)
+            p = jfmg.Problem(d, device="cuda:0")
+            U = p.initial_state(pert)
+            st0 = p.implicit_step(U, raise_on_error=False)
+            _sync()
+            t0 = time.perf_counter()
+            sts = [p.implicit_step(U, raise_on_error=False) for _ in range(steps)]
+            _sync()
+            el = (time.perf_counter() - t0) / steps
+            res[key] = {"ms_per_step": 1e3 * el,
+                        "gmres_its_per_step": sum(x["gmres_its"] for x in sts) / steps,
+                        "jvps_per_step": sum(x["jvps"] for x in sts) / steps,
+                        "fv_matvecs_per_step": sum(sum(x["fv_matvecs"]) for x in sts) / steps,
+                        "ok": st0["status"] == 0 and all(x["status"] == 0 for x in sts)}
+            del p, U
+        out[wname] = res
+    return out
+
+
 def large_roofline(reps=20):
     """The FV operator and the DG JVP on vectors far above the 256 MB cache:
     a 1024x1024-quad, k = 3 problem (FV level 4096x4096 cells, DG vector 537 MB,
@@ -496,6 +532,7 @@ def main():
         forms.update(serving_forms(a.serve_requests))
         forms["inertia_gravity"] = inertia_gravity_forms()
         forms["explicit_reference"] = explicit_reference_form(d, pert, 1e3 * el / a.steps)
+        forms["preconditioner_keys"] = preconditioner_keys()
     if not a.no_large:
         out["roofline_hbm_resident"] = large_roofline()
     # copy bandwidth of the device: HBM-resident (1 GiB) and cache-resident (32 MiB)
