@@ -649,6 +649,13 @@ struct MgState {
                          // kernel that wrote b), with this many ||x||^2 partials
 };
 
+// coefficient alpha_j of the s-stage low-storage pseudo-time smoother (j from 0):
+// the configured one, else 1/(s - j)
+double smoother_alpha(const jfmg_problem* p, int j)
+{
+    return p->cfg.rk_alpha[j] > 0 ? p->cfg.rk_alpha[j] : 1.0 / (p->cfg.rk_stages - j);
+}
+
 template <typename T> struct Mg {
     jfmg_problem* p;
     MgState s;
@@ -656,8 +663,7 @@ template <typename T> struct Mg {
 
     void init()
     {
-        const int S = p->cfg.rk_stages;
-        for (int j = 0; j < 4; ++j) alpha[j] = p->cfg.rk_alpha[j] > 0 ? p->cfg.rk_alpha[j] : 1.0 / (S - j);
+        for (int j = 0; j < 4; ++j) alpha[j] = smoother_alpha(p, j);
         for (int l = 0; l < MAXLEV; ++l) s.pre[l] = 0;
     }
     // the first stage of level l from x = 0 can be fused into the kernel that writes b
@@ -823,7 +829,7 @@ void jvp_slot(jfmg_problem* p, const double* y, double* out, int yslot)
 // except that the very last stage writes it into slot `last` instead.  The stages
 // alternate between z (the last stage of a sweep, in place over z_0) and tmp1; tmp2
 // holds the products.
-void dg_smooth(jfmg_problem* p, const Mg<double>& mg, double* z, const double* r, int nu, bool& zzero, int last)
+void dg_smooth(jfmg_problem* p, double* z, const double* r, int nu, bool& zzero, int last)
 {
     const int S = p->cfg.rk_stages;
     double* xs = p->tmp1;
@@ -837,12 +843,13 @@ void dg_smooth(jfmg_problem* p, const Mg<double>& mg, double* z, const double* r
             const int slot = lastst ? (sw == nu - 1 ? last : S_DGZ) : S_DGX;
             if (j == 0 && zzero) {   // reads r, writes z_1
                 ProfScope ps(p, JFMG_K_DG_SMOOTH, 2.0 * p->N * 8);
-                launch_dg_smooth(out, nullptr, r, nullptr, mg.alpha[j], dtau, p->N, red_at(p, slot), p->st, p->mb);
+                launch_dg_smooth(out, nullptr, r, nullptr, smoother_alpha(p, j), dtau, p->N, red_at(p, slot), p->st,
+                                 p->mb);
             } else {                 // reads r, G' z_{j-1} and z_0 (when nonzero), writes z_j
                 jvp_slot(p, prev, t, j == 0 ? S_DGZ : S_DGX);
                 ProfScope ps(p, JFMG_K_DG_SMOOTH, (zzero ? 3.0 : 4.0) * p->N * 8);
-                launch_dg_smooth(out, zzero ? nullptr : z, r, t, mg.alpha[j], dtau, p->N, red_at(p, slot), p->st,
-                                 p->mb);
+                launch_dg_smooth(out, zzero ? nullptr : z, r, t, smoother_alpha(p, j), dtau, p->N, red_at(p, slot),
+                                 p->st, p->mb);
             }
         }
         zzero = false;
@@ -854,11 +861,9 @@ void dg_smooth(jfmg_problem* p, const Mg<double>& mg, double* z, const double* r
 template <typename T> jfmg_status mg_apply_dg_t(jfmg_problem* p, double* r, double* z, int zslot, const double* rnrm2)
 {
     const Key& k = p->key;
-    Mg<double> mg{p};
-    mg.init();
     if (rnrm2) launch_scale(r, r, p->N, rnrm2, p->st, 1.0, p->mb);
     bool zzero = true;
-    dg_smooth(p, mg, z, r, k.a, zzero, S_DGZ);
+    dg_smooth(p, z, r, k.a, zzero, S_DGZ);
     const int cslot = k.b ? S_DGZ : zslot;
     jfmg_status s;
     if (zzero) {
@@ -877,7 +882,7 @@ template <typename T> jfmg_status mg_apply_dg_t(jfmg_problem* p, double* r, doub
     }
     if (s) return s;
     zzero = false;
-    dg_smooth(p, mg, z, r, k.b, zzero, zslot);
+    dg_smooth(p, z, r, k.b, zzero, zslot);
     return check_launch(p);
 }
 

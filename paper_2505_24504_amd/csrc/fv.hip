@@ -54,14 +54,14 @@ enum { FVM_LIN = 0, FVM_STAGE = 1, FVM_MATVEC = 2, FVM_DEFECT = 3, FVM_STAGE_PC 
 //           the coarse level's first RK stage from zero, out2 = alpha_j dtau_c out (dtau_c in
 //           slots2), and its ||.||^2 block partials into red
 //   STAGE_PC the STAGE result v is not stored: it corrects the next finer level's x in
-//           out2 by injection, x_f -= P v (x_f = -P v when cfl != 0, x_f being zero), with the
+//           out2 by injection, x_f -= P v (x_f = -P v when fzero is set, x_f being zero), with the
 //           ||x_f||^2 block partials into red (the last smoother stage of a coarse level)
 template <typename T, int TX, int TZ, int NTH, int WPE, bool LATE, bool ZREV, bool MB, int MODE>
 __global__ void __launch_bounds__(NTH, WPE)
 fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, const T* __restrict__ xp,
                const T* __restrict__ x0, const T* __restrict__ b, T* __restrict__ out, T* __restrict__ out2,
                const double* __restrict__ xpart, int xcount, double* __restrict__ slots,
-               const double* __restrict__ slots2, double alpha_j, double adt, double cfl, Red red, long ms)
+               const double* __restrict__ slots2, double alpha_j, double adt, int fzero, Red red, long ms)
 {
     if constexpr (MB) {   // member blockIdx.z of a lock-step batch
         u = mbr(u, ms);
@@ -322,7 +322,6 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
             double nrm = 0.0;
             if (valid) {
                 const T s = (T)(alpha_j * slots[LV_DTAU]);
-                const bool fzero = cfl != 0.0;
                 const long nxf = 2L * nxl, ncf = 4 * nc;
                 const long q00 = (long)(2 * J) * nxf + 2 * I, q10 = q00 + nxf;
 #pragma unroll
@@ -507,42 +506,42 @@ static inline dim3 tile_grid(int nx, int nz, int members = 1)
 template <typename T, int TX, int TZ, int NTH, int WPE, bool LATE, bool ZREV, int MODE>
 static int tile_launch_shape(const FvArgs<T>& A, const T* u, const T* F0, const T* xp, const T* x0, const T* b,
                              T* out, T* out2, const double* xpart, int xcount, double* slots, const double* slots2,
-                             double alpha_j, double adt, double cfl, Red red, hipStream_t st, const Mb& mb)
+                             double alpha_j, double adt, int fzero, Red red, hipStream_t st, const Mb& mb)
 {
     const dim3 g((unsigned)((A.nxl + TX - 1) / TX), (unsigned)((A.nzl + TZ - 1) / TZ), (unsigned)mb.n);
     if (mb.n > 1)
         timed_launch(fv_tile_kernel<T, TX, TZ, NTH, WPE, LATE, ZREV, true, MODE>, g, dim3(NTH), st, A, u, F0, xp, x0, b,
-                     out, out2, xpart, xcount, slots, slots2, alpha_j, adt, cfl, red, mb.ms);
+                     out, out2, xpart, xcount, slots, slots2, alpha_j, adt, fzero, red, mb.ms);
     else
         timed_launch(fv_tile_kernel<T, TX, TZ, NTH, WPE, LATE, ZREV, false, MODE>, g, dim3(NTH), st, A, u, F0, xp, x0,
-                     b, out, out2, xpart, xcount, slots, slots2, alpha_j, adt, cfl, red, 0L);
+                     b, out, out2, xpart, xcount, slots, slots2, alpha_j, adt, fzero, red, 0L);
     return (int)(g.x * g.y);
 }
 
 template <typename T, int MODE>
 static int tile_launch(const FvArgs<T>& A, const T* u, const T* F0, const T* xp, const T* x0, const T* b, T* out,
-                       const double* xpart, int xcount, double* slots, double alpha_j, double adt, double cfl,
+                       const double* xpart, int xcount, double* slots, double alpha_j, double adt, int fzero,
                        Red red, hipStream_t st, const Mb& mb, T* out2 = nullptr, const double* slots2 = nullptr)
 {
     switch (A.tile) {
     case JFMG_TILE_64x8:
         return tile_launch_shape<T, 64, 8, 512, 4, true, true, MODE>(A, u, F0, xp, x0, b, out, out2, xpart, xcount,
-                                                                       slots, slots2, alpha_j, adt, cfl, red, st, mb);
+                                                                       slots, slots2, alpha_j, adt, fzero, red, st, mb);
     case JFMG_TILE_16x4:
         return tile_launch_shape<T, 16, 4, 256, 1, false, true, MODE>(A, u, F0, xp, x0, b, out, out2, xpart, xcount,
-                                                                        slots, slots2, alpha_j, adt, cfl, red, st, mb);
+                                                                        slots, slots2, alpha_j, adt, fzero, red, st, mb);
     case JFMG_TILE_8x4:
         return tile_launch_shape<T, 8, 4, 128, 1, false, true, MODE>(A, u, F0, xp, x0, b, out, out2, xpart, xcount,
-                                                                       slots, slots2, alpha_j, adt, cfl, red, st, mb);
+                                                                       slots, slots2, alpha_j, adt, fzero, red, st, mb);
     case JFMG_TILE_32x4:
         return tile_launch_shape<T, 32, 4, 256, 2, false, true, MODE>(A, u, F0, xp, x0, b, out, out2, xpart, xcount,
-                                                                        slots, slots2, alpha_j, adt, cfl, red, st, mb);
+                                                                        slots, slots2, alpha_j, adt, fzero, red, st, mb);
     case JFMG_TILE_64x4_512:
         return tile_launch_shape<T, 64, 4, 512, 4, true, true, MODE>(A, u, F0, xp, x0, b, out, out2, xpart, xcount,
-                                                                       slots, slots2, alpha_j, adt, cfl, red, st, mb);
+                                                                       slots, slots2, alpha_j, adt, fzero, red, st, mb);
     default:
         return tile_launch_shape<T, 64, 4, 256, 4, true, true, MODE>(A, u, F0, xp, x0, b, out, out2, xpart, xcount,
-                                                                       slots, slots2, alpha_j, adt, cfl, red, st, mb);
+                                                                       slots, slots2, alpha_j, adt, fzero, red, st, mb);
     }
 }
 
@@ -551,7 +550,7 @@ void FvLaunch<T>::lin_level(const FvArgs<T>& A, const T* u, T* F0, Red red, doub
                             hipStream_t st, const Mb& mb)
 {
     const int nb = tile_launch<T, FVM_LIN>(A, u, nullptr, nullptr, nullptr, nullptr, F0, nullptr, 0, slots, 0.0, adt,
-                                           cfl, red, st, mb);
+                                           0, red, st, mb);
     fv_lin_finalize_kernel<<<dim3(1, 1, mb.n), dim3(256), 0, st>>>(red.partials, nb, slots, (double)A.hx,
                                                                    (double)A.hz, (double)A.mu, adt, cfl, mb.ms);
 }
@@ -567,7 +566,7 @@ int FvLaunch<T>::stage(const FvArgs<T>& A, const T* u, const T* F0, const T* xp,
         return nb;
     }
     return tile_launch<T, FVM_STAGE>(A, u, F0, xp, x0, b, xo, xpart, xcount, const_cast<double*>(slots), alpha_j,
-                                     adt, 0.0, red, st, mb);
+                                     adt, 0, red, st, mb);
 }
 template <typename T>
 int FvLaunch<T>::stage_prolong(const FvArgs<T>& A, const T* u, const T* F0, const T* xp, const T* x0, const T* b,
@@ -575,14 +574,14 @@ int FvLaunch<T>::stage_prolong(const FvArgs<T>& A, const T* u, const T* F0, cons
                                double alpha_j, double adt, Red red, hipStream_t st, const Mb& mb)
 {
     return tile_launch<T, FVM_STAGE_PC>(A, u, F0, xp, x0, b, nullptr, xpart, xcount, const_cast<double*>(slots),
-                                        alpha_j, adt, fine_zero ? 1.0 : 0.0, red, st, mb, xf);
+                                        alpha_j, adt, fine_zero ? 1 : 0, red, st, mb, xf);
 }
 template <typename T>
 void FvLaunch<T>::matvec(const FvArgs<T>& A, const T* u, const T* F0, const T* x, T* out, const double* xpart,
                          int xcount, const double* slots, double adt, hipStream_t st, const Mb& mb)
 {
     tile_launch<T, FVM_MATVEC>(A, u, F0, x, nullptr, nullptr, out, xpart, xcount, const_cast<double*>(slots), 0.0,
-                               adt, 0.0, Red{nullptr, nullptr}, st, mb);
+                               adt, 0, Red{nullptr, nullptr}, st, mb);
 }
 template <typename T>
 int FvLaunch<T>::defect_restrict(const FvArgs<T>& A, const T* u, const T* F0, const T* x, const T* b, T* rc,
@@ -595,7 +594,7 @@ int FvLaunch<T>::defect_restrict(const FvArgs<T>& A, const T* u, const T* F0, co
         return 0;
     }
     const int nb = tile_launch<T, FVM_DEFECT>(A, u, F0, x, nullptr, b, rc, xpart, xcount, const_cast<double*>(slots),
-                                              z0.alpha, adt, 0.0, z0.red, st, mb, z0.x1, z0.slots);
+                                              z0.alpha, adt, 0, z0.red, st, mb, z0.x1, z0.slots);
     return z0.x1 ? nb : 0;
 }
 template <typename T>
