@@ -2,13 +2,12 @@
 
 A step is one implicit SDIRK2 step of the density-current workload (256 x 64
 quads, k = 3, viscous, dt = 2 s, Newton rtol 1e-8, FGMRES(30), 4 FV levels,
-mg002222V, 3-stage RK smoother) with the whole solver on the GPU: residuals,
+mg002222V, one-stage RK smoother) with the whole solver on the GPU: residuals,
 FD Jacobian-vector products, transfers, FV multigrid and Arnoldi.  value =
 (timed steps x unknowns) / wall seconds, inputs resident in HBM.  The plain
 FP64 form is the headline; the FP32-multigrid form is timed beside it.
 
-Prints ONE JSON line.  --gpus > 1 is not supported (one GPU per process and
-this build runs on one GPU).
+Prints ONE JSON line.  --gpus > 1 is not supported (the solver runs on one GPU).
 """
 from __future__ import annotations
 
@@ -445,7 +444,7 @@ def cpu_baseline():
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     import torch
 
