@@ -259,9 +259,9 @@ jfmg_status jfmg_autotune(jfmg_problem* p, int reps, int* shapes, double* times_
    stream it runs on; jfmg_profile_read returns per class the summed event time
    [ms], the launch count and the summed algorithmic HBM bytes (what the launch
    must read and write at minimum, e.g. 6 FV vectors for a smoother stage with a
-   matvec).  While a mask is set, implicit steps launch eagerly instead of
-   replaying their captured HIP graphs (event timing inside graphs is not
-   available).  Enabling resets the counters and synchronizes the stream. */
+   matvec).  While a mask is set, implicit steps launch kernel by kernel even
+   with JFMG_GRAPH=1 (event timing inside graphs is not available).  Enabling
+   resets the counters and synchronizes the stream. */
 typedef enum {
     JFMG_K_DG_RESIDUAL = 0,   /* stage residual G and ||G||                         */
     JFMG_K_DG_JVP = 1,        /* fused FD Jacobian-vector product                   */

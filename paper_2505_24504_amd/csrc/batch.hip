@@ -4,9 +4,8 @@
 // Every member is an ordinary jfmg_problem whose workspace is a first-fit range
 // of the caller's arena.  A fixed pool of host worker threads advances the
 // members one implicit step at a time; each step runs on the member's private
-// stream (captured-graph replay per FGMRES iteration), so the small, latency
-// bound kernels of different members overlap on the GPU while one member's
-// host waits for its Arnoldi scalars.  Members share no device memory and every
+// stream, so the small, latency bound kernels of different members overlap on
+// the GPU while one member's host waits for its Arnoldi scalars.  Members share no device memory and every
 // kernel reduces in a fixed order, so a member's result does not depend on what
 // else runs beside it.
 #include <hip/hip_runtime.h>
