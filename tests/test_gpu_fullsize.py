@@ -1,0 +1,114 @@
+"""Parity at the density-current size, in the configuration bench.py times (256 x 64 quads,
+k = 3, viscous, 4 FV levels 1024x256 .. 128x32 cells, the default FV tile shapes, FP64):
+L_h, the FD Jacobian-vector product, the finest-level FV matvec, one multigrid cycle and the
+whole preconditioner against the oracle on the complete vectors (the oracle takes seconds at
+this size), and an implicit step checked through properties that hold at any size: the
+oracle's stage residual at the GPU's result meets the Newton tolerance, and rho / rho theta
+mass is kept.  Tolerances are those of the small-case tests (tests/test_gpu_parity.py)."""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from paper_2505_24504_amd import jfmg, workloads as W  # noqa: E402
+
+from gpu_common import DEV, EPS, dg_mass, fv_total_norm, node_total_norm, pair, to_dev, to_np  # noqa: E402
+
+
+def setup_module(module):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    jfmg.load_library()
+
+
+@pytest.fixture(scope="module")
+def dc():
+    d, pert, _ = W.density_current()
+    p, o = pair(d)
+    assert p.get_tiles() == ["64x8", "64x4_512", "16x4", "8x4"]   # the shapes bench.py times
+    U0 = o.initial_state(pert)
+    # a state a few steps into the run: the bubble plus a seeded perturbation
+    U = U0 + W.random_state(o.ndof, 91, [1e-4, 1e-2, 1e-2, 3e-2])
+    return d, pert, p, o, U0, U
+
+
+def test_residual_full_size(dc):
+    d, _, p, o, _, U = dc
+    print("case full-size residual", flush=True)
+    for minv in (0, 1):
+        Lg = to_np(p.residual(to_dev(U), apply_minv=bool(minv)))
+        Lo = o.residual(U, minv)
+        sig = o.residual(U, 3)
+        if minv:
+            sig = sig / dg_mass(d)[None, :].repeat(4, 0).ravel()
+        tol = 1e-12 * max(np.linalg.norm(Lo), np.linalg.norm(sig))
+        err = np.linalg.norm(Lg - Lo)
+        print(f"  minv={minv} err={err:.3e} tol={tol:.3e} rel={err / np.linalg.norm(Lo):.3e}")
+        assert err <= tol
+
+
+def test_jvp_fv_matvec_and_preconditioner_full_size(dc):
+    d, _, p, o, _, U = dc
+    print("case full-size jvp / fv matvec / mg", flush=True)
+    adt = (1.0 - 2.0 ** -0.5) * d["dt"]   # the SDIRK2 stage alpha dt of the workload
+    p.linearize(to_dev(U), adt)
+    o.linearize(U, adt)
+    # JVP: the L_h bound through the difference quotient, as for the small cases
+    y = W.random_state(o.ndof, 92, [1e-3, 1.0, 1.0, 1.0])
+    jg = to_np(p.jvp(to_dev(y)))
+    jo = o.jvp(y)
+    ut, _ = node_total_norm(o, d, U)
+    eps = np.sqrt(EPS) * ut / np.linalg.norm(y)   # fd_eps_mode 1 of the workload
+    tol = 2 * (adt / eps) * (1.0 / dg_mass(d).min()) * 1e-12 * np.linalg.norm(o.residual(U, 3))
+    err = np.linalg.norm(jg - jo)
+    print(f"  jvp err {err:.3e} tol {tol:.3e} rel {err / np.linalg.norm(jo):.3e}")
+    assert err <= tol
+    # finest-level FV matvec (64x8 tiles): the FD bound of the tile-shape tests
+    x = W.random_state(o.fv_size(0), 93, [1e-3, 1.0, 1.0, 0.3])
+    ag = to_np(p.fv_matvec(0, to_dev(x)))
+    ao = o.fv_matvec(0, x)
+    nx, nz = o.fv_dims(0)
+    h = min((d["x1"] - d["x0"]) / nx, (d["z1"] - d["z0"]) / nz)
+    eps = np.sqrt(EPS) * fv_total_norm(o, d, 0, o.fv_level_state(0)) / np.linalg.norm(x)
+    tol = 2 * 64 * (adt / eps) * EPS * (4 * 1.1e5 / h) * np.sqrt(x.size)
+    err = np.linalg.norm(ag - ao)
+    print(f"  fv matvec err {err:.3e} tol {tol:.3e} rel {err / np.linalg.norm(ao):.3e}")
+    assert err <= tol
+    # one FV cycle and the whole preconditioner: 1e-6 relative
+    b = W.random_state(o.fv_size(0), 94, [1e-3, 1.0, 1.0, 0.3])
+    e1 = np.linalg.norm(to_np(p.mg_fv(to_dev(b))) - o.mg_fv(b)) / np.linalg.norm(o.mg_fv(b))
+    r = W.random_state(o.ndof, 95, [1e-3, 1.0, 1.0, 1.0])
+    zo = o.mg_apply(r)
+    e2 = np.linalg.norm(to_np(p.mg_apply(to_dev(r))) - zo) / np.linalg.norm(zo)
+    print(f"  mg_fv rel err {e1:.3e}, mg_apply rel err {e2:.3e}")
+    assert e1 <= 1e-6 and e2 <= 1e-6
+
+
+def test_implicit_step_full_size_properties(dc):
+    """One implicit-Euler step of the full-size problem (the same solver as the SDIRK2
+    stages): the oracle's G(U1) = U1 - dt f(U1) - U0 at the GPU's result is within the
+    Newton tolerance of G(U0) (plus the rounding floor of G, 1e-13 of its rounding scale),
+    and rho / rho theta mass is kept to round-off."""
+    d, pert, _, o, U0, _ = dc
+    print("case full-size implicit step", flush=True)
+    de = dict(d, scheme=0)
+    p = jfmg.Problem(de, device=DEV)
+    oe = oracle.Oracle(de)
+    U = to_dev(U0)
+    st = p.implicit_step(U)
+    U1 = to_np(U)
+    G0 = oe.stage_residual(U0, U0, d["dt"])
+    G1 = oe.stage_residual(U1, U0, d["dt"])
+    floor = 1e-13 * d["dt"] * np.linalg.norm(oe.residual(U1, 3) / dg_mass(d)[None, :].repeat(4, 0).ravel())
+    r = np.linalg.norm(G1) / np.linalg.norm(G0)
+    print(f"  newton {st['newton_its']} gmres {st['gmres_its']}: oracle ||G(U1)||/||G(U0)|| = {r:.3e} "
+          f"(rtol {d['newton_rtol']:.0e}, floor {floor / np.linalg.norm(G0):.1e})")
+    assert np.linalg.norm(G1) <= 2 * d["newton_rtol"] * np.linalg.norm(G0) + floor
+    m = dg_mass(d)
+    a, b = np.asarray(U0).reshape(4, -1), U1.reshape(4, -1)
+    for c in (0, 3):
+        drift = abs((m * (b[c] - a[c])).sum()) / (m * np.abs(b[c] - a[c])).sum()
+        print(f"  mass drift c={c}: {drift:.2e}")
+        assert drift < 1e-12
