@@ -112,3 +112,41 @@ def test_implicit_step_full_size_properties(dc):
         drift = abs((m * (b[c] - a[c])).sum()) / (m * np.abs(b[c] - a[c])).sum()
         print(f"  mass drift c={c}: {drift:.2e}")
         assert drift < 1e-12
+
+
+def test_inertia_gravity_full_size_fp32_multigrid():
+    """The inertia-gravity wave at its full size (600 x 20 quads, k = 3, 4 FV levels) with the
+    FP32 multigrid of its benchmark form: L_h against the oracle, the FP32 preconditioner
+    against the FP64 oracle's to the FP32 cycle's accuracy (FD step sqrt(2^-23) ||u||/||x||:
+    2e-3, as for the small FP32 cases), and a step through the oracle's stage residual (the
+    stage may end at the rounding floor of G, reading newton_stall)."""
+    d, pert, _ = W.inertia_gravity(mg_precision=32)
+    print("case full-size inertia-gravity fp32", flush=True)
+    p = jfmg.Problem(d, device=DEV)
+    o = oracle.Oracle(dict(d, mg_precision=64))
+    U0 = o.initial_state(pert)
+    U = U0 + W.random_state(o.ndof, 96, [1e-6, 1e-3, 1e-3, 3e-3])
+    Lg = to_np(p.residual(to_dev(U), apply_minv=True))
+    Lo = o.residual(U, 1)
+    sig = o.residual(U, 3) / dg_mass(d)[None, :].repeat(4, 0).ravel()
+    assert np.linalg.norm(Lg - Lo) <= 1e-12 * max(np.linalg.norm(Lo), np.linalg.norm(sig))
+    adt = (1.0 - 2.0 ** -0.5) * d["dt"]
+    p.linearize(to_dev(U), adt)
+    o.linearize(U, adt)
+    r = W.random_state(o.ndof, 97, [1e-3, 1.0, 1.0, 1.0])
+    zo = o.mg_apply(r)
+    e = np.linalg.norm(to_np(p.mg_apply(to_dev(r))) - zo) / np.linalg.norm(zo)
+    print(f"  fp32 mg_apply vs fp64 oracle: rel {e:.3e}")
+    assert e <= 2e-3
+    de = dict(d, scheme=0)
+    q = jfmg.Problem(de, device=DEV)
+    oe = oracle.Oracle(dict(de, mg_precision=64))
+    V = to_dev(U0)
+    st = q.implicit_step(V)
+    U1 = to_np(V)
+    G0 = np.linalg.norm(oe.stage_residual(U0, U0, d["dt"]))
+    G1 = np.linalg.norm(oe.stage_residual(U1, U0, d["dt"]))
+    bound = (d["newton_stall"] if st["stall_stops"] else 2 * d["newton_rtol"]) * G0
+    print(f"  newton {st['newton_its']} gmres {st['gmres_its']} stalls {st['stall_stops']}: "
+          f"||G(U1)||/||G(U0)|| = {G1 / G0:.3e}")
+    assert G1 <= bound
