@@ -150,3 +150,62 @@ def test_inertia_gravity_full_size_fp32_multigrid():
     print(f"  newton {st['newton_its']} gmres {st['gmres_its']} stalls {st['stall_stops']}: "
           f"||G(U1)||/||G(U0)|| = {G1 / G0:.3e}")
     assert G1 <= bound
+
+
+def test_largest_problem_residual():
+    """The largest problem bench.py runs (the HBM-resident roofline case: 1024 x 1024 quads,
+    k = 3, 16.8 M unknowns, 134 MB per DG vector): L_h and M^-1 L_h on the complete vectors."""
+    d0, pert, _ = W.density_current()
+    d = dict(d0, nx=1024, nz=1024, z1=25600.0, gmres_m=2)
+    print("case largest residual", flush=True)
+    p, o = pair(d)
+    U = o.initial_state(pert) + W.random_state(o.ndof, 98, [1e-4, 1e-2, 1e-2, 3e-2])
+    Ud = to_dev(U)
+    for minv in (0, 1):
+        Lg = to_np(p.residual(Ud, apply_minv=bool(minv)))
+        Lo = o.residual(U, minv)
+        assert np.all(np.isfinite(Lo))
+        sig = o.residual(U, 3)
+        if minv:
+            sig = sig / dg_mass(d)[None, :].repeat(4, 0).ravel()
+        err = np.linalg.norm(Lg - Lo)
+        print(f"  minv={minv} rel err {err / np.linalg.norm(Lo):.3e}")
+        assert err <= 1e-12 * max(np.linalg.norm(Lo), np.linalg.norm(sig))
+
+
+def test_deepest_hierarchy():
+    """The largest hierarchy, 8 FV levels (128 x 128 cells down to 1 x 1): the preconditioner
+    against the oracle's (1e-6, as for 3 levels)."""
+    d = W.small(nx=64, nz=64, k=1, mg_levels=8, physics=1, mu=75.0)
+    print("case 8 levels", flush=True)
+    p, o = pair(d)
+    U = W.random_state(o.ndof, 61, [1e-2, 0.3, 0.3, 3.0])
+    p.linearize(to_dev(U), 0.8)
+    o.linearize(U, 0.8)
+    r = W.random_state(o.ndof, 62, [1.0, 30.0, 30.0, 300.0])
+    zo = o.mg_apply(r)
+    err = np.linalg.norm(to_np(p.mg_apply(to_dev(r))) - zo) / np.linalg.norm(zo)
+    print(f"  rel err {err:.3e}")
+    assert err <= 1e-6
+
+
+def test_longest_restart_cycle():
+    """FGMRES(64), the largest restart length, without a preconditioner so that every linear
+    solve runs full 64-iteration cycles and restarts (about 100 iterations per Newton step):
+    an implicit-Euler step against the oracle's, with the same iteration counts."""
+    rtol = 1e-9
+    d = W.small(nx=8, nz=8, k=2, mg_levels=2, gmres_m=64, scheme=0, dt=0.5, newton_rtol=rtol, precond=0)
+    pert = dict(shape=0, amp=-3.0, xc=500.0, zc=500.0, xr=300.0, zr=300.0)
+    print("case FGMRES(64)", flush=True)
+    p, o = pair(d)
+    U0 = o.initial_state(pert)
+    rc, Uo, st_o = o.implicit_step(U0)
+    assert rc == 0
+    U = to_dev(U0)
+    st = p.implicit_step(U)
+    Ug = to_np(U)
+    diff, upd = np.linalg.norm(Ug - Uo), np.linalg.norm(Uo - U0)
+    print(f"  gpu {st['newton_its']}/{st['gmres_its']} oracle {st_o['newton_its']}/{st_o['gmres_its']} "
+          f"rel(update) {diff / upd:.3e}")
+    assert st["gmres_its"] > 2 * 64
+    assert diff <= 20 * rtol * upd
