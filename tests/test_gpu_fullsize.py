@@ -209,3 +209,21 @@ def test_longest_restart_cycle():
           f"rel(update) {diff / upd:.3e}")
     assert st["gmres_its"] > 2 * 64
     assert diff <= 20 * rtol * upd
+
+
+def test_explicit_steps_third_order_full_size(dc):
+    """The GPU's SSP RK(4,3) at the density-current size converges at third order in dt
+    (against a 32x finer run of the same kernels), a property that holds at any size."""
+    d, pert, p, o, U0, _ = dc
+    print("case full-size explicit order", flush=True)
+    T = 0.4   # dt from 0.025 s, inside the stability limit (about 0.04 s at this resolution)
+    ref = to_dev(U0)
+    p.explicit_steps(ref, T / 1024, 1024)
+    errs = []
+    for n in (16, 32, 64):
+        U = to_dev(U0)
+        p.explicit_steps(U, T / n, n)
+        errs.append(torch.linalg.norm(U - ref).item())
+    orders = [np.log2(errs[0] / errs[1]), np.log2(errs[1] / errs[2])]
+    print(f"  errors {errs}, observed orders {orders}")
+    assert all(abs(r - 3.0) < 0.3 for r in orders)
