@@ -227,3 +227,27 @@ def test_explicit_steps_third_order_full_size(dc):
     orders = [np.log2(errs[0] / errs[1]), np.log2(errs[1] / errs[2])]
     print(f"  errors {errs}, observed orders {orders}")
     assert all(abs(r - 3.0) < 0.3 for r in orders)
+
+
+def test_well_balanced_and_dg_smoothing_full_size(dc):
+    """At the density-current size: the hydrostatic rest state gives L_h = 0 bitwise without
+    viscosity and to round-off with it; the preconditioner with DG-level smoothing
+    (mg112222V, the one-stage smoother at c*_DG = 0.1) matches the oracle's (1e-6)."""
+    d, pert, _, o, U0, U = dc
+    print("case full-size well-balancing and DG smoothing", flush=True)
+    pe = jfmg.Problem(dict(d, physics=0, mu=0.0), device=DEV)
+    assert torch.count_nonzero(pe.residual(pe.dg_zeros())).item() == 0
+    pn = jfmg.Problem(d, device=DEV)
+    Ln = to_np(pn.residual(pn.dg_zeros()))
+    assert np.linalg.norm(Ln) <= 1e-12 * np.linalg.norm(o.residual(np.zeros(o.ndof), 3))
+    ds = dict(d, mg_key="mg112222V", pseudo_cfl_dg=0.1)
+    ps, os_ = pair(ds)
+    adt = (1.0 - 2.0 ** -0.5) * d["dt"]
+    ps.linearize(to_dev(U), adt)
+    os_.linearize(U, adt)
+    assert abs(ps.dg_dtau() - os_.dg_dtau()) <= 1e-13 * os_.dg_dtau()
+    r = W.random_state(os_.ndof, 99, [1e-3, 1.0, 1.0, 1.0])
+    zo = os_.mg_apply(r)
+    err = np.linalg.norm(to_np(ps.mg_apply(to_dev(r))) - zo) / np.linalg.norm(zo)
+    print(f"  DG-smoothing mg_apply rel err {err:.3e}")
+    assert err <= 1e-6
