@@ -205,8 +205,9 @@ jfmg_status jfmg_prolong(jfmg_problem* p, int coarse_level, const void* coarse, 
 jfmg_status jfmg_fv_level_state(jfmg_problem* p, int level, void* u);
 /* Pseudo time step of `level` (host double; synchronizes). */
 jfmg_status jfmg_fv_dtau(jfmg_problem* p, int level, double* dtau);
-/* Pseudo time step of the DG-level smoother (see pseudo_cfl_dg; host double;
-   synchronizes).  ESTATE without jfmg_linearize; EINVAL when a = b = 0. */
+/* Pseudo time step of the DG-level smoother (Sec. "Smoother / Pseudo time
+   iteration"; formula at pseudo_cfl_dg; host double; synchronizes).  ESTATE
+   without jfmg_linearize; EINVAL when a = b = 0. */
 jfmg_status jfmg_dg_dtau(jfmg_problem* p, double* dtau);
 /* out = g'_l(u_l) x = x - (alpha dt/eps)(f_low(u_l + eps x) - f_low(u_l)),
    eps = sqrt(eps_p) ||u_l + Ubar|| / ||x||. */
