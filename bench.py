@@ -477,7 +477,9 @@ def main():
     # other preconditioner configurations of the same workload (same rtol, same steps)
     for name, kw in () if a.no_forms else (("fp64_mg_3stage_smoother", dict(rk_stages=3)),
                      ("fp64_mg111111V_dg_smoothing", dict(mg_key="mg111111V", pseudo_cfl_dg=0.3)),
-                     ("fp64_mg112222V_dg_smoothing", dict(mg_key="mg112222V", pseudo_cfl_dg=0.1))):
+                     ("fp64_mg112222V_dg_smoothing", dict(mg_key="mg112222V", pseudo_cfl_dg=0.1)),
+                     ("fp64_mg_l2_projection_transfer", dict(transfer=1)),
+                     ("fp64_mg_interpolation_without_mass_fix", dict(mass_fix=0))):
         try:
             _, elv, latv, itsv, _ = run_form(dict(d, **kw), pert, a.steps, a.warmup, [])
         except Exception as ex:   # a configuration that does not converge is reported, not fatal
