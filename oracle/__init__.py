@@ -96,6 +96,8 @@ def lib():
         L.orc_dg_dtau.restype = C.c_double
         L.orc_dg_dtau.argtypes = [C.c_void_p]
         L.orc_fv_matvec.argtypes = [C.c_void_p, C.c_int, dp, dp]
+        L.orc_counters.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                   C.c_int]
         L.orc_jvp.argtypes = [C.c_void_p, dp, dp]
         L.orc_mg_fv.argtypes = [C.c_void_p, dp, dp]
         L.orc_mg_apply.argtypes = [C.c_void_p, dp, dp]
@@ -303,6 +305,14 @@ class Oracle:
     def dg_dtau(self):
         """Pseudo time step of the DG-level smoother (key counts a, b)."""
         return self.L.orc_dg_dtau(self.h)
+
+    def counters(self, reset=False):
+        """Operation counts since creation or the last reset: FV matvecs per level,
+        DG JVPs and L_h calls (instrumentation; no arithmetic)."""
+        mv = (C.c_int * 8)()
+        j, lh = C.c_int(), C.c_int()
+        self.L.orc_counters(self.h, mv, C.byref(j), C.byref(lh), int(bool(reset)))
+        return {"fv_matvecs": list(mv), "jvps": j.value, "lh_evals": lh.value}
 
     def fv_matvec(self, level, x):
         x = np.ascontiguousarray(x, dtype=np.float64)

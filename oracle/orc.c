@@ -926,6 +926,19 @@ double orc_fv_dtau(const orc_ctx* X, int l) { return X->dtau[l]; }
 
 double orc_dg_dtau(const orc_ctx* X) { return X->dtau_dg; }
 
+/* Operation counts since the context was created or last reset (instrumentation
+   for the tests, no arithmetic): FV matvecs per level, DG JVPs, L_h calls. */
+void orc_counters(orc_ctx* X, int* fv_matvecs, int* jvps, int* lh_evals, int reset)
+{
+    for (int l = 0; l < MAXLEV; ++l) {
+        if (fv_matvecs) fv_matvecs[l] = X->mv_local[l];
+        if (reset) X->mv_local[l] = 0;
+    }
+    if (jvps) *jvps = X->jvp_count;
+    if (lh_evals) *lh_evals = X->lh_count;
+    if (reset) { X->jvp_count = 0; X->lh_count = 0; }
+}
+
 /* FV Jacobian-free matvec g'_l(u) x = x - (alpha dt / eps)(f_low(u + eps x) - f_low(u)),
    eps = sqrt(eps_mach) ||u + Ubar||_2 / ||x||_2; x = 0 gives 0. */
 void orc_fv_matvec(orc_ctx* X, int l, const double* x, double* out)

@@ -96,6 +96,9 @@ int  orc_linearize(orc_ctx* X, const double* U, double alpha_dt);
 void orc_fv_level_state(const orc_ctx* X, int level, double* u);
 double orc_fv_dtau(const orc_ctx* X, int level);
 double orc_dg_dtau(const orc_ctx* X);
+/* operation counts (FV matvecs per level, JVPs, L_h calls) since creation or the
+   last call with reset = 1; test instrumentation */
+void orc_counters(orc_ctx* X, int* fv_matvecs, int* jvps, int* lh_evals, int reset);
 void orc_fv_matvec(orc_ctx* X, int level, const double* x, double* out);
 void orc_jvp(orc_ctx* X, const double* y, double* out);
 void orc_mg_fv(orc_ctx* X, const double* b, double* x);
