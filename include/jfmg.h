@@ -338,6 +338,33 @@ jfmg_status jfmg_batch_retire(jfmg_batch* b, int slot);
 size_t jfmg_batch_arena_free(jfmg_batch* b);
 const char* jfmg_batch_last_error(const jfmg_batch* b);
 
+/* ---- allocation-free stage residual ----
+   For callers that cannot allocate device memory: code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+   G = U - alpha_dt f(U) - Ubar as jfmg_stage_residual, for the single problem
+   described by cfg, without a problem handle or a workspace: the background
+   tables of the DG kernel and the block partials of the norm live in a
+   file-scope device array of JFMG_NOALLOC_SCRATCH_BYTES (1 MiB) per GPU, held
+   until the process ends.  U, Ubar, G: caller-owned device DG vectors of
+   N = 4 nx nz (k+1)^2 doubles (layout as everywhere above); norm2: NULL or a
+   caller-owned device double that receives ||G||_2^2.  Stream ordered on
+   hip_stream (NULL = default stream); no host synchronization, no device
+   memory allocation (the first call on a device resolves the array's address
+   once).  Errors: EINVAL for a null vector, an invalid configuration, batch > 1
+   or a non-finite alpha_dt; ENOMEM when the tables and partials of the problem
+   exceed the array (tables of 88 bytes per node row, nz (k+1) rows, and 80 per
+   element face row, nz + 1 rows, plus 8 bytes per DG work-group of 8 to 16
+   elements, each region 256-byte aligned: every configuration with
+   nz (k+1) <= 2048 and nx nz <= 65536 fits);
+   EDEVICE for a HIP error.  Messages through jfmg_last_error(NULL).  Every call
+   on one GPU uses that GPU's array: calls that overlap on one GPU (different
+   streams or threads) race on it and must be serialized by the caller.  The
+   background tables are evaluated on the device, so G agrees with
+   jfmg_stage_residual to rounding, not bitwise. */
+#define JFMG_NOALLOC_SCRATCH_BYTES ((size_t)1 << 20)
+jfmg_status jfmg_stage_residual_noalloc(const jfmg_config* cfg, const double* U, const double* Ubar,
+                                        double alpha_dt, double* G, double* norm2, void* hip_stream);
+
 /* Message of the last failed call on p (or of the last failed creation if p is NULL). */
 const char* jfmg_last_error(const jfmg_problem* p);
 

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libjfmg.so")
-SOURCES = ["dg.hip", "transfer.hip", "fv.hip", "la.hip", "driver.hip", "batch.hip"]
+SOURCES = ["dg.hip", "transfer.hip", "fv.hip", "la.hip", "driver.hip", "batch.hip", "noalloc.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -145,7 +145,7 @@ void lagrange_coefs(int n, const double* x, int j, double* coef)
 // transfer 0: the subcell-centre values of the nodal polynomial (V) and the inverse
 // map; transfer 1: its subcell averages (L2 projection onto the subcells), in 1D
 // P_ia = (1/h) int over [s_i, s_i + h] of l_a, h = 2/(k+1), integrated term by term.
-bool build_reftab(int k, int transfer, RefTab& R)
+bool reftab(int k, int transfer, RefTab& R)
 {
     const int n = k + 1;
     std::memset(&R, 0, sizeof(R));
@@ -207,49 +207,6 @@ bool build_reftab(int k, int transfer, RefTab& R)
         R.wnc[i] = integ;
     }
     return true;
-}
-
-// ---------------------------------------------------------------------------
-// Background atmospheres (paper test cases): neutral theta = theta0 with
-// T = theta0 - g z / cp, p = p0 (T/theta0)^(cp/R); or constant N with
-// theta = T0 e^{z/H}, T = T0 (a - (a-1) e^{z/H}), p = p0 exp(cp/R (ln(T/T0) - z/H)),
-// H = g/N^2, a = g H/(cp T0), T0 = theta0.  rho theta = p0^{R/cp} p^{1/gamma}/R.
-// ---------------------------------------------------------------------------
-struct BgPoint {
-    double U[4], dU[4], theta;
-};
-
-BgPoint background_at(const jfmg_config& c, double z)
-{
-    const double cp = c.gamma * c.R / (c.gamma - 1.0);
-    double th, dth, p, dp;
-    if (c.background == 0) {
-        th = c.theta0;
-        dth = 0.0;
-        const double T = c.theta0 - c.g * z / cp;
-        p = c.p0 * std::pow(T / c.theta0, cp / c.R);
-        dp = -(c.g * c.p0 / (c.R * c.theta0)) * std::pow(T / c.theta0, cp / c.R - 1.0);
-    } else {
-        const double H = c.g / (c.N * c.N);
-        const double a = c.g * H / (cp * c.theta0);
-        const double ez = std::exp(z / H);
-        th = c.theta0 * ez;
-        dth = th / H;
-        const double T = c.theta0 * (a - (a - 1.0) * ez);
-        const double dT = -c.theta0 * (a - 1.0) * ez / H;
-        p = c.p0 * std::exp((cp / c.R) * (std::log(T / c.theta0) - z / H));
-        dp = p * (cp / c.R) * (dT / T - 1.0 / H);
-    }
-    const double C = std::pow(c.p0, c.R / cp) / c.R;
-    const double rt = C * std::pow(p, 1.0 / c.gamma);
-    const double drt = C * (1.0 / c.gamma) * std::pow(p, 1.0 / c.gamma - 1.0) * dp;
-    const double rho = rt / th;
-    const double drho = (drt - rho * dth) / th;
-    BgPoint b;
-    b.U[0] = rho; b.U[1] = rho * c.u_mean; b.U[2] = 0.0; b.U[3] = rt;
-    b.dU[0] = drho; b.dU[1] = drho * c.u_mean; b.dU[2] = 0.0; b.dU[3] = drt;
-    b.theta = th;
-    return b;
 }
 
 struct Key {
@@ -588,7 +545,25 @@ template <typename T> Gas<T> make_gas(const jfmg_config& c)
 }
 
 // background pressure p0 (R rho_theta / p0)^gamma of the potential-temperature equation of state
-double bg_pressure(const jfmg_config& c, double rt) { return c.p0 * std::pow(c.R * rt / c.p0, c.gamma); }
+
+}  // namespace
+
+bool jfmg::build_reftab(int k, int transfer, RefTab& R) { return reftab(k, transfer, R); }
+
+jfmg_status jfmg::check_config(const jfmg_config& c, const char** msg)
+{
+    thread_local std::string m;
+    Key key;
+    const jfmg_status s = validate(c, key, m);
+    if (msg) *msg = m.c_str();
+    return s;
+}
+
+Gas<double> jfmg::gas_of(const jfmg_config& c) { return make_gas<double>(c); }
+
+void jfmg::set_create_error(const std::string& msg) { g_create_error = msg; }
+
+namespace {
 
 template <typename T> FvArgs<T> fv_args(const jfmg_problem* p, int l)
 {
@@ -1382,7 +1357,7 @@ jfmg_status jfmg_create_problem(const jfmg_config* cfg, void* workspace, size_t 
         const char* g = std::getenv("JFMG_GRAPH");
         p->use_graphs = g && g[0] == '1';
     }
-    if (!build_reftab(cfg->k, cfg->transfer, p->R)) {
+    if (!reftab(cfg->k, cfg->transfer, p->R)) {
         delete p;
         return fail(nullptr, JFMG_EINVAL, "singular subcell transfer");
     }

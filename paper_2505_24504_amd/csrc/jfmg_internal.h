@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <string>
 
 #include "jfmg.h"
 #include "jfmg_dev.h"
@@ -40,6 +41,66 @@ struct RefTab {
     double xi[MAXN1], w[MAXN1], D[MAXN1][MAXN1], em[MAXN1], ep[MAXN1], dm[MAXN1], dp[MAXN1];
     double V[MAXN1][MAXN1], Vinv[MAXN1][MAXN1], wnc[MAXN1];
 };
+
+// ---------------------------------------------------------------------------
+// Background atmospheres (paper test cases): neutral theta = theta0 with
+// T = theta0 - g z / cp, p = p0 (T/theta0)^(cp/R); or constant N with
+// theta = T0 e^{z/H}, T = T0 (a - (a-1) e^{z/H}), p = p0 exp(cp/R (ln(T/T0) - z/H)),
+// H = g/N^2, a = g H/(cp T0), T0 = theta0.  rho theta = p0^{R/cp} p^{1/gamma}/R.
+// Host code builds the problem tables with it; the allocation-free residual
+// evaluates the same formula on the device.
+// ---------------------------------------------------------------------------
+struct BgPoint {
+    double U[4], dU[4], theta;
+};
+
+__host__ __device__ inline BgPoint background_at(const jfmg_config& c, double z)
+{
+    const double cp = c.gamma * c.R / (c.gamma - 1.0);
+    double th, dth, p, dp;
+    if (c.background == 0) {
+        th = c.theta0;
+        dth = 0.0;
+        const double T = c.theta0 - c.g * z / cp;
+        p = c.p0 * ::pow(T / c.theta0, cp / c.R);
+        dp = -(c.g * c.p0 / (c.R * c.theta0)) * ::pow(T / c.theta0, cp / c.R - 1.0);
+    } else {
+        const double H = c.g / (c.N * c.N);
+        const double a = c.g * H / (cp * c.theta0);
+        const double ez = ::exp(z / H);
+        th = c.theta0 * ez;
+        dth = th / H;
+        const double T = c.theta0 * (a - (a - 1.0) * ez);
+        const double dT = -c.theta0 * (a - 1.0) * ez / H;
+        p = c.p0 * ::exp((cp / c.R) * (::log(T / c.theta0) - z / H));
+        dp = p * (cp / c.R) * (dT / T - 1.0 / H);
+    }
+    const double C = ::pow(c.p0, c.R / cp) / c.R;
+    const double rt = C * ::pow(p, 1.0 / c.gamma);
+    const double drt = C * (1.0 / c.gamma) * ::pow(p, 1.0 / c.gamma - 1.0) * dp;
+    const double rho = rt / th;
+    const double drho = (drt - rho * dth) / th;
+    BgPoint b;
+    b.U[0] = rho; b.U[1] = rho * c.u_mean; b.U[2] = 0.0; b.U[3] = rt;
+    b.dU[0] = drho; b.dU[1] = drho * c.u_mean; b.dU[2] = 0.0; b.dU[3] = drt;
+    b.theta = th;
+    return b;
+}
+
+// background pressure p0 (R rho_theta / p0)^gamma of the potential-temperature equation of state
+__host__ __device__ inline double bg_pressure(const jfmg_config& c, double rt)
+{
+    return c.p0 * ::pow(c.R * rt / c.p0, c.gamma);
+}
+
+// Host helpers of the driver used by other translation units: the reference
+// element tables, the configuration check (EINVAL with a message) and the gas
+// constants of the DG kernels.
+bool build_reftab(int k, int transfer, RefTab& R);
+jfmg_status check_config(const jfmg_config& c, const char** msg);
+Gas<double> gas_of(const jfmg_config& c);
+// message returned by jfmg_last_error(NULL) for calls without a problem
+void set_create_error(const std::string& msg);
 
 // Everything a DG kernel needs about the grid, the gas and the background.
 struct DgArgs {

@@ -66,6 +66,7 @@ EXPORTS = [
     "jfmg_batch_create", "jfmg_batch_destroy", "jfmg_batch_admit", "jfmg_batch_member", "jfmg_batch_run",
     "jfmg_batch_start", "jfmg_batch_stop", "jfmg_batch_wait_any", "jfmg_batch_poll", "jfmg_batch_retire",
     "jfmg_batch_arena_free", "jfmg_batch_last_error", "jfmg_get_tiles", "jfmg_set_tiles", "jfmg_autotune",
+    "jfmg_stage_residual_noalloc",
 ]
 
 # FV operator tile shapes (jfmg_tile), by index
@@ -127,6 +128,7 @@ def load_library(path: str = LIB_PATH):
         "jfmg_get_tiles": (C.c_int, [vp, ip]),
         "jfmg_set_tiles": (C.c_int, [vp, ip]),
         "jfmg_autotune": (C.c_int, [vp, C.c_int, ip, dp]),
+        "jfmg_stage_residual_noalloc": (C.c_int, [C.POINTER(Config), vp, vp, C.c_double, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -359,6 +361,24 @@ class Problem:
         self._check(self.L.jfmg_autotune(self.h, int(reps), a, t))
         times = {l: {TILES[s]: t[l * len(TILES) + s] for s in range(len(TILES))} for l in range(n)}
         return [TILES[a[i]] for i in range(n)], times
+
+
+def stage_residual_noalloc(d: dict, U, Ubar, alpha_dt, G=None, norm2=None, stream=None):
+    """jfmg_stage_residual_noalloc: G = U - alpha_dt f(U) - Ubar and ||G||^2 into the
+    device tensors G and norm2 (one FP64 entry), without a problem or a workspace;
+    returns (G, norm2).  Stream ordered on `stream` (default: torch's current one)."""
+    L = load_library()
+    cfg = make_config(d)
+    if G is None:
+        G = torch.empty_like(U)
+    if norm2 is None:
+        norm2 = torch.empty(1, dtype=torch.float64, device=U.device)
+    st = stream if stream is not None else torch.cuda.current_stream(U.device)
+    rc = L.jfmg_stage_residual_noalloc(C.byref(cfg), _ptr(U), _ptr(Ubar), float(alpha_dt), _ptr(G), _ptr(norm2),
+                                       C.c_void_p(st.cuda_stream))
+    if rc:
+        raise JfmgError(rc, L.jfmg_last_error(None).decode())
+    return G, norm2
 
 
 def num_dofs(d: dict) -> int:

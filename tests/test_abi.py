@@ -97,3 +97,22 @@ def test_create_rejects_small_workspace(lib):
     rc = lib.jfmg_create_problem(C.byref(cfg), C.c_void_p(256), 16, None, C.byref(h))
     assert rc == jfmg.ENOMEM
     assert b"workspace" in lib.jfmg_last_error(None)
+
+
+def test_noalloc_residual_rejects_bad_arguments_before_device_work(lib):
+    """The allocation-free residual checks its arguments and the size of the static
+    scratch before it touches the device: null vectors and invalid configurations are
+    EINVAL, a problem whose tables and partials exceed the array is ENOMEM."""
+    d, _, _ = W.bubble_small()
+    fake = C.c_void_p(256)   # never dereferenced: every case fails its host checks first
+    cfg = jfmg.make_config(d)
+    assert lib.jfmg_stage_residual_noalloc(C.byref(cfg), None, fake, 1.0, fake, None, None) == jfmg.EINVAL
+    bad = jfmg.make_config(dict(d, k=5))
+    assert lib.jfmg_stage_residual_noalloc(C.byref(bad), fake, fake, 1.0, fake, None, None) == jfmg.EINVAL
+    assert b"k must" in lib.jfmg_last_error(None)
+    batched = jfmg.make_config(dict(d, batch=2))
+    assert lib.jfmg_stage_residual_noalloc(C.byref(batched), fake, fake, 1.0, fake, None, None) == jfmg.EINVAL
+    assert lib.jfmg_stage_residual_noalloc(C.byref(cfg), fake, fake, float("nan"), fake, None, None) == jfmg.EINVAL
+    big = jfmg.make_config(dict(d, nx=1024, nz=1024, k=3, mg_levels=1))   # 131072 partials: 1 MiB alone
+    assert lib.jfmg_stage_residual_noalloc(C.byref(big), fake, fake, 1.0, fake, None, None) == jfmg.ENOMEM
+    assert b"static scratch" in lib.jfmg_last_error(None)
