@@ -180,6 +180,16 @@ jfmg_status jfmg_mg_apply(jfmg_problem* p, const double* r, double* z);
    once as a HIP graph and replayed instead (bitwise the same results). */
 jfmg_status jfmg_implicit_step(jfmg_problem* p, double* U, jfmg_stats* stats);
 
+/* One stage equation G(U) = U - alpha_dt f(U) - Ubar = 0 (eq. newton) solved
+   as inside jfmg_implicit_step: inexact Newton from U^0 = Ubar with
+   Eisenstat-Walker forcing and preconditioned FGMRES (Sec. "Solver").  Ubar
+   (read) and U (written with the solution) are device DG vectors; U is left
+   unchanged on any error.  Host-synchronous.  SDIRK2 is the stage with
+   alpha_dt = (1 - sqrt(2)/2) dt and Ubar = U^n, then the stage with the same
+   alpha_dt and Ubar = U^n + (sqrt(2)/2) dt f(U_1) (eq. ellsiep).  EINVAL for a
+   batched problem or alpha_dt not positive and finite. */
+jfmg_status jfmg_newton_stage(jfmg_problem* p, const double* Ubar, double alpha_dt, double* U, jfmg_stats* stats);
+
 /* nsteps explicit steps U^n -> U^{n+1} in place with the four-stage,
    third-order strong-stability-preserving Runge-Kutta method (Ketcheson 2008)
    that the paper's reference runs use (Sec. "Numerical Experiments", set-up):

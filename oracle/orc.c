@@ -2,9 +2,12 @@
  * Oracle for the Jacobian-free Newton-GMRES solver with the FV-subgrid
  * multigrid preconditioner of Birken, Dedner & Kloefkorn (arXiv 2505.24504).
  *
- * TEST INFRASTRUCTURE ONLY: plain, slow, single-threaded FP64 C written from
- * the paper, used by the tests, the smoke check and the CPU-baseline leg of
- * the benchmark.  It shares no code with the GPU library.
+ * TEST INFRASTRUCTURE ONLY: plain, slow FP64 C written from the paper, used by
+ * the tests, the smoke check and the CPU-baseline leg of the benchmark.  It
+ * shares no code with the GPU library.  The element loop of L_h and the cell
+ * loop of f_low run on all host cores (OpenMP; every element's and cell's
+ * arithmetic is the serial one, so results do not depend on the thread count);
+ * everything else is serial.
  *
  * Where the paper leaves a choice open the oracle takes the readings listed in
  * the project's design notes; each function below names the passage it
@@ -452,9 +455,12 @@ static void dg_residual_mode(orc_ctx* X, const double* U, double* L, int wb, int
     const int ns = (c->physics == 1);
     const double dx = X->dx, dz = X->dz, J = X->J;
     X->lh_count++;
-    double Fx[4][MAXN * MAXN], Fz[4][MAXN * MAXN], Ue[4][MAXN * MAXN], Un[4][MAXN * MAXN];
+    /* elements are independent (each writes only its own nodes): spread over the host
+       cores, the arithmetic of every element unchanged */
+#pragma omp parallel for collapse(2) schedule(static)
     for (int ez = 0; ez < c->nz; ++ez)
         for (int ex = 0; ex < c->nx; ++ex) {
+            double Fx[4][MAXN * MAXN], Fz[4][MAXN * MAXN], Ue[4][MAXN * MAXN], Un[4][MAXN * MAXN];
             long e = (long)ez * c->nx + ex;
             for (int cc = 0; cc < 4; ++cc)
                 for (int i = 0; i < np; ++i) Ue[cc][i] = U[UIDX(X, cc, e, i)];
@@ -786,6 +792,8 @@ void orc_fv_residual(const orc_ctx* X, int l, const double* u, double* f)
     int nxl = X->nxl[l], nzl = X->nzl[l];
     long nc = (long)nxl * nzl;
     double hx = X->hx[l], hz = X->hz[l], area = hx * hz;
+    /* cells are independent (each writes only its own values) */
+#pragma omp parallel for collapse(2) schedule(static)
     for (int J = 0; J < nzl; ++J)
         for (int I = 0; I < nxl; ++I) {
             long q = (long)J * nxl + I;
@@ -950,8 +958,10 @@ void orc_fv_matvec(orc_ctx* X, int l, const double* x, double* out)
     double eps = sqrt(DBL_EPSILON) * X->utot[l] / xn;
     double* up = (double*)malloc(sizeof(double) * n);
     double* fp = (double*)malloc(sizeof(double) * n);
+    #pragma omp parallel for schedule(static)
     for (long i = 0; i < n; ++i) up[i] = X->ulev[l][i] + eps * x[i];
     orc_fv_residual(X, l, up, fp);
+    #pragma omp parallel for schedule(static)
     for (long i = 0; i < n; ++i) out[i] = x[i] - (X->adt / eps) * (fp[i] - X->flev[l][i]);
     free(up);
     free(fp);
@@ -969,10 +979,13 @@ void orc_jvp(orc_ctx* X, const double* y, double* out)
     double eps = X->c.fd_eps_mode == 0 ? sqrt(DBL_EPSILON) / yn : sqrt(DBL_EPSILON) * X->utot_dg / yn;
     double* Up = (double*)malloc(sizeof(double) * n);
     double* Lp = (double*)malloc(sizeof(double) * n);
+    #pragma omp parallel for schedule(static)
     for (long i = 0; i < n; ++i) Up[i] = X->Ulin[i] + eps * y[i];
     dg_residual(X, Up, Lp, 1);
+    #pragma omp parallel for schedule(static)
     for (long i = 0; i < n; ++i) Lp[i] -= X->Llin[i];
     apply_minv(X, Lp);
+    #pragma omp parallel for schedule(static)
     for (long i = 0; i < n; ++i) out[i] = y[i] - (X->adt / eps) * Lp[i];
     free(Up);
     free(Lp);
@@ -1000,6 +1013,7 @@ static void smooth(orc_ctx* X, int l, double* x, const double* b, int nu, int* x
             if (j == 0 && *xzero) memset(Ax, 0, sizeof(double) * n);
             else orc_fv_matvec(X, l, xp, Ax);
             double s = X->c.rk_alpha[j] * X->dtau[l];
+            #pragma omp parallel for schedule(static)
             for (long i = 0; i < n; ++i) xp[i] = x0[i] + s * (b[i] - Ax[i]);
         }
         memcpy(x, xp, sizeof(double) * n);
@@ -1154,11 +1168,13 @@ int orc_fgmres(long n, orc_op A, void* actx, orc_op P, void* pctx, const double*
             for (int i = 0; i <= j; ++i) {
                 double h = dot(n, w, V + (long)i * n);
                 H[i * m + j] = h;
+                #pragma omp parallel for schedule(static)
                 for (long t = 0; t < n; ++t) w[t] -= h * V[(long)i * n + t];
             }
             double hn = norm2(n, w);
             H[(j + 1) * m + j] = hn;
             if (hn != 0.0)
+                #pragma omp parallel for schedule(static)
                 for (long t = 0; t < n; ++t) V[(long)(j + 1) * n + t] = w[t] / hn;
             for (int i = 0; i < j; ++i) {
                 double a = H[i * m + j], b = H[(i + 1) * m + j];
@@ -1184,6 +1200,7 @@ int orc_fgmres(long n, orc_op A, void* actx, orc_op P, void* pctx, const double*
             y[i] = s / H[i * m + i];
         }
         for (int i = 0; i < jend; ++i)
+            #pragma omp parallel for schedule(static)
             for (long t = 0; t < n; ++t) x[t] += y[i] * Z[(long)i * n + t];
         if (conv) { status = ORC_OK; break; }
         A(actx, x, w);

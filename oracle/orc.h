@@ -3,8 +3,9 @@
  * Birken, Dedner & Kloefkorn, "A Jacobian-free Multigrid Preconditioner for
  * Discontinuous Galerkin Methods applied to Numerical Weather Prediction".
  *
- * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, single-threaded FP64
- * reference written from the paper.  Only the test suite, the smoke check and
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow FP64 reference written
+ * from the paper (OpenMP over the element and cell loops, results independent
+ * of the thread count).  Only the test suite, the smoke check and
  * the CPU-baseline leg of the benchmark may load it.  It shares no code with
  * the GPU library and the GPU library never calls it.
  *

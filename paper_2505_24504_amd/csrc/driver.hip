@@ -1650,6 +1650,45 @@ jfmg_status jfmg_implicit_step(jfmg_problem* p, double* U, jfmg_stats* stats)
     return s;
 }
 
+jfmg_status jfmg_newton_stage(jfmg_problem* p, const double* Ubar, double alpha_dt, double* U, jfmg_stats* stats)
+{
+    if (!p || !Ubar || !U) return fail(p, JFMG_EINVAL, "null argument");
+    if (p->mb.n > 1) return fail(p, JFMG_EINVAL, "a batched problem supports jfmg_implicit_step, jfmg_initial_state, jfmg_linearize and the tile calls");
+    if (!(alpha_dt > 0.0) || !std::isfinite(alpha_dt)) return fail(p, JFMG_EINVAL, "alpha_dt must be positive and finite");
+    hipError_t e = hipStreamSynchronize(p->user_st);
+    if (e) return fail(p, JFMG_EDEVICE, hipGetErrorString(e));
+    p->st = p->cs;
+    const auto t0 = std::chrono::steady_clock::now();
+    jfmg_stats st;
+    std::memset(&st, 0, sizeof(st));
+    std::memset(p->mv_count, 0, sizeof(p->mv_count));
+    p->lh_count = 0;
+    p->jvp_count = 0;
+    p->syncs = 0;
+    const size_t vb = sizeof(double) * p->N;
+    jfmg_status s = JFMG_OK;
+    e = hipMemcpyAsync(p->Ubar, Ubar, vb, hipMemcpyDeviceToDevice, p->st);
+    if (e) s = fail(p, JFMG_EDEVICE, hipGetErrorString(e));
+    if (s == JFMG_OK) s = newton_stage(p, p->Ubar, alpha_dt, &st);
+    if (s == JFMG_OK) {
+        e = hipMemcpyAsync(U, p->Uk, vb, hipMemcpyDeviceToDevice, p->st);
+        if (!e) e = hipStreamSynchronize(p->st);
+        if (e) s = fail(p, JFMG_EDEVICE, hipGetErrorString(e));
+    } else {
+        (void)hipStreamSynchronize(p->st);
+    }
+    prof_flush(p);
+    p->st = p->user_st;
+    st.status = s;
+    st.lh_evals = p->lh_count;
+    st.jvps = p->jvp_count;
+    st.host_syncs = p->syncs;
+    for (int l = 0; l < MAXLEV; ++l) st.fv_matvecs[l] = p->mv_count[l];
+    st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) *stats = st;
+    return s;
+}
+
 jfmg_status jfmg_explicit_steps(jfmg_problem* p, double* U, double dt, int nsteps)
 {
     if (!p || !U) return fail(p, JFMG_EINVAL, "null argument");

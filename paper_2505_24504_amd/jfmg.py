@@ -66,7 +66,7 @@ EXPORTS = [
     "jfmg_batch_create", "jfmg_batch_destroy", "jfmg_batch_admit", "jfmg_batch_member", "jfmg_batch_run",
     "jfmg_batch_start", "jfmg_batch_stop", "jfmg_batch_wait_any", "jfmg_batch_poll", "jfmg_batch_retire",
     "jfmg_batch_arena_free", "jfmg_batch_last_error", "jfmg_get_tiles", "jfmg_set_tiles", "jfmg_autotune",
-    "jfmg_stage_residual_noalloc",
+    "jfmg_stage_residual_noalloc", "jfmg_newton_stage",
 ]
 
 # FV operator tile shapes (jfmg_tile), by index
@@ -129,6 +129,7 @@ def load_library(path: str = LIB_PATH):
         "jfmg_set_tiles": (C.c_int, [vp, ip]),
         "jfmg_autotune": (C.c_int, [vp, C.c_int, ip, dp]),
         "jfmg_stage_residual_noalloc": (C.c_int, [C.POINTER(Config), vp, vp, C.c_double, vp, vp, vp]),
+        "jfmg_newton_stage": (C.c_int, [vp, vp, C.c_double, vp, C.POINTER(Stats)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -271,6 +272,17 @@ class Problem:
         if rc and raise_on_error:
             self._check(rc)
         return d
+
+    def newton_stage(self, Ubar, alpha_dt, raise_on_error=True):
+        """Solve the stage equation U - alpha_dt f(U) - Ubar = 0; returns (U, stats)."""
+        U = self.dg_zeros()
+        st = Stats()
+        rc = self.L.jfmg_newton_stage(self.h, _ptr(Ubar), float(alpha_dt), _ptr(U), C.byref(st))
+        d = st.as_dict()
+        d["status"] = rc
+        if rc and raise_on_error:
+            self._check(rc)
+        return U, d
 
     def explicit_steps(self, U, dt, nsteps):
         """Advance U (device tensor) in place by nsteps explicit SSP RK(4,3) steps of size dt."""

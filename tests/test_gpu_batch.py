@@ -76,12 +76,21 @@ def test_served_same_result_alone_and_in_mix():
     b.close()
     assert all(r["status"] == "ok" for r in recs)
     s = serve.summary(recs)
-    print(f"served {s['completed']} requests, p50 {s['p50_ms']:.1f} ms p99 {s['p99_ms']:.1f} ms")
-    for r, q in list(zip(recs, reqs))[::4]:
+    # continuous batching: some request was admitted while another one was still running
+    overlap = sum(1 for a in recs for b in recs
+                  if a["id"] < b["id"] and a["admitted"] < b["completed"] and b["admitted"] < a["completed"])
+    print(f"served {s['completed']} requests, p50 {s['p50_ms']:.1f} ms p99 {s['p99_ms']:.1f} ms, "
+          f"{overlap} overlapping pairs")
+    assert overlap > 0
+    for r, q in zip(recs, reqs):
         assert torch.equal(r["U"], _alone(q["cfg"], q["pert"], q["steps"])), r["id"]
 
 
-def _fp32_vs_oracle(d, pert, rtol_factor=20.0):
+def _fp32_vs_oracle(d, pert, rel):
+    """Both runs end below the Newton tolerance on different iteration paths (the FP32
+    preconditioner changes the Krylov iterates), so they differ by how far below rtol each
+    one stops; `rel` bounds the difference relative to the update (about 8x the measured
+    value), and the oracle's own stage residual at the GPU's result meets the Newton test."""
     d32 = dict(d, mg_precision=32)
     o = oracle.Oracle(dict(d, mg_precision=64))
     U0 = o.initial_state(pert)
@@ -98,19 +107,22 @@ def _fp32_vs_oracle(d, pert, rtol_factor=20.0):
             for c in range(4)]
     print(f"fp32 mg: gpu {st['newton_its']}/{st['gmres_its']} oracle fp64 {st_o['newton_its']}/{st_o['gmres_its']} "
           f"rel(update) {diff / upd:.3e} per component {['%.2e' % x for x in comp]} rel(U+Ubar) {diff / ut:.3e}")
-    assert diff <= rtol_factor * d["newton_rtol"] * upd
+    assert diff <= rel * upd
+    if d.get("scheme", 1) == 0:
+        G0 = np.linalg.norm(o.stage_residual(U0, U0, d["dt"]))
+        assert np.linalg.norm(o.stage_residual(Ug, U0, d["dt"])) <= 2 * d["newton_rtol"] * G0
 
 
 def test_fp32_mg_step_vs_fp64_oracle_bubble():
     d, pert, _ = W.ensemble(seed=4, members=1)[0]
-    _fp32_vs_oracle(dict(d, nx=32, nz=16), pert)
+    _fp32_vs_oracle(dict(d, nx=32, nz=16), pert, 8e-10)       # measured 8.2e-11
 
 
 def test_fp32_mg_step_vs_fp64_oracle_inertia_gravity():
     d, pert, _ = W.inertia_gravity(mg_precision=32)
     d = dict(d, nx=60, nz=4, x1=30000.0)
     pert = dict(pert, xc=15000.0)
-    _fp32_vs_oracle(d, pert)
+    _fp32_vs_oracle(d, pert, 1.5e-9)                           # measured 1.8e-10
 
 
 @pytest.mark.parametrize("prec,key", [(32, None), (64, None), (32, "mg112222V")])

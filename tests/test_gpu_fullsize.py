@@ -4,7 +4,9 @@ L_h, the FD Jacobian-vector product, the finest-level FV matvec, one multigrid c
 whole preconditioner against the oracle on the complete vectors (the oracle takes seconds at
 this size), and an implicit step checked through properties that hold at any size: the
 oracle's stage residual at the GPU's result meets the Newton tolerance, and rho / rho theta
-mass is kept.  Tolerances are those of the small-case tests (tests/test_gpu_parity.py)."""
+mass is kept, and an SDIRK2 step whose two stages are solved one by one through the library
+and checked through both of the oracle's stage residuals.  Tolerances are those of the
+small-case tests (tests/gpu_common.py)."""
 import numpy as np
 import pytest
 import torch
@@ -14,7 +16,8 @@ pytestmark = pytest.mark.gpu
 import oracle  # noqa: E402
 from paper_2505_24504_amd import jfmg, workloads as W  # noqa: E402
 
-from gpu_common import DEV, EPS, dg_mass, fv_total_norm, node_total_norm, pair, to_dev, to_np  # noqa: E402
+from gpu_common import (C_FV, C_JVP, C_LH, DEV, EPS, REL_MG_APPLY, REL_MG_FV, dg_mass, fv_scale,  # noqa: E402
+                        lh_scale, node_total_norm, pair, to_dev, to_np)
 
 
 def setup_module(module):
@@ -40,13 +43,11 @@ def test_residual_full_size(dc):
     for minv in (0, 1):
         Lg = to_np(p.residual(to_dev(U), apply_minv=bool(minv)))
         Lo = o.residual(U, minv)
-        sig = o.residual(U, 3)
-        if minv:
-            sig = sig / dg_mass(d)[None, :].repeat(4, 0).ravel()
-        tol = 1e-12 * max(np.linalg.norm(Lo), np.linalg.norm(sig))
+        sc = lh_scale(o, d, U, minv)
         err = np.linalg.norm(Lg - Lo)
-        print(f"  minv={minv} err={err:.3e} tol={tol:.3e} rel={err / np.linalg.norm(Lo):.3e}")
-        assert err <= tol
+        print(f"  minv={minv} err={err:.3e} tol={C_LH * EPS * sc:.3e} rel={err / np.linalg.norm(Lo):.3e} "
+              f"ratio={err / (EPS * sc):.3f}")
+        assert err <= C_LH * EPS * sc
 
 
 def test_jvp_fv_matvec_and_preconditioner_full_size(dc):
@@ -61,29 +62,26 @@ def test_jvp_fv_matvec_and_preconditioner_full_size(dc):
     jo = o.jvp(y)
     ut, _ = node_total_norm(o, d, U)
     eps = np.sqrt(EPS) * ut / np.linalg.norm(y)   # fd_eps_mode 1 of the workload
-    tol = 2 * (adt / eps) * (1.0 / dg_mass(d).min()) * 1e-12 * np.linalg.norm(o.residual(U, 3))
+    scale = (adt / eps) * EPS * lh_scale(o, d, U, 1)
     err = np.linalg.norm(jg - jo)
-    print(f"  jvp err {err:.3e} tol {tol:.3e} rel {err / np.linalg.norm(jo):.3e}")
-    assert err <= tol
+    print(f"  jvp err {err:.3e} tol {C_JVP * scale:.3e} rel {err / np.linalg.norm(jo):.3e} ratio {err / scale:.3f}")
+    assert err <= C_JVP * scale
     # finest-level FV matvec (64x8 tiles): the FD bound of the tile-shape tests
     x = W.random_state(o.fv_size(0), 93, [1e-3, 1.0, 1.0, 0.3])
     ag = to_np(p.fv_matvec(0, to_dev(x)))
     ao = o.fv_matvec(0, x)
-    nx, nz = o.fv_dims(0)
-    h = min((d["x1"] - d["x0"]) / nx, (d["z1"] - d["z0"]) / nz)
-    eps = np.sqrt(EPS) * fv_total_norm(o, d, 0, o.fv_level_state(0)) / np.linalg.norm(x)
-    tol = 2 * 64 * (adt / eps) * EPS * (4 * 1.1e5 / h) * np.sqrt(x.size)
+    scale = fv_scale(o, d, 0, o.fv_level_state(0), x, adt)
     err = np.linalg.norm(ag - ao)
-    print(f"  fv matvec err {err:.3e} tol {tol:.3e} rel {err / np.linalg.norm(ao):.3e}")
-    assert err <= tol
-    # one FV cycle and the whole preconditioner: 1e-6 relative
+    print(f"  fv matvec err {err:.3e} tol {C_FV * scale:.3e} rel {err / np.linalg.norm(ao):.3e} ratio {err / scale:.3f}")
+    assert err <= C_FV * scale
+    # one FV cycle and the whole preconditioner
     b = W.random_state(o.fv_size(0), 94, [1e-3, 1.0, 1.0, 0.3])
     e1 = np.linalg.norm(to_np(p.mg_fv(to_dev(b))) - o.mg_fv(b)) / np.linalg.norm(o.mg_fv(b))
     r = W.random_state(o.ndof, 95, [1e-3, 1.0, 1.0, 1.0])
     zo = o.mg_apply(r)
     e2 = np.linalg.norm(to_np(p.mg_apply(to_dev(r))) - zo) / np.linalg.norm(zo)
     print(f"  mg_fv rel err {e1:.3e}, mg_apply rel err {e2:.3e}")
-    assert e1 <= 1e-6 and e2 <= 1e-6
+    assert e1 <= REL_MG_FV and e2 <= REL_MG_APPLY
 
 
 def test_implicit_step_full_size_properties(dc):
@@ -111,7 +109,7 @@ def test_implicit_step_full_size_properties(dc):
     for c in (0, 3):
         drift = abs((m * (b[c] - a[c])).sum()) / (m * np.abs(b[c] - a[c])).sum()
         print(f"  mass drift c={c}: {drift:.2e}")
-        assert drift < 1e-12
+        assert drift < 2e-14      # measured <= 2.3e-15
 
 
 def test_inertia_gravity_full_size_fp32_multigrid():
@@ -128,8 +126,9 @@ def test_inertia_gravity_full_size_fp32_multigrid():
     U = U0 + W.random_state(o.ndof, 96, [1e-6, 1e-3, 1e-3, 3e-3])
     Lg = to_np(p.residual(to_dev(U), apply_minv=True))
     Lo = o.residual(U, 1)
-    sig = o.residual(U, 3) / dg_mass(d)[None, :].repeat(4, 0).ravel()
-    assert np.linalg.norm(Lg - Lo) <= 1e-12 * max(np.linalg.norm(Lo), np.linalg.norm(sig))
+    sc = lh_scale(o, d, U, 1)
+    print(f"  residual ratio {np.linalg.norm(Lg - Lo) / (EPS * sc):.3f}")
+    assert np.linalg.norm(Lg - Lo) <= C_LH * EPS * sc
     adt = (1.0 - 2.0 ** -0.5) * d["dt"]
     p.linearize(to_dev(U), adt)
     o.linearize(U, adt)
@@ -165,17 +164,15 @@ def test_largest_problem_residual():
         Lg = to_np(p.residual(Ud, apply_minv=bool(minv)))
         Lo = o.residual(U, minv)
         assert np.all(np.isfinite(Lo))
-        sig = o.residual(U, 3)
-        if minv:
-            sig = sig / dg_mass(d)[None, :].repeat(4, 0).ravel()
+        sc = lh_scale(o, d, U, minv)
         err = np.linalg.norm(Lg - Lo)
-        print(f"  minv={minv} rel err {err / np.linalg.norm(Lo):.3e}")
-        assert err <= 1e-12 * max(np.linalg.norm(Lo), np.linalg.norm(sig))
+        print(f"  minv={minv} rel err {err / np.linalg.norm(Lo):.3e} ratio {err / (EPS * sc):.3f}")
+        assert err <= C_LH * EPS * sc
 
 
 def test_deepest_hierarchy():
     """The largest hierarchy, 8 FV levels (128 x 128 cells down to 1 x 1): the preconditioner
-    against the oracle's (1e-6, as for 3 levels)."""
+    against the oracle's (as for 3 levels)."""
     d = W.small(nx=64, nz=64, k=1, mg_levels=8, physics=1, mu=75.0)
     print("case 8 levels", flush=True)
     p, o = pair(d)
@@ -186,7 +183,7 @@ def test_deepest_hierarchy():
     zo = o.mg_apply(r)
     err = np.linalg.norm(to_np(p.mg_apply(to_dev(r))) - zo) / np.linalg.norm(zo)
     print(f"  rel err {err:.3e}")
-    assert err <= 1e-6
+    assert err <= 2e-7        # measured 2.3e-8
 
 
 def test_longest_restart_cycle():
@@ -206,9 +203,10 @@ def test_longest_restart_cycle():
     Ug = to_np(U)
     diff, upd = np.linalg.norm(Ug - Uo), np.linalg.norm(Uo - U0)
     print(f"  gpu {st['newton_its']}/{st['gmres_its']} oracle {st_o['newton_its']}/{st_o['gmres_its']} "
-          f"rel(update) {diff / upd:.3e}")
+          f"rel(update) {diff / upd:.3e} rel(U') {diff / np.linalg.norm(Uo):.3e}")
     assert st["gmres_its"] > 2 * 64
-    assert diff <= 20 * rtol * upd
+    assert st["newton_its"] == st_o["newton_its"] and st["gmres_its"] == st_o["gmres_its"]
+    assert diff <= 6e-11 * np.linalg.norm(Uo)   # measured 7.7e-12
 
 
 def test_explicit_steps_third_order_full_size(dc):
@@ -239,15 +237,53 @@ def test_well_balanced_and_dg_smoothing_full_size(dc):
     assert torch.count_nonzero(pe.residual(pe.dg_zeros())).item() == 0
     pn = jfmg.Problem(d, device=DEV)
     Ln = to_np(pn.residual(pn.dg_zeros()))
-    assert np.linalg.norm(Ln) <= 1e-12 * np.linalg.norm(o.residual(np.zeros(o.ndof), 3))
+    sc = lh_scale(o, d, np.zeros(o.ndof), 0)
+    print(f"  viscous rest state ratio {np.linalg.norm(Ln) / (EPS * sc):.3e}")
+    assert np.linalg.norm(Ln) <= 4e-5 * EPS * sc    # the background's viscous flux, as for the small cases
     ds = dict(d, mg_key="mg112222V", pseudo_cfl_dg=0.1)
     ps, os_ = pair(ds)
     adt = (1.0 - 2.0 ** -0.5) * d["dt"]
     ps.linearize(to_dev(U), adt)
     os_.linearize(U, adt)
-    assert abs(ps.dg_dtau() - os_.dg_dtau()) <= 1e-13 * os_.dg_dtau()
+    assert abs(ps.dg_dtau() - os_.dg_dtau()) <= 8 * EPS * os_.dg_dtau()
     r = W.random_state(os_.ndof, 99, [1e-3, 1.0, 1.0, 1.0])
     zo = os_.mg_apply(r)
     err = np.linalg.norm(to_np(ps.mg_apply(to_dev(r))) - zo) / np.linalg.norm(zo)
     print(f"  DG-smoothing mg_apply rel err {err:.3e}")
-    assert err <= 1e-6
+    assert err <= REL_MG_APPLY
+
+
+def test_sdirk2_step_full_size_through_both_stage_residuals(dc):
+    """The benchmarked SDIRK2 step at full size (density current, 1 048 576 unknowns, the
+    bench configuration): its two stages solved one by one through jfmg_newton_stage give
+    the jfmg_implicit_step result, and each stage solution satisfies the oracle's own stage
+    equation to the Newton tolerance: stage 1 G(U1) = U1 - a dt f(U1) - U^n, stage 2
+    G(U2) = U2 - a dt f(U2) - Ubar_2 with Ubar_2 = U^n + (1 - a) dt f(U1) formed by the
+    oracle from the GPU's U1 (eq. ellsiep).  The oracle's residual at the GPU's solution
+    exceeds the GPU's own only by the rounding floor of G, so the bound is 2 rtol."""
+    d, pert, p, o, U0, _ = dc
+    print("case full-size SDIRK2 stages", flush=True)
+    a = 1.0 - np.sqrt(2.0) / 2.0
+    adt = a * d["dt"]
+    Ud = to_dev(U0)
+    U1, s1 = p.newton_stage(Ud, adt)
+    f1 = p.residual(U1, apply_minv=True)
+    Ubar2 = Ud + (1.0 - a) * d["dt"] * f1
+    U2, s2 = p.newton_stage(Ubar2, adt)
+    Us = Ud.clone()
+    st = p.implicit_step(Us)
+    step_diff = torch.linalg.norm(Us - U2).item() / torch.linalg.norm(U2 - Ud).item()
+    print(f"  stages newton {s1['newton_its']}+{s2['newton_its']} gmres {s1['gmres_its']}+{s2['gmres_its']}; "
+          f"implicit_step newton {st['newton_its']} gmres {st['gmres_its']}; relative distance {step_diff:.3e}")
+    assert st["newton_its"] == s1["newton_its"] + s2["newton_its"]
+    assert st["gmres_its"] == s1["gmres_its"] + s2["gmres_its"]
+    assert torch.equal(Us, U2)      # the same kernels in the same order
+    u1, u2 = to_np(U1), to_np(U2)
+    ratios = []
+    G0 = np.linalg.norm(o.stage_residual(U0, U0, adt))
+    ratios.append(np.linalg.norm(o.stage_residual(u1, U0, adt)) / G0)
+    ub2 = U0 + (1.0 - a) * d["dt"] * o.residual(u1, 1)
+    G0b = np.linalg.norm(o.stage_residual(ub2, ub2, adt))
+    ratios.append(np.linalg.norm(o.stage_residual(u2, ub2, adt)) / G0b)
+    print(f"  oracle ||G(U_s)|| / ||G(Ubar_s)||: stage 1 {ratios[0]:.3e}, stage 2 {ratios[1]:.3e}")
+    assert max(ratios) <= 2 * d["newton_rtol"]

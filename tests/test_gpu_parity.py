@@ -1,16 +1,22 @@
 """Parity of the HIP path (through the C-ABI) with the CPU oracle.
 
-Tolerances (floating point):
-  * L_h: ||L_gpu - L_orc|| <= 1e-12 max(||L_orc||, sigma), sigma = the rounding
-    scale of the oracle (same sums over absolute values of the unsubtracted
-    terms): the well-balanced form subtracts O(p) fluxes, so two correct
-    implementations differ by rounding of those, not of the small result.
-  * FD products (DG JVP, FV matvec): the L_h bound propagated through the
-    difference quotient, 2 (alpha dt / eps) max(1/m) 1e-12 sigma.
-  * multigrid / preconditioner in FP64: 1e-6 relative (a fixed composition of
-    ~50 FD products, each with sqrt(eps_mach)-level relative round-off).
-  * implicit steps in FP64: 1e-10 relative L2 of the state U' + Ubar, and the
-    difference of the two results within 20 rtol of the update (Newton test).
+Every floating-point bound is a constant times a scale that the arithmetic
+fixes, with the constant about 8x (never more than 10x) the largest normalized
+error measured on MI355X:
+  * L_h: C_LH eps ||sigma||, sigma = the oracle's rounding scale (per node the
+    sum of absolute values of the terms it adds, before the background
+    subtraction; / m for M^-1 L_h).  The well-balanced form subtracts O(p)
+    fluxes, so two correct implementations differ by the rounding of those:
+    measured 0.43-0.50 eps ||sigma||.  On the O(1e-2) states this is also
+    within 1e-13 ||L_orc||.
+  * DG JVP: the L_h rounding through the difference quotient,
+    C_JVP (alpha dt / eps) eps_mach ||sigma / m|| (measured 0.56-0.70).
+  * FV matvec: C_FV (alpha dt / eps) eps_mach (4 p0 / h) sqrt(n), four face
+    fluxes of size p / h per cell (measured 0.23-0.27).
+  * multigrid cycle / preconditioner in FP64: REL_MG_FV / REL_MG_APPLY relative
+    (a fixed composition of FD products, each with ~1e-8 relative noise).
+  * implicit steps in FP64: equal Newton and FGMRES counts, and the relative L2
+    difference of U' within REL_STEP_* (measured 4e-11 and 6e-12).
 Index maps, restriction and prolongation: bit-exact.
 """
 import numpy as np
@@ -22,14 +28,16 @@ pytestmark = pytest.mark.gpu
 import oracle  # noqa: E402
 from paper_2505_24504_amd import jfmg, workloads as W  # noqa: E402
 
-from gpu_common import (DEV, EPS, dg_mass, fv_total_norm, node_total_norm, pair, rand_state,  # noqa: E402
-                        to_dev, to_np)
+from gpu_common import (C_FV, C_JVP, C_LH, DEV, EPS, REL_MG_APPLY, REL_MG_FV, REL_STEP_BUBBLE,  # noqa: E402
+                        REL_STEP_SDIRK2, dg_mass, fv_scale as _fv_scale, fv_total_norm, node_total_norm, pair,
+                        rand_state, to_dev, to_np)
 
 
 def setup_module(module):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     jfmg.load_library()
+
 
 
 def _cfg(k, nx=5, nz=3, **kw):
@@ -82,6 +90,18 @@ def test_restrict_prolong_bitexact(prec):
 # initial data and the DG operator
 # --------------------------------------------------------------------------
 
+def _total_density_norm(o, d, U):
+    """||rho' + rho_bar||_2 over all DG nodes."""
+    t = oracle.ref_tables(d["k"])
+    n1 = d["k"] + 1
+    dz = (d["z1"] - d["z0"]) / d["nz"]
+    r = U[:o.ndof // 4].reshape(d["nz"], d["nx"], n1, n1).copy()
+    for ez in range(d["nz"]):
+        for b in range(n1):
+            r[ez, :, b, :] += o.background(d["z0"] + (ez + 0.5 * (1 + t["xi"][b])) * dz)[0][0]
+    return float(np.linalg.norm(r))
+
+
 @pytest.mark.parametrize("which", ["bubble", "dc", "ig"])
 def test_initial_state_parity(which):
     if which == "bubble":
@@ -98,8 +118,12 @@ def test_initial_state_parity(which):
     n = o.ndof // 4
     assert np.all(Ug[3 * n:] == 0.0) and np.all(Ug[2 * n:3 * n] == 0.0)
     # rho' = rho - rho_bar cancels: its round-off is relative to the total density
-    ut, _ = node_total_norm(o, d, Uo)
-    assert np.linalg.norm(Ug - Uo) <= 1e-13 * np.linalg.norm(Uo) + 1e-15 * ut
+    # rho' = rho - rho_bar with rho = (rho theta)_bar / (theta_bar + theta'): a few roundings
+    # of the total density per node
+    rho = _total_density_norm(o, d, Uo)
+    err = np.linalg.norm(Ug - Uo)
+    print(f"initial state {which}: err {err:.3e} ratio {err / (EPS * rho):.3f}")
+    assert err <= 16 * EPS * rho
 
 
 @pytest.mark.parametrize("case", CASES)
@@ -110,7 +134,12 @@ def test_well_balanced_gpu(case):
     if case[1] == 0:
         assert np.all(L == 0.0)
     else:
-        assert np.linalg.norm(L) <= 1e-12 * np.linalg.norm(o.residual(np.zeros(o.ndof), 3))
+        # at rest only the viscous flux of the background is left, mu (dUbar_c/dz - (Ubar_c /
+        # rho_bar) d rho_bar/dz), a cancellation about 1e-5 of the size of the pressure terms
+        # in sigma: measured 4.9e-6 eps ||sigma|| (the oracle's own rest residual 1.5e-6)
+        sig = np.linalg.norm(o.residual(np.zeros(o.ndof), 3))
+        print(f"rest state viscous: |L| {np.linalg.norm(L):.3e} ratio {np.linalg.norm(L) / (EPS * sig):.3e}")
+        assert np.linalg.norm(L) <= 4e-5 * EPS * sig
 
 
 @pytest.mark.parametrize("case", CASES)
@@ -126,10 +155,13 @@ def test_residual_parity(case, rel):
         sig = o.residual(U, 3)
         if minv:
             sig = sig / dg_mass(d)[None, :].repeat(4, 0).ravel()
-        tol = 1e-12 * max(np.linalg.norm(Lo), np.linalg.norm(sig))
+        tol = C_LH * EPS * np.linalg.norm(sig)
         err = np.linalg.norm(Lg - Lo)
-        print(f"  minv={minv} err={err:.3e} tol={tol:.3e} rel={err / np.linalg.norm(Lo):.3e}")
+        print(f"  minv={minv} err={err:.3e} tol={tol:.3e} rel={err / np.linalg.norm(Lo):.3e} "
+              f"ratio={err / (EPS * np.linalg.norm(sig)):.3f}")
         assert err <= tol
+        if rel >= 1e-2:   # the result dominates the rounding scale's cancellation
+            assert err <= 1e-13 * np.linalg.norm(Lo)
 
 
 def test_stage_residual_parity():
@@ -140,8 +172,11 @@ def test_stage_residual_parity():
     Gg, ng = p.stage_residual(to_dev(U), to_dev(Ub), 0.7)
     Go = o.stage_residual(U, Ub, 0.7)
     sig = 0.7 * o.residual(U, 3) / np.tile(dg_mass(d), 4)
-    assert np.linalg.norm(to_np(Gg) - Go) <= 1e-12 * max(np.linalg.norm(Go), np.linalg.norm(sig))
-    assert ng == pytest.approx(np.linalg.norm(Go), rel=1e-10)
+    err = np.linalg.norm(to_np(Gg) - Go)
+    print(f"stage residual err={err:.3e} ratio={err / (EPS * np.linalg.norm(sig)):.3f} "
+          f"norm rel diff {abs(ng - np.linalg.norm(Go)) / np.linalg.norm(Go):.3e}")
+    assert err <= C_LH * EPS * np.linalg.norm(sig)
+    assert abs(ng - np.linalg.norm(Go)) <= err + 4 * EPS * np.linalg.norm(Go)
 
 
 # --------------------------------------------------------------------------
@@ -165,11 +200,10 @@ def test_jvp_parity(case, mode):
         yn = np.linalg.norm(y)
         ut, _ = node_total_norm(o, d, U)
         eps = np.sqrt(EPS) / yn if mode == 0 else np.sqrt(EPS) * ut / yn
-        sig = np.linalg.norm(o.residual(U, 3))
-        tol = 2 * (adt / eps) * (1.0 / dg_mass(d).min()) * 1e-12 * sig
+        scale = (adt / eps) * EPS * np.linalg.norm(o.residual(U, 3) / np.tile(dg_mass(d), 4))
         err = np.linalg.norm(Jg - Jo)
-        print(f"  err={err:.3e} tol={tol:.3e} rel={err / np.linalg.norm(Jo):.3e}")
-        assert err <= tol
+        print(f"  err={err:.3e} tol={C_JVP * scale:.3e} rel={err / np.linalg.norm(Jo):.3e} ratio={err / scale:.3f}")
+        assert err <= C_JVP * scale
     assert np.all(to_np(p.jvp(p.dg_zeros())) == 0.0)
 
 
@@ -195,16 +229,21 @@ def test_transfer_parity(k, mass_fix, transfer, prec):
     U = rand_state(o, 31, 1.0)
     tg = to_np(p.transfer(0, to_dev(U)))
     to_ = o.transfer_T(U)
-    tol = 1e-13 if prec == 64 else 2e-7
-    assert np.linalg.norm(tg - to_) <= tol * np.linalg.norm(to_)
+    e1 = np.linalg.norm(tg - to_) / np.linalg.norm(to_)
     u = o.transfer_T(U)
     dt = torch.float32 if prec == 32 else torch.float64
     Ug = to_np(p.transfer(1, to_dev(u, dt)))
     Uo = o.transfer_Tinv(u.astype(np.float32).astype(np.float64) if prec == 32 else u)
-    assert np.linalg.norm(Ug - Uo) <= 1e-13 * np.linalg.norm(Uo)
+    e2 = np.linalg.norm(Ug - Uo) / np.linalg.norm(Uo)
+    print(f"transfer k={k} mass_fix={mass_fix} transfer={transfer} fp{prec}: T {e1:.3e} Tinv {e2:.3e}")
+    # T: a (k+1)^2-term sum per value (+ the mass fix), rounded to the multigrid precision;
+    # T^-1 in FP64 (measured <= 7.8 eps and 1.1 FP32 ulps)
+    assert e1 <= (16 * EPS if prec == 64 else 2 * 2.0 ** -24)
+    assert e2 <= 16 * EPS
 
 
 FV_CASES = [(1, 0, 0, 0), (2, 0, 1, 1), (3, 1, 0, 0), (3, 0, 0, 0)]
+
 
 
 def _fv_cfg(case):
@@ -223,8 +262,13 @@ def test_fv_linearization_parity(case):
     for lev in range(3):
         ug = to_np(p.fv_level_state(lev))
         uo = o.fv_level_state(lev)
-        assert np.linalg.norm(ug - uo) <= 1e-13 * np.linalg.norm(uo)
-        assert p.fv_dtau(lev) == pytest.approx(o.fv_dtau(lev), rel=1e-13)
+        e_u = np.linalg.norm(ug - uo) / np.linalg.norm(uo)
+        e_t = abs(p.fv_dtau(lev) - o.fv_dtau(lev)) / o.fv_dtau(lev)
+        print(f"linearization {case} level {lev}: state {e_u:.3e} dtau {e_t:.3e}")
+        # the transfer's rounding, relative to a norm that halves per level for random
+        # states (the restriction averages): measured 7.6, 10.1, 20 eps on levels 0, 1, 2
+        assert e_u <= 16 * EPS * 2 ** lev
+        assert e_t <= 8 * EPS       # measured <= 1.0 eps
 
 
 @pytest.mark.parametrize("case", FV_CASES)
@@ -242,13 +286,11 @@ def test_fv_matvec_parity(case):
         u = o.fv_level_state(lev)
         nx, nz = o.fv_dims(lev)
         # rounding scale of f_low per cell: four face fluxes of size p / h
-        h = min((d["x1"] - d["x0"]) / nx, (d["z1"] - d["z0"]) / nz)
-        sig = 4 * 1.1e5 / h
-        eps = np.sqrt(EPS) * fv_total_norm(o, d, lev, u) / np.linalg.norm(x)
-        tol = 2 * 64 * (adt / eps) * EPS * sig * np.sqrt(x.size)
+        scale = _fv_scale(o, d, lev, u, x, adt)
         err = np.linalg.norm(ag - ao)
-        print(f"  lev={lev} err={err:.3e} tol={tol:.3e} rel={err / np.linalg.norm(ao):.3e}")
-        assert err <= tol
+        print(f"  lev={lev} err={err:.3e} tol={C_FV * scale:.3e} rel={err / np.linalg.norm(ao):.3e} "
+              f"ratio={err / scale:.3f}")
+        assert err <= C_FV * scale
 
 
 @pytest.mark.parametrize("tile", jfmg.TILES)
@@ -273,17 +315,15 @@ def test_fv_tile_shapes_parity(case, tile):
         ag = to_np(p.fv_matvec(lev, to_dev(x)))
         ao = o.fv_matvec(lev, x)
         u = o.fv_level_state(lev)
-        nx, nz = o.fv_dims(lev)
-        h = min((d["x1"] - d["x0"]) / nx, (d["z1"] - d["z0"]) / nz)
-        eps = np.sqrt(EPS) * fv_total_norm(o, d, lev, u) / np.linalg.norm(x)
-        tol = 2 * 64 * (adt / eps) * EPS * (4 * 1.1e5 / h) * np.sqrt(x.size)
-        assert np.linalg.norm(ag - ao) <= tol, (lev, tile)
+        scale = _fv_scale(o, d, lev, u, x, adt)
+        print(f"tile {tile} case {case} level {lev}: matvec ratio {np.linalg.norm(ag - ao) / scale:.3f}")
+        assert np.linalg.norm(ag - ao) <= C_FV * scale, (lev, tile)
     b = W.random_state(o.fv_size(0), 75, [1e-3, 1.0, 1.0, 0.3])
     xg = to_np(p.mg_fv(to_dev(b)))
     xo = o.mg_fv(b)
     err = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
     print(f"tile {tile} case {case}: mg_fv rel err {err:.3e}")
-    assert err <= 1e-6
+    assert err <= REL_MG_FV
 
 
 @pytest.mark.parametrize("tile", jfmg.TILES)
@@ -333,7 +373,7 @@ def test_autotune_choice_and_step_parity():
     assert rc == 0
     U = to_dev(U0)
     st = p.implicit_step(U)
-    _step_check(d, Uo, U0, to_np(U), rtol, st, st_o)
+    _step_check(d, Uo, U0, to_np(U), REL_STEP_BUBBLE, st, st_o)
     with pytest.raises(jfmg.JfmgError):
         p.set_tiles([7] * n)
     assert p.get_tiles() == shapes
@@ -356,7 +396,7 @@ def test_mg_fv_parity(case, key, stages):
     xo = o.mg_fv(b)
     err = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
     print(f"case mg_fv {case} {key} s={stages}: rel err {err:.3e}")
-    assert err <= 1e-6
+    assert err <= REL_MG_FV
 
 
 @pytest.mark.parametrize("case", [(1, 0, 0, 0, 0.0), (3, 1, 0, 0, 0.0), (2, 0, 1, 1, 20.0)])
@@ -372,11 +412,11 @@ def test_mg_apply_parity(case, precond, transfer):
     zo = o.mg_apply(r)
     err = np.linalg.norm(zg - zo) / np.linalg.norm(zo)
     print(f"case mg_apply {case} precond={precond}: rel err {err:.3e}")
-    assert err <= (1e-6 if precond else 0.0)
+    assert err <= (REL_MG_APPLY if precond else 0.0)
 
 
 # DG-level smoothing (key a, b): a JVP per smoother stage, so the FD products' round-off
-# enters like in the FV matvecs; same 1e-6 bound as the preconditioner above
+# enters like in the FV matvecs; same bound as the preconditioner above
 DG_KEYS = ["mg102222V", "mg012222V", "mg112222V", "mg211111W"]
 
 
@@ -389,13 +429,13 @@ def test_mg_apply_dg_smoothing_parity(case, key):
     p.linearize(to_dev(U), 0.8)
     o.linearize(U, 0.8)
     dg, do = p.dg_dtau(), o.dg_dtau()
-    assert abs(dg - do) <= 1e-13 * do
+    assert abs(dg - do) <= 8 * EPS * do
     r = rand_state(o, 62, 1.0)
     zg = to_np(p.mg_apply(to_dev(r)))
     zo = o.mg_apply(r)
     err = np.linalg.norm(zg - zo) / np.linalg.norm(zo)
-    print(f"case mg_apply {case} {key}: dtau_dg {dg:.6e} rel err {err:.3e}")
-    assert err <= 1e-6
+    print(f"case mg_apply {case} {key}: dtau_dg {dg:.6e} (rel diff {abs(dg - do) / do:.1e}) rel err {err:.3e}")
+    assert err <= REL_MG_APPLY
 
 
 def test_dg_dtau_needs_dg_smoothing():
@@ -410,18 +450,20 @@ def test_dg_dtau_needs_dg_smoothing():
 # whole implicit steps
 # --------------------------------------------------------------------------
 
-def _step_check(d, Uo, U0, Ug, rtol, st, st_o):
-    """Two converged stage solves agree to what the Newton test fixes: each has
-    ||G|| < rtol ||G^0||, so the results differ by O(rtol) of the update (bound
-    20 rtol ||U^{n+1} - U^n||); the total state U' + Ubar agrees to 1e-10 relative."""
+def _step_check(d, Uo, U0, Ug, rel, st, st_o, gmres_slack=0):
+    """Both sides take the same Newton and FGMRES iterations (the step is determined only
+    to the Newton tolerance, so the same path is what makes the results comparable), and
+    U' agrees to `rel` relative L2: the difference is the rounding of the two operator
+    implementations carried through the same iterations."""
     o = oracle.Oracle(d)
     ut, _ = node_total_norm(o, d, Uo)
     diff = np.linalg.norm(Ug - Uo)
     upd = np.linalg.norm(Uo - U0)
     print(f"gpu {st['newton_its']}/{st['gmres_its']} oracle {st_o['newton_its']}/{st_o['gmres_its']} "
           f"rel(U+Ubar) {diff / ut:.3e} rel(update) {diff / upd:.3e} rel(U') {diff / np.linalg.norm(Uo):.3e}")
-    assert diff <= 1e-10 * ut
-    assert diff <= 20 * rtol * upd
+    assert st["newton_its"] == st_o["newton_its"]
+    assert abs(st["gmres_its"] - st_o["gmres_its"]) <= gmres_slack
+    assert diff <= rel * np.linalg.norm(Uo)
 
 
 @pytest.mark.parametrize("transfer", [0, 1])
@@ -435,7 +477,7 @@ def test_implicit_euler_step_parity_bubble(transfer):
     assert rc == 0
     U = to_dev(U0)
     st = p.implicit_step(U)
-    _step_check(d, Uo, U0, to_np(U), rtol, st, st_o)
+    _step_check(d, Uo, U0, to_np(U), REL_STEP_BUBBLE, st, st_o)
 
 
 @pytest.mark.parametrize("key", ["mg112222V", "mg011111V"])
@@ -450,7 +492,7 @@ def test_implicit_step_dg_smoothing_parity(key):
     assert rc == 0
     U = to_dev(U0)
     st = p.implicit_step(U)
-    _step_check(d, Uo, U0, to_np(U), rtol, st, st_o)
+    _step_check(d, Uo, U0, to_np(U), REL_STEP_BUBBLE, st, st_o)
 
 
 @pytest.mark.parametrize("physics", [0, 1])
@@ -465,7 +507,7 @@ def test_sdirk2_step_parity(physics):
     assert rc == 0
     U = to_dev(U0)
     st = p.implicit_step(U)
-    _step_check(d, Uo, U0, to_np(U), rtol, st, st_o)
+    _step_check(d, Uo, U0, to_np(U), REL_STEP_SDIRK2, st, st_o)
 
 
 def test_newton_stall_stop():
@@ -479,7 +521,9 @@ def test_newton_stall_stop():
     U = to_dev(U0)
     st = p.implicit_step(U)
     assert st["stall_stops"] == 1
-    _step_check(d, Uo, U0, to_np(U), 1e-9, st, st_o)
+    # the last linear solve ends at the rounding floor of G, where the two sides' FGMRES
+    # stopping tests may differ by one iteration (measured 87 against 86)
+    _step_check(d, Uo, U0, to_np(U), REL_STEP_BUBBLE, st, st_o, gmres_slack=1)
 
 
 def test_step_determinism_and_mass():
@@ -502,7 +546,8 @@ def test_step_determinism_and_mass():
         drift[(mass_fix, transfer)] = max(abs((m * (b[c] - a[c])).sum()) / (m * np.abs(b[c] - a[c])).sum()
                                           for c in (0, 3))
     print("relative rho / rho-theta mass drift of one step:", drift)
-    assert drift[(1, 0)] < 1e-12 and drift[(0, 1)] < 1e-12
+    # conservative transfers: a few ulps of the change's absolute mass (measured <= 1.9e-16)
+    assert drift[(1, 0)] < 1.4e-15 and drift[(0, 1)] < 1.4e-15
     assert drift[(0, 0)] > 100 * max(drift[(1, 0)], drift[(0, 1)])
 
 
@@ -515,17 +560,17 @@ def _cfl_dt(d, frac=0.3, speed=380.0):
     return frac * h / ((2 * d["k"] + 1) * speed)
 
 
-def _explicit_check(d, o, U0, Ug, Uo, dt, n):
+def _explicit_check(d, o, U0, Ug, Uo, dt, n, c):
     """Each of the 4n stages adds the rounding of L_h, a few ulps of the rounding scale
     sigma of the well-balanced form (sums of absolute values of the unsubtracted terms),
-    scaled by dt/2, and rounding of the stage combination relative to U itself:
-    tol = 1e-11 ||update|| + 1e-15 n dt ||sigma / m|| + 1e-14 ||U||."""
+    scaled by dt/2: tol = c eps n dt ||sigma / m|| (measured 0.14-0.20 eps n dt ||sigma / m||
+    on the random states, 0.09 on the bubble)."""
     sig = o.residual(U0, 3) / dg_mass(d)[None, :].repeat(4, 0).ravel()
     sdt = n * dt * np.linalg.norm(sig)
-    tol = 1e-11 * np.linalg.norm(Uo - U0) + 1e-15 * sdt + 1e-14 * np.linalg.norm(Uo)
+    tol = c * EPS * sdt
     err = np.linalg.norm(Ug - Uo)
     print(f"  dt={dt:.4g} steps={n} err={err:.3e} tol={tol:.3e} rel={err / np.linalg.norm(Uo - U0):.3e} "
-          f"err/(n dt sigma)={err / sdt:.3e}")
+          f"ratio={err / (EPS * sdt):.3f}")
     assert np.all(np.isfinite(Ug)) and err <= tol
 
 
@@ -539,7 +584,7 @@ def test_explicit_steps_parity(case):
     dt, n = _cfl_dt(d), 3
     Ug = to_dev(U0)
     p.explicit_steps(Ug, dt, n)
-    _explicit_check(d, o, U0, to_np(Ug), o.explicit_steps(U0, dt, n), dt, n)
+    _explicit_check(d, o, U0, to_np(Ug), o.explicit_steps(U0, dt, n), dt, n, 1.4)
 
 
 def test_explicit_steps_rest_and_bubble():
@@ -560,7 +605,7 @@ def test_explicit_steps_rest_and_bubble():
     p.explicit_steps(U, dt, n)
     Uo = o.explicit_steps(to_np(U0), dt, n)
     Ug = to_np(U)
-    _explicit_check(d, o, to_np(U0), Ug, Uo, dt, n)
+    _explicit_check(d, o, to_np(U0), Ug, Uo, dt, n, 0.8)
     # mass: the face fluxes cancel between neighbours up to rounding of the flux sums
     # (scale sigma, summed over the 4n stages of size dt/2) and of the updates (scale m |U|)
     m = dg_mass(d)
@@ -569,7 +614,7 @@ def test_explicit_steps_rest_and_bubble():
     for c in (0, 3):
         scale = (m * (np.abs(a[c]) + np.abs(b[c]))).sum() + 2 * n * dt * sig[c].sum()
         print(f"  mass drift c={c}: {abs((m * (b[c] - a[c])).sum()):.3e} of scale {scale:.3e}")
-        assert abs((m * (b[c] - a[c])).sum()) <= 1e-14 * scale
+        assert abs((m * (b[c] - a[c])).sum()) <= 5 * EPS * scale   # measured <= 0.6 eps scale
     for bad in ((dt, -1), (float("nan"), 1), (float("inf"), 1)):
         with pytest.raises(jfmg.JfmgError):
             p.explicit_steps(U, *bad)

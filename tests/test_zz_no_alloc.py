@@ -4,8 +4,8 @@ through the static scratch, the second on a smaller problem, and the rest state.
 
 Tolerance: the allocation-free call evaluates the background tables on the
 device, the problem on the host, so the two differ by the rounding of L_h (the
-parity bound of the residual: 4 ulps of the rounding scale, the sums of absolute
-values of the unsubtracted terms, times alpha dt / m per node)."""
+rounding scale of the residual, the sums of absolute values of the unsubtracted
+terms, times alpha dt / m per node: measured 0.22 eps of that scale, bound 2 eps)."""
 import ctypes
 
 import numpy as np
@@ -39,7 +39,7 @@ def _check(d, seed, adt):
     Gs, n2 = jfmg.stage_residual_noalloc(d, to_dev(U), to_dev(Ub), adt)
     gp, gs = to_np(Gp), to_np(Gs)
     sig = adt * o.residual(U, 3) / np.tile(dg_mass(d), 4)
-    tol = 4 * EPS * np.linalg.norm(sig)
+    tol = 2 * EPS * np.linalg.norm(sig)
     err = np.linalg.norm(gs - gp)
     nrm = float(np.sqrt(to_np(n2)[0]))
     print(f"noalloc k={d['k']} {d['nx']}x{d['nz']} physics={d['physics']}: err {err:.3e} tol {tol:.3e} "
