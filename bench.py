@@ -58,12 +58,24 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the ensemble, serving and inertia-gravity forms")
-    ap.add_argument("--serve-requests", type=int, default=32)
+    ap.add_argument("--serve-requests", type=int, default=500,
+                    help="requests of the seed-5 stream served at saturation (FP32 and FP64 multigrid)")
+    ap.add_argument("--serve-sweep-requests", type=int, default=200,
+                    help="requests per offered rate below saturation")
+    ap.add_argument("--serial-requests", type=int, default=100,
+                    help="requests of the stream solved one at a time with the FP64 multigrid")
+    ap.add_argument("--cpu-repeats", type=int, default=3,
+                    help="oracle runs of the headline step (median; fewer if one takes over a minute)")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the HBM-resident (above cache size) kernel measurements")
     ap.add_argument("--profile-class", default="auto",
                     help="kernel class timed with HIP events ('auto': largest total time)")
     return ap.parse_args()
+
+
+def progress(msg):
+    """One line per finished part of the benchmark on stderr (the JSON line stays on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def percentile(xs, q):
@@ -121,23 +133,32 @@ def autotune_report(d, pert):
     return out
 
 
-def stream_copy(nbytes, reps=20):
-    """STREAM-style device copy of nbytes (read + write counted): GB/s."""
+def stream_copy(nbytes, reps=20, triad=False):
+    """STREAM-style device copy y = x (2 arrays moved) or triad z = x + s y (3 arrays)
+    over nbytes per array: GB/s of the arrays moved."""
     import torch
     n = nbytes // 8
     x = torch.ones(n, dtype=torch.float64, device="cuda:0")
     y = torch.empty_like(x)
-    y.copy_(x)
+    z = torch.empty_like(x) if triad else None
+    y.fill_(2.0)
+
+    def once():
+        if triad:
+            torch.add(x, y, alpha=3.0, out=z)
+        else:
+            y.copy_(x)
+    once()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
-        y.copy_(x)
+        once()
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
-    del x, y
-    return 2.0 * n * 8 / (ms * 1e-3) / 1e9
+    del x, y, z
+    return (3.0 if triad else 2.0) * n * 8 / (ms * 1e-3) / 1e9
 
 
 def _sync():
@@ -145,12 +166,43 @@ def _sync():
     torch.cuda.synchronize()
 
 
-def ensemble_forms():
-    """64-member ensemble (k = 2 warm bubbles on 32x16 / 64x32 / 96x48, 5 SDIRK2
-    steps each) with the FP32 multigrid, lock-step (one batched problem per grid
-    size) and as concurrent single problems from one arena, against the members
-    run one after another with the plain FP64 multigrid."""
+def _lockstep_ensemble(mem, prec):
+    """The members of each grid size form one lock-step problem (every kernel launch
+    covers all of them, tiles by the autotuner); the three problems run concurrently."""
     import torch
+    from paper_2505_24504_amd import jfmg
+    groups = {}
+    for d, pert, n in mem:
+        groups.setdefault((d["nx"], d["nz"]), []).append((dict(d, mg_precision=prec), pert, n))
+    b = jfmg.Batch(48 << 30, max_members=len(groups), workers=len(groups), device="cuda:0")
+    gslots = []
+    for ms in groups.values():
+        single = jfmg.Problem(ms[0][0], device="cuda:0")
+        U = torch.cat([single.initial_state(pert) for _, pert, _ in ms])
+        del single
+        gslots.append(b.admit(dict(ms[0][0], batch=len(ms)), ms[0][2], None, U))
+    t0 = time.perf_counter()
+    tiles = [b.autotune(s_) for s_ in gslots]
+    el_tune = time.perf_counter() - t0
+    _sync()
+    t0 = time.perf_counter()
+    b.run()
+    el = time.perf_counter() - t0
+    polled = [b.poll(s_) for s_ in gslots]
+    b.close()
+    ok = sum(len(ms) for ms, (f_, _, st) in zip(groups.values(), polled) if f_ and st["status"] == 0)
+    return el, {"members_ok": ok, "groups": [len(ms) for ms in groups.values()], "tiles": tiles,
+                "autotune_seconds": el_tune, "lockstep_gmres_its": [st["gmres_its"] for _, _, st in polled],
+                "stall_stops": sum(st["stall_stops"] for _, _, st in polled),
+                "reached_rtol": max(st["reached_rtol"] for _, _, st in polled)}
+
+
+def ensemble_forms():
+    """64-member ensemble (k = 2 warm bubbles on 32x16 / 64x32 / 96x48, 5 SDIRK2 steps
+    each): lock-step groups (one batched problem per grid size) with the FP32 and with the
+    FP64 multigrid, concurrent single problems from one arena (FP32), and the members run
+    one after another (FP64).  Stages may end at the rounding floor of G (stall stops,
+    newton_stall 1e-7); reached_rtol is the largest final ||G|| / ||G^0|| of any stage."""
     from paper_2505_24504_amd import jfmg, workloads as W
     mem = W.ensemble(seed=4, members=64)
     work = sum(jfmg.num_dofs(d) * n for d, _, n in mem)
@@ -160,12 +212,10 @@ def ensemble_forms():
     t0 = time.perf_counter()
     b.run()
     el_b = time.perf_counter() - t0
-    polled = [b.poll(s) for s in slots]
+    polled = [b.poll(s_) for s_ in slots]
     b.close()
     ok_b = sum(1 for f, _, st in polled if f and st["status"] == 0)
-    its_b = sum(st["gmres_its"] for _, _, st in polled)
-    stalls_b = sum(st["stall_stops"] for _, _, st in polled)
-    el_s, its_s, ok_s, stalls_s = 0.0, 0, 0, 0
+    el_s, its_s, ok_s, stalls_s, reach_s = 0.0, 0, 0, 0, 0.0
     for d, pert, n in mem:
         p = jfmg.Problem(dict(d, mg_precision=64), device="cuda:0")
         U = p.initial_state(pert)
@@ -176,60 +226,78 @@ def ensemble_forms():
             st = p.implicit_step(U, raise_on_error=False)
             its_s += st["gmres_its"]
             stalls_s += st["stall_stops"]
+            reach_s = max(reach_s, st["reached_rtol"])
             good = good and st["status"] == 0
         _sync()
         el_s += time.perf_counter() - t0
         ok_s += good
         del p
-    # lock-step: the members of each grid size form one batched problem (every kernel
-    # launch covers all of them); the three problems run concurrently
-    groups = {}
-    for d, pert, n in mem:
-        groups.setdefault((d["nx"], d["nz"]), []).append((d, pert, n))
-    b = jfmg.Batch(48 << 30, max_members=len(groups), workers=len(groups), device="cuda:0")
-    gslots = []
-    for ms in groups.values():
-        single = jfmg.Problem(ms[0][0], device="cuda:0")
-        U = torch.cat([single.initial_state(pert) for _, pert, _ in ms])
-        del single
-        gslots.append(b.admit(dict(ms[0][0], batch=len(ms)), ms[0][2], None, U))
-    # FV tile shapes of each lock-step problem by the autotuner (setup, not timed)
-    t0 = time.perf_counter()
-    tiles = [b.autotune(s) for s in gslots]
-    el_tune = time.perf_counter() - t0
-    _sync()
-    t0 = time.perf_counter()
-    b.run()
-    el_l = time.perf_counter() - t0
-    polled_l = [b.poll(s) for s in gslots]
-    b.close()
-    ok_l = sum(len(ms) for ms, (f_, _, st) in zip(groups.values(), polled_l) if f_ and st["status"] == 0)
-    return {"ensemble_lockstep_fp32": {"value": work / el_l, "seconds": el_l, "members_ok": ok_l,
-                                       "groups": [len(ms) for ms in groups.values()],
-                                       "tiles": tiles, "autotune_seconds": el_tune,
-                                       "lockstep_gmres_its": [st["gmres_its"] for _, _, st in polled_l]},
-            "ensemble_batched_fp32": {"value": work / el_b, "seconds": el_b, "members_ok": ok_b,
-                                      "gmres_its": its_b, "stall_stops": stalls_b},
-            "ensemble_serial_fp64": {"value": work / el_s, "seconds": el_s, "members_ok": ok_s,
-                                     "gmres_its": its_s, "stall_stops": stalls_s},
-            "ensemble_workload": "64 warm bubbles, k=2, grids 32x16/64x32/96x48, 5 SDIRK2 steps each, "
-                                 f"{work} DOF-Newton-steps"}
+    out = {}
+    progress(f"ensemble concurrent and serial forms done ({el_b:.1f} s, {el_s:.1f} s)")
+    for prec in (32, 64):
+        el_l, info = _lockstep_ensemble(mem, prec)
+        out[f"ensemble_lockstep_fp{prec}"] = dict({"value": work / el_l, "seconds": el_l}, **info)
+        progress(f"ensemble lock-step FP{prec}: {work / el_l:.3e} DOF-Newton-steps/s")
+    out.update({
+        "ensemble_batched_fp32": {"value": work / el_b, "seconds": el_b, "members_ok": ok_b,
+                                  "gmres_its": sum(st["gmres_its"] for _, _, st in polled),
+                                  "stall_stops": sum(st["stall_stops"] for _, _, st in polled),
+                                  "reached_rtol": max(st["reached_rtol"] for _, _, st in polled)},
+        "ensemble_serial_fp64": {"value": work / el_s, "seconds": el_s, "members_ok": ok_s,
+                                 "gmres_its": its_s, "stall_stops": stalls_s, "reached_rtol": reach_s},
+        "ensemble_workload": "64 warm bubbles, k=2, grids 32x16/64x32/96x48, 5 SDIRK2 steps each, "
+                             f"{work} DOF-Newton-steps; 640 stages"})
+    return out
 
 
-def serving_forms(n_requests):
-    """The first n_requests of the Poisson request stream (200/s; grid, k, physics,
-    steps drawn per request) served with continuous batching from a 64 GB arena
-    (FP32 multigrid), against a one-at-a-time FIFO server running each request
-    with the plain FP64 multigrid (its latencies from the measured service times)."""
-    from paper_2505_24504_amd import jfmg, serve, workloads as W
-    reqs = W.serving_requests(seed=5, n_requests=n_requests)
+def _serve_once(reqs, prec, rate_scale=1.0):
+    """Serve reqs (arrival times scaled by rate_scale) with continuous batching from a
+    64 GB arena; returns the summary with the stall statistics."""
+    from paper_2505_24504_amd import jfmg, serve
+    rq = [dict(r, cfg=dict(r["cfg"], mg_precision=prec)) for r in reqs]
     arena = 64 << 30
     b = jfmg.Batch(arena, max_members=64, workers=8, device="cuda:0")
-    recs = serve.serve(reqs, b, jfmg.workspace_bytes, arena)
+    recs = serve.serve(rq, b, jfmg.workspace_bytes, arena, time_scale=rate_scale)
     b.close()
     s = serve.summary(recs)
+    s["offered_req_per_s"] = len(rq) / (rq[-1]["arrival"] * rate_scale) if rq else None
+    s["stall_stops"] = sum(r.get("stall_stops", 0) for r in recs)
+    s["reached_rtol"] = max((r.get("reached_rtol", 0.0) for r in recs), default=0.0)
+    return s
+
+
+def serving_forms(n_sat, n_sweep, n_serial):
+    """The seed-5 request stream (Poisson, 200 req/s as configured; grid, k, physics and
+    steps drawn per request).  (1) Saturation: the first n_sat requests at the configured
+    rate, far above what one GPU sustains, served with continuous batching with the FP32
+    and with the FP64 multigrid (throughput = saturation throughput; latency = queueing).
+    (2) Load sweep: the first n_sweep requests with arrival times stretched so that the
+    offered rate is 0.5 and 0.8 of the FP32 saturation rate (p50/p99 against offered rate).
+    (3) The first n_serial requests solved one at a time with the plain FP64 multigrid."""
+    from paper_2505_24504_amd import jfmg, serve, workloads as W
+    reqs = W.serving_requests(seed=5, n_requests=max(n_sat, n_sweep, n_serial))
+    out = {}
+    sat = reqs[:n_sat]
+    work = sum(jfmg.num_dofs(r["cfg"]) * r["steps"] for r in sat)
+    for prec in (32, 64):
+        out[f"served_fp{prec}_saturation"] = _serve_once(sat, prec)
+        progress(f"served {n_sat} requests at saturation, FP{prec} multigrid: "
+                 f"{out[f'served_fp{prec}_saturation']['value']:.3e} DOF-Newton-steps/s")
+    # requests per second the FP32 server completes at saturation
+    s32 = out["served_fp32_saturation"]
+    sat_rate = s32["completed"] / s32["makespan_s"]
+    sweep = reqs[:n_sweep]
+    base_rate = len(sweep) / sweep[-1]["arrival"]
+    out["served_fp32_load_sweep"] = {}
+    for frac in (0.5, 0.8):
+        scale = base_rate / (frac * sat_rate)
+        r = _serve_once(sweep, 32, rate_scale=scale)
+        r["fraction_of_saturation"] = frac
+        out["served_fp32_load_sweep"][str(frac)] = r
+        progress(f"served at {frac} of saturation: p50 {r['p50_ms']:.0f} ms p99 {r['p99_ms']:.0f} ms")
     svc, ok = [], 0
-    for r in reqs:
+    ser = reqs[:n_serial]
+    for r in ser:
         _sync()
         t0 = time.perf_counter()
         p = jfmg.Problem(dict(r["cfg"], mg_precision=64), device="cuda:0")
@@ -241,19 +309,23 @@ def serving_forms(n_requests):
         svc.append(time.perf_counter() - t0)
         ok += good
         del p
-    lat = serve.serial_fifo(reqs, svc)
-    work = sum(jfmg.num_dofs(r["cfg"]) * r["steps"] for r in reqs)
-    return {"served_fp32": s,
-            "serial_fp64": {"value": work / sum(svc), "seconds": sum(svc), "completed": ok,
-                            "p50_ms": 1e3 * percentile(lat, 50), "p99_ms": 1e3 * percentile(lat, 99)},
-            "serving_workload": f"first {n_requests} requests of the seed-5 stream (Poisson 200/s), "
-                                "grids 16x8..256x128, k 1..3, Euler or viscous, 1..10 SDIRK2 steps, "
-                                f"{work} DOF-Newton-steps"}
+    lat = serve.serial_fifo(ser, svc)
+    wser = sum(jfmg.num_dofs(r["cfg"]) * r["steps"] for r in ser)
+    out["serial_fp64"] = {"value": wser / sum(svc), "seconds": sum(svc), "completed": ok, "requests": len(ser),
+                          "p50_ms": 1e3 * percentile(lat, 50), "p99_ms": 1e3 * percentile(lat, 99),
+                          "note": "latencies of a one-at-a-time FIFO server on the configured arrivals"}
+    progress(f"serial FP64 requests done ({sum(svc):.1f} s)")
+    out["saturation_req_per_s_fp32"] = sat_rate
+    out["serving_workload"] = (f"seed-5 stream (Poisson 200/s), grids 16x8..256x128, k 1..3, Euler or viscous, "
+                               f"1..10 SDIRK2 steps; saturation runs: first {n_sat} requests, {work} DOF-Newton-steps; "
+                               f"load sweep: first {n_sweep}; serial: first {n_serial}")
+    return out
 
 
-def inertia_gravity_forms(steps=3):
-    """Inertia-gravity wave (600x20, k=3, periodic, N = 0.01, 20 m/s wind, dt = 12 s):
-    FP32 multigrid against FP64 multigrid, and how far the two solutions are apart."""
+def inertia_gravity_forms(steps=20):
+    """Inertia-gravity wave (600x20, k=3, periodic, N = 0.01, 20 m/s wind, dt = 12 s), the
+    configured 20 steps: FP32 multigrid against FP64 multigrid, and how far the two solutions
+    are apart after the 20 steps."""
     import numpy as np
     from paper_2505_24504_amd import jfmg, workloads as W
     out, Us = {}, {}
@@ -266,16 +338,23 @@ def inertia_gravity_forms(steps=3):
         U.copy_(U0)
         _sync()
         t0 = time.perf_counter()
-        its = [p.implicit_step(U, raise_on_error=False) for _ in range(steps)]
+        lat, its = [], []
+        for _ in range(steps):
+            ts = time.perf_counter()
+            its.append(p.implicit_step(U, raise_on_error=False))
+            lat.append(time.perf_counter() - ts)
         _sync()
         el = time.perf_counter() - t0
         n = jfmg.num_dofs(d)
         out[f"fp{prec}_mg"] = {"value": steps * n / el, "ms_per_step": 1e3 * el / steps,
+                               "p50_ms": 1e3 * percentile(lat, 50), "p99_ms": 1e3 * percentile(lat, 99),
                                "newton_its": sum(s["newton_its"] for s in its),
                                "gmres_its": sum(s["gmres_its"] for s in its),
                                "stall_stops": sum(s["stall_stops"] for s in its),
+                               "reached_rtol": max(s["reached_rtol"] for s in its),
                                "ok": all(s["status"] == 0 for s in its)}
         Us[prec] = (U0.cpu().numpy(), U.cpu().numpy())
+        progress(f"inertia-gravity FP{prec} multigrid: {1e3 * el / steps:.1f} ms/step")
         del p
     (a0, a), (_, b) = Us[64], Us[32]
     n4 = a.size // 4
@@ -283,6 +362,38 @@ def inertia_gravity_forms(steps=3):
         float(np.linalg.norm((b - a)[c * n4:(c + 1) * n4]) / max(np.linalg.norm((a - a0)[c * n4:(c + 1) * n4]), 1e-300))
         for c in range(4)]
     out["workload"] = f"inertia-gravity wave, 600x20 quads, k=3, {steps} SDIRK2 steps of 12 s"
+    return out
+
+
+def bubble_small_form(steps=20):
+    """The tiny warm bubble (16x16 quads, k = 1, one implicit-Euler step of 1 s, FGMRES(20),
+    3 levels, mg002222V with the three-stage smoother), launch-latency bound: time per step
+    and per FGMRES iteration at the configured Newton rtol 1e-6 and at 1e-8."""
+    from paper_2505_24504_amd import jfmg, workloads as W
+    d0, pert, _ = W.bubble_small()
+    out = {}
+    for rtol in (1e-6, 1e-8):
+        d = dict(d0, newton_rtol=rtol)
+        p = jfmg.Problem(d, device="cuda:0")
+        U0 = p.initial_state(pert)
+        U = U0.clone()
+        p.implicit_step(U)
+        _sync()
+        lat, its = [], []
+        for _ in range(steps):
+            U.copy_(U0)
+            _sync()
+            ts = time.perf_counter()
+            its.append(p.implicit_step(U))
+            lat.append(time.perf_counter() - ts)
+        g = sum(s["gmres_its"] for s in its)
+        out[f"rtol_{rtol:.0e}"] = {"ms_per_step": 1e3 * sum(lat) / steps, "p50_ms": 1e3 * percentile(lat, 50),
+                                  "p99_ms": 1e3 * percentile(lat, 99), "gmres_its_per_step": g / steps,
+                                  "newton_its_per_step": sum(s["newton_its"] for s in its) / steps,
+                                  "us_per_gmres_iteration": 1e6 * sum(lat) / g,
+                                  "value": jfmg.num_dofs(d) * steps / sum(lat)}
+        del p
+    out["workload"] = "warm bubble 16x16 quads, k=1, implicit Euler dt=1 s, FGMRES(20), 3 levels, 3-stage smoother"
     return out
 
 
@@ -372,6 +483,7 @@ def preconditioner_keys(steps=2):
                         "ok": st0["status"] == 0 and all(x["status"] == 0 for x in sts)}
             del p, U
         out[wname] = res
+        progress(f"preconditioner keys on {wname} done")
     return out
 
 
@@ -424,22 +536,53 @@ def large_roofline(reps=20):
     return out
 
 
-def cpu_baseline():
-    """The oracle timed on the host: first SDIRK2 step of the density current on a
-    48 x 12 quad grid of the same domain (k = 3, same physics and solver settings)."""
+def host_info():
+    """CPU model and core counts of the host the benchmark runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
+def cpu_baseline(repeats=3):
+    """The oracle timed on the host on the headline workload itself: the first SDIRK2 step
+    of the density current (256 x 64 quads, k = 3, 1 048 576 unknowns, same solver
+    settings), from the initial state, median of `repeats` runs (one run when the first
+    takes over a minute).  The oracle's element and cell loops run on OMP_NUM_THREADS
+    threads (default: every usable core); norms and inner products stay serial."""
+    h = host_info()
+    threads = int(os.environ.get("OMP_NUM_THREADS") or h["usable_cpus"] or 1)
+    os.environ["OMP_NUM_THREADS"] = str(threads)   # read when the oracle library loads
     import oracle
     from paper_2505_24504_amd import workloads as W
     d, pert, _ = W.density_current()
-    d = dict(d, nx=48, nz=12)
     o = oracle.Oracle(d)
-    U = o.initial_state(pert)
-    t0 = time.perf_counter()
-    rc, _, st = o.implicit_step(U)
-    el = time.perf_counter() - t0
-    return {"value": o.ndof / el, "unit": "DOF-Newton-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"one SDIRK2 step of the density current on 48x12 quads (k=3, N={o.ndof}), "
-                      f"single-threaded FP64 C, {el:.1f} s, newton {st['newton_its']} gmres {st['gmres_its']}, "
-                      f"status {rc}"}
+    U0 = o.initial_state(pert)
+    times, st, rc = [], None, None
+    for i in range(repeats):
+        t0 = time.perf_counter()
+        rc, _, st = o.implicit_step(U0)
+        times.append(time.perf_counter() - t0)
+        progress(f"oracle step {i + 1}: {times[-1]:.1f} s")
+        if times[0] > 60.0:
+            break
+    el = sorted(times)[len(times) // 2]
+    return {"value": o.ndof / el, "unit": "DOF-Newton-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"first SDIRK2 step of the density current (256x64 quads, k=3, N={o.ndof}), FP64 C with "
+                      f"OpenMP over elements and cells on {threads} threads; median of {len(times)} runs "
+                      f"({', '.join(f'{t:.1f}' for t in times)} s); newton {st['newton_its']} gmres "
+                      f"{st['gmres_its']}, status {rc}",
+            "host": h}
 
 
 def main():
@@ -457,12 +600,21 @@ def main():
 
     # pass 1 (untimed for the metric): find the kernel class with the largest total time
     prof_cls = a.profile_class
-    if prof_cls == "auto":
-        _, _, _, _, prof_all = run_form(d, pert, 1, 0, jfmg.KERNEL_CLASSES)
-        prof_cls = max(prof_all, key=lambda k: prof_all[k]["ms"])
+    # kernel-class time per FGMRES iteration of one step (event-timed, eager launches), FP64
+    # and FP32 multigrid: where an iteration's time goes in either precision
+    breakdown = {}
+    for prec in (64, 32) if not a.no_fp32 else (64,):
+        _, _, _, its_b, prof_b = run_form(dict(d, mg_precision=prec), pert, 1, 0, jfmg.KERNEL_CLASSES)
+        g = max(1, sum(st_["gmres_its"] for st_ in its_b))
+        breakdown[f"fp{prec}"] = {"gmres_its": g, "us_per_iteration": {
+            k: round(1e3 * v["ms"] / g, 2) for k, v in prof_b.items() if v["launches"]},
+            "launches_per_iteration": {k: round(v["launches"] / g, 2) for k, v in prof_b.items() if v["launches"]}}
+        if prec == 64 and prof_cls == "auto":
+            prof_cls = max(prof_b, key=lambda k: prof_b[k]["ms"])
     # timed pass, FP64 multigrid (headline): no instrumentation
     p, el, lat, its, _ = run_form(d, pert, a.steps, a.warmup, [])
     value = a.steps * N / el
+    progress(f"headline: {value:.4e} DOF-Newton-steps/s, {1e3 * el / a.steps:.2f} ms/step")
     # second timed pass of the same workload: the dominant kernel class timed by the
     # start/stop events of its own dispatches (eager launches; see include/jfmg.h)
     _, el_prof, _, _, prof = run_form(d, pert, a.steps, a.warmup, [prof_cls])
@@ -485,6 +637,7 @@ def main():
         except Exception as ex:   # a configuration that does not converge is reported, not fatal
             forms[name] = {"config": kw, "error": str(ex)}
             continue
+        progress(f"form {name}: {1e3 * elv / a.steps:.1f} ms/step")
         forms[name] = {"value": a.steps * N / elv, "ms_per_step": 1e3 * elv / a.steps, "config": kw,
                        "p50_ms": 1e3 * percentile(latv, 50), "p99_ms": 1e3 * percentile(latv, 99),
                        "newton_its": sum(s["newton_its"] for s in itsv),
@@ -496,7 +649,12 @@ def main():
         forms["fp32_mg"] = {"value": a.steps * N / el32, "ms_per_step": 1e3 * el32 / a.steps, "tiles": p32.tiles,
                             "p50_ms": 1e3 * percentile(lat32, 50), "p99_ms": 1e3 * percentile(lat32, 99),
                             "newton_its": sum(s["newton_its"] for s in its32),
-                            "gmres_its": sum(s["gmres_its"] for s in its32)}
+                            "gmres_its": sum(s["gmres_its"] for s in its32),
+                            "reached_rtol": max(s["reached_rtol"] for s in its32)}
+    forms["fp64_mg"]["newton_its"] = sum(s["newton_its"] for s in its)
+    forms["fp64_mg"]["gmres_its"] = sum(s["gmres_its"] for s in its)
+    forms["fp64_mg"]["reached_rtol"] = max(s["reached_rtol"] for s in its)
+    forms["iteration_breakdown"] = breakdown
     out = {
         "metric": "DOF-Newton-steps/s at rtol 1e-8, FP32-MG vs FP64 plain; p50/p99 step latency",
         "value": value,
@@ -530,20 +688,27 @@ def main():
                                f"of the same {a.steps} steps ({1e3 * el_prof / a.steps:.1f} ms/step with the events)"},
     }
     if not a.no_forms:
+        forms["bubble_small"] = bubble_small_form()
+        progress("tiny bubble done")
         forms.update(ensemble_forms())
-        forms.update(serving_forms(a.serve_requests))
+        forms.update(serving_forms(a.serve_requests, a.serve_sweep_requests, a.serial_requests))
         forms["inertia_gravity"] = inertia_gravity_forms()
         forms["explicit_reference"] = explicit_reference_form(d, pert, 1e3 * el / a.steps)
+        progress("explicit reference done")
         forms["preconditioner_keys"] = preconditioner_keys()
+        progress("preconditioner keys done")
     if not a.no_large:
         out["roofline_hbm_resident"] = large_roofline()
-    # copy bandwidth of the device: HBM-resident (1 GiB) and cache-resident (32 MiB)
+    # copy and triad bandwidth of the device: HBM-resident (1 GiB) and cache-resident (32 MiB)
     hbm_copy, mall_copy = stream_copy(1 << 30), stream_copy(32 << 20)
+    hbm_triad, mall_triad = stream_copy(1 << 30, triad=True), stream_copy(32 << 20, triad=True)
     out["stream_copy"] = {"hbm_1GiB_GBs": hbm_copy, "mall_32MiB_GBs": mall_copy,
+                          "triad_hbm_1GiB_GBs": hbm_triad, "triad_mall_32MiB_GBs": mall_triad,
                           "roofline_frac_vs_hbm_copy": achieved / hbm_copy if achieved else None,
                           "roofline_frac_vs_mall_copy": achieved / mall_copy if achieved else None}
+    out["host"] = host_info()
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(a.cpu_repeats)
     print(json.dumps(out), flush=True)
 
 

@@ -95,6 +95,8 @@ typedef struct {
     int stall_stops, pad;     /* stages ended at the rounding floor (newton_stall)     */
     double g0_norm, g_norm;   /* ||G(U^0)||, ||G|| at exit of the last stage          */
     double seconds;           /* host wall time of the call                           */
+    double reached_rtol;      /* largest final ||G|| / ||G^0|| over the call's stages
+                                 (and members): the Newton tolerance actually met      */
 } jfmg_stats;
 
 typedef struct jfmg_problem jfmg_problem;

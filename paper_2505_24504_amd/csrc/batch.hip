@@ -112,6 +112,7 @@ void accumulate(jfmg_stats& a, const jfmg_stats& s)
     a.g0_norm = s.g0_norm;
     a.g_norm = s.g_norm;
     a.seconds += s.seconds;
+    a.reached_rtol = a.reached_rtol > s.reached_rtol ? a.reached_rtol : s.reached_rtol;
     if (a.status == JFMG_OK) a.status = s.status;
 }
 

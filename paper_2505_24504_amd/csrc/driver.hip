@@ -1218,12 +1218,16 @@ jfmg_status newton_stage(jfmg_problem* p, const double* Ubar, double adt, jfmg_s
             if (!active[b]) continue;
             if (!std::isfinite(gk[b])) return fail(p, JFMG_ENONFINITE, "non-finite stage residual");
             gmax = std::max(gmax, gk[b]);
-            if (gk[b] < c.newton_rtol * g0[b]) { active[b] = 0; --left; continue; }
+            bool stop = gk[b] < c.newton_rtol * g0[b];
             // rounding floor of G: no halving any more although already below newton_stall ||G^0||
-            if (c.newton_stall > 0.0 && gk[b] <= c.newton_stall * g0[b] && gk[b] > 0.5 * gprev[b]) {
+            if (!stop && c.newton_stall > 0.0 && gk[b] <= c.newton_stall * g0[b] && gk[b] > 0.5 * gprev[b]) {
                 if (st) st->stall_stops++;
+                stop = true;
+            }
+            if (stop) {
                 active[b] = 0;
                 --left;
+                if (st) st->reached_rtol = std::max(st->reached_rtol, gk[b] / g0[b]);
             }
         }
         if (st) st->g_norm = gmax;

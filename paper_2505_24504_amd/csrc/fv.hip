@@ -40,6 +40,90 @@ enum { FVM_LIN = 0, FVM_STAGE = 1, FVM_MATVEC = 2, FVM_DEFECT = 3, FVM_STAGE_PC 
 // measurements also ruled out 32x8, 16x4 with 128/192 threads, 64x4 with 2/3 waves
 // per SIMD and early own-cell loads).
 
+// Net flux through one face of a tile (HLLC minus the k = 0 interior-penalty diffusion
+// flux, along +x or +z, times the face length) from the tile's staged states; face
+// idx of the x-faces (XF) or z-faces in row-major order of the tile.
+template <typename T, int TX, int TZ, int HZ, int HX, bool XF>
+__device__ __forceinline__ void fv_face(const FvArgs<T>& A, const T (&sw)[4][HZ][HX], const T (&sBc)[TZ][6],
+                                        const T (&sBf)[TZ + 1][10], T (&sFx)[TZ][TX + 1][4], T (&sFz)[TZ + 1][TX][4],
+                                        int I0, int J0, int nxl, int nzl, int idx)
+{
+    constexpr int D = XF ? 1 : 2;   // normal momentum component
+    int rl, cl, rr, cr, brow;       // LDS row/col of the low (L) and high (R) cell; background row of the tile
+    bool skip, wallL, wallR;
+    if constexpr (XF) {
+        const int jj = idx / (TX + 1), fi = idx - jj * (TX + 1);
+        const int Jf = J0 + jj, Ir = I0 + fi, Il = Ir - 1;
+        skip = (Jf >= nzl) || (Il >= nxl);
+        wallL = (Ir == 0) && A.bc != 1;
+        wallR = (Il == nxl - 1) && A.bc != 1;
+        rl = jj + 1; rr = jj + 1; cl = fi; cr = fi + 1;
+        brow = jj;
+    } else {
+        const int fj = idx / TX, ii = idx - fj * TX;
+        const int If = I0 + ii, Ja = J0 + fj, Jb = Ja - 1;
+        skip = (If >= nxl) || (Jb >= nzl);
+        wallL = (Jb < 0);
+        wallR = (Ja == nzl);
+        rl = fj; rr = fj + 1; cl = ii + 1; cr = ii + 1;
+        brow = fj;
+    }
+    T Phi[4] = {T(0), T(0), T(0), T(0)};
+    if (!skip) {
+        const T* bg = XF ? &sBc[brow][0] : &sBf[brow][0];   // Ubar, then p, 1/(rho theta)
+        const T* pr = bg + 4;
+        const bool wall = wallL || wallR;
+        // a slip wall: the missing side is the inside cell mirrored (normal momentum negated)
+        const int rlx = wallL ? rr : rl, clx = wallL ? cr : cl;
+        const int rrx = wallR ? rl : rr, crx = wallR ? cl : cr;
+        T wL[4], wR[4], UL[4], UR[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            wL[c] = sw[c][rlx][clx];
+            wR[c] = sw[c][rrx][crx];
+            UL[c] = wL[c] + bg[c];
+            UR[c] = wR[c] + bg[c];
+        }
+        if (wallL) UL[D] = -UL[D];
+        if (wallR) UR[D] = -UR[D];
+        const T pb = pr[0], irb = pr[1];
+        const T pL = pert_pressure(A.gas, wL[3], irb, pb), pR = pert_pressure(A.gas, wR[3], irb, pb);
+        const T irL = frcp<T>(UL[0]), irR = frcp<T>(UR[0]);
+        hllc_ax<T, D>(A.gas, UL, UR, pL, pR, irL, irR, Phi);
+        if (A.physics == 1 && !wall) {
+            // k = 0 diffusion: mean of mu (G_c - (U_c/rho) G_rho) over both sides, where the
+            // only gradient is the background's (z-faces), minus the interior penalty
+            // (mu/h) (dw_c - (U_c/rho)_avg dw_rho), dw = w_L - w_R, on the averaged state
+            const T irs = frcp<T>(UL[0] + UR[0]);
+            const T muh = A.mu / (XF ? A.hx : A.hz);
+            const T* dbg = &sBf[brow][6];
+            const T dw0 = wL[0] - wR[0];
+#pragma unroll
+            for (int c = 1; c < 4; ++c) {
+                if constexpr (!XF) {
+                    const T fl = A.mu * (dbg[c] - UL[c] * irL * dbg[0]);
+                    const T fr = A.mu * (dbg[c] - UR[c] * irR * dbg[0]);
+                    Phi[c] -= T(0.5) * (fl + fr);
+                }
+                const T rr = (UL[c] + UR[c]) * irs;
+                Phi[c] += muh * ((wL[c] - wR[c]) - rr * dw0);
+            }
+        }
+        const T elen = XF ? A.hz : A.hx;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Phi[c] *= elen;
+    }
+    if constexpr (XF) {
+        const int jj = idx / (TX + 1), fi = idx - jj * (TX + 1);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sFx[jj][fi][c] = Phi[c];
+    } else {
+        const int fj = idx / TX, ii = idx - fj * TX;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sFz[fj][ii][c] = Phi[c];
+    }
+}
+
 // FV operator on one tile of TX x TZ cells, face-centric: the perturbed states
 // w = u + eps x of the tile and a one-cell halo are staged in LDS, every face
 // of the tile gets its net flux Phi (HLLC minus the interior-penalty diffusion
@@ -174,81 +258,7 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
         // thread order (the threads with a second x-face are not those with a
         // second z-face) ----
         auto face = [&](auto xf_tag, int idx) {
-            constexpr bool XF = decltype(xf_tag)::value;
-            constexpr int D = XF ? 1 : 2;   // normal momentum component
-            int rl, cl, rr, cr, brow;       // LDS row/col of the low (L) and high (R) cell; background row of the tile
-            bool skip, wallL, wallR;
-            if constexpr (XF) {
-                const int jj = idx / (TX + 1), fi = idx - jj * (TX + 1);
-                const int Jf = J0 + jj, Ir = I0 + fi, Il = Ir - 1;
-                skip = (Jf >= nzl) || (Il >= nxl);
-                wallL = (Ir == 0) && A.bc != 1;
-                wallR = (Il == nxl - 1) && A.bc != 1;
-                rl = jj + 1; rr = jj + 1; cl = fi; cr = fi + 1;
-                brow = jj;
-            } else {
-                const int fj = idx / TX, ii = idx - fj * TX;
-                const int If = I0 + ii, Ja = J0 + fj, Jb = Ja - 1;
-                skip = (If >= nxl) || (Jb >= nzl);
-                wallL = (Jb < 0);
-                wallR = (Ja == nzl);
-                rl = fj; rr = fj + 1; cl = ii + 1; cr = ii + 1;
-                brow = fj;
-            }
-            T Phi[4] = {T(0), T(0), T(0), T(0)};
-            if (!skip) {
-                const T* bg = XF ? &sBc[brow][0] : &sBf[brow][0];   // Ubar, then p, 1/(rho theta)
-                const T* pr = bg + 4;
-                const bool wall = wallL || wallR;
-                // a slip wall: the missing side is the inside cell mirrored (normal momentum negated)
-                const int rlx = wallL ? rr : rl, clx = wallL ? cr : cl;
-                const int rrx = wallR ? rl : rr, crx = wallR ? cl : cr;
-                T wL[4], wR[4], UL[4], UR[4];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    wL[c] = sw[c][rlx][clx];
-                    wR[c] = sw[c][rrx][crx];
-                    UL[c] = wL[c] + bg[c];
-                    UR[c] = wR[c] + bg[c];
-                }
-                if (wallL) UL[D] = -UL[D];
-                if (wallR) UR[D] = -UR[D];
-                const T pb = pr[0], irb = pr[1];
-                const T pL = pert_pressure(A.gas, wL[3], irb, pb), pR = pert_pressure(A.gas, wR[3], irb, pb);
-                const T irL = frcp<T>(UL[0]), irR = frcp<T>(UR[0]);
-                hllc_ax<T, D>(A.gas, UL, UR, pL, pR, irL, irR, Phi);
-                if (A.physics == 1 && !wall) {
-                    // k = 0 diffusion: mean of mu (G_c - (U_c/rho) G_rho) over both sides, where the
-                    // only gradient is the background's (z-faces), minus the interior penalty
-                    // (mu/h) (dw_c - (U_c/rho)_avg dw_rho), dw = w_L - w_R, on the averaged state
-                    const T irs = frcp<T>(UL[0] + UR[0]);
-                    const T muh = A.mu / (XF ? A.hx : A.hz);
-                    const T* dbg = &sBf[brow][6];
-                    const T dw0 = wL[0] - wR[0];
-#pragma unroll
-                    for (int c = 1; c < 4; ++c) {
-                        if constexpr (!XF) {
-                            const T fl = A.mu * (dbg[c] - UL[c] * irL * dbg[0]);
-                            const T fr = A.mu * (dbg[c] - UR[c] * irR * dbg[0]);
-                            Phi[c] -= T(0.5) * (fl + fr);
-                        }
-                        const T rr = (UL[c] + UR[c]) * irs;
-                        Phi[c] += muh * ((wL[c] - wR[c]) - rr * dw0);
-                    }
-                }
-                const T elen = XF ? A.hz : A.hx;
-#pragma unroll
-                for (int c = 0; c < 4; ++c) Phi[c] *= elen;
-            }
-            if constexpr (XF) {
-                const int jj = idx / (TX + 1), fi = idx - jj * (TX + 1);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) sFx[jj][fi][c] = Phi[c];
-            } else {
-                const int fj = idx / TX, ii = idx - fj * TX;
-#pragma unroll
-                for (int c = 0; c < 4; ++c) sFz[fj][ii][c] = Phi[c];
-            }
+            fv_face<T, TX, TZ, HZ, HX, decltype(xf_tag)::value>(A, sw, sBc, sBf, sFx, sFz, I0, J0, nxl, nzl, idx);
         };
         for (int fx = tid; fx < NFX; fx += NTH) face(std::true_type{}, fx);
         if constexpr (ZREV)   // z-faces from the last thread down

@@ -53,10 +53,10 @@ def test_struct_layout_matches_header(tmp_path):
 #include <stddef.h>
 #include "jfmg.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(jfmg_config), offsetof(jfmg_config, mg_key),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(jfmg_config), offsetof(jfmg_config, mg_key),
          offsetof(jfmg_config, x0), offsetof(jfmg_config, rk_alpha), offsetof(jfmg_config, newton_stall),
          offsetof(jfmg_config, pseudo_cfl_dg), sizeof(jfmg_perturbation), sizeof(jfmg_stats),
-         offsetof(jfmg_stats, g0_norm));
+         offsetof(jfmg_stats, g0_norm), offsetof(jfmg_stats, reached_rtol));
   return 0; }
 ''')
     exe = tmp_path / "lay"
@@ -65,7 +65,7 @@ int main(void) {
     assert vals == [C.sizeof(jfmg.Config), jfmg.Config.mg_key.offset, jfmg.Config.x0.offset,
                     jfmg.Config.rk_alpha.offset, jfmg.Config.newton_stall.offset, jfmg.Config.pseudo_cfl_dg.offset,
                     C.sizeof(jfmg.Perturbation),
-                    C.sizeof(jfmg.Stats), jfmg.Stats.g0_norm.offset]
+                    C.sizeof(jfmg.Stats), jfmg.Stats.g0_norm.offset, jfmg.Stats.reached_rtol.offset]
 
 
 def test_workspace_sizes(lib):
