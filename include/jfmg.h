@@ -290,7 +290,8 @@ typedef enum {
     JFMG_K_UPDATE = 10,       /* Arnoldi w -= V h                                   */
     JFMG_K_FV_STAGE_SMALL = 11, /* the same on narrower levels (small-tile kernel)    */
     JFMG_K_DG_SMOOTH = 12,    /* DG-level smoother stage combination (key a, b)     */
-    JFMG_K_NCLASS = 13
+    JFMG_K_DG_LINEARIZE = 13, /* fluxes of the linearization state for the JVPs     */
+    JFMG_K_NCLASS = 14
 } jfmg_kernel_class;
 jfmg_status jfmg_profile_enable(jfmg_problem* p, unsigned class_mask);
 /* ms, launches and bytes are host arrays of JFMG_K_NCLASS entries. */

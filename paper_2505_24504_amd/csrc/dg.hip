@@ -7,13 +7,16 @@
 //   B  evaluates the volume flux at its node (total state U' + Ubar minus the
 //      background flux, minus the viscous flux) into LDS,
 //   C  loads the neighbour element's trace and normal derivative at one face
-//      point from global memory into registers (faces are recomputed from both
+//      point from global memory into registers (faces are evaluated from both
 //      sides; this costs flops, not HBM bytes) and evaluates HLLC minus the
 //      background HLLC, the interior-penalty terms and the symmetric term there,
 //   D  contracts the volume fluxes with the GL derivative matrix, lifts the
 //      face terms to its node and writes the requested output.
-// The same kernel in JVP mode carries two states, U' and U' + eps y, and
-// differences the fluxes point by point before contracting.
+// In JVP mode the kernel evaluates the fluxes of U' + eps y and differences them
+// point by point with those of U' before contracting.  The fluxes of U' are the
+// same for every product with one linearization state: mode 5 writes them (volume
+// fluxes per node, face terms per face point) once per linearization, and each
+// product reads them back instead of evaluating a second state.
 #include "jfmg_internal.h"
 
 namespace jfmg {
@@ -22,6 +25,7 @@ template <int N1> struct DgShape {
     static constexpr int NP = N1 * N1;
     static constexpr int NTH = (N1 == 2) ? 64 : 128;
     static constexpr int EPB = NTH / NP;
+    static constexpr int FPE = 4 * N1;   // face points per element
 };
 
 __device__ __forceinline__ int face_nb(int f, int ex, int ez, int nx, int nz, int bc)
@@ -33,14 +37,130 @@ __device__ __forceinline__ int face_nb(int f, int ex, int ez, int nx, int nz, in
     return ez < nz - 1 ? (ez + 1) * nx + ex : -1;
 }
 
-// At most 168 VGPRs so that three waves fit per SIMD (with 24 KB of LDS per
-// 128-thread work-group, LDS allows six work-groups per CU).
+// Face terms of one state at face point r of an x-face (xf) or z-face of element
+// row ez with outward normal +e_D (pos) or -e_D, before the quadrature weight:
+//   fl = -H(U_in, U_out; n) (minus the background's H when BGSUB) plus, for
+//        viscous flow, the average of both sides' F_v . n minus the interior
+//        penalty on the jump of the velocity-like variables,
+//   sy = the symmetric term's jump mu (U_c,in - U_c,out - (U_c/rho)_in (rho_in - rho_out)).
+// The element's own values come from its LDS block sv; the neighbour nb (-1: a
+// slip wall, mirrored state) is read from U, plus eps Y when PLUSY.  When pos is
+// uniform over the wave the trace weights are scalar loads.
+template <int N1, bool NS, bool BGSUB, bool PLUSY>
+__device__ __forceinline__ void dg_face(const DgArgs& A, const double (&sv)[4][N1 * N1], const double* __restrict__ U,
+                                        const double* __restrict__ Y, double eps, long N, int nb, bool xf, bool pos,
+                                        int r, int ez, double (&fl)[4], double (&sy)[4])
+{
+    constexpr int NP = N1 * N1;
+    const RefTab& R = A.R;
+    const double sg = pos ? 1.0 : -1.0;
+    const bool wall = nb < 0;
+    // trace and normal-derivative weights of the own and the other side
+    const double* es = pos ? R.ep : R.em;
+    const double* ds = pos ? R.dp : R.dm;
+    const double* eo = pos ? R.em : R.ep;
+    const double* dso = pos ? R.dm : R.dp;
+    double trx[4], dnx[4];   // the neighbour's trace and normal derivative (d/d xi)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        trx[c] = 0.0;
+        dnx[c] = 0.0;
+        if (!wall) {
+#pragma unroll
+            for (int j = 0; j < N1; ++j) {
+                const unsigned o = (unsigned)nb * NP + (xf ? r * N1 + j : j * N1 + r);
+                double v = ld(U + c * N, o);
+                if constexpr (PLUSY) v = v + eps * ld(Y + c * N, o);
+                trx[c] += eo[j] * v;
+                if constexpr (NS) dnx[c] += dso[j] * v;
+            }
+        }
+    }
+    double Ub[4], dUb[4];
+    const int zrow = xf ? (ez * N1 + r) : (ez + (pos ? 1 : 0));
+    const double* bgp = xf ? A.bg_node : A.bg_face;
+    const double* dbgp = xf ? A.dbg_node : A.dbg_face;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) { Ub[c] = bgp[zrow * 4 + c]; dUb[c] = dbgp[zrow * 4 + c]; }
+    const double pbz = xf ? A.pb_node[zrow] : A.pb_face[zrow];
+    const double irz = xf ? A.irt_node[zrow] : A.irt_face[zrow];
+    double tro[4], Uo[4], Ux[4], H[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        double v = 0.0;
+#pragma unroll
+        for (int j = 0; j < N1; ++j) v += es[j] * sv[c][xf ? r * N1 + j : j * N1 + r];
+        tro[c] = v;
+        Uo[c] = v + Ub[c];
+    }
+    const double po = pert_pressure(A.gas, tro[3], irz, pbz);
+    double px = po;
+    if (wall) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Ux[c] = Uo[c];
+        if (xf) Ux[1] = -Uo[1]; else Ux[2] = -Uo[2];
+    } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Ux[c] = trx[c] + Ub[c];
+        px = pert_pressure(A.gas, trx[3], irz, pbz);
+    }
+    const double iro = frcp(Uo[0]), irx = frcp(Ux[0]);
+    hllc_face(A.gas, Uo, Ux, po, px, iro, irx, xf, sg, H);
+    if constexpr (BGSUB) {
+        double Um[4], Hb[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Um[c] = Ub[c];
+        if (wall) { if (xf) Um[1] = -Ub[1]; else Um[2] = -Ub[2]; }
+        const double irb = frcp(Ub[0]);
+        hllc_face(A.gas, Ub, Um, pbz, pbz, irb, irb, xf, sg, Hb);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) H[c] -= Hb[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) { fl[c] = -H[c]; sy[c] = 0.0; }
+    if constexpr (NS) {
+        if (!wall) {
+            // F_v(U, G) . n of a Cartesian face involves only the normal derivative
+            // G_n (the tangential part enters multiplied by 0): own side from the
+            // element's values, other side from the neighbour's trace derivative,
+            // plus the background's z-derivative on z-faces
+            const double gs = xf ? A.rdx2 : A.rdz2;
+            double Gno[4], Gnx[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                double sn = 0.0;
+#pragma unroll
+                for (int j = 0; j < N1; ++j) sn += ds[j] * sv[c][xf ? r * N1 + j : j * N1 + r];
+                const double db = xf ? 0.0 : dUb[c];
+                Gno[c] = gs * sn + db;
+                Gnx[c] = gs * dnx[c] + db;
+            }
+            const double eta = xf ? A.eta_x : A.eta_z;
+            const double Dl0 = tro[0] - trx[0];
+            const double irm = frcp(0.5 * (Uo[0] + Ux[0]));
+#pragma unroll
+            for (int c = 1; c < 4; ++c) {
+                const double ro = Uo[c] * iro;
+                const double Fo = sg * A.mu * (Gno[c] - ro * Gno[0]);
+                const double Fxx = sg * A.mu * (Gnx[c] - Ux[c] * irx * Gnx[0]);
+                const double Dlc = tro[c] - trx[c];
+                const double pen = eta * A.mu * (Dlc - (0.5 * (Uo[c] + Ux[c]) * irm) * Dl0);
+                fl[c] += 0.5 * (Fo + Fxx) - pen;
+                sy[c] = 0.5 * A.mu * (Dlc - ro * Dl0);
+            }
+        }
+    }
+}
+
+// k = 3: at most 128 VGPRs (four waves per SIMD) and 20 KB of LDS per 128-thread
+// work-group, so that eight work-groups fit per CU; lower degrees at most 168.
 template <int N1, bool NS, int MODE>
-__global__ void __launch_bounds__(DgShape<N1>::NTH, 3)
+__global__ void __launch_bounds__(DgShape<N1>::NTH, N1 == 4 ? 4 : 3)
 dg_kernel(DgArgs A, const double* __restrict__ U, const double* __restrict__ Y, const double* __restrict__ Ubar,
           double* __restrict__ out, const double* __restrict__ yn2p, const double* __restrict__ ut2p, int eps_mode,
           double adt, Red red, long ms, ExStage rk)
 {
+    double* lin0 = A.lin0;
     if (gridDim.z > 1) {   // member of a lock-step batch
         U = mbr(U, ms);
         Y = mbr(Y, ms);
@@ -49,243 +169,170 @@ dg_kernel(DgArgs A, const double* __restrict__ U, const double* __restrict__ Y, 
         yn2p = mbr(yn2p, ms);
         ut2p = mbr(ut2p, ms);
         red = mbr(red, ms);
+        lin0 = mbr(lin0, ms);
     }
-    constexpr int NP = DgShape<N1>::NP, NTH = DgShape<N1>::NTH, EPB = DgShape<N1>::EPB;
-    constexpr int NSt = (MODE == 3) ? 2 : 1;
-    __shared__ double sS[NSt][EPB][4][NP];
-    __shared__ double sFx[EPB][4][NP], sFz[EPB][4][NP];
-    __shared__ double sFc[EPB][4][N1][4];
-    __shared__ double sSy[NS ? EPB : 1][4][N1][4];
+    constexpr int NP = DgShape<N1>::NP, NTH = DgShape<N1>::NTH, EPB = DgShape<N1>::EPB, FPE = DgShape<N1>::FPE;
+    constexpr bool OUTL = MODE != 5;   // the fluxes stay in LDS for the contraction
+    __shared__ double sS[EPB][4][NP];
+    __shared__ double sFx[OUTL ? EPB : 1][4][NP], sFz[OUTL ? EPB : 1][4][NP];
+    __shared__ double sFc[OUTL ? EPB : 1][4][N1][4];
+    __shared__ double sSy[OUTL && NS ? EPB : 1][4][N1][4];
 
     const int t = threadIdx.x;
     const int le = t / NP, nd = t - le * NP;
     const bool act = le < EPB;
-    const long e = (long)xcd_tile(blockIdx.x, gridDim.x) * EPB + le;   // XCD-contiguous element ranges
+    const long eb = (long)xcd_tile(blockIdx.x, gridDim.x) * EPB;   // XCD-contiguous element ranges
+    const long e = eb + le;
     const bool valid = act && e < A.ne;
     const int ez = valid ? (int)(e / A.nx) : 0;
-    const int ex = valid ? (int)(e - (long)ez * A.nx) : 0;
-    const long N = A.ne * NP;
+    const long N = A.ne * NP, NF = A.ne * FPE;
     const RefTab& R = A.R;
+    double* vol0 = lin0;              // [8][N]
+    double* face0 = lin0 + 8 * N;     // [8][NF]
 
+    const unsigned no = (unsigned)(e * NP + nd);   // the thread's node in component arrays
+    // ---- A: stage the element values (JVP: of U' + eps y).  The loads are issued
+    // before the step size is known (it depends on a device scalar). ----
+    double u0[4], y0[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        u0[c] = valid ? ld(U + c * N, no) : 0.0;
+        y0[c] = (MODE == 3 && valid) ? ld(Y + c * N, no) : 0.0;
+    }
     double eps = 0.0;
     if constexpr (MODE == 3) {
         const double yn2 = yn2p[0];
         if (!(yn2 > 0.0)) {   // y = 0: the product is 0 (uniform over the grid)
             if (valid)
-                for (int c = 0; c < 4; ++c) out[c * N + e * NP + nd] = 0.0;
+                for (int c = 0; c < 4; ++c) st(out + c * N, no, 0.0);
             return;
         }
-        eps = eps_mode == 0 ? FdEps<double>::sqrt_eps / sqrt(yn2)
-                            : FdEps<double>::sqrt_eps * sqrt(ut2p[0]) / sqrt(yn2);
+        eps = uniform(eps_mode == 0 ? FdEps<double>::sqrt_eps / sqrt(yn2)
+                                    : FdEps<double>::sqrt_eps * sqrt(ut2p[0]) / sqrt(yn2));
     }
-
-    // ---- A: stage element values ----
-    double yv[4] = {0, 0, 0, 0};
     if (act) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const double u = valid ? U[c * N + e * NP + nd] : 0.0;
-            sS[0][le][c][nd] = u;
-            if constexpr (MODE == 3) {
-                yv[c] = valid ? Y[c * N + e * NP + nd] : 0.0;
-                sS[1][le][c][nd] = u + eps * yv[c];
-            }
-        }
+        for (int c = 0; c < 4; ++c) sS[le][c][nd] = MODE == 3 ? u0[c] + eps * y0[c] : u0[c];
     }
     __syncthreads();
 
     const int a = nd % N1, b = nd / N1;
-    // ---- B: volume fluxes ----
+    // ---- B: volume fluxes (JVP: minus those of U') ----
     if (act) {
         double Ub[4], dUb[4];
         const int zi = ez * N1 + b;
 #pragma unroll
         for (int c = 0; c < 4; ++c) { Ub[c] = A.bg_node[zi * 4 + c]; dUb[c] = A.dbg_node[zi * 4 + c]; }
         const double pbz = A.pb_node[zi], irz = A.irt_node[zi];
-        double fx[4], fz[4];
+        double Ut[4], Fx[4], Fz[4];
 #pragma unroll
-        for (int s = 0; s < NSt; ++s) {
-            double Ut[4], Fx[4], Fz[4];
+        for (int c = 0; c < 4; ++c) Ut[c] = sS[le][c][nd] + Ub[c];
+        const double pt = pert_pressure(A.gas, sS[le][3][nd], irz, pbz);
+        conv_flux_xz(Ut, pt, Fx, Fz);
+        if constexpr (MODE != 3 && MODE != 5) {
+            double Bx[4], Bz[4];
+            conv_flux_xz(Ub, pbz, Bx, Bz);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) Ut[c] = sS[s][le][c][nd] + Ub[c];
-            const double pt = pert_pressure(A.gas, sS[s][le][3][nd], irz, pbz);
-            conv_flux_xz(Ut, pt, Fx, Fz);
-            if constexpr (MODE != 3) {
-                double Bx[4], Bz[4];
-                conv_flux_xz(Ub, pbz, Bx, Bz);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) { Fx[c] -= Bx[c]; Fz[c] -= Bz[c]; }
-            }
-            if constexpr (NS) {
-                // F_v^x and F_v^z: mu (G_c - (U_c/rho) G_rho) with the x- and z-derivatives
-                double Gx[4], Gz[4];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    double sx = 0.0, sz = 0.0;
-#pragma unroll
-                    for (int j = 0; j < N1; ++j) {
-                        sx += R.D[a][j] * sS[s][le][c][b * N1 + j];
-                        sz += R.D[b][j] * sS[s][le][c][j * N1 + a];
-                    }
-                    Gx[c] = (2.0 / A.dx) * sx;
-                    Gz[c] = (2.0 / A.dz) * sz + dUb[c];
-                }
-                const double ir = frcp(Ut[0]);
-#pragma unroll
-                for (int c = 1; c < 4; ++c) {
-                    const double rc = Ut[c] * ir;
-                    Fx[c] -= A.mu * (Gx[c] - rc * Gx[0]);
-                    Fz[c] -= A.mu * (Gz[c] - rc * Gz[0]);
-                }
-            }
-            if (s == 0) {
-#pragma unroll
-                for (int c = 0; c < 4; ++c) { fx[c] = Fx[c]; fz[c] = Fz[c]; }
-            } else {
-#pragma unroll
-                for (int c = 0; c < 4; ++c) { fx[c] = Fx[c] - fx[c]; fz[c] = Fz[c] - fz[c]; }
-            }
+            for (int c = 0; c < 4; ++c) { Fx[c] -= Bx[c]; Fz[c] -= Bz[c]; }
         }
-#pragma unroll
-        for (int c = 0; c < 4; ++c) { sFx[le][c][nd] = fx[c]; sFz[le][c][nd] = fz[c]; }
-    }
-
-    // ---- C: face fluxes; the neighbour element's trace and normal derivative at
-    // the face point come straight from global memory into registers ----
-    if (act) {
-        for (int fp = nd; fp < 4 * N1; fp += NP) {
-            const int f = fp / N1, r = fp - f * N1;
-            const bool xf = f < 2;
-            const int side = (f == 0 || f == 2) ? -1 : 1;
-            const double nxn = xf ? (double)side : 0.0, nzn = xf ? 0.0 : (double)side;
-            const double* es = side > 0 ? R.ep : R.em;
-            const double* ds = side > 0 ? R.dp : R.dm;
-            const double hperp = xf ? A.dx : A.dz;
-            const double flen = xf ? A.dz : A.dx;
-            const int nb = valid ? face_nb(f, ex, ez, A.nx, A.nz, A.bc) : -1;
-            const bool wall = nb < 0;
-            double trx[NSt][4], dnx[NSt][4];   // other side: trace and normal derivative (d/d xi of the neighbour)
-            {
-                const double* eo = side > 0 ? R.em : R.ep;
-                const double* dso = side > 0 ? R.dm : R.dp;
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-#pragma unroll
-                    for (int st = 0; st < NSt; ++st) { trx[st][c] = 0.0; dnx[st][c] = 0.0; }
-                    if (!wall) {
-#pragma unroll
-                        for (int j = 0; j < N1; ++j) {
-                            const int idx = xf ? r * N1 + j : j * N1 + r;
-                            const double v = U[c * N + (long)nb * NP + idx];
-                            trx[0][c] += eo[j] * v;
-                            if constexpr (NS) dnx[0][c] += dso[j] * v;
-                            if constexpr (MODE == 3) {
-                                const double v1 = v + eps * Y[c * N + (long)nb * NP + idx];
-                                trx[1][c] += eo[j] * v1;
-                                if constexpr (NS) dnx[1][c] += dso[j] * v1;
-                            }
-                        }
-                    }
-                }
-            }
-            double Ub[4], dUb[4];
-            const int zrow = xf ? (ez * N1 + r) : (ez + (side > 0 ? 1 : 0));
-            const double* bgp = xf ? A.bg_node : A.bg_face;
-            const double* dbgp = xf ? A.dbg_node : A.dbg_face;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) { Ub[c] = bgp[zrow * 4 + c]; dUb[c] = dbgp[zrow * 4 + c]; }
-            const double pbz = xf ? A.pb_node[zrow] : A.pb_face[zrow];
-            const double irz = xf ? A.irt_node[zrow] : A.irt_face[zrow];
-            double flux[4] = {0, 0, 0, 0}, sym[4] = {0, 0, 0, 0};
-#pragma unroll
-            for (int s = 0; s < NSt; ++s) {
-                double tro[4], Uo[4], Ux[4], H[4];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    double v = 0.0;
-#pragma unroll
-                    for (int j = 0; j < N1; ++j) v += es[j] * sS[s][le][c][xf ? r * N1 + j : j * N1 + r];
-                    tro[c] = v;
-                    Uo[c] = v + Ub[c];
-                }
-                const double po = pert_pressure(A.gas, tro[3], irz, pbz);
-                double px = po;
-                if (wall) {
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) Ux[c] = Uo[c];
-                    if (xf) Ux[1] = -Uo[1]; else Ux[2] = -Uo[2];
-                } else {
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) Ux[c] = trx[s][c] + Ub[c];
-                    px = pert_pressure(A.gas, trx[s][3], irz, pbz);
-                }
-                hllc(A.gas, Uo, Ux, po, px, nxn, nzn, H);
-                double fl[4], sy[4] = {0, 0, 0, 0};
-                if constexpr (MODE != 3) {
-                    double Um[4], Hb[4];
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) Um[c] = Ub[c];
-                    if (wall) { if (xf) Um[1] = -Ub[1]; else Um[2] = -Ub[2]; }
-                    hllc(A.gas, Ub, Um, pbz, pbz, nxn, nzn, Hb);
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) H[c] -= Hb[c];
-                }
-#pragma unroll
-                for (int c = 0; c < 4; ++c) fl[c] = -H[c];
-                if constexpr (NS) {
-                    if (!wall) {
-                        // F_v(U, G) . n of a Cartesian face involves only the normal derivative
-                        // G_n (the tangential part enters multiplied by 0): own side from the
-                        // element's values, other side from the neighbour's trace derivative,
-                        // plus the background's z-derivative on z-faces
-                        const double gs = 2.0 / hperp, sg = (double)side;
-                        const double iro = frcp(Uo[0]), irx = frcp(Ux[0]);
-                        double Gno[4], Gnx[4];
-#pragma unroll
-                        for (int c = 0; c < 4; ++c) {
-                            double sn = 0.0;
-#pragma unroll
-                            for (int j = 0; j < N1; ++j) sn += ds[j] * sS[s][le][c][xf ? r * N1 + j : j * N1 + r];
-                            const double db = xf ? 0.0 : dUb[c];
-                            Gno[c] = gs * sn + db;
-                            Gnx[c] = gs * dnx[s][c] + db;
-                        }
-                        const double eta = A.c_ip * (double)(N1 * N1) / hperp;
-                        const double Dl0 = tro[0] - trx[s][0];
-                        const double irm = frcp(0.5 * (Uo[0] + Ux[0]));
-#pragma unroll
-                        for (int c = 1; c < 4; ++c) {
-                            const double ro = Uo[c] * iro;
-                            const double Fo = sg * A.mu * (Gno[c] - ro * Gno[0]);
-                            const double Fxx = sg * A.mu * (Gnx[c] - Ux[c] * irx * Gnx[0]);
-                            const double Dlc = tro[c] - trx[s][c];
-                            const double pen = eta * A.mu * (Dlc - (0.5 * (Uo[c] + Ux[c]) * irm) * Dl0);
-                            fl[c] += 0.5 * (Fo + Fxx) - pen;
-                            sy[c] = 0.5 * A.mu * (Dlc - ro * Dl0);
-                        }
-                    }
-                }
-                if (s == 0) {
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) { flux[c] = fl[c]; sym[c] = sy[c]; }
-                } else {
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) { flux[c] = fl[c] - flux[c]; sym[c] = sy[c] - sym[c]; }
-                }
-            }
-            const double W = R.w[r] * flen * 0.5;
+        if constexpr (NS) {
+            // F_v^x and F_v^z: mu (G_c - (U_c/rho) G_rho) with the x- and z-derivatives
+            double Gx[4], Gz[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                sFc[le][f][r][c] = W * flux[c];
-                if constexpr (NS) sSy[le][f][r][c] = W * sym[c];
+                double sx = 0.0, sz = 0.0;
+#pragma unroll
+                for (int j = 0; j < N1; ++j) {
+                    sx += R.D[a][j] * sS[le][c][b * N1 + j];
+                    sz += R.D[b][j] * sS[le][c][j * N1 + a];
+                }
+                Gx[c] = A.rdx2 * sx;
+                Gz[c] = A.rdz2 * sz + dUb[c];
+            }
+            const double ir = frcp(Ut[0]);
+#pragma unroll
+            for (int c = 1; c < 4; ++c) {
+                const double rc = Ut[c] * ir;
+                Fx[c] -= A.mu * (Gx[c] - rc * Gx[0]);
+                Fz[c] -= A.mu * (Gz[c] - rc * Gz[0]);
             }
         }
+        if constexpr (MODE == 5) {
+            if (valid) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) { st(vol0 + c * N, no, Fx[c]); st(vol0 + (4 + c) * N, no, Fz[c]); }
+            }
+        } else {
+            if constexpr (MODE == 3) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    Fx[c] = Fx[c] - (valid ? ld(vol0 + c * N, no) : 0.0);
+                    Fz[c] = Fz[c] - (valid ? ld(vol0 + (4 + c) * N, no) : 0.0);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) { sFx[le][c][nd] = Fx[c]; sFz[le][c][nd] = Fz[c]; }
+        }
     }
+
+    // ---- C: face terms (JVP: minus those of U'); the neighbour element's trace
+    // and normal derivative at the face point come straight from global memory
+    // into registers.  With k = 3 (16 face points and 16 threads per element)
+    // wave 0 takes the faces with outward normal -e_x / -e_z of all eight
+    // elements and wave 1 those with +e_x / +e_z, so that the side, and with it
+    // every trace weight, is uniform per wave. ----
+    auto face_point = [&](int fle, int f, int r, bool pos) {
+        const int fe = (int)eb + fle;
+        const bool fvalid = fe < A.ne;
+        const int fez = fvalid ? fe / A.nx : 0;
+        const int fex = fvalid ? fe - fez * A.nx : 0;
+        const int nb = fvalid ? face_nb(f, fex, fez, A.nx, A.nz, A.bc) : -1;
+        const bool xf = f < 2;
+        const unsigned q = (unsigned)fe * FPE + f * N1 + r;
+        double fl[4], sy[4];
+        dg_face<N1, NS, MODE != 3 && MODE != 5, MODE == 3>(A, sS[fle], U, Y, eps, N, nb, xf, pos, r, fez, fl, sy);
+        if constexpr (MODE == 5) {
+            if (fvalid) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    st(face0 + c * NF, q, fl[c]);
+                    if constexpr (NS) st(face0 + (4 + c) * NF, q, sy[c]);
+                }
+            }
+            return;
+        }
+        if constexpr (MODE == 3) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                fl[c] = fl[c] - (fvalid ? ld(face0 + c * NF, q) : 0.0);
+                if constexpr (NS) sy[c] = sy[c] - (fvalid ? ld(face0 + (4 + c) * NF, q) : 0.0);
+            }
+        }
+        const double W = R.w[r] * (xf ? A.dz : A.dx) * 0.5;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            sFc[fle][f][r][c] = W * fl[c];
+            if constexpr (NS) sSy[fle][f][r][c] = W * sy[c];
+        }
+    };
+    if constexpr (N1 == 4 && NTH == 128) {
+        const int w = __builtin_amdgcn_readfirstlane(t >> 6);   // wave index, uniform
+        const int l = t & 63, qf = l & 7;
+        face_point(l >> 3, ((qf >> 2) << 1) | w, qf & 3, w != 0);
+    } else if (act) {
+        for (int fp = nd; fp < FPE; fp += NP) {
+            const int f = fp / N1;
+            face_point(le, f, fp - f * N1, (f & 1) != 0);
+        }
+    }
+    if constexpr (MODE == 5) return;
     __syncthreads();
 
     // ---- D: contraction, lifting and output ----
     double nrm = 0.0;
     if (valid) {
+        const double* Ud = opaque(U);   // U' and y are read again here
+        const double* Yd = opaque(Y);
         const double m = R.w[a] * R.w[b] * A.J, im = frcp(m);
         const double sc = MODE == 3 ? adt / eps : 0.0;
 #pragma unroll
@@ -295,30 +342,33 @@ dg_kernel(DgArgs A, const double* __restrict__ U, const double* __restrict__ Y, 
             for (int q = 0; q < N1; ++q) sx += R.w[q] * R.D[q][a] * sFx[le][c][b * N1 + q];
 #pragma unroll
             for (int q = 0; q < N1; ++q) sz += R.w[q] * R.D[q][b] * sFz[le][c][q * N1 + a];
-            double L = A.J * ((2.0 / A.dx) * R.w[b] * sx + (2.0 / A.dz) * R.w[a] * sz);
+            double L = A.J * (A.rdx2 * R.w[b] * sx + A.rdz2 * R.w[a] * sz);
             L += sFc[le][0][b][c] * R.em[a] + sFc[le][1][b][c] * R.ep[a];
             L += sFc[le][2][a][c] * R.em[b] + sFc[le][3][a][c] * R.ep[b];
             if constexpr (NS) {
-                L += sSy[le][0][b][c] * (-(2.0 / A.dx) * R.dm[a]) + sSy[le][1][b][c] * ((2.0 / A.dx) * R.dp[a]);
-                L += sSy[le][2][a][c] * (-(2.0 / A.dz) * R.dm[b]) + sSy[le][3][a][c] * ((2.0 / A.dz) * R.dp[b]);
+                L += sSy[le][0][b][c] * (-A.rdx2 * R.dm[a]) + sSy[le][1][b][c] * (A.rdx2 * R.dp[a]);
+                L += sSy[le][2][a][c] * (-A.rdz2 * R.dm[b]) + sSy[le][3][a][c] * (A.rdz2 * R.dp[b]);
             }
             if (c == 2) {
-                if constexpr (MODE == 3) L += m * (-A.g * (sS[1][le][0][nd] - sS[0][le][0][nd]));
-                else L += m * (-A.g * sS[0][le][0][nd]);
+                // gravity; JVP: of (U' + eps y)_rho - U'_rho
+                if constexpr (MODE == 3) L += m * (-A.g * (sS[le][0][nd] - ld(Ud, no)));
+                else L += m * (-A.g * sS[le][0][nd]);
             }
-            const long o = c * N + e * NP + nd;
-            if constexpr (MODE == 0) out[o] = L;
-            else if constexpr (MODE == 1) out[o] = L * im;
+            if constexpr (MODE == 0) st(out + c * N, no, L);
+            else if constexpr (MODE == 1) st(out + c * N, no, L * im);
             else if constexpr (MODE == 2) {
-                const double G = sS[0][le][c][nd] - adt * (L * im) - Ubar[o];
-                out[o] = G;
+                const double G = sS[le][c][nd] - adt * (L * im) - ld(Ubar + c * N, no);
+                st(out + c * N, no, G);
                 nrm += G * G;
             } else if constexpr (MODE == 3) {
-                out[o] = yv[c] - sc * (L * im);
+                st(out + c * N, no, ld(Yd + c * N, no) - sc * (L * im));
             } else {   // explicit Runge-Kutta stage
-                const double base = rk.a0 != 0.0 ? rk.a0 * Ubar[o] : 0.0;
-                out[o] = base + rk.a1 * sS[0][le][c][nd] + rk.c * (L * im);
+                const double base = rk.a0 != 0.0 ? rk.a0 * ld(Ubar + c * N, no) : 0.0;
+                st(out + c * N, no, base + rk.a1 * sS[le][c][nd] + rk.c * (L * im));
             }
+            // one component at a time: keeps the LDS reads of the next component
+            // from being hoisted into this one (register pressure)
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
     if constexpr (MODE == 2) put_partial<NTH>(red, nrm);
@@ -331,10 +381,15 @@ int dg_grid(int k, long ne)
 }
 
 template <int N1, bool NS>
-static void launch_dg_n(int mode, const DgArgs& A, const double* U, const double* Y, const double* Ubar,
+static void launch_dg_n(int mode, const DgArgs& A0, const double* U, const double* Y, const double* Ubar,
                         double* out, const double* yn2, const double* ut2, int eps_mode, double adt, Red red,
                         hipStream_t st, const Mb& mb, const ExStage& ex)
 {
+    DgArgs A = A0;
+    A.rdx2 = 2.0 / A.dx;
+    A.rdz2 = 2.0 / A.dz;
+    A.eta_x = A.c_ip * (double)(N1 * N1) / A.dx;
+    A.eta_z = A.c_ip * (double)(N1 * N1) / A.dz;
     const dim3 grid(dg_grid(N1 - 1, A.ne), 1, mb.n), block(DgShape<N1>::NTH);
     if (mode == 2 && red.out) {
         timed_launch(dg_kernel<N1, NS, 2>, grid, block, st, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, mb.ms,
@@ -352,6 +407,7 @@ static void launch_dg_n(int mode, const DgArgs& A, const double* U, const double
         JFMG_DG_CASE(1)
         JFMG_DG_CASE(2)
         JFMG_DG_CASE(4)
+        JFMG_DG_CASE(5)
     default:
         timed_launch(dg_kernel<N1, NS, 3>, grid, block, st, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, mb.ms,
                      ex);

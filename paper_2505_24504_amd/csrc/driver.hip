@@ -308,7 +308,7 @@ struct jfmg_problem {
     int xcnt[MAXLEV][3];
     double* bg_node; double* dbg_node; double* th_node; double* bg_face; double* dbg_face;
     double* pb_node; double* pb_face;   // [.][2]: background pressure, 1/(rho theta)
-    double *Un, *Ubar, *Uk, *G, *delta, *tmp1, *tmp2, *Ulin;
+    double *Un, *Ubar, *Uk, *G, *delta, *tmp1, *tmp2, *Ulin, *lin0;
     double *V, *Z;
     int m;
     Mb mb;   // members of a lock-step batch (1 for a single problem) and their byte stride
@@ -427,6 +427,9 @@ jfmg_status validate(const jfmg_config& c, Key& key, std::string& msg)
     if (c.batch < 0 || c.batch > 4096) { msg = "batch must be in 0..4096"; return JFMG_EINVAL; }
     if (c.k < 1 || c.k > 3) { msg = "k must be 1, 2 or 3"; return JFMG_EINVAL; }
     if (c.nx < 1 || c.nz < 1) { msg = "nx, nz must be positive"; return JFMG_EINVAL; }
+    // node arrays are addressed with 32-bit byte offsets per component (far above
+    // what a workspace of 288 GB can hold)
+    if ((long)c.nx * c.nz * (c.k + 1) * (c.k + 1) > (1L << 28)) { msg = "grid too large"; return JFMG_EINVAL; }
     if (!(c.x1 > c.x0) || !(c.z1 > c.z0)) { msg = "empty domain"; return JFMG_EINVAL; }
     if (c.physics < 0 || c.physics > 1 || c.background < 0 || c.background > 1 || c.bc < 0 || c.bc > 1 ||
         c.scheme < 0 || c.scheme > 1) { msg = "physics/background/bc/scheme out of range"; return JFMG_EINVAL; }
@@ -483,6 +486,7 @@ size_t layout(const jfmg_config& c, char* base, F&& bind)
     bind("pb_face", cv.take((size_t)(c.nz + 1) * 2 * 8), 0);
     const char* dgn[] = {"Un", "Ubar", "Uk", "G", "delta", "tmp1", "tmp2", "Ulin"};
     for (const char* s : dgn) bind(s, cv.take((size_t)N * 8), 0);
+    bind("lin0", cv.take((size_t)lin_doubles(c.k, ne) * 8), 0);
     bind("V", cv.take((size_t)N * 8 * (m + 1)), 0);
     bind("Z", cv.take((size_t)N * 8 * m), 0);
     int nxl = n1 * c.nx, nzl = n1 * c.nz;
@@ -587,6 +591,12 @@ template <typename T> jfmg_status linearize_t(jfmg_problem* p, const double* U, 
     if (U != p->Ulin) HIPCHK(p, copy_members(p, p->Ulin, U, sizeof(double) * p->N));
     p->adt = adt;
     launch_norm2_total(p->cfg.k, p->A, p->Ulin, red_at(p, S_UTOT), st, p->mb);
+    {
+        // the volume fluxes and face terms of U' that every product with this state differences against
+        ProfScope ps(p, JFMG_K_DG_LINEARIZE, (double)p->N * 8 + 8.0 * lin_doubles(p->cfg.k, p->ne));
+        launch_dg(p->cfg.k, p->cfg.physics == 1, 5, p->A, p->Ulin, nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0.0,
+                  no_red(), st, p->mb);
+    }
     launch_transfer_T<T>(p->cfg.k, p->A, mass_fix_of(p), p->Ulin, (T*)p->lev[0].u, p->lev[0].nx, st, nullptr, nullptr,
                          p->mb);
     for (int l = 0; l + 1 < p->nlev; ++l)
@@ -793,7 +803,7 @@ template <typename T> jfmg_status mg_apply_t(jfmg_problem* p, double* r, double*
 // out = G'(U_lin) y with ||y||^2 already in slot yslot
 void jvp_slot(jfmg_problem* p, const double* y, double* out, int yslot)
 {
-    ProfScope ps(p, JFMG_K_DG_JVP, 3.0 * p->N * 8);
+    ProfScope ps(p, JFMG_K_DG_JVP, 3.0 * p->N * 8 + 8.0 * lin_doubles(p->cfg.k, p->ne));
     launch_dg(p->cfg.k, p->cfg.physics == 1, 3, p->A, p->Ulin, y, nullptr, out, p->scal + yslot, p->scal + S_UTOT,
               p->cfg.fd_eps_mode, p->adt, no_red(), p->st, p->mb);
     p->jvp_count++;
@@ -1385,6 +1395,7 @@ jfmg_status jfmg_create_problem(const jfmg_config* cfg, void* workspace, size_t 
         else if (nm == "tmp1") p->tmp1 = (double*)ptr;
         else if (nm == "tmp2") p->tmp2 = (double*)ptr;
         else if (nm == "Ulin") p->Ulin = (double*)ptr;
+        else if (nm == "lin0") p->lin0 = (double*)ptr;
         else if (nm == "V") p->V = (double*)ptr;
         else if (nm == "Z") p->Z = (double*)ptr;
         else {
@@ -1501,6 +1512,7 @@ jfmg_status jfmg_create_problem(const jfmg_config* cfg, void* workspace, size_t 
     A.pb_node = p->pb_node; A.irt_node = p->pb_node + (size_t)cfg->nz * p->n1;
     A.pb_face = p->pb_face; A.irt_face = p->pb_face + (cfg->nz + 1);
     A.R = p->R;
+    A.lin0 = p->lin0;
     *out = p;
     return JFMG_OK;
 }

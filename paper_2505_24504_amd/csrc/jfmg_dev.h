@@ -65,6 +65,37 @@ template <typename T> __device__ __forceinline__ T dabs(T a)
     else return fabs(a);
 }
 
+// Element i of an array addressed by a 32-bit byte offset from its base (usually
+// wave-uniform, in scalar registers): one vector register per address instead of
+// two.  Arrays must be smaller than 4 GiB.
+template <typename T> __device__ __forceinline__ T ld(const T* base, unsigned i)
+{
+    return *(const T*)((const char*)base + i * (unsigned)sizeof(T));
+}
+template <typename T> __device__ __forceinline__ void st(T* base, unsigned i, T v)
+{
+    *(T*)((char*)base + i * (unsigned)sizeof(T)) = v;
+}
+
+// The same (wave-uniform) pointer, opaque to the optimizer: loads through it are
+// issued again instead of being merged with earlier loads of the same address,
+// whose values would otherwise be held in registers in between.
+template <typename T> __device__ __forceinline__ T* opaque(T* p)
+{
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
+// A value that is the same in every lane of the wave, moved to scalar registers
+// (keeps it out of the vector register budget).
+__device__ __forceinline__ double uniform(double v)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 // Reciprocal from the hardware estimate refined by Newton's iteration for 1/a,
 // r <- r + r (1 - a r): the FP64 estimate (relative error ~5e-8) needs two steps
 // to reach the accuracy of a correctly rounded division (measured: within one ulp,
@@ -224,6 +255,27 @@ __device__ __forceinline__ void hllc_ax(const Gas<T>& G, const T* UL, const T* U
     F[D] = (Ss * (SK * uD - (uD * qK + pK)) + SK * pst) * iden;
     F[E] = (Ss * (SK * uE - uE * qK)) * iden;
     F[3] = (Ss * (SK * u3 - u3 * qK)) * iden;
+}
+
+// HLLC flux F . n on a Cartesian face whose normal n = side e_D (side = +-1) has
+// its axis chosen per thread (xf: D = 1, else D = 2), so that the lanes of a wave
+// working on x- and z-faces take one path: both states are rotated into the face
+// frame (normal momentum side U_D, tangential U_E), the one-dimensional form above
+// is evaluated there and its normal-momentum component rotated back (F_D = side
+// times it).  Multiplication by +-1 and the component swap are exact.
+template <typename T>
+__device__ __forceinline__ void hllc_face(const Gas<T>& G, const T* UL, const T* UR, T pL, T pR, T irL, T irR,
+                                          bool xf, T side, T* F)
+{
+    const T a[4] = {UL[0], side * (xf ? UL[1] : UL[2]), xf ? UL[2] : UL[1], UL[3]};
+    const T b[4] = {UR[0], side * (xf ? UR[1] : UR[2]), xf ? UR[2] : UR[1], UR[3]};
+    T Fn[4];
+    hllc_ax<T, 1>(G, a, b, pL, pR, irL, irR, Fn);
+    const T fd = side * Fn[1];
+    F[0] = Fn[0];
+    F[1] = xf ? fd : Fn[2];
+    F[2] = xf ? Fn[2] : fd;
+    F[3] = Fn[3];
 }
 
 // Viscous flux F_v(U, G) . n = mu rho grad(U_c / rho) . n written with the

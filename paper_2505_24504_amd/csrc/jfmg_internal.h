@@ -107,6 +107,9 @@ struct DgArgs {
     long ne;
     int nx, nz, bc, physics;
     double dx, dz, J, g, mu, c_ip;
+    // set by the launcher from dx, dz and c_ip: 2/dx, 2/dz and the interior
+    // penalty factors c_ip (k+1)^2 / h of x- and z-faces
+    double rdx2, rdz2, eta_x, eta_z;
     Gas<double> gas;
     const double* bg_node;   // [nz*(k+1)][4] background at the z of each node row
     const double* dbg_node;  // [nz*(k+1)][4] d/dz of it
@@ -117,6 +120,11 @@ struct DgArgs {
     const double* irt_node;
     const double* pb_face;   // [nz+1]        the same at element z-faces
     const double* irt_face;
+    // fluxes of the linearization state U', written once per linearization (mode 5)
+    // and read by every product with it (mode 3): the volume fluxes F^x, F^z per
+    // node, [8][ne (k+1)^2], then the face terms per face point of every element,
+    // [8][ne 4 (k+1)] (flux, then the symmetric term's jump); lin_doubles() long
+    double* lin0 = nullptr;
     RefTab R;
 };
 
@@ -150,12 +158,15 @@ struct Mb {
 //         yn2 = ||Y||^2 and ut2 = ||U + Ubar||^2 (eps_mode 1)
 // mode 4: explicit Runge-Kutta stage out = ex.a0 Ubar + ex.a1 U + ex.c M^-1 L(U)
 //         (out must not alias U: neighbour traces are read from U by other blocks)
+// mode 5: the fluxes of U into A.lin0 (the linearization state of mode 3's products)
 struct ExStage {
     double a0 = 0.0, a1 = 1.0, c = 0.0;
 };
 void launch_dg(int k, bool ns, int mode, const DgArgs& A, const double* U, const double* Y,
                const double* Ubar, double* out, const double* yn2, const double* ut2, int eps_mode,
                double adt, Red red, hipStream_t st, const Mb& mb = Mb{}, const ExStage& ex = ExStage{});
+// doubles of DgArgs::lin0 for degree k and ne elements
+inline long lin_doubles(int k, long ne) { return 8 * ne * (k + 1) * (k + 1) + 8 * ne * 4 * (k + 1); }
 int transfer_grid(int k, long ne);
 int dg_grid(int k, long ne);
 void launch_initial_state(int k, const DgArgs& A, int shape, double amp, double xc, double zc,

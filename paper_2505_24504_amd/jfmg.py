@@ -75,7 +75,7 @@ TILES = ["64x4", "64x8", "16x4", "8x4", "32x4", "64x4_512"]
 
 KERNEL_CLASSES = ["dg_residual", "dg_jvp", "fv_stage", "fv_stage_zero", "fv_defect_restrict",
                   "fv_prolong_correct", "fv_linearize", "transfer_T", "transfer_Tinv", "multidot",
-                  "update", "fv_stage_small", "dg_smooth"]
+                  "update", "fv_stage_small", "dg_smooth", "dg_linearize"]
 
 
 def load_library(path: str = LIB_PATH):
