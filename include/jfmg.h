@@ -174,6 +174,27 @@ jfmg_status jfmg_mg_apply(jfmg_problem* p, const double* r, double* z);
    jfmg_autotune accept batched problems; the other calls return EINVAL.  Stats
    count the lock-step iterations. */
 
+/* ---- ragged batches: ensemble members of different grid sizes ----
+   n configurations that differ only in nx, nz and the domain (x0, x1, z0, z1)
+   form one lock-step batch: every member has a workspace region laid out for the
+   envelope grid (the largest nx and nz), a device table carries each member's
+   sizes, geometry and background tables, and every kernel still covers all
+   members in one launch (grid z = member): its work-groups beyond a smaller
+   member's elements or tiles stay idle and store zero partial sums, so each
+   member's result is bitwise the one it gives as a single problem with the same
+   FV tile shapes (the tile shapes apply to all members).  State vectors are the
+   members' DG vectors back to back, member m with jfmg_member_dofs(p, m)
+   entries; initial states come from single problems.  The calls accepted are
+   those of lock-step batches except jfmg_initial_state; the multigrid key must
+   not use DG-level smoothing (a, b = 0).  EINVAL for members that differ in
+   anything else, ENOMEM for a short workspace. */
+jfmg_status jfmg_ensemble_workspace_bytes(const jfmg_config* cfgs, int n, size_t* bytes);
+jfmg_status jfmg_create_ensemble(const jfmg_config* cfgs, int n, void* workspace, size_t ws_bytes,
+                                 void* hip_stream, jfmg_problem** out);
+/* DG entries of member `member` (N of a single problem or a lock-step batch's
+   member; 0 for a member index out of range). */
+size_t jfmg_member_dofs(const jfmg_problem* p, int member);
+
 /* One implicit step U^n -> U^{n+1} in place (implicit Euler or SDIRK2), each
    stage by inexact Newton with Eisenstat-Walker forcing and right-preconditioned
    FGMRES (Sec. "Solver").  On any error U is left unchanged.  stats may be NULL.

@@ -154,12 +154,13 @@ __device__ __forceinline__ void dg_face(const DgArgs& A, const double (&sv)[4][N
 
 // k = 3: at most 128 VGPRs (four waves per SIMD) and 20 KB of LDS per 128-thread
 // work-group, so that eight work-groups fit per CU; lower degrees at most 168.
-template <int N1, bool NS, int MODE>
+template <int N1, bool NS, int MODE, bool RG>
 __global__ void __launch_bounds__(DgShape<N1>::NTH, N1 == 4 ? 4 : 3)
-dg_kernel(DgArgs A, const double* __restrict__ U, const double* __restrict__ Y, const double* __restrict__ Ubar,
-          double* __restrict__ out, const double* __restrict__ yn2p, const double* __restrict__ ut2p, int eps_mode,
-          double adt, Red red, long ms, ExStage rk)
+dg_kernel(DgArgs Aa, const MemberArgs* __restrict__ mt, const double* __restrict__ U, const double* __restrict__ Y,
+          const double* __restrict__ Ubar, double* __restrict__ out, const double* __restrict__ yn2p,
+          const double* __restrict__ ut2p, int eps_mode, double adt, Red red, long ms, ExStage rk)
 {
+    const DgArgs& A = dg_of<RG>(Aa, mt);
     double* lin0 = A.lin0;
     if (gridDim.z > 1) {   // member of a lock-step batch
         U = mbr(U, ms);
@@ -169,9 +170,14 @@ dg_kernel(DgArgs A, const double* __restrict__ U, const double* __restrict__ Y, 
         yn2p = mbr(yn2p, ms);
         ut2p = mbr(ut2p, ms);
         red = mbr(red, ms);
-        lin0 = mbr(lin0, ms);
+        if (!RG) lin0 = mbr(lin0, ms);   // a ragged member's pointer is its own
     }
     constexpr int NP = DgShape<N1>::NP, NTH = DgShape<N1>::NTH, EPB = DgShape<N1>::EPB, FPE = DgShape<N1>::FPE;
+    const int nbm = (int)((A.ne + EPB - 1) / EPB);   // this member's work-groups
+    if ((int)blockIdx.x >= nbm) {                     // beyond a smaller member of a ragged batch
+        if (MODE == 2 && threadIdx.x == 0) red.partials[block_linear()] = 0.0;
+        return;
+    }
     constexpr bool OUTL = MODE != 5;   // the fluxes stay in LDS for the contraction
     __shared__ double sS[EPB][4][NP];
     __shared__ double sFx[OUTL ? EPB : 1][4][NP], sFz[OUTL ? EPB : 1][4][NP];
@@ -181,7 +187,7 @@ dg_kernel(DgArgs A, const double* __restrict__ U, const double* __restrict__ Y, 
     const int t = threadIdx.x;
     const int le = t / NP, nd = t - le * NP;
     const bool act = le < EPB;
-    const long eb = (long)xcd_tile(blockIdx.x, gridDim.x) * EPB;   // XCD-contiguous element ranges
+    const long eb = (long)xcd_tile(blockIdx.x, nbm) * EPB;   // XCD-contiguous element ranges
     const long e = eb + le;
     const bool valid = act && e < A.ne;
     const int ez = valid ? (int)(e / A.nx) : 0;
@@ -380,7 +386,7 @@ int dg_grid(int k, long ne)
     return (int)((ne + epb - 1) / epb);
 }
 
-template <int N1, bool NS>
+template <int N1, bool NS, bool RG>
 static void launch_dg_n(int mode, const DgArgs& A0, const double* U, const double* Y, const double* Ubar,
                         double* out, const double* yn2, const double* ut2, int eps_mode, double adt, Red red,
                         hipStream_t st, const Mb& mb, const ExStage& ex)
@@ -392,15 +398,15 @@ static void launch_dg_n(int mode, const DgArgs& A0, const double* U, const doubl
     A.eta_z = A.c_ip * (double)(N1 * N1) / A.dz;
     const dim3 grid(dg_grid(N1 - 1, A.ne), 1, mb.n), block(DgShape<N1>::NTH);
     if (mode == 2 && red.out) {
-        timed_launch(dg_kernel<N1, NS, 2>, grid, block, st, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, mb.ms,
-                     ex);
+        timed_launch(dg_kernel<N1, NS, 2, RG>, grid, block, st, A, mb.tab, U, Y, Ubar, out, yn2, ut2, eps_mode, adt,
+                     red, mb.ms, ex);
         launch_finalize(red.partials, (int)grid.x, 1, red.out, st, Gate{}, mb);
         return;
     }
-#define JFMG_DG_CASE(M)                                                                                             \
-    case M:                                                                                                         \
-        timed_launch(dg_kernel<N1, NS, M>, grid, block, st, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, mb.ms, \
-                     ex);                                                                                           \
+#define JFMG_DG_CASE(M)                                                                                            \
+    case M:                                                                                                        \
+        timed_launch(dg_kernel<N1, NS, M, RG>, grid, block, st, A, mb.tab, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, \
+                     red, mb.ms, ex);                                                                              \
         break;
     switch (mode) {
         JFMG_DG_CASE(0)
@@ -409,23 +415,34 @@ static void launch_dg_n(int mode, const DgArgs& A0, const double* U, const doubl
         JFMG_DG_CASE(4)
         JFMG_DG_CASE(5)
     default:
-        timed_launch(dg_kernel<N1, NS, 3>, grid, block, st, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, mb.ms,
-                     ex);
+        timed_launch(dg_kernel<N1, NS, 3, RG>, grid, block, st, A, mb.tab, U, Y, Ubar, out, yn2, ut2, eps_mode, adt,
+                     red, mb.ms, ex);
         break;
     }
 #undef JFMG_DG_CASE
+}
+
+template <int N1>
+static void launch_dg_k(bool ns, int mode, const DgArgs& A, const double* U, const double* Y, const double* Ubar,
+                        double* out, const double* yn2, const double* ut2, int eps_mode, double adt, Red red,
+                        hipStream_t st, const Mb& mb, const ExStage& ex)
+{
+    if (mb.tab) {
+        if (ns) launch_dg_n<N1, true, true>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb, ex);
+        else launch_dg_n<N1, false, true>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb, ex);
+    } else {
+        if (ns) launch_dg_n<N1, true, false>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb, ex);
+        else launch_dg_n<N1, false, false>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb, ex);
+    }
 }
 
 void launch_dg(int k, bool ns, int mode, const DgArgs& A, const double* U, const double* Y, const double* Ubar,
                double* out, const double* yn2, const double* ut2, int eps_mode, double adt, Red red, hipStream_t st,
                const Mb& mb, const ExStage& ex)
 {
-    if (k == 1) { if (ns) launch_dg_n<2, true>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb, ex);
-                  else launch_dg_n<2, false>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb, ex); }
-    else if (k == 2) { if (ns) launch_dg_n<3, true>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb, ex);
-                       else launch_dg_n<3, false>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb, ex); }
-    else { if (ns) launch_dg_n<4, true>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb, ex);
-           else launch_dg_n<4, false>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb, ex); }
+    if (k == 1) launch_dg_k<2>(ns, mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb, ex);
+    else if (k == 2) launch_dg_k<3>(ns, mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb, ex);
+    else launch_dg_k<4>(ns, mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb, ex);
 }
 
 // ---------------------------------------------------------------------------
@@ -477,15 +494,18 @@ void launch_initial_state(int k, const DgArgs& A, int shape, double amp, double 
 }
 
 // sum over all nodes and components of (U' + Ubar)^2
-template <int N1>
-__global__ void __launch_bounds__(256) norm_total_kernel(DgArgs A, const double* __restrict__ U, Red red, long ms)
+template <int N1, bool RG>
+__global__ void __launch_bounds__(256)
+norm_total_kernel(DgArgs Aa, const MemberArgs* __restrict__ mt, const double* __restrict__ U, Red red, long ms)
 {
+    const DgArgs& A = dg_of<RG>(Aa, mt);
     U = mbr(U, ms);
     red = mbr(red, ms);
     constexpr int NP = N1 * N1;
     const long n = A.ne * NP;
+    const long nb = (n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024;   // this member's work-groups
     double s = 0.0;
-    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += nb * 256) {
         const long e = i / NP;
         const int b = (int)(i - e * NP) / N1;
         const int zi = (int)(e / A.nx) * N1 + b;
@@ -495,7 +515,7 @@ __global__ void __launch_bounds__(256) norm_total_kernel(DgArgs A, const double*
             s += v * v;
         }
     }
-    put_partial<256>(red, s);
+    put_partial<256>(red, s);   // 0 from the work-groups beyond a smaller member
 }
 
 int norm_total_grid(long n)
@@ -504,13 +524,20 @@ int norm_total_grid(long n)
     return (int)(b < 1024 ? b : 1024);
 }
 
+template <int N1>
+static void launch_norm_total_k(const DgArgs& A, const double* U, Red red, hipStream_t st, const Mb& mb, dim3 grid)
+{
+    if (mb.tab) norm_total_kernel<N1, true><<<grid, dim3(256), 0, st>>>(A, mb.tab, U, red, mb.ms);
+    else norm_total_kernel<N1, false><<<grid, dim3(256), 0, st>>>(A, nullptr, U, red, mb.ms);
+}
+
 void launch_norm2_total(int k, const DgArgs& A, const double* U, Red red, hipStream_t st, const Mb& mb)
 {
     const long n = A.ne * (k + 1) * (k + 1);
-    const dim3 grid(norm_total_grid(n), 1, mb.n), block(256);
-    if (k == 1) norm_total_kernel<2><<<grid, block, 0, st>>>(A, U, red, mb.ms);
-    else if (k == 2) norm_total_kernel<3><<<grid, block, 0, st>>>(A, U, red, mb.ms);
-    else norm_total_kernel<4><<<grid, block, 0, st>>>(A, U, red, mb.ms);
+    const dim3 grid(norm_total_grid(n), 1, mb.n);
+    if (k == 1) launch_norm_total_k<2>(A, U, red, st, mb, grid);
+    else if (k == 2) launch_norm_total_k<3>(A, U, red, st, mb, grid);
+    else launch_norm_total_k<4>(A, U, red, st, mb, grid);
     launch_finalize(red.partials, (int)grid.x, 1, red.out, st, Gate{}, mb);
 }
 

@@ -312,6 +312,11 @@ struct jfmg_problem {
     double *V, *Z;
     int m;
     Mb mb;   // members of a lock-step batch (1 for a single problem) and their byte stride
+    // ragged batch: members of different grid sizes, each in an envelope-sized region;
+    // DG length and offset of each member in the caller's (packed) state vectors
+    bool ragged = false;
+    std::vector<long> mlen, moff;
+    MemberArgs* tab = nullptr;   // device member table (in the workspace, after the members)
     // kernel-class timing (HIP events on st), used by the benchmark
     struct Pend { int cls; hipEvent_t a, b; double bytes; };
     struct Prof {
@@ -515,6 +520,33 @@ hipError_t copy_members(jfmg_problem* p, void* dst, const void* src, size_t byte
     return hipMemcpy2DAsync(dst, (size_t)p->mb.ms, src, (size_t)p->mb.ms, bytes, (size_t)p->mb.n,
                             hipMemcpyDeviceToDevice, p->st);
 }
+// the caller's state vectors hold the members back to back (each its own length);
+// in the workspace member m starts m * ms bytes after member 0
+hipError_t members_in(jfmg_problem* p, double* ws, const double* user)
+{
+    const size_t vb = sizeof(double) * p->N;
+    if (p->mb.n == 1) return hipMemcpyAsync(ws, user, vb, hipMemcpyDeviceToDevice, p->st);
+    if (!p->ragged)
+        return hipMemcpy2DAsync(ws, (size_t)p->mb.ms, user, vb, vb, (size_t)p->mb.n, hipMemcpyDeviceToDevice, p->st);
+    hipError_t e = hipSuccess;
+    for (int m = 0; m < p->mb.n && !e; ++m)
+        e = hipMemcpyAsync((char*)ws + (size_t)m * p->mb.ms, user + p->moff[m], sizeof(double) * p->mlen[m],
+                           hipMemcpyDeviceToDevice, p->st);
+    return e;
+}
+hipError_t members_out(jfmg_problem* p, double* user, const double* ws)
+{
+    const size_t vb = sizeof(double) * p->N;
+    if (p->mb.n == 1) return hipMemcpyAsync(user, ws, vb, hipMemcpyDeviceToDevice, p->st);
+    if (!p->ragged)
+        return hipMemcpy2DAsync(user, vb, ws, (size_t)p->mb.ms, vb, (size_t)p->mb.n, hipMemcpyDeviceToDevice, p->st);
+    hipError_t e = hipSuccess;
+    for (int m = 0; m < p->mb.n && !e; ++m)
+        e = hipMemcpyAsync(user + p->moff[m], (const char*)ws + (size_t)m * p->mb.ms, sizeof(double) * p->mlen[m],
+                           hipMemcpyDeviceToDevice, p->st);
+    return e;
+}
+
 Red no_red() { return Red{nullptr, nullptr}; }
 // the mass fix corrects the interpolation transfer only (the L2 projection conserves mass)
 int mass_fix_of(const jfmg_problem* p) { return p->cfg.transfer == 0 ? p->cfg.mass_fix : 0; }
@@ -579,6 +611,7 @@ template <typename T> FvArgs<T> fv_args(const jfmg_problem* p, int l)
     A.bgc = (const T*)L.bgc; A.bgf = (const T*)L.bgf; A.dbgf = (const T*)L.dbgf;
     A.pc = (const T*)L.pc; A.pf = (const T*)L.pf;
     A.tile = L.tile;
+    A.lev = l;
     return A;
 }
 
@@ -1326,33 +1359,185 @@ jfmg_status jfmg_config_default(jfmg_config* c)
     return JFMG_OK;
 }
 
-jfmg_status jfmg_workspace_bytes(const jfmg_config* cfg, size_t* bytes)
+}  // extern "C"
+
+namespace {
+
+// Members of a ragged batch may differ in these fields only.
+bool same_but_grid(const jfmg_config& a, const jfmg_config& b)
 {
-    if (!cfg || !bytes) return fail(nullptr, JFMG_EINVAL, "null argument");
-    Key key;
-    std::string msg;
-    jfmg_status s = validate(*cfg, key, msg);
-    if (s) return fail(nullptr, s, msg);
-    *bytes = layout(*cfg, nullptr, [](const char*, void*, size_t) {}) * (size_t)members_of(*cfg);
-    return JFMG_OK;
+    static_assert(sizeof(jfmg_config) == 14 * 4 + 16 + 26 * 8 + 2 * 4 + 8, "jfmg_config has no padding");
+    jfmg_config x = a, y = b;
+    for (jfmg_config* c : {&x, &y}) {
+        c->nx = c->nz = 0;
+        c->x0 = c->x1 = c->z0 = c->z1 = 0.0;
+        c->batch = 0;
+    }
+    return std::memcmp(&x, &y, sizeof(x)) == 0;
 }
 
-jfmg_status jfmg_create_problem(const jfmg_config* cfg, void* workspace, size_t ws_bytes, void* hip_stream,
-                                jfmg_problem** out)
+// The configuration whose workspace layout every member of a ragged batch uses:
+// the largest grid in each direction.
+jfmg_config envelope(const jfmg_config* cfgs, int n)
 {
-    if (!cfg || !out) return fail(nullptr, JFMG_EINVAL, "null argument");
+    jfmg_config e = cfgs[0];
+    for (int m = 1; m < n; ++m) {
+        e.nx = std::max(e.nx, cfgs[m].nx);
+        e.nz = std::max(e.nz, cfgs[m].nz);
+    }
+    e.batch = n;
+    return e;
+}
+
+size_t table_bytes(int n) { return ((sizeof(MemberArgs) * (size_t)n + 255) & ~size_t(255)); }
+
+jfmg_status validate_ensemble(const jfmg_config* cfgs, int n, Key& key, std::string& msg)
+{
+    if (!cfgs || n < 1 || n > 4096) { msg = "an ensemble has 1..4096 members"; return JFMG_EINVAL; }
+    for (int m = 0; m < n; ++m) {
+        jfmg_config c = cfgs[m];
+        if (c.batch > 1) { msg = "ensemble members are single problems (batch 0 or 1)"; return JFMG_EINVAL; }
+        c.batch = 0;
+        jfmg_status s = validate(c, key, msg);
+        if (s) { msg = "member " + std::to_string(m) + ": " + msg; return s; }
+        if (!same_but_grid(cfgs[0], c)) {
+            msg = "ensemble members may differ only in nx, nz and the domain";
+            return JFMG_EINVAL;
+        }
+    }
+    if (key.a || key.b) { msg = "DG-level smoothing (key a, b) is not available in a ragged batch"; return JFMG_EINVAL; }
+    const jfmg_config e = envelope(cfgs, n);
+    return validate(e, key, msg);
+}
+
+// Background tables of configuration c (its own grid and domain) into the member
+// region that starts `off` bytes after member 0.  The host arrays are kept in
+// `keep` until the stream is synchronized.
+hipError_t upload_tables(jfmg_problem* p, const jfmg_config& c, size_t off, std::vector<std::vector<char>>& keep)
+{
+    auto at = [off](void* ptr) { return (void*)((char*)ptr + off); };
+    hipStream_t st = p->st;
+    auto up = [&](void* dst, const std::vector<double>& v, bool single) {
+        std::vector<char> b(v.size() * (single ? 4 : 8));
+        if (single) { for (size_t i = 0; i < v.size(); ++i) ((float*)b.data())[i] = (float)v[i]; }
+        else std::memcpy(b.data(), v.data(), b.size());
+        keep.push_back(std::move(b));
+        return hipMemcpyAsync(at(dst), keep.back().data(), keep.back().size(), hipMemcpyHostToDevice, st);
+    };
+    const int n1 = p->n1;
+    const double dz = (c.z1 - c.z0) / c.nz;
+    std::vector<double> bgn((size_t)c.nz * n1 * 4), dbgn(bgn.size()), thn((size_t)c.nz * n1);
+    std::vector<double> bgf((size_t)(c.nz + 1) * 4), dbgf(bgf.size());
+    std::vector<double> pbn((size_t)c.nz * n1 * 2), pbfc((size_t)(c.nz + 1) * 2);   // [pb | 1/rt]
+    for (int ez = 0; ez < c.nz; ++ez)
+        for (int b = 0; b < n1; ++b) {
+            const double z = c.z0 + (ez + 0.5 * (1.0 + p->R.xi[b])) * dz;
+            const BgPoint bp = background_at(c, z);
+            const int zi = ez * n1 + b;
+            for (int k = 0; k < 4; ++k) { bgn[zi * 4 + k] = bp.U[k]; dbgn[zi * 4 + k] = bp.dU[k]; }
+            thn[zi] = bp.theta;
+            pbn[zi] = bg_pressure(c, bp.U[3]);
+            pbn[(size_t)c.nz * n1 + zi] = 1.0 / bp.U[3];
+        }
+    for (int f = 0; f <= c.nz; ++f) {
+        const BgPoint bp = background_at(c, c.z0 + f * dz);
+        for (int k = 0; k < 4; ++k) { bgf[f * 4 + k] = bp.U[k]; dbgf[f * 4 + k] = bp.dU[k]; }
+        pbfc[f] = bg_pressure(c, bp.U[3]);
+        pbfc[c.nz + 1 + f] = 1.0 / bp.U[3];
+    }
+    hipError_t e = hipSuccess;
+    e = e ? e : up(p->bg_node, bgn, false);
+    e = e ? e : up(p->dbg_node, dbgn, false);
+    e = e ? e : up(p->th_node, thn, false);
+    e = e ? e : up(p->bg_face, bgf, false);
+    e = e ? e : up(p->dbg_face, dbgf, false);
+    e = e ? e : up(p->pb_node, pbn, false);
+    e = e ? e : up(p->pb_face, pbfc, false);
+    int nzl = n1 * c.nz;
+    for (int l = 0; l < p->nlev && !e; ++l, nzl /= 2) {
+        const Level& L = p->lev[l];
+        const double hz = (c.z1 - c.z0) / nzl;
+        std::vector<double> c4((size_t)nzl * 4), f4((size_t)(nzl + 1) * 4), df4(f4.size());
+        std::vector<double> pc2((size_t)nzl * 2), pf2((size_t)(nzl + 1) * 2);
+        for (int J = 0; J < nzl; ++J) {
+            const BgPoint bp = background_at(c, c.z0 + (J + 0.5) * hz);
+            for (int k = 0; k < 4; ++k) c4[J * 4 + k] = bp.U[k];
+            pc2[2 * J] = bg_pressure(c, bp.U[3]);
+            pc2[2 * J + 1] = 1.0 / bp.U[3];
+        }
+        for (int J = 0; J <= nzl; ++J) {
+            const BgPoint bp = background_at(c, c.z0 + J * hz);
+            for (int k = 0; k < 4; ++k) { f4[J * 4 + k] = bp.U[k]; df4[J * 4 + k] = bp.dU[k]; }
+            pf2[2 * J] = bg_pressure(c, bp.U[3]);
+            pf2[2 * J + 1] = 1.0 / bp.U[3];
+        }
+        const std::vector<double>* src[5] = {&c4, &f4, &df4, &pc2, &pf2};
+        void* dst[5] = {L.bgc, L.bgf, L.dbgf, L.pc, L.pf};
+        for (int t = 0; t < 5 && !e; ++t) e = up(dst[t], *src[t], p->prec == 32);
+    }
+    return e;
+}
+
+// DG kernel arguments of configuration c whose tables start `off` bytes after member 0's
+DgArgs dg_args_of(const jfmg_problem* p, const jfmg_config& c, size_t off)
+{
+    auto at = [off](const double* ptr) { return (const double*)((const char*)ptr + off); };
+    DgArgs A;
+    A.ne = (long)c.nx * c.nz; A.nx = c.nx; A.nz = c.nz; A.bc = c.bc; A.physics = c.physics;
+    A.dx = (c.x1 - c.x0) / c.nx; A.dz = (c.z1 - c.z0) / c.nz;
+    A.J = A.dx * A.dz / 4.0; A.g = c.g; A.mu = c.mu; A.c_ip = c.c_ip;
+    A.rdx2 = 2.0 / A.dx;
+    A.rdz2 = 2.0 / A.dz;
+    A.eta_x = A.c_ip * (double)(p->n1 * p->n1) / A.dx;
+    A.eta_z = A.c_ip * (double)(p->n1 * p->n1) / A.dz;
+    A.gas = make_gas<double>(c);
+    A.bg_node = at(p->bg_node); A.dbg_node = at(p->dbg_node); A.th_node = at(p->th_node);
+    A.bg_face = at(p->bg_face); A.dbg_face = at(p->dbg_face);
+    A.pb_node = at(p->pb_node); A.irt_node = at(p->pb_node + (size_t)c.nz * p->n1);
+    A.pb_face = at(p->pb_face); A.irt_face = at(p->pb_face + (c.nz + 1));
+    A.R = p->R;
+    A.lin0 = (double*)((char*)p->lin0 + off);
+    return A;
+}
+
+// FV level l of configuration c whose tables start `off` bytes after member 0's
+template <typename T> FvArgs<T> fv_args_of(const jfmg_problem* p, const jfmg_config& c, int l, size_t off)
+{
+    auto at = [off](const void* ptr) { return (const T*)((const char*)ptr + off); };
+    const Level& L = p->lev[l];
+    FvArgs<T> A;
+    A.nxl = (p->n1 * c.nx) >> l; A.nzl = (p->n1 * c.nz) >> l; A.bc = c.bc; A.physics = c.physics;
+    A.nc = (long)A.nxl * A.nzl;
+    const double hx = (c.x1 - c.x0) / A.nxl, hz = (c.z1 - c.z0) / A.nzl;
+    A.hx = (T)hx; A.hz = (T)hz; A.area = (T)(hx * hz); A.iarea = (T)(1.0 / (hx * hz)); A.g = (T)c.g; A.mu = (T)c.mu;
+    A.gas = make_gas<T>(c);
+    A.bgc = at(L.bgc); A.bgf = at(L.bgf); A.dbgf = at(L.dbgf); A.pc = at(L.pc); A.pf = at(L.pf);
+    A.tile = L.tile;
+    A.lev = l;
+    return A;
+}
+
+// One problem: a single one (n = 1), a lock-step batch of equal members
+// (cfgs[0].batch members) or a ragged batch of the n configurations.
+jfmg_status create_impl(const jfmg_config* cfgs, int n, bool ragged, void* workspace, size_t ws_bytes,
+                        void* hip_stream, jfmg_problem** out)
+{
+    if (!cfgs || !out) return fail(nullptr, JFMG_EINVAL, "null argument");
     *out = nullptr;
     Key key;
     std::string msg;
-    jfmg_status s = validate(*cfg, key, msg);
+    jfmg_status s = ragged ? validate_ensemble(cfgs, n, key, msg) : validate(cfgs[0], key, msg);
     if (s) return fail(nullptr, s, msg);
-    const size_t member_bytes = layout(*cfg, nullptr, [](const char*, void*, size_t) {});
-    const size_t need = member_bytes * (size_t)members_of(*cfg);
+    const jfmg_config env = ragged ? envelope(cfgs, n) : cfgs[0];
+    const jfmg_config* cfg = &env;
+    const int members = members_of(env);
+    const size_t member_bytes = layout(env, nullptr, [](const char*, void*, size_t) {});
+    const size_t need = member_bytes * (size_t)members + (ragged ? table_bytes(members) : 0);
     if (!workspace || ws_bytes < need) return fail(nullptr, JFMG_ENOMEM, "workspace too small");
     if (((uintptr_t)workspace & 255) != 0) return fail(nullptr, JFMG_EINVAL, "workspace must be 256-byte aligned");
 
     jfmg_problem* p = new jfmg_problem();
-    p->cfg = *cfg;
+    p->cfg = env;
     p->key = key;
     p->n1 = cfg->k + 1;
     p->np = p->n1 * p->n1;
@@ -1363,7 +1548,8 @@ jfmg_status jfmg_create_problem(const jfmg_config* cfg, void* workspace, size_t 
     p->nlev = cfg->mg_levels;
     p->prec = cfg->mg_precision;
     p->m = cfg->gmres_m;
-    p->mb = Mb{members_of(*cfg), (long)member_bytes};
+    p->mb = Mb{members, (long)member_bytes};
+    p->ragged = ragged;
     p->st = (hipStream_t)hip_stream;
     p->user_st = p->st;
     p->cs = nullptr;
@@ -1375,11 +1561,11 @@ jfmg_status jfmg_create_problem(const jfmg_config* cfg, void* workspace, size_t 
         delete p;
         return fail(nullptr, JFMG_EINVAL, "singular subcell transfer");
     }
-    layout(*cfg, (char*)workspace, [&](const char* name, void* ptr, size_t n) {
+    layout(*cfg, (char*)workspace, [&](const char* name, void* ptr, size_t nn) {
         const std::string nm(name);
         if (nm == "scal") p->scal = (double*)ptr;
-        else if (nm == "fvpart") { p->fvpart = (double*)ptr; p->fvp = n; }
-        else if (nm == "partials") { p->partials = (double*)ptr; p->npartials = n; }
+        else if (nm == "fvpart") { p->fvpart = (double*)ptr; p->fvp = nn; }
+        else if (nm == "partials") { p->partials = (double*)ptr; p->npartials = nn; }
         else if (nm == "bg_node") p->bg_node = (double*)ptr;
         else if (nm == "dbg_node") p->dbg_node = (double*)ptr;
         else if (nm == "th_node") p->th_node = (double*)ptr;
@@ -1399,7 +1585,7 @@ jfmg_status jfmg_create_problem(const jfmg_config* cfg, void* workspace, size_t 
         else if (nm == "V") p->V = (double*)ptr;
         else if (nm == "Z") p->Z = (double*)ptr;
         else {
-            Level& L = p->lev[n];
+            Level& L = p->lev[nn];
             if (nm == "u") L.u = ptr;
             else if (nm == "F0") L.F0 = ptr;
             else if (nm == "x0") L.buf[0] = ptr;
@@ -1413,7 +1599,7 @@ jfmg_status jfmg_create_problem(const jfmg_config* cfg, void* workspace, size_t 
             else if (nm == "pf") L.pf = ptr;
         }
     });
-    // level geometry
+    // level geometry (the envelope's for a ragged batch: launch shapes)
     int nxl = p->n1 * cfg->nx, nzl = p->n1 * cfg->nz;
     for (int l = 0; l < p->nlev; ++l) {
         Level& L = p->lev[l];
@@ -1424,66 +1610,35 @@ jfmg_status jfmg_create_problem(const jfmg_config* cfg, void* workspace, size_t 
         nxl /= 2;
         nzl /= 2;
     }
-    // host tables
-    const int n1 = p->n1;
-    std::vector<double> bgn((size_t)cfg->nz * n1 * 4), dbgn(bgn.size()), thn((size_t)cfg->nz * n1);
-    std::vector<double> bgf((size_t)(cfg->nz + 1) * 4), dbgf(bgf.size());
-    std::vector<double> pbn((size_t)cfg->nz * n1 * 2), pbfc((size_t)(cfg->nz + 1) * 2);   // [pb | 1/rt]
-    for (int ez = 0; ez < cfg->nz; ++ez)
-        for (int b = 0; b < n1; ++b) {
-            const double z = cfg->z0 + (ez + 0.5 * (1.0 + p->R.xi[b])) * p->dz;
-            const BgPoint bp = background_at(*cfg, z);
-            const int zi = ez * n1 + b;
-            for (int c = 0; c < 4; ++c) { bgn[zi * 4 + c] = bp.U[c]; dbgn[zi * 4 + c] = bp.dU[c]; }
-            thn[zi] = bp.theta;
-            pbn[zi] = bg_pressure(*cfg, bp.U[3]);
-            pbn[(size_t)cfg->nz * n1 + zi] = 1.0 / bp.U[3];
-        }
-    for (int f = 0; f <= cfg->nz; ++f) {
-        const BgPoint bp = background_at(*cfg, cfg->z0 + f * p->dz);
-        for (int c = 0; c < 4; ++c) { bgf[f * 4 + c] = bp.U[c]; dbgf[f * 4 + c] = bp.dU[c]; }
-        pbfc[f] = bg_pressure(*cfg, bp.U[3]);
-        pbfc[cfg->nz + 1 + f] = 1.0 / bp.U[3];
-    }
     hipStream_t st = p->st;
-    auto up = [&](void* dst, const void* src, size_t bytes) { return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st); };
-    std::vector<std::vector<double>> keep_d;
-    std::vector<std::vector<float>> keep_f;
+    std::vector<std::vector<char>> keep;
+    std::vector<MemberArgs> tab;
     hipError_t e = hipSuccess;
-    e = e ? e : up(p->bg_node, bgn.data(), bgn.size() * 8);
-    e = e ? e : up(p->dbg_node, dbgn.data(), dbgn.size() * 8);
-    e = e ? e : up(p->th_node, thn.data(), thn.size() * 8);
-    e = e ? e : up(p->bg_face, bgf.data(), bgf.size() * 8);
-    e = e ? e : up(p->dbg_face, dbgf.data(), dbgf.size() * 8);
-    e = e ? e : up(p->pb_node, pbn.data(), pbn.size() * 8);
-    e = e ? e : up(p->pb_face, pbfc.data(), pbfc.size() * 8);
-    for (int l = 0; l < p->nlev && !e; ++l) {
-        Level& L = p->lev[l];
-        std::vector<double> c4((size_t)L.nz * 4), f4((size_t)(L.nz + 1) * 4), df4(f4.size());
-        std::vector<double> pc2((size_t)L.nz * 2), pf2((size_t)(L.nz + 1) * 2);
-        for (int J = 0; J < L.nz; ++J) {
-            const BgPoint bp = background_at(*cfg, cfg->z0 + (J + 0.5) * L.hz);
-            for (int c = 0; c < 4; ++c) c4[J * 4 + c] = bp.U[c];
-            pc2[2 * J] = bg_pressure(*cfg, bp.U[3]);
-            pc2[2 * J + 1] = 1.0 / bp.U[3];
-        }
-        for (int J = 0; J <= L.nz; ++J) {
-            const BgPoint bp = background_at(*cfg, cfg->z0 + J * L.hz);
-            for (int c = 0; c < 4; ++c) { f4[J * 4 + c] = bp.U[c]; df4[J * 4 + c] = bp.dU[c]; }
-            pf2[2 * J] = bg_pressure(*cfg, bp.U[3]);
-            pf2[2 * J + 1] = 1.0 / bp.U[3];
-        }
-        const std::vector<double>* src[5] = {&c4, &f4, &df4, &pc2, &pf2};
-        void* dst[5] = {L.bgc, L.bgf, L.dbgf, L.pc, L.pf};
-        for (int t = 0; t < 5 && !e; ++t) {
-            if (p->prec == 64) {
-                keep_d.push_back(*src[t]);
-                e = up(dst[t], keep_d.back().data(), keep_d.back().size() * 8);
-            } else {
-                keep_f.emplace_back(src[t]->begin(), src[t]->end());
-                e = up(dst[t], keep_f.back().data(), keep_f.back().size() * 4);
+    if (!ragged) {
+        // one set of tables (member 0's; the members of a lock-step batch share them)
+        e = upload_tables(p, *cfg, 0, keep);
+    } else {
+        tab.resize(members);
+        long off = 0;
+        for (int m = 0; m < members && !e; ++m) {
+            const jfmg_config& c = cfgs[m];
+            const size_t ob = (size_t)m * member_bytes;
+            e = upload_tables(p, c, ob, keep);
+            MemberArgs& M = tab[m];
+            std::memset(&M, 0, sizeof(M));
+            M.dg = dg_args_of(p, c, ob);
+            M.N = 4L * c.nx * c.nz * p->np;
+            for (int l = 0; l < p->nlev; ++l) {
+                if (p->prec == 32) M.f32[l] = fv_args_of<float>(p, c, l, ob);
+                else M.f64[l] = fv_args_of<double>(p, c, l, ob);
             }
+            p->mlen.push_back(M.N);
+            p->moff.push_back(off);
+            off += M.N;
         }
+        p->tab = (MemberArgs*)((char*)workspace + (size_t)members * member_bytes);
+        if (!e) e = hipMemcpyAsync(p->tab, tab.data(), sizeof(MemberArgs) * members, hipMemcpyHostToDevice, st);
+        p->mb.tab = p->tab;
     }
     for (int b = 0; b < p->mb.n && !e; ++b) e = hipMemsetAsync((char*)p->scal + (size_t)b * p->mb.ms, 0, NSCAL * 8, st);
     e = e ? e : hipStreamSynchronize(st);
@@ -1502,19 +1657,49 @@ jfmg_status jfmg_create_problem(const jfmg_config* cfg, void* workspace, size_t 
         delete p;
         return fail(nullptr, JFMG_EDEVICE, m2);
     }
-    // DG kernel arguments
-    DgArgs& A = p->A;
-    A.ne = p->ne; A.nx = cfg->nx; A.nz = cfg->nz; A.bc = cfg->bc; A.physics = cfg->physics;
-    A.dx = p->dx; A.dz = p->dz; A.J = p->dx * p->dz / 4.0; A.g = cfg->g; A.mu = cfg->mu; A.c_ip = cfg->c_ip;
-    A.gas = make_gas<double>(*cfg);
-    A.bg_node = p->bg_node; A.dbg_node = p->dbg_node; A.th_node = p->th_node;
-    A.bg_face = p->bg_face; A.dbg_face = p->dbg_face;
-    A.pb_node = p->pb_node; A.irt_node = p->pb_node + (size_t)cfg->nz * p->n1;
-    A.pb_face = p->pb_face; A.irt_face = p->pb_face + (cfg->nz + 1);
-    A.R = p->R;
-    A.lin0 = p->lin0;
+    // DG kernel arguments (the envelope's for a ragged batch: launch shapes)
+    p->A = dg_args_of(p, *cfg, 0);
     *out = p;
     return JFMG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+jfmg_status jfmg_workspace_bytes(const jfmg_config* cfg, size_t* bytes)
+{
+    if (!cfg || !bytes) return fail(nullptr, JFMG_EINVAL, "null argument");
+    Key key;
+    std::string msg;
+    jfmg_status s = validate(*cfg, key, msg);
+    if (s) return fail(nullptr, s, msg);
+    *bytes = layout(*cfg, nullptr, [](const char*, void*, size_t) {}) * (size_t)members_of(*cfg);
+    return JFMG_OK;
+}
+
+jfmg_status jfmg_create_problem(const jfmg_config* cfg, void* workspace, size_t ws_bytes, void* hip_stream,
+                                jfmg_problem** out)
+{
+    return create_impl(cfg, 1, false, workspace, ws_bytes, hip_stream, out);
+}
+
+jfmg_status jfmg_ensemble_workspace_bytes(const jfmg_config* cfgs, int n, size_t* bytes)
+{
+    if (!cfgs || !bytes) return fail(nullptr, JFMG_EINVAL, "null argument");
+    Key key;
+    std::string msg;
+    jfmg_status s = validate_ensemble(cfgs, n, key, msg);
+    if (s) return fail(nullptr, s, msg);
+    const jfmg_config env = envelope(cfgs, n);
+    *bytes = layout(env, nullptr, [](const char*, void*, size_t) {}) * (size_t)n + table_bytes(n);
+    return JFMG_OK;
+}
+
+jfmg_status jfmg_create_ensemble(const jfmg_config* cfgs, int n, void* workspace, size_t ws_bytes, void* hip_stream,
+                                 jfmg_problem** out)
+{
+    return create_impl(cfgs, n, true, workspace, ws_bytes, hip_stream, out);
 }
 
 jfmg_status jfmg_destroy_problem(jfmg_problem* p)
@@ -1536,6 +1721,12 @@ jfmg_status jfmg_destroy_problem(jfmg_problem* p)
 
 size_t jfmg_num_dofs(const jfmg_problem* p) { return p ? (size_t)p->N : 0; }
 
+size_t jfmg_member_dofs(const jfmg_problem* p, int member)
+{
+    if (!p || member < 0 || member >= p->mb.n) return 0;
+    return p->ragged ? (size_t)p->mlen[member] : (size_t)p->N;
+}
+
 size_t jfmg_fv_size(const jfmg_problem* p, int level)
 {
     if (!p || level < 0 || level >= p->nlev) return 0;
@@ -1546,6 +1737,7 @@ jfmg_status jfmg_initial_state(jfmg_problem* p, const jfmg_perturbation* q, doub
 {
     if (!p || !q || !U) return fail(p, JFMG_EINVAL, "null argument");
     if (q->shape < 0 || q->shape > 1) return fail(p, JFMG_EINVAL, "unknown perturbation shape");
+    if (p->ragged) return fail(p, JFMG_EINVAL, "a ragged batch takes its members' initial states from single problems");
     // every member of a batch gets the same state ([members][N] back to back)
     launch_initial_state(p->cfg.k, p->A, q->shape, q->amp, q->xc, q->zc, q->xr, q->zr, q->a, q->Z, p->cfg.x0,
                          p->cfg.z0, p->cfg.u_mean, U, p->st, Mb{p->mb.n, (long)(sizeof(double) * p->N)});
@@ -1573,9 +1765,7 @@ jfmg_status jfmg_linearize(jfmg_problem* p, const double* U, double alpha_dt)
 {
     if (!p || !U) return fail(p, JFMG_EINVAL, "null argument");
     if (p->mb.n > 1) {   // caller's members back to back -> member-strided workspace
-        const size_t vb = sizeof(double) * p->N;
-        HIPCHK(p, hipMemcpy2DAsync(p->Ulin, (size_t)p->mb.ms, U, vb, vb, (size_t)p->mb.n, hipMemcpyDeviceToDevice,
-                                   p->st));
+        HIPCHK(p, members_in(p, p->Ulin, U));
         return linearize(p, p->Ulin, alpha_dt);
     }
     return linearize(p, U, alpha_dt);
@@ -1610,12 +1800,8 @@ static jfmg_status implicit_step_body(jfmg_problem* p, double* U, jfmg_stats* st
     p->syncs = 0;
     const jfmg_config& c = p->cfg;
     jfmg_status s;
-    // the caller's U holds the members back to back ([members][N])
-    const size_t vb = sizeof(double) * p->N;
-    hipError_t e = p->mb.n == 1
-                       ? hipMemcpyAsync(p->Un, U, vb, hipMemcpyDeviceToDevice, p->st)
-                       : hipMemcpy2DAsync(p->Un, (size_t)p->mb.ms, U, vb, vb, (size_t)p->mb.n, hipMemcpyDeviceToDevice,
-                                          p->st);
+    // the caller's U holds the members back to back
+    hipError_t e = members_in(p, p->Un, U);
     if (e) return fail(p, JFMG_EDEVICE, hipGetErrorString(e));
     if (c.scheme == 0) {
         s = newton_stage(p, p->Un, c.dt, &st);
@@ -1633,9 +1819,7 @@ static jfmg_status implicit_step_body(jfmg_problem* p, double* U, jfmg_stats* st
         }
     }
     if (s == JFMG_OK) {
-        e = p->mb.n == 1 ? hipMemcpyAsync(U, p->Uk, vb, hipMemcpyDeviceToDevice, p->st)
-                         : hipMemcpy2DAsync(U, vb, p->Uk, (size_t)p->mb.ms, vb, (size_t)p->mb.n,
-                                            hipMemcpyDeviceToDevice, p->st);
+        e = members_out(p, U, p->Uk);
         if (!e) e = hipStreamSynchronize(p->st);
         if (e) s = fail(p, JFMG_EDEVICE, hipGetErrorString(e));
     } else {

@@ -140,13 +140,15 @@ __device__ __forceinline__ void fv_face(const FvArgs<T>& A, const T (&sw)[4][HZ]
 //   STAGE_PC the STAGE result v is not stored: it corrects the next finer level's x in
 //           out2 by injection, x_f -= P v (x_f = -P v when fzero is set, x_f being zero), with the
 //           ||x_f||^2 block partials into red (the last smoother stage of a coarse level)
-template <typename T, int TX, int TZ, int NTH, int WPE, bool LATE, bool ZREV, bool MB, int MODE>
+template <typename T, int TX, int TZ, int NTH, int WPE, bool LATE, bool ZREV, bool MB, int MODE, bool RG>
 __global__ void __launch_bounds__(NTH, WPE)
-fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, const T* __restrict__ xp,
+fv_tile_kernel(FvArgs<T> Aa, const MemberArgs* __restrict__ mt, const T* __restrict__ u, const T* __restrict__ F0,
+               const T* __restrict__ xp,
                const T* __restrict__ x0, const T* __restrict__ b, T* __restrict__ out, T* __restrict__ out2,
                const double* __restrict__ xpart, int xcount, double* __restrict__ slots,
                const double* __restrict__ slots2, double alpha_j, double adt, int fzero, Red red, long ms)
 {
+    const FvArgs<T>& A = fv_of<T, RG>(Aa, mt);
     if constexpr (MB) {   // member blockIdx.z of a lock-step batch
         u = mbr(u, ms);
         F0 = mbr(F0, ms);
@@ -173,10 +175,26 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
     __shared__ T sBc[TZ][6];
     __shared__ T sBf[TZ + 1][10];
     const int tid = threadIdx.x;
-    const unsigned tile = xcd_tile(block_linear(), gridDim.x * gridDim.y);
-    const int I0 = (int)(tile % gridDim.x) * TX, J0 = (int)(tile / gridDim.x) * TZ;
     const long nc = A.nc;
     const int nxl = A.nxl, nzl = A.nzl;
+    // tiles of this member (a one-dimensional grid; in a ragged batch the work-groups
+    // beyond a smaller member's tiles only store zero partial sums)
+    const unsigned ntx = (unsigned)((nxl + TX - 1) / TX), ntiles = ntx * (unsigned)((nzl + TZ - 1) / TZ);
+    if (blockIdx.x >= ntiles) {
+        if (tid == 0) {
+            if constexpr (MODE == FVM_LIN) {
+                red.partials[blockIdx.x] = 0.0;
+                red.partials[gridDim.x + blockIdx.x] = 0.0;
+            } else if constexpr (MODE == FVM_STAGE || MODE == FVM_STAGE_PC) {
+                red.partials[blockIdx.x] = 0.0;
+            } else if constexpr (MODE == FVM_DEFECT) {
+                if (out2) red.partials[blockIdx.x] = 0.0;
+            }
+        }
+        return;
+    }
+    const unsigned tile = xcd_tile(blockIdx.x, ntiles);
+    const int I0 = (int)(tile % ntx) * TX, J0 = (int)(tile / ntx) * TZ;
     // own cell (threads tid < NCELL)
     const int ti = tid % TX, tj = tid / TX;
     const int I = I0 + ti, J = J0 + tj;
@@ -301,9 +319,8 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
         const double bs = block_sum<NTH>(ss, sh);
         const double bm = block_max<NTH>(lam, sh);
         if (tid == 0) {
-            const unsigned nb = gridDim.x * gridDim.y;
-            red.partials[block_linear()] = bs;
-            red.partials[nb + block_linear()] = bm;
+            red.partials[blockIdx.x] = bs;
+            red.partials[gridDim.x + blockIdx.x] = bm;
         }
         return;
     } else {
@@ -378,18 +395,20 @@ fv_tile_kernel(FvArgs<T> A, const T* __restrict__ u, const T* __restrict__ F0, c
 }
 
 // first stage of a sweep from x = 0: out = alpha_1 dtau b, with ||out||^2
-template <typename T>
+template <typename T, bool RG>
 __global__ void __launch_bounds__(256)
-fv_stage_zero_kernel(const T* __restrict__ b, T* __restrict__ out, long n, const double* __restrict__ slots,
-                     double alpha_j, Red red, long ms)
+fv_stage_zero_kernel(FvArgs<T> Aa, const MemberArgs* __restrict__ mt, const T* __restrict__ b, T* __restrict__ out,
+                     const double* __restrict__ slots, double alpha_j, Red red, long ms)
 {
+    const FvArgs<T>& A = fv_of<T, RG>(Aa, mt);
     b = mbr(b, ms);
     out = mbr(out, ms);
     slots = mbr(slots, ms);
     red = mbr(red, ms);
+    const long n = 4 * A.nc, nb = (n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024;   // this member's work-groups
     const T s = (T)(alpha_j * slots[LV_DTAU]);
     double nrm = 0.0;
-    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += nb * 256) {
         const T v = s * b[i];
         out[i] = v;
         nrm += (double)v * (double)v;
@@ -398,10 +417,12 @@ fv_stage_zero_kernel(const T* __restrict__ b, T* __restrict__ out, long n, const
 }
 
 // coarse = R(-b): the defect of x = 0
-template <typename T>
+template <typename T, bool RG>
 __global__ void __launch_bounds__(256)
-fv_restrict_neg_kernel(FvArgs<T> A, const T* __restrict__ f, T* __restrict__ c, long ms)
+fv_restrict_neg_kernel(FvArgs<T> Aa, const MemberArgs* __restrict__ mt, const T* __restrict__ f, T* __restrict__ c,
+                       long ms)
 {
+    const FvArgs<T>& A = fv_of<T, RG>(Aa, mt);
     f = mbr(f, ms);
     c = mbr(c, ms);
     const int nxc = A.nxl / 2, nzc = A.nzl / 2;
@@ -418,15 +439,23 @@ fv_restrict_neg_kernel(FvArgs<T> A, const T* __restrict__ f, T* __restrict__ c, 
 }
 
 // x -= P v (injection) on the fine level, with ||x||^2
-template <typename T>
+template <typename T, bool RG>
 __global__ void __launch_bounds__(FV_NTH)
-fv_prolong_correct_kernel(FvArgs<T> A, T* __restrict__ x, const T* __restrict__ v, Red red, long ms)
+fv_prolong_correct_kernel(FvArgs<T> Aa, const MemberArgs* __restrict__ mt, T* __restrict__ x, const T* __restrict__ v,
+                          Red red, long ms)
 {
+    const FvArgs<T>& A = fv_of<T, RG>(Aa, mt);
     x = mbr(x, ms);
     v = mbr(v, ms);
     red = mbr(red, ms);
-    const int I = blockIdx.x * FV_TX + (threadIdx.x & (FV_TX - 1));
-    const int J = blockIdx.y * FV_TZ + (threadIdx.x / FV_TX);
+    // a one-dimensional grid over this member's 64 x 4 tiles (row-major)
+    const unsigned gx = (unsigned)((A.nxl + FV_TX - 1) / FV_TX), nt = gx * (unsigned)((A.nzl + FV_TZ - 1) / FV_TZ);
+    if (blockIdx.x >= nt) {   // beyond a smaller member of a ragged batch
+        if (threadIdx.x == 0) red.partials[blockIdx.x] = 0.0;
+        return;
+    }
+    const int I = (blockIdx.x % gx) * FV_TX + (threadIdx.x & (FV_TX - 1));
+    const int J = (blockIdx.x / gx) * FV_TZ + (threadIdx.x / FV_TX);
     double nrm = 0.0;
     if (I < A.nxl && J < A.nzl) {
         const long q = (long)J * A.nxl + I;
@@ -441,10 +470,11 @@ fv_prolong_correct_kernel(FvArgs<T> A, T* __restrict__ x, const T* __restrict__ 
     put_partial<FV_NTH>(red, nrm);
 }
 
-template <typename T>
+template <typename T, bool RG>
 __global__ void __launch_bounds__(FV_NTH)
-fv_restrict_kernel(FvArgs<T> A, const T* __restrict__ f, T* __restrict__ c, long ms)
+fv_restrict_kernel(FvArgs<T> Aa, const MemberArgs* __restrict__ mt, const T* __restrict__ f, T* __restrict__ c, long ms)
 {
+    const FvArgs<T>& A = fv_of<T, RG>(Aa, mt);
     f = mbr(f, ms);
     c = mbr(c, ms);
     const int nxc = A.nxl / 2, nzc = A.nzl / 2;
@@ -460,10 +490,11 @@ fv_restrict_kernel(FvArgs<T> A, const T* __restrict__ f, T* __restrict__ c, long
     }
 }
 
-template <typename T>
+template <typename T, bool RG>
 __global__ void __launch_bounds__(FV_NTH)
-fv_prolong_kernel(FvArgs<T> A, const T* __restrict__ c, T* __restrict__ f, long ms)
+fv_prolong_kernel(FvArgs<T> Aa, const MemberArgs* __restrict__ mt, const T* __restrict__ c, T* __restrict__ f, long ms)
 {
+    const FvArgs<T>& A = fv_of<T, RG>(Aa, mt);
     c = mbr(c, ms);
     f = mbr(f, ms);
     const int I = blockIdx.x * FV_TX + (threadIdx.x & (FV_TX - 1));
@@ -489,12 +520,18 @@ __global__ void __launch_bounds__(256) fv_norm2_kernel(const T* __restrict__ x, 
 }
 
 // level slots from the LIN partials: ||u + Ubar||, max(|v| + c), pseudo time step
+template <typename T>
 __global__ void __launch_bounds__(256)
 fv_lin_finalize_kernel(const double* __restrict__ p, int nb, double* __restrict__ slots, double hx, double hz,
-                       double mu, double adt, double cfl, long ms)
+                       double mu, double adt, double cfl, long ms, const MemberArgs* __restrict__ mt, int lev)
 {
     p = mbr(p, ms);
     slots = mbr(slots, ms);
+    if (mt) {   // a ragged member's own cell widths
+        const FvArgs<T>& A = fv_entry<T>(mt, lev);
+        hx = (double)A.hx;
+        hz = (double)A.hz;
+    }
     __shared__ double sh[4];
     double a = 0.0, m = 0.0;
     for (int i = threadIdx.x; i < nb; i += 256) { a += p[i]; m = fmax(m, p[nb + i]); }
@@ -512,20 +549,30 @@ static inline dim3 tile_grid(int nx, int nz, int members = 1)
 {
     return dim3((unsigned)((nx + FV_TX - 1) / FV_TX), (unsigned)((nz + FV_TZ - 1) / FV_TZ), (unsigned)members);
 }
+// the same 64 x 4 tiles as a one-dimensional grid
+static inline dim3 tile_grid_1d(int nx, int nz, int members = 1)
+{
+    const dim3 g = tile_grid(nx, nz);
+    return dim3(g.x * g.y, 1, (unsigned)members);
+}
 
 template <typename T, int TX, int TZ, int NTH, int WPE, bool LATE, bool ZREV, int MODE>
 static int tile_launch_shape(const FvArgs<T>& A, const T* u, const T* F0, const T* xp, const T* x0, const T* b,
                              T* out, T* out2, const double* xpart, int xcount, double* slots, const double* slots2,
                              double alpha_j, double adt, int fzero, Red red, hipStream_t st, const Mb& mb)
 {
-    const dim3 g((unsigned)((A.nxl + TX - 1) / TX), (unsigned)((A.nzl + TZ - 1) / TZ), (unsigned)mb.n);
-    if (mb.n > 1)
-        timed_launch(fv_tile_kernel<T, TX, TZ, NTH, WPE, LATE, ZREV, true, MODE>, g, dim3(NTH), st, A, u, F0, xp, x0, b,
-                     out, out2, xpart, xcount, slots, slots2, alpha_j, adt, fzero, red, mb.ms);
+    const unsigned nt = (unsigned)((A.nxl + TX - 1) / TX) * (unsigned)((A.nzl + TZ - 1) / TZ);
+    const dim3 g(nt, 1, (unsigned)mb.n);
+    if (mb.tab)
+        timed_launch(fv_tile_kernel<T, TX, TZ, NTH, WPE, LATE, ZREV, true, MODE, true>, g, dim3(NTH), st, A, mb.tab, u,
+                     F0, xp, x0, b, out, out2, xpart, xcount, slots, slots2, alpha_j, adt, fzero, red, mb.ms);
+    else if (mb.n > 1)
+        timed_launch(fv_tile_kernel<T, TX, TZ, NTH, WPE, LATE, ZREV, true, MODE, false>, g, dim3(NTH), st, A, mb.tab,
+                     u, F0, xp, x0, b, out, out2, xpart, xcount, slots, slots2, alpha_j, adt, fzero, red, mb.ms);
     else
-        timed_launch(fv_tile_kernel<T, TX, TZ, NTH, WPE, LATE, ZREV, false, MODE>, g, dim3(NTH), st, A, u, F0, xp, x0,
-                     b, out, out2, xpart, xcount, slots, slots2, alpha_j, adt, fzero, red, 0L);
-    return (int)(g.x * g.y);
+        timed_launch(fv_tile_kernel<T, TX, TZ, NTH, WPE, LATE, ZREV, false, MODE, false>, g, dim3(NTH), st, A, mb.tab,
+                     u, F0, xp, x0, b, out, out2, xpart, xcount, slots, slots2, alpha_j, adt, fzero, red, 0L);
+    return (int)nt;
 }
 
 template <typename T, int MODE>
@@ -561,8 +608,9 @@ void FvLaunch<T>::lin_level(const FvArgs<T>& A, const T* u, T* F0, Red red, doub
 {
     const int nb = tile_launch<T, FVM_LIN>(A, u, nullptr, nullptr, nullptr, nullptr, F0, nullptr, 0, slots, 0.0, adt,
                                            0, red, st, mb);
-    fv_lin_finalize_kernel<<<dim3(1, 1, mb.n), dim3(256), 0, st>>>(red.partials, nb, slots, (double)A.hx,
-                                                                   (double)A.hz, (double)A.mu, adt, cfl, mb.ms);
+    fv_lin_finalize_kernel<T><<<dim3(1, 1, mb.n), dim3(256), 0, st>>>(red.partials, nb, slots, (double)A.hx,
+                                                                      (double)A.hz, (double)A.mu, adt, cfl, mb.ms,
+                                                                      mb.tab, A.lev);
 }
 template <typename T>
 int FvLaunch<T>::stage(const FvArgs<T>& A, const T* u, const T* F0, const T* xp, const T* x0, const T* b, T* xo,
@@ -572,7 +620,12 @@ int FvLaunch<T>::stage(const FvArgs<T>& A, const T* u, const T* F0, const T* xp,
     if (zero) {
         const long n = 4 * A.nc;
         const int nb = norm_blocks(n);
-        timed_launch(fv_stage_zero_kernel<T>, dim3(nb, 1, mb.n), dim3(256), st, b, xo, n, slots, alpha_j, red, mb.ms);
+        if (mb.tab)
+            timed_launch(fv_stage_zero_kernel<T, true>, dim3(nb, 1, mb.n), dim3(256), st, A, mb.tab, b, xo, slots,
+                         alpha_j, red, mb.ms);
+        else
+            timed_launch(fv_stage_zero_kernel<T, false>, dim3(nb, 1, mb.n), dim3(256), st, A, mb.tab, b, xo, slots,
+                         alpha_j, red, mb.ms);
         return nb;
     }
     return tile_launch<T, FVM_STAGE>(A, u, F0, xp, x0, b, xo, xpart, xcount, const_cast<double*>(slots), alpha_j,
@@ -600,7 +653,8 @@ int FvLaunch<T>::defect_restrict(const FvArgs<T>& A, const T* u, const T* F0, co
 {
     if (zero) {
         const dim3 g((unsigned)((A.nxl / 2 + 63) / 64), (unsigned)((A.nzl / 2 + 3) / 4), (unsigned)mb.n);
-        timed_launch(fv_restrict_neg_kernel<T>, g, dim3(256), st, A, b, rc, mb.ms);
+        if (mb.tab) timed_launch(fv_restrict_neg_kernel<T, true>, g, dim3(256), st, A, mb.tab, b, rc, mb.ms);
+        else timed_launch(fv_restrict_neg_kernel<T, false>, g, dim3(256), st, A, mb.tab, b, rc, mb.ms);
         return 0;
     }
     const int nb = tile_launch<T, FVM_DEFECT>(A, u, F0, x, nullptr, b, rc, xpart, xcount, const_cast<double*>(slots),
@@ -610,19 +664,24 @@ int FvLaunch<T>::defect_restrict(const FvArgs<T>& A, const T* u, const T* F0, co
 template <typename T>
 int FvLaunch<T>::prolong_correct(const FvArgs<T>& Af, T* x, const T* v, Red red, hipStream_t st, const Mb& mb)
 {
-    const dim3 g = tile_grid(Af.nxl, Af.nzl, mb.n);
-    timed_launch(fv_prolong_correct_kernel<T>, g, dim3(FV_NTH), st, Af, x, v, red, mb.ms);
-    return (int)(g.x * g.y);
+    const dim3 g = tile_grid_1d(Af.nxl, Af.nzl, mb.n);
+    if (mb.tab) timed_launch(fv_prolong_correct_kernel<T, true>, g, dim3(FV_NTH), st, Af, mb.tab, x, v, red, mb.ms);
+    else timed_launch(fv_prolong_correct_kernel<T, false>, g, dim3(FV_NTH), st, Af, mb.tab, x, v, red, mb.ms);
+    return (int)g.x;
 }
 template <typename T>
 void FvLaunch<T>::restrict_(const FvArgs<T>& Af, const T* f, T* c, hipStream_t st, const Mb& mb)
 {
-    fv_restrict_kernel<T><<<tile_grid(Af.nxl / 2, Af.nzl / 2, mb.n), dim3(FV_NTH), 0, st>>>(Af, f, c, mb.ms);
+    const dim3 g = tile_grid(Af.nxl / 2, Af.nzl / 2, mb.n);
+    if (mb.tab) fv_restrict_kernel<T, true><<<g, dim3(FV_NTH), 0, st>>>(Af, mb.tab, f, c, mb.ms);
+    else fv_restrict_kernel<T, false><<<g, dim3(FV_NTH), 0, st>>>(Af, mb.tab, f, c, mb.ms);
 }
 template <typename T>
 void FvLaunch<T>::prolong(const FvArgs<T>& Af, const T* c, T* f, hipStream_t st, const Mb& mb)
 {
-    fv_prolong_kernel<T><<<tile_grid(Af.nxl, Af.nzl, mb.n), dim3(FV_NTH), 0, st>>>(Af, c, f, mb.ms);
+    const dim3 g = tile_grid(Af.nxl, Af.nzl, mb.n);
+    if (mb.tab) fv_prolong_kernel<T, true><<<g, dim3(FV_NTH), 0, st>>>(Af, mb.tab, c, f, mb.ms);
+    else fv_prolong_kernel<T, false><<<g, dim3(FV_NTH), 0, st>>>(Af, mb.tab, c, f, mb.ms);
 }
 template <typename T>
 void FvLaunch<T>::norm2(const T* x, long n, Red red, hipStream_t st, const Mb& mb)

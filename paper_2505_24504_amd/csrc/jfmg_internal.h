@@ -134,6 +134,7 @@ template <typename T> struct FvArgs {
     long nc;
     T hx, hz, area, iarea, g, mu;
     int tile;        // jfmg_tile shape of the operator kernels on this level (host side)
+    int lev;         // level index (the entry of a ragged batch's member table)
     Gas<T> gas;
     const T* bgc;    // [nzl][4]   background at cell-centre z
     const T* bgf;    // [nzl+1][4] background at z-faces
@@ -145,12 +146,47 @@ template <typename T> struct FvArgs {
 // device scalar slots of one FV level (doubles)
 enum { LV_UTOT = 0, LV_LAM = 1, LV_DTAU = 2, LV_IUTOT = 3, LV_NSLOT = 4 };   // LV_IUTOT = 1/||u + Ubar||
 
+// Kernel arguments of one member of a ragged batch (members of different grid
+// sizes and domains in one problem): device resident, one entry per member.  Each
+// kernel of a ragged launch reads its member's entry (blockIdx.z), takes its
+// extents from it and leaves the blocks beyond them idle (writing zero partial
+// sums), so every member computes exactly what it computes alone; table pointers
+// are absolute (into the member's own workspace region).
+struct MemberArgs {
+    DgArgs dg;
+    long N;                        // DG vector length 4 ne (k+1)^2
+    FvArgs<double> f64[MAXLEV];    // FV levels (the entries of the problem's precision are set)
+    FvArgs<float> f32[MAXLEV];
+};
+
 // Members of a lock-step batch: n members, member m at byte offset m * ms from
 // member 0 in every per-member buffer (device workspace regions of equal layout).
+// tab: the member table of a ragged batch (null for a single problem and for a
+// batch of equal members).
 struct Mb {
     int n = 1;
     long ms = 0;
+    const MemberArgs* tab = nullptr;
 };
+
+// The arguments a kernel works with: its own (RG false) or its member's entry.
+template <bool RG> __device__ __forceinline__ const DgArgs& dg_of(const DgArgs& a, const MemberArgs* t)
+{
+    if constexpr (RG) return t[blockIdx.z].dg;
+    else return a;
+}
+template <typename T> __device__ __forceinline__ const FvArgs<T>& fv_entry(const MemberArgs* t, int lev)
+{
+    if constexpr (std::is_same_v<T, float>) return t[blockIdx.z].f32[lev];
+    else return t[blockIdx.z].f64[lev];
+}
+template <typename T, bool RG> __device__ __forceinline__ const FvArgs<T>& fv_of(const FvArgs<T>& a, const MemberArgs* t)
+{
+    if constexpr (RG) return fv_entry<T>(t, a.lev);
+    else return a;
+}
+// a vector length of the member (ragged batch) or the given one
+__device__ __forceinline__ long len_of(long n, const MemberArgs* t) { return t ? t[blockIdx.z].N : n; }
 
 // ---- DG kernels (dg.hip) ----
 // mode 0: <psi,L>  1: M^-1 L  2: G = U - adt M^-1 L - Ubar (+ ||G||^2 into red.out)

@@ -109,12 +109,15 @@ void launch_scatter(double* dst, int count, const double* host, long hstride, hi
     scatter_kernel<<<dim3(1, 1, mb.n), dim3(64), 0, st>>>(dst, count, host, hstride, mb.ms);
 }
 
-__global__ void __launch_bounds__(256) norm2_kernel(const double* __restrict__ x, long n, Red red, long ms)
+__global__ void __launch_bounds__(256)
+norm2_kernel(const double* __restrict__ x, long n, Red red, long ms, const MemberArgs* __restrict__ mt)
 {
     x = mbr(x, ms);
     red = mbr(red, ms);
+    n = len_of(n, mt);
+    const long nb = (n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024;   // this member's work-groups
     double s = 0.0;
-    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) s += x[i] * x[i];
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += nb * 256) s += x[i] * x[i];
     put_partial<256>(red, s);
 }
 
@@ -122,7 +125,7 @@ void launch_norm2(const double* x, long n, Red red, hipStream_t st, const Mb& mb
 {
     long b = (n + 255) / 256;
     const int nb = (int)(b < 1024 ? b : 1024);
-    norm2_kernel<<<dim3(nb, 1, mb.n), dim3(256), 0, st>>>(x, n, red, mb.ms);
+    norm2_kernel<<<dim3(nb, 1, mb.n), dim3(256), 0, st>>>(x, n, red, mb.ms, mb.tab);
     if (red.out) launch_finalize(red.partials, nb, 1, red.out, st, Gate{}, mb);
 }
 
@@ -135,9 +138,10 @@ void launch_norm2(const double* x, long n, Red red, hipStream_t st, const Mb& mb
 template <int MAXV>
 __global__ void __launch_bounds__(LA_NTH)
 multidot_kernel(const double* __restrict__ w, const double* __restrict__ V, long ld, int nv, int self, long n, Gate gate,
-                Red red, long ms)
+                Red red, long ms, const MemberArgs* __restrict__ mt)
 {
     constexpr int NW = LA_NTH / 64;
+    n = len_of(n, mt);   // a ragged member's length: blocks beyond it store zero partials
     __shared__ double sh[NW][MAXV];
     w = mbr(w, ms);
     V = mbr(V, ms);
@@ -189,14 +193,15 @@ void launch_multidot(const double* w, const double* V, long ld, int nv, int self
     // with all entries in one group (w is re-read once per group, V once)
     const int nt = nv + self;
     const dim3 g(la_blocks(n), (nt + 3) / 4, mb.n);
-    timed_launch(multidot_kernel<4>, g, dim3(LA_NTH), st, w, V, ld, nv, self, n, gate, red, mb.ms);
+    timed_launch(multidot_kernel<4>, g, dim3(LA_NTH), st, w, V, ld, nv, self, n, gate, red, mb.ms, mb.tab);
     launch_finalize(red.partials, la_blocks(n), nt, red.out, st, gate, mb);
 }
 
 __global__ void __launch_bounds__(LA_NTH)
 update_kernel(double* __restrict__ w, const double* __restrict__ V, long ld, int nv, long n,
-              const double* __restrict__ h, Gate gate, Red red, long ms)
+              const double* __restrict__ h, Gate gate, Red red, long ms, const MemberArgs* __restrict__ mt)
 {
+    n = len_of(n, mt);
     gate.after = mbr(gate.after, ms);
     gate.before = mbr(gate.before, ms);
     if (!gate_open(gate)) return;
@@ -235,14 +240,16 @@ update_kernel(double* __restrict__ w, const double* __restrict__ V, long ld, int
 void launch_update(double* w, const double* V, long ld, int nv, long n, const double* h, Red red, hipStream_t st,
                    Gate gate, const Mb& mb)
 {
-    timed_launch(update_kernel, dim3(la_blocks(n), 1, mb.n), dim3(LA_NTH), st, w, V, ld, nv, n, h, gate, red, mb.ms);
+    timed_launch(update_kernel, dim3(la_blocks(n), 1, mb.n), dim3(LA_NTH), st, w, V, ld, nv, n, h, gate, red, mb.ms,
+                 mb.tab);
     if (red.out) launch_finalize(red.partials, la_blocks(n), 1, red.out, st, Gate{}, mb);
 }
 
 __global__ void __launch_bounds__(256)
 scale_kernel(double* __restrict__ out, const double* __restrict__ in, long n, const double* __restrict__ nrm2,
-             double sgn, long ms)
+             double sgn, long ms, const MemberArgs* __restrict__ mt)
 {
+    n = len_of(n, mt);
     out = mbr(out, ms);
     in = mbr(in, ms);
     nrm2 = mbr(nrm2, ms);
@@ -255,13 +262,15 @@ void launch_scale(double* out, const double* in, long n, const double* nrm2, hip
                   const Mb& mb)
 {
     long b = (n + 255) / 256;
-    scale_kernel<<<dim3((unsigned)(b < 4096 ? b : 4096), 1, mb.n), dim3(256), 0, st>>>(out, in, n, nrm2, sgn, mb.ms);
+    scale_kernel<<<dim3((unsigned)(b < 4096 ? b : 4096), 1, mb.n), dim3(256), 0, st>>>(out, in, n, nrm2, sgn, mb.ms,
+                                                                                       mb.tab);
 }
 
 __global__ void __launch_bounds__(LA_NTH)
 lincomb_kernel(double* out, const double* base_, const double* __restrict__ Z, long ld, int nv, long n,
-               const double* __restrict__ y, long ms)
+               const double* __restrict__ y, long ms, const MemberArgs* __restrict__ mt)
 {
+    n = len_of(n, mt);
     out = mbr(out, ms);
     base_ = mbr(base_, ms);
     Z = mbr(Z, ms);
@@ -293,13 +302,14 @@ lincomb_kernel(double* out, const double* base_, const double* __restrict__ Z, l
 void launch_lincomb(double* out, const double* base, const double* Z, long ld, int nv, long n, const double* y,
                     hipStream_t st, const Mb& mb)
 {
-    lincomb_kernel<<<dim3(la_blocks(n), 1, mb.n), dim3(LA_NTH), 0, st>>>(out, base, Z, ld, nv, n, y, mb.ms);
+    lincomb_kernel<<<dim3(la_blocks(n), 1, mb.n), dim3(LA_NTH), 0, st>>>(out, base, Z, ld, nv, n, y, mb.ms, mb.tab);
 }
 
 __global__ void __launch_bounds__(256)
 axpby_kernel(double* out, double a, const double* x, double b, const double* y,
-             long n, long ms)
+             long n, long ms, const MemberArgs* __restrict__ mt)
 {
+    n = len_of(n, mt);
     out = mbr(out, ms);
     x = mbr(x, ms);
     y = mbr(y, ms);
@@ -310,7 +320,8 @@ void launch_axpby(double* out, double a, const double* x, double b, const double
                   const Mb& mb)
 {
     long blk = (n + 255) / 256;
-    axpby_kernel<<<dim3((unsigned)(blk < 4096 ? blk : 4096), 1, mb.n), dim3(256), 0, st>>>(out, a, x, b, y, n, mb.ms);
+    axpby_kernel<<<dim3((unsigned)(blk < 4096 ? blk : 4096), 1, mb.n), dim3(256), 0, st>>>(out, a, x, b, y, n, mb.ms,
+                                                                                           mb.tab);
 }
 
 // Stage of the DG-level pseudo-time smoother; out may alias x0 or t (no restrict):

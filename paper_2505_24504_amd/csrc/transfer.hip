@@ -30,11 +30,14 @@ __device__ __forceinline__ long subcell_index(int ex, int ez, int i, int j, int 
 // written by the same thread).
 // With x1 != nullptr the kernel also takes the first RK stage of the finest FV
 // level from x = 0: x1 = (alpha dtau) u and the block partials of ||x1||^2.
-template <int N1, typename T>
+template <int N1, typename T, bool RG>
 __global__ void __launch_bounds__(TrShape<N1>::NTH)
-transfer_T_kernel(DgArgs A, int mass_fix, const double* U, T* __restrict__ u, int nxf, const double* snrm2,
-                  double* Us, T* __restrict__ x1, const double* __restrict__ slots, double alpha, Red red, long ms)
+transfer_T_kernel(DgArgs Aa, const MemberArgs* __restrict__ mt, int mass_fix, const double* U, T* __restrict__ u,
+                  int nxf, const double* snrm2, double* Us, T* __restrict__ x1, const double* __restrict__ slots,
+                  double alpha, Red red, long ms)
 {
+    const DgArgs& A = dg_of<RG>(Aa, mt);
+    if (RG) nxf = N1 * A.nx;
     U = mbr(U, ms);
     u = mbr(u, ms);
     snrm2 = mbr(snrm2, ms);
@@ -43,6 +46,10 @@ transfer_T_kernel(DgArgs A, int mass_fix, const double* U, T* __restrict__ u, in
     slots = mbr(slots, ms);
     red = mbr(red, ms);
     constexpr int NP = TrShape<N1>::NP, EPB = TrShape<N1>::EPB;
+    if ((long)blockIdx.x * EPB >= A.ne) {   // beyond a smaller member of a ragged batch
+        if (x1 && threadIdx.x == 0) red.partials[block_linear()] = 0.0;
+        return;
+    }
     __shared__ double sU[EPB][4][NP];
     __shared__ double sH[EPB][4][NP];
     const int t = threadIdx.x, le = t / NP, nd = t - le * NP;
@@ -118,15 +125,21 @@ transfer_T_kernel(DgArgs A, int mass_fix, const double* U, T* __restrict__ u, in
     if (x1) put_partial<TrShape<N1>::NTH>(red, nrm);
 }
 
-template <int N1, typename T>
+template <int N1, typename T, bool RG>
 __global__ void __launch_bounds__(TrShape<N1>::NTH)
-transfer_Tinv_kernel(DgArgs A, int mass_fix, const T* __restrict__ u, double* __restrict__ U, int nxf, Red red,
-                     long ms)
+transfer_Tinv_kernel(DgArgs Aa, const MemberArgs* __restrict__ mt, int mass_fix, const T* __restrict__ u,
+                     double* __restrict__ U, int nxf, Red red, long ms)
 {
+    const DgArgs& A = dg_of<RG>(Aa, mt);
+    if (RG) nxf = N1 * A.nx;
     u = mbr(u, ms);
     U = mbr(U, ms);
     red = mbr(red, ms);
     constexpr int NP = TrShape<N1>::NP, NTH = TrShape<N1>::NTH, EPB = TrShape<N1>::EPB;
+    if ((long)blockIdx.x * EPB >= A.ne) {   // beyond a smaller member of a ragged batch
+        if (red.partials && threadIdx.x == 0) red.partials[block_linear()] = 0.0;
+        return;
+    }
     __shared__ double sT[EPB][4][NP];
     __shared__ double sH[EPB][4][NP];
     const int t = threadIdx.x, le = t / NP, nd = t - le * NP;
@@ -195,21 +208,43 @@ int transfer_grid(int k, long ne)
     return (int)((ne + epb - 1) / epb);
 }
 
+template <int N1, typename T, bool RG>
+static void transfer_T_n(dim3 g, const DgArgs& A, int mass_fix, const double* U, T* u, int nxf, hipStream_t st,
+                         const double* snrm2, double* Us, const Mb& mb, const ZeroStage<T>& z0)
+{
+    timed_launch(transfer_T_kernel<N1, T, RG>, g, dim3(TrShape<N1>::NTH), st, A, mb.tab, mass_fix, U, u, nxf, snrm2,
+                 Us, z0.x1, z0.slots, z0.alpha, z0.red, mb.ms);
+}
+
+template <int N1, typename T>
+static void transfer_T_k(dim3 g, const DgArgs& A, int mass_fix, const double* U, T* u, int nxf, hipStream_t st,
+                         const double* snrm2, double* Us, const Mb& mb, const ZeroStage<T>& z0)
+{
+    if (mb.tab) transfer_T_n<N1, T, true>(g, A, mass_fix, U, u, nxf, st, snrm2, Us, mb, z0);
+    else transfer_T_n<N1, T, false>(g, A, mass_fix, U, u, nxf, st, snrm2, Us, mb, z0);
+}
+
 template <typename T>
 int launch_transfer_T(int k, const DgArgs& A, int mass_fix, const double* U, T* u, int nxf, hipStream_t st,
                       const double* snrm2, double* Us, const Mb& mb, const ZeroStage<T>& z0)
 {
     const dim3 g(transfer_grid(k, A.ne), 1, mb.n);
-    if (k == 1)
-        timed_launch(transfer_T_kernel<2, T>, g, dim3(TrShape<2>::NTH), st, A, mass_fix, U, u, nxf, snrm2, Us, z0.x1,
-                     z0.slots, z0.alpha, z0.red, mb.ms);
-    else if (k == 2)
-        timed_launch(transfer_T_kernel<3, T>, g, dim3(TrShape<3>::NTH), st, A, mass_fix, U, u, nxf, snrm2, Us, z0.x1,
-                     z0.slots, z0.alpha, z0.red, mb.ms);
-    else
-        timed_launch(transfer_T_kernel<4, T>, g, dim3(TrShape<4>::NTH), st, A, mass_fix, U, u, nxf, snrm2, Us, z0.x1,
-                     z0.slots, z0.alpha, z0.red, mb.ms);
+    if (k == 1) transfer_T_k<2, T>(g, A, mass_fix, U, u, nxf, st, snrm2, Us, mb, z0);
+    else if (k == 2) transfer_T_k<3, T>(g, A, mass_fix, U, u, nxf, st, snrm2, Us, mb, z0);
+    else transfer_T_k<4, T>(g, A, mass_fix, U, u, nxf, st, snrm2, Us, mb, z0);
     return (int)g.x;
+}
+
+template <int N1, typename T>
+static void transfer_Tinv_k(dim3 g, const DgArgs& A, int mass_fix, const T* u, double* U, int nxf, Red red,
+                            hipStream_t st, const Mb& mb)
+{
+    if (mb.tab)
+        timed_launch(transfer_Tinv_kernel<N1, T, true>, g, dim3(TrShape<N1>::NTH), st, A, mb.tab, mass_fix, u, U, nxf,
+                     red, mb.ms);
+    else
+        timed_launch(transfer_Tinv_kernel<N1, T, false>, g, dim3(TrShape<N1>::NTH), st, A, mb.tab, mass_fix, u, U,
+                     nxf, red, mb.ms);
 }
 
 template <typename T>
@@ -217,9 +252,9 @@ void launch_transfer_Tinv(int k, const DgArgs& A, int mass_fix, const T* u, doub
                           const Mb& mb)
 {
     const dim3 g(transfer_grid(k, A.ne), 1, mb.n);
-    if (k == 1) timed_launch(transfer_Tinv_kernel<2, T>, g, dim3(TrShape<2>::NTH), st, A, mass_fix, u, U, nxf, red, mb.ms);
-    else if (k == 2) timed_launch(transfer_Tinv_kernel<3, T>, g, dim3(TrShape<3>::NTH), st, A, mass_fix, u, U, nxf, red, mb.ms);
-    else timed_launch(transfer_Tinv_kernel<4, T>, g, dim3(TrShape<4>::NTH), st, A, mass_fix, u, U, nxf, red, mb.ms);
+    if (k == 1) transfer_Tinv_k<2, T>(g, A, mass_fix, u, U, nxf, red, st, mb);
+    else if (k == 2) transfer_Tinv_k<3, T>(g, A, mass_fix, u, U, nxf, red, st, mb);
+    else transfer_Tinv_k<4, T>(g, A, mass_fix, u, U, nxf, red, st, mb);
     if (red.out) launch_finalize(red.partials, (int)g.x, 1, red.out, st, Gate{}, mb);
 }
 

@@ -67,7 +67,8 @@ EXPORTS = [
     "jfmg_batch_create", "jfmg_batch_destroy", "jfmg_batch_admit", "jfmg_batch_member", "jfmg_batch_run",
     "jfmg_batch_start", "jfmg_batch_stop", "jfmg_batch_wait_any", "jfmg_batch_poll", "jfmg_batch_retire",
     "jfmg_batch_arena_free", "jfmg_batch_last_error", "jfmg_get_tiles", "jfmg_set_tiles", "jfmg_autotune",
-    "jfmg_stage_residual_noalloc", "jfmg_newton_stage",
+    "jfmg_stage_residual_noalloc", "jfmg_newton_stage", "jfmg_ensemble_workspace_bytes", "jfmg_create_ensemble",
+    "jfmg_member_dofs",
 ]
 
 # FV operator tile shapes (jfmg_tile), by index
@@ -131,6 +132,9 @@ def load_library(path: str = LIB_PATH):
         "jfmg_autotune": (C.c_int, [vp, C.c_int, ip, dp]),
         "jfmg_stage_residual_noalloc": (C.c_int, [C.POINTER(Config), vp, vp, C.c_double, vp, vp, vp]),
         "jfmg_newton_stage": (C.c_int, [vp, vp, C.c_double, vp, C.POINTER(Stats)]),
+        "jfmg_ensemble_workspace_bytes": (C.c_int, [C.POINTER(Config), C.c_int, C.POINTER(C.c_size_t)]),
+        "jfmg_create_ensemble": (C.c_int, [C.POINTER(Config), C.c_int, vp, C.c_size_t, vp, C.POINTER(vp)]),
+        "jfmg_member_dofs": (C.c_size_t, [vp, C.c_int]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -182,16 +186,41 @@ def workspace_bytes(d: dict) -> int:
     return n.value
 
 
+def _configs(ds):
+    arr = (Config * len(ds))()
+    for i, d in enumerate(ds):
+        arr[i] = make_config(d)
+    return arr
+
+
+def ensemble_workspace_bytes(ds) -> int:
+    """Workspace bytes of a ragged batch of the member descriptions ds."""
+    L = load_library()
+    n = C.c_size_t()
+    rc = L.jfmg_ensemble_workspace_bytes(_configs(ds), len(ds), C.byref(n))
+    if rc:
+        raise JfmgError(rc, L.jfmg_last_error(None).decode())
+    return n.value
+
+
 class Problem:
     """One problem in a device workspace owned by this object (a torch tensor)."""
 
-    def __init__(self, d: dict, device="cuda", stream=None, workspace=None):
+    def __init__(self, d, device="cuda", stream=None, workspace=None):
+        """d: a problem description, or a list of them for a ragged batch (ensemble members
+        of different grid sizes in one problem)."""
         self.L = load_library()
-        self.d = dict(d)
-        self.cfg = make_config(d)
+        ragged = isinstance(d, (list, tuple))
+        self.d = [dict(x) for x in d] if ragged else dict(d)
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        nbytes = workspace_bytes(d)
+        if ragged:
+            self.cfgs = _configs(d)
+            self.cfg = self.cfgs[0]
+            nbytes = ensemble_workspace_bytes(d)
+        else:
+            self.cfg = make_config(d)
+            nbytes = workspace_bytes(d)
         self.ws_bytes = nbytes
         if workspace is None:
             workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
@@ -199,13 +228,20 @@ class Problem:
         base = workspace.data_ptr()
         off = (-base) % 256
         h = C.c_void_p()
-        rc = self.L.jfmg_create_problem(C.byref(self.cfg), C.c_void_p(base + off), nbytes,
-                                        C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if ragged:
+            rc = self.L.jfmg_create_ensemble(self.cfgs, len(d), C.c_void_p(base + off), nbytes,
+                                             C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        else:
+            rc = self.L.jfmg_create_problem(C.byref(self.cfg), C.c_void_p(base + off), nbytes,
+                                            C.c_void_p(self.stream.cuda_stream), C.byref(h))
         if rc:
             raise JfmgError(rc, self.L.jfmg_last_error(None).decode())
         self.h = h
-        self.ndof = self.L.jfmg_num_dofs(h)            # per member
-        self.members = max(1, int(self.cfg.batch))    # lock-step batch size
+        self.ragged = ragged
+        self.members = len(d) if ragged else max(1, int(self.cfg.batch))   # batch size
+        # DG entries of each member; state vectors hold the members back to back
+        self.member_ndof = [self.L.jfmg_member_dofs(h, m) for m in range(self.members)]
+        self.ndof = self.L.jfmg_num_dofs(h)            # per member (the envelope's in a ragged batch)
         self.fv_dtype = torch.float32 if self.cfg.mg_precision == 32 else torch.float64
 
     def __del__(self):
@@ -223,8 +259,16 @@ class Problem:
         return torch.zeros(self.ndof, dtype=torch.float64, device=self.device)
 
     def state_zeros(self):
-        """A state of every member, members back to back (B * N)."""
-        return torch.zeros(self.members * self.ndof, dtype=torch.float64, device=self.device)
+        """A state of every member, members back to back."""
+        return torch.zeros(sum(self.member_ndof), dtype=torch.float64, device=self.device)
+
+    def member_slices(self):
+        """The slice of each member in a state vector."""
+        out, o = [], 0
+        for n in self.member_ndof:
+            out.append(slice(o, o + n))
+            o += n
+        return out
 
     def fv_size(self, level=0):
         return self.L.jfmg_fv_size(self.h, level)

@@ -90,6 +90,31 @@ def test_invalid_configs_rejected(lib, bad, what):
     assert what in str(ei.value)
 
 
+def test_ensemble_workspace_and_member_checks(lib):
+    """A ragged batch is laid out for the envelope grid (each member a region of the
+    largest nx and nz, plus the member table); members that differ in anything but
+    the grid and the domain, or a key with DG-level smoothing, are EINVAL."""
+    ens = W.ensemble(seed=4, members=64)
+    ds = [ens[0][0], dict(ens[0][0], nx=96, nz=16), dict(ens[0][0], nx=32, nz=48, x1=800.0)]
+    b = jfmg.ensemble_workspace_bytes(ds)
+    env = jfmg.workspace_bytes(dict(ds[0], nx=96, nz=48))
+    assert 3 * env < b <= 3 * env + 3 * 8192 + 256
+    assert jfmg.ensemble_workspace_bytes(ds[:1]) > jfmg.workspace_bytes(ds[0])
+    for bad, what in [({"k": 3}, "differ only"), ({"dt": 2.0}, "differ only"), ({"batch": 2}, "single problems"),
+                      ({"nx": 3}, "member 1")]:
+        with pytest.raises(jfmg.JfmgError) as ei:
+            jfmg.ensemble_workspace_bytes([ds[0], dict(ds[1], **bad)])
+        assert ei.value.status == jfmg.EINVAL and what in str(ei.value), (bad, str(ei.value))
+    with pytest.raises(jfmg.JfmgError) as ei:
+        jfmg.ensemble_workspace_bytes([dict(d, mg_key="mg102222V", pseudo_cfl_dg=0.3) for d in ds])
+    assert "DG-level smoothing" in str(ei.value)
+    with pytest.raises(jfmg.JfmgError):
+        jfmg.ensemble_workspace_bytes([])
+    cfgs = (jfmg.Config * 2)(jfmg.make_config(ds[0]), jfmg.make_config(ds[1]))
+    h = C.c_void_p()
+    assert lib.jfmg_create_ensemble(cfgs, 2, C.c_void_p(256), 16, None, C.byref(h)) == jfmg.ENOMEM
+
+
 def test_create_rejects_small_workspace(lib):
     d, _, _ = W.bubble_small()
     cfg = jfmg.make_config(d)

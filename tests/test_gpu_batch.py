@@ -175,3 +175,55 @@ def test_lockstep_rejects_single_problem_calls():
     pb = jfmg.Problem(dict(d, batch=2), device=DEV)
     with pytest.raises(jfmg.JfmgError):
         pb.residual(pb.dg_zeros())
+
+
+def _ragged_vs_alone(members, steps, prec):
+    """A ragged batch (members of different grid sizes and domains in one problem, every
+    kernel one launch over all members) gives each member bitwise the result of the same
+    member as a single problem with the same FV tile shapes."""
+    ds = [dict(d, mg_precision=prec) for d, _ in members]
+    pb = jfmg.Problem(ds, device=DEV)
+    tiles = pb.get_tiles()
+    U = torch.cat([jfmg.Problem(d, device=DEV).initial_state(pert) for d, (_, pert) in zip(ds, members)])
+    assert U.numel() == sum(pb.member_ndof)
+    for _ in range(steps):
+        st = pb.implicit_step(U)
+        assert st["status"] == 0, st
+    torch.cuda.synchronize()
+    for i, (d, (_, pert)) in enumerate(zip(ds, members)):
+        q = jfmg.Problem(d, device=DEV)
+        q.set_tiles(tiles)
+        Ua = q.initial_state(pert)
+        for _ in range(steps):
+            q.implicit_step(Ua)
+        torch.cuda.synchronize()
+        print(f"ragged member {d['nx']}x{d['nz']} fp{prec}: equal {torch.equal(U[pb.member_slices()[i]], Ua)}")
+        assert torch.equal(U[pb.member_slices()[i]], Ua), i
+
+
+@pytest.mark.parametrize("prec", [32, 64])
+def test_ragged_ensemble_members_equal_alone(prec):
+    ens = W.ensemble(seed=4, members=64)
+    picked = []
+    for g in W.ENSEMBLE_GRIDS:   # two members of every grid, the smallest first and last
+        picked += [(d, pert) for d, pert, _ in ens if (d["nx"], d["nz"]) == g][:2]
+    picked.append(picked.pop(0))
+    _ragged_vs_alone(picked, 2, prec)
+
+
+def test_ragged_viscous_k3_different_domains():
+    d, pert, _ = W.bubble_small()
+    a = dict(d, nx=16, nz=8, k=3, physics=1, mu=75.0, x0=0.0, x1=2000.0, z0=0.0, z1=1000.0, mg_levels=3)
+    b = dict(a, nx=24, nz=16, x1=1500.0, z1=1200.0)
+    pa = dict(pert, xc=1000.0, zc=400.0)
+    pbb = dict(pert, xc=700.0, zc=500.0)
+    _ragged_vs_alone([(b, pbb), (a, pa)], 1, 64)
+
+
+def test_ragged_rejects_single_problem_calls():
+    d, _, _ = W.ensemble(seed=4, members=1)[0]
+    pb = jfmg.Problem([d, dict(d, nx=64, nz=32)], device=DEV)
+    with pytest.raises(jfmg.JfmgError):
+        pb.residual(pb.dg_zeros())
+    with pytest.raises(jfmg.JfmgError):
+        pb.initial_state(dict(shape=0, amp=1.0, xc=500.0, zc=300.0, xr=250.0, zr=250.0))
