@@ -197,6 +197,44 @@ def _lockstep_ensemble(mem, prec):
                 "reached_rtol": max(st["reached_rtol"] for _, _, st in polled)}
 
 
+def _ragged_ensemble(mem, prec, graphs=False):
+    """All members in one ragged batch (one problem; every kernel one launch over the 64
+    members of three grid sizes, tiles by the autotuner on the batch), 5 steps; with
+    graphs, every FGMRES iteration replays a captured HIP graph."""
+    import torch
+    from paper_2505_24504_amd import jfmg
+    ds = [dict(d, mg_precision=prec) for d, _, _ in mem]
+    old = os.environ.get("JFMG_GRAPH")
+    os.environ["JFMG_GRAPH"] = "1" if graphs else "0"
+    try:
+        pb = jfmg.Problem(ds, device="cuda:0")
+    finally:
+        if old is None:
+            del os.environ["JFMG_GRAPH"]
+        else:
+            os.environ["JFMG_GRAPH"] = old
+    U = torch.cat([jfmg.Problem(d, device="cuda:0").initial_state(pert) for d, (_, pert, _) in zip(ds, mem)])
+    t0 = time.perf_counter()
+    pb.linearize(U, (1.0 - 2 ** -0.5) * ds[0]["dt"])
+    tiles, _ = pb.autotune(reps=5)
+    el_tune = time.perf_counter() - t0
+    steps = mem[0][2]
+    its, stalls, reach, ok = 0, 0, 0.0, True
+    _sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st = pb.implicit_step(U, raise_on_error=False)
+        its += st["gmres_its"]
+        stalls += st["stall_stops"]
+        reach = max(reach, st["reached_rtol"])
+        ok = ok and st["status"] == 0
+    _sync()
+    el = time.perf_counter() - t0
+    return el, {"members_ok": len(mem) if ok else 0, "tiles": tiles, "autotune_seconds": el_tune,
+                "lockstep_gmres_its": its, "stall_stops": stalls, "reached_rtol": reach, "graphs": graphs,
+                "launches": "one per kernel over all 64 members (ragged batch)"}
+
+
 def ensemble_forms():
     """64-member ensemble (k = 2 warm bubbles on 32x16 / 64x32 / 96x48, 5 SDIRK2 steps
     each): lock-step groups (one batched problem per grid size) with the FP32 and with the
@@ -234,6 +272,12 @@ def ensemble_forms():
         del p
     out = {}
     progress(f"ensemble concurrent and serial forms done ({el_b:.1f} s, {el_s:.1f} s)")
+    assert len({n for _, _, n in mem}) == 1
+    for prec, graphs in ((32, False), (64, False), (32, True)):
+        el_r, info = _ragged_ensemble(mem, prec, graphs)
+        key = f"ensemble_ragged_fp{prec}" + ("_graph" if graphs else "")
+        out[key] = dict({"value": work / el_r, "seconds": el_r}, **info)
+        progress(f"ensemble ragged batch FP{prec}{' graphs' if graphs else ''}: {work / el_r:.3e} DOF-Newton-steps/s")
     for prec in (32, 64):
         el_l, info = _lockstep_ensemble(mem, prec)
         out[f"ensemble_lockstep_fp{prec}"] = dict({"value": work / el_l, "seconds": el_l}, **info)

@@ -174,7 +174,7 @@ dg_kernel(DgArgs Aa, const MemberArgs* __restrict__ mt, const double* __restrict
     }
     constexpr int NP = DgShape<N1>::NP, NTH = DgShape<N1>::NTH, EPB = DgShape<N1>::EPB, FPE = DgShape<N1>::FPE;
     const int nbm = (int)((A.ne + EPB - 1) / EPB);   // this member's work-groups
-    if ((int)blockIdx.x >= nbm) {                     // beyond a smaller member of a ragged batch
+    if ((int)blockIdx.x >= nbm || (RG && sits_out(mt))) {   // beyond a smaller member, or one that sits out
         if (MODE == 2 && threadIdx.x == 0) red.partials[block_linear()] = 0.0;
         return;
     }
@@ -502,7 +502,7 @@ norm_total_kernel(DgArgs Aa, const MemberArgs* __restrict__ mt, const double* __
     U = mbr(U, ms);
     red = mbr(red, ms);
     constexpr int NP = N1 * N1;
-    const long n = A.ne * NP;
+    const long n = sits_out(mt) ? 0 : A.ne * NP;
     const long nb = (n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024;   // this member's work-groups
     double s = 0.0;
     for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += nb * 256) {

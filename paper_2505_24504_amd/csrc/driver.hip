@@ -1046,7 +1046,17 @@ jfmg_status run_iter(jfmg_problem* p, int j)
 // Hessenberg column is read from its own pinned block and a member stops
 // taking part (its coefficients stay 0, so its delta is no longer changed)
 // once it has converged.  `active` marks the members that solve at all.
-jfmg_status fgmres(jfmg_problem* p, const double* G, const std::vector<double>& gnorm, const std::vector<double>& tol,
+// ragged batch: live flags of the members (1 for those that pred selects) in the device table
+template <typename F> void set_live(jfmg_problem* p, F&& pred)
+{
+    if (!p->ragged) return;
+    LiveBits bits{};
+    for (int b = 0; b < p->mb.n; ++b)
+        if (pred(b)) bits.w[b >> 6] |= 1ull << (b & 63);
+    launch_set_live(p->tab, p->mb.n, bits, p->st);
+}
+
+jfmg_status fgmres_cycles(jfmg_problem* p, const double* G, const std::vector<double>& gnorm, const std::vector<double>& tol,
                    const std::vector<char>& active, double* U, int* its_out)
 {
     const long N = p->N;
@@ -1079,6 +1089,7 @@ jfmg_status fgmres(jfmg_problem* p, const double* G, const std::vector<double>& 
     launch_zero(p->delta, sizeof(double) * N, st, p->mb);
     std::vector<double> ybuf((size_t)B * m), r2(B);
     jfmg_status status = left ? JFMG_ENOCONV : JFMG_OK;
+    std::vector<char> part(B);   // members that take part in the current cycle
     for (int cyc = 0; left && cyc <= p->cfg.gmres_max_restarts; ++cyc) {
         for (Member& x : M) {
             std::fill(x.g.begin(), x.g.end(), 0.0);
@@ -1087,6 +1098,10 @@ jfmg_status fgmres(jfmg_problem* p, const double* G, const std::vector<double>& 
             x.jend = 0;
             x.conv = false;
         }
+        // in a ragged batch the members that are done, and later those that converge
+        // within the cycle, sit out the iterations' kernels
+        for (int b = 0; b < B; ++b) part[b] = !M[b].done;
+        set_live(p, [&](int b) { return part[b] != 0; });
         // Iteration j+1 is issued before the host looks at iteration j's
         // Hessenberg columns, so the readback round trip overlaps GPU work, except
         // where iteration j is likely to end the cycle: a speculative iteration
@@ -1127,7 +1142,7 @@ jfmg_status fgmres(jfmg_problem* p, const double* G, const std::vector<double>& 
             HIPCHK(p, hipEventSynchronize(p->hev[j]));
             p->syncs++;
             ++its;
-            bool all_conv = true;
+            bool all_conv = true, conv_now = false;
             for (int mb = 0; mb < B; ++mb) {
                 Member& x = M[mb];
                 if (x.done || x.conv) continue;
@@ -1155,16 +1170,18 @@ jfmg_status fgmres(jfmg_problem* p, const double* G, const std::vector<double>& 
                     *its_out = its;
                     return fail(p, JFMG_ENONFINITE, "non-finite value in the Arnoldi process");
                 }
-                if (std::fabs(x.g[j + 1]) <= tol[mb] || hn == 0.0) x.conv = true;
+                if (std::fabs(x.g[j + 1]) <= tol[mb] || hn == 0.0) x.conv = conv_now = true;
                 else all_conv = false;
             }
             if (all_conv) break;
+            if (p->ragged && conv_now) set_live(p, [&](int b) { return part[b] && !M[b].conv; });
             if (next == j + 1 && j + 1 < m) {   // not issued speculatively
                 jfmg_status s = issue(j + 1);
                 if (s) return s;
                 ++next;
             }
         }
+        set_live(p, [&](int b) { return part[b] != 0; });   // the cycle's update, restart residual
         int jmax = 0;
         std::fill(ybuf.begin(), ybuf.end(), 0.0);
         for (int mb = 0; mb < B; ++mb) {
@@ -1209,8 +1226,17 @@ jfmg_status fgmres(jfmg_problem* p, const double* G, const std::vector<double>& 
     }
     *its_out = its;
     if (status != JFMG_OK) return fail(p, JFMG_ENOCONV, "FGMRES did not reach its tolerance");
+    set_live(p, [](int) { return true; });   // every member's delta, from all cycles
     launch_axpby(U, 1.0, U, 1.0, p->delta, N, st, p->mb);
     return check_launch(p);
+}
+
+jfmg_status fgmres(jfmg_problem* p, const double* G, const std::vector<double>& gnorm, const std::vector<double>& tol,
+                   const std::vector<char>& active, double* U, int* its_out)
+{
+    const jfmg_status s = fgmres_cycles(p, G, gnorm, tol, active, U, its_out);
+    set_live(p, [](int) { return true; });   // every member takes part in the Newton-level work
+    return s;
 }
 
 // Inexact Newton for G(U) = U - adt f(U) - Ubar = 0 from U^0 = Ubar; result in
@@ -1628,6 +1654,7 @@ jfmg_status create_impl(const jfmg_config* cfgs, int n, bool ragged, void* works
             std::memset(&M, 0, sizeof(M));
             M.dg = dg_args_of(p, c, ob);
             M.N = 4L * c.nx * c.nz * p->np;
+            M.live = 1;
             for (int l = 0; l < p->nlev; ++l) {
                 if (p->prec == 32) M.f32[l] = fv_args_of<float>(p, c, l, ob);
                 else M.f64[l] = fv_args_of<double>(p, c, l, ob);

@@ -180,7 +180,7 @@ fv_tile_kernel(FvArgs<T> Aa, const MemberArgs* __restrict__ mt, const T* __restr
     // tiles of this member (a one-dimensional grid; in a ragged batch the work-groups
     // beyond a smaller member's tiles only store zero partial sums)
     const unsigned ntx = (unsigned)((nxl + TX - 1) / TX), ntiles = ntx * (unsigned)((nzl + TZ - 1) / TZ);
-    if (blockIdx.x >= ntiles) {
+    if (blockIdx.x >= ntiles || (RG && sits_out(mt))) {
         if (tid == 0) {
             if constexpr (MODE == FVM_LIN) {
                 red.partials[blockIdx.x] = 0.0;
@@ -405,7 +405,8 @@ fv_stage_zero_kernel(FvArgs<T> Aa, const MemberArgs* __restrict__ mt, const T* _
     out = mbr(out, ms);
     slots = mbr(slots, ms);
     red = mbr(red, ms);
-    const long n = 4 * A.nc, nb = (n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024;   // this member's work-groups
+    const long n = sits_out(mt) ? 0 : 4 * A.nc;
+    const long nb = (n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024;   // this member's work-groups
     const T s = (T)(alpha_j * slots[LV_DTAU]);
     double nrm = 0.0;
     for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += nb * 256) {
@@ -423,6 +424,7 @@ fv_restrict_neg_kernel(FvArgs<T> Aa, const MemberArgs* __restrict__ mt, const T*
                        long ms)
 {
     const FvArgs<T>& A = fv_of<T, RG>(Aa, mt);
+    if (RG && sits_out(mt)) return;
     f = mbr(f, ms);
     c = mbr(c, ms);
     const int nxc = A.nxl / 2, nzc = A.nzl / 2;
@@ -450,7 +452,7 @@ fv_prolong_correct_kernel(FvArgs<T> Aa, const MemberArgs* __restrict__ mt, T* __
     red = mbr(red, ms);
     // a one-dimensional grid over this member's 64 x 4 tiles (row-major)
     const unsigned gx = (unsigned)((A.nxl + FV_TX - 1) / FV_TX), nt = gx * (unsigned)((A.nzl + FV_TZ - 1) / FV_TZ);
-    if (blockIdx.x >= nt) {   // beyond a smaller member of a ragged batch
+    if (blockIdx.x >= nt || sits_out(mt)) {   // beyond a smaller member, or one that sits out
         if (threadIdx.x == 0) red.partials[blockIdx.x] = 0.0;
         return;
     }
@@ -475,6 +477,7 @@ __global__ void __launch_bounds__(FV_NTH)
 fv_restrict_kernel(FvArgs<T> Aa, const MemberArgs* __restrict__ mt, const T* __restrict__ f, T* __restrict__ c, long ms)
 {
     const FvArgs<T>& A = fv_of<T, RG>(Aa, mt);
+    if (RG && sits_out(mt)) return;
     f = mbr(f, ms);
     c = mbr(c, ms);
     const int nxc = A.nxl / 2, nzc = A.nzl / 2;
@@ -495,6 +498,7 @@ __global__ void __launch_bounds__(FV_NTH)
 fv_prolong_kernel(FvArgs<T> Aa, const MemberArgs* __restrict__ mt, const T* __restrict__ c, T* __restrict__ f, long ms)
 {
     const FvArgs<T>& A = fv_of<T, RG>(Aa, mt);
+    if (RG && sits_out(mt)) return;
     c = mbr(c, ms);
     f = mbr(f, ms);
     const int I = blockIdx.x * FV_TX + (threadIdx.x & (FV_TX - 1));

@@ -155,6 +155,7 @@ enum { LV_UTOT = 0, LV_LAM = 1, LV_DTAU = 2, LV_IUTOT = 3, LV_NSLOT = 4 };   // 
 struct MemberArgs {
     DgArgs dg;
     long N;                        // DG vector length 4 ne (k+1)^2
+    int live;                      // 0: the member sits out (kernels skip it, zero partials)
     FvArgs<double> f64[MAXLEV];    // FV levels (the entries of the problem's precision are set)
     FvArgs<float> f32[MAXLEV];
 };
@@ -185,8 +186,19 @@ template <typename T, bool RG> __device__ __forceinline__ const FvArgs<T>& fv_of
     if constexpr (RG) return fv_entry<T>(t, a.lev);
     else return a;
 }
-// a vector length of the member (ragged batch) or the given one
-__device__ __forceinline__ long len_of(long n, const MemberArgs* t) { return t ? t[blockIdx.z].N : n; }
+// a vector length of the member (ragged batch; 0 while it sits out) or the given one
+__device__ __forceinline__ long len_of(long n, const MemberArgs* t)
+{
+    return t ? (t[blockIdx.z].live ? t[blockIdx.z].N : 0) : n;
+}
+// a ragged member that sits out (converged while others iterate)
+__device__ __forceinline__ bool sits_out(const MemberArgs* t) { return t && !t[blockIdx.z].live; }
+// live[m] = 1 for the members m in `bits` (at most MAXMEMBERS), by a kernel
+constexpr int MAXMEMBERS = 4096;
+struct LiveBits {
+    unsigned long long w[MAXMEMBERS / 64];
+};
+void launch_set_live(MemberArgs* tab, int n, const LiveBits& bits, hipStream_t st);
 
 // ---- DG kernels (dg.hip) ----
 // mode 0: <psi,L>  1: M^-1 L  2: G = U - adt M^-1 L - Ubar (+ ||G||^2 into red.out)

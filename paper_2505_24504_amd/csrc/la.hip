@@ -402,4 +402,15 @@ void launch_zero(void* ptr, size_t bytes, hipStream_t st, const Mb& mb)
     zero_kernel<<<dim3((unsigned)(blk < 4096 ? blk : 4096), 1, mb.n), dim3(256), 0, st>>>((unsigned*)ptr, n, mb.ms);
 }
 
+__global__ void __launch_bounds__(256) set_live_kernel(MemberArgs* __restrict__ tab, int n, LiveBits bits)
+{
+    for (int m = blockIdx.x * 256 + threadIdx.x; m < n; m += gridDim.x * 256)
+        tab[m].live = (int)((bits.w[m >> 6] >> (m & 63)) & 1ull);
+}
+
+void launch_set_live(MemberArgs* tab, int n, const LiveBits& bits, hipStream_t st)
+{
+    set_live_kernel<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(tab, n, bits);
+}
+
 }  // namespace jfmg

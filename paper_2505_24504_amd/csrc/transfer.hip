@@ -46,7 +46,7 @@ transfer_T_kernel(DgArgs Aa, const MemberArgs* __restrict__ mt, int mass_fix, co
     slots = mbr(slots, ms);
     red = mbr(red, ms);
     constexpr int NP = TrShape<N1>::NP, EPB = TrShape<N1>::EPB;
-    if ((long)blockIdx.x * EPB >= A.ne) {   // beyond a smaller member of a ragged batch
+    if ((long)blockIdx.x * EPB >= A.ne || sits_out(mt)) {   // beyond a smaller member, or one that sits out
         if (x1 && threadIdx.x == 0) red.partials[block_linear()] = 0.0;
         return;
     }
@@ -136,7 +136,7 @@ transfer_Tinv_kernel(DgArgs Aa, const MemberArgs* __restrict__ mt, int mass_fix,
     U = mbr(U, ms);
     red = mbr(red, ms);
     constexpr int NP = TrShape<N1>::NP, NTH = TrShape<N1>::NTH, EPB = TrShape<N1>::EPB;
-    if ((long)blockIdx.x * EPB >= A.ne) {   // beyond a smaller member of a ragged batch
+    if ((long)blockIdx.x * EPB >= A.ne || sits_out(mt)) {   // beyond a smaller member, or one that sits out
         if (red.partials && threadIdx.x == 0) red.partials[block_linear()] = 0.0;
         return;
     }
