@@ -17,6 +17,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liborc.so")
 _SRC = os.path.join(_HERE, "orc.c")
+# ORC_LIB names another build of orc.c to load (the sanitizer test's)
+_LOAD_PATH = os.environ.get("ORC_LIB") or _LIB_PATH
 
 GCC_CMD = ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fPIC", "-shared", "-fopenmp",
            "-ffp-contract=off", "-o", _LIB_PATH, _SRC, "-lm"]
@@ -66,9 +68,10 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        if _LOAD_PATH == _LIB_PATH and (not os.path.exists(_LIB_PATH)
+                                        or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC)):
             build()
-        L = C.CDLL(_LIB_PATH)
+        L = C.CDLL(_LOAD_PATH)
         dp = C.POINTER(C.c_double)
         L.orc_create.restype = C.c_void_p
         L.orc_create.argtypes = [C.POINTER(OrcCfg)]

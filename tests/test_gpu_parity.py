@@ -653,3 +653,26 @@ def test_graph_replay_matches_eager(monkeypatch):
     p_eager.implicit_step(U2)
     assert s1["gmres_its"] == s2["gmres_its"]
     assert torch.equal(U1, U2)
+
+
+def test_checkpoint_resume_bitwise(tmp_path):
+    """A run stopped after two steps, its state written to a file and read into a new
+    problem, continues bitwise as the uninterrupted run: an implicit step carries no
+    solver state besides U (the Newton iteration starts from U^n, the linearization,
+    Krylov basis and multigrid levels are rebuilt inside the step)."""
+    d, pert, _ = W.bubble_small()
+    d = dict(d, scheme=1, nx=12, nz=12, k=2)
+    p = jfmg.Problem(d, device=DEV)
+    U = p.initial_state(pert)
+    ref = U.clone()
+    for _ in range(3):
+        assert p.implicit_step(ref)["status"] == 0
+    for _ in range(2):
+        p.implicit_step(U)
+    np.save(tmp_path / "checkpoint.npy", U.cpu().numpy())
+    del p
+    q = jfmg.Problem(d, device=DEV)
+    U2 = torch.from_numpy(np.load(tmp_path / "checkpoint.npy")).to(DEV)
+    assert q.implicit_step(U2)["status"] == 0
+    torch.cuda.synchronize()
+    assert torch.equal(U2, ref)
