@@ -4,8 +4,12 @@
 // f_low on level l is the DG scheme with k = 0 on the subgrid: HLLC on the face
 // total states (cell value + Ubar at the face), the k = 0 interior-penalty
 // diffusion flux with penalty 1/h, and the gravity source.  The kernels carry
-// the flux sum without the constant background-flux term; every use is a
-// difference f(u + eps x) - f(u), in which that constant cancels.
+// the flux sum without the constant background-flux term, and each face's
+// normal-momentum flux without the face's background pressure pb (the HLLC flux
+// is affine in the pressure: F = F' + pb e_D, F' computed from p - pb); every
+// use is a difference f(u + eps x) - f(u), in which those state-independent
+// terms cancel, and the difference then loses digits only at the scale of
+// p - pb and of the other fluxes, not at that of pb (about 10^5 Pa).
 //
 // Layout: SoA [4][nzl][nxl].  A work-group is a 64 x 4 tile of cells (one
 // wave per row of 64 cells along x, so loads of a component are 256-byte
@@ -87,9 +91,11 @@ __device__ __forceinline__ void fv_face(const FvArgs<T>& A, const T (&sw)[4][HZ]
         if (wallL) UL[D] = -UL[D];
         if (wallR) UR[D] = -UR[D];
         const T pb = pr[0], irb = pr[1];
-        const T pL = pert_pressure(A.gas, wL[3], irb, pb), pR = pert_pressure(A.gas, wR[3], irb, pb);
+        // the face's background pressure is left out of the flux (see the file comment)
+        const T dpL = pert_dpress(A.gas, wL[3], irb, pb), dpR = pert_dpress(A.gas, wR[3], irb, pb);
+        const T pL = pb + dpL, pR = pb + dpR;
         const T irL = frcp<T>(UL[0]), irR = frcp<T>(UR[0]);
-        hllc_ax<T, D>(A.gas, UL, UR, pL, pR, irL, irR, Phi);
+        hllc_ax_dp<T, D>(A.gas, UL, UR, pL, pR, dpL, dpR, irL, irR, Phi);
         if (A.physics == 1 && !wall) {
             // k = 0 diffusion: mean of mu (G_c - (U_c/rho) G_rho) over both sides, where the
             // only gradient is the background's (z-faces), minus the interior penalty

@@ -145,6 +145,34 @@ template <typename T> __device__ __forceinline__ T pert_pressure(const Gas<T>& G
     return pb * f;
 }
 
+// The pressure's deviation from the background, p - pb = pb ((1 + s)^gamma - 1): the
+// series of pert_pressure without its constant term, so that it is accurate to the
+// unit roundoff of p - pb rather than of p (FP32 FV operators, whose values enter only
+// differences of two evaluations, carry p - pb where the pressure enters additively).
+template <typename T> __device__ __forceinline__ T pert_dpress(const Gas<T>& G, T rt1, T irtb, T pb)
+{
+    constexpr bool F32 = std::is_same_v<T, float>;
+    const T s = rt1 * irtb;
+    const T as = dabs<T>(s);
+    T f;
+    if (as <= T(1.0 / 1024.0)) {
+        constexpr int n = F32 ? 4 : 6;
+        f = G.cg[n - 1];
+#pragma unroll
+        for (int k = n - 2; k >= 1; --k) f = f * s + G.cg[k];
+        f = f * s;
+    } else if (as <= T(0.05)) {
+        constexpr int n = F32 ? 7 : GAS_NCOEF;
+        f = G.cg[n - 1];
+#pragma unroll
+        for (int k = n - 2; k >= 1; --k) f = f * s + G.cg[k];
+        f = f * s;
+    } else {
+        f = dpow<T>(T(1) + s, G.gamma) - T(1);
+    }
+    return pb * f;
+}
+
 // Convective flux F_c(U) . n for an axis-aligned unit normal (nx, nz), pressure p given.
 template <typename T>
 __device__ __forceinline__ void conv_flux(const T* U, T p, T nx, T nz, T* F)
@@ -276,6 +304,47 @@ __device__ __forceinline__ void hllc_face(const Gas<T>& G, const T* UL, const T*
     F[1] = xf ? fd : Fn[2];
     F[2] = xf ? Fn[2] : fd;
     F[3] = Fn[3];
+}
+
+// The same HLLC flux less pb e_D (pb: the background pressure of the face, the same on
+// both sides): p (full) sets the sound speeds, dp = p - pb enters wherever the pressure
+// is added (the physical fluxes, the star pressure, p_R - p_L).  Algebraically
+// F - pb e_D, since the star flux (S*(S_K U_K - F_K) + S_K p*_K e_D) / (S_K - S*) is
+// affine in the pressure with weight one.
+template <typename T, int D>
+__device__ __forceinline__ void hllc_ax_dp(const Gas<T>& G, const T* UL, const T* UR, T pL, T pR, T dpL, T dpR, T irL,
+                                           T irR, T* F)
+{
+    constexpr int E = 3 - D;   // tangential momentum
+    const T rL = UL[0], rR = UR[0];
+    const T qL = UL[D] * irL, qR = UR[D] * irR;
+    const T cL = psqrt<T>(G.gamma * pL * irL), cR = psqrt<T>(G.gamma * pR * irR);
+    const T SL = fmin(qL - cL, qR - cR);
+    const T SR = fmax(qL + cL, qR + cR);
+    if (SL >= T(0)) {
+        F[0] = UL[D];
+        F[D] = UL[D] * qL + dpL;
+        F[E] = UL[E] * qL;
+        F[3] = UL[3] * qL;
+        return;
+    }
+    if (SR <= T(0)) {
+        F[0] = UR[D];
+        F[D] = UR[D] * qR + dpR;
+        F[E] = UR[E] * qR;
+        F[3] = UR[3] * qR;
+        return;
+    }
+    const T Ss = (dpR - dpL + rL * qL * (SL - qL) - rR * qR * (SR - qR)) * frcp<T>(rL * (SL - qL) - rR * (SR - qR));
+    const bool lk = Ss >= T(0);
+    const T SK = lk ? SL : SR, rK = lk ? rL : rR, qK = lk ? qL : qR, dpK = lk ? dpL : dpR;
+    const T uD = lk ? UL[D] : UR[D], uE = lk ? UL[E] : UR[E], u3 = lk ? UL[3] : UR[3];
+    const T pst = dpK + rK * (SK - qK) * (Ss - qK);
+    const T iden = frcp<T>(SK - Ss);
+    F[0] = (Ss * (SK * rK - uD)) * iden;
+    F[D] = (Ss * (SK * uD - (uD * qK + dpK)) + SK * pst) * iden;
+    F[E] = (Ss * (SK * uE - uE * qK)) * iden;
+    F[3] = (Ss * (SK * u3 - u3 * qK)) * iden;
 }
 
 // Viscous flux F_v(U, G) . n = mu rho grad(U_c / rho) . n written with the

@@ -13,9 +13,9 @@ EPS = 2.0 ** -52
 # (never above 10x) the largest normalized error measured on MI355X.
 C_LH = 4.0            # L_h: x eps ||sigma (/ m)||, sigma the rounding scale    (measured 0.41-0.50)
 C_JVP = 5.0           # JVP: x (alpha dt / eps) eps ||sigma / m||               (measured 0.56-0.70)
-C_FV = 2.15           # FV matvec: x (alpha dt / eps) eps (4 p0 / h) sqrt(n)    (measured 0.22-0.27)
-REL_MG_FV = 1.5e-7    # one FV cycle, relative                                 (measured <= 1.8e-8)
-REL_MG_APPLY = 2.5e-7  # Q^-1, relative                                        (measured <= 3.8e-8)
+C_FV = 1.65           # FV matvec: x (alpha dt / eps) eps (4 p0 / h) sqrt(n)    (measured 0.17-0.21)
+REL_MG_FV = 1.1e-7    # one FV cycle, relative                                 (measured <= 1.34e-8)
+REL_MG_APPLY = 2.25e-7  # Q^-1, relative                                       (measured <= 2.81e-8)
 REL_STEP_BUBBLE = 1e-10   # relative L2 of U', 16x16 bubble steps              (measured <= 4.1e-11)
 REL_STEP_SDIRK2 = 5e-11   # relative L2 of U', 8x8 SDIRK2 steps                (measured <= 6.2e-12)
 

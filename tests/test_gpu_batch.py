@@ -122,7 +122,7 @@ def test_fp32_mg_step_vs_fp64_oracle_inertia_gravity():
     d, pert, _ = W.inertia_gravity(mg_precision=32)
     d = dict(d, nx=60, nz=4, x1=30000.0)
     pert = dict(pert, xc=15000.0)
-    _fp32_vs_oracle(d, pert, 1.5e-9)                           # measured 1.8e-10
+    _fp32_vs_oracle(d, pert, 1.5e-9)                           # measured 1.7-1.8e-10
 
 
 @pytest.mark.parametrize("prec,key", [(32, None), (64, None), (32, "mg112222V")])

@@ -117,7 +117,6 @@ def test_initial_state_parity(which):
     Uo = o.initial_state(pert)
     n = o.ndof // 4
     assert np.all(Ug[3 * n:] == 0.0) and np.all(Ug[2 * n:3 * n] == 0.0)
-    # rho' = rho - rho_bar cancels: its round-off is relative to the total density
     # rho' = rho - rho_bar with rho = (rho theta)_bar / (theta_bar + theta'): a few roundings
     # of the total density per node
     rho = _total_density_norm(o, d, Uo)
