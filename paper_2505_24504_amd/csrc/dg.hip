@@ -332,13 +332,23 @@ dg_kernel(DgArgs Aa, const MemberArgs* __restrict__ mt, const double* __restrict
         }
     }
     if constexpr (MODE == 5) return;
+    // U'_rho and y are read again for the output (not held through the face phase);
+    // the loads are issued before the barrier so that their latency overlaps it
+    double y_d[4] = {0.0, 0.0, 0.0, 0.0}, urho_d = 0.0;
+    if constexpr (MODE == 3) {
+        if (valid) {
+            const double* Ud = opaque(U);
+            const double* Yd = opaque(Y);
+            urho_d = ld(Ud, no);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) y_d[c] = ld(Yd + c * N, no);
+        }
+    }
     __syncthreads();
 
     // ---- D: contraction, lifting and output ----
     double nrm = 0.0;
     if (valid) {
-        const double* Ud = opaque(U);   // U' and y are read again here
-        const double* Yd = opaque(Y);
         const double m = R.w[a] * R.w[b] * A.J, im = frcp(m);
         const double sc = MODE == 3 ? adt / eps : 0.0;
 #pragma unroll
@@ -357,7 +367,7 @@ dg_kernel(DgArgs Aa, const MemberArgs* __restrict__ mt, const double* __restrict
             }
             if (c == 2) {
                 // gravity; JVP: of (U' + eps y)_rho - U'_rho
-                if constexpr (MODE == 3) L += m * (-A.g * (sS[le][0][nd] - ld(Ud, no)));
+                if constexpr (MODE == 3) L += m * (-A.g * (sS[le][0][nd] - urho_d));
                 else L += m * (-A.g * sS[le][0][nd]);
             }
             if constexpr (MODE == 0) st(out + c * N, no, L);
@@ -367,7 +377,7 @@ dg_kernel(DgArgs Aa, const MemberArgs* __restrict__ mt, const double* __restrict
                 st(out + c * N, no, G);
                 nrm += G * G;
             } else if constexpr (MODE == 3) {
-                st(out + c * N, no, ld(Yd + c * N, no) - sc * (L * im));
+                st(out + c * N, no, y_d[c] - sc * (L * im));
             } else {   // explicit Runge-Kutta stage
                 const double base = rk.a0 != 0.0 ? rk.a0 * ld(Ubar + c * N, no) : 0.0;
                 st(out + c * N, no, base + rk.a1 * sS[le][c][nd] + rk.c * (L * im));

@@ -207,20 +207,53 @@ fv_tile_kernel(FvArgs<T> Aa, const MemberArgs* __restrict__ mt, const T* __restr
     const bool valid = tid < NCELL && I < nxl && J < nzl;
     const long q = (long)J * nxl + I;
 
-    // ---- every global load first (own-cell operands, then the halo states), or
-    // the own-cell operands only after the face loop (LATE: fewer live registers) ----
+    // ---- every global load first (the level's scalars and background rows, the
+    // own-cell operands, then the halo states), or the own-cell operands only after
+    // the face loop (LATE: fewer live registers).  Nothing below waits on memory
+    // before the partial sums of ||x||^2 have arrived. ----
+    double s_utot = 0.0, s_iutot = 0.0, s_dtau = 0.0;
+    if constexpr (PERT) {
+        s_utot = slots[LV_UTOT];
+        s_iutot = slots[LV_IUTOT];
+    }
+    if constexpr (MODE == FVM_STAGE || MODE == FVM_STAGE_PC) s_dtau = slots[LV_DTAU];
+    if constexpr (MODE == FVM_DEFECT) s_dtau = out2 ? slots2[LV_DTAU] : 0.0;
+    static_assert(NTH >= 6 * TZ + 10 * (TZ + 1), "background staging");
+    T bg_v = T(0);   // this thread's entry of sBc / sBf
+    if (tid < 6 * TZ) {
+        const int r = tid / 6, k = tid - 6 * r, Jr = J0 + r;
+        if (Jr < nzl) bg_v = k < 4 ? A.bgc[4 * Jr + k] : A.pc[2 * Jr + k - 4];
+    } else if (tid < 6 * TZ + 10 * (TZ + 1)) {
+        const int t2 = tid - 6 * TZ, r = t2 / 10, k = t2 - 10 * r, Jr = J0 + r;
+        if (Jr <= nzl) bg_v = k < 4 ? A.bgf[4 * Jr + k] : k < 6 ? A.pf[2 * Jr + k - 4] : A.dbgf[4 * Jr + k - 6];
+    }
     T own_x[4] = {T(0), T(0), T(0), T(0)}, own_f0[4] = {T(0), T(0), T(0), T(0)};
     T own_b[4] = {T(0), T(0), T(0), T(0)}, own_x0[4] = {T(0), T(0), T(0), T(0)};
+    // STAGE_PC: the finer level's four children of the cell, read with the own-cell
+    // operands (before any of them is written)
+    T own_xf[4][4] = {};
     auto load_own = [&]() {
         if (valid) {
+            if constexpr (MODE == FVM_STAGE_PC)
+                if (!fzero) {
+                    const long nxf = 2L * nxl, ncf = 4 * nc;
+                    const long q00 = (long)(2 * J) * nxf + 2 * I, q10 = q00 + nxf;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const T* xf = out2 + c * ncf;
+                        own_xf[c][0] = xf[q00]; own_xf[c][1] = xf[q00 + 1];
+                        own_xf[c][2] = xf[q10]; own_xf[c][3] = xf[q10 + 1];
+                    }
+                }
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 if constexpr (PERT) { own_x[c] = xp[c * nc + q]; own_f0[c] = F0[c * nc + q]; }
                 if constexpr (MODE == FVM_STAGE || MODE == FVM_STAGE_PC || MODE == FVM_DEFECT)
                     own_b[c] = b[c * nc + q];
-                // the first stage of a sweep has x^(0) = x^(j-1): no second load
+                // the first stage of a sweep has x^(0) = x^(j-1): no second load (the copy
+                // is taken where x^(0) is used, so that no load waits for another)
                 if constexpr (MODE == FVM_STAGE || MODE == FVM_STAGE_PC)
-                    own_x0[c] = x0 ? (x0 == xp ? own_x[c] : x0[c * nc + q]) : T(0);
+                    if (x0 && x0 != xp) own_x0[c] = x0[c * nc + q];
             }
         }
     };
@@ -252,8 +285,8 @@ fv_tile_kernel(FvArgs<T> Aa, const MemberArgs* __restrict__ mt, const T* __restr
             xzero = true;
         } else {
             const double xn = psqrt(xn2);
-            eps = (T)(FdEps<T>::sqrt_eps * slots[LV_UTOT] * frcp(xn));
-            sc = (T)(adt * xn * (FdEps<T>::inv_sqrt_eps * slots[LV_IUTOT]));
+            eps = (T)(FdEps<T>::sqrt_eps * s_utot * frcp(xn));
+            sc = (T)(adt * xn * (FdEps<T>::inv_sqrt_eps * s_iutot));
         }
     }
 
@@ -269,13 +302,12 @@ fv_tile_kernel(FvArgs<T> Aa, const MemberArgs* __restrict__ mt, const T* __restr
                     sw[c][h / HX][h % HX] = v;
                 }
         }
-        static_assert(NTH >= 6 * TZ + 10 * (TZ + 1), "background staging");
         if (tid < 6 * TZ) {
-            const int r = tid / 6, k = tid - 6 * r, J = J0 + r;
-            if (J < nzl) sBc[r][k] = k < 4 ? A.bgc[4 * J + k] : A.pc[2 * J + k - 4];
+            const int r = tid / 6, k = tid - 6 * r;
+            if (J0 + r < nzl) sBc[r][k] = bg_v;
         } else if (tid < 6 * TZ + 10 * (TZ + 1)) {
-            const int t2 = tid - 6 * TZ, r = t2 / 10, k = t2 - 10 * r, J = J0 + r;
-            if (J <= nzl) sBf[r][k] = k < 4 ? A.bgf[4 * J + k] : k < 6 ? A.pf[2 * J + k - 4] : A.dbgf[4 * J + k - 6];
+            const int t2 = tid - 6 * TZ, r = t2 / 10, k = t2 - 10 * r;
+            if (J0 + r <= nzl) sBf[r][k] = bg_v;
         }
         __syncthreads();
         // ---- one net flux per face: x-faces in thread order, z-faces in reverse
@@ -342,10 +374,10 @@ fv_tile_kernel(FvArgs<T> Aa, const MemberArgs* __restrict__ mt, const T* __restr
         } else if constexpr (MODE == FVM_STAGE) {
             double nrm = 0.0;
             if (valid) {
-                const T s = (T)(alpha_j * slots[LV_DTAU]);
+                const T s = (T)(alpha_j * s_dtau);
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    const T v = own_x0[c] + s * (own_b[c] - Ax[c]);
+                    const T v = (x0 == xp ? own_x[c] : own_x0[c]) + s * (own_b[c] - Ax[c]);
                     out[c * nc + q] = v;
                     nrm += (double)v * (double)v;
                 }
@@ -354,17 +386,17 @@ fv_tile_kernel(FvArgs<T> Aa, const MemberArgs* __restrict__ mt, const T* __restr
         } else if constexpr (MODE == FVM_STAGE_PC) {
             double nrm = 0.0;
             if (valid) {
-                const T s = (T)(alpha_j * slots[LV_DTAU]);
+                const T s = (T)(alpha_j * s_dtau);
                 const long nxf = 2L * nxl, ncf = 4 * nc;
                 const long q00 = (long)(2 * J) * nxf + 2 * I, q10 = q00 + nxf;
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    const T v = own_x0[c] + s * (own_b[c] - Ax[c]);
+                    const T v = (x0 == xp ? own_x[c] : own_x0[c]) + s * (own_b[c] - Ax[c]);
                     T* xf = out2 + c * ncf;
                     T f00 = -v, f01 = -v, f10 = -v, f11 = -v;
                     if (!fzero) {
-                        f00 = xf[q00] - v; f01 = xf[q00 + 1] - v;
-                        f10 = xf[q10] - v; f11 = xf[q10 + 1] - v;
+                        f00 = own_xf[c][0] - v; f01 = own_xf[c][1] - v;
+                        f10 = own_xf[c][2] - v; f11 = own_xf[c][3] - v;
                     }
                     xf[q00] = f00; xf[q00 + 1] = f01;
                     xf[q10] = f10; xf[q10 + 1] = f11;
@@ -383,7 +415,7 @@ fv_tile_kernel(FvArgs<T> Aa, const MemberArgs* __restrict__ mt, const T* __restr
             if (valid && !(ti & 1) && !(tj & 1)) {
                 const int nxc = nxl / 2;
                 const long ncc = (long)nxc * (nzl / 2), qc = (long)(J / 2) * nxc + I / 2;
-                const T s1 = out2 ? (T)(alpha_j * slots2[LV_DTAU]) : T(0);
+                const T s1 = out2 ? (T)(alpha_j * s_dtau) : T(0);
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     const T r = ((sw[c][tj][ti] + sw[c][tj][ti + 1]) + (sw[c][tj + 1][ti] + sw[c][tj + 1][ti + 1])) * T(0.25);

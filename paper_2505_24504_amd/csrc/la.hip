@@ -155,16 +155,33 @@ multidot_kernel(const double* __restrict__ w, const double* __restrict__ V, long
     double acc[MAXV];
 #pragma unroll
     for (int q = 0; q < MAXV; ++q) acc[q] = 0.0;
+    if (base - threadIdx.x + LA_NTH * LA_EL <= n && v0 + MAXV <= nv) {
+        // a whole block of basis vectors: every load issued before the first product
+        // (the same products in the same order as below)
+        double wv[LA_EL], vv[LA_EL][MAXV];
 #pragma unroll
-    for (int k = 0; k < LA_EL; ++k) {
-        const long i = base + (long)k * LA_NTH;
-        if (i < n) {
-            const double wi = w[i];
+        for (int k = 0; k < LA_EL; ++k) {
+            const long i = base + (long)k * LA_NTH;
+            wv[k] = w[i];
 #pragma unroll
-            for (int q = 0; q < MAXV; ++q) {
-                const int v = v0 + q;
-                if (v < nv) acc[q] += wi * V[(long)v * ld + i];
-                else if (v == nv && self) acc[q] += wi * wi;
+            for (int q = 0; q < MAXV; ++q) vv[k][q] = V[(long)(v0 + q) * ld + i];
+        }
+#pragma unroll
+        for (int k = 0; k < LA_EL; ++k)
+#pragma unroll
+            for (int q = 0; q < MAXV; ++q) acc[q] += wv[k] * vv[k][q];
+    } else {
+#pragma unroll
+        for (int k = 0; k < LA_EL; ++k) {
+            const long i = base + (long)k * LA_NTH;
+            if (i < n) {
+                const double wi = w[i];
+#pragma unroll
+                for (int q = 0; q < MAXV; ++q) {
+                    const int v = v0 + q;
+                    if (v < nv) acc[q] += wi * V[(long)v * ld + i];
+                    else if (v == nv && self) acc[q] += wi * wi;
+                }
             }
         }
     }
@@ -216,7 +233,25 @@ update_kernel(double* __restrict__ w, const double* __restrict__ V, long ld, int
         const long i = base + (long)k * LA_NTH;
         acc[k] = i < n ? w[i] : 0.0;
     }
-    for (int v = 0; v < nv; ++v) {
+    int v = 0;
+    if (base - threadIdx.x + LA_NTH * LA_EL <= n) {
+        // whole block: four basis vectors at a time, every load issued before the
+        // products (the same products in the same order as below)
+        for (; v + 4 <= nv; v += 4) {
+            double vv[4][LA_EL];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int k = 0; k < LA_EL; ++k) vv[r][k] = V[(long)(v + r) * ld + base + (long)k * LA_NTH];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const double hv = h[v + r];
+#pragma unroll
+                for (int k = 0; k < LA_EL; ++k) acc[k] -= hv * vv[r][k];
+            }
+        }
+    }
+    for (; v < nv; ++v) {
         const double hv = h[v];
         const double* Vi = V + (long)v * ld;
 #pragma unroll

@@ -58,27 +58,39 @@ transfer_T_kernel(DgArgs Aa, const MemberArgs* __restrict__ mt, int mass_fix, co
     const bool valid = act && e < A.ne;
     const long N = A.ne * NP;
     const long nc = N;   // number of finest FV cells
-    const double s = snrm2 ? 1.0 / sqrt(snrm2[0]) : 1.0;
+    const int i = nd % N1, j = nd / N1;   // this thread: x-index i, z-index j
+    // every global load first (the node's four components, ||U||^2, the pseudo time
+    // step and this thread's rows of V), so that their latencies overlap
+    double uv[4] = {0.0, 0.0, 0.0, 0.0};
+    if (valid)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) uv[c] = U[c * N + e * NP + nd];
+    const double sn2 = snrm2 ? snrm2[0] : 1.0;
+    const double dtau = x1 ? slots[LV_DTAU] : 0.0;
+    double Vi[N1], Vj[N1];
+#pragma unroll
+    for (int a = 0; a < N1; ++a) {
+        Vi[a] = A.R.V[i][a];
+        Vj[a] = A.R.V[j][a];
+    }
+    const double s = snrm2 ? 1.0 / sqrt(sn2) : 1.0;
     if (act)
+#pragma unroll
         for (int c = 0; c < 4; ++c) {
-            double v = 0.0;
-            if (valid) {
-                v = U[c * N + e * NP + nd];
-                if (snrm2) {
-                    v = v * s;
-                    Us[c * N + e * NP + nd] = v;
-                }
+            double v = uv[c];
+            if (valid && snrm2) {
+                v = v * s;
+                Us[c * N + e * NP + nd] = v;
             }
             sU[le][c][nd] = v;
         }
     __syncthreads();
-    const int i = nd % N1, j = nd / N1;   // this thread: x-index i, z-index j
     // first contraction along x: h_{b,i} = sum_a V_ia u_ab (stored at node slot b*N1+i)
     if (act)
         for (int c = 0; c < 4; ++c) {
             double s2 = 0.0;
 #pragma unroll
-            for (int a = 0; a < N1; ++a) s2 += A.R.V[i][a] * sU[le][c][j * N1 + a];
+            for (int a = 0; a < N1; ++a) s2 += Vi[a] * sU[le][c][j * N1 + a];
             sH[le][c][j * N1 + i] = s2;
         }
     __syncthreads();
@@ -87,7 +99,7 @@ transfer_T_kernel(DgArgs Aa, const MemberArgs* __restrict__ mt, int mass_fix, co
         for (int c = 0; c < 4; ++c) {
             double s2 = 0.0;
 #pragma unroll
-            for (int bb = 0; bb < N1; ++bb) s2 += A.R.V[j][bb] * sH[le][c][bb * N1 + i];
+            for (int bb = 0; bb < N1; ++bb) s2 += Vj[bb] * sH[le][c][bb * N1 + i];
             tv[c] = s2;
         }
     __syncthreads();
@@ -98,7 +110,7 @@ transfer_T_kernel(DgArgs Aa, const MemberArgs* __restrict__ mt, int mass_fix, co
     if (valid) {
         const int ez = (int)(e / A.nx), ex = (int)(e - (long)ez * A.nx);
         const long o = subcell_index(ex, ez, i, j, N1, nxf);
-        const T s1 = x1 ? (T)(alpha * slots[LV_DTAU]) : T(0);
+        const T s1 = x1 ? (T)(alpha * dtau) : T(0);
         for (int c = 0; c < 4; ++c) {
             double shift = 0.0;
             if (mass_fix) {
@@ -149,17 +161,29 @@ transfer_Tinv_kernel(DgArgs Aa, const MemberArgs* __restrict__ mt, int mass_fix,
     const long N = A.ne * NP;
     const int ez = valid ? (int)(e / A.nx) : 0, ex = valid ? (int)(e - (long)ez * A.nx) : 0;
     const int i = nd % N1, j = nd / N1;
-    if (act)
-        for (int c = 0; c < 4; ++c)
-            sT[le][c][nd] = valid ? (double)u[c * N + subcell_index(ex, ez, i, j, N1, nxf)] : 0.0;
-    __syncthreads();
+    // every global load first: the subcell's four components and this thread's rows
+    // of V^-1
+    T tv[4] = {T(0), T(0), T(0), T(0)};
+    if (valid)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) tv[c] = u[c * N + subcell_index(ex, ez, i, j, N1, nxf)];
     // thread slot nd = b*N1 + a computes DG node (a, b)
     const int a = i, b = j;
+    double Va[N1], Vb[N1];
+#pragma unroll
+    for (int q = 0; q < N1; ++q) {
+        Va[q] = A.R.Vinv[a][q];
+        Vb[q] = A.R.Vinv[b][q];
+    }
+    if (act)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sT[le][c][nd] = (double)tv[c];
+    __syncthreads();
     if (act)
         for (int c = 0; c < 4; ++c) {
             double s = 0.0;   // h_{jj,a} = sum_i Vinv_ai t_{i,jj}, stored at slot jj*N1+a
 #pragma unroll
-            for (int ii = 0; ii < N1; ++ii) s += A.R.Vinv[a][ii] * sT[le][c][b * N1 + ii];
+            for (int ii = 0; ii < N1; ++ii) s += Va[ii] * sT[le][c][b * N1 + ii];
             sH[le][c][b * N1 + a] = s;
         }
     __syncthreads();
@@ -168,7 +192,7 @@ transfer_Tinv_kernel(DgArgs Aa, const MemberArgs* __restrict__ mt, int mass_fix,
         for (int c = 0; c < 4; ++c) {
             double s = 0.0;
 #pragma unroll
-            for (int jj = 0; jj < N1; ++jj) s += A.R.Vinv[b][jj] * sH[le][c][jj * N1 + a];
+            for (int jj = 0; jj < N1; ++jj) s += Vb[jj] * sH[le][c][jj * N1 + a];
             double shift = 0.0;
             if (mass_fix) {
                 double mean = 0.0, quad = 0.0;
