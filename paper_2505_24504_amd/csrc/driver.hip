@@ -678,6 +678,11 @@ template <typename T> struct Mg {
     jfmg_problem* p;
     MgState s;
     double alpha[4];
+    // set by mg_apply_t: the last stage of the cycle on the finest level applies the
+    // FV -> DG transfer itself (FvLaunch::stage_tinv), ||z||^2 into tinv_red.out
+    const TinvOut* tinv = nullptr;
+    Red tinv_red{};
+    bool tinv_done = false;
 
     void init()
     {
@@ -700,7 +705,9 @@ template <typename T> struct Mg {
     // nu sweeps on level l.  With pc >= 0 (the next finer level) the last stage of the
     // last sweep does not store its result v but applies the coarse-grid correction
     // x_pc -= P v itself (FvLaunch::stage_prolong); returns whether it did.
-    bool smooth(int l, int nu, int pc = -1)
+    // With post set on the finest level (the cycle's final sweeps) the very last stage
+    // may apply the FV -> DG transfer instead (tinv).
+    bool smooth(int l, int nu, int pc = -1, bool post = false)
     {
         const FvArgs<T> A = fv_args<T>(p, l);
         Level& L = p->lev[l];
@@ -736,6 +743,22 @@ template <typename T> struct Mg {
                     s.xzero[pc] = false;
                     fused = true;
                     prev = out;   // v itself is not needed any more
+                    continue;
+                }
+                if (tinv && post && l == 0 && pc < 0 && sw == nu - 1 && j == S - 1 && !zero) {
+                    int nb;
+                    {   // reads u, F0, x^(j-1), x^(0) (when not x^(j-1)), b; writes the DG vector z
+                        ProfScope ps(p, fv_wide_tile(L.tile) ? JFMG_K_FV_STAGE : JFMG_K_FV_STAGE_SMALL,
+                                     (x0 && prev != i0 ? 5 : 4) * vb + 4.0 * L.nc * 8.0);
+                        nb = FvLaunch<T>::stage_tinv(A, (const T*)L.u, (const T*)L.F0, (const T*)L.buf[prev], x0,
+                                                     (const T*)L.b, *tinv, fvpart(p, l, prev), p->xcnt[l][prev],
+                                                     p->scal + S_LEV + 4 * l, alpha[j], p->adt, tinv_red, p->st,
+                                                     p->mb);
+                    }
+                    launch_finalize(tinv_red.partials, nb, 1, tinv_red.out, p->st, Gate{}, p->mb);
+                    p->mv_count[l]++;
+                    tinv_done = true;
+                    prev = out;
                     continue;
                 }
                 // algorithmic bytes: reads u, F0, x^(j-1), x^(0), b, writes x^(j) (x^(0) not when it is 0
@@ -796,7 +819,7 @@ template <typename T> struct Mg {
                 s.xzero[l] = false;
             }
         }
-        return smooth(l, fine ? k.d : k.f, pc);
+        return smooth(l, fine ? k.d : k.f, pc, fine);
     }
 
     // x = MG(0, b) on the finest level; b must be in lev[0].b; result pointer returned
@@ -805,6 +828,7 @@ template <typename T> struct Mg {
         s.xi[0] = 0;
         s.xzero[0] = true;
         cycle(0);
+        if (tinv_done) return nullptr;   // z has been written by the last stage
         Level& L = p->lev[0];
         if (s.xzero[0]) launch_zero(L.buf[s.xi[0]], sizeof(T) * 4 * L.nc, p->st, p->mb);
         return (T*)L.buf[s.xi[0]];
@@ -827,7 +851,18 @@ template <typename T> jfmg_status mg_apply_t(jfmg_problem* p, double* r, double*
                                             rnrm2 ? r : nullptr, p->mb, z0);
         if (z0.x1) mg.s.pre[0] = nb;
     }
+    TinvOut tv;
+    if (fv_tile_fits_elements(L.tile, p->n1)) {   // the last finest-level stage transfers back itself
+        tv.z = z;
+        tv.n1 = p->n1;
+        tv.mass_fix = mass_fix_of(p);
+        std::memcpy(tv.Vinv, p->A.R.Vinv, sizeof(tv.Vinv));
+        std::memcpy(tv.wnc, p->A.R.wnc, sizeof(tv.wnc));
+        mg.tinv = &tv;
+        mg.tinv_red = red_at(p, zslot);
+    }
     T* x = mg.run();
+    if (!x) return check_launch(p);
     ProfScope ps(p, JFMG_K_TRANSFER_TINV, (double)p->N * (8 + sizeof(T)));
     launch_transfer_Tinv<T>(p->cfg.k, p->A, mass_fix_of(p), x, z, L.nx, red_at(p, zslot), p->st, p->mb);
     return check_launch(p);

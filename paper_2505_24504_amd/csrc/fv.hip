@@ -22,7 +22,7 @@ namespace jfmg {
 
 constexpr int FV_TX = 64, FV_TZ = 4, FV_NTH = FV_TX * FV_TZ;
 
-enum { FVM_LIN = 0, FVM_STAGE = 1, FVM_MATVEC = 2, FVM_DEFECT = 3, FVM_STAGE_PC = 4 };
+enum { FVM_LIN = 0, FVM_STAGE = 1, FVM_MATVEC = 2, FVM_DEFECT = 3, FVM_STAGE_PC = 4, FVM_STAGE_TINV = 5 };
 
 // Tile shapes of the FV operator kernels (jfmg_tile; chosen per level, by
 // jfmg_autotune or by default):
@@ -146,13 +146,18 @@ __device__ __forceinline__ void fv_face(const FvArgs<T>& A, const T (&sw)[4][HZ]
 //   STAGE_PC the STAGE result v is not stored: it corrects the next finer level's x in
 //           out2 by injection, x_f -= P v (x_f = -P v when fzero is set, x_f being zero), with the
 //           ||x_f||^2 block partials into red (the last smoother stage of a coarse level)
+//   STAGE_TINV (finest level, tiles of whole DG elements) the STAGE result v is not stored:
+//           the tile's elements are transferred back to the DG space, tv.z = T^-1 v with the
+//           mass fix when tv.mass_fix is set (the arithmetic of transfer_Tinv_kernel), with the
+//           ||z||^2 block partials into red (the last smoother stage of the cycle)
 template <typename T, int TX, int TZ, int NTH, int WPE, bool LATE, bool ZREV, bool MB, int MODE, bool RG>
 __global__ void __launch_bounds__(NTH, WPE)
 fv_tile_kernel(FvArgs<T> Aa, const MemberArgs* __restrict__ mt, const T* __restrict__ u, const T* __restrict__ F0,
                const T* __restrict__ xp,
                const T* __restrict__ x0, const T* __restrict__ b, T* __restrict__ out, T* __restrict__ out2,
                const double* __restrict__ xpart, int xcount, double* __restrict__ slots,
-               const double* __restrict__ slots2, double alpha_j, double adt, int fzero, Red red, long ms)
+               const double* __restrict__ slots2, double alpha_j, double adt, int fzero, Red red, long ms,
+               TinvOut tv)
 {
     const FvArgs<T>& A = fv_of<T, RG>(Aa, mt);
     if constexpr (MB) {   // member blockIdx.z of a lock-step batch
@@ -168,10 +173,13 @@ fv_tile_kernel(FvArgs<T> Aa, const MemberArgs* __restrict__ mt, const T* __restr
         slots = mbr(slots, ms);
         red = mbr(red, ms);
     }
+    double* const zout = MB ? mbr(tv.z, ms) : tv.z;   // STAGE_TINV output (tv stays in the arguments)
     constexpr int NCELL = TX * TZ, HX = TX + 2, HZ = TZ + 2;
     constexpr int NH = HX * HZ, HITEMS = (NH + NTH - 1) / NTH;
     constexpr int NFX = TZ * (TX + 1), NFZ = (TZ + 1) * TX;
     constexpr bool PERT = (MODE != FVM_LIN);
+    constexpr bool STG = (MODE == FVM_STAGE || MODE == FVM_STAGE_PC || MODE == FVM_STAGE_TINV);
+    constexpr bool TI = (MODE == FVM_STAGE_TINV);
     static_assert(NTH >= NCELL && NTH % 64 == 0, "tile shape");
     __shared__ T sw[4][HZ][HX];
     __shared__ T sFx[TZ][TX + 1][4];
@@ -180,6 +188,9 @@ fv_tile_kernel(FvArgs<T> Aa, const MemberArgs* __restrict__ mt, const T* __restr
     // [Ubar(4), p, 1/(rho theta), dUbar/dz(4)]
     __shared__ T sBc[TZ][6];
     __shared__ T sBf[TZ + 1][10];
+    // STAGE_TINV: V^-1, the Newton-Cotes weights and the first contraction of T^-1
+    __shared__ double sVi[TI ? MAXN1 : 1][MAXN1], sWn[TI ? MAXN1 : 1];
+    __shared__ double sHt[TI ? 4 : 1][TI ? TZ : 1][TI ? TX : 1];
     const int tid = threadIdx.x;
     const long nc = A.nc;
     const int nxl = A.nxl, nzl = A.nzl;
@@ -191,7 +202,7 @@ fv_tile_kernel(FvArgs<T> Aa, const MemberArgs* __restrict__ mt, const T* __restr
             if constexpr (MODE == FVM_LIN) {
                 red.partials[blockIdx.x] = 0.0;
                 red.partials[gridDim.x + blockIdx.x] = 0.0;
-            } else if constexpr (MODE == FVM_STAGE || MODE == FVM_STAGE_PC) {
+            } else if constexpr (STG) {
                 red.partials[blockIdx.x] = 0.0;
             } else if constexpr (MODE == FVM_DEFECT) {
                 if (out2) red.partials[blockIdx.x] = 0.0;
@@ -216,7 +227,11 @@ fv_tile_kernel(FvArgs<T> Aa, const MemberArgs* __restrict__ mt, const T* __restr
         s_utot = slots[LV_UTOT];
         s_iutot = slots[LV_IUTOT];
     }
-    if constexpr (MODE == FVM_STAGE || MODE == FVM_STAGE_PC) s_dtau = slots[LV_DTAU];
+    if constexpr (STG) s_dtau = slots[LV_DTAU];
+    if constexpr (TI) {
+        if (tid < MAXN1 * MAXN1) sVi[tid / MAXN1][tid % MAXN1] = tv.Vinv[tid / MAXN1][tid % MAXN1];
+        else if (tid < MAXN1 * MAXN1 + MAXN1) sWn[tid - MAXN1 * MAXN1] = tv.wnc[tid - MAXN1 * MAXN1];
+    }
     if constexpr (MODE == FVM_DEFECT) s_dtau = out2 ? slots2[LV_DTAU] : 0.0;
     static_assert(NTH >= 6 * TZ + 10 * (TZ + 1), "background staging");
     T bg_v = T(0);   // this thread's entry of sBc / sBf
@@ -248,11 +263,11 @@ fv_tile_kernel(FvArgs<T> Aa, const MemberArgs* __restrict__ mt, const T* __restr
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 if constexpr (PERT) { own_x[c] = xp[c * nc + q]; own_f0[c] = F0[c * nc + q]; }
-                if constexpr (MODE == FVM_STAGE || MODE == FVM_STAGE_PC || MODE == FVM_DEFECT)
+                if constexpr (STG || MODE == FVM_DEFECT)
                     own_b[c] = b[c * nc + q];
                 // the first stage of a sweep has x^(0) = x^(j-1): no second load (the copy
                 // is taken where x^(0) is used, so that no load waits for another)
-                if constexpr (MODE == FVM_STAGE || MODE == FVM_STAGE_PC)
+                if constexpr (STG)
                     if (x0 && x0 != xp) own_x0[c] = x0[c * nc + q];
             }
         }
@@ -404,6 +419,77 @@ fv_tile_kernel(FvArgs<T> Aa, const MemberArgs* __restrict__ mt, const T* __restr
                            ((double)f10 * (double)f10 + (double)f11 * (double)f11);
                 }
             }
+            put_partial<NTH>(red, nrm);
+        } else if constexpr (MODE == FVM_STAGE_TINV) {
+            T v[4] = {T(0), T(0), T(0), T(0)};
+            if (valid) {
+                const T s = (T)(alpha_j * s_dtau);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) v[c] = (x0 == xp ? own_x[c] : own_x0[c]) + s * (own_b[c] - Ax[c]);
+            }
+            __syncthreads();   // the staged states are read no more: the tile of v replaces them
+            if (valid)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) sw[c][tj][ti] = v[c];
+            __syncthreads();
+            // T^-1 with k + 1 = N1 known at compile time (tiles of whole elements: N1 = 2 or 4)
+            double nrm = 0.0;
+            auto tinv = [&](auto n1c) {
+                constexpr int N1 = decltype(n1c)::value, NP = N1 * N1;
+                // first contraction, one thread per subcell (a, bb) of its element:
+                // h_{bb,a} = sum_i Vinv_ai t_{i,bb}
+                if (valid) {
+                    const int a = ti % N1, ea = ti - a;
+                    double va[N1];
+#pragma unroll
+                    for (int ii = 0; ii < N1; ++ii) va[ii] = sVi[a][ii];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int ii = 0; ii < N1; ++ii) s += va[ii] * (double)sw[c][tj][ea + ii];
+                        sHt[c][tj][ti] = s;
+                    }
+                }
+                __syncthreads();
+                // second contraction and mass fix, one thread per DG node in the order of the
+                // DG vector (the tile's elements of one element row are consecutive there)
+                constexpr int ROW = TX * N1;   // nodes of one element row of the tile
+                if (tid < NCELL) {
+                    const int er = tid / ROW, rem = tid - er * ROW, el = rem / NP, nd = rem - el * NP;
+                    const int a = nd % N1, bb = nd / N1, ea = el * N1, eb = er * N1;
+                    if (I0 + ea < nxl && J0 + eb < nzl) {
+                        const long e = (long)((J0 + eb) / N1) * (nxl / N1) + (I0 + ea) / N1;
+                        double vb[N1];
+#pragma unroll
+                        for (int jj = 0; jj < N1; ++jj) vb[jj] = sVi[bb][jj];
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            double s = 0.0;
+#pragma unroll
+                            for (int jj = 0; jj < N1; ++jj) s += vb[jj] * sHt[c][eb + jj][ea + a];
+                            double shift = 0.0;
+                            if (tv.mass_fix) {
+                                double mean = 0.0, quad = 0.0;
+#pragma unroll
+                                for (int jj = 0; jj < N1; ++jj)
+#pragma unroll
+                                    for (int ii = 0; ii < N1; ++ii) {
+                                        const double w = sw[c][eb + jj][ea + ii];
+                                        mean += w;
+                                        quad += sWn[ii] * sWn[jj] * w;
+                                    }
+                                shift = quad - mean / NP;
+                            }
+                            const double z = s - shift;
+                            zout[c * nc + e * NP + nd] = z;   // the DG vector has nc nodes per component
+                            nrm += z * z;
+                        }
+                    }
+                }
+            };
+            if (tv.n1 == 4) tinv(std::integral_constant<int, 4>{});
+            else tinv(std::integral_constant<int, 2>{});
             put_partial<NTH>(red, nrm);
         } else {   // DEFECT: reuse the state tile for d = g'x - b, then agglomerate 2x2
             __syncthreads();
@@ -601,46 +687,48 @@ static inline dim3 tile_grid_1d(int nx, int nz, int members = 1)
 template <typename T, int TX, int TZ, int NTH, int WPE, bool LATE, bool ZREV, int MODE>
 static int tile_launch_shape(const FvArgs<T>& A, const T* u, const T* F0, const T* xp, const T* x0, const T* b,
                              T* out, T* out2, const double* xpart, int xcount, double* slots, const double* slots2,
-                             double alpha_j, double adt, int fzero, Red red, hipStream_t st, const Mb& mb)
+                             double alpha_j, double adt, int fzero, Red red, hipStream_t st, const Mb& mb,
+                             const TinvOut& tv)
 {
     const unsigned nt = (unsigned)((A.nxl + TX - 1) / TX) * (unsigned)((A.nzl + TZ - 1) / TZ);
     const dim3 g(nt, 1, (unsigned)mb.n);
     if (mb.tab)
         timed_launch(fv_tile_kernel<T, TX, TZ, NTH, WPE, LATE, ZREV, true, MODE, true>, g, dim3(NTH), st, A, mb.tab, u,
-                     F0, xp, x0, b, out, out2, xpart, xcount, slots, slots2, alpha_j, adt, fzero, red, mb.ms);
+                     F0, xp, x0, b, out, out2, xpart, xcount, slots, slots2, alpha_j, adt, fzero, red, mb.ms, tv);
     else if (mb.n > 1)
         timed_launch(fv_tile_kernel<T, TX, TZ, NTH, WPE, LATE, ZREV, true, MODE, false>, g, dim3(NTH), st, A, mb.tab,
-                     u, F0, xp, x0, b, out, out2, xpart, xcount, slots, slots2, alpha_j, adt, fzero, red, mb.ms);
+                     u, F0, xp, x0, b, out, out2, xpart, xcount, slots, slots2, alpha_j, adt, fzero, red, mb.ms, tv);
     else
         timed_launch(fv_tile_kernel<T, TX, TZ, NTH, WPE, LATE, ZREV, false, MODE, false>, g, dim3(NTH), st, A, mb.tab,
-                     u, F0, xp, x0, b, out, out2, xpart, xcount, slots, slots2, alpha_j, adt, fzero, red, 0L);
+                     u, F0, xp, x0, b, out, out2, xpart, xcount, slots, slots2, alpha_j, adt, fzero, red, 0L, tv);
     return (int)nt;
 }
 
 template <typename T, int MODE>
 static int tile_launch(const FvArgs<T>& A, const T* u, const T* F0, const T* xp, const T* x0, const T* b, T* out,
                        const double* xpart, int xcount, double* slots, double alpha_j, double adt, int fzero,
-                       Red red, hipStream_t st, const Mb& mb, T* out2 = nullptr, const double* slots2 = nullptr)
+                       Red red, hipStream_t st, const Mb& mb, T* out2 = nullptr, const double* slots2 = nullptr,
+                       const TinvOut& tv = TinvOut{})
 {
     switch (A.tile) {
     case JFMG_TILE_64x8:
         return tile_launch_shape<T, 64, 8, 512, 4, true, true, MODE>(A, u, F0, xp, x0, b, out, out2, xpart, xcount,
-                                                                       slots, slots2, alpha_j, adt, fzero, red, st, mb);
+                                                                       slots, slots2, alpha_j, adt, fzero, red, st, mb, tv);
     case JFMG_TILE_16x4:
         return tile_launch_shape<T, 16, 4, 256, 1, false, true, MODE>(A, u, F0, xp, x0, b, out, out2, xpart, xcount,
-                                                                        slots, slots2, alpha_j, adt, fzero, red, st, mb);
+                                                                        slots, slots2, alpha_j, adt, fzero, red, st, mb, tv);
     case JFMG_TILE_8x4:
         return tile_launch_shape<T, 8, 4, 128, 1, false, true, MODE>(A, u, F0, xp, x0, b, out, out2, xpart, xcount,
-                                                                       slots, slots2, alpha_j, adt, fzero, red, st, mb);
+                                                                       slots, slots2, alpha_j, adt, fzero, red, st, mb, tv);
     case JFMG_TILE_32x4:
         return tile_launch_shape<T, 32, 4, 256, 2, false, true, MODE>(A, u, F0, xp, x0, b, out, out2, xpart, xcount,
-                                                                        slots, slots2, alpha_j, adt, fzero, red, st, mb);
+                                                                        slots, slots2, alpha_j, adt, fzero, red, st, mb, tv);
     case JFMG_TILE_64x4_512:
         return tile_launch_shape<T, 64, 4, 512, 4, true, true, MODE>(A, u, F0, xp, x0, b, out, out2, xpart, xcount,
-                                                                       slots, slots2, alpha_j, adt, fzero, red, st, mb);
+                                                                       slots, slots2, alpha_j, adt, fzero, red, st, mb, tv);
     default:
         return tile_launch_shape<T, 64, 4, 256, 4, true, true, MODE>(A, u, F0, xp, x0, b, out, out2, xpart, xcount,
-                                                                       slots, slots2, alpha_j, adt, fzero, red, st, mb);
+                                                                       slots, slots2, alpha_j, adt, fzero, red, st, mb, tv);
     }
 }
 
@@ -680,6 +768,14 @@ int FvLaunch<T>::stage_prolong(const FvArgs<T>& A, const T* u, const T* F0, cons
 {
     return tile_launch<T, FVM_STAGE_PC>(A, u, F0, xp, x0, b, nullptr, xpart, xcount, const_cast<double*>(slots),
                                         alpha_j, adt, fine_zero ? 1 : 0, red, st, mb, xf);
+}
+template <typename T>
+int FvLaunch<T>::stage_tinv(const FvArgs<T>& A, const T* u, const T* F0, const T* xp, const T* x0, const T* b,
+                            const TinvOut& tv, const double* xpart, int xcount, const double* slots, double alpha_j,
+                            double adt, Red red, hipStream_t st, const Mb& mb)
+{
+    return tile_launch<T, FVM_STAGE_TINV>(A, u, F0, xp, x0, b, nullptr, xpart, xcount, const_cast<double*>(slots),
+                                          alpha_j, adt, 0, red, st, mb, nullptr, nullptr, tv);
 }
 template <typename T>
 void FvLaunch<T>::matvec(const FvArgs<T>& A, const T* u, const T* F0, const T* x, T* out, const double* xpart,
@@ -738,6 +834,12 @@ int fv_default_tile(long nxl)
            : nxl >= 256 ? JFMG_TILE_16x4 : JFMG_TILE_8x4;
 }
 bool fv_wide_tile(int tile) { return tile == JFMG_TILE_64x4 || tile == JFMG_TILE_64x8 || tile == JFMG_TILE_64x4_512; }
+bool fv_tile_fits_elements(int tile, int n1)
+{
+    const int tx = tile == JFMG_TILE_16x4 ? 16 : tile == JFMG_TILE_8x4 ? 8 : tile == JFMG_TILE_32x4 ? 32 : 64;
+    const int tz = tile == JFMG_TILE_64x8 ? 8 : 4;
+    return (n1 == 2 || n1 == 4) && tx % n1 == 0 && tz % n1 == 0;   // the stage kernel's two N1
+}
 
 long fv_partial_blocks(long nxl, long nzl)
 {

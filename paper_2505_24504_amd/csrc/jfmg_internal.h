@@ -251,6 +251,18 @@ bool fv_wide_tile(int tile);
 // FV partial-sum blocks needed by the largest launch on a level of nxl x nzl cells
 long fv_partial_blocks(long nxl, long nzl);
 
+// The FV -> DG transfer applied by the last smoother stage of a cycle on the finest
+// level (FvLaunch::stage_tinv): output vector, k + 1, the mass-fix flag and the tables
+// of transfer_Tinv_kernel.
+struct TinvOut {
+    double* z = nullptr;
+    int n1 = 0, mass_fix = 0;
+    double Vinv[MAXN1][MAXN1] = {};
+    double wnc[MAXN1] = {};
+};
+// whether stage_tinv serves this tile shape and k + 1 (tiles of whole elements, k + 1 = 2 or 4)
+bool fv_tile_fits_elements(int tile, int n1);
+
 template <typename T> struct FvLaunch {
     // F0 = f~(u), then the level slots (||u + Ubar||, max |v| + c, dtau) via red.partials
     static void lin_level(const FvArgs<T>& A, const T* u, T* F0, Red red, double* slots, double adt, double cfl,
@@ -266,6 +278,12 @@ template <typename T> struct FvLaunch {
     static int stage_prolong(const FvArgs<T>& A, const T* u, const T* F0, const T* xp, const T* x0, const T* b,
                              T* xf, bool fine_zero, const double* xpart, int xcount, const double* slots,
                              double alpha_j, double adt, Red red, hipStream_t st, const Mb& mb = Mb{});
+    // the same stage on the finest level without storing its result v: z = T^-1 v into
+    // tv.z (tiles of whole elements), with the ||z||^2 partials into red.partials;
+    // returns their count
+    static int stage_tinv(const FvArgs<T>& A, const T* u, const T* F0, const T* xp, const T* x0, const T* b,
+                          const TinvOut& tv, const double* xpart, int xcount, const double* slots, double alpha_j,
+                          double adt, Red red, hipStream_t st, const Mb& mb = Mb{});
     static void matvec(const FvArgs<T>& A, const T* u, const T* F0, const T* x, T* out, const double* xpart,
                        int xcount, const double* slots, double adt, hipStream_t st, const Mb& mb = Mb{});
     // coarse defect rc = R(g'x - b) (x = 0: R(-b)); with z0.x1 the first RK stage of the
