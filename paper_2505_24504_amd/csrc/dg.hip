@@ -158,7 +158,7 @@ template <int N1, bool NS, int MODE, bool RG>
 __global__ void __launch_bounds__(DgShape<N1>::NTH, N1 == 4 ? 4 : 3)
 dg_kernel(DgArgs Aa, const MemberArgs* __restrict__ mt, const double* __restrict__ U, const double* __restrict__ Y,
           const double* __restrict__ Ubar, double* __restrict__ out, const double* __restrict__ yn2p,
-          const double* __restrict__ ut2p, int eps_mode, double adt, Red red, long ms, ExStage rk)
+          const double* __restrict__ ut2p, int eps_mode, double adt, Red red, long ms, ExStage rk, int ycount)
 {
     const DgArgs& A = dg_of<RG>(Aa, mt);
     double* lin0 = A.lin0;
@@ -207,7 +207,22 @@ dg_kernel(DgArgs Aa, const MemberArgs* __restrict__ mt, const double* __restrict
     }
     double eps = 0.0;
     if constexpr (MODE == 3) {
-        const double yn2 = yn2p[0];
+        // ||y||^2: yn2p[0], or with ycount > 0 the sum of the ycount block partials at yn2p
+        // (fixed order; sFx serves as scratch until phase B writes it)
+        double yn2;
+        if (ycount > 0) {
+            double a = 0.0;
+            for (int i = t; i < ycount; i += NTH) a += yn2p[i];
+            a = wave_sum(a);
+            double* scr = &sFx[0][0][0];
+            if ((t & 63) == 0) scr[t >> 6] = a;
+            __syncthreads();
+            yn2 = scr[0];
+#pragma unroll
+            for (int w = 1; w < NTH / 64; ++w) yn2 += scr[w];
+        } else {
+            yn2 = yn2p[0];
+        }
         if (!(yn2 > 0.0)) {   // y = 0: the product is 0 (uniform over the grid)
             if (valid)
                 for (int c = 0; c < 4; ++c) st(out + c * N, no, 0.0);
@@ -399,7 +414,7 @@ int dg_grid(int k, long ne)
 template <int N1, bool NS, bool RG>
 static void launch_dg_n(int mode, const DgArgs& A0, const double* U, const double* Y, const double* Ubar,
                         double* out, const double* yn2, const double* ut2, int eps_mode, double adt, Red red,
-                        hipStream_t st, const Mb& mb, const ExStage& ex)
+                        hipStream_t st, const Mb& mb, const ExStage& ex, int ycount)
 {
     DgArgs A = A0;
     A.rdx2 = 2.0 / A.dx;
@@ -409,14 +424,14 @@ static void launch_dg_n(int mode, const DgArgs& A0, const double* U, const doubl
     const dim3 grid(dg_grid(N1 - 1, A.ne), 1, mb.n), block(DgShape<N1>::NTH);
     if (mode == 2 && red.out) {
         timed_launch(dg_kernel<N1, NS, 2, RG>, grid, block, st, A, mb.tab, U, Y, Ubar, out, yn2, ut2, eps_mode, adt,
-                     red, mb.ms, ex);
+                     red, mb.ms, ex, 0);
         launch_finalize(red.partials, (int)grid.x, 1, red.out, st, Gate{}, mb);
         return;
     }
 #define JFMG_DG_CASE(M)                                                                                            \
     case M:                                                                                                        \
         timed_launch(dg_kernel<N1, NS, M, RG>, grid, block, st, A, mb.tab, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, \
-                     red, mb.ms, ex);                                                                              \
+                     red, mb.ms, ex, 0);                                                                           \
         break;
     switch (mode) {
         JFMG_DG_CASE(0)
@@ -426,7 +441,7 @@ static void launch_dg_n(int mode, const DgArgs& A0, const double* U, const doubl
         JFMG_DG_CASE(5)
     default:
         timed_launch(dg_kernel<N1, NS, 3, RG>, grid, block, st, A, mb.tab, U, Y, Ubar, out, yn2, ut2, eps_mode, adt,
-                     red, mb.ms, ex);
+                     red, mb.ms, ex, ycount);
         break;
     }
 #undef JFMG_DG_CASE
@@ -435,24 +450,24 @@ static void launch_dg_n(int mode, const DgArgs& A0, const double* U, const doubl
 template <int N1>
 static void launch_dg_k(bool ns, int mode, const DgArgs& A, const double* U, const double* Y, const double* Ubar,
                         double* out, const double* yn2, const double* ut2, int eps_mode, double adt, Red red,
-                        hipStream_t st, const Mb& mb, const ExStage& ex)
+                        hipStream_t st, const Mb& mb, const ExStage& ex, int yc)
 {
     if (mb.tab) {
-        if (ns) launch_dg_n<N1, true, true>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb, ex);
-        else launch_dg_n<N1, false, true>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb, ex);
+        if (ns) launch_dg_n<N1, true, true>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb, ex, yc);
+        else launch_dg_n<N1, false, true>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb, ex, yc);
     } else {
-        if (ns) launch_dg_n<N1, true, false>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb, ex);
-        else launch_dg_n<N1, false, false>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb, ex);
+        if (ns) launch_dg_n<N1, true, false>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb, ex, yc);
+        else launch_dg_n<N1, false, false>(mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb, ex, yc);
     }
 }
 
 void launch_dg(int k, bool ns, int mode, const DgArgs& A, const double* U, const double* Y, const double* Ubar,
                double* out, const double* yn2, const double* ut2, int eps_mode, double adt, Red red, hipStream_t st,
-               const Mb& mb, const ExStage& ex)
+               const Mb& mb, const ExStage& ex, int ycount)
 {
-    if (k == 1) launch_dg_k<2>(ns, mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb, ex);
-    else if (k == 2) launch_dg_k<3>(ns, mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb, ex);
-    else launch_dg_k<4>(ns, mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb, ex);
+    if (k == 1) launch_dg_k<2>(ns, mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb, ex, ycount);
+    else if (k == 2) launch_dg_k<3>(ns, mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb, ex, ycount);
+    else launch_dg_k<4>(ns, mode, A, U, Y, Ubar, out, yn2, ut2, eps_mode, adt, red, st, mb, ex, ycount);
 }
 
 // ---------------------------------------------------------------------------

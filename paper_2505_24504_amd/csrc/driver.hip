@@ -681,8 +681,9 @@ template <typename T> struct Mg {
     // set by mg_apply_t: the last stage of the cycle on the finest level applies the
     // FV -> DG transfer itself (FvLaunch::stage_tinv), ||z||^2 into tinv_red.out
     const TinvOut* tinv = nullptr;
-    Red tinv_red{};
+    Red tinv_red{};   // without .out the partials are left for the consumer
     bool tinv_done = false;
+    int tinv_count = 0;   // number of ||z||^2 partials
 
     void init()
     {
@@ -755,9 +756,10 @@ template <typename T> struct Mg {
                                                      p->scal + S_LEV + 4 * l, alpha[j], p->adt, tinv_red, p->st,
                                                      p->mb);
                     }
-                    launch_finalize(tinv_red.partials, nb, 1, tinv_red.out, p->st, Gate{}, p->mb);
+                    if (tinv_red.out) launch_finalize(tinv_red.partials, nb, 1, tinv_red.out, p->st, Gate{}, p->mb);
                     p->mv_count[l]++;
                     tinv_done = true;
+                    tinv_count = nb;
                     prev = out;
                     continue;
                 }
@@ -836,8 +838,11 @@ template <typename T> struct Mg {
 };
 
 // z = Q^-1 r, ||z||^2 into slot zslot; with rnrm2 != nullptr r is first
-// normalized in place, r /= sqrt(rnrm2[0]), by the DG -> FV transfer
-template <typename T> jfmg_status mg_apply_t(jfmg_problem* p, double* r, double* z, int zslot, const double* rnrm2)
+// normalized in place, r /= sqrt(rnrm2[0]), by the DG -> FV transfer.  With
+// zcount != nullptr the ||z||^2 block partials are left in p->partials instead
+// (*zcount of them, for a consumer that sums them itself) and the slot is not written.
+template <typename T>
+jfmg_status mg_apply_t(jfmg_problem* p, double* r, double* z, int zslot, const double* rnrm2, int* zcount = nullptr)
 {
     Level& L = p->lev[0];
     Mg<T> mg{p};
@@ -859,21 +864,28 @@ template <typename T> jfmg_status mg_apply_t(jfmg_problem* p, double* r, double*
         std::memcpy(tv.Vinv, p->A.R.Vinv, sizeof(tv.Vinv));
         std::memcpy(tv.wnc, p->A.R.wnc, sizeof(tv.wnc));
         mg.tinv = &tv;
-        mg.tinv_red = red_at(p, zslot);
+        mg.tinv_red = zcount ? Red{p->partials, nullptr} : red_at(p, zslot);
     }
     T* x = mg.run();
-    if (!x) return check_launch(p);
+    if (!x) {
+        if (zcount) *zcount = mg.tinv_count;
+        return check_launch(p);
+    }
     ProfScope ps(p, JFMG_K_TRANSFER_TINV, (double)p->N * (8 + sizeof(T)));
-    launch_transfer_Tinv<T>(p->cfg.k, p->A, mass_fix_of(p), x, z, L.nx, red_at(p, zslot), p->st, p->mb);
+    launch_transfer_Tinv<T>(p->cfg.k, p->A, mass_fix_of(p), x, z, L.nx,
+                            zcount ? Red{p->partials, nullptr} : red_at(p, zslot), p->st, p->mb);
+    if (zcount) *zcount = transfer_grid(p->cfg.k, p->A.ne);
     return check_launch(p);
 }
 
-// out = G'(U_lin) y with ||y||^2 already in slot yslot
-void jvp_slot(jfmg_problem* p, const double* y, double* out, int yslot)
+// out = G'(U_lin) y with ||y||^2 already in slot yslot, or (ycount > 0) as ycount
+// block partials in p->partials
+void jvp_slot(jfmg_problem* p, const double* y, double* out, int yslot, int ycount = 0)
 {
     ProfScope ps(p, JFMG_K_DG_JVP, 3.0 * p->N * 8 + 8.0 * lin_doubles(p->cfg.k, p->ne));
-    launch_dg(p->cfg.k, p->cfg.physics == 1, 3, p->A, p->Ulin, y, nullptr, out, p->scal + yslot, p->scal + S_UTOT,
-              p->cfg.fd_eps_mode, p->adt, no_red(), p->st, p->mb);
+    launch_dg(p->cfg.k, p->cfg.physics == 1, 3, p->A, p->Ulin, y, nullptr, out,
+              ycount > 0 ? p->partials : p->scal + yslot, p->scal + S_UTOT, p->cfg.fd_eps_mode, p->adt, no_red(),
+              p->st, p->mb, ExStage{}, ycount);
     p->jvp_count++;
 }
 
@@ -940,9 +952,13 @@ template <typename T> jfmg_status mg_apply_dg_t(jfmg_problem* p, double* r, doub
 }
 
 // z = Q^-1 r, ||z||^2 into slot zslot; with rnrm2 != nullptr r is first
-// normalized in place (r /= sqrt(rnrm2[0]), the Arnoldi v_j = w / ||w||)
-jfmg_status precond(jfmg_problem* p, double* r, double* z, int zslot, const double* rnrm2 = nullptr)
+// normalized in place (r /= sqrt(rnrm2[0]), the Arnoldi v_j = w / ||w||).  With
+// zcount != nullptr the FV multigrid form may leave the ||z||^2 partials in
+// p->partials instead (*zcount > 0 then; 0 means the slot was written).
+jfmg_status precond(jfmg_problem* p, double* r, double* z, int zslot, const double* rnrm2 = nullptr,
+                    int* zcount = nullptr)
 {
+    if (zcount) *zcount = 0;
     if (!p->cfg.precond) {
         if (rnrm2) launch_scale(r, r, p->N, rnrm2, p->st, 1.0, p->mb);
         HIPCHK(p, copy_members(p, z, r, sizeof(double) * p->N));
@@ -951,7 +967,8 @@ jfmg_status precond(jfmg_problem* p, double* r, double* z, int zslot, const doub
     }
     if (p->key.a || p->key.b)
         return p->prec == 32 ? mg_apply_dg_t<float>(p, r, z, zslot, rnrm2) : mg_apply_dg_t<double>(p, r, z, zslot, rnrm2);
-    return p->prec == 32 ? mg_apply_t<float>(p, r, z, zslot, rnrm2) : mg_apply_t<double>(p, r, z, zslot, rnrm2);
+    return p->prec == 32 ? mg_apply_t<float>(p, r, z, zslot, rnrm2, zcount)
+                         : mg_apply_t<double>(p, r, z, zslot, rnrm2, zcount);
 }
 
 // G = U - adt f(U) - Ubar and its norm (host)
@@ -994,9 +1011,10 @@ jfmg_status iter_ops(jfmg_problem* p, int j)
     double* zj = p->Z + (long)j * N;
     double* w = p->V + (long)(j + 1) * N;
     // v_j = w_{j-1} / ||w_{j-1}|| (j > 0) is formed by the preconditioner's first kernel
-    jfmg_status s = precond(p, vj, zj, S_Z, j > 0 ? p->scal + S_W : nullptr);
+    int zc = 0;   // > 0: ||z_j||^2 is left as block partials, summed by the JVP itself
+    jfmg_status s = precond(p, vj, zj, S_Z, j > 0 ? p->scal + S_W : nullptr, &zc);
     if (s) return s;
-    jvp_slot(p, zj, w, S_Z);
+    jvp_slot(p, zj, w, S_Z, zc);
     // Classical Gram-Schmidt; the second (re-orthogonalization) pass runs only
     // where the first one cancelled more than 1 - REORTH_TAU of ||w||, decided
     // on the device (the gated kernels return at once otherwise).

@@ -210,9 +210,11 @@ void launch_set_live(MemberArgs* tab, int n, const LiveBits& bits, hipStream_t s
 struct ExStage {
     double a0 = 0.0, a1 = 1.0, c = 0.0;
 };
+// mode 3 (JVP): ||y||^2 is yn2[0], or with ycount > 0 the sum of ycount block partials at yn2
 void launch_dg(int k, bool ns, int mode, const DgArgs& A, const double* U, const double* Y,
                const double* Ubar, double* out, const double* yn2, const double* ut2, int eps_mode,
-               double adt, Red red, hipStream_t st, const Mb& mb = Mb{}, const ExStage& ex = ExStage{});
+               double adt, Red red, hipStream_t st, const Mb& mb = Mb{}, const ExStage& ex = ExStage{},
+               int ycount = 0);
 // doubles of DgArgs::lin0 for degree k and ne elements
 inline long lin_doubles(int k, long ne) { return 8 * ne * (k + 1) * (k + 1) + 8 * ne * 4 * (k + 1); }
 int transfer_grid(int k, long ne);
