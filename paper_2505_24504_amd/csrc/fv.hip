@@ -438,8 +438,14 @@ fv_tile_kernel(FvArgs<T> Aa, const MemberArgs* __restrict__ mt, const T* __restr
                 constexpr int N1 = decltype(n1c)::value, NP = N1 * N1;
                 // first contraction, one thread per subcell (a, bb) of its element:
                 // h_{bb,a} = sum_i Vinv_ai t_{i,bb}
+                // the element sums of the mass fix (mean and Newton-Cotes quadrature of each
+                // component, each in the order of transfer_Tinv_kernel) in the flux rows, which
+                // the cell sums have finished reading: one (sum, component) pair per thread
+                constexpr int NEX = TX / N1, NEL = NEX * (TZ / N1);
+                static_assert(8 * NEL * sizeof(double) <= sizeof(sFz), "element sums");
+                double* const sSum = reinterpret_cast<double*>(&sFz[0][0][0]);   // [8][NEL]
                 if (valid) {
-                    const int a = ti % N1, ea = ti - a;
+                    const int a = ti % N1, ea = ti - a, b1 = tj % N1, eb = tj - b1;
                     double va[N1];
 #pragma unroll
                     for (int ii = 0; ii < N1; ++ii) va[ii] = sVi[a][ii];
@@ -449,6 +455,28 @@ fv_tile_kernel(FvArgs<T> Aa, const MemberArgs* __restrict__ mt, const T* __restr
 #pragma unroll
                         for (int ii = 0; ii < N1; ++ii) s += va[ii] * (double)sw[c][tj][ea + ii];
                         sHt[c][tj][ti] = s;
+                    }
+                    if (tv.mass_fix) {
+                        const int el = (eb / N1) * NEX + ea / N1;
+                        for (int qs = b1 * N1 + a; qs < 8; qs += NP) {
+                            const int c = qs & 3;
+                            double acc = 0.0;
+                            if (qs < 4) {
+#pragma unroll
+                                for (int jj = 0; jj < N1; ++jj)
+#pragma unroll
+                                    for (int ii = 0; ii < N1; ++ii) acc += (double)sw[c][eb + jj][ea + ii];
+                            } else {
+#pragma unroll
+                                for (int jj = 0; jj < N1; ++jj)
+#pragma unroll
+                                    for (int ii = 0; ii < N1; ++ii) {
+                                        const double w = sw[c][eb + jj][ea + ii];
+                                        acc += sWn[ii] * sWn[jj] * w;
+                                    }
+                            }
+                            sSum[qs * NEL + el] = acc;
+                        }
                     }
                 }
                 __syncthreads();
@@ -470,16 +498,8 @@ fv_tile_kernel(FvArgs<T> Aa, const MemberArgs* __restrict__ mt, const T* __restr
                             for (int jj = 0; jj < N1; ++jj) s += vb[jj] * sHt[c][eb + jj][ea + a];
                             double shift = 0.0;
                             if (tv.mass_fix) {
-                                double mean = 0.0, quad = 0.0;
-#pragma unroll
-                                for (int jj = 0; jj < N1; ++jj)
-#pragma unroll
-                                    for (int ii = 0; ii < N1; ++ii) {
-                                        const double w = sw[c][eb + jj][ea + ii];
-                                        mean += w;
-                                        quad += sWn[ii] * sWn[jj] * w;
-                                    }
-                                shift = quad - mean / NP;
+                                const int el2 = er * NEX + el;
+                                shift = sSum[(4 + c) * NEL + el2] - sSum[c * NEL + el2] / NP;
                             }
                             const double z = s - shift;
                             zout[c * nc + e * NP + nd] = z;   // the DG vector has nc nodes per component
