@@ -336,6 +336,7 @@ struct jfmg_problem {
     std::vector<IterGraph> graphs;
     double graph_adt = 0.0;
     bool use_graphs = false;
+    bool fuse_tinv = true;   // the last finest-level stage applies T^-1 (JFMG_NO_FUSED_TINV=1: off)
     IterGraph* capturing = nullptr;
     double* hpin = nullptr;            // coherent pinned host copies of the Arnoldi scalars, per iteration
     double* hscal = nullptr;           // coherent pinned: scalars read by the host, [member][HSCAL]
@@ -857,7 +858,7 @@ jfmg_status mg_apply_t(jfmg_problem* p, double* r, double* z, int zslot, const d
         if (z0.x1) mg.s.pre[0] = nb;
     }
     TinvOut tv;
-    if (fv_tile_fits_elements(L.tile, p->n1)) {   // the last finest-level stage transfers back itself
+    if (p->fuse_tinv && fv_tile_fits_elements(L.tile, p->n1)) {   // the last finest-level stage transfers back itself
         tv.z = z;
         tv.n1 = p->n1;
         tv.mass_fix = mass_fix_of(p);
@@ -1635,6 +1636,8 @@ jfmg_status create_impl(const jfmg_config* cfgs, int n, bool ragged, void* works
     {   // FGMRES iterations run eagerly unless JFMG_GRAPH=1 asks for graph replay
         const char* g = std::getenv("JFMG_GRAPH");
         p->use_graphs = g && g[0] == '1';
+        const char* f = std::getenv("JFMG_NO_FUSED_TINV");
+        p->fuse_tinv = !(f && f[0] == '1');
     }
     if (!reftab(cfg->k, cfg->transfer, p->R)) {
         delete p;

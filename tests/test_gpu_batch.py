@@ -125,14 +125,17 @@ def test_fp32_mg_step_vs_fp64_oracle_inertia_gravity():
     _fp32_vs_oracle(d, pert, 1.5e-9)                           # measured 1.7-1.8e-10
 
 
-@pytest.mark.parametrize("prec,key", [(32, None), (64, None), (32, "mg112222V")])
-def test_lockstep_members_equal_alone(prec, key):
+@pytest.mark.parametrize("prec,key,k", [(32, None, None), (64, None, None), (32, "mg112222V", None), (64, None, 3)])
+def test_lockstep_members_equal_alone(prec, key, k):
     """A lock-step batch (one problem, all members in every launch) gives each
     member bitwise the result of the same member as a single problem (also with
-    DG-level smoothing in the preconditioner)."""
+    DG-level smoothing in the preconditioner, and with k = 3, where the last
+    finest-level stage applies the FV -> DG transfer itself)."""
     ens = [m for m in W.ensemble(seed=4, members=64) if m[0]["nx"] == 32][:3]
     assert len(ens) == 3
     d = dict(ens[0][0], mg_precision=prec)
+    if k is not None:
+        d["k"] = k
     if key:   # DG-level smoothing with the one-stage smoother needs a small c*_DG
         d.update(mg_key=key, pseudo_cfl_dg=0.1)
     alone = [_alone(d, pert, 2) for _, pert, _ in ens]

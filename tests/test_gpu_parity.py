@@ -414,6 +414,38 @@ def test_mg_apply_parity(case, precond, transfer):
     assert err <= (REL_MG_APPLY if precond else 0.0)
 
 
+@pytest.mark.parametrize("case,extra", [
+    ((1, 0, 0, 0, 0.0), {}),                                    # k + 1 = 2
+    ((3, 1, 0, 0, 0.0), {}),                                    # k + 1 = 4, viscous, mass fix
+    ((3, 1, 0, 0, 0.0), {"mass_fix": 0}),
+    ((3, 0, 1, 1, 20.0), {"transfer": 1}),                      # L2 projection
+    ((3, 1, 0, 0, 0.0), {"mg_precision": 32}),
+    ((3, 1, 0, 0, 0.0), {"mg_key": "mg001111W", "rk_stages": 3}),   # x^(0) != x^(j-1) in the last stage
+    ((1, 0, 0, 0, 0.0), {"mg_levels": 1}),                      # single level: smoothing only
+    ((2, 0, 0, 0, 0.0), {}),                                    # k + 1 = 3: separate transfer in both
+])
+def test_fused_inverse_transfer_equals_transfer_kernel(case, extra, monkeypatch):
+    """The last finest-level smoother stage that applies T^-1 itself gives bitwise the z of
+    the same cycle followed by the transfer kernel (JFMG_NO_FUSED_TINV=1)."""
+    d = dict(_case_cfg(case, nx=16, nz=8), mg_levels=3)
+    d.update(extra)
+    print(f"case fused T^-1 {case} {extra}", flush=True)
+    pf = jfmg.Problem(d, device=DEV)
+    monkeypatch.setenv("JFMG_NO_FUSED_TINV", "1")
+    ps = jfmg.Problem(d, device=DEV)
+    monkeypatch.delenv("JFMG_NO_FUSED_TINV")
+    o = oracle.Oracle(dict(d, mg_precision=64))
+    U = to_dev(rand_state(o, 61))
+    r = to_dev(rand_state(o, 62, 1.0))
+    zs = []
+    for p in (pf, ps):
+        p.linearize(U, 0.8)
+        zs.append(p.mg_apply(r))
+    torch.cuda.synchronize()
+    assert float(zs[0].abs().max()) > 0.0
+    assert torch.equal(zs[0], zs[1])
+
+
 # DG-level smoothing (key a, b): a JVP per smoother stage, so the FD products' round-off
 # enters like in the FV matvecs; same bound as the preconditioner above
 DG_KEYS = ["mg102222V", "mg012222V", "mg112222V", "mg211111W"]
