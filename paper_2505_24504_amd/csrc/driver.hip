@@ -239,7 +239,6 @@ enum {
     S_W = 258,      // ||w||^2 after orthogonalization (right after h2: one readback)
     S_R = 5,        // restart residual norm^2
     S_TMP = 6,
-    S_W1 = 8,       // ||w||^2 after the first Gram-Schmidt pass
     S_DGZ = 9,      // ||z||^2 and ||z_j||^2 of the DG-level smoother (key a, b)
     S_DGX = 10,
     S_DGC = 11,     // ||T^-1 x||^2 of a coarse correction that is added to z
@@ -1021,15 +1020,17 @@ jfmg_status iter_ops(jfmg_problem* p, int j)
     // on the device (the gated kernels return at once otherwise).
     const int nv = j + 1;
     const double md = (j + 2.0) * N * 8, up = (j + 3.0) * N * 8;
-    const Gate reorth{p->scal + S_W1, p->scal + S_H1 + nv, REORTH_TAU * REORTH_TAU};
+    // ||w||^2 after the first pass is taken by Pythagoras from its coefficients and
+    // ||w||^2 before it (Gate), so the first update needs no norm of its own
+    const Gate reorth{p->scal + S_H1, nv, REORTH_TAU * REORTH_TAU};
     { ProfScope ps(p, JFMG_K_MULTIDOT, md); launch_multidot(w, p->V, N, nv, 1, N, Gate{}, red_at(p, S_H1), st, p->mb); }
-    { ProfScope ps(p, JFMG_K_UPDATE, up); launch_update(w, p->V, N, nv, N, p->scal + S_H1, red_at(p, S_W1), st, Gate{}, p->mb); }
+    { ProfScope ps(p, JFMG_K_UPDATE, up); launch_update(w, p->V, N, nv, N, p->scal + S_H1, Red{nullptr, nullptr}, st, Gate{}, p->mb); }
     launch_multidot(w, p->V, N, nv, 0, N, reorth, red_at(p, S_H2), st, p->mb);
     launch_update(w, p->V, N, nv, N, p->scal + S_H2, Red{p->partials, nullptr}, st, reorth, p->mb);
-    // ||w||^2 (of whichever pass ran last), and the scalar block h1, h2, ||w||^2 of
-    // iteration j to pinned host memory
+    // ||w||^2 (of the second pass where it ran, else the first pass's by Pythagoras), and
+    // the scalar block h1, h2, ||w||^2 of iteration j to pinned host memory
     launch_finalize_publish(p->partials, la_blocks(N), p->scal + S_W, p->scal + S_H1, S_HB, S_W - S_H1,
-                            p->hpin + (size_t)j * S_HB, reorth, p->scal + S_W1, st, p->mb, (long)S_HB * p->m);
+                            p->hpin + (size_t)j * S_HB, reorth, st, p->mb, (long)S_HB * p->m);
     return check_launch(p);
 }
 

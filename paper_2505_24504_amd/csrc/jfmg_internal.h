@@ -304,20 +304,32 @@ template <typename T> struct FvLaunch {
 // ---- linear algebra (la.hip) ----
 int la_blocks(long n);
 // out[q] = sum over nb block partials [q][nb], fixed order (one block)
-// Gate of the Arnoldi re-orthogonalization pass: the gated kernels work only
-// where after[0] < tau2 * before[0] (after/before: ||w||^2 after and before the
-// first Gram-Schmidt pass); after == nullptr means always open.
+// Gate of the Arnoldi re-orthogonalization pass.  h holds the first Gram-Schmidt
+// pass's coefficients h[0..nv) and ||w||^2 before the pass in h[nv]; ||w||^2 after
+// it is, by Pythagoras, h[nv] - sum_i h[i]^2 (gate_after: accurate to a few
+// hundred ulps where the gate stays closed, i.e. where the pass kept more than
+// sqrt(tau2) of ||w||; nv <= 64, the FGMRES restart length).  The gated kernels work only where gate_after < tau2 h[nv];
+// h == nullptr means always open.
 struct Gate {
-    const double* after = nullptr;
-    const double* before = nullptr;
+    const double* h = nullptr;
+    int nv = 0;
     double tau2 = 0.0;
 };
-__device__ __forceinline__ bool gate_open(const Gate& g) { return !g.after || g.after[0] < g.tau2 * g.before[0]; }
+// every wave evaluates it with one load per lane and a butterfly sum (nv <= 64): the
+// same fixed order, so the same value, in every wave and every kernel.  All 64 lanes
+// of the wave must call it (no divergent branch around the call).
+__device__ __forceinline__ double gate_after(const Gate& g)
+{
+    const int l = threadIdx.x & 63;
+    const double hl = l < g.nv ? g.h[l] : 0.0;
+    return g.h[g.nv] - wave_sum(hl * hl);
+}
+__device__ __forceinline__ bool gate_open(const Gate& g) { return !g.h || gate_after(g) < g.tau2 * g.h[g.nv]; }
 
 void launch_finalize(const double* partials, int nb, int nq, double* out, hipStream_t st, Gate gate = Gate{},
                      const Mb& mb = Mb{});
 void launch_finalize_publish(const double* partials, int nb, double* out, const double* src, int n, int idx,
-                             double* host, Gate gate, const double* fallback, hipStream_t st, const Mb& mb,
+                             double* host, Gate gate, hipStream_t st, const Mb& mb,
                              long host_stride);
 void launch_norm2(const double* x, long n, Red red, hipStream_t st, const Mb& mb = Mb{});
 // device scalar slots <-> coherent pinned host memory (count values per member)

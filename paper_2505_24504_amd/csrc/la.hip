@@ -20,8 +20,7 @@ __global__ void __launch_bounds__(256) finalize_kernel(const double* __restrict_
 {
     p = mbr(p, ms);
     out = mbr(out, ms);
-    gate.after = mbr(gate.after, ms);
-    gate.before = mbr(gate.before, ms);
+    gate.h = mbr(gate.h, ms);
     __shared__ double sh[4];
     const int q = blockIdx.x;
     if (!gate_open(gate)) {
@@ -39,33 +38,32 @@ void launch_finalize(const double* partials, int nb, int nq, double* out, hipStr
     finalize_kernel<<<dim3(nq, 1, mb.n), dim3(256), 0, st>>>(partials, nb, out, gate, mb.ms);
 }
 
-// Last reduction of an FGMRES iteration: out[0] = sum of the partials (or
-// fallback[0] where the gate is closed, i.e. the re-orthogonalization pass that
-// would have produced the partials was skipped), and the iteration's scalar
+// Last reduction of an FGMRES iteration: out[0] = sum of the partials (or the
+// gate's ||w||^2 after the first pass where the gate is closed, i.e. the
+// re-orthogonalization pass that would have produced the partials was skipped),
+// and the iteration's scalar
 // block src[0..n) (entry idx replaced by out[0]) stored to host-visible pinned
 // memory, so the host reads the Hessenberg column after the iteration's
 // completion event without a separate copy.
 __global__ void __launch_bounds__(256)
 finalize_publish_kernel(const double* __restrict__ p, int nb, double* __restrict__ out, const double* __restrict__ src,
-                        int n, int idx, double* __restrict__ host, Gate gate, const double* __restrict__ fallback,
-                        long ms, long host_stride)
+                        int n, int idx, double* __restrict__ host, Gate gate, long ms, long host_stride)
 {
     p = mbr(p, ms);
     out = mbr(out, ms);
     src = mbr(src, ms);
-    fallback = mbr(fallback, ms);
-    gate.after = mbr(gate.after, ms);
-    gate.before = mbr(gate.before, ms);
+    gate.h = mbr(gate.h, ms);
     host += (long)blockIdx.z * host_stride;
     __shared__ double sh[4];
     __shared__ double total;
     const bool open = gate_open(gate);
+    const double after = gate.h ? gate_after(gate) : 0.0;   // every lane takes part in its wave sum
     double a = 0.0;
     if (open)
         for (int i = threadIdx.x; i < nb; i += 256) a += p[i];
     a = block_sum<256>(a, sh);
     if (threadIdx.x == 0) {
-        total = open ? a : fallback[0];
+        total = open ? a : after;
         out[0] = total;
     }
     __syncthreads();
@@ -73,11 +71,10 @@ finalize_publish_kernel(const double* __restrict__ p, int nb, double* __restrict
 }
 
 void launch_finalize_publish(const double* partials, int nb, double* out, const double* src, int n, int idx,
-                             double* host, Gate gate, const double* fallback, hipStream_t st, const Mb& mb,
-                             long host_stride)
+                             double* host, Gate gate, hipStream_t st, const Mb& mb, long host_stride)
 {
     finalize_publish_kernel<<<dim3(1, 1, mb.n), dim3(256), 0, st>>>(partials, nb, out, src, n, idx, host, gate,
-                                                                    fallback, mb.ms, host_stride);
+                                                                    mb.ms, host_stride);
 }
 
 // Scalars between the device slots of every member and coherent pinned host
@@ -145,8 +142,7 @@ multidot_kernel(const double* __restrict__ w, const double* __restrict__ V, long
     __shared__ double sh[NW][MAXV];
     w = mbr(w, ms);
     V = mbr(V, ms);
-    gate.after = mbr(gate.after, ms);
-    gate.before = mbr(gate.before, ms);
+    gate.h = mbr(gate.h, ms);
     red = mbr(red, ms);
     if (!gate_open(gate)) return;
     const int nt = nv + self;
@@ -219,8 +215,7 @@ update_kernel(double* __restrict__ w, const double* __restrict__ V, long ld, int
               const double* __restrict__ h, Gate gate, Red red, long ms, const MemberArgs* __restrict__ mt)
 {
     n = len_of(n, mt);
-    gate.after = mbr(gate.after, ms);
-    gate.before = mbr(gate.before, ms);
+    gate.h = mbr(gate.h, ms);
     if (!gate_open(gate)) return;
     w = mbr(w, ms);
     V = mbr(V, ms);
