@@ -30,10 +30,10 @@ HBM_PEAK_GBS = 8000.0
 # device copy of that same run (FETCH_SIZE x2, WRITE_SIZE x1).
 # It describes the kernel sources hashed below and is reported as null once
 # they change.
-TRAFFIC = {"class": "fv_stage", "bytes_per_launch": 2.9624e+07,
+TRAFFIC = {"class": "fv_stage", "bytes_per_launch": 2.9758e+07,
            "sources": ["paper_2505_24504_amd/csrc/fv.hip", "paper_2505_24504_amd/csrc/jfmg_dev.h",
                        "paper_2505_24504_amd/csrc/jfmg_internal.h"],
-           "sha256": "bec9d48131b65b685a7b36494adc66b115e7c671c6fff0a4468a03dd3403c721",
+           "sha256": "38863c0153d2aabfb1b5d7fc5410ddfe39930a7e93f45c0abb478e9eb83b145d",
            "profile": "profiles/traffic_fv_stage_density_current_fp64.md"}
 
 
