@@ -632,13 +632,21 @@ template <typename T> jfmg_status linearize_t(jfmg_problem* p, const double* U, 
     }
     launch_transfer_T<T>(p->cfg.k, p->A, mass_fix_of(p), p->Ulin, (T*)p->lev[0].u, p->lev[0].nx, st, nullptr, nullptr,
                          p->mb);
-    for (int l = 0; l + 1 < p->nlev; ++l)
-        FvLaunch<T>::restrict_(fv_args<T>(p, l), (const T*)p->lev[l].u, (T*)p->lev[l + 1].u, st, p->mb);
+    // level by level: F0 = f~(u_l), its partials, and u_{l+1} = R u_l from the same tiles;
+    // then the slots of all levels in one launch
+    LinLevels lv{};
     for (int l = 0; l < p->nlev; ++l) {
-        ProfScope ps(p, JFMG_K_FV_LINEARIZE, 2.0 * 4.0 * p->lev[l].nc * sizeof(T));
-        FvLaunch<T>::lin_level(fv_args<T>(p, l), (const T*)p->lev[l].u, (T*)p->lev[l].F0, Red{p->partials, nullptr},
-                               p->scal + S_LEV + 4 * l, adt, p->cfg.pseudo_cfl, st, p->mb);
+        const bool coarser = l + 1 < p->nlev;
+        ProfScope ps(p, JFMG_K_FV_LINEARIZE, (2.0 + (coarser ? 0.25 : 0.0)) * 4.0 * p->lev[l].nc * sizeof(T));
+        const FvArgs<T> A = fv_args<T>(p, l);
+        lv.nb[l] = FvLaunch<T>::lin_level(A, (const T*)p->lev[l].u, (T*)p->lev[l].F0,
+                                          coarser ? (T*)p->lev[l + 1].u : nullptr, Red{fvpart(p, l, 0), nullptr}, adt,
+                                          st, p->mb);
+        lv.hx[l] = (double)A.hx;
+        lv.hz[l] = (double)A.hz;
     }
+    FvLaunch<T>::lin_finalize(fvpart(p, 0, 0), (long)FVP_PER_LEVEL * p->fvp, lv, p->nlev, p->scal + S_LEV,
+                              (double)fv_args<T>(p, 0).mu, adt, p->cfg.pseudo_cfl, st, p->mb);
     if (p->key.a || p->key.b) {
         // DG-level pseudo time step: the level formula with the element widths over
         // 2k+1 (the explicit DG step scale) and the finest FV level's wave speed
@@ -1141,7 +1149,7 @@ jfmg_status fgmres_cycles(jfmg_problem* p, const double* G, const std::vector<do
     int its = 0;
     // V_0 = -G / ||G|| (||G||^2 of each member in slot S_G)
     launch_scale(p->V, G, N, p->scal + S_G, st, -1.0, p->mb);
-    launch_zero(p->delta, sizeof(double) * N, st, p->mb);
+    bool delta_zero = true;   // delta = 0 until the first cycle's combination writes it
     std::vector<double> ybuf((size_t)B * m), r2(B);
     jfmg_status status = left ? JFMG_ENOCONV : JFMG_OK;
     std::vector<char> part(B);   // members that take part in the current cycle
@@ -1255,7 +1263,12 @@ jfmg_status fgmres_cycles(jfmg_problem* p, const double* G, const std::vector<do
             // followed by a synchronizing read or this cycle's event waits)
             std::copy(ybuf.begin(), ybuf.end(), p->ycoef);
             launch_scatter(p->scal + S_Yc, jmax, p->ycoef, m, st, p->mb);
-            launch_lincomb(p->delta, p->delta, p->Z, N, jmax, N, p->scal + S_Yc, st, p->mb);
+            // the first combination starts from zero (delta = Z y); a ragged member that sits it
+            // out needs its delta cleared first
+            if (delta_zero && p->ragged && std::find(part.begin(), part.end(), 0) != part.end())
+                launch_zero(p->delta, sizeof(double) * N, st, p->mb), delta_zero = false;
+            launch_lincomb(p->delta, delta_zero ? nullptr : p->delta, p->Z, N, jmax, N, p->scal + S_Yc, st, p->mb);
+            delta_zero = false;
         }
         prof_flush(p);
         for (Member& x : M)
@@ -1282,7 +1295,7 @@ jfmg_status fgmres_cycles(jfmg_problem* p, const double* G, const std::vector<do
     *its_out = its;
     if (status != JFMG_OK) return fail(p, JFMG_ENOCONV, "FGMRES did not reach its tolerance");
     set_live(p, [](int) { return true; });   // every member's delta, from all cycles
-    launch_axpby(U, 1.0, U, 1.0, p->delta, N, st, p->mb);
+    if (!delta_zero) launch_axpby(U, 1.0, U, 1.0, p->delta, N, st, p->mb);
     return check_launch(p);
 }
 

@@ -137,7 +137,9 @@ __device__ __forceinline__ void fv_face(const FvArgs<T>& A, const T (&sw)[4][HZ]
 //   |q| f~ = -hz (Phi_{I+1/2} - Phi_{I-1/2}) - hx (Phi_{J+1/2} - Phi_{J-1/2}) - |q| g w_rho.
 // The flux through a face seen from the other cell is the same number with
 // the opposite sign (HLLC(L,R;n) = -HLLC(R,L;-n)).  Modes:
-//   LIN     out = F0 = f~(u); ||u + Ubar||^2 and max(|v| + c) -> level slots, dtau
+//   LIN     out = F0 = f~(u); ||u + Ubar||^2 and max(|v| + c) block partials (the level
+//           slots and dtau from them: fv_lin_finalize_kernel); with out2 also the next coarser
+//           level's state R u
 //   STAGE   out = x0 + alpha_j dtau (b - g'x), g'x = x - adt/eps (f~(u + eps x) - F0)
 //   MATVEC  out = g'x
 //   DEFECT  out(coarse) = R(g'x - b), 2x2 agglomeration inside the tile; with out2 also
@@ -354,6 +356,16 @@ fv_tile_kernel(FvArgs<T> Aa, const MemberArgs* __restrict__ mt, const T* __restr
         }
     }
     if constexpr (MODE == FVM_LIN) {
+        // with out2: the next coarser level's state R u from the staged tile (the 2 x 2
+        // means of fv_restrict_kernel, in its order)
+        if (out2 && valid && !(ti & 1) && !(tj & 1)) {
+            const int nxc = nxl / 2;
+            const long ncc = (long)nxc * (nzl / 2), qc = (long)(J / 2) * nxc + I / 2;
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                out2[c * ncc + qc] =
+                    ((sw[c][tj + 1][ti + 1] + sw[c][tj + 1][ti + 2]) + (sw[c][tj + 2][ti + 1] + sw[c][tj + 2][ti + 2])) * T(0.25);
+        }
         double ss = 0.0, lam = 0.0;
         if (valid) {
             T Ut[4];
@@ -668,13 +680,18 @@ __global__ void __launch_bounds__(256) fv_norm2_kernel(const T* __restrict__ x, 
 }
 
 // level slots from the LIN partials: ||u + Ubar||, max(|v| + c), pseudo time step
+// The slots of every level from the LIN partials (one work-group per level, level l's
+// 2 x nb[l] partials at p + l * pstride): ||u + Ubar||, its inverse, max(|v| + c), dtau
 template <typename T>
 __global__ void __launch_bounds__(256)
-fv_lin_finalize_kernel(const double* __restrict__ p, int nb, double* __restrict__ slots, double hx, double hz,
-                       double mu, double adt, double cfl, long ms, const MemberArgs* __restrict__ mt, int lev)
+fv_lin_finalize_kernel(const double* __restrict__ p, long pstride, LinLevels lv, double* __restrict__ slots,
+                       double mu, double adt, double cfl, long ms, const MemberArgs* __restrict__ mt)
 {
-    p = mbr(p, ms);
-    slots = mbr(slots, ms);
+    const int lev = blockIdx.x;
+    p = mbr(p, ms) + lev * pstride;
+    slots = mbr(slots, ms) + 4 * lev;
+    const int nb = lv.nb[lev];
+    double hx = lv.hx[lev], hz = lv.hz[lev];
     if (mt) {   // a ragged member's own cell widths
         const FvArgs<T>& A = fv_entry<T>(mt, lev);
         hx = (double)A.hx;
@@ -753,14 +770,18 @@ static int tile_launch(const FvArgs<T>& A, const T* u, const T* F0, const T* xp,
 }
 
 template <typename T>
-void FvLaunch<T>::lin_level(const FvArgs<T>& A, const T* u, T* F0, Red red, double* slots, double adt, double cfl,
-                            hipStream_t st, const Mb& mb)
+int FvLaunch<T>::lin_level(const FvArgs<T>& A, const T* u, T* F0, T* uc, Red red, double adt, hipStream_t st,
+                           const Mb& mb)
 {
-    const int nb = tile_launch<T, FVM_LIN>(A, u, nullptr, nullptr, nullptr, nullptr, F0, nullptr, 0, slots, 0.0, adt,
-                                           0, red, st, mb);
-    fv_lin_finalize_kernel<T><<<dim3(1, 1, mb.n), dim3(256), 0, st>>>(red.partials, nb, slots, (double)A.hx,
-                                                                      (double)A.hz, (double)A.mu, adt, cfl, mb.ms,
-                                                                      mb.tab, A.lev);
+    return tile_launch<T, FVM_LIN>(A, u, nullptr, nullptr, nullptr, nullptr, F0, nullptr, 0, nullptr, 0.0, adt, 0, red,
+                                   st, mb, uc);
+}
+template <typename T>
+void FvLaunch<T>::lin_finalize(const double* partials, long pstride, const LinLevels& lv, int nlev, double* slots,
+                               double mu, double adt, double cfl, hipStream_t st, const Mb& mb)
+{
+    fv_lin_finalize_kernel<T><<<dim3(nlev, 1, mb.n), dim3(256), 0, st>>>(partials, pstride, lv, slots, mu, adt, cfl,
+                                                                         mb.ms, mb.tab);
 }
 template <typename T>
 int FvLaunch<T>::stage(const FvArgs<T>& A, const T* u, const T* F0, const T* xp, const T* x0, const T* b, T* xo,

@@ -265,10 +265,21 @@ struct TinvOut {
 // whether stage_tinv serves this tile shape and k + 1 (tiles of whole elements, k + 1 = 2 or 4)
 bool fv_tile_fits_elements(int tile, int n1);
 
+// per level of a linearization: number of LIN partials and cell widths
+struct LinLevels {
+    int nb[MAXLEV];
+    double hx[MAXLEV], hz[MAXLEV];
+};
+
 template <typename T> struct FvLaunch {
-    // F0 = f~(u), then the level slots (||u + Ubar||, max |v| + c, dtau) via red.partials
-    static void lin_level(const FvArgs<T>& A, const T* u, T* F0, Red red, double* slots, double adt, double cfl,
-                          hipStream_t st, const Mb& mb = Mb{});
+    // F0 = f~(u) and the block partials of ||u + Ubar||^2 and max |v| + c (2 x the returned
+    // count at red.partials); with uc != nullptr also uc = R u, the next coarser level's state
+    static int lin_level(const FvArgs<T>& A, const T* u, T* F0, T* uc, Red red, double adt, hipStream_t st,
+                         const Mb& mb = Mb{});
+    // the slots of levels 0..nlev-1 (||u + Ubar||, max |v| + c, dtau at slots + 4 l) from
+    // their LIN partials at partials + l * pstride, one launch for all levels
+    static void lin_finalize(const double* partials, long pstride, const LinLevels& lv, int nlev, double* slots,
+                             double mu, double adt, double cfl, hipStream_t st, const Mb& mb = Mb{});
     // one RK stage; ||x_p||^2 is the sum of xcount partials at xpart; writes the
     // ||xo||^2 partials to red.partials and returns their count
     static int stage(const FvArgs<T>& A, const T* u, const T* F0, const T* xp, const T* x0, const T* b, T* xo,
