@@ -205,6 +205,22 @@ dg_kernel(DgArgs Aa, const MemberArgs* __restrict__ mt, const double* __restrict
         u0[c] = valid ? ld(U + c * N, no) : 0.0;
         y0[c] = (MODE == 3 && valid) ? ld(Y + c * N, no) : 0.0;
     }
+    // the node row's background and (JVP) the stored volume fluxes of U', with the loads above
+    const int a = nd % N1, b = nd / N1;
+    double Ub[4], dUb[4], v0x[4], v0z[4];
+    double pbz = 0.0, irz = 0.0;
+    {
+        const int zi = ez * N1 + b;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) { Ub[c] = act ? A.bg_node[zi * 4 + c] : 0.0; dUb[c] = act ? A.dbg_node[zi * 4 + c] : 0.0; }
+        pbz = act ? A.pb_node[zi] : 0.0;
+        irz = act ? A.irt_node[zi] : 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            v0x[c] = (MODE == 3 && valid) ? ld(vol0 + c * N, no) : 0.0;
+            v0z[c] = (MODE == 3 && valid) ? ld(vol0 + (4 + c) * N, no) : 0.0;
+        }
+    }
     double eps = 0.0;
     if constexpr (MODE == 3) {
         // ||y||^2: yn2p[0], or with ycount > 0 the sum of the ycount block partials at yn2p
@@ -237,14 +253,8 @@ dg_kernel(DgArgs Aa, const MemberArgs* __restrict__ mt, const double* __restrict
     }
     __syncthreads();
 
-    const int a = nd % N1, b = nd / N1;
     // ---- B: volume fluxes (JVP: minus those of U') ----
     if (act) {
-        double Ub[4], dUb[4];
-        const int zi = ez * N1 + b;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) { Ub[c] = A.bg_node[zi * 4 + c]; dUb[c] = A.dbg_node[zi * 4 + c]; }
-        const double pbz = A.pb_node[zi], irz = A.irt_node[zi];
         double Ut[4], Fx[4], Fz[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) Ut[c] = sS[le][c][nd] + Ub[c];
@@ -287,8 +297,8 @@ dg_kernel(DgArgs Aa, const MemberArgs* __restrict__ mt, const double* __restrict
             if constexpr (MODE == 3) {
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    Fx[c] = Fx[c] - (valid ? ld(vol0 + c * N, no) : 0.0);
-                    Fz[c] = Fz[c] - (valid ? ld(vol0 + (4 + c) * N, no) : 0.0);
+                    Fx[c] = Fx[c] - v0x[c];
+                    Fz[c] = Fz[c] - v0z[c];
                 }
             }
 #pragma unroll
