@@ -60,6 +60,14 @@ __device__ __forceinline__ void dg_face(const DgArgs& A, const double (&sv)[4][N
     const double* ds = pos ? R.dp : R.dm;
     const double* eo = pos ? R.em : R.ep;
     const double* dso = pos ? R.dm : R.dp;
+    double Ub[4], dUb[4];
+    const int zrow = xf ? (ez * N1 + r) : (ez + (pos ? 1 : 0));
+    const double* bgp = xf ? A.bg_node : A.bg_face;
+    const double* dbgp = xf ? A.dbg_node : A.dbg_face;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) { Ub[c] = bgp[zrow * 4 + c]; dUb[c] = dbgp[zrow * 4 + c]; }
+    const double pbz = xf ? A.pb_node[zrow] : A.pb_face[zrow];
+    const double irz = xf ? A.irt_node[zrow] : A.irt_face[zrow];
     double trx[4], dnx[4];   // the neighbour's trace and normal derivative (d/d xi)
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -76,14 +84,6 @@ __device__ __forceinline__ void dg_face(const DgArgs& A, const double (&sv)[4][N
             }
         }
     }
-    double Ub[4], dUb[4];
-    const int zrow = xf ? (ez * N1 + r) : (ez + (pos ? 1 : 0));
-    const double* bgp = xf ? A.bg_node : A.bg_face;
-    const double* dbgp = xf ? A.dbg_node : A.dbg_face;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) { Ub[c] = bgp[zrow * 4 + c]; dUb[c] = dbgp[zrow * 4 + c]; }
-    const double pbz = xf ? A.pb_node[zrow] : A.pb_face[zrow];
-    const double irz = xf ? A.irt_node[zrow] : A.irt_face[zrow];
     double tro[4], Uo[4], Ux[4], H[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -223,6 +223,7 @@ dg_kernel(DgArgs Aa, const MemberArgs* __restrict__ mt, const double* __restrict
     }
     double eps = 0.0;
     if constexpr (MODE == 3) {
+        const double ut2 = eps_mode == 0 ? 0.0 : ut2p[0];
         // ||y||^2: yn2p[0], or with ycount > 0 the sum of the ycount block partials at yn2p
         // (fixed order; sFx serves as scratch until phase B writes it)
         double yn2;
@@ -245,7 +246,7 @@ dg_kernel(DgArgs Aa, const MemberArgs* __restrict__ mt, const double* __restrict
             return;
         }
         eps = uniform(eps_mode == 0 ? FdEps<double>::sqrt_eps / sqrt(yn2)
-                                    : FdEps<double>::sqrt_eps * sqrt(ut2p[0]) / sqrt(yn2));
+                                    : FdEps<double>::sqrt_eps * sqrt(ut2) / sqrt(yn2));
     }
     if (act) {
 #pragma unroll
