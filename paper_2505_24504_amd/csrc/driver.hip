@@ -336,6 +336,7 @@ struct jfmg_problem {
     double graph_adt = 0.0;
     bool use_graphs = false;
     bool fuse_tinv = true;   // the last finest-level stage applies T^-1 (JFMG_NO_FUSED_TINV=1: off)
+    bool reorth_always = false;   // the second Gram-Schmidt pass on every iteration (JFMG_REORTH_ALWAYS=1)
     IterGraph* capturing = nullptr;
     double* hpin = nullptr;            // coherent pinned host copies of the Arnoldi scalars, per iteration
     double* hscal = nullptr;           // coherent pinned: scalars read by the host, [member][HSCAL]
@@ -1030,15 +1031,19 @@ jfmg_status iter_ops(jfmg_problem* p, int j)
     const double md = (j + 2.0) * N * 8, up = (j + 3.0) * N * 8;
     // ||w||^2 after the first pass is taken by Pythagoras from its coefficients and
     // ||w||^2 before it (Gate), so the first update needs no norm of its own
-    const Gate reorth{p->scal + S_H1, nv, REORTH_TAU * REORTH_TAU};
+    const Gate reorth{p->scal + S_H1, nv, p->reorth_always ? 1e300 : REORTH_TAU * REORTH_TAU};
     { ProfScope ps(p, JFMG_K_MULTIDOT, md); launch_multidot(w, p->V, N, nv, 1, N, Gate{}, red_at(p, S_H1), st, p->mb); }
     { ProfScope ps(p, JFMG_K_UPDATE, up); launch_update(w, p->V, N, nv, N, p->scal + S_H1, Red{nullptr, nullptr}, st, Gate{}, p->mb); }
-    launch_multidot(w, p->V, N, nv, 0, N, reorth, red_at(p, S_H2), st, p->mb);
-    launch_update(w, p->V, N, nv, N, p->scal + S_H2, Red{p->partials, nullptr}, st, reorth, p->mb);
+    // the gated second pass: its coefficients are summed by the update kernel itself (no
+    // finalize launch); its ||w||^2 partials go after the multi-dot's
+    double* wpart = p->partials + (long)(p->m + 1) * la_blocks(N);
+    launch_multidot(w, p->V, N, nv, 0, N, reorth, Red{p->partials, nullptr}, st, p->mb);
+    launch_update(w, p->V, N, nv, N, nullptr, Red{wpart, nullptr}, st, reorth, p->mb, p->partials, p->scal + S_H2);
     // ||w||^2 (of the second pass where it ran, else the first pass's by Pythagoras), and
-    // the scalar block h1, h2, ||w||^2 of iteration j to pinned host memory
-    launch_finalize_publish(p->partials, la_blocks(N), p->scal + S_W, p->scal + S_H1, S_HB, S_W - S_H1,
-                            p->hpin + (size_t)j * S_HB, reorth, st, p->mb, (long)S_HB * p->m);
+    // the scalar block h1, h2 (0 where the second pass did not run), ||w||^2 of iteration j
+    // to pinned host memory
+    launch_finalize_publish(wpart, la_blocks(N), p->scal + S_W, p->scal + S_H1, S_HB, S_W - S_H1,
+                            p->hpin + (size_t)j * S_HB, reorth, st, p->mb, (long)S_HB * p->m, S_H2 - S_H1, nv);
     return check_launch(p);
 }
 
@@ -1652,6 +1657,8 @@ jfmg_status create_impl(const jfmg_config* cfgs, int n, bool ragged, void* works
         p->use_graphs = g && g[0] == '1';
         const char* f = std::getenv("JFMG_NO_FUSED_TINV");
         p->fuse_tinv = !(f && f[0] == '1');
+        const char* ra = std::getenv("JFMG_REORTH_ALWAYS");
+        p->reorth_always = ra && ra[0] == '1';
     }
     if (!reftab(cfg->k, cfg->transfer, p->R)) {
         delete p;

@@ -341,16 +341,19 @@ void launch_finalize(const double* partials, int nb, int nq, double* out, hipStr
                      const Mb& mb = Mb{});
 void launch_finalize_publish(const double* partials, int nb, double* out, const double* src, int n, int idx,
                              double* host, Gate gate, hipStream_t st, const Mb& mb,
-                             long host_stride);
+                             long host_stride, int zoff, int zn);
 void launch_norm2(const double* x, long n, Red red, hipStream_t st, const Mb& mb = Mb{});
 // device scalar slots <-> coherent pinned host memory (count values per member)
 void launch_gather(const double* src, int count, double* host, hipStream_t st, const Mb& mb);
 void launch_scatter(double* dst, int count, const double* host, long hstride, hipStream_t st, const Mb& mb);
+// the finalize into red.out is launched only when red.out != nullptr
 void launch_multidot(const double* w, const double* V, long ld, int nv, int self, long n, Gate gate, Red red,
                      hipStream_t st, const Mb& mb = Mb{});
-// w -= sum_i h[i] V_i; optional ||w||^2 into red.out when red.out != nullptr
+// w -= sum_i h[i] V_i; optional ||w||^2 into red.out when red.out != nullptr.  With hpart
+// the coefficients are summed from the multi-dot's partials there (la_blocks(n) per entry)
+// by every work-group and stored to hout (h unused).
 void launch_update(double* w, const double* V, long ld, int nv, long n, const double* h, Red red, hipStream_t st,
-                   Gate gate = Gate{}, const Mb& mb = Mb{});
+                   Gate gate = Gate{}, const Mb& mb = Mb{}, const double* hpart = nullptr, double* hout = nullptr);
 void launch_scale(double* out, const double* in, long n, const double* nrm2, hipStream_t st, double sgn = 1.0,
                   const Mb& mb = Mb{});
 // out = base + sum_i y[i] Z_i   (base may alias out)

@@ -40,14 +40,16 @@ void launch_finalize(const double* partials, int nb, int nq, double* out, hipStr
 
 // Last reduction of an FGMRES iteration: out[0] = sum of the partials (or the
 // gate's ||w||^2 after the first pass where the gate is closed, i.e. the
-// re-orthogonalization pass that would have produced the partials was skipped),
-// and the iteration's scalar
+// re-orthogonalization pass that would have produced the partials was skipped;
+// the entries zoff .. zoff+zn of the published block, that pass's coefficients,
+// are then 0), and the iteration's scalar
 // block src[0..n) (entry idx replaced by out[0]) stored to host-visible pinned
 // memory, so the host reads the Hessenberg column after the iteration's
 // completion event without a separate copy.
 __global__ void __launch_bounds__(256)
 finalize_publish_kernel(const double* __restrict__ p, int nb, double* __restrict__ out, const double* __restrict__ src,
-                        int n, int idx, double* __restrict__ host, Gate gate, long ms, long host_stride)
+                        int n, int idx, double* __restrict__ host, Gate gate, long ms, long host_stride, int zoff,
+                        int zn)
 {
     p = mbr(p, ms);
     out = mbr(out, ms);
@@ -67,14 +69,17 @@ finalize_publish_kernel(const double* __restrict__ p, int nb, double* __restrict
         out[0] = total;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += 256) host[i] = (i == idx) ? total : src[i];
+    // entries zoff .. zoff+zn (the second pass's coefficients) are 0 where the gate is closed
+    for (int i = threadIdx.x; i < n; i += 256)
+        host[i] = (i == idx) ? total : (!open && i >= zoff && i < zoff + zn) ? 0.0 : src[i];
 }
 
 void launch_finalize_publish(const double* partials, int nb, double* out, const double* src, int n, int idx,
-                             double* host, Gate gate, hipStream_t st, const Mb& mb, long host_stride)
+                             double* host, Gate gate, hipStream_t st, const Mb& mb, long host_stride, int zoff,
+                             int zn)
 {
     finalize_publish_kernel<<<dim3(1, 1, mb.n), dim3(256), 0, st>>>(partials, nb, out, src, n, idx, host, gate,
-                                                                    mb.ms, host_stride);
+                                                                    mb.ms, host_stride, zoff, zn);
 }
 
 // Scalars between the device slots of every member and coherent pinned host
@@ -207,20 +212,42 @@ void launch_multidot(const double* w, const double* V, long ld, int nv, int self
     const int nt = nv + self;
     const dim3 g(la_blocks(n), (nt + 3) / 4, mb.n);
     timed_launch(multidot_kernel<4>, g, dim3(LA_NTH), st, w, V, ld, nv, self, n, gate, red, mb.ms, mb.tab);
-    launch_finalize(red.partials, la_blocks(n), nt, red.out, st, gate, mb);
+    if (red.out) launch_finalize(red.partials, la_blocks(n), nt, red.out, st, gate, mb);
 }
 
+// w -= sum_v h[v] V_v.  SELF (the gated second Gram-Schmidt pass): h is not given but
+// formed by every work-group from the multi-dot's hnb block partials per entry at hpart
+// (lane-strided sums and the wave's butterfly, a fixed order), and work-group 0 stores it
+// to hout for the host; the pass runs only where its gate opens, so the finalize launch
+// it replaces is saved on every iteration where it does not.
+template <bool SELF>
 __global__ void __launch_bounds__(LA_NTH)
 update_kernel(double* __restrict__ w, const double* __restrict__ V, long ld, int nv, long n,
-              const double* __restrict__ h, Gate gate, Red red, long ms, const MemberArgs* __restrict__ mt)
+              const double* __restrict__ h, Gate gate, Red red, long ms, const MemberArgs* __restrict__ mt,
+              const double* __restrict__ hpart, int hnb, double* __restrict__ hout)
 {
     n = len_of(n, mt);
     gate.h = mbr(gate.h, ms);
     if (!gate_open(gate)) return;
     w = mbr(w, ms);
     V = mbr(V, ms);
-    h = mbr(h, ms);
     red = mbr(red, ms);
+    __shared__ double hs[SELF ? 64 : 1];
+    if constexpr (SELF) {
+        hpart = mbr(hpart, ms);
+        const int lane = threadIdx.x & 63;
+        for (int q = threadIdx.x >> 6; q < nv; q += LA_NTH / 64) {
+            double a = 0.0;
+            for (int i = lane; i < hnb; i += 64) a += hpart[(long)q * hnb + i];
+            a = wave_sum(a);
+            if (lane == 0) hs[q] = a;
+        }
+        __syncthreads();
+        if (blockIdx.x == 0 && (int)threadIdx.x < nv) mbr(hout, ms)[threadIdx.x] = hs[threadIdx.x];
+    } else {
+        h = mbr(h, ms);
+    }
+    auto coef = [&](int v) { if constexpr (SELF) return hs[v]; else return h[v]; };
     const long base = (long)blockIdx.x * LA_NTH * LA_EL + threadIdx.x;
     double acc[LA_EL];
 #pragma unroll
@@ -240,14 +267,14 @@ update_kernel(double* __restrict__ w, const double* __restrict__ V, long ld, int
                 for (int k = 0; k < LA_EL; ++k) vv[r][k] = V[(long)(v + r) * ld + base + (long)k * LA_NTH];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const double hv = h[v + r];
+                const double hv = coef(v + r);
 #pragma unroll
                 for (int k = 0; k < LA_EL; ++k) acc[k] -= hv * vv[r][k];
             }
         }
     }
     for (; v < nv; ++v) {
-        const double hv = h[v];
+        const double hv = coef(v);
         const double* Vi = V + (long)v * ld;
 #pragma unroll
         for (int k = 0; k < LA_EL; ++k) {
@@ -268,10 +295,14 @@ update_kernel(double* __restrict__ w, const double* __restrict__ V, long ld, int
 }
 
 void launch_update(double* w, const double* V, long ld, int nv, long n, const double* h, Red red, hipStream_t st,
-                   Gate gate, const Mb& mb)
+                   Gate gate, const Mb& mb, const double* hpart, double* hout)
 {
-    timed_launch(update_kernel, dim3(la_blocks(n), 1, mb.n), dim3(LA_NTH), st, w, V, ld, nv, n, h, gate, red, mb.ms,
-                 mb.tab);
+    if (hpart)
+        timed_launch(update_kernel<true>, dim3(la_blocks(n), 1, mb.n), dim3(LA_NTH), st, w, V, ld, nv, n, h, gate, red,
+                     mb.ms, mb.tab, hpart, la_blocks(n), hout);
+    else
+        timed_launch(update_kernel<false>, dim3(la_blocks(n), 1, mb.n), dim3(LA_NTH), st, w, V, ld, nv, n, h, gate,
+                     red, mb.ms, mb.tab, (const double*)nullptr, 0, (double*)nullptr);
     if (red.out) launch_finalize(red.partials, la_blocks(n), 1, red.out, st, Gate{}, mb);
 }
 

@@ -511,6 +511,31 @@ def test_implicit_euler_step_parity_bubble(transfer):
     _step_check(d, Uo, U0, to_np(U), REL_STEP_BUBBLE, st, st_o)
 
 
+def test_implicit_step_with_second_gram_schmidt_pass_every_iteration(monkeypatch):
+    """The re-orthogonalization pass (coefficients summed by the update kernel, ||w|| of the
+    second pass) on every FGMRES iteration (JFMG_REORTH_ALWAYS=1): the oracle's Newton and
+    FGMRES path and U' to the step bound, as with the gate; the gated default stays within
+    the same bound of it."""
+    d, pert, _ = W.bubble_small()
+    d = dict(d, newton_rtol=1e-9)
+    o = oracle.Oracle(d)
+    U0 = o.initial_state(pert)
+    rc, Uo, st_o = o.implicit_step(U0)
+    assert rc == 0
+    monkeypatch.setenv("JFMG_REORTH_ALWAYS", "1")
+    p = jfmg.Problem(d, device=DEV)
+    monkeypatch.delenv("JFMG_REORTH_ALWAYS")
+    U = to_dev(U0)
+    st = p.implicit_step(U)
+    print("case reorth every iteration", flush=True)
+    _step_check(d, Uo, U0, to_np(U), REL_STEP_BUBBLE, st, st_o)
+    q = jfmg.Problem(d, device=DEV)
+    Ud = to_dev(U0)
+    sd = q.implicit_step(Ud)
+    assert sd["gmres_its"] == st["gmres_its"] and sd["newton_its"] == st["newton_its"]
+    assert np.linalg.norm(to_np(Ud) - to_np(U)) <= REL_STEP_BUBBLE * np.linalg.norm(Uo)
+
+
 @pytest.mark.parametrize("key", ["mg112222V", "mg011111V"])
 def test_implicit_step_dg_smoothing_parity(key):
     """Steps preconditioned with DG-level smoothing against the oracle's (16x16 bubble, k = 1)."""
