@@ -284,6 +284,13 @@ struct Level {
 
 }  // namespace
 
+// v = sgn src / sqrt(nrm2[0]), formed by the preconditioner's first kernel
+struct Norm {
+    const double* src = nullptr;
+    const double* nrm2 = nullptr;
+    double sgn = 1.0;
+};
+
 struct jfmg_problem {
     jfmg_config cfg;
     Key key;
@@ -337,6 +344,7 @@ struct jfmg_problem {
     bool use_graphs = false;
     bool fuse_tinv = true;   // the last finest-level stage applies T^-1 (JFMG_NO_FUSED_TINV=1: off)
     bool reorth_always = false;   // the second Gram-Schmidt pass on every iteration (JFMG_REORTH_ALWAYS=1)
+    Norm v0;   // set by a cycle start: v_0 formed by iteration 0's first kernel (eager launches only)
     IterGraph* capturing = nullptr;
     double* hpin = nullptr;            // coherent pinned host copies of the Arnoldi scalars, per iteration
     double* hscal = nullptr;           // coherent pinned: scalars read by the host, [member][HSCAL]
@@ -846,12 +854,12 @@ template <typename T> struct Mg {
     }
 };
 
-// z = Q^-1 r, ||z||^2 into slot zslot; with rnrm2 != nullptr r is first
-// normalized in place, r /= sqrt(rnrm2[0]), by the DG -> FV transfer.  With
-// zcount != nullptr the ||z||^2 block partials are left in p->partials instead
+// z = Q^-1 r, ||z||^2 into slot zslot; with nm != nullptr r is first formed as
+// nm->sgn nm->src / sqrt(nm->nrm2[0]) (in place when src == r) by the DG -> FV transfer.
+// With zcount != nullptr the ||z||^2 block partials are left in p->partials instead
 // (*zcount of them, for a consumer that sums them itself) and the slot is not written.
 template <typename T>
-jfmg_status mg_apply_t(jfmg_problem* p, double* r, double* z, int zslot, const double* rnrm2, int* zcount = nullptr)
+jfmg_status mg_apply_t(jfmg_problem* p, double* r, double* z, int zslot, const Norm* nm, int* zcount = nullptr)
 {
     Level& L = p->lev[0];
     Mg<T> mg{p};
@@ -860,9 +868,9 @@ jfmg_status mg_apply_t(jfmg_problem* p, double* r, double* z, int zslot, const d
         // b = T r, and the finest level's first stage from zero in the same kernel
         const ZeroStage<T> z0 = mg.zero_stage(0, p->key.c);
         ProfScope ps(p, JFMG_K_TRANSFER_T,
-                     (double)p->N * (8 + (z0.x1 ? 2 : 1) * sizeof(T)) + (rnrm2 ? 8.0 * p->N : 0.0));
-        const int nb = launch_transfer_T<T>(p->cfg.k, p->A, mass_fix_of(p), r, (T*)L.b, L.nx, p->st, rnrm2,
-                                            rnrm2 ? r : nullptr, p->mb, z0);
+                     (double)p->N * (8 + (z0.x1 ? 2 : 1) * sizeof(T)) + (nm ? 8.0 * p->N : 0.0));
+        const int nb = launch_transfer_T<T>(p->cfg.k, p->A, mass_fix_of(p), nm ? nm->src : r, (T*)L.b, L.nx, p->st,
+                                            nm ? nm->nrm2 : nullptr, nm ? r : nullptr, p->mb, z0, nm ? nm->sgn : 1.0);
         if (z0.x1) mg.s.pre[0] = nb;
     }
     TinvOut tv;
@@ -932,10 +940,10 @@ void dg_smooth(jfmg_problem* p, double* z, const double* r, int nu, bool& zzero,
 
 // z = Q^-1 r with the DG data as the finest level of the cycle (key a, b > 0): a DG
 // sweeps from z = 0, z += T^-1 q^-1 T (r - G' z), b DG sweeps; ||z||^2 into zslot
-template <typename T> jfmg_status mg_apply_dg_t(jfmg_problem* p, double* r, double* z, int zslot, const double* rnrm2)
+template <typename T> jfmg_status mg_apply_dg_t(jfmg_problem* p, double* r, double* z, int zslot, const Norm* nm)
 {
     const Key& k = p->key;
-    if (rnrm2) launch_scale(r, r, p->N, rnrm2, p->st, 1.0, p->mb);
+    if (nm) launch_scale(r, nm->src, p->N, nm->nrm2, p->st, nm->sgn, p->mb);
     bool zzero = true;
     dg_smooth(p, z, r, k.a, zzero, S_DGZ);
     const int cslot = k.b ? S_DGZ : zslot;
@@ -960,24 +968,24 @@ template <typename T> jfmg_status mg_apply_dg_t(jfmg_problem* p, double* r, doub
     return check_launch(p);
 }
 
-// z = Q^-1 r, ||z||^2 into slot zslot; with rnrm2 != nullptr r is first
-// normalized in place (r /= sqrt(rnrm2[0]), the Arnoldi v_j = w / ||w||).  With
+// z = Q^-1 r, ||z||^2 into slot zslot; with nm != nullptr r is first formed as
+// nm->sgn nm->src / ||nm->src|| (the Arnoldi v_j = w / ||w||, v_0 = -G / ||G||).  With
 // zcount != nullptr the FV multigrid form may leave the ||z||^2 partials in
 // p->partials instead (*zcount > 0 then; 0 means the slot was written).
-jfmg_status precond(jfmg_problem* p, double* r, double* z, int zslot, const double* rnrm2 = nullptr,
+jfmg_status precond(jfmg_problem* p, double* r, double* z, int zslot, const Norm* nm = nullptr,
                     int* zcount = nullptr)
 {
     if (zcount) *zcount = 0;
     if (!p->cfg.precond) {
-        if (rnrm2) launch_scale(r, r, p->N, rnrm2, p->st, 1.0, p->mb);
+        if (nm) launch_scale(r, nm->src, p->N, nm->nrm2, p->st, nm->sgn, p->mb);
         HIPCHK(p, copy_members(p, z, r, sizeof(double) * p->N));
         launch_norm2(z, p->N, red_at(p, zslot), p->st, p->mb);
         return check_launch(p);
     }
     if (p->key.a || p->key.b)
-        return p->prec == 32 ? mg_apply_dg_t<float>(p, r, z, zslot, rnrm2) : mg_apply_dg_t<double>(p, r, z, zslot, rnrm2);
-    return p->prec == 32 ? mg_apply_t<float>(p, r, z, zslot, rnrm2, zcount)
-                         : mg_apply_t<double>(p, r, z, zslot, rnrm2, zcount);
+        return p->prec == 32 ? mg_apply_dg_t<float>(p, r, z, zslot, nm) : mg_apply_dg_t<double>(p, r, z, zslot, nm);
+    return p->prec == 32 ? mg_apply_t<float>(p, r, z, zslot, nm, zcount)
+                         : mg_apply_t<double>(p, r, z, zslot, nm, zcount);
 }
 
 // G = U - adt f(U) - Ubar and its norm (host)
@@ -1019,9 +1027,12 @@ jfmg_status iter_ops(jfmg_problem* p, int j)
     double* vj = p->V + (long)j * N;
     double* zj = p->Z + (long)j * N;
     double* w = p->V + (long)(j + 1) * N;
-    // v_j = w_{j-1} / ||w_{j-1}|| (j > 0) is formed by the preconditioner's first kernel
+    // v_j = w_{j-1} / ||w_{j-1}|| (j > 0), and v_0 where the cycle left it to this
+    // iteration (p->v0), is formed by the preconditioner's first kernel
     int zc = 0;   // > 0: ||z_j||^2 is left as block partials, summed by the JVP itself
-    jfmg_status s = precond(p, vj, zj, S_Z, j > 0 ? p->scal + S_W : nullptr, &zc);
+    const Norm nw{vj, p->scal + S_W, 1.0};
+    const Norm* nm = j > 0 ? &nw : (p->v0.src ? &p->v0 : nullptr);
+    jfmg_status s = precond(p, vj, zj, S_Z, nm, &zc);
     if (s) return s;
     jvp_slot(p, zj, w, S_Z, zc);
     // Classical Gram-Schmidt; the second (re-orthogonalization) pass runs only
@@ -1152,8 +1163,13 @@ jfmg_status fgmres_cycles(jfmg_problem* p, const double* G, const std::vector<do
         left += !x.done;
     }
     int its = 0;
-    // V_0 = -G / ||G|| (||G||^2 of each member in slot S_G)
-    launch_scale(p->V, G, N, p->scal + S_G, st, -1.0, p->mb);
+    // V_0 = -G / ||G|| (||G||^2 of each member in slot S_G), formed by iteration 0's first
+    // kernel (a separate launch where iterations are replayed from graphs)
+    auto set_v0 = [&](const double* src, int slot, double sgn) {
+        if (p->use_graphs) launch_scale(p->V, src, N, p->scal + slot, st, sgn, p->mb);
+        else p->v0 = Norm{src, p->scal + slot, sgn};
+    };
+    set_v0(G, S_G, -1.0);
     bool delta_zero = true;   // delta = 0 until the first cycle's combination writes it
     std::vector<double> ybuf((size_t)B * m), r2(B);
     jfmg_status status = left ? JFMG_ENOCONV : JFMG_OK;
@@ -1199,6 +1215,7 @@ jfmg_status fgmres_cycles(jfmg_problem* p, const double* G, const std::vector<do
             return JFMG_OK;
         };
         jfmg_status s0 = issue(0);
+        p->v0 = Norm{};
         if (s0) return s0;
         int next = 1;   // next iteration to issue
         for (int j = 0; j < m; ++j) {
@@ -1295,7 +1312,7 @@ jfmg_status fgmres_cycles(jfmg_problem* p, const double* G, const std::vector<do
             if (x.beta <= tol[mb]) { x.done = true; --left; }
         }
         if (!left) { status = JFMG_OK; break; }
-        launch_scale(p->V, p->tmp2, N, p->scal + S_R, st, 1.0, p->mb);   // V_0 = r / ||r||
+        set_v0(p->tmp2, S_R, 1.0);   // V_0 = r / ||r||
     }
     *its_out = its;
     if (status != JFMG_OK) return fail(p, JFMG_ENOCONV, "FGMRES did not reach its tolerance");
@@ -1308,6 +1325,7 @@ jfmg_status fgmres(jfmg_problem* p, const double* G, const std::vector<double>& 
                    const std::vector<char>& active, double* U, int* its_out)
 {
     const jfmg_status s = fgmres_cycles(p, G, gnorm, tol, active, U, its_out);
+    p->v0 = Norm{};
     set_live(p, [](int) { return true; });   // every member takes part in the Newton-level work
     return s;
 }

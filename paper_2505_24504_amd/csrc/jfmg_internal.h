@@ -236,10 +236,11 @@ template <typename T> struct ZeroStage {
     double alpha = 0.0;
     Red red{nullptr, nullptr};
 };
+// u = T U; with snrm2 the input is first scaled, sgn U / sqrt(snrm2[0]), and written to Us
 template <typename T>
 int launch_transfer_T(int k, const DgArgs& A, int mass_fix, const double* U, T* u, int nxf, hipStream_t st,
                       const double* snrm2 = nullptr, double* Us = nullptr, const Mb& mb = Mb{},
-                      const ZeroStage<T>& z0 = ZeroStage<T>{});
+                      const ZeroStage<T>& z0 = ZeroStage<T>{}, double sgn = 1.0);
 template <typename T>
 void launch_transfer_Tinv(int k, const DgArgs& A, int mass_fix, const T* u, double* U, int nxf, Red red,
                           hipStream_t st, const Mb& mb = Mb{});

@@ -25,16 +25,16 @@ __device__ __forceinline__ long subcell_index(int ex, int ez, int i, int j, int 
     return (long)(ez * n1 + j) * nxf + (long)ex * n1 + i;
 }
 
-// snrm2 != nullptr: the input is U / ||U|| (||U||^2 = snrm2[0]); the scaled DG
-// vector is also written back to Us (may alias U: every value is read and
-// written by the same thread).
+// snrm2 != nullptr: the input is sgn U / ||U|| (||U||^2 = snrm2[0]); the scaled DG
+// vector is also written to Us (may alias U: every value is read and written by
+// the same thread).
 // With x1 != nullptr the kernel also takes the first RK stage of the finest FV
 // level from x = 0: x1 = (alpha dtau) u and the block partials of ||x1||^2.
 template <int N1, typename T, bool RG>
 __global__ void __launch_bounds__(TrShape<N1>::NTH)
 transfer_T_kernel(DgArgs Aa, const MemberArgs* __restrict__ mt, int mass_fix, const double* U, T* __restrict__ u,
                   int nxf, const double* snrm2, double* Us, T* __restrict__ x1, const double* __restrict__ slots,
-                  double alpha, Red red, long ms)
+                  double alpha, Red red, long ms, double sgn)
 {
     const DgArgs& A = dg_of<RG>(Aa, mt);
     if (RG) nxf = N1 * A.nx;
@@ -73,7 +73,7 @@ transfer_T_kernel(DgArgs Aa, const MemberArgs* __restrict__ mt, int mass_fix, co
         Vi[a] = A.R.V[i][a];
         Vj[a] = A.R.V[j][a];
     }
-    const double s = snrm2 ? 1.0 / sqrt(sn2) : 1.0;
+    const double s = snrm2 ? sgn / sqrt(sn2) : 1.0;
     if (act)
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
@@ -234,28 +234,28 @@ int transfer_grid(int k, long ne)
 
 template <int N1, typename T, bool RG>
 static void transfer_T_n(dim3 g, const DgArgs& A, int mass_fix, const double* U, T* u, int nxf, hipStream_t st,
-                         const double* snrm2, double* Us, const Mb& mb, const ZeroStage<T>& z0)
+                         const double* snrm2, double* Us, const Mb& mb, const ZeroStage<T>& z0, double sgn)
 {
     timed_launch(transfer_T_kernel<N1, T, RG>, g, dim3(TrShape<N1>::NTH), st, A, mb.tab, mass_fix, U, u, nxf, snrm2,
-                 Us, z0.x1, z0.slots, z0.alpha, z0.red, mb.ms);
+                 Us, z0.x1, z0.slots, z0.alpha, z0.red, mb.ms, sgn);
 }
 
 template <int N1, typename T>
 static void transfer_T_k(dim3 g, const DgArgs& A, int mass_fix, const double* U, T* u, int nxf, hipStream_t st,
-                         const double* snrm2, double* Us, const Mb& mb, const ZeroStage<T>& z0)
+                         const double* snrm2, double* Us, const Mb& mb, const ZeroStage<T>& z0, double sgn)
 {
-    if (mb.tab) transfer_T_n<N1, T, true>(g, A, mass_fix, U, u, nxf, st, snrm2, Us, mb, z0);
-    else transfer_T_n<N1, T, false>(g, A, mass_fix, U, u, nxf, st, snrm2, Us, mb, z0);
+    if (mb.tab) transfer_T_n<N1, T, true>(g, A, mass_fix, U, u, nxf, st, snrm2, Us, mb, z0, sgn);
+    else transfer_T_n<N1, T, false>(g, A, mass_fix, U, u, nxf, st, snrm2, Us, mb, z0, sgn);
 }
 
 template <typename T>
 int launch_transfer_T(int k, const DgArgs& A, int mass_fix, const double* U, T* u, int nxf, hipStream_t st,
-                      const double* snrm2, double* Us, const Mb& mb, const ZeroStage<T>& z0)
+                      const double* snrm2, double* Us, const Mb& mb, const ZeroStage<T>& z0, double sgn)
 {
     const dim3 g(transfer_grid(k, A.ne), 1, mb.n);
-    if (k == 1) transfer_T_k<2, T>(g, A, mass_fix, U, u, nxf, st, snrm2, Us, mb, z0);
-    else if (k == 2) transfer_T_k<3, T>(g, A, mass_fix, U, u, nxf, st, snrm2, Us, mb, z0);
-    else transfer_T_k<4, T>(g, A, mass_fix, U, u, nxf, st, snrm2, Us, mb, z0);
+    if (k == 1) transfer_T_k<2, T>(g, A, mass_fix, U, u, nxf, st, snrm2, Us, mb, z0, sgn);
+    else if (k == 2) transfer_T_k<3, T>(g, A, mass_fix, U, u, nxf, st, snrm2, Us, mb, z0, sgn);
+    else transfer_T_k<4, T>(g, A, mass_fix, U, u, nxf, st, snrm2, Us, mb, z0, sgn);
     return (int)g.x;
 }
 
@@ -283,9 +283,9 @@ void launch_transfer_Tinv(int k, const DgArgs& A, int mass_fix, const T* u, doub
 }
 
 template int launch_transfer_T<double>(int, const DgArgs&, int, const double*, double*, int, hipStream_t,
-                                       const double*, double*, const Mb&, const ZeroStage<double>&);
+                                       const double*, double*, const Mb&, const ZeroStage<double>&, double);
 template int launch_transfer_T<float>(int, const DgArgs&, int, const double*, float*, int, hipStream_t,
-                                      const double*, double*, const Mb&, const ZeroStage<float>&);
+                                      const double*, double*, const Mb&, const ZeroStage<float>&, double);
 template void launch_transfer_Tinv<double>(int, const DgArgs&, int, const double*, double*, int, Red, hipStream_t,
                                            const Mb&);
 template void launch_transfer_Tinv<float>(int, const DgArgs&, int, const float*, double*, int, Red, hipStream_t,
