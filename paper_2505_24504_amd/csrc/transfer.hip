@@ -106,6 +106,33 @@ transfer_T_kernel(DgArgs Aa, const MemberArgs* __restrict__ mt, int mass_fix, co
     if (act)
         for (int c = 0; c < 4; ++c) sU[le][c][nd] = tv[c];
     __syncthreads();
+    // the element's mass-fix sums (mean and Newton-Cotes quadrature of each component, each
+    // summed in the order below by one of the element's threads) into sH, which the
+    // contractions are done with: [le] as 8 consecutive doubles
+    double* const ssum = &sH[act ? le : 0][0][0];
+    if (mass_fix) {
+        if (act)
+            for (int q = nd; q < 8; q += NP) {
+                const int c = q & 3;
+                double acc = 0.0;
+                if (q < 4) {
+#pragma unroll
+                    for (int jj = 0; jj < N1; ++jj)
+#pragma unroll
+                        for (int ii = 0; ii < N1; ++ii) acc += sU[le][c][jj * N1 + ii];
+                } else {
+#pragma unroll
+                    for (int jj = 0; jj < N1; ++jj)
+#pragma unroll
+                        for (int ii = 0; ii < N1; ++ii) {
+                            const double v = sU[le][c][jj * N1 + ii];
+                            acc += A.R.wnc[ii] * A.R.wnc[jj] * v;
+                        }
+                }
+                ssum[q] = acc;
+            }
+        __syncthreads();
+    }
     double nrm = 0.0;
     if (valid) {
         const int ez = (int)(e / A.nx), ex = (int)(e - (long)ez * A.nx);
@@ -113,18 +140,7 @@ transfer_T_kernel(DgArgs Aa, const MemberArgs* __restrict__ mt, int mass_fix, co
         const T s1 = x1 ? (T)(alpha * dtau) : T(0);
         for (int c = 0; c < 4; ++c) {
             double shift = 0.0;
-            if (mass_fix) {
-                double mean = 0.0, quad = 0.0;
-#pragma unroll
-                for (int jj = 0; jj < N1; ++jj)
-#pragma unroll
-                    for (int ii = 0; ii < N1; ++ii) {
-                        const double v = sU[le][c][jj * N1 + ii];
-                        mean += v;
-                        quad += A.R.wnc[ii] * A.R.wnc[jj] * v;
-                    }
-                shift = mean / NP - quad;
-            }
+            if (mass_fix) shift = ssum[c] / NP - ssum[4 + c];   // mean / NP - quad
             const T b = (T)(tv[c] - shift);
             u[c * nc + o] = b;
             if (x1) {
