@@ -1043,12 +1043,14 @@ jfmg_status iter_ops(jfmg_problem* p, int j)
     // ||w||^2 after the first pass is taken by Pythagoras from its coefficients and
     // ||w||^2 before it (Gate), so the first update needs no norm of its own
     const Gate reorth{p->scal + S_H1, nv, p->reorth_always ? 1e300 : REORTH_TAU * REORTH_TAU};
+    // the gated second pass: its multi-dot is taken by the first update kernel (from the w
+    // it has formed), its coefficients are summed by its own update kernel (no finalize
+    // launch), and its ||w||^2 partials go after the multi-dot's
     { ProfScope ps(p, JFMG_K_MULTIDOT, md); launch_multidot(w, p->V, N, nv, 1, N, Gate{}, red_at(p, S_H1), st, p->mb); }
-    { ProfScope ps(p, JFMG_K_UPDATE, up); launch_update(w, p->V, N, nv, N, p->scal + S_H1, Red{nullptr, nullptr}, st, Gate{}, p->mb); }
-    // the gated second pass: its coefficients are summed by the update kernel itself (no
-    // finalize launch); its ||w||^2 partials go after the multi-dot's
+    { ProfScope ps(p, JFMG_K_UPDATE, up);
+      launch_update(w, p->V, N, nv, N, p->scal + S_H1, Red{nullptr, nullptr}, st, Gate{}, p->mb, nullptr, nullptr,
+                    reorth, p->partials); }
     double* wpart = p->partials + (long)(p->m + 1) * la_blocks(N);
-    launch_multidot(w, p->V, N, nv, 0, N, reorth, Red{p->partials, nullptr}, st, p->mb);
     launch_update(w, p->V, N, nv, N, nullptr, Red{wpart, nullptr}, st, reorth, p->mb, p->partials, p->scal + S_H2);
     // ||w||^2 (of the second pass where it ran, else the first pass's by Pythagoras), and
     // the scalar block h1, h2 (0 where the second pass did not run), ||w||^2 of iteration j

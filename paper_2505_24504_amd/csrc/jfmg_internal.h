@@ -352,9 +352,12 @@ void launch_multidot(const double* w, const double* V, long ld, int nv, int self
                      hipStream_t st, const Mb& mb = Mb{});
 // w -= sum_i h[i] V_i; optional ||w||^2 into red.out when red.out != nullptr.  With hpart
 // the coefficients are summed from the multi-dot's partials there (la_blocks(n) per entry)
-// by every work-group and stored to hout (h unused).
+// by every work-group and stored to hout (h unused).  With dots (and no hpart), where gate g2
+// opens, the multi-dot <w_new, v_i> (i < nv) of the updated w follows in the same kernel, its
+// block partials at dots (la_blocks(n) per entry, as launch_multidot stores them).
 void launch_update(double* w, const double* V, long ld, int nv, long n, const double* h, Red red, hipStream_t st,
-                   Gate gate = Gate{}, const Mb& mb = Mb{}, const double* hpart = nullptr, double* hout = nullptr);
+                   Gate gate = Gate{}, const Mb& mb = Mb{}, const double* hpart = nullptr, double* hout = nullptr,
+                   Gate g2 = Gate{}, double* dots = nullptr);
 void launch_scale(double* out, const double* in, long n, const double* nrm2, hipStream_t st, double sgn = 1.0,
                   const Mb& mb = Mb{});
 // out = base + sum_i y[i] Z_i   (base may alias out)

@@ -220,15 +220,23 @@ void launch_multidot(const double* w, const double* V, long ld, int nv, int self
 // (lane-strided sums and the wave's butterfly, a fixed order), and work-group 0 stores it
 // to hout for the host; the pass runs only where its gate opens, so the finalize launch
 // it replaces is saved on every iteration where it does not.
+// With dots (the first pass), where the gate g2 of the second pass opens, the kernel goes on
+// to that pass's multi-dot <w, v_q> of the w it has just formed, still in registers: the
+// block partials at dots[q * gridDim.x + blockIdx.x], with the multi-dot kernel's products,
+// order and partial layout (its launch, one kernel per iteration, is saved).
 template <bool SELF>
 __global__ void __launch_bounds__(LA_NTH)
 update_kernel(double* __restrict__ w, const double* __restrict__ V, long ld, int nv, long n,
               const double* __restrict__ h, Gate gate, Red red, long ms, const MemberArgs* __restrict__ mt,
-              const double* __restrict__ hpart, int hnb, double* __restrict__ hout)
+              const double* __restrict__ hpart, int hnb, double* __restrict__ hout, Gate g2,
+              double* __restrict__ dots)
 {
     n = len_of(n, mt);
     gate.h = mbr(gate.h, ms);
+    g2.h = mbr(g2.h, ms);
+    // every lane takes part in the gates' wave sums
     if (!gate_open(gate)) return;
+    const bool dots2 = !SELF && dots && gate_open(g2);
     w = mbr(w, ms);
     V = mbr(V, ms);
     red = mbr(red, ms);
@@ -292,17 +300,64 @@ update_kernel(double* __restrict__ w, const double* __restrict__ V, long ld, int
         }
     }
     if (red.partials) put_partial<LA_NTH>(red, s);
+    if (!dots2) return;
+    dots = mbr(dots, ms);
+    constexpr int NW = LA_NTH / 64, G = 4;
+    __shared__ double sd[NW][G];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const bool whole = base - threadIdx.x + LA_NTH * LA_EL <= n;
+    for (int v0 = 0; v0 < nv; v0 += G) {
+        double a[G];
+#pragma unroll
+        for (int q = 0; q < G; ++q) a[q] = 0.0;
+        if (whole && v0 + G <= nv) {
+            double vv[LA_EL][G];
+#pragma unroll
+            for (int k = 0; k < LA_EL; ++k)
+#pragma unroll
+                for (int q = 0; q < G; ++q) vv[k][q] = V[(long)(v0 + q) * ld + base + (long)k * LA_NTH];
+#pragma unroll
+            for (int k = 0; k < LA_EL; ++k)
+#pragma unroll
+                for (int q = 0; q < G; ++q) a[q] += acc[k] * vv[k][q];
+        } else {
+#pragma unroll
+            for (int k = 0; k < LA_EL; ++k) {
+                const long i = base + (long)k * LA_NTH;
+                if (i < n) {
+#pragma unroll
+                    for (int q = 0; q < G; ++q)
+                        if (v0 + q < nv) a[q] += acc[k] * V[(long)(v0 + q) * ld + i];
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            if (v0 + q < nv) {
+                const double t = wave_sum(a[q]);
+                if (lane == 0) sd[wid][q] = t;
+            }
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < G && v0 + (int)threadIdx.x < nv) {
+            double t = 0.0;
+#pragma unroll
+            for (int r = 0; r < NW; ++r) t += sd[r][threadIdx.x];
+            dots[(long)(v0 + threadIdx.x) * gridDim.x + blockIdx.x] = t;
+        }
+        __syncthreads();
+    }
 }
 
 void launch_update(double* w, const double* V, long ld, int nv, long n, const double* h, Red red, hipStream_t st,
-                   Gate gate, const Mb& mb, const double* hpart, double* hout)
+                   Gate gate, const Mb& mb, const double* hpart, double* hout, Gate g2, double* dots)
 {
     if (hpart)
         timed_launch(update_kernel<true>, dim3(la_blocks(n), 1, mb.n), dim3(LA_NTH), st, w, V, ld, nv, n, h, gate, red,
-                     mb.ms, mb.tab, hpart, la_blocks(n), hout);
+                     mb.ms, mb.tab, hpart, la_blocks(n), hout, Gate{}, (double*)nullptr);
     else
         timed_launch(update_kernel<false>, dim3(la_blocks(n), 1, mb.n), dim3(LA_NTH), st, w, V, ld, nv, n, h, gate,
-                     red, mb.ms, mb.tab, (const double*)nullptr, 0, (double*)nullptr);
+                     red, mb.ms, mb.tab, (const double*)nullptr, 0, (double*)nullptr, g2, dots);
     if (red.out) launch_finalize(red.partials, la_blocks(n), 1, red.out, st, Gate{}, mb);
 }
 
