@@ -239,6 +239,7 @@ enum {
     S_W = 258,      // ||w||^2 after orthogonalization (right after h2: one readback)
     S_R = 5,        // restart residual norm^2
     S_TMP = 6,
+    S_CNT = 7,      // counter of the gated pass's work-groups (64-bit, zero between launches)
     S_DGZ = 9,      // ||z||^2 and ||z_j||^2 of the DG-level smoother (key a, b)
     S_DGX = 10,
     S_DGC = 11,     // ||T^-1 x||^2 of a coarse correction that is added to z
@@ -1044,19 +1045,26 @@ jfmg_status iter_ops(jfmg_problem* p, int j)
     // ||w||^2 before it (Gate), so the first update needs no norm of its own
     const Gate reorth{p->scal + S_H1, nv, p->reorth_always ? 1e300 : REORTH_TAU * REORTH_TAU};
     // the gated second pass: its multi-dot is taken by the first update kernel (from the w
-    // it has formed), its coefficients are summed by its own update kernel (no finalize
-    // launch), and its ||w||^2 partials go after the multi-dot's
+    // it has formed); its coefficients are summed by its own update kernel, which also
+    // stores ||w||^2 (of the second pass where it ran, else the first pass's by Pythagoras)
+    // and publishes the scalar block h1, h2 (0 where the second pass did not run), ||w||^2
+    // of iteration j to pinned host memory; its ||w||^2 partials go after the multi-dot's
     { ProfScope ps(p, JFMG_K_MULTIDOT, md); launch_multidot(w, p->V, N, nv, 1, N, Gate{}, red_at(p, S_H1), st, p->mb); }
     { ProfScope ps(p, JFMG_K_UPDATE, up);
-      launch_update(w, p->V, N, nv, N, p->scal + S_H1, Red{nullptr, nullptr}, st, Gate{}, p->mb, nullptr, nullptr,
-                    reorth, p->partials); }
+      launch_update(w, p->V, N, nv, N, p->scal + S_H1, Red{nullptr, nullptr}, st, Gate{}, p->mb, reorth,
+                    p->partials); }
     double* wpart = p->partials + (long)(p->m + 1) * la_blocks(N);
-    launch_update(w, p->V, N, nv, N, nullptr, Red{wpart, nullptr}, st, reorth, p->mb, p->partials, p->scal + S_H2);
-    // ||w||^2 (of the second pass where it ran, else the first pass's by Pythagoras), and
-    // the scalar block h1, h2 (0 where the second pass did not run), ||w||^2 of iteration j
-    // to pinned host memory
-    launch_finalize_publish(wpart, la_blocks(N), p->scal + S_W, p->scal + S_H1, S_HB, S_W - S_H1,
-                            p->hpin + (size_t)j * S_HB, reorth, st, p->mb, (long)S_HB * p->m, S_H2 - S_H1, nv);
+    Publish pub;
+    pub.out = p->scal + S_W;
+    pub.src = p->scal + S_H1;
+    pub.ns = S_HB;
+    pub.idx = S_W - S_H1;
+    pub.host = p->hpin + (size_t)j * S_HB;
+    pub.host_stride = (long)S_HB * p->m;
+    pub.zoff = S_H2 - S_H1;
+    pub.zn = nv;
+    pub.cnt = (unsigned long long*)(p->scal + S_CNT);
+    launch_update2_publish(w, p->V, N, nv, N, reorth, p->partials, p->scal + S_H2, wpart, pub, st, p->mb);
     return check_launch(p);
 }
 

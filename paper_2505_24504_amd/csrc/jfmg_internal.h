@@ -340,9 +340,6 @@ __device__ __forceinline__ bool gate_open(const Gate& g) { return !g.h || gate_a
 
 void launch_finalize(const double* partials, int nb, int nq, double* out, hipStream_t st, Gate gate = Gate{},
                      const Mb& mb = Mb{});
-void launch_finalize_publish(const double* partials, int nb, double* out, const double* src, int n, int idx,
-                             double* host, Gate gate, hipStream_t st, const Mb& mb,
-                             long host_stride, int zoff, int zn);
 void launch_norm2(const double* x, long n, Red red, hipStream_t st, const Mb& mb = Mb{});
 // device scalar slots <-> coherent pinned host memory (count values per member)
 void launch_gather(const double* src, int count, double* host, hipStream_t st, const Mb& mb);
@@ -350,14 +347,29 @@ void launch_scatter(double* dst, int count, const double* host, long hstride, hi
 // the finalize into red.out is launched only when red.out != nullptr
 void launch_multidot(const double* w, const double* V, long ld, int nv, int self, long n, Gate gate, Red red,
                      hipStream_t st, const Mb& mb = Mb{});
-// w -= sum_i h[i] V_i; optional ||w||^2 into red.out when red.out != nullptr.  With hpart
-// the coefficients are summed from the multi-dot's partials there (la_blocks(n) per entry)
-// by every work-group and stored to hout (h unused).  With dots (and no hpart), where gate g2
-// opens, the multi-dot <w_new, v_i> (i < nv) of the updated w follows in the same kernel, its
-// block partials at dots (la_blocks(n) per entry, as launch_multidot stores them).
+// w -= sum_i h[i] V_i; optional ||w||^2 into red.out when red.out != nullptr.  With dots, where
+// gate g2 opens, the multi-dot <w_new, v_i> (i < nv) of the updated w follows in the same
+// kernel, its block partials at dots (la_blocks(n) per entry, as launch_multidot stores them).
 void launch_update(double* w, const double* V, long ld, int nv, long n, const double* h, Red red, hipStream_t st,
-                   Gate gate = Gate{}, const Mb& mb = Mb{}, const double* hpart = nullptr, double* hout = nullptr,
-                   Gate g2 = Gate{}, double* dots = nullptr);
+                   Gate gate = Gate{}, const Mb& mb = Mb{}, Gate g2 = Gate{}, double* dots = nullptr);
+// Publication of an FGMRES iteration's scalars: src[0..ns) to host-visible pinned memory
+// (host, member m at host + m * host_stride), entry idx replaced by ||w||^2 (also stored to
+// out[0]), entries zoff .. zoff+zn by 0 where the second pass was skipped; cnt: a counter in
+// device memory, zero between launches.
+struct Publish {
+    double* out = nullptr;
+    const double* src = nullptr;
+    int ns = 0, idx = 0;
+    double* host = nullptr;
+    long host_stride = 0;
+    int zoff = 0, zn = 0;
+    unsigned long long* cnt = nullptr;
+};
+// The gated second Gram-Schmidt pass (coefficients summed from the multi-dot's partials at
+// hpart, la_blocks(n) per entry, stored to hout; ||w||^2 partials at wpart) and the
+// iteration's publication in one launch.  gate.h must be set.
+void launch_update2_publish(double* w, const double* V, long ld, int nv, long n, Gate gate, const double* hpart,
+                            double* hout, double* wpart, const Publish& pub, hipStream_t st, const Mb& mb);
 void launch_scale(double* out, const double* in, long n, const double* nrm2, hipStream_t st, double sgn = 1.0,
                   const Mb& mb = Mb{});
 // out = base + sum_i y[i] Z_i   (base may alias out)

@@ -38,50 +38,6 @@ void launch_finalize(const double* partials, int nb, int nq, double* out, hipStr
     finalize_kernel<<<dim3(nq, 1, mb.n), dim3(256), 0, st>>>(partials, nb, out, gate, mb.ms);
 }
 
-// Last reduction of an FGMRES iteration: out[0] = sum of the partials (or the
-// gate's ||w||^2 after the first pass where the gate is closed, i.e. the
-// re-orthogonalization pass that would have produced the partials was skipped;
-// the entries zoff .. zoff+zn of the published block, that pass's coefficients,
-// are then 0), and the iteration's scalar
-// block src[0..n) (entry idx replaced by out[0]) stored to host-visible pinned
-// memory, so the host reads the Hessenberg column after the iteration's
-// completion event without a separate copy.
-__global__ void __launch_bounds__(256)
-finalize_publish_kernel(const double* __restrict__ p, int nb, double* __restrict__ out, const double* __restrict__ src,
-                        int n, int idx, double* __restrict__ host, Gate gate, long ms, long host_stride, int zoff,
-                        int zn)
-{
-    p = mbr(p, ms);
-    out = mbr(out, ms);
-    src = mbr(src, ms);
-    gate.h = mbr(gate.h, ms);
-    host += (long)blockIdx.z * host_stride;
-    __shared__ double sh[4];
-    __shared__ double total;
-    const bool open = gate_open(gate);
-    const double after = gate.h ? gate_after(gate) : 0.0;   // every lane takes part in its wave sum
-    double a = 0.0;
-    if (open)
-        for (int i = threadIdx.x; i < nb; i += 256) a += p[i];
-    a = block_sum<256>(a, sh);
-    if (threadIdx.x == 0) {
-        total = open ? a : after;
-        out[0] = total;
-    }
-    __syncthreads();
-    // entries zoff .. zoff+zn (the second pass's coefficients) are 0 where the gate is closed
-    for (int i = threadIdx.x; i < n; i += 256)
-        host[i] = (i == idx) ? total : (!open && i >= zoff && i < zoff + zn) ? 0.0 : src[i];
-}
-
-void launch_finalize_publish(const double* partials, int nb, double* out, const double* src, int n, int idx,
-                             double* host, Gate gate, hipStream_t st, const Mb& mb, long host_stride, int zoff,
-                             int zn)
-{
-    finalize_publish_kernel<<<dim3(1, 1, mb.n), dim3(256), 0, st>>>(partials, nb, out, src, n, idx, host, gate,
-                                                                    mb.ms, host_stride, zoff, zn);
-}
-
 // Scalars between the device slots of every member and coherent pinned host
 // memory, by kernels (no copy engine): gather host[m * count + i] = slot_m[i],
 // scatter slot_m[i] = host[m * hstride + i].
@@ -215,27 +171,54 @@ void launch_multidot(const double* w, const double* V, long ld, int nv, int self
     if (red.out) launch_finalize(red.partials, la_blocks(n), nt, red.out, st, gate, mb);
 }
 
-// w -= sum_v h[v] V_v.  SELF (the gated second Gram-Schmidt pass): h is not given but
-// formed by every work-group from the multi-dot's hnb block partials per entry at hpart
-// (lane-strided sums and the wave's butterfly, a fixed order), and work-group 0 stores it
-// to hout for the host; the pass runs only where its gate opens, so the finalize launch
-// it replaces is saved on every iteration where it does not.
+// w -= sum_v h[v] V_v.
 // With dots (the first pass), where the gate g2 of the second pass opens, the kernel goes on
 // to that pass's multi-dot <w, v_q> of the w it has just formed, still in registers: the
 // block partials at dots[q * gridDim.x + blockIdx.x], with the multi-dot kernel's products,
 // order and partial layout (its launch, one kernel per iteration, is saved).
+// SELF: the gated second Gram-Schmidt pass together with the iteration's last reduction and
+// its publication (pub), in one launch:
+//  * gate closed (the pass is skipped): work-group 0 stores ||w||^2 after the first pass, by
+//    Pythagoras, to pub.out and publishes; every other work-group returns at once;
+//  * gate open: h is not given but formed by every work-group from the multi-dot's hnb block
+//    partials per entry at hpart (lane-strided sums and the wave's butterfly, a fixed order;
+//    work-group 0 stores it to hout), each work-group updates its part of w and stores its
+//    ||w||^2 partial in red; the last work-group to finish (a release fence and a counter in
+//    device memory, so no work-group waits for another) sums the partials in a fixed order into
+//    pub.out, publishes, and clears the counter for the next launch.
+// Publishing stores the scalar block pub.src[0..ns) to host-visible pinned memory, entry idx
+// replaced by pub.out's value and, where the gate is closed, entries zoff .. zoff+zn (the
+// skipped pass's coefficients) by 0, so the host reads the Hessenberg column after the
+// iteration's completion event without a separate copy.
 template <bool SELF>
 __global__ void __launch_bounds__(LA_NTH)
 update_kernel(double* __restrict__ w, const double* __restrict__ V, long ld, int nv, long n,
               const double* __restrict__ h, Gate gate, Red red, long ms, const MemberArgs* __restrict__ mt,
               const double* __restrict__ hpart, int hnb, double* __restrict__ hout, Gate g2,
-              double* __restrict__ dots)
+              double* __restrict__ dots, Publish pub)
 {
     n = len_of(n, mt);
     gate.h = mbr(gate.h, ms);
     g2.h = mbr(g2.h, ms);
-    // every lane takes part in the gates' wave sums
-    if (!gate_open(gate)) return;
+    if constexpr (SELF) {
+        pub.out = mbr(pub.out, ms);
+        pub.src = mbr(pub.src, ms);
+        pub.cnt = mbr(pub.cnt, ms);
+        pub.host += (long)blockIdx.z * pub.host_stride;
+        // every lane takes part in the wave sum; the decision is gate_open's
+        const double after = gate_after(gate);
+        if (!(after < gate.tau2 * gate.h[gate.nv])) {
+            if (blockIdx.x == 0) {
+                if (threadIdx.x == 0) pub.out[0] = after;
+                for (int i = threadIdx.x; i < pub.ns; i += LA_NTH)
+                    pub.host[i] = (i == pub.idx) ? after : (i >= pub.zoff && i < pub.zoff + pub.zn) ? 0.0 : pub.src[i];
+            }
+            return;
+        }
+    } else {
+        // every lane takes part in the gates' wave sums
+        if (!gate_open(gate)) return;
+    }
     const bool dots2 = !SELF && dots && gate_open(g2);
     w = mbr(w, ms);
     V = mbr(V, ms);
@@ -300,6 +283,28 @@ update_kernel(double* __restrict__ w, const double* __restrict__ V, long ld, int
         }
     }
     if (red.partials) put_partial<LA_NTH>(red, s);
+    if constexpr (SELF) {
+        __shared__ bool last;
+        __shared__ double sh[LA_NTH / 64], total;
+        if (threadIdx.x == 0) {
+            __threadfence();   // this work-group's partial (and work-group 0's hout) before the count
+            last = atomicAdd(pub.cnt, 1ull) == (unsigned long long)(gridDim.x - 1);
+        }
+        __syncthreads();
+        if (!last) return;
+        __threadfence();   // every other work-group's partial is visible after its count
+        double a = 0.0;
+        for (int i = threadIdx.x; i < (int)gridDim.x; i += LA_NTH) a += red.partials[i];
+        a = block_sum<LA_NTH>(a, sh);   // in thread 0
+        if (threadIdx.x == 0) {
+            pub.out[0] = a;
+            total = a;
+            atomicExch(pub.cnt, 0ull);
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < pub.ns; i += LA_NTH) pub.host[i] = (i == pub.idx) ? total : pub.src[i];
+        return;
+    }
     if (!dots2) return;
     dots = mbr(dots, ms);
     constexpr int NW = LA_NTH / 64, G = 4;
@@ -350,15 +355,19 @@ update_kernel(double* __restrict__ w, const double* __restrict__ V, long ld, int
 }
 
 void launch_update(double* w, const double* V, long ld, int nv, long n, const double* h, Red red, hipStream_t st,
-                   Gate gate, const Mb& mb, const double* hpart, double* hout, Gate g2, double* dots)
+                   Gate gate, const Mb& mb, Gate g2, double* dots)
 {
-    if (hpart)
-        timed_launch(update_kernel<true>, dim3(la_blocks(n), 1, mb.n), dim3(LA_NTH), st, w, V, ld, nv, n, h, gate, red,
-                     mb.ms, mb.tab, hpart, la_blocks(n), hout, Gate{}, (double*)nullptr);
-    else
-        timed_launch(update_kernel<false>, dim3(la_blocks(n), 1, mb.n), dim3(LA_NTH), st, w, V, ld, nv, n, h, gate,
-                     red, mb.ms, mb.tab, (const double*)nullptr, 0, (double*)nullptr, g2, dots);
+    timed_launch(update_kernel<false>, dim3(la_blocks(n), 1, mb.n), dim3(LA_NTH), st, w, V, ld, nv, n, h, gate,
+                 red, mb.ms, mb.tab, (const double*)nullptr, 0, (double*)nullptr, g2, dots, Publish{});
     if (red.out) launch_finalize(red.partials, la_blocks(n), 1, red.out, st, Gate{}, mb);
+}
+
+void launch_update2_publish(double* w, const double* V, long ld, int nv, long n, Gate gate, const double* hpart,
+                            double* hout, double* wpart, const Publish& pub, hipStream_t st, const Mb& mb)
+{
+    timed_launch(update_kernel<true>, dim3(la_blocks(n), 1, mb.n), dim3(LA_NTH), st, w, V, ld, nv, n,
+                 (const double*)nullptr, gate, Red{wpart, nullptr}, mb.ms, mb.tab, hpart, la_blocks(n), hout, Gate{},
+                 (double*)nullptr, pub);
 }
 
 __global__ void __launch_bounds__(256)

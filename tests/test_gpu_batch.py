@@ -150,6 +150,26 @@ def test_lockstep_members_equal_alone(prec, key, k):
         assert torch.equal(U[i * n:(i + 1) * n], alone[i]), i
 
 
+def test_batches_with_second_gram_schmidt_pass_every_iteration(monkeypatch):
+    """With the re-orthogonalization pass on every FGMRES iteration (JFMG_REORTH_ALWAYS=1:
+    the pass's update kernel sums its norm partials and publishes through a per-member
+    counter), lock-step and ragged batch members are bitwise equal to the same members
+    run alone."""
+    monkeypatch.setenv("JFMG_REORTH_ALWAYS", "1")
+    ens = [m for m in W.ensemble(seed=4, members=64) if m[0]["nx"] == 32][:3]
+    d = dict(ens[0][0], mg_precision=64)
+    alone = [_alone(d, pert, 2) for _, pert, _ in ens]
+    pb = jfmg.Problem(dict(d, batch=len(ens)), device=DEV)
+    U = torch.cat([jfmg.Problem(d, device=DEV).initial_state(pert) for _, pert, _ in ens])
+    for _ in range(2):
+        assert pb.implicit_step(U)["status"] == 0
+    n = pb.ndof
+    for i in range(len(ens)):
+        assert torch.equal(U[i * n:(i + 1) * n], alone[i]), i
+    big = [m for m in W.ensemble(seed=4, members=64) if m[0]["nx"] > 32][:1]
+    _ragged_vs_alone([(m[0], m[1]) for m in big] + [(e[0], e[1]) for e in ens[:2]], 1, 64)
+
+
 def test_lockstep_autotuned_members_equal_alone():
     """A lock-step batch tuned by the autotuner and single problems given the same
     tile shapes give bitwise the same members."""
