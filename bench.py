@@ -194,6 +194,7 @@ def _lockstep_ensemble(mem, prec):
     return el, {"members_ok": ok, "groups": [len(ms) for ms in groups.values()], "tiles": tiles,
                 "autotune_seconds": el_tune, "lockstep_gmres_its": [st["gmres_its"] for _, _, st in polled],
                 "stall_stops": sum(st["stall_stops"] for _, _, st in polled),
+                "reorth_its": sum(st["reorth_its"] for _, _, st in polled),
                 "reached_rtol": max(st["reached_rtol"] for _, _, st in polled)}
 
 
@@ -219,19 +220,20 @@ def _ragged_ensemble(mem, prec, graphs=False):
     tiles, _ = pb.autotune(reps=5)
     el_tune = time.perf_counter() - t0
     steps = mem[0][2]
-    its, stalls, reach, ok = 0, 0, 0.0, True
+    its, stalls, reorth, reach, ok = 0, 0, 0, 0.0, True
     _sync()
     t0 = time.perf_counter()
     for _ in range(steps):
         st = pb.implicit_step(U, raise_on_error=False)
         its += st["gmres_its"]
         stalls += st["stall_stops"]
+        reorth += st["reorth_its"]
         reach = max(reach, st["reached_rtol"])
         ok = ok and st["status"] == 0
     _sync()
     el = time.perf_counter() - t0
     return el, {"members_ok": len(mem) if ok else 0, "tiles": tiles, "autotune_seconds": el_tune,
-                "lockstep_gmres_its": its, "stall_stops": stalls, "reached_rtol": reach, "graphs": graphs,
+                "lockstep_gmres_its": its, "stall_stops": stalls, "reorth_its": reorth, "reached_rtol": reach, "graphs": graphs,
                 "launches": "one per kernel over all 64 members (ragged batch)"}
 
 
@@ -253,7 +255,7 @@ def ensemble_forms():
     polled = [b.poll(s_) for s_ in slots]
     b.close()
     ok_b = sum(1 for f, _, st in polled if f and st["status"] == 0)
-    el_s, its_s, ok_s, stalls_s, reach_s = 0.0, 0, 0, 0, 0.0
+    el_s, its_s, ok_s, stalls_s, reorth_s, reach_s = 0.0, 0, 0, 0, 0, 0.0
     for d, pert, n in mem:
         p = jfmg.Problem(dict(d, mg_precision=64), device="cuda:0")
         U = p.initial_state(pert)
@@ -264,6 +266,7 @@ def ensemble_forms():
             st = p.implicit_step(U, raise_on_error=False)
             its_s += st["gmres_its"]
             stalls_s += st["stall_stops"]
+            reorth_s += st["reorth_its"]
             reach_s = max(reach_s, st["reached_rtol"])
             good = good and st["status"] == 0
         _sync()
@@ -286,9 +289,11 @@ def ensemble_forms():
         "ensemble_batched_fp32": {"value": work / el_b, "seconds": el_b, "members_ok": ok_b,
                                   "gmres_its": sum(st["gmres_its"] for _, _, st in polled),
                                   "stall_stops": sum(st["stall_stops"] for _, _, st in polled),
+                                  "reorth_its": sum(st["reorth_its"] for _, _, st in polled),
                                   "reached_rtol": max(st["reached_rtol"] for _, _, st in polled)},
         "ensemble_serial_fp64": {"value": work / el_s, "seconds": el_s, "members_ok": ok_s,
-                                 "gmres_its": its_s, "stall_stops": stalls_s, "reached_rtol": reach_s},
+                                 "gmres_its": its_s, "stall_stops": stalls_s, "reorth_its": reorth_s,
+                                 "reached_rtol": reach_s},
         "ensemble_workload": "64 warm bubbles, k=2, grids 32x16/64x32/96x48, 5 SDIRK2 steps each, "
                              f"{work} DOF-Newton-steps; 640 stages"})
     return out
@@ -306,6 +311,7 @@ def _serve_once(reqs, prec, rate_scale=1.0):
     s = serve.summary(recs)
     s["offered_req_per_s"] = len(rq) / (rq[-1]["arrival"] * rate_scale) if rq else None
     s["stall_stops"] = sum(r.get("stall_stops", 0) for r in recs)
+    s["reorth_its"] = sum(r.get("reorth_its", 0) for r in recs)
     s["reached_rtol"] = max((r.get("reached_rtol", 0.0) for r in recs), default=0.0)
     return s
 
@@ -395,6 +401,7 @@ def inertia_gravity_forms(steps=20):
                                "newton_its": sum(s["newton_its"] for s in its),
                                "gmres_its": sum(s["gmres_its"] for s in its),
                                "stall_stops": sum(s["stall_stops"] for s in its),
+                               "reorth_its": sum(s["reorth_its"] for s in its),
                                "reached_rtol": max(s["reached_rtol"] for s in its),
                                "ok": all(s["status"] == 0 for s in its)}
         Us[prec] = (U0.cpu().numpy(), U.cpu().numpy())
@@ -689,6 +696,7 @@ def main():
                        "p50_ms": 1e3 * percentile(latv, 50), "p99_ms": 1e3 * percentile(latv, 99),
                        "newton_its": sum(s["newton_its"] for s in itsv),
                        "gmres_its": sum(s["gmres_its"] for s in itsv), "jvps": sum(s["jvps"] for s in itsv),
+                       "reorth_its": sum(s["reorth_its"] for s in itsv),
                        "ok": all(s["status"] == 0 for s in itsv)}
     if not a.no_fp32:
         d32 = dict(d, mg_precision=32)
@@ -697,9 +705,11 @@ def main():
                             "p50_ms": 1e3 * percentile(lat32, 50), "p99_ms": 1e3 * percentile(lat32, 99),
                             "newton_its": sum(s["newton_its"] for s in its32),
                             "gmres_its": sum(s["gmres_its"] for s in its32),
+                            "reorth_its": sum(s["reorth_its"] for s in its32),
                             "reached_rtol": max(s["reached_rtol"] for s in its32)}
     forms["fp64_mg"]["newton_its"] = sum(s["newton_its"] for s in its)
     forms["fp64_mg"]["gmres_its"] = sum(s["gmres_its"] for s in its)
+    forms["fp64_mg"]["reorth_its"] = sum(s["reorth_its"] for s in its)
     forms["fp64_mg"]["reached_rtol"] = max(s["reached_rtol"] for s in its)
     forms["iteration_breakdown"] = breakdown
     out = {
@@ -724,7 +734,8 @@ def main():
         "iterations": {"newton": sum(s["newton_its"] for s in its), "gmres": sum(s["gmres_its"] for s in its),
                        "lh_evals": sum(s["lh_evals"] for s in its), "jvps": sum(s["jvps"] for s in its),
                        "fv_matvecs_per_level": [sum(s["fv_matvecs"][l] for s in its) for l in range(4)],
-                       "host_syncs": sum(s["host_syncs"] for s in its)},
+                       "host_syncs": sum(s["host_syncs"] for s in its),
+                       "reorth_its": sum(s["reorth_its"] for s in its)},
         "forms": forms,
         "roofline": {"bound": "hbm", "kernel": prof_cls, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None,

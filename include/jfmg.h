@@ -92,7 +92,9 @@ typedef struct {
     int newton_its, gmres_its, lh_evals, jvps;
     int fv_matvecs[8];        /* FV operator evaluations per level (finest first)      */
     int host_syncs, status;
-    int stall_stops, pad;     /* stages ended at the rounding floor (newton_stall)     */
+    int stall_stops;          /* stages ended at the rounding floor (newton_stall)     */
+    int reorth_its;           /* FGMRES iterations (per member) whose second
+                                 Gram-Schmidt pass ran                                 */
     double g0_norm, g_norm;   /* ||G(U^0)||, ||G|| at exit of the last stage          */
     double seconds;           /* host wall time of the call                           */
     double reached_rtol;      /* largest final ||G|| / ||G^0|| over the call's stages

@@ -109,6 +109,7 @@ void accumulate(jfmg_stats& a, const jfmg_stats& s)
     for (int l = 0; l < 8; ++l) a.fv_matvecs[l] += s.fv_matvecs[l];
     a.host_syncs += s.host_syncs;
     a.stall_stops += s.stall_stops;
+    a.reorth_its += s.reorth_its;
     a.g0_norm = s.g0_norm;
     a.g_norm = s.g_norm;
     a.seconds += s.seconds;

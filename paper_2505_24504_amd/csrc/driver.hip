@@ -358,6 +358,7 @@ struct jfmg_problem {
     jfmg_stats* stats;
     int mv_count[MAXLEV];
     int lh_count, jvp_count, syncs;
+    int reorths;   // FGMRES iterations (per member) whose second Gram-Schmidt pass ran
     std::vector<double> hbuf;
 };
 
@@ -1243,7 +1244,12 @@ jfmg_status fgmres_cycles(jfmg_problem* p, const double* G, const std::vector<do
                 if (x.done || x.conv) continue;
                 std::vector<double>& H = x.H;
                 const double* hb = p->hpin + ((size_t)mb * m + j) * S_HB;
-                for (int i = 0; i <= j; ++i) H[i * m + j] = hb[i] + hb[(S_H2 - S_H1) + i];
+                bool second = false;   // the pass's coefficients are published as 0 where it was skipped
+                for (int i = 0; i <= j; ++i) {
+                    H[i * m + j] = hb[i] + hb[(S_H2 - S_H1) + i];
+                    second = second || hb[(S_H2 - S_H1) + i] != 0.0;
+                }
+                p->reorths += second;
                 const double hn = std::sqrt(hb[S_W - S_H1]);
                 H[(j + 1) * m + j] = hn;
                 for (int i = 0; i < j; ++i) {
@@ -1930,6 +1936,7 @@ static jfmg_status implicit_step_body(jfmg_problem* p, double* U, jfmg_stats* st
     p->lh_count = 0;
     p->jvp_count = 0;
     p->syncs = 0;
+    p->reorths = 0;
     const jfmg_config& c = p->cfg;
     jfmg_status s;
     // the caller's U holds the members back to back
@@ -1962,6 +1969,7 @@ static jfmg_status implicit_step_body(jfmg_problem* p, double* U, jfmg_stats* st
     st.lh_evals = p->lh_count;
     st.jvps = p->jvp_count;
     st.host_syncs = p->syncs;
+    st.reorth_its = p->reorths;
     for (int l = 0; l < MAXLEV && l < 8; ++l) st.fv_matvecs[l] = p->mv_count[l];
     st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (stats) *stats = st;
@@ -1997,6 +2005,7 @@ jfmg_status jfmg_newton_stage(jfmg_problem* p, const double* Ubar, double alpha_
     p->lh_count = 0;
     p->jvp_count = 0;
     p->syncs = 0;
+    p->reorths = 0;
     const size_t vb = sizeof(double) * p->N;
     jfmg_status s = JFMG_OK;
     e = hipMemcpyAsync(p->Ubar, Ubar, vb, hipMemcpyDeviceToDevice, p->st);
@@ -2015,6 +2024,7 @@ jfmg_status jfmg_newton_stage(jfmg_problem* p, const double* Ubar, double alpha_
     st.lh_evals = p->lh_count;
     st.jvps = p->jvp_count;
     st.host_syncs = p->syncs;
+    st.reorth_its = p->reorths;
     for (int l = 0; l < MAXLEV; ++l) st.fv_matvecs[l] = p->mv_count[l];
     st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (stats) *stats = st;

@@ -287,12 +287,14 @@ update_kernel(double* __restrict__ w, const double* __restrict__ V, long ld, int
         __shared__ bool last;
         __shared__ double sh[LA_NTH / 64], total;
         if (threadIdx.x == 0) {
-            __threadfence();   // this work-group's partial (and work-group 0's hout) before the count
+            // release: this work-group's partial (and work-group 0's hout) before its count
+            // (no cache invalidation, which the other work-groups' reads of hpart would pay)
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             last = atomicAdd(pub.cnt, 1ull) == (unsigned long long)(gridDim.x - 1);
         }
         __syncthreads();
         if (!last) return;
-        __threadfence();   // every other work-group's partial is visible after its count
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // every work-group's partial after its count
         double a = 0.0;
         for (int i = threadIdx.x; i < (int)gridDim.x; i += LA_NTH) a += red.partials[i];
         a = block_sum<LA_NTH>(a, sh);   // in thread 0

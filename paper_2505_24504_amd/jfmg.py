@@ -44,14 +44,14 @@ class Perturbation(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("newton_its", C.c_int), ("gmres_its", C.c_int), ("lh_evals", C.c_int), ("jvps", C.c_int),
                 ("fv_matvecs", C.c_int * 8), ("host_syncs", C.c_int), ("status", C.c_int),
-                ("stall_stops", C.c_int), ("pad", C.c_int),
+                ("stall_stops", C.c_int), ("reorth_its", C.c_int),
                 ("g0_norm", C.c_double), ("g_norm", C.c_double), ("seconds", C.c_double),
                 ("reached_rtol", C.c_double)]
 
     def as_dict(self):
         return {"newton_its": self.newton_its, "gmres_its": self.gmres_its, "lh_evals": self.lh_evals,
                 "jvps": self.jvps, "fv_matvecs": list(self.fv_matvecs), "host_syncs": self.host_syncs,
-                "status": self.status, "stall_stops": self.stall_stops, "g0_norm": self.g0_norm,
+                "status": self.status, "stall_stops": self.stall_stops, "reorth_its": self.reorth_its, "g0_norm": self.g0_norm,
                 "g_norm": self.g_norm,
                 "seconds": self.seconds, "reached_rtol": self.reached_rtol}
 

@@ -68,7 +68,8 @@ def serve(requests, batch, need_bytes, arena_bytes, clock=time.perf_counter, sle
             rec.update(completed=done_at, latency=done_at - rec["arrival"], steps_done=steps_done,
                        status="ok" if stats["status"] == 0 else f"error {stats['status']}",
                        newton_its=stats["newton_its"], gmres_its=stats["gmres_its"],
-                       stall_stops=stats.get("stall_stops", 0), reached_rtol=stats.get("reached_rtol", 0.0))
+                       stall_stops=stats.get("stall_stops", 0), reorth_its=stats.get("reorth_its", 0),
+                       reached_rtol=stats.get("reached_rtol", 0.0))
             if keep_state:
                 rec["U"] = U
     finally:

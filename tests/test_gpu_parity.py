@@ -528,6 +528,7 @@ def test_implicit_step_with_second_gram_schmidt_pass_every_iteration(monkeypatch
     U = to_dev(U0)
     st = p.implicit_step(U)
     print("case reorth every iteration", flush=True)
+    assert st["reorth_its"] == st["gmres_its"]
     _step_check(d, Uo, U0, to_np(U), REL_STEP_BUBBLE, st, st_o)
     q = jfmg.Problem(d, device=DEV)
     Ud = to_dev(U0)
