@@ -1046,15 +1046,11 @@ jfmg_status iter_ops(jfmg_problem* p, int j)
     // ||w||^2 before it (Gate), so the first update needs no norm of its own
     const Gate reorth{p->scal + S_H1, nv, p->reorth_always ? 1e300 : REORTH_TAU * REORTH_TAU};
     // the gated second pass: its multi-dot is taken by the first update kernel (from the w
-    // it has formed); its coefficients are summed by its own update kernel, which also
-    // stores ||w||^2 (of the second pass where it ran, else the first pass's by Pythagoras)
-    // and publishes the scalar block h1, h2 (0 where the second pass did not run), ||w||^2
-    // of iteration j to pinned host memory; its ||w||^2 partials go after the multi-dot's
-    { ProfScope ps(p, JFMG_K_MULTIDOT, md); launch_multidot(w, p->V, N, nv, 1, N, Gate{}, red_at(p, S_H1), st, p->mb); }
-    { ProfScope ps(p, JFMG_K_UPDATE, up);
-      launch_update(w, p->V, N, nv, N, p->scal + S_H1, Red{nullptr, nullptr}, st, Gate{}, p->mb, reorth,
-                    p->partials); }
-    double* wpart = p->partials + (long)(p->m + 1) * la_blocks(N);
+    // it has formed), its coefficients are summed by its own update kernel, and its ||w||^2
+    // partials go after the multi-dot's.  The scalar block h1, h2 (0 where the second pass
+    // did not run), ||w||^2 (of the second pass where it ran, else the first pass's by
+    // Pythagoras) of iteration j goes to pinned host memory from the first update kernel
+    // where the pass is skipped, else from the second
     Publish pub;
     pub.out = p->scal + S_W;
     pub.src = p->scal + S_H1;
@@ -1065,6 +1061,11 @@ jfmg_status iter_ops(jfmg_problem* p, int j)
     pub.zoff = S_H2 - S_H1;
     pub.zn = nv;
     pub.cnt = (unsigned long long*)(p->scal + S_CNT);
+    { ProfScope ps(p, JFMG_K_MULTIDOT, md); launch_multidot(w, p->V, N, nv, 1, N, Gate{}, red_at(p, S_H1), st, p->mb); }
+    { ProfScope ps(p, JFMG_K_UPDATE, up);
+      launch_update(w, p->V, N, nv, N, p->scal + S_H1, Red{nullptr, nullptr}, st, Gate{}, p->mb, reorth,
+                    p->partials, pub); }
+    double* wpart = p->partials + (long)(p->m + 1) * la_blocks(N);
     launch_update2_publish(w, p->V, N, nv, N, reorth, p->partials, p->scal + S_H2, wpart, pub, st, p->mb);
     return check_launch(p);
 }

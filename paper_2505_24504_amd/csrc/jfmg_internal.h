@@ -347,11 +347,13 @@ void launch_scatter(double* dst, int count, const double* host, long hstride, hi
 // the finalize into red.out is launched only when red.out != nullptr
 void launch_multidot(const double* w, const double* V, long ld, int nv, int self, long n, Gate gate, Red red,
                      hipStream_t st, const Mb& mb = Mb{});
-// w -= sum_i h[i] V_i; optional ||w||^2 into red.out when red.out != nullptr.  With dots, where
-// gate g2 opens, the multi-dot <w_new, v_i> (i < nv) of the updated w follows in the same
-// kernel, its block partials at dots (la_blocks(n) per entry, as launch_multidot stores them).
+struct Publish;
+// w -= sum_i h[i] V_i; optional ||w||^2 into red.out when red.out != nullptr.  With dots (g2.h
+// set), where gate g2 opens, the multi-dot <w_new, v_i> (i < nv) of the updated w follows in the
+// same kernel, its block partials at dots (la_blocks(n) per entry, as launch_multidot stores
+// them); where it stays closed, the kernel publishes (pub) with ||w_new||^2 by Pythagoras.
 void launch_update(double* w, const double* V, long ld, int nv, long n, const double* h, Red red, hipStream_t st,
-                   Gate gate = Gate{}, const Mb& mb = Mb{}, Gate g2 = Gate{}, double* dots = nullptr);
+                   Gate gate, const Mb& mb, Gate g2, double* dots, const Publish& pub);
 // Publication of an FGMRES iteration's scalars: src[0..ns) to host-visible pinned memory
 // (host, member m at host + m * host_stride), entry idx replaced by ||w||^2 (also stored to
 // out[0]), entries zoff .. zoff+zn by 0 where the second pass was skipped; cnt: a counter in
@@ -366,8 +368,9 @@ struct Publish {
     unsigned long long* cnt = nullptr;
 };
 // The gated second Gram-Schmidt pass (coefficients summed from the multi-dot's partials at
-// hpart, la_blocks(n) per entry, stored to hout; ||w||^2 partials at wpart) and the
-// iteration's publication in one launch.  gate.h must be set.
+// hpart, la_blocks(n) per entry, stored to hout; ||w||^2 partials at wpart) and, where it runs,
+// the iteration's publication, in one launch (where the gate stays closed the first pass's
+// update kernel publishes).  gate.h must be set.
 void launch_update2_publish(double* w, const double* V, long ld, int nv, long n, Gate gate, const double* hpart,
                             double* hout, double* wpart, const Publish& pub, hipStream_t st, const Mb& mb);
 void launch_scale(double* out, const double* in, long n, const double* nrm2, hipStream_t st, double sgn = 1.0,

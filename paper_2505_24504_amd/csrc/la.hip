@@ -172,14 +172,15 @@ void launch_multidot(const double* w, const double* V, long ld, int nv, int self
 }
 
 // w -= sum_v h[v] V_v.
-// With dots (the first pass), where the gate g2 of the second pass opens, the kernel goes on
-// to that pass's multi-dot <w, v_q> of the w it has just formed, still in registers: the
-// block partials at dots[q * gridDim.x + blockIdx.x], with the multi-dot kernel's products,
-// order and partial layout (its launch, one kernel per iteration, is saved).
+// With dots (the first pass) the gate g2 of the second pass decides: where it opens, the
+// kernel goes on to that pass's multi-dot <w, v_q> of the w it has just formed, still in
+// registers: the block partials at dots[q * gridDim.x + blockIdx.x], with the multi-dot
+// kernel's products, order and partial layout (its launch, one kernel per iteration, is
+// saved); where it stays closed, work-group 0 stores ||w||^2 after this pass, by Pythagoras,
+// to pub.out and publishes (first thing, so that its loads and host stores overlap the update).
 // SELF: the gated second Gram-Schmidt pass together with the iteration's last reduction and
 // its publication (pub), in one launch:
-//  * gate closed (the pass is skipped): work-group 0 stores ||w||^2 after the first pass, by
-//    Pythagoras, to pub.out and publishes; every other work-group returns at once;
+//  * gate closed (the pass is skipped): every work-group returns at once;
 //  * gate open: h is not given but formed by every work-group from the multi-dot's hnb block
 //    partials per entry at hpart (lane-strided sums and the wave's butterfly, a fixed order;
 //    work-group 0 stores it to hout), each work-group updates its part of w and stores its
@@ -200,26 +201,25 @@ update_kernel(double* __restrict__ w, const double* __restrict__ V, long ld, int
     n = len_of(n, mt);
     gate.h = mbr(gate.h, ms);
     g2.h = mbr(g2.h, ms);
+    pub.out = mbr(pub.out, ms);
+    pub.src = mbr(pub.src, ms);
+    pub.cnt = mbr(pub.cnt, ms);
+    pub.host += (long)blockIdx.z * pub.host_stride;
+    bool dots2 = false;
     if constexpr (SELF) {
-        pub.out = mbr(pub.out, ms);
-        pub.src = mbr(pub.src, ms);
-        pub.cnt = mbr(pub.cnt, ms);
-        pub.host += (long)blockIdx.z * pub.host_stride;
-        // every lane takes part in the wave sum; the decision is gate_open's
-        const double after = gate_after(gate);
-        if (!(after < gate.tau2 * gate.h[gate.nv])) {
-            if (blockIdx.x == 0) {
+        if (!gate_open(gate)) return;   // every lane takes part in the gate's wave sum
+    } else {
+        if (!gate_open(gate)) return;
+        if (dots) {
+            const double after = gate_after(g2);   // every lane, as above
+            dots2 = after < g2.tau2 * g2.h[g2.nv];   // gate_open's decision
+            if (!dots2 && blockIdx.x == 0) {
                 if (threadIdx.x == 0) pub.out[0] = after;
                 for (int i = threadIdx.x; i < pub.ns; i += LA_NTH)
                     pub.host[i] = (i == pub.idx) ? after : (i >= pub.zoff && i < pub.zoff + pub.zn) ? 0.0 : pub.src[i];
             }
-            return;
         }
-    } else {
-        // every lane takes part in the gates' wave sums
-        if (!gate_open(gate)) return;
     }
-    const bool dots2 = !SELF && dots && gate_open(g2);
     w = mbr(w, ms);
     V = mbr(V, ms);
     red = mbr(red, ms);
@@ -357,10 +357,10 @@ update_kernel(double* __restrict__ w, const double* __restrict__ V, long ld, int
 }
 
 void launch_update(double* w, const double* V, long ld, int nv, long n, const double* h, Red red, hipStream_t st,
-                   Gate gate, const Mb& mb, Gate g2, double* dots)
+                   Gate gate, const Mb& mb, Gate g2, double* dots, const Publish& pub)
 {
     timed_launch(update_kernel<false>, dim3(la_blocks(n), 1, mb.n), dim3(LA_NTH), st, w, V, ld, nv, n, h, gate,
-                 red, mb.ms, mb.tab, (const double*)nullptr, 0, (double*)nullptr, g2, dots, Publish{});
+                 red, mb.ms, mb.tab, (const double*)nullptr, 0, (double*)nullptr, g2, dots, pub);
     if (red.out) launch_finalize(red.partials, la_blocks(n), 1, red.out, st, Gate{}, mb);
 }
 
