@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC = {"class": "fv_stage", "bytes_per_launch": 2.9739e+07,
            "sources": ["paper_2505_24504_amd/csrc/fv.hip", "paper_2505_24504_amd/csrc/jfmg_dev.h",
                        "paper_2505_24504_amd/csrc/jfmg_internal.h"],
-           "sha256": "b5597e10f9a418ba91488d25bda5141f151b8d3d6b63a0ed8823125bf90f0052",
+           "sha256": "1ddb92973a0fc83dc3e7d5774a9c48fffa4a6ea16e023bbead5fa1f1b62ccb65",
            "profile": "profiles/traffic_fv_stage_density_current_fp64.md"}
 
 

@@ -247,7 +247,8 @@ enum {
     S_LEV = 16,     // + 4*level: LV_* slots
     S_H1 = 128,     // 65 entries: h of the first pass, then ||w||^2 before it
     S_H2 = 193,     // 65 entries
-    S_HB = 131,     // doubles from S_H1 through S_W
+    S_RF = 259,     // 1 where the second Gram-Schmidt pass ran, else 0 (published only)
+    S_HB = 132,     // doubles from S_H1 through S_RF
     S_Yc = 384,     // 65 entries: FGMRES coefficients
     HSCAL = 8       // scalars per member the host reads at once
 };
@@ -1060,6 +1061,7 @@ jfmg_status iter_ops(jfmg_problem* p, int j)
     pub.host_stride = (long)S_HB * p->m;
     pub.zoff = S_H2 - S_H1;
     pub.zn = nv;
+    pub.fidx = S_RF - S_H1;
     pub.cnt = (unsigned long long*)(p->scal + S_CNT);
     { ProfScope ps(p, JFMG_K_MULTIDOT, md); launch_multidot(w, p->V, N, nv, 1, N, Gate{}, red_at(p, S_H1), st, p->mb); }
     { ProfScope ps(p, JFMG_K_UPDATE, up);
@@ -1245,12 +1247,8 @@ jfmg_status fgmres_cycles(jfmg_problem* p, const double* G, const std::vector<do
                 if (x.done || x.conv) continue;
                 std::vector<double>& H = x.H;
                 const double* hb = p->hpin + ((size_t)mb * m + j) * S_HB;
-                bool second = false;   // the pass's coefficients are published as 0 where it was skipped
-                for (int i = 0; i <= j; ++i) {
-                    H[i * m + j] = hb[i] + hb[(S_H2 - S_H1) + i];
-                    second = second || hb[(S_H2 - S_H1) + i] != 0.0;
-                }
-                p->reorths += second;
+                for (int i = 0; i <= j; ++i) H[i * m + j] = hb[i] + hb[(S_H2 - S_H1) + i];
+                p->reorths += hb[S_RF - S_H1] != 0.0;
                 const double hn = std::sqrt(hb[S_W - S_H1]);
                 H[(j + 1) * m + j] = hn;
                 for (int i = 0; i < j; ++i) {

@@ -356,15 +356,16 @@ void launch_update(double* w, const double* V, long ld, int nv, long n, const do
                    Gate gate, const Mb& mb, Gate g2, double* dots, const Publish& pub);
 // Publication of an FGMRES iteration's scalars: src[0..ns) to host-visible pinned memory
 // (host, member m at host + m * host_stride), entry idx replaced by ||w||^2 (also stored to
-// out[0]), entries zoff .. zoff+zn by 0 where the second pass was skipped; cnt: a counter in
-// device memory, zero between launches.
+// out[0]), entries zoff .. zoff+zn by 0 where the second pass was skipped, entry fidx by 1
+// where it ran and 0 where it was skipped; cnt: a counter in device memory, zero between
+// launches.
 struct Publish {
     double* out = nullptr;
     const double* src = nullptr;
     int ns = 0, idx = 0;
     double* host = nullptr;
     long host_stride = 0;
-    int zoff = 0, zn = 0;
+    int zoff = 0, zn = 0, fidx = -1;
     unsigned long long* cnt = nullptr;
 };
 // The gated second Gram-Schmidt pass (coefficients summed from the multi-dot's partials at

@@ -188,9 +188,10 @@ void launch_multidot(const double* w, const double* V, long ld, int nv, int self
 //    device memory, so no work-group waits for another) sums the partials in a fixed order into
 //    pub.out, publishes, and clears the counter for the next launch.
 // Publishing stores the scalar block pub.src[0..ns) to host-visible pinned memory, entry idx
-// replaced by pub.out's value and, where the gate is closed, entries zoff .. zoff+zn (the
-// skipped pass's coefficients) by 0, so the host reads the Hessenberg column after the
-// iteration's completion event without a separate copy.
+// replaced by pub.out's value, entry fidx by 1 where the second pass ran (else 0) and, where
+// the gate is closed, entries zoff .. zoff+zn (the skipped pass's coefficients) by 0, so the
+// host reads the Hessenberg column after the iteration's completion event without a separate
+// copy.
 template <bool SELF>
 __global__ void __launch_bounds__(LA_NTH)
 update_kernel(double* __restrict__ w, const double* __restrict__ V, long ld, int nv, long n,
@@ -216,7 +217,10 @@ update_kernel(double* __restrict__ w, const double* __restrict__ V, long ld, int
             if (!dots2 && blockIdx.x == 0) {
                 if (threadIdx.x == 0) pub.out[0] = after;
                 for (int i = threadIdx.x; i < pub.ns; i += LA_NTH)
-                    pub.host[i] = (i == pub.idx) ? after : (i >= pub.zoff && i < pub.zoff + pub.zn) ? 0.0 : pub.src[i];
+                    pub.host[i] = (i == pub.idx)                             ? after
+                                  : (i == pub.fidx)                          ? 0.0
+                                  : (i >= pub.zoff && i < pub.zoff + pub.zn) ? 0.0
+                                                                             : pub.src[i];
             }
         }
     }
@@ -304,7 +308,8 @@ update_kernel(double* __restrict__ w, const double* __restrict__ V, long ld, int
             atomicExch(pub.cnt, 0ull);
         }
         __syncthreads();
-        for (int i = threadIdx.x; i < pub.ns; i += LA_NTH) pub.host[i] = (i == pub.idx) ? total : pub.src[i];
+        for (int i = threadIdx.x; i < pub.ns; i += LA_NTH)
+            pub.host[i] = (i == pub.idx) ? total : (i == pub.fidx) ? 1.0 : pub.src[i];
         return;
     }
     if (!dots2) return;
