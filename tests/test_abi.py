@@ -57,6 +57,7 @@ int main(void) {
          offsetof(jfmg_config, x0), offsetof(jfmg_config, rk_alpha), offsetof(jfmg_config, newton_stall),
          offsetof(jfmg_config, pseudo_cfl_dg), sizeof(jfmg_perturbation), sizeof(jfmg_stats),
          offsetof(jfmg_stats, g0_norm), offsetof(jfmg_stats, reached_rtol));
+  printf("%zu %zu\n", offsetof(jfmg_stats, stall_stops), offsetof(jfmg_stats, reorth_its));
   return 0; }
 ''')
     exe = tmp_path / "lay"
@@ -65,7 +66,8 @@ int main(void) {
     assert vals == [C.sizeof(jfmg.Config), jfmg.Config.mg_key.offset, jfmg.Config.x0.offset,
                     jfmg.Config.rk_alpha.offset, jfmg.Config.newton_stall.offset, jfmg.Config.pseudo_cfl_dg.offset,
                     C.sizeof(jfmg.Perturbation),
-                    C.sizeof(jfmg.Stats), jfmg.Stats.g0_norm.offset, jfmg.Stats.reached_rtol.offset]
+                    C.sizeof(jfmg.Stats), jfmg.Stats.g0_norm.offset, jfmg.Stats.reached_rtol.offset,
+                    jfmg.Stats.stall_stops.offset, jfmg.Stats.reorth_its.offset]
 
 
 def test_workspace_sizes(lib):
