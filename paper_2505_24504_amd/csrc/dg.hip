@@ -70,19 +70,28 @@ __device__ __forceinline__ void dg_face(const DgArgs& A, const double (&sv)[4][N
     const double irz = xf ? A.irt_node[zrow] : A.irt_face[zrow];
     double trx[4], dnx[4];   // the neighbour's trace and normal derivative (d/d xi)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        trx[c] = 0.0;
-        dnx[c] = 0.0;
-        if (!wall) {
+    for (int c = 0; c < 4; ++c) trx[c] = dnx[c] = 0.0;
+    if (!wall) {
+        // every load of the neighbour's nodes first (one block: one memory round trip
+        // instead of one per component), then the sums in the same order
+        double vu[4][N1], vy[PLUSY ? 4 : 1][PLUSY ? N1 : 1];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
 #pragma unroll
             for (int j = 0; j < N1; ++j) {
                 const unsigned o = (unsigned)nb * NP + (xf ? r * N1 + j : j * N1 + r);
-                double v = ld(U + c * N, o);
-                if constexpr (PLUSY) v = v + eps * ld(Y + c * N, o);
+                vu[c][j] = ld(U + c * N, o);
+                if constexpr (PLUSY) vy[c][j] = ld(Y + c * N, o);
+            }
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int j = 0; j < N1; ++j) {
+                double v = vu[c][j];
+                if constexpr (PLUSY) v = v + eps * vy[c][j];
                 trx[c] += eo[j] * v;
                 if constexpr (NS) dnx[c] += dso[j] * v;
             }
-        }
     }
     double tro[4], Uo[4], Ux[4], H[4];
 #pragma unroll
